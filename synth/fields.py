@@ -1,0 +1,129 @@
+"""Seeded input generators (no solver arithmetic; see package docstring)."""
+
+import math
+
+import numpy as np
+
+# Per-side interior sizes of the batched workload (uneven instance mix).
+BATCH_SIZES = (63, 127, 255, 511, 1023)
+
+
+def grid_coords(n):
+    """Interior node coordinates x_i = i/(n+1), i = 1..n, on (0, 1)."""
+    return np.arange(1, n + 1, dtype=np.float64) / (n + 1)
+
+
+def _mesh(shape):
+    """Coordinate arrays for a C-order (.., ny, nx) grid, x fastest."""
+    axes = [grid_coords(n) for n in shape]
+    return np.meshgrid(*axes, indexing="ij")
+
+
+def manufactured_c1(n):
+    """2D -Lap u + u^3 = f, u = sin(pi x) sin(pi y) (1 + x y).
+
+    Returns (u_exact, f) sampled on the n x n interior grid, shape (ny, nx).
+    -Lap u = 2 pi^2 s_x s_y (1+xy) - 2 pi (y c_x s_y + x s_x c_y).
+    """
+    y, x = _mesh((n, n))
+    sx, sy = np.sin(math.pi * x), np.sin(math.pi * y)
+    cx, cy = np.cos(math.pi * x), np.cos(math.pi * y)
+    u = sx * sy * (1.0 + x * y)
+    mlap = 2.0 * math.pi ** 2 * sx * sy * (1.0 + x * y) - 2.0 * math.pi * (
+        y * cx * sy + x * sx * cy)
+    return u, mlap + u ** 3
+
+
+def manufactured_c2(n):
+    """3D -Lap u + u^3 = f, u = sin(pi x) sin(pi y) sin(pi z) exp(x+y+z)/e^3.
+
+    Returns (u_exact, f), shape (nz, ny, nx).  With g(t) = sin(pi t) e^t,
+    g'' = e^t ((1 - pi^2) sin(pi t) + 2 pi cos(pi t)).
+    """
+    z, y, x = _mesh((n, n, n))
+
+    def g(t):
+        return np.sin(math.pi * t) * np.exp(t)
+
+    def g2(t):
+        return np.exp(t) * ((1.0 - math.pi ** 2) * np.sin(math.pi * t)
+                            + 2.0 * math.pi * np.cos(math.pi * t))
+
+    e3 = math.exp(-3.0)
+    gx, gy, gz = g(x), g(y), g(z)
+    u = gx * gy * gz * e3
+    lap = (g2(x) * gy * gz + gx * g2(y) * gz + gx * gy * g2(z)) * e3
+    return u, -lap + u ** 3
+
+
+def amplitude_c3(seed):
+    """Seeded amplitude A ~ U[0.5, 2] of the quasi-linear manufactured solution."""
+    return float(np.random.default_rng(seed).uniform(0.5, 2.0))
+
+
+def manufactured_c3(n, amplitude):
+    """3D -div((1+u^2) grad u) = f with u = A sin(pi x) sin(pi y) sin(pi z).
+
+    -div((1+u^2) grad u) = -(1+u^2) Lap u - 2 u |grad u|^2 and Lap u = -3 pi^2 u,
+    so f = 3 pi^2 u (1+u^2) - 2 u |grad u|^2.  Returns (u_exact, f).
+    """
+    z, y, x = _mesh((n, n, n))
+    sx, sy, sz = (np.sin(math.pi * t) for t in (x, y, z))
+    cx, cy, cz = (np.cos(math.pi * t) for t in (x, y, z))
+    u = amplitude * sx * sy * sz
+    grad2 = (amplitude * math.pi) ** 2 * (
+        (cx * sy * sz) ** 2 + (sx * cy * sz) ** 2 + (sx * sy * cz) ** 2)
+    f = 3.0 * math.pi ** 2 * u * (1.0 + u * u) - 2.0 * u * grad2
+    return u, f
+
+
+def random_field(shape, seed, scale=1.0):
+    """Seeded i.i.d. N(0, scale^2) float64 array of the given shape."""
+    return scale * np.random.default_rng(seed).standard_normal(shape)
+
+
+def _sine_synthesis_matrix(n):
+    """B[i, k] = sin(k pi x_i): samples sine mode k at interior node i."""
+    i = np.arange(1, n + 1, dtype=np.float64)
+    return np.sin(math.pi * np.outer(i, i) / (n + 1))
+
+
+def gaussian_random_field(n, length_scale, rng):
+    """Zero-boundary Gaussian random field on the n x n interior grid.
+
+    A sine series f(x, y) = sum_{k,l} sqrt(s_k s_l) xi_{kl} sin(k pi x) sin(l pi y)
+    with xi ~ N(0,1) i.i.d. and the squared-exponential spectral weight
+    s_k = exp(-(length_scale k pi)^2 / 2), then scaled to unit empirical
+    variance over the grid.  Shape (ny, nx).
+    """
+    k = np.arange(1, n + 1, dtype=np.float64)
+    s = np.exp(-0.5 * (length_scale * k * math.pi) ** 2)
+    w = np.sqrt(np.outer(s, s))
+    xi = rng.standard_normal((n, n))
+    b = _sine_synthesis_matrix(n)
+    f = b @ (w * xi) @ b.T
+    std = math.sqrt(float(np.mean(f * f)))
+    return f / std if std > 0 else f
+
+
+def batched_instance(i):
+    """Instance i of the batched workload: 2D, N drawn from BATCH_SIZES.
+
+    Even i: scalar -Lap u + u^3 = f.  Odd i: 2-component system with sources
+    (f1, f2).  Sources are unit-variance GRFs with length scale 0.1.
+    Returns dict(n, ncomp, f) with f of shape (ncomp, n, n).
+    """
+    rng = np.random.default_rng(4000000 + i)
+    n = int(BATCH_SIZES[int(rng.integers(0, len(BATCH_SIZES)))])
+    ncomp = 1 if i % 2 == 0 else 2
+    f = np.stack([gaussian_random_field(n, 0.1, rng) for _ in range(ncomp)])
+    return {"n": n, "ncomp": ncomp, "f": f}
+
+
+def learned_guess_rhs(seed, n=255):
+    """Source for the learned-initial-guess workload: GRF with a seeded length
+    scale in [0.05, 0.3] and amplitude in [1, 50].  Shape (n, n)."""
+    rng = np.random.default_rng(seed)
+    ell = float(rng.uniform(0.05, 0.3))
+    amp = float(rng.uniform(1.0, 50.0))
+    return amp * gaussian_random_field(n, ell, rng)
