@@ -1,0 +1,189 @@
+/*
+ * qn.h - C ABI of the MI355X (gfx950) quasi-Newton / tensor-product solver.
+ *
+ * Method: Hao, Lee & Zhang, "An Efficient Quasi-Newton Method with Tensor
+ * Product Implementation for Solving Quasi-Linear Elliptic Equations and
+ * Systems" (arXiv 2502.03611).  The library runs the quasi-Newton iteration
+ *     vec(U_{k+1}) = vec(U_k) - [c_k A_h + beta_k I]^-1 F^h(U_k)
+ * (Section 4, eq. identity-method) on a finite-difference grid with
+ * homogeneous Dirichlet data (Section 3.2), applying the inverse by the
+ * tensor-product (fast diagonalisation) formula of Section 4.1
+ * (eq. fin_inverse): mode-n products with the 1D eigenvector matrix along
+ * every axis, a pointwise divide by c(lam_i + lam_j (+ lam_k)) + beta, and
+ * the inverse mode-n products.
+ *
+ * Data layout (all device arrays): FP64, contiguous, C-order
+ * (ncomp, nz, ny, nx) in 3D and (ncomp, ny, nx) in 2D, x fastest; this is the
+ * paper's vec order (first index fastest).  n[a] counts INTERIOR nodes on
+ * (0,1) along axis a, h_a = 1/(n[a]+1); boundary values are zero and are not
+ * stored.  The source F is the PDE right-hand side sampled at interior nodes.
+ *
+ * Problems (the paper's model -Lap u + lambda u + f(x,u) = 0, Section 2, with
+ * lambda = 0):
+ *   QN_NL_CUBIC       -Lap u + u^3 = f                      (ncomp = 1)
+ *   QN_NL_SYS2_CUBIC  -Lap u + u^3 - v = f1,
+ *                     -Lap v + v^3 - u = f2 (Section 4.3)     (ncomp = 2)
+ *   QN_NL_QUASILIN    -div((1+u^2) grad u) = f, conservative flux form with
+ *                     arithmetic-mean face coefficients       (ncomp = 1)
+ *
+ * Shift rules (beta_mode):
+ *   QN_BETA_FIXED     beta_k = beta (the value given to qn_setup), c_k = 1.
+ *   QN_BETA_MIDPOINT  beta_k = (min mu + max mu)/2 over the grid, c_k = 1,
+ *                     where mu = f_u = 3U^2 (Section 4, midpoint rule) or,
+ *                     for the system, mu ranges over the 2x2-block
+ *                     eigenvalues of Section 4.3 eq. eigenvalues.
+ *   QN_NL_QUASILIN always uses c_k = (min a + max a)/2, a = 1 + U^2, and the
+ *   fixed beta; QN_BETA_MIDPOINT is rejected for it.
+ *
+ * Precision (transforms only; residual, norms, shift rule and the update are
+ * always FP64): QN_PREC_FP64 (FP64 MFMA), QN_PREC_FP32 (FP32 MFMA),
+ * QN_PREC_BF16X3 (each operand split into bf16 hi + lo parts, three bf16 MFMA
+ * products hi*hi + hi*lo + lo*hi accumulated in FP32).
+ *
+ * Ownership: the library never allocates or frees device memory.  The caller
+ * queries qn_workspace_bytes, allocates that many bytes of device memory
+ * (256-byte aligned) and binds it with qn_bind_workspace; the eigenvector
+ * matrices, eigenvalues and transform scratch live there.  All device
+ * pointers passed in stay owned by the caller.
+ *
+ * Ordering: every call is enqueued on the context's stream (options.stream,
+ * NULL = the default stream).  qn_residual and qn_fdm_solve are asynchronous.
+ * qn_iterate synchronises the stream once per iteration to read the residual
+ * norm, and returns when it has stopped.
+ *
+ * Errors: every entry point returns a qn_status; nothing aborts or throws
+ * across the ABI.  qn_last_error() gives a thread-local message for the last
+ * non-OK status.  A HIP runtime error is sticky: the context must then be
+ * destroyed.  Out-parameters are written only on QN_OK, except qn_iterate,
+ * which always fills *stats and leaves U at the last iterate.
+ *
+ * Threading: a context is not thread-safe; distinct contexts on distinct
+ * streams are independent.
+ */
+#ifndef QN_H
+#define QN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QN_OK = 0,
+  QN_ERR_INVALID = 1,       /* bad argument, null/misaligned pointer, singular shift */
+  QN_ERR_HIP = 2,           /* HIP runtime error (sticky) */
+  QN_ERR_NOT_CONVERGED = 3, /* max_iter solves done without reaching rtol */
+  QN_ERR_DIVERGED = 4,      /* residual became non-finite or exceeded 1e30 * ||F|| */
+  QN_ERR_WORKSPACE = 5,     /* workspace missing, too small or misaligned */
+  QN_ERR_UNSUPPORTED = 6    /* valid request this build does not implement */
+} qn_status;
+
+typedef enum { QN_NL_CUBIC = 0, QN_NL_QUASILIN = 1, QN_NL_SYS2_CUBIC = 2 } qn_nonlinearity;
+typedef enum { QN_PREC_FP64 = 0, QN_PREC_FP32 = 1, QN_PREC_BF16X3 = 2 } qn_precision;
+typedef enum { QN_BETA_FIXED = 0, QN_BETA_MIDPOINT = 1 } qn_beta_mode;
+
+/* dim: 2 or 3.  n[0] = nx, n[1] = ny, n[2] = nz (ignored when dim = 2);
+ * 1 <= n[a] <= 4096.  ncomp: 1, or 2 for QN_NL_SYS2_CUBIC. */
+typedef struct {
+  int32_t dim;
+  int32_t n[3];
+  int32_t ncomp;
+} qn_grid;
+
+/* precision: qn_precision; beta_mode: qn_beta_mode; timing: nonzero records
+ * HIP events around every kernel launch (see qn_timing_*); stream: a
+ * hipStream_t, NULL = default stream. */
+typedef struct {
+  int32_t precision;
+  int32_t beta_mode;
+  int32_t timing;
+  int32_t reserved;
+  void* stream;
+} qn_options;
+
+/* iters: solves performed; status: the qn_status qn_iterate returned;
+ * relres: ||F^h(U)||_2 / ||F||_2 at the returned U; relres0: same at U_0;
+ * beta_last / scale_last: shift and scale of the last solve; seconds: wall
+ * time of the call. */
+typedef struct {
+  int32_t iters;
+  int32_t status;
+  double relres;
+  double relres0;
+  double beta_last;
+  double scale_last;
+  double seconds;
+} qn_stats;
+
+typedef struct qn_ctx_s* qn_ctx;
+
+/* Create a context: validates the grid, computes the closed-form sine
+ * eigenpairs of the 1D stiffness matrix h^-2 tridiag(-1,2,-1) per axis
+ * (Section 3.2 eq. Sy; Section 4.2 with M = I) on the host.  beta: the fixed
+ * shift (must satisfy beta + sum_a lam_min,a > 0).  opt may be NULL (FP64,
+ * fixed beta, no timing, default stream).  No device memory is touched.
+ * Errors: QN_ERR_INVALID for dim not in {2,3}, n out of range, ncomp
+ * inconsistent with nonlinearity, unknown enum values, a singular shift or
+ * QN_BETA_MIDPOINT with QN_NL_QUASILIN. */
+qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity,
+                   const qn_options* opt, qn_ctx* out);
+
+/* Bytes of device workspace the context needs (written to *bytes). */
+qn_status qn_workspace_bytes(qn_ctx ctx, size_t* bytes);
+
+/* Bind caller-owned device memory of at least qn_workspace_bytes bytes,
+ * 256-byte aligned, and upload the eigen-data into it (stream-ordered).
+ * The memory must stay valid until the context is destroyed or rebound.
+ * Errors: QN_ERR_WORKSPACE if too small or misaligned. */
+qn_status qn_bind_workspace(qn_ctx ctx, void* d_ws, size_t bytes);
+
+/* Change the stream subsequent calls are enqueued on (NULL = default). */
+qn_status qn_set_stream(qn_ctx ctx, void* stream);
+
+/* Residual F^h(U) = A_h vec(U) + N_h(U) (Section 4, eq. F_u; system:
+ * Section 4.3) with its reductions.  d_U, d_F: inputs; d_R: output (may not
+ * alias d_U); all (ncomp, [nz,] ny, nx).  d_red: NULL or device double[4]
+ * receiving { sum R^2, min mu, max mu, sum F^2 }, where mu is f_u = 3U^2
+ * (cubic), the block eigenvalues lam_- (min) / lam_+ (max) (system), or
+ * a = 1 + U^2 (quasi-linear).  Asynchronous. */
+qn_status qn_residual(qn_ctx ctx, const double* d_U, const double* d_F, double* d_R,
+                      double* d_red);
+
+/* Tensor-product solve X = (scale A_h + shift I)^-1 R per component
+ * (Section 4.1, eq. fin_inverse), in the context's precision.  d_X may alias
+ * d_R.  Errors: QN_ERR_INVALID if scale <= 0 or scale*sum lam_min + shift <= 0.
+ * Asynchronous. */
+qn_status qn_fdm_solve(qn_ctx ctx, const double* d_R, double scale, double shift,
+                       double* d_X);
+
+/* Quasi-Newton iteration from d_U (in: U_0, out: last iterate) for source
+ * d_F, until ||F^h(U_k)|| / ||F|| <= rtol or max_iter solves.  rtol = 0 runs
+ * exactly max_iter solves (status QN_ERR_NOT_CONVERGED).  Returns QN_OK,
+ * QN_ERR_NOT_CONVERGED or QN_ERR_DIVERGED; *stats (may be NULL) is always
+ * filled.  ||F|| = 0 gives QN_ERR_INVALID. */
+qn_status qn_iterate(qn_ctx ctx, double* d_U, const double* d_F, double rtol,
+                     int32_t max_iter, qn_stats* stats);
+
+/* Kernel timing (contexts created with options.timing != 0).  qn_timing_read
+ * synchronises the stream, folds all recorded launches into the table, and
+ * writes entry i: its kernel name (static string), launch count and total
+ * milliseconds.  i ranges over 0 .. qn_timing_count()-1.  qn_timing_reset
+ * clears the table. */
+int32_t qn_timing_count(void);
+qn_status qn_timing_read(qn_ctx ctx, int32_t i, const char** name, int64_t* launches,
+                         double* total_ms);
+qn_status qn_timing_reset(qn_ctx ctx);
+
+/* Destroy a context (NULL is a no-op).  Does not free the bound workspace. */
+void qn_destroy(qn_ctx ctx);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* qn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QN_H */

@@ -1,0 +1,210 @@
+"""ctypes binding of libqn (include/qn.h).  Argument marshalling only: every
+step of the solver runs in the library's HIP kernels.  PyTorch provides the
+device memory (caller tensors and the workspace) and the current stream."""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqn.so")
+
+QN_OK = 0
+QN_ERR_INVALID = 1
+QN_ERR_HIP = 2
+QN_ERR_NOT_CONVERGED = 3
+QN_ERR_DIVERGED = 4
+QN_ERR_WORKSPACE = 5
+QN_ERR_UNSUPPORTED = 6
+
+NONLINEARITIES = {"cubic": 0, "quasilinear": 1, "system": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+BETA_MODES = {"fixed": 0, "midpoint": 1}
+
+c_i32 = ctypes.c_int32
+c_dbl = ctypes.c_double
+c_vp = ctypes.c_void_p
+
+
+class QNGrid(ctypes.Structure):
+    _fields_ = [("dim", c_i32), ("n", c_i32 * 3), ("ncomp", c_i32)]
+
+
+class QNOptions(ctypes.Structure):
+    _fields_ = [("precision", c_i32), ("beta_mode", c_i32), ("timing", c_i32),
+                ("reserved", c_i32), ("stream", c_vp)]
+
+
+class QNStats(ctypes.Structure):
+    _fields_ = [("iters", c_i32), ("status", c_i32), ("relres", c_dbl), ("relres0", c_dbl),
+                ("beta_last", c_dbl), ("scale_last", c_dbl), ("seconds", c_dbl)]
+
+
+class QNError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libqn status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libqn.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2502_03611_amd.build` "
+                           "(there is no fallback implementation)")
+    L = ctypes.CDLL(LIB_PATH)
+    L.qn_setup.argtypes = [ctypes.POINTER(QNGrid), c_dbl, c_i32, ctypes.POINTER(QNOptions),
+                           ctypes.POINTER(c_vp)]
+    L.qn_workspace_bytes.argtypes = [c_vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.qn_bind_workspace.argtypes = [c_vp, c_vp, ctypes.c_size_t]
+    L.qn_set_stream.argtypes = [c_vp, c_vp]
+    L.qn_residual.argtypes = [c_vp, c_vp, c_vp, c_vp, c_vp]
+    L.qn_fdm_solve.argtypes = [c_vp, c_vp, c_dbl, c_dbl, c_vp]
+    L.qn_iterate.argtypes = [c_vp, c_vp, c_vp, c_dbl, c_i32, ctypes.POINTER(QNStats)]
+    L.qn_timing_count.argtypes = []
+    L.qn_timing_read.argtypes = [c_vp, c_i32, ctypes.POINTER(ctypes.c_char_p),
+                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(c_dbl)]
+    L.qn_timing_reset.argtypes = [c_vp]
+    L.qn_destroy.argtypes = [c_vp]
+    L.qn_destroy.restype = None
+    L.qn_last_error.argtypes = []
+    L.qn_last_error.restype = ctypes.c_char_p
+    for name in ("qn_setup", "qn_workspace_bytes", "qn_bind_workspace", "qn_set_stream",
+                 "qn_residual", "qn_fdm_solve", "qn_iterate", "qn_timing_count",
+                 "qn_timing_read", "qn_timing_reset"):
+        getattr(L, name).restype = c_i32
+    _lib = L
+    return L
+
+
+def last_error():
+    return lib().qn_last_error().decode()
+
+
+def check(status):
+    if status != QN_OK:
+        raise QNError(status, last_error())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class Solver:
+    """One problem instance: grid, nonlinearity, shift rule and precision.
+
+    shape: array shape of one component, (ny, nx) or (nz, ny, nx), interior
+    nodes.  Field tensors passed to the methods are float64, contiguous, on
+    the GPU, with shape (ncomp,) + shape.
+    """
+
+    def __init__(self, shape, nonlinearity="cubic", beta=0.0, beta_mode="fixed",
+                 precision="fp64", timing=False, device="cuda"):
+        L = lib()
+        self.shape = tuple(int(s) for s in shape)
+        self.dim = len(self.shape)
+        self.nl = nonlinearity
+        self.ncomp = 2 if nonlinearity == "system" else 1
+        self.device = torch.device(device)
+        g = QNGrid()
+        g.dim = self.dim
+        rev = list(reversed(self.shape)) + [1] * (3 - self.dim)
+        for a in range(3):
+            g.n[a] = rev[a]
+        g.ncomp = self.ncomp
+        o = QNOptions()
+        o.precision = PRECISIONS[precision]
+        o.beta_mode = BETA_MODES[beta_mode]
+        o.timing = 1 if timing else 0
+        o.stream = None
+        ctx = c_vp()
+        check(L.qn_setup(ctypes.byref(g), float(beta), NONLINEARITIES[nonlinearity],
+                         ctypes.byref(o), ctypes.byref(ctx)))
+        self._ctx = ctx
+        nbytes = ctypes.c_size_t()
+        check(L.qn_workspace_bytes(ctx, ctypes.byref(nbytes)))
+        self.workspace_bytes = nbytes.value
+        self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        self._sync_stream()
+        check(L.qn_bind_workspace(ctx, _ptr(self._ws), self.workspace_bytes))
+
+    # -- helpers
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        check(lib().qn_set_stream(self._ctx, ctypes.c_void_p(s)))
+
+    def _field(self, t, name):
+        want = (self.ncomp,) + self.shape
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+            raise ValueError(f"{name} must be a float64 CUDA tensor")
+        if tuple(t.shape) != want or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {want}, got {tuple(t.shape)}")
+        return t
+
+    def empty(self):
+        return torch.empty((self.ncomp,) + self.shape, dtype=torch.float64, device=self.device)
+
+    # -- entry points
+    def residual(self, U, F, R=None, red=None):
+        """R = F^h(U); red (optional, float64[4] CUDA) gets {sum R^2, min mu, max mu, sum F^2}."""
+        self._field(U, "U")
+        self._field(F, "F")
+        R = self.empty() if R is None else self._field(R, "R")
+        self._sync_stream()
+        check(lib().qn_residual(self._ctx, _ptr(U), _ptr(F), _ptr(R), _ptr(red)))
+        return R
+
+    def fdm_solve(self, R, scale=1.0, shift=0.0, X=None):
+        """X = (scale A_h + shift I)^-1 R per component."""
+        self._field(R, "R")
+        X = self.empty() if X is None else self._field(X, "X")
+        self._sync_stream()
+        check(lib().qn_fdm_solve(self._ctx, _ptr(R), float(scale), float(shift), _ptr(X)))
+        return X
+
+    def iterate(self, U, F, rtol=1e-10, max_iter=200, raise_on_error=False):
+        """Run the quasi-Newton iteration in place on U; returns a stats dict."""
+        self._field(U, "U")
+        self._field(F, "F")
+        self._sync_stream()
+        st = QNStats()
+        status = lib().qn_iterate(self._ctx, _ptr(U), _ptr(F), float(rtol), int(max_iter),
+                                  ctypes.byref(st))
+        if status in (QN_ERR_INVALID, QN_ERR_HIP, QN_ERR_WORKSPACE, QN_ERR_UNSUPPORTED) or (
+                raise_on_error and status != QN_OK):
+            check(status)
+        return {"status": status, "iters": st.iters, "relres": st.relres, "relres0": st.relres0,
+                "beta_last": st.beta_last, "scale_last": st.scale_last, "seconds": st.seconds,
+                "message": last_error() if status != QN_OK else ""}
+
+    def timing(self, reset=False):
+        """{kernel name: (launches, total ms)} for timing-enabled solvers."""
+        L = lib()
+        out = {}
+        for i in range(L.qn_timing_count()):
+            name = ctypes.c_char_p()
+            n = ctypes.c_int64()
+            ms = c_dbl()
+            check(L.qn_timing_read(self._ctx, i, ctypes.byref(name), ctypes.byref(n),
+                                   ctypes.byref(ms)))
+            out[name.value.decode()] = (n.value, ms.value)
+        if reset:
+            check(L.qn_timing_reset(self._ctx))
+        return out
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().qn_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,619 @@
+// Host side of libqn: the C ABI declared in include/qn.h.
+//
+// A context holds the grid, the closed-form 1D eigen-data per axis (computed
+// on the host at setup, uploaded into the caller-bound workspace), and the
+// per-iteration kernel sequence:
+//   residual + reductions -> finalize (norms, shift rule on device)
+//   -> forward mode products x, y(, z) with the spectral divide fused into the
+//   last one -> inverse mode products (z,) y, x with U -= dU fused into the
+//   last one (Section 4.1 eq. fin_inverse, Section 4 eq. identity-method).
+// All work is enqueued on the context's stream; qn_iterate reads four
+// scalars back per iteration to test the stopping rule.
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/qn.h"
+#include "qn_internal.h"
+
+using namespace qn;
+
+namespace {
+
+thread_local std::string g_err;
+
+qn_status fail(qn_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+enum KernelId {
+  K_RESIDUAL = 0,
+  K_FINALIZE,
+  K_GEMM_X,
+  K_GEMM_YZ,
+  K_GEMM_DIVIDE,
+  K_GEMM_X_UPDATE,
+  K_PAD_COPY,
+  K_COUNT
+};
+const char* const kKernelNames[K_COUNT] = {"residual",     "finalize",      "gemm_x",
+                                           "gemm_yz",      "gemm_divide",   "gemm_x_update",
+                                           "pad_copy"};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float bf16_to_float(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+int pick_tile(long long extent) {
+  if (extent % 128 == 0) return 128;
+  if (extent % 64 == 0) return 64;
+  return 32;
+}
+
+struct Pending {
+  int kid;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct qn_ctx_s {
+  int dim = 3, ncomp = 1, nl = 0, prec = 0, beta_mode = 0, timing = 0;
+  int n[3] = {1, 1, 1};  // interior x, y, z (z = 1 in 2D)
+  int p[3] = {32, 32, 1};
+  double beta = 0.0;
+  double lam_min_sum = 0.0;
+  hipStream_t stream = nullptr;
+  std::vector<double> hS[3], hlam[3];
+  // workspace layout (byte offsets)
+  size_t off_S[3] = {0, 0, 0}, off_Slo[3] = {0, 0, 0}, off_lam[3] = {0, 0, 0};
+  size_t off_W1 = 0, off_W2 = 0, off_part = 0, off_scal = 0, off_coef = 0, need = 0;
+  int max_blocks = 0;
+  char* ws = nullptr;
+  hipError_t sticky = hipSuccess;
+  // timing
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  double tot_ms[K_COUNT] = {};
+  long long launches[K_COUNT] = {};
+
+  size_t elem() const { return prec == QN_PREC_FP64 ? 8 : 4; }
+  size_t tensor_elems() const { return (size_t)ncomp * p[2] * p[1] * p[0]; }
+  template <typename T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  DevScalars* scal() const { return at<DevScalars>(off_scal); }
+};
+
+namespace {
+
+qn_status check_ctx(qn_ctx c, bool need_ws) {
+  if (!c) return fail(QN_ERR_INVALID, "null context");
+  if (c->sticky != hipSuccess)
+    return fail(QN_ERR_HIP, "context has a sticky HIP error: %s", hipGetErrorString(c->sticky));
+  if (need_ws && !c->ws) return fail(QN_ERR_WORKSPACE, "workspace not bound");
+  return QN_OK;
+}
+
+qn_status hip_fail(qn_ctx c, hipError_t e, const char* what) {
+  c->sticky = e;
+  return fail(QN_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
+
+hipEvent_t take_event(qn_ctx c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch `fn` bracketed by timing events when the context asks for them.
+template <typename Fn>
+hipError_t timed(qn_ctx c, int kid, Fn fn) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (c->timing) {
+    a = take_event(c);
+    b = take_event(c);
+    if (a) hipEventRecord(a, c->stream);
+  }
+  hipError_t e = fn();
+  if (c->timing && a && b) {
+    hipEventRecord(b, c->stream);
+    c->pending.push_back({kid, a, b});
+  }
+  return e;
+}
+
+void fold_timing(qn_ctx c) {
+  if (c->pending.empty()) return;
+  hipStreamSynchronize(c->stream);
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->tot_ms[p.kid] += ms;
+      c->launches[p.kid] += 1;
+    }
+    c->pool.push_back(p.a);
+    c->pool.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
+// Closed-form eigenpairs of h^-2 tridiag(-1, 2, -1) of order n (Section 3.2
+// eq. Sy; Section 4.2 with M = I): S[j][k] = sqrt(2/(n+1)) sin(j k pi/(n+1)),
+// lam_k = 4 (n+1)^2 sin^2(k pi / (2(n+1))), stored zero-padded to p x p; the
+// padded eigenvalues repeat lam_n so padded denominators stay positive.
+void eigen_1d(int n, int p, std::vector<double>& S, std::vector<double>& lam) {
+  const long long m = n + 1;
+  const double pi = 3.14159265358979323846;
+  S.assign((size_t)p * p, 0.0);
+  lam.assign((size_t)p, 0.0);
+  const double nrm = std::sqrt(2.0 / (double)m);
+  for (int j = 1; j <= n; ++j)
+    for (int k = 1; k <= n; ++k) {
+      const long long red = ((long long)j * k) % (2 * m);
+      S[(size_t)(j - 1) * p + (k - 1)] = nrm * std::sin(pi * (double)red / (double)m);
+    }
+  for (int k = 1; k <= n; ++k) {
+    const double s = std::sin(pi * k / (2.0 * m));
+    lam[k - 1] = 4.0 * (double)(m * m) * s * s;
+  }
+  for (int k = n; k < p; ++k) lam[k] = lam[n - 1];
+}
+
+int rule_of(qn_ctx c) {
+  if (c->nl == QN_NL_QUASILIN) return RULE_COEFF_MID;
+  return c->beta_mode == QN_BETA_MIDPOINT ? RULE_MIDPOINT : RULE_FIXED;
+}
+
+GemmOperands operands(qn_ctx c, int axis) {
+  GemmOperands g{};
+  if (c->prec == QN_PREC_BF16X3) {
+    g.Shi = c->ws + c->off_S[axis];
+    g.Slo = c->ws + c->off_Slo[axis];
+  } else {
+    g.S = c->ws + c->off_S[axis];
+  }
+  return g;
+}
+
+// Residual of U into the padded transform workspace W1 (+ partials), then
+// the on-device finalize with the context's shift rule.
+hipError_t residual_into_ws(qn_ctx c, const double* U, const double* F, double* red_out) {
+  ResidualArgs a{};
+  a.U = U;
+  a.F = F;
+  a.R = c->ws + c->off_W1;
+  a.out_prec = c->prec == QN_PREC_FP64 ? 0 : 1;
+  a.r_cstride = (long long)c->p[2] * c->p[1] * c->p[0];
+  a.r_zstride = c->p[1] * c->p[0];
+  a.r_ystride = c->p[0];
+  a.ox = c->p[0];
+  a.oy = c->p[1];
+  a.oz = c->p[2];
+  a.nx = c->n[0];
+  a.ny = c->n[1];
+  a.nz = c->n[2];
+  a.dim = c->dim;
+  a.nl = c->nl;
+  a.ihx2 = (double)(c->n[0] + 1) * (c->n[0] + 1);
+  a.ihy2 = (double)(c->n[1] + 1) * (c->n[1] + 1);
+  a.ihz2 = c->dim == 3 ? (double)(c->n[2] + 1) * (c->n[2] + 1) : 0.0;
+  a.partials = c->at<double>(c->off_part);
+  int nb = 0;
+  hipError_t e = timed(c, K_RESIDUAL, [&] { return launch_residual(a, &nb, c->stream); });
+  if (e != hipSuccess) return e;
+  return timed(c, K_FINALIZE, [&] {
+    return launch_finalize(a.partials, nb, c->scal(), rule_of(c), c->beta, c->lam_min_sum, red_out,
+                           c->stream);
+  });
+}
+
+// The tensor-product solve of the padded tensor in W1 with coefficients
+// coef = {scale, beta} (device); the result goes to `dense` with epilogue
+// epi_last (EPI_SUB_DENSE: U -= X, EPI_STORE_DENSE: X).
+hipError_t solve_ws(qn_ctx c, const double* coef, double* dense, int epi_last) {
+  void* W1 = c->ws + c->off_W1;
+  void* W2 = c->ws + c->off_W2;
+  const int px = c->p[0], py = c->p[1], pz = c->p[2];
+  const int pr = c->prec;
+  EpiArgs ep{};
+  ep.coef = coef;
+  ep.dense = dense;
+  ep.px = px;
+  ep.py = py;
+  ep.pz = pz;
+  ep.nx = c->n[0];
+  ep.ny = c->n[1];
+  ep.nz = c->n[2];
+  ep.lamX = c->at<double>(c->off_lam[0]);
+  const GemmOperands Sx = operands(c, 0), Sy = operands(c, 1), Sz = operands(c, 2);
+  const int rows = c->ncomp * pz * py;
+  const int tmx = pick_tile(rows), tnx = pick_tile(px);
+  const int tmy = pick_tile(py), tny = pick_tile(px);
+  const long long yslab = (long long)py * px;
+  hipError_t e;
+#define QN_TRY(x)               \
+  do {                          \
+    e = (x);                    \
+    if (e != hipSuccess) return e; \
+  } while (0)
+  // forward x
+  QN_TRY(timed(c, K_GEMM_X, [&] {
+    return launch_gemm_right(pr, Sx, W1, W2, rows, px, EPI_STORE, ep, tmx, tnx, c->stream);
+  }));
+  if (c->dim == 2) {
+    EpiArgs ed = ep;
+    ed.lamM = c->at<double>(c->off_lam[1]);
+    ed.lamY = nullptr;
+    QN_TRY(timed(c, K_GEMM_DIVIDE, [&] {
+      return launch_gemm_left(pr, Sy, W2, W1, py, px, c->ncomp, yslab, EPI_DIVIDE, ed, tmy, tny,
+                              c->stream);
+    }));
+    QN_TRY(timed(c, K_GEMM_YZ, [&] {
+      return launch_gemm_left(pr, Sy, W1, W2, py, px, c->ncomp, yslab, EPI_STORE, ep, tmy, tny,
+                              c->stream);
+    }));
+  } else {
+    const long long zslab = (long long)pz * py * px;
+    const int tmz = pick_tile(pz), tnz = pick_tile(yslab);
+    QN_TRY(timed(c, K_GEMM_YZ, [&] {
+      return launch_gemm_left(pr, Sy, W2, W1, py, px, c->ncomp * pz, yslab, EPI_STORE, ep, tmy,
+                              tny, c->stream);
+    }));
+    EpiArgs ed = ep;
+    ed.lamM = c->at<double>(c->off_lam[2]);
+    ed.lamY = c->at<double>(c->off_lam[1]);
+    QN_TRY(timed(c, K_GEMM_DIVIDE, [&] {
+      return launch_gemm_left(pr, Sz, W1, W2, pz, (int)yslab, c->ncomp, zslab, EPI_DIVIDE, ed,
+                              tmz, tnz, c->stream);
+    }));
+    QN_TRY(timed(c, K_GEMM_YZ, [&] {
+      return launch_gemm_left(pr, Sz, W2, W1, pz, (int)yslab, c->ncomp, zslab, EPI_STORE, ep, tmz,
+                              tnz, c->stream);
+    }));
+    QN_TRY(timed(c, K_GEMM_YZ, [&] {
+      return launch_gemm_left(pr, Sy, W1, W2, py, px, c->ncomp * pz, yslab, EPI_STORE, ep, tmy,
+                              tny, c->stream);
+    }));
+  }
+  // inverse x with the fused dense epilogue
+  QN_TRY(timed(c, K_GEMM_X_UPDATE, [&] {
+    return launch_gemm_right(pr, Sx, W2, nullptr, rows, px, epi_last, ep, tmx, tnx, c->stream);
+  }));
+#undef QN_TRY
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const qn_options* opt,
+                   qn_ctx* out) {
+  if (!grid || !out) return fail(QN_ERR_INVALID, "null grid or output pointer");
+  if (grid->dim != 2 && grid->dim != 3) return fail(QN_ERR_INVALID, "dim must be 2 or 3");
+  for (int a = 0; a < grid->dim; ++a)
+    if (grid->n[a] < 1 || grid->n[a] > 4096)
+      return fail(QN_ERR_INVALID, "n[%d] = %d out of range [1, 4096]", a, grid->n[a]);
+  if (nonlinearity < 0 || nonlinearity > 2) return fail(QN_ERR_INVALID, "unknown nonlinearity");
+  const int want_comp = nonlinearity == QN_NL_SYS2_CUBIC ? 2 : 1;
+  if (grid->ncomp != want_comp)
+    return fail(QN_ERR_INVALID, "ncomp = %d but the nonlinearity needs %d", grid->ncomp,
+                want_comp);
+  qn_options o{};
+  if (opt) o = *opt;
+  if (o.precision < 0 || o.precision > 2) return fail(QN_ERR_INVALID, "unknown precision");
+  if (o.beta_mode < 0 || o.beta_mode > 1) return fail(QN_ERR_INVALID, "unknown beta_mode");
+  if (nonlinearity == QN_NL_QUASILIN && o.beta_mode == QN_BETA_MIDPOINT)
+    return fail(QN_ERR_INVALID, "the quasi-linear problem uses the coefficient midpoint rule "
+                                "and a fixed beta; QN_BETA_MIDPOINT is not accepted");
+  if (!std::isfinite(beta)) return fail(QN_ERR_INVALID, "beta is not finite");
+
+  qn_ctx c = new qn_ctx_s();
+  c->dim = grid->dim;
+  c->ncomp = grid->ncomp;
+  c->nl = nonlinearity;
+  c->prec = o.precision;
+  c->beta_mode = o.beta_mode;
+  c->timing = o.timing;
+  c->beta = beta;
+  c->stream = (hipStream_t)o.stream;
+  c->n[0] = grid->n[0];
+  c->n[1] = grid->n[1];
+  c->n[2] = grid->dim == 3 ? grid->n[2] : 1;
+  for (int a = 0; a < 3; ++a) c->p[a] = (a < c->dim) ? ((c->n[a] + 31) / 32) * 32 : 1;
+  c->lam_min_sum = 0.0;
+  for (int a = 0; a < c->dim; ++a) {
+    eigen_1d(c->n[a], c->p[a], c->hS[a], c->hlam[a]);
+    c->lam_min_sum += c->hlam[a][0];
+  }
+  // The fixed beta must give a positive definite solve operator (Section 5:
+  // beta > -lam_min(A_h)).  The midpoint rules produce beta >= 0 here.
+  if (o.beta_mode == QN_BETA_FIXED && c->lam_min_sum + beta <= 0.0) {
+    const double lmin = c->lam_min_sum;
+    delete c;
+    return fail(QN_ERR_INVALID, "beta = %g makes A_h + beta I singular or indefinite "
+                                "(lam_min(A_h) = %g)", beta, lmin);
+  }
+
+  size_t off = 0;
+  for (int a = 0; a < c->dim; ++a) {
+    const size_t pp = (size_t)c->p[a] * c->p[a];
+    const size_t eb = c->prec == QN_PREC_FP64 ? 8 : (c->prec == QN_PREC_FP32 ? 4 : 2);
+    c->off_S[a] = off;
+    off += align256(pp * eb);
+    if (c->prec == QN_PREC_BF16X3) {
+      c->off_Slo[a] = off;
+      off += align256(pp * 2);
+    }
+    c->off_lam[a] = off;
+    off += align256((size_t)c->p[a] * 8);
+  }
+  if (c->dim == 2) {  // unused z axis aliases y (never read)
+    c->off_S[2] = c->off_S[1];
+    c->off_Slo[2] = c->off_Slo[1];
+    c->off_lam[2] = c->off_lam[1];
+  }
+  c->off_W1 = off;
+  off += align256(c->tensor_elems() * c->elem());
+  c->off_W2 = off;
+  off += align256(c->tensor_elems() * c->elem());
+  c->max_blocks = residual_max_blocks(c->dim, c->p[0], c->p[1], c->p[2]);
+  c->off_part = off;
+  off += align256((size_t)c->max_blocks * 4 * sizeof(double));
+  c->off_scal = off;
+  off += align256(sizeof(DevScalars));
+  c->off_coef = off;
+  off += align256(2 * sizeof(double));
+  c->need = off;
+  *out = c;
+  return QN_OK;
+}
+
+qn_status qn_workspace_bytes(qn_ctx ctx, size_t* bytes) {
+  if (!ctx || !bytes) return fail(QN_ERR_INVALID, "null argument");
+  *bytes = ctx->need;
+  return QN_OK;
+}
+
+qn_status qn_bind_workspace(qn_ctx c, void* d_ws, size_t bytes) {
+  qn_status s = check_ctx(c, false);
+  if (s != QN_OK) return s;
+  if (!d_ws) return fail(QN_ERR_WORKSPACE, "null workspace");
+  if (((uintptr_t)d_ws & 255u) != 0) return fail(QN_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (bytes < c->need)
+    return fail(QN_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, c->need);
+  c->ws = (char*)d_ws;
+  hipError_t e = launch_zero(c->ws, c->need, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "zero workspace");
+  for (int a = 0; a < c->dim; ++a) {
+    const size_t pp = (size_t)c->p[a] * c->p[a];
+    if (c->prec == QN_PREC_FP64) {
+      e = hipMemcpyAsync(c->ws + c->off_S[a], c->hS[a].data(), pp * 8, hipMemcpyHostToDevice,
+                         c->stream);
+    } else if (c->prec == QN_PREC_FP32) {
+      std::vector<float> s32(pp);
+      for (size_t i = 0; i < pp; ++i) s32[i] = (float)c->hS[a][i];
+      e = hipMemcpyAsync(c->ws + c->off_S[a], s32.data(), pp * 4, hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // s32 is a host temporary
+    } else {
+      std::vector<uint16_t> hi(pp), lo(pp);
+      for (size_t i = 0; i < pp; ++i) {
+        const double v = c->hS[a][i];
+        hi[i] = bf16_rne((float)v);
+        lo[i] = bf16_rne((float)(v - (double)bf16_to_float(hi[i])));
+      }
+      e = hipMemcpyAsync(c->ws + c->off_S[a], hi.data(), pp * 2, hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(c->ws + c->off_Slo[a], lo.data(), pp * 2, hipMemcpyHostToDevice,
+                           c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->ws + c->off_lam[a], c->hlam[a].data(), (size_t)c->p[a] * 8,
+                         hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "upload eigen-data");
+  }
+  // hS/hlam stay alive in the context, so the async uploads above are safe.
+  return QN_OK;
+}
+
+qn_status qn_set_stream(qn_ctx c, void* stream) {
+  if (!c) return fail(QN_ERR_INVALID, "null context");
+  c->stream = (hipStream_t)stream;
+  return QN_OK;
+}
+
+qn_status qn_residual(qn_ctx c, const double* d_U, const double* d_F, double* d_R, double* d_red) {
+  qn_status s = check_ctx(c, true);
+  if (s != QN_OK) return s;
+  if (!d_U || !d_F || !d_R) return fail(QN_ERR_INVALID, "null U, F or R");
+  if (!aligned8(d_U) || !aligned8(d_F) || !aligned8(d_R) || (d_red && !aligned8(d_red)))
+    return fail(QN_ERR_INVALID, "pointers must be 8-byte aligned");
+  if (d_R == d_U) return fail(QN_ERR_INVALID, "R may not alias U");
+  ResidualArgs a{};
+  a.U = d_U;
+  a.F = d_F;
+  a.R = d_R;
+  a.out_prec = 0;
+  a.r_cstride = (long long)c->n[2] * c->n[1] * c->n[0];
+  a.r_zstride = c->n[1] * c->n[0];
+  a.r_ystride = c->n[0];
+  a.ox = c->n[0];
+  a.oy = c->n[1];
+  a.oz = c->n[2];
+  a.nx = c->n[0];
+  a.ny = c->n[1];
+  a.nz = c->n[2];
+  a.dim = c->dim;
+  a.nl = c->nl;
+  a.ihx2 = (double)(c->n[0] + 1) * (c->n[0] + 1);
+  a.ihy2 = (double)(c->n[1] + 1) * (c->n[1] + 1);
+  a.ihz2 = c->dim == 3 ? (double)(c->n[2] + 1) * (c->n[2] + 1) : 0.0;
+  a.partials = c->at<double>(c->off_part);
+  int nb = 0;
+  hipError_t e = timed(c, K_RESIDUAL, [&] { return launch_residual(a, &nb, c->stream); });
+  if (e == hipSuccess)
+    e = timed(c, K_FINALIZE, [&] {
+      return launch_finalize(a.partials, nb, c->scal(), rule_of(c), c->beta, c->lam_min_sum, d_red,
+                             c->stream);
+    });
+  if (e != hipSuccess) return hip_fail(c, e, "residual launch");
+  return QN_OK;
+}
+
+qn_status qn_fdm_solve(qn_ctx c, const double* d_R, double scale, double shift, double* d_X) {
+  qn_status s = check_ctx(c, true);
+  if (s != QN_OK) return s;
+  if (!d_R || !d_X) return fail(QN_ERR_INVALID, "null R or X");
+  if (!aligned8(d_R) || !aligned8(d_X)) return fail(QN_ERR_INVALID, "pointers must be 8-byte aligned");
+  if (!(scale > 0.0) || !std::isfinite(scale) || !std::isfinite(shift))
+    return fail(QN_ERR_INVALID, "scale must be positive and finite, shift finite");
+  if (scale * c->lam_min_sum + shift <= 0.0)
+    return fail(QN_ERR_INVALID, "scale*lam_min(A_h) + shift = %g <= 0: singular or indefinite",
+                scale * c->lam_min_sum + shift);
+  double* coef = c->at<double>(c->off_coef);
+  hipError_t e = launch_set_coef(coef, scale, shift, c->stream);
+  if (e == hipSuccess)
+    e = timed(c, K_PAD_COPY, [&] {
+      return launch_pad_copy(d_R, c->ws + c->off_W1, c->prec == QN_PREC_FP64 ? 0 : 1, c->ncomp,
+                             c->n[0], c->n[1], c->n[2], c->p[0], c->p[1], c->p[2], c->stream);
+    });
+  if (e == hipSuccess) e = solve_ws(c, coef, d_X, EPI_STORE_DENSE);
+  if (e != hipSuccess) return hip_fail(c, e, "fdm solve launch");
+  return QN_OK;
+}
+
+qn_status qn_iterate(qn_ctx c, double* d_U, const double* d_F, double rtol, int32_t max_iter,
+                     qn_stats* stats) {
+  qn_stats st{};
+  st.status = QN_ERR_INVALID;
+  auto finish = [&](qn_status s) {
+    st.status = s;
+    if (stats) *stats = st;
+    return s;
+  };
+  qn_status s = check_ctx(c, true);
+  if (s != QN_OK) return finish(s);
+  if (!d_U || !d_F) return finish(fail(QN_ERR_INVALID, "null U or F"));
+  if (!aligned8(d_U) || !aligned8(d_F)) return finish(fail(QN_ERR_INVALID, "pointers must be 8-byte aligned"));
+  if (!(rtol >= 0.0) || max_iter < 0) return finish(fail(QN_ERR_INVALID, "rtol < 0 or max_iter < 0"));
+  const auto t0 = std::chrono::steady_clock::now();
+  auto elapsed = [&] {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
+  DevScalars h{};
+  int k = 0;
+  for (;;) {
+    hipError_t e = residual_into_ws(c, d_U, d_F, nullptr);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, c->scal(), sizeof h, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      st.seconds = elapsed();
+      return finish(hip_fail(c, e, "iteration"));
+    }
+    if (k == 0) {
+      if (h.sumsqF == 0.0) {
+        st.seconds = elapsed();
+        return finish(fail(QN_ERR_INVALID, "||F|| = 0: the relative stopping rule is undefined"));
+      }
+      st.relres0 = h.relres;
+    }
+    st.relres = h.relres;
+    st.iters = k;
+    if (!std::isfinite(h.relres) || h.relres > 1e30) {
+      st.seconds = elapsed();
+      return finish(fail(QN_ERR_DIVERGED, "residual became non-finite or exploded at iteration %d", k));
+    }
+    if (h.relres <= rtol) {
+      st.seconds = elapsed();
+      g_err.clear();
+      return finish(QN_OK);
+    }
+    if (k >= max_iter) {
+      st.seconds = elapsed();
+      return finish(fail(QN_ERR_NOT_CONVERGED, "no convergence in %d solves (relres %.3e)", k,
+                         h.relres));
+    }
+    if (h.flag != 0.0) {
+      st.seconds = elapsed();
+      return finish(fail(QN_ERR_DIVERGED, "shift rule produced a singular operator at iteration %d", k));
+    }
+    st.beta_last = h.beta;
+    st.scale_last = h.scale;
+    e = solve_ws(c, &c->scal()->scale, d_U, EPI_SUB_DENSE);
+    if (e != hipSuccess) {
+      st.seconds = elapsed();
+      return finish(hip_fail(c, e, "solve"));
+    }
+    ++k;
+  }
+}
+
+int32_t qn_timing_count(void) { return K_COUNT; }
+
+qn_status qn_timing_read(qn_ctx c, int32_t i, const char** name, int64_t* launches,
+                         double* total_ms) {
+  if (!c) return fail(QN_ERR_INVALID, "null context");
+  if (i < 0 || i >= K_COUNT) return fail(QN_ERR_INVALID, "timing index out of range");
+  fold_timing(c);
+  if (name) *name = kKernelNames[i];
+  if (launches) *launches = c->launches[i];
+  if (total_ms) *total_ms = c->tot_ms[i];
+  return QN_OK;
+}
+
+qn_status qn_timing_reset(qn_ctx c) {
+  if (!c) return fail(QN_ERR_INVALID, "null context");
+  fold_timing(c);
+  for (int i = 0; i < K_COUNT; ++i) {
+    c->tot_ms[i] = 0.0;
+    c->launches[i] = 0;
+  }
+  return QN_OK;
+}
+
+void qn_destroy(qn_ctx c) {
+  if (!c) return;
+  if (!c->pending.empty()) hipStreamSynchronize(c->stream);
+  for (auto& p : c->pending) {
+    hipEventDestroy(p.a);
+    hipEventDestroy(p.b);
+  }
+  for (auto e : c->pool) hipEventDestroy(e);
+  delete c;
+}
+
+const char* qn_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

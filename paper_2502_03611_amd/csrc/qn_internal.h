@@ -1,0 +1,103 @@
+// Internal declarations shared by the HIP kernels and the host API of libqn.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace qn {
+
+// Device-resident scalars of one context.  The residual reduction writes the
+// norms and extreme values; the shift rule writes scale/beta, which the
+// spectral-divide epilogue reads, so no host round trip is needed between
+// the residual and the solve.
+struct DevScalars {
+  double sumsqR;   // sum of squared residual entries
+  double mumin;    // min of the Jacobian-diagonal quantity (see shift rule)
+  double mumax;    // max of it
+  double sumsqF;   // sum of squared source entries
+  double relres;   // sqrt(sumsqR / sumsqF)
+  double scale;    // c_k of the current solve
+  double beta;     // beta_k of the current solve
+  double flag;     // 1 if the solve operator is singular / indefinite
+};
+
+// Shift rules executed on device after the residual reduction.
+enum ShiftRule : int {
+  RULE_FIXED = 0,      // c = 1, beta fixed
+  RULE_MIDPOINT = 1,   // c = 1, beta = (mumin + mumax)/2
+  RULE_COEFF_MID = 2,  // c = (mumin + mumax)/2, beta fixed (quasi-linear)
+};
+
+enum Nonlin : int { NL_CUBIC = 0, NL_QUASILIN = 1, NL_SYS2 = 2 };
+
+// Epilogues of the mode-product GEMMs.
+enum Epi : int {
+  EPI_STORE = 0,        // padded store
+  EPI_DIVIDE = 1,       // padded store of acc / (scale * (lamM + lamX + lamY) + beta)
+  EPI_SUB_DENSE = 2,    // dense[..] -= acc (interior only)
+  EPI_STORE_DENSE = 3,  // dense[..] = acc (interior only)
+};
+
+struct EpiArgs {
+  const double* lamM;   // eigenvalues along the product's own axis (row index m)
+  const double* lamX;   // eigenvalues along x (column index n % px)
+  const double* lamY;   // eigenvalues along y (column index n / px), NULL in 2D
+  const double* coef;   // device {scale, beta} (points into DevScalars or solve slot)
+  double* dense;        // caller array (ncomp, nz, ny, nx) for the dense epilogues
+  int px, py, pz;       // padded extents
+  int nx, ny, nz;       // interior extents
+};
+
+// Host-side launchers (defined in qn_gemm.hip / qn_pointwise.hip).  All take
+// an explicit stream and return the launch status.
+// Form L: C[b][m][n] = sum_k S[m][k] B[b][k][n]  (S symmetric, P x P, ld = P)
+// Form R: C[r][n]    = sum_k A[r][k] S[k][n]     (A rows of length K = P)
+// prec: 0 = fp64 (T = double), 1 = fp32 (T = float), 2 = bf16x3 (T = float,
+// S given as bf16 hi/lo pair in Shi/Slo).
+struct GemmOperands {
+  const void* S;     // fp64 or fp32 matrix, or NULL for bf16x3
+  const void* Shi;   // bf16x3 only
+  const void* Slo;   // bf16x3 only
+};
+
+hipError_t launch_gemm_left(int prec, const GemmOperands& s, const void* B, void* C, int M,
+                            int ncols, int batch, long long bstride, int epi, const EpiArgs& ep,
+                            int tm, int tn, hipStream_t st);
+hipError_t launch_gemm_right(int prec, const GemmOperands& s, const void* A, void* C, int rows,
+                             int K, int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st);
+
+// Residual of the nonlinear problem, written (with zero padding) into the
+// transform workspace or into a dense caller array.  out_prec: 0 fp64, 1 fp32.
+struct ResidualArgs {
+  const double* U;
+  const double* F;
+  void* R;                 // output base
+  int out_prec;            // 0: double, 1: float
+  long long r_cstride;     // output stride between components
+  int r_zstride, r_ystride;// output strides of z and y (x stride 1)
+  int ox, oy, oz;          // output extents to cover (padded or interior)
+  int nx, ny, nz;          // interior extents (nz = 1 in 2D)
+  int dim, nl;
+  double ihx2, ihy2, ihz2; // 1/h^2 per axis
+  double* partials;        // per-block {sumR2, mumin, mumax, sumF2}
+};
+hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t st);
+int residual_max_blocks(int dim, int ox, int oy, int oz);
+
+// Fixed-order reduction of the residual partials + shift rule.
+hipError_t launch_finalize(const double* partials, int nblocks, DevScalars* sc, int rule,
+                           double beta_fixed, double lam_min_sum, double* red_out,
+                           hipStream_t st);
+
+// Dense (ncomp, nz, ny, nx) fp64 -> padded (ncomp, pz, py, px) fp64/fp32, zero pads.
+hipError_t launch_pad_copy(const double* src, void* dst, int out_prec, int ncomp, int nx, int ny,
+                           int nz, int px, int py, int pz, hipStream_t st);
+// Write {scale, beta} into a device slot.
+hipError_t launch_set_coef(double* slot, double scale, double beta, hipStream_t st);
+// Fill n bytes with zero (a kernel, not a memset node).
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+
+}  // namespace qn

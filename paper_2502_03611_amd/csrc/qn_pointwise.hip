@@ -1,0 +1,300 @@
+// Bandwidth-bound passes of the quasi-Newton iteration:
+//  * the residual F^h(U) = A_h vec(U) + N_h(U) (Section 4, eq. F_u) with the
+//    pointwise nonlinearity fused into the stencil pass, the squared norms of
+//    R and F and the extreme values of the Jacobian-diagonal quantity
+//    reduced per workgroup (wave64 shuffles, then LDS across the 4 waves);
+//  * a one-workgroup, fixed-order reduction of those partials that also
+//    evaluates the shift rule on the device (Section 4 midpoint beta;
+//    Section 4.3 eq. eigenvalues for the 2-component system);
+//  * the dense -> padded copy feeding a stand-alone solve.
+//
+// The residual kernel marches along z: each thread owns one (x, y) column of
+// a z-slab and keeps U(z-1), U(z), U(z+1) in registers, so each U value is
+// fetched from memory once for its z-neighbours; x/y neighbours come from the
+// caches.  2D grids are the nz = 1 case with 1/h_z^2 = 0.  Output points
+// outside the interior (padding of the transform workspace) are written as
+// zero on every call, so padding never carries stale values.
+
+#include <cfloat>
+
+#include "qn_internal.h"
+
+namespace qn {
+
+constexpr int RX = 64, RY = 4, RZ = 16;  // residual block (x, y) and z-slab depth
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Reduce (s0, mn, mx, s1) over a 256-thread block; thread 0 gets the result.
+__device__ inline void block_reduce4(double& s0, double& mn, double& mx, double& s1) {
+  __shared__ double red[4][4];
+  const int lane = threadIdx.x + blockDim.x * threadIdx.y;
+  const int w = lane >> 6, l = lane & 63;
+  s0 = wave_sum(s0);
+  mn = wave_min(mn);
+  mx = wave_max(mx);
+  s1 = wave_sum(s1);
+  if (l == 0) {
+    red[w][0] = s0;
+    red[w][1] = mn;
+    red[w][2] = mx;
+    red[w][3] = s1;
+  }
+  __syncthreads();
+  if (lane == 0) {
+    for (int i = 1; i < 4; ++i) {
+      s0 += red[i][0];
+      mn = fmin(mn, red[i][1]);
+      mx = fmax(mx, red[i][2]);
+      s1 += red[i][3];
+    }
+  }
+}
+
+template <typename TO>
+__device__ inline void put(void* base, long long idx, double v) {
+  reinterpret_cast<TO*>(base)[idx] = (TO)v;
+}
+
+template <int NL, typename TO>
+__global__ __launch_bounds__(256) void k_residual(ResidualArgs a) {
+  const int x = blockIdx.x * RX + threadIdx.x;
+  const int y = blockIdx.y * RY + threadIdx.y;
+  const int z0 = blockIdx.z * RZ;
+  const int z1 = min(z0 + RZ, a.oz);
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const long long plane = (long long)nx * ny;
+  const long long comp = plane * nz;
+  const bool in_xy = (x < nx) && (y < ny);
+  const bool out_xy = (x < a.ox) && (y < a.oy);
+  constexpr int NC = (NL == NL_SYS2) ? 2 : 1;
+
+  double s_r = 0.0, s_f = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
+  double um[NC], uc[NC];
+  const long long col = (long long)y * nx + x;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    um[c] = (in_xy && z0 > 0 && z0 - 1 < nz) ? a.U[c * comp + (long long)(z0 - 1) * plane + col] : 0.0;
+    uc[c] = (in_xy && z0 < nz) ? a.U[c * comp + (long long)z0 * plane + col] : 0.0;
+  }
+  for (int z = z0; z < z1; ++z) {
+    double up[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      up[c] = (in_xy && z + 1 < nz) ? a.U[c * comp + (long long)(z + 1) * plane + col] : 0.0;
+    if (in_xy && z < nz) {
+      const long long p = (long long)z * plane + col;
+      double r[NC];
+      if (NL == NL_QUASILIN) {
+        const double* U = a.U;
+        const double u = uc[0];
+        const double ac = 1.0 + u * u;
+        const double n_xm = x > 0 ? U[p - 1] : 0.0, n_xp = x + 1 < nx ? U[p + 1] : 0.0;
+        const double n_ym = y > 0 ? U[p - nx] : 0.0, n_yp = y + 1 < ny ? U[p + nx] : 0.0;
+        const double n_zm = um[0], n_zp = up[0];
+        auto flux = [&](double un) { return 0.5 * (ac + (1.0 + un * un)) * (u - un); };
+        const double lx = (flux(n_xm) + flux(n_xp)) * a.ihx2;
+        const double ly = (flux(n_ym) + flux(n_yp)) * a.ihy2;
+        const double lz = (flux(n_zm) + flux(n_zp)) * a.ihz2;
+        const double f = a.F[p];
+        r[0] = lx + ly + lz - f;
+        s_f += f * f;
+        mn = fmin(mn, ac);
+        mx = fmax(mx, ac);
+      } else {
+        double lap[NC], f[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const double* U = a.U + c * comp;
+          const double u = uc[c];
+          const double n_xm = x > 0 ? U[p - 1] : 0.0, n_xp = x + 1 < nx ? U[p + 1] : 0.0;
+          const double n_ym = y > 0 ? U[p - nx] : 0.0, n_yp = y + 1 < ny ? U[p + nx] : 0.0;
+          lap[c] = (2.0 * u - n_xm - n_xp) * a.ihx2 + (2.0 * u - n_ym - n_yp) * a.ihy2 +
+                   (2.0 * u - um[c] - up[c]) * a.ihz2;
+          f[c] = a.F[c * comp + p];
+          s_f += f[c] * f[c];
+        }
+        if (NL == NL_CUBIC) {
+          const double u = uc[0];
+          r[0] = lap[0] + u * u * u - f[0];
+          const double fu = 3.0 * u * u;
+          mn = fmin(mn, fu);
+          mx = fmax(mx, fu);
+        } else {
+          const double u = uc[0], v = uc[NC - 1];
+          r[0] = lap[0] + u * u * u - v - f[0];
+          r[NC - 1] = lap[NC - 1] + v * v * v - u - f[NC - 1];
+          // 2x2 block [[3u^2, -1], [-1, 3v^2]]: eigenvalues (a+d -+ sqrt((a-d)^2 + 4)) / 2
+          const double ea = 3.0 * u * u, ed = 3.0 * v * v;
+          const double disc = sqrt((ea - ed) * (ea - ed) + 4.0);
+          mn = fmin(mn, 0.5 * (ea + ed - disc));
+          mx = fmax(mx, 0.5 * (ea + ed + disc));
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        s_r += r[c] * r[c];
+        const long long o = c * a.r_cstride + (long long)z * a.r_zstride + (long long)y * a.r_ystride + x;
+        put<TO>(a.R, o, r[c]);
+      }
+    } else if (out_xy) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const long long o = c * a.r_cstride + (long long)z * a.r_zstride + (long long)y * a.r_ystride + x;
+        put<TO>(a.R, o, 0.0);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      um[c] = uc[c];
+      uc[c] = up[c];
+    }
+  }
+
+  block_reduce4(s_r, mn, mx, s_f);
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    const long long bid = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    double* pp = a.partials + 4 * bid;
+    pp[0] = s_r;
+    pp[1] = mn;
+    pp[2] = mx;
+    pp[3] = s_f;
+  }
+}
+
+static dim3 residual_grid(int ox, int oy, int oz) {
+  return dim3((ox + RX - 1) / RX, (oy + RY - 1) / RY, (oz + RZ - 1) / RZ);
+}
+
+int residual_max_blocks(int dim, int ox, int oy, int oz) {
+  (void)dim;
+  const dim3 g = residual_grid(ox, oy, oz);
+  return (int)(g.x * g.y * g.z);
+}
+
+template <int NL>
+static void launch_nl(const ResidualArgs& a, dim3 g, hipStream_t st) {
+  if (a.out_prec == 0)
+    hipLaunchKernelGGL((k_residual<NL, double>), g, dim3(RX, RY), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_residual<NL, float>), g, dim3(RX, RY), 0, st, a);
+}
+
+hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t st) {
+  const dim3 g = residual_grid(a.ox, a.oy, a.oz);
+  *nblocks_out = (int)(g.x * g.y * g.z);
+  switch (a.nl) {
+    case NL_CUBIC: launch_nl<NL_CUBIC>(a, g, st); break;
+    case NL_QUASILIN: launch_nl<NL_QUASILIN>(a, g, st); break;
+    default: launch_nl<NL_SYS2>(a, g, st); break;
+  }
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partials, int nblocks,
+                                                  DevScalars* sc, int rule, double beta_fixed,
+                                                  double lam_min_sum, double* red_out) {
+  double s0 = 0.0, s1 = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
+  for (int i = threadIdx.x; i < nblocks; i += 256) {
+    s0 += partials[4 * i + 0];
+    mn = fmin(mn, partials[4 * i + 1]);
+    mx = fmax(mx, partials[4 * i + 2]);
+    s1 += partials[4 * i + 3];
+  }
+  block_reduce4(s0, mn, mx, s1);
+  if (threadIdx.x == 0) {
+    double scale = 1.0, beta = beta_fixed;
+    if (rule == RULE_MIDPOINT) beta = 0.5 * (mn + mx);
+    if (rule == RULE_COEFF_MID) scale = 0.5 * (mn + mx);
+    sc->sumsqR = s0;
+    sc->mumin = mn;
+    sc->mumax = mx;
+    sc->sumsqF = s1;
+    sc->relres = sqrt(s0) / sqrt(s1);
+    sc->scale = scale;
+    sc->beta = beta;
+    sc->flag = (scale > 0.0 && scale * lam_min_sum + beta > 0.0) ? 0.0 : 1.0;
+    if (red_out) {
+      red_out[0] = s0;
+      red_out[1] = mn;
+      red_out[2] = mx;
+      red_out[3] = s1;
+    }
+  }
+}
+
+hipError_t launch_finalize(const double* partials, int nblocks, DevScalars* sc, int rule,
+                           double beta_fixed, double lam_min_sum, double* red_out,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partials, nblocks, sc, rule,
+                     beta_fixed, lam_min_sum, red_out);
+  return hipGetLastError();
+}
+
+template <typename TO>
+__global__ __launch_bounds__(256) void k_pad_copy(const double* __restrict__ src, TO* __restrict__ dst,
+                                                  int nx, int ny, int nz, int px, int py, int pz) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  const int zc = blockIdx.z;  // c * pz + z
+  const int z = zc % pz, c = zc / pz;
+  if (x >= px || y >= py) return;
+  double v = 0.0;
+  if (x < nx && y < ny && z < nz)
+    v = src[(((long long)c * nz + z) * ny + y) * nx + x];
+  dst[((long long)zc * py + y) * px + x] = (TO)v;
+}
+
+hipError_t launch_pad_copy(const double* src, void* dst, int out_prec, int ncomp, int nx, int ny,
+                           int nz, int px, int py, int pz, hipStream_t st) {
+  dim3 g((px + 63) / 64, (py + 3) / 4, ncomp * pz);
+  if (out_prec == 0)
+    hipLaunchKernelGGL((k_pad_copy<double>), g, dim3(64, 4), 0, st, src, (double*)dst, nx, ny, nz,
+                       px, py, pz);
+  else
+    hipLaunchKernelGGL((k_pad_copy<float>), g, dim3(64, 4), 0, st, src, (float*)dst, nx, ny, nz,
+                       px, py, pz);
+  return hipGetLastError();
+}
+
+__global__ void k_set_coef(double* slot, double scale, double beta) {
+  slot[0] = scale;
+  slot[1] = beta;
+}
+
+hipError_t launch_set_coef(double* slot, double scale, double beta, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_coef, dim3(1), dim3(1), 0, st, slot, scale, beta);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_zero(uint4* p, size_t n16) {
+  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * 256;
+  for (; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+  // Workspace segments are 256-byte aligned and sized in multiples of 256.
+  const size_t n16 = bytes / 16;
+  if (n16 == 0) return hipSuccess;
+  size_t blocks = (n16 + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, (uint4*)p, n16);
+  return hipGetLastError();
+}
+
+}  // namespace qn
