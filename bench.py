@@ -1,0 +1,180 @@
+"""Benchmark: quasi-Newton iterations per second and time-to-tolerance at 3D 511^3.
+
+Workload: -div((1+u^2) grad u) = f on (0,1)^3, homogeneous Dirichlet data,
+511^3 interior nodes (1.33e8 unknowns), f manufactured from
+u = A sin(pi x) sin(pi y) sin(pi z) with the seeded amplitude A (seed 0), U_0 = 0.
+Inputs are synthetic and resident in HBM before any timed region.
+
+A step is one full quasi-Newton iteration of the hot path: the fused
+residual/nonlinearity/reduction pass, the on-device shift rule, the three
+forward mode products (spectral divide fused into the last), and the three
+inverse mode products (U -= dU fused into the last).  `value` is FP64
+iterations per second over exactly --steps steps, timed with a device
+synchronisation on both sides.  Extra fields report time-to-tolerance (relres
+1e-10) in FP64 and in the reduced-precision transform forms, the roofline of
+the dominant kernel from HIP events recorded around every launch inside the
+timed region, and the CPU oracle timed on a bounded sample.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from paper_2502_03611_amd import Solver  # noqa: E402
+
+METRIC = "time-to-tol & iters/s at 3D 511^3, FP64 vs mixed+learned guess; % MFMA/HBM peak"
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n, amp):
+    """The CPU oracle, as it stands, on a bounded sample: one quasi-Newton
+    iteration (residual, shift rule, tensor-product solve, residual) at the
+    same 511^3 workload.  Returns iterations per second."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import qn as oqn
+
+    _, f = synth.manufactured_c3(n, amp)
+    log("cpu baseline: one oracle iteration")
+    t0 = time.perf_counter()
+    oqn.qn_solve(oqn.QUASILINEAR, f[None], rtol=0.0, max_iter=1)
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"value": 1.0 / dt, "unit": "iters/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"1 quasi-Newton iteration of the same 511^3 quasi-linear workload "
+                      f"(NumPy FP64 oracle, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=511)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-time-to-tol", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "decomposition of this solver is not built", file=sys.stderr)
+        sys.exit(2)
+
+    n = args.n
+    amp = synth.amplitude_c3(0)
+    log(f"generating inputs n={n}")
+    u_ex, f = synth.manufactured_c3(n, amp)
+    F = torch.from_numpy(f[None]).cuda()
+    del f
+    shape = (n, n, n)
+
+    log("timed FP64 steps")
+    solver = Solver(shape, "quasilinear", beta=0.0, precision="fp64", timing=True)
+    U = torch.zeros((1,) + shape, dtype=torch.float64, device="cuda")
+    if args.warmup > 0:
+        solver.iterate(U, F, rtol=0.0, max_iter=args.warmup)
+    torch.cuda.synchronize()
+    solver.timing(reset=True)
+    U.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = solver.iterate(U, F, rtol=0.0, max_iter=args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert st["iters"] == args.steps, st
+    tim = solver.timing(reset=True)
+    value = args.steps / dt
+
+    # dominant kernel: the plain y/z mode product (3 of the 6 products per step)
+    flops_per_product = 2.0 * float(n) ** 4
+    launches, tot_ms = tim["gemm_yz"]
+    avg_ms = tot_ms / max(launches, 1)
+    achieved = flops_per_product / (avg_ms * 1e-3) / 1e12
+    roof = {"bound": "mfma", "kernel": "k_gemm_left<double,128,128,EPI_STORE>",
+            "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+            "avg_launch_ms": round(avg_ms, 4), "launches": launches,
+            "algorithmic_flops_per_launch": flops_per_product}
+    # the residual pass (HBM-bound): read U and F, write R, 8 bytes each
+    rl, rms = tim["residual"]
+    r_avg = rms / max(rl, 1)
+    r_bytes = 24.0 * n ** 3
+    kernels = {k: {"launches": v[0], "avg_ms": round(v[1] / max(v[0], 1), 4)} for k, v in tim.items() if v[0]}
+    all_gemm_ms = sum(tim[k][1] for k in ("gemm_x", "gemm_yz", "gemm_divide", "gemm_x_update"))
+    all_gemm_launches = sum(tim[k][0] for k in ("gemm_x", "gemm_yz", "gemm_divide", "gemm_x_update"))
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (manufactured solution, seeded amplitude)",
+        "config": {"workload": "3D quasi-linear -div((1+u^2) grad u) = f, 511^3 interior, "
+                               "FD Dirichlet, FP64 transforms, U0 = 0",
+                   "n": n, "amplitude": amp, "seed": 0},
+        "roofline": roof,
+        "residual_roofline": {"bound": "hbm", "achieved": round(r_bytes / (r_avg * 1e-3) / 1e9, 1),
+                              "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                              "frac": round(r_bytes / (r_avg * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                              "avg_launch_ms": round(r_avg, 4),
+                              "algorithmic_bytes_per_launch": r_bytes},
+        "all_mode_products_tflops": round(flops_per_product * all_gemm_launches /
+                                          (all_gemm_ms * 1e-3) / 1e12, 3),
+        "kernels": kernels,
+    }
+
+    if not args.no_time_to_tol:
+        ttt = {}
+        u64 = None
+        solver.close()
+        for prec in ("fp64", "fp32", "bf16x3"):
+            log(f"time to tolerance: {prec}")
+            s = Solver(shape, "quasilinear", beta=0.0, precision=prec)
+            U.zero_()
+            s.iterate(U, F, rtol=0.0, max_iter=1)  # untimed warm-up of this context
+            U.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = s.iterate(U, F, rtol=1e-10, max_iter=400)
+            torch.cuda.synchronize()
+            tt = time.perf_counter() - t0
+            Uh = U[0].cpu().numpy()
+            rec = {"status": st["status"], "iters": st["iters"], "time_to_tol_s": round(tt, 4),
+                   "iters_per_s": round(st["iters"] / tt, 2), "relres": st["relres"],
+                   "max_err_vs_exact": float(np.abs(Uh - u_ex).max())}
+            if prec == "fp64":
+                u64 = Uh
+            else:
+                rec["rel_l2_vs_fp64"] = float(np.linalg.norm(Uh - u64) / np.linalg.norm(u64))
+            ttt[prec] = rec
+            s.close()
+        out["time_to_tol"] = ttt
+        out["speedup_fp32_vs_fp64"] = round(ttt["fp64"]["time_to_tol_s"] / ttt["fp32"]["time_to_tol_s"], 3)
+        out["speedup_bf16x3_vs_fp64"] = round(ttt["fp64"]["time_to_tol_s"] / ttt["bf16x3"]["time_to_tol_s"], 3)
+
+    solver.close()
+    del U, F
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(n, amp)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

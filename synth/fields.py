@@ -38,21 +38,16 @@ def manufactured_c2(n):
     """3D -Lap u + u^3 = f, u = sin(pi x) sin(pi y) sin(pi z) exp(x+y+z)/e^3.
 
     Returns (u_exact, f), shape (nz, ny, nx).  With g(t) = sin(pi t) e^t,
-    g'' = e^t ((1 - pi^2) sin(pi t) + 2 pi cos(pi t)).
+    g'' = e^t ((1 - pi^2) sin(pi t) + 2 pi cos(pi t)).  The fields are
+    separable, so the 1D factors are evaluated once and broadcast.
     """
-    z, y, x = _mesh((n, n, n))
-
-    def g(t):
-        return np.sin(math.pi * t) * np.exp(t)
-
-    def g2(t):
-        return np.exp(t) * ((1.0 - math.pi ** 2) * np.sin(math.pi * t)
-                            + 2.0 * math.pi * np.cos(math.pi * t))
-
-    e3 = math.exp(-3.0)
-    gx, gy, gz = g(x), g(y), g(z)
-    u = gx * gy * gz * e3
-    lap = (g2(x) * gy * gz + gx * g2(y) * gz + gx * gy * g2(z)) * e3
+    t = grid_coords(n)
+    g = np.sin(math.pi * t) * np.exp(t - 1.0)
+    g2 = np.exp(t - 1.0) * ((1.0 - math.pi ** 2) * np.sin(math.pi * t)
+                             + 2.0 * math.pi * np.cos(math.pi * t))
+    gz, gy, gx = g[:, None, None], g[None, :, None], g[None, None, :]
+    u = gz * gy * gx
+    lap = g2[:, None, None] * gy * gx + gz * g2[None, :, None] * gx + gz * gy * g2[None, None, :]
     return u, -lap + u ** 3
 
 
@@ -65,14 +60,16 @@ def manufactured_c3(n, amplitude):
     """3D -div((1+u^2) grad u) = f with u = A sin(pi x) sin(pi y) sin(pi z).
 
     -div((1+u^2) grad u) = -(1+u^2) Lap u - 2 u |grad u|^2 and Lap u = -3 pi^2 u,
-    so f = 3 pi^2 u (1+u^2) - 2 u |grad u|^2.  Returns (u_exact, f).
+    so f = 3 pi^2 u (1+u^2) - 2 u |grad u|^2.  Returns (u_exact, f); the 1D
+    factors are evaluated once and broadcast.
     """
-    z, y, x = _mesh((n, n, n))
-    sx, sy, sz = (np.sin(math.pi * t) for t in (x, y, z))
-    cx, cy, cz = (np.cos(math.pi * t) for t in (x, y, z))
-    u = amplitude * sx * sy * sz
+    t = grid_coords(n)
+    s1, c1 = np.sin(math.pi * t), np.cos(math.pi * t)
+    sz, sy, sx = s1[:, None, None], s1[None, :, None], s1[None, None, :]
+    cz, cy, cx = c1[:, None, None], c1[None, :, None], c1[None, None, :]
+    u = amplitude * (sz * sy * sx)
     grad2 = (amplitude * math.pi) ** 2 * (
-        (cx * sy * sz) ** 2 + (sx * cy * sz) ** 2 + (sx * sy * cz) ** 2)
+        (sz * sy * cx) ** 2 + (sz * cy * sx) ** 2 + (cz * sy * sx) ** 2)
     f = 3.0 * math.pi ** 2 * u * (1.0 + u * u) - 2.0 * u * grad2
     return u, f
 
