@@ -15,9 +15,10 @@
 // owns a TM x TN output tile and walks K in chunks of TK, staging both
 // operand chunks in LDS (double buffered, one barrier per chunk).  Each wave
 // computes a (TM/2) x (TN/2) sub-tile as 16 x 16 MFMA blocks.  FP64 uses
-// v_mfma_f64_16x16x4f64, FP32 v_mfma_f32_16x16x4f32.  Operand chunks are
-// stored in LDS k-major ([k][m], [k][n]) so that every A/B fragment read is
-// 16 contiguous elements per 16-lane group.  Tiles are numbered so that
+// v_mfma_f64_16x16x4f64, FP32 v_mfma_f32_16x16x4f32.  Chunks read from S
+// and the form-L tensor chunk are stored in LDS k-major ([k][m], [k][n]), so
+// a fragment read is 16 contiguous elements per 16-lane group; the form-R
+// tensor chunk keeps its [r][k] layout with padded rows.  Tiles are numbered so that
 // neighbours share an operand panel, and the workgroup -> tile map gives each
 // of the 8 XCDs (which receive workgroups round-robin) a contiguous range of
 // tiles, so a panel is fetched into one XCD's L2 and reused there.
@@ -55,19 +56,15 @@ __device__ inline int xcd_tile(int w, int total) {
   return (total % 8 == 0) ? (w % 8) * (total / 8) + (w / 8) : w;
 }
 
-template <typename T>
-__device__ inline void epi_dense(const EpiArgs& ep, int epi, int r, int n, T v) {
+// Padded row r = (c * pz + z) * py + y of a form-R product -> offset of the
+// dense caller row (c, z, y); false for padding rows.
+__device__ inline bool dense_row(const EpiArgs& ep, int r, long long& base) {
   const int y = r % ep.py;
   const int zc = r / ep.py;
   const int z = zc % ep.pz;
   const int c = zc / ep.pz;
-  if (n < ep.nx && y < ep.ny && z < ep.nz) {
-    const long long idx = (((long long)c * ep.nz + z) * ep.ny + y) * ep.nx + n;
-    if (epi == EPI_SUB_DENSE)
-      ep.dense[idx] -= (double)v;
-    else
-      ep.dense[idx] = (double)v;
-  }
+  base = (((long long)c * ep.nz + z) * ep.ny + y) * ep.nx;
+  return y < ep.ny && z < ep.nz;
 }
 
 template <typename T, int TM, int TN, int EPI>
@@ -150,27 +147,41 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left(const T* __restrict__ S,
   }
 
   T* Cb = C + (long long)b * bstride;
-  double scale = 0.0, beta = 0.0;
   if (EPI == EPI_DIVIDE) {
-    scale = ep.coef[0];
-    beta = ep.coef[1];
-  }
+    // d(m, n) = scale * (lamM[m] + lamX[n % px] + lamY[n / px]) + beta; the
+    // column part depends on (j, lane) only, the row part on (i, q) only.
+    const double scale = ep.coef[0], beta = ep.coef[1];
+    double cn[BN];
 #pragma unroll
-  for (int i = 0; i < BM; ++i)
+    for (int j = 0; j < BN; ++j) {
+      const int n = n0 + wn + 16 * j + (lane & 15);
+      const int ny_ = n / ep.px;
+      cn[j] = ep.lamX[n - ny_ * ep.px] + (ep.lamY ? ep.lamY[ny_] : 0.0);
+    }
 #pragma unroll
-    for (int j = 0; j < BN; ++j)
+    for (int i = 0; i < BM; ++i)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int m = m0 + wm + 16 * i + MF::row(lane, q);
-        const int n = n0 + wn + 16 * j + (lane & 15);
-        T v = acc[i][j][q];
-        if (EPI == EPI_DIVIDE) {
-          const double ly = ep.lamY ? ep.lamY[n / ep.px] : 0.0;
-          const double d = scale * (ep.lamM[m] + ep.lamX[n % ep.px] + ly) + beta;
-          v = (T)((double)v / d);
+        const double lm = ep.lamM[m];
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          const int n = n0 + wn + 16 * j + (lane & 15);
+          const double d = scale * (lm + cn[j]) + beta;
+          Cb[(long long)m * ncols + n] = (T)((double)acc[i][j][q] / d);
         }
-        Cb[(long long)m * ncols + n] = v;
       }
+  } else {
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + wm + 16 * i + MF::row(lane, q);
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+          Cb[(long long)m * ncols + n0 + wn + 16 * j + (lane & 15)] = acc[i][j][q];
+      }
+  }
 }
 
 template <typename T, int TM, int TN, int EPI>
@@ -185,10 +196,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right(const T* __restrict__ A,
   constexpr int WM = TM / 2, WN = TN / 2, BM = WM / 16, BN = WN / 16;
   constexpr int NA = TK * TM / (VE * 256), NB = TK * TN / (VE * 256);
   static_assert(NA >= 1 && NB >= 1, "tile too small for 256 threads");
-  // A chunk is transposed on its way into LDS ([k][r]); one element of
-  // padding per k-row spreads the transposing stores over the banks.
-  constexpr int APAD = (sizeof(T) == 8 && TM == 128) ? 0 : 1;
-  __shared__ __attribute__((aligned(16))) T As[2][TK][TM + APAD];
+  // The A chunk keeps its natural [r][k] layout in LDS.  Rows are padded to
+  // TK + 16/sizeof(T) elements (144 bytes for both types): vector stores stay
+  // 16-byte aligned and the 16 rows read by a fragment fall on distinct banks.
+  constexpr int AK = TK + VE;
+  __shared__ __attribute__((aligned(16))) T As[2][TM][AK];
   __shared__ __attribute__((aligned(16))) T Bs[2][TK][TN];
 
   const int MT = rows / TM, NT = K / TN;
@@ -221,8 +233,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right(const T* __restrict__ A,
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int v = tid + 256 * i, row = v / (TK / VE), kv = (v % (TK / VE)) * VE;
-#pragma unroll
-      for (int e = 0; e < VE; ++e) As[buf][kv + e][row] = ra[i][e];
+      *reinterpret_cast<V*>(&As[buf][row][kv]) = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -242,7 +253,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right(const T* __restrict__ A,
     for (int ks = 0; ks < TK; ks += 4) {
       T a[BM], bb[BN];
 #pragma unroll
-      for (int i = 0; i < BM; ++i) a[i] = As[buf][ks + (lane >> 4)][wm + 16 * i + (lane & 15)];
+      for (int i = 0; i < BM; ++i) a[i] = As[buf][wm + 16 * i + (lane & 15)][ks + (lane >> 4)];
 #pragma unroll
       for (int j = 0; j < BN; ++j) bb[j] = Bs[buf][ks + (lane >> 4)][wn + 16 * j + (lane & 15)];
 #pragma unroll
@@ -257,17 +268,28 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right(const T* __restrict__ A,
 #pragma unroll
   for (int i = 0; i < BM; ++i)
 #pragma unroll
-    for (int j = 0; j < BN; ++j)
+    for (int q = 0; q < 4; ++q) {
+      const int r = r0 + wm + 16 * i + MF::row(lane, q);
+      if (EPI == EPI_STORE) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = r0 + wm + 16 * i + MF::row(lane, q);
-        const int n = n0 + wn + 16 * j + (lane & 15);
-        const T v = acc[i][j][q];
-        if (EPI == EPI_STORE)
-          C[(long long)r * K + n] = v;
-        else
-          epi_dense<T>(ep, EPI, r, n, v);
+        for (int j = 0; j < BN; ++j)
+          C[(long long)r * K + n0 + wn + 16 * j + (lane & 15)] = acc[i][j][q];
+      } else {
+        long long base;
+        if (dense_row(ep, r, base)) {
+#pragma unroll
+          for (int j = 0; j < BN; ++j) {
+            const int n = n0 + wn + 16 * j + (lane & 15);
+            if (n < ep.nx) {
+              if (EPI == EPI_SUB_DENSE)
+                ep.dense[base + n] -= (double)acc[i][j][q];
+              else
+                ep.dense[base + n] = (double)acc[i][j][q];
+            }
+          }
+        }
       }
+    }
 }
 
 // ---------------------------------------------------------------- dispatch

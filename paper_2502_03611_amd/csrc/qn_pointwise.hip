@@ -2,7 +2,7 @@
 //  * the residual F^h(U) = A_h vec(U) + N_h(U) (Section 4, eq. F_u) with the
 //    pointwise nonlinearity fused into the stencil pass, the squared norms of
 //    R and F and the extreme values of the Jacobian-diagonal quantity
-//    reduced per workgroup (wave64 shuffles, then LDS across the 4 waves);
+//    reduced per workgroup (wave64 shuffles, then LDS across its waves);
 //  * a one-workgroup, fixed-order reduction of those partials that also
 //    evaluates the shift rule on the device (Section 4 midpoint beta;
 //    Section 4.3 eq. eigenvalues for the 2-component system);
@@ -21,7 +21,7 @@
 
 namespace qn {
 
-constexpr int RX = 64, RY = 4, RZ = 16;  // residual block (x, y) and z-slab depth
+constexpr int RX = 64, RY = 16, RZ = 32;  // residual block (x, y) and z-slab depth
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -39,9 +39,10 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
-// Reduce (s0, mn, mx, s1) over a 256-thread block; thread 0 gets the result.
+// Reduce (s0, mn, mx, s1) over a block of NW wave64s; thread 0 gets the result.
+template <int NW>
 __device__ inline void block_reduce4(double& s0, double& mn, double& mx, double& s1) {
-  __shared__ double red[4][4];
+  __shared__ double red[NW][4];
   const int lane = threadIdx.x + blockDim.x * threadIdx.y;
   const int w = lane >> 6, l = lane & 63;
   s0 = wave_sum(s0);
@@ -56,7 +57,7 @@ __device__ inline void block_reduce4(double& s0, double& mn, double& mx, double&
   }
   __syncthreads();
   if (lane == 0) {
-    for (int i = 1; i < 4; ++i) {
+    for (int i = 1; i < NW; ++i) {
       s0 += red[i][0];
       mn = fmin(mn, red[i][1]);
       mx = fmax(mx, red[i][2]);
@@ -71,7 +72,7 @@ __device__ inline void put(void* base, long long idx, double v) {
 }
 
 template <int NL, typename TO>
-__global__ __launch_bounds__(256) void k_residual(ResidualArgs a) {
+__global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
   const int x = blockIdx.x * RX + threadIdx.x;
   const int y = blockIdx.y * RY + threadIdx.y;
   const int z0 = blockIdx.z * RZ;
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(256) void k_residual(ResidualArgs a) {
     }
   }
 
-  block_reduce4(s_r, mn, mx, s_f);
+  block_reduce4<RX * RY / 64>(s_r, mn, mx, s_f);
   if (threadIdx.x == 0 && threadIdx.y == 0) {
     const long long bid = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     double* pp = a.partials + 4 * bid;
@@ -205,17 +206,20 @@ hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t 
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partials, int nblocks,
-                                                  DevScalars* sc, int rule, double beta_fixed,
-                                                  double lam_min_sum, double* red_out) {
+constexpr int FIN_THREADS = 1024;
+
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double* __restrict__ partials,
+                                                          int nblocks, DevScalars* sc, int rule,
+                                                          double beta_fixed, double lam_min_sum,
+                                                          double* red_out) {
   double s0 = 0.0, s1 = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
-  for (int i = threadIdx.x; i < nblocks; i += 256) {
+  for (int i = threadIdx.x; i < nblocks; i += FIN_THREADS) {
     s0 += partials[4 * i + 0];
     mn = fmin(mn, partials[4 * i + 1]);
     mx = fmax(mx, partials[4 * i + 2]);
     s1 += partials[4 * i + 3];
   }
-  block_reduce4(s0, mn, mx, s1);
+  block_reduce4<FIN_THREADS / 64>(s0, mn, mx, s1);
   if (threadIdx.x == 0) {
     double scale = 1.0, beta = beta_fixed;
     if (rule == RULE_MIDPOINT) beta = 0.5 * (mn + mx);
@@ -240,7 +244,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
 hipError_t launch_finalize(const double* partials, int nblocks, DevScalars* sc, int rule,
                            double beta_fixed, double lam_min_sum, double* red_out,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partials, nblocks, sc, rule,
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, st, partials, nblocks, sc, rule,
                      beta_fixed, lam_min_sum, red_out);
   return hipGetLastError();
 }
