@@ -1,0 +1,84 @@
+/*
+ * qn_batched.h - C ABI of the batched quasi-Newton solver: many independent
+ * 2D instances of uneven size, scalar -Lap u + u^3 = f and 2-component
+ * systems -Lap u + u^3 - v = f1, -Lap v + v^3 - u = f2 (Section 4.3,
+ * eq. system), each iterated with the quasi-Newton step of Section 4
+ * (eq. identity-method) and the tensor-product solve of Section 4.1
+ * (eq. fin_inverse), with one shift beta per instance (midpoint of the
+ * Jacobian-diagonal / 2x2-block eigenvalue range, Section 4.3 eq. eigenvalues,
+ * or a fixed value).
+ *
+ * Execution: instances of equal (n, ncomp) form a class.  One iteration is,
+ * per class, a residual launch, a finalize launch (stopping and shift rules on
+ * the device) and four mode-product launches; the classes run on concurrent
+ * streams.  A number of iterations is captured once in a hipGraph and the
+ * graph is replayed until every instance has stopped; finished instances are
+ * skipped on the device by per-instance flags.  Mode-product tile shapes are
+ * chosen per class by qnb_autotune (measured with HIP events) or by a default
+ * rule.  Transforms run in the chosen precision; residuals, norms, shift rule
+ * and update are FP64.
+ *
+ * Fields: the caller allocates two FP64 device pools (U and F) of
+ * qnb_field_elems() doubles.  Instance i's component c occupies n*n
+ * contiguous doubles (x fastest) at element offset
+ *     offset[i] + c * comp_stride[i]   (qnb_instance_layout).
+ * Workspace, ownership, ordering and errors follow qn.h.
+ */
+#ifndef QN_BATCHED_H
+#define QN_BATCHED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "qn.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qnb_ctx_s* qnb_ctx;
+
+/* Per-instance result of qnb_iterate. */
+typedef struct {
+  int32_t iters;   /* solves performed */
+  int32_t status;  /* QN_OK, QN_ERR_NOT_CONVERGED or QN_ERR_DIVERGED */
+  double relres;   /* ||F^h(U)|| / ||F|| at the returned U */
+  double relres0;  /* same at U_0 */
+} qnb_result;
+
+/* count instances (1..65536); n[i] interior points per side (1..4096);
+ * ncomp[i] in {1, 2}; precision: qn_precision of the transforms; beta_mode
+ * and beta as in qn_setup (applied to every instance).  Host only. */
+qn_status qnb_setup(int32_t count, const int32_t* n, const int32_t* ncomp, int32_t precision,
+                    int32_t beta_mode, double beta, qnb_ctx* out);
+qn_status qnb_field_elems(qnb_ctx ctx, int64_t* elems);
+qn_status qnb_instance_layout(qnb_ctx ctx, int32_t i, int64_t* offset, int64_t* comp_stride);
+qn_status qnb_workspace_bytes(qnb_ctx ctx, size_t* bytes);
+qn_status qnb_bind_workspace(qnb_ctx ctx, void* d_ws, size_t bytes);
+qn_status qnb_set_stream(qnb_ctx ctx, void* stream);
+
+/* Time every admissible tile shape of every class's mode products on the
+ * bound workspace (contents are overwritten) and keep the fastest.
+ * Synchronous. */
+qn_status qnb_autotune(qnb_ctx ctx);
+/* Number of classes, and class k's (n, ncomp, instance count, tile_m, tile_n
+ * of the y products, tile_m, tile_n of the x products). */
+qn_status qnb_class_count(qnb_ctx ctx, int32_t* classes);
+qn_status qnb_class_info(qnb_ctx ctx, int32_t k, int32_t* info8);
+
+/* Iterate every instance from the U pool (in: U_0, out: last iterates) until
+ * relres <= rtol or max_iter solves.  graph_iters iterations are captured per
+ * graph replay (>= 1; the graph is rebuilt when pointers or parameters
+ * change).  results: host array of count entries (may be NULL).  Returns
+ * QN_OK if every instance converged, QN_ERR_NOT_CONVERGED or QN_ERR_DIVERGED
+ * if any did not. */
+qn_status qnb_iterate(qnb_ctx ctx, double* d_U, const double* d_F, double rtol, int32_t max_iter,
+                      int32_t graph_iters, qnb_result* results);
+
+void qnb_destroy(qnb_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QN_BATCHED_H */

@@ -81,6 +81,19 @@ struct Pending {
 
 }  // namespace
 
+namespace qn {
+// Shared with the network's C ABI (qnn_api.cpp): sets the thread-local message.
+qn_status set_error(qn_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+}  // namespace qn
+
 struct qn_ctx_s {
   int dim = 3, ncomp = 1, nl = 0, prec = 0, beta_mode = 0, timing = 0;
   int n[3] = {1, 1, 1};  // interior x, y, z (z = 1 in 2D)
@@ -229,6 +242,7 @@ hipError_t residual_into_ws(qn_ctx c, const double* U, const double* F, double* 
   a.ihy2 = (double)(c->n[1] + 1) * (c->n[1] + 1);
   a.ihz2 = c->dim == 3 ? (double)(c->n[2] + 1) * (c->n[2] + 1) : 0.0;
   a.partials = c->at<double>(c->off_part);
+  a.rz = RESIDUAL_RZ;
   int nb = 0;
   hipError_t e = timed(c, K_RESIDUAL, [&] { return launch_residual(a, &nb, c->stream); });
   if (e != hipSuccess) return e;
@@ -247,6 +261,7 @@ hipError_t solve_ws(qn_ctx c, const double* coef, double* dense, int epi_last) {
   const int px = c->p[0], py = c->p[1], pz = c->p[2];
   const int pr = c->prec;
   EpiArgs ep{};
+  ep.inst_mod = 1;
   ep.coef = coef;
   ep.dense = dense;
   ep.px = px;
@@ -388,7 +403,7 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   off += align256(c->tensor_elems() * c->elem());
   c->off_W2 = off;
   off += align256(c->tensor_elems() * c->elem());
-  c->max_blocks = residual_max_blocks(c->dim, c->p[0], c->p[1], c->p[2]);
+  c->max_blocks = residual_max_blocks(c->p[0], c->p[1], c->p[2], RESIDUAL_RZ);
   c->off_part = off;
   off += align256((size_t)c->max_blocks * 4 * sizeof(double));
   c->off_scal = off;
@@ -481,6 +496,7 @@ qn_status qn_residual(qn_ctx c, const double* d_U, const double* d_F, double* d_
   a.ihy2 = (double)(c->n[1] + 1) * (c->n[1] + 1);
   a.ihz2 = c->dim == 3 ? (double)(c->n[2] + 1) * (c->n[2] + 1) : 0.0;
   a.partials = c->at<double>(c->off_part);
+  a.rz = RESIDUAL_RZ;
   int nb = 0;
   hipError_t e = timed(c, K_RESIDUAL, [&] { return launch_residual(a, &nb, c->stream); });
   if (e == hipSuccess)

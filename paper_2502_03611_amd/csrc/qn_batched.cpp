@@ -1,0 +1,545 @@
+// Host side of the batched solver (include/qn_batched.h).
+//
+// Instances with equal (n, ncomp) form a class whose fields are stored as one
+// (ncomp, K, n, n) block, and whose transform workspace is (ncomp, K, P, P)
+// with P = n rounded up to 32.  With that layout the single-problem kernels
+// cover a whole class per launch: the residual treats the K instances as
+// z-planes (1/h_z^2 = 0, one plane per workgroup), the y products batch over
+// the ncomp*K slabs, and the x products run over ncomp*K*P rows; per-instance
+// skip flags and shift coefficients are looked up as slab or row index % K.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "../../include/qn_batched.h"
+#include "qn_internal.h"
+
+namespace qn {
+qn_status set_error(qn_status s, const char* fmt, ...);
+}
+using namespace qn;
+
+namespace {
+
+size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
+
+uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float bf16_val(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+int largest_tile(long long extent) {
+  if (extent % 128 == 0) return 128;
+  if (extent % 64 == 0) return 64;
+  return 32;
+}
+
+struct Cls {
+  int n = 0, p = 0, ncomp = 1, K = 0;
+  std::vector<int> members;
+  long long off_field = 0;  // element offset of the (ncomp, K, n, n) block
+  size_t off_S = 0, off_Slo = 0, off_lam = 0, off_W1 = 0, off_W2 = 0, off_part = 0, off_state = 0,
+         off_done = 0;
+  int bpi = 0;                // residual workgroups per instance
+  int tmL = 32, tnL = 32;     // y-product tile
+  int tmR = 32, tnR = 32;     // x-product tile
+  hipStream_t s = nullptr;    // per-class stream (default priority)
+  hipEvent_t ev = nullptr;
+  std::vector<double> hS, hlam;
+};
+
+}  // namespace
+
+struct qnb_ctx_s {
+  int count = 0, prec = 0, beta_mode = 0;
+  double beta = 0.0;
+  std::vector<int> n, ncomp, inst_cls, inst_pos;
+  std::vector<Cls> cls;
+  long long field_elems = 0;
+  size_t need = 0;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  // parameters the captured graph was built with
+  double* g_U = nullptr;
+  const double* g_F = nullptr;
+  double g_rtol = -1.0;
+  int g_max = -1, g_iters = 0;
+  hipStream_t g_stream = nullptr;
+  hipError_t sticky = hipSuccess;
+  size_t elem() const { return prec == QN_PREC_FP64 ? 8 : 4; }
+};
+
+namespace {
+
+qn_status bad(qn_status s, const char* m) { return set_error(s, "%s", m); }
+qn_status hip_bad(qnb_ctx c, hipError_t e, const char* what) {
+  c->sticky = e;
+  return set_error(QN_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+void eigen_1d(int n, int p, std::vector<double>& S, std::vector<double>& lam) {
+  const long long m = n + 1;
+  const double pi = 3.14159265358979323846;
+  S.assign((size_t)p * p, 0.0);
+  lam.assign((size_t)p, 0.0);
+  const double nrm = std::sqrt(2.0 / (double)m);
+  for (int j = 1; j <= n; ++j)
+    for (int k = 1; k <= n; ++k) {
+      const long long red = ((long long)j * k) % (2 * m);
+      S[(size_t)(j - 1) * p + (k - 1)] = nrm * std::sin(pi * (double)red / (double)m);
+    }
+  for (int k = 1; k <= n; ++k) {
+    const double s = std::sin(pi * k / (2.0 * m));
+    lam[k - 1] = 4.0 * (double)(m * m) * s * s;
+  }
+  for (int k = n; k < p; ++k) lam[k] = lam[n - 1];
+}
+
+GemmOperands ops(qnb_ctx c, const Cls& k) {
+  GemmOperands g{};
+  if (c->prec == QN_PREC_BF16X3) {
+    g.Shi = c->ws + k.off_S;
+    g.Slo = c->ws + k.off_Slo;
+  } else {
+    g.S = c->ws + k.off_S;
+  }
+  return g;
+}
+
+EpiArgs epi_for(qnb_ctx c, const Cls& k, double* dense_base) {
+  EpiArgs ep{};
+  ep.lamM = (const double*)(c->ws + k.off_lam);
+  ep.lamX = ep.lamM;
+  ep.lamY = nullptr;
+  BState* st = (BState*)(c->ws + k.off_state);
+  ep.coef = &st[0].scale;
+  ep.coef_stride = (int)(sizeof(BState) / sizeof(double));
+  ep.dense = dense_base ? dense_base + k.off_field : nullptr;
+  ep.px = ep.py = k.p;
+  ep.pz = 1;
+  ep.nx = ep.ny = k.n;
+  ep.nz = 1;
+  ep.skip = (const int*)(c->ws + k.off_done);
+  ep.inst_mod = k.K;
+  return ep;
+}
+
+// One quasi-Newton iteration of class k on stream s.
+hipError_t class_iteration(qnb_ctx c, Cls& k, double* U, const double* F, double rtol, int max_iter,
+                           hipStream_t s) {
+  ResidualArgs a{};
+  a.U = U + k.off_field;
+  a.F = F + k.off_field;
+  a.R = c->ws + k.off_W1;
+  a.out_prec = c->prec == QN_PREC_FP64 ? 0 : 1;
+  a.r_cstride = (long long)k.K * k.p * k.p;
+  a.r_zstride = k.p * k.p;
+  a.r_ystride = k.p;
+  a.ox = a.oy = k.p;
+  a.oz = k.K;
+  a.nx = a.ny = k.n;
+  a.nz = k.K;
+  a.dim = 2;
+  a.nl = k.ncomp == 2 ? NL_SYS2 : NL_CUBIC;
+  a.ihx2 = a.ihy2 = (double)(k.n + 1) * (k.n + 1);
+  a.ihz2 = 0.0;
+  a.partials = (double*)(c->ws + k.off_part);
+  a.rz = 1;
+  a.skip = (const int*)(c->ws + k.off_done);
+  int nb = 0;
+  hipError_t e = launch_residual(a, &nb, s);
+  if (e != hipSuccess) return e;
+  BState* st = (BState*)(c->ws + k.off_state);
+  int* done = (int*)(c->ws + k.off_done);
+  e = launch_bfinalize(a.partials, k.bpi, k.K, st, done, c->beta_mode == QN_BETA_MIDPOINT, c->beta,
+                       rtol, max_iter, s);
+  if (e != hipSuccess) return e;
+  void* W1 = c->ws + k.off_W1;
+  void* W2 = c->ws + k.off_W2;
+  const GemmOperands S = ops(c, k);
+  EpiArgs ep = epi_for(c, k, U);
+  const int rows = k.ncomp * k.K * k.p;
+  const int slabs = k.ncomp * k.K;
+  const long long sl = (long long)k.p * k.p;
+  e = launch_gemm_right(c->prec, S, W1, W2, rows, k.p, EPI_STORE, ep, k.tmR, k.tnR, s);
+  if (e == hipSuccess)
+    e = launch_gemm_left(c->prec, S, W2, W1, k.p, k.p, slabs, sl, EPI_DIVIDE, ep, k.tmL, k.tnL, s);
+  if (e == hipSuccess)
+    e = launch_gemm_left(c->prec, S, W1, W2, k.p, k.p, slabs, sl, EPI_STORE, ep, k.tmL, k.tnL, s);
+  if (e == hipSuccess)
+    e = launch_gemm_right(c->prec, S, W2, nullptr, rows, k.p, EPI_SUB_DENSE, ep, k.tmR, k.tnR, s);
+  return e;
+}
+
+// Enqueue `iters` iterations of every class: fork onto the class streams,
+// join back onto the context stream.
+hipError_t enqueue(qnb_ctx c, double* U, const double* F, double rtol, int max_iter, int iters) {
+  hipError_t e = hipEventRecord(c->fork, c->stream);
+  for (auto& k : c->cls) {
+    if (e == hipSuccess) e = hipStreamWaitEvent(k.s, c->fork, 0);
+    for (int it = 0; it < iters && e == hipSuccess; ++it)
+      e = class_iteration(c, k, U, F, rtol, max_iter, k.s);
+    if (e == hipSuccess) e = hipEventRecord(k.ev, k.s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, k.ev, 0);
+  }
+  return e;
+}
+
+void drop_graph(qnb_ctx c) {
+  if (c->exec) hipGraphExecDestroy(c->exec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->exec = nullptr;
+  c->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+qn_status qnb_setup(int32_t count, const int32_t* n, const int32_t* ncomp, int32_t precision,
+                    int32_t beta_mode, double beta, qnb_ctx* out) {
+  if (!out || !n || !ncomp) return bad(QN_ERR_INVALID, "null argument");
+  if (count < 1 || count > 65536) return bad(QN_ERR_INVALID, "count must be in [1, 65536]");
+  if (precision < 0 || precision > 2) return bad(QN_ERR_INVALID, "unknown precision");
+  if (beta_mode < 0 || beta_mode > 1) return bad(QN_ERR_INVALID, "unknown beta_mode");
+  if (!std::isfinite(beta)) return bad(QN_ERR_INVALID, "beta not finite");
+  std::map<std::pair<int, int>, int> key;
+  qnb_ctx c = new qnb_ctx_s();
+  c->count = count;
+  c->prec = precision;
+  c->beta_mode = beta_mode;
+  c->beta = beta;
+  c->n.assign(n, n + count);
+  c->ncomp.assign(ncomp, ncomp + count);
+  c->inst_cls.resize(count);
+  c->inst_pos.resize(count);
+  for (int i = 0; i < count; ++i) {
+    if (n[i] < 1 || n[i] > 4096 || (ncomp[i] != 1 && ncomp[i] != 2)) {
+      delete c;
+      return set_error(QN_ERR_INVALID, "instance %d: n = %d, ncomp = %d out of range", i, n[i], ncomp[i]);
+    }
+    auto kk = std::make_pair(n[i], ncomp[i]);
+    auto it = key.find(kk);
+    int ci;
+    if (it == key.end()) {
+      ci = (int)c->cls.size();
+      key[kk] = ci;
+      Cls k;
+      k.n = n[i];
+      k.ncomp = ncomp[i];
+      k.p = ((n[i] + 31) / 32) * 32;
+      c->cls.push_back(k);
+    } else {
+      ci = it->second;
+    }
+    c->inst_cls[i] = ci;
+    c->inst_pos[i] = c->cls[ci].K++;
+    c->cls[ci].members.push_back(i);
+  }
+  double lam_min = 1e300;
+  long long fe = 0;
+  size_t off = 0;
+  for (auto& k : c->cls) {
+    eigen_1d(k.n, k.p, k.hS, k.hlam);
+    lam_min = std::min(lam_min, 2.0 * k.hlam[0]);
+    k.off_field = fe;
+    fe += (long long)k.ncomp * k.K * k.n * k.n;
+    const size_t pp = (size_t)k.p * k.p;
+    const size_t eb = precision == QN_PREC_FP64 ? 8 : (precision == QN_PREC_FP32 ? 4 : 2);
+    k.off_S = off;
+    off += a256(pp * eb);
+    if (precision == QN_PREC_BF16X3) {
+      k.off_Slo = off;
+      off += a256(pp * 2);
+    }
+    k.off_lam = off;
+    off += a256((size_t)k.p * 8);
+    const size_t te = (size_t)k.ncomp * k.K * pp * c->elem();
+    k.off_W1 = off;
+    off += a256(te);
+    k.off_W2 = off;
+    off += a256(te);
+    k.bpi = residual_max_blocks(k.p, k.p, 1, 1);
+    k.off_part = off;
+    off += a256((size_t)k.bpi * k.K * 4 * sizeof(double));
+    k.off_state = off;
+    off += a256((size_t)k.K * sizeof(BState));
+    k.off_done = off;
+    off += a256((size_t)k.K * sizeof(int));
+    k.tmL = largest_tile(k.p);
+    k.tnL = largest_tile(k.p);
+    // An x-product row tile must not straddle two instances (skip flags are
+    // per tile), so its height divides P.
+    k.tmR = largest_tile(k.p);
+    k.tnR = largest_tile(k.p);
+  }
+  if (beta_mode == QN_BETA_FIXED && lam_min + beta <= 0.0) {
+    delete c;
+    return bad(QN_ERR_INVALID, "fixed beta makes some instance's operator singular or indefinite");
+  }
+  c->field_elems = fe;
+  c->need = off;
+  *out = c;
+  return QN_OK;
+}
+
+qn_status qnb_field_elems(qnb_ctx c, int64_t* elems) {
+  if (!c || !elems) return bad(QN_ERR_INVALID, "null argument");
+  *elems = c->field_elems;
+  return QN_OK;
+}
+
+qn_status qnb_instance_layout(qnb_ctx c, int32_t i, int64_t* offset, int64_t* comp_stride) {
+  if (!c || !offset || !comp_stride) return bad(QN_ERR_INVALID, "null argument");
+  if (i < 0 || i >= c->count) return bad(QN_ERR_INVALID, "instance index out of range");
+  const Cls& k = c->cls[c->inst_cls[i]];
+  const long long nn = (long long)k.n * k.n;
+  *offset = k.off_field + (long long)c->inst_pos[i] * nn;
+  *comp_stride = (long long)k.K * nn;
+  return QN_OK;
+}
+
+qn_status qnb_workspace_bytes(qnb_ctx c, size_t* bytes) {
+  if (!c || !bytes) return bad(QN_ERR_INVALID, "null argument");
+  *bytes = c->need;
+  return QN_OK;
+}
+
+qn_status qnb_set_stream(qnb_ctx c, void* stream) {
+  if (!c) return bad(QN_ERR_INVALID, "null context");
+  c->stream = (hipStream_t)stream;
+  return QN_OK;
+}
+
+qn_status qnb_bind_workspace(qnb_ctx c, void* d_ws, size_t bytes) {
+  if (!c) return bad(QN_ERR_INVALID, "null context");
+  if (c->sticky != hipSuccess) return set_error(QN_ERR_HIP, "sticky HIP error");
+  if (!d_ws || ((uintptr_t)d_ws & 255u)) return bad(QN_ERR_WORKSPACE, "workspace null or misaligned");
+  if (bytes < c->need) return set_error(QN_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, c->need);
+  drop_graph(c);
+  c->ws = (char*)d_ws;
+  hipError_t e = hipSuccess;
+  if (!c->fork) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+  for (auto& k : c->cls) {
+    if (e == hipSuccess && !k.s) e = hipStreamCreateWithFlags(&k.s, hipStreamNonBlocking);
+    if (e == hipSuccess && !k.ev) e = hipEventCreateWithFlags(&k.ev, hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = launch_zero(c->ws, c->need, c->stream);
+  for (auto& k : c->cls) {
+    const size_t pp = (size_t)k.p * k.p;
+    if (e != hipSuccess) break;
+    if (c->prec == QN_PREC_FP64) {
+      e = hipMemcpyAsync(c->ws + k.off_S, k.hS.data(), pp * 8, hipMemcpyHostToDevice, c->stream);
+    } else if (c->prec == QN_PREC_FP32) {
+      std::vector<float> s32(pp);
+      for (size_t i = 0; i < pp; ++i) s32[i] = (float)k.hS[i];
+      e = hipMemcpyAsync(c->ws + k.off_S, s32.data(), pp * 4, hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    } else {
+      std::vector<uint16_t> hi(pp), lo(pp);
+      for (size_t i = 0; i < pp; ++i) {
+        hi[i] = bf16_rne((float)k.hS[i]);
+        lo[i] = bf16_rne((float)(k.hS[i] - (double)bf16_val(hi[i])));
+      }
+      e = hipMemcpyAsync(c->ws + k.off_S, hi.data(), pp * 2, hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(c->ws + k.off_Slo, lo.data(), pp * 2, hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->ws + k.off_lam, k.hlam.data(), (size_t)k.p * 8, hipMemcpyHostToDevice,
+                         c->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_bad(c, e, "bind workspace");
+  return QN_OK;
+}
+
+qn_status qnb_autotune(qnb_ctx c) {
+  if (!c || !c->ws) return bad(QN_ERR_WORKSPACE, "workspace not bound");
+  if (c->sticky != hipSuccess) return set_error(QN_ERR_HIP, "sticky HIP error");
+  drop_graph(c);
+  hipEvent_t t0, t1;
+  hipError_t e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  if (e != hipSuccess) return hip_bad(c, e, "autotune events");
+  const int cand[3] = {32, 64, 128};
+  for (auto& k : c->cls) {
+    EpiArgs ep = epi_for(c, k, nullptr);
+    ep.skip = nullptr;  // time every tile
+    const GemmOperands S = ops(c, k);
+    void* W1 = c->ws + k.off_W1;
+    void* W2 = c->ws + k.off_W2;
+    const int rows = k.ncomp * k.K * k.p, slabs = k.ncomp * k.K;
+    const long long sl = (long long)k.p * k.p;
+    for (int form = 0; form < 2 && e == hipSuccess; ++form) {
+      float best = 1e30f;
+      int bm = 32, bn = 32;
+      for (int tm : cand)
+        for (int tn : cand) {
+          if (k.p % tm || k.p % tn) continue;  // tiles never straddle instances
+          auto run = [&]() {
+            return form == 0 ? launch_gemm_left(c->prec, S, W1, W2, k.p, k.p, slabs, sl, EPI_STORE,
+                                                ep, tm, tn, c->stream)
+                             : launch_gemm_right(c->prec, S, W1, W2, rows, k.p, EPI_STORE, ep, tm,
+                                                 tn, c->stream);
+          };
+          e = run();  // warm-up
+          if (e == hipSuccess) e = hipEventRecord(t0, c->stream);
+          for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run();
+          if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
+          if (e == hipSuccess) e = hipEventSynchronize(t1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+          if (e != hipSuccess) break;
+          if (ms < best) {
+            best = ms;
+            bm = tm;
+            bn = tn;
+          }
+        }
+      if (form == 0) {
+        k.tmL = bm;
+        k.tnL = bn;
+      } else {
+        k.tmR = bm;
+        k.tnR = bn;
+      }
+    }
+  }
+  hipEventDestroy(t0);
+  hipEventDestroy(t1);
+  if (e != hipSuccess) return hip_bad(c, e, "autotune");
+  return QN_OK;
+}
+
+qn_status qnb_class_count(qnb_ctx c, int32_t* classes) {
+  if (!c || !classes) return bad(QN_ERR_INVALID, "null argument");
+  *classes = (int32_t)c->cls.size();
+  return QN_OK;
+}
+
+qn_status qnb_class_info(qnb_ctx c, int32_t i, int32_t* info) {
+  if (!c || !info) return bad(QN_ERR_INVALID, "null argument");
+  if (i < 0 || i >= (int)c->cls.size()) return bad(QN_ERR_INVALID, "class index out of range");
+  const Cls& k = c->cls[i];
+  const int32_t v[8] = {k.n, k.ncomp, k.K, k.tmL, k.tnL, k.tmR, k.tnR, k.p};
+  std::memcpy(info, v, sizeof v);
+  return QN_OK;
+}
+
+qn_status qnb_iterate(qnb_ctx c, double* d_U, const double* d_F, double rtol, int32_t max_iter,
+                      int32_t graph_iters, qnb_result* results) {
+  if (!c) return bad(QN_ERR_INVALID, "null context");
+  if (c->sticky != hipSuccess) return set_error(QN_ERR_HIP, "sticky HIP error");
+  if (!c->ws) return bad(QN_ERR_WORKSPACE, "workspace not bound");
+  if (!d_U || !d_F || ((uintptr_t)d_U & 7u) || ((uintptr_t)d_F & 7u))
+    return bad(QN_ERR_INVALID, "U and F must be non-null and 8-byte aligned");
+  if (!(rtol >= 0.0) || max_iter < 0 || graph_iters < 1 || graph_iters > 64)
+    return bad(QN_ERR_INVALID, "rtol >= 0, max_iter >= 0, 1 <= graph_iters <= 64 required");
+  hipError_t e = hipSuccess;
+  for (auto& k : c->cls) {
+    if (e == hipSuccess)
+      e = launch_breset((BState*)(c->ws + k.off_state), (int*)(c->ws + k.off_done), k.K, c->stream);
+  }
+  if (e != hipSuccess) return hip_bad(c, e, "reset");
+  if (!c->exec || c->g_U != d_U || c->g_F != d_F || c->g_rtol != rtol || c->g_max != max_iter ||
+      c->g_iters != graph_iters || c->g_stream != c->stream) {
+    drop_graph(c);
+    // Capture on a private stream so the caller's stream is never in capture mode.
+    hipStream_t cap;
+    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_bad(c, e, "capture stream");
+    hipStream_t saved = c->stream;
+    c->stream = cap;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t e2 = enqueue(c, d_U, d_F, rtol, max_iter, graph_iters);
+      e = hipStreamEndCapture(cap, &c->graph);
+      if (e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0);
+    c->stream = saved;
+    hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+      drop_graph(c);
+      return hip_bad(c, e, "graph capture");
+    }
+    c->g_U = d_U;
+    c->g_F = d_F;
+    c->g_rtol = rtol;
+    c->g_max = max_iter;
+    c->g_iters = graph_iters;
+    c->g_stream = c->stream;
+  }
+  // Replay until every instance is done (at most max_iter + 1 residual evaluations each).
+  std::vector<int> done;
+  const int max_replays = (max_iter + 1 + graph_iters - 1) / graph_iters + 1;
+  bool all_done = false;
+  for (int r = 0; r < max_replays && !all_done && e == hipSuccess; ++r) {
+    e = hipGraphLaunch(c->exec, c->stream);
+    all_done = true;
+    for (auto& k : c->cls) {
+      done.resize(k.K);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(done.data(), c->ws + k.off_done, k.K * sizeof(int), hipMemcpyDeviceToHost,
+                           c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      for (int v : done) all_done = all_done && v;
+    }
+  }
+  if (e != hipSuccess) return hip_bad(c, e, "graph replay");
+  qn_status worst = QN_OK;
+  std::vector<BState> hs;
+  for (auto& k : c->cls) {
+    hs.resize(k.K);
+    e = hipMemcpyAsync(hs.data(), c->ws + k.off_state, k.K * sizeof(BState), hipMemcpyDeviceToHost,
+                       c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_bad(c, e, "read results");
+    for (int j = 0; j < k.K; ++j) {
+      const BState& s = hs[j];
+      const qn_status st = !s.done ? QN_ERR_NOT_CONVERGED : (qn_status)s.status;
+      if (st == QN_ERR_DIVERGED) worst = QN_ERR_DIVERGED;
+      else if (st != QN_OK && worst == QN_OK) worst = st;
+      if (results) {
+        qnb_result& o = results[k.members[j]];
+        o.iters = s.iters;
+        o.status = st;
+        o.relres = s.relres;
+        o.relres0 = s.relres0;
+      }
+    }
+  }
+  if (worst != QN_OK) set_error(worst, "some instances did not converge");
+  return worst;
+}
+
+void qnb_destroy(qnb_ctx c) {
+  if (!c) return;
+  drop_graph(c);
+  for (auto& k : c->cls) {
+    if (k.s) hipStreamDestroy(k.s);
+    if (k.ev) hipEventDestroy(k.ev);
+  }
+  if (c->fork) hipEventDestroy(c->fork);
+  delete c;
+}
+
+}  // extern "C"

@@ -85,6 +85,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left(const T* __restrict__ S,
   const int MT = M / TM, NT = ncols / TN;
   const int t = xcd_tile(blockIdx.x, batch * MT * NT);
   const int mt = t % MT, rest = t / MT, nt = rest % NT, b = rest / NT;
+  const int inst = b % ep.inst_mod;
+  if (ep.skip && ep.skip[inst]) return;  // whole workgroup: finished instance
   const int m0 = mt * TM, n0 = nt * TN;
   const T* Bb = B + (long long)b * bstride;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -150,7 +152,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left(const T* __restrict__ S,
   if (EPI == EPI_DIVIDE) {
     // d(m, n) = scale * (lamM[m] + lamX[n % px] + lamY[n / px]) + beta; the
     // column part depends on (j, lane) only, the row part on (i, q) only.
-    const double scale = ep.coef[0], beta = ep.coef[1];
+    const double* cf = ep.coef + (long long)inst * ep.coef_stride;
+    const double scale = cf[0], beta = cf[1];
     double cn[BN];
 #pragma unroll
     for (int j = 0; j < BN; ++j) {
@@ -207,6 +210,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right(const T* __restrict__ A,
   const int t = xcd_tile(blockIdx.x, MT * NT);
   const int nt = t % NT, mt = t / NT;
   const int r0 = mt * TM, n0 = nt * TN;
+  if (ep.skip && ep.skip[(r0 / ep.py / ep.pz) % ep.inst_mod]) return;  // finished instance
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
 

@@ -59,6 +59,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf3(const __bf16* __restri
   const int MT = M / TM, NT = ncols / TN;
   const int t = bf_tile(blockIdx.x, batch * MT * NT);
   const int mt = t % MT, rest = t / MT, nt = rest % NT, b = rest / NT;
+  const int inst = b % ep.inst_mod;
+  if (ep.skip && ep.skip[inst]) return;  // whole workgroup: finished instance
   const int m0 = mt * TM, n0 = nt * TN;
   const float* Bb = B + (long long)b * bstride;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -155,8 +157,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf3(const __bf16* __restri
   float* Cb = C + (long long)b * bstride;
   double scale = 0.0, beta = 0.0;
   if (EPI == EPI_DIVIDE) {
-    scale = ep.coef[0];
-    beta = ep.coef[1];
+    const double* cf = ep.coef + (long long)inst * ep.coef_stride;
+    scale = cf[0];
+    beta = cf[1];
   }
 #pragma unroll
   for (int i = 0; i < BM; ++i)
@@ -195,6 +198,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf3(const float* __restri
   const int t = bf_tile(blockIdx.x, MT * NT);
   const int nt = t % NT, mt = t / NT;
   const int r0 = mt * TM, n0 = nt * TN;
+  if (ep.skip && ep.skip[(r0 / ep.py / ep.pz) % ep.inst_mod]) return;  // finished instance
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
 

@@ -49,6 +49,13 @@ struct EpiArgs {
   double* dense;        // caller array (ncomp, nz, ny, nx) for the dense epilogues
   int px, py, pz;       // padded extents
   int nx, ny, nz;       // interior extents
+  // Batched solver: slabs / row blocks belong to instance (index % inst_mod);
+  // an instance whose skip flag is set is left untouched, and its {scale, beta}
+  // sit at coef + instance * coef_stride.  A single problem uses skip = NULL,
+  // inst_mod = 1, coef_stride = 0.
+  const int* skip;
+  int inst_mod;
+  int coef_stride;
 };
 
 // Host-side launchers (defined in qn_gemm.hip / qn_pointwise.hip).  All take
@@ -83,9 +90,27 @@ struct ResidualArgs {
   int dim, nl;
   double ihx2, ihy2, ihz2; // 1/h^2 per axis
   double* partials;        // per-block {sumR2, mumin, mumax, sumF2}
+  int rz;                  // z-planes per workgroup (the batched solver uses 1)
+  const int* skip;         // batched solver: per-z-plane (instance) skip flags, else NULL
 };
 hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t st);
-int residual_max_blocks(int dim, int ox, int oy, int oz);
+int residual_max_blocks(int ox, int oy, int oz, int rz);
+constexpr int RESIDUAL_RZ = 32;  // z-slab depth of a single 3D problem
+
+// Per-instance state of the batched solver.  scale and beta are adjacent so
+// the divide epilogue can read them as {scale, beta}.
+struct BState {
+  double relres, relres0, sumsqF, scale, beta;
+  int iters, done, status, pad;
+};
+static_assert(sizeof(BState) % sizeof(double) == 0, "BState must be a whole number of doubles");
+// Batched finalize: workgroup k reduces partials [k*bpi, (k+1)*bpi) of one
+// class and updates st[k] (stopping rule, shift rule, iteration count).
+// done[k] mirrors st[k].done as a plain int array (the GEMM/residual skip flags).
+hipError_t launch_bfinalize(const double* partials, int bpi, int K, BState* st, int* done,
+                            int midpoint, double beta_fixed, double rtol, int max_iter,
+                            hipStream_t s);
+hipError_t launch_breset(BState* st, int* done, int K, hipStream_t s);
 
 // Fixed-order reduction of the residual partials + shift rule.
 hipError_t launch_finalize(const double* partials, int nblocks, DevScalars* sc, int rule,

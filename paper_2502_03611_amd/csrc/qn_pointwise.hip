@@ -21,7 +21,7 @@
 
 namespace qn {
 
-constexpr int RX = 64, RY = 16, RZ = 32;  // residual block (x, y) and z-slab depth
+constexpr int RX = 64, RY = 16;  // residual block (x, y); z-slab depth is a launch argument
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -75,8 +75,9 @@ template <int NL, typename TO>
 __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
   const int x = blockIdx.x * RX + threadIdx.x;
   const int y = blockIdx.y * RY + threadIdx.y;
-  const int z0 = blockIdx.z * RZ;
-  const int z1 = min(z0 + RZ, a.oz);
+  const int z0 = blockIdx.z * a.rz;
+  const int z1 = min(z0 + a.rz, a.oz);
+  if (a.skip && a.skip[z0]) return;  // batched solver: finished instance (rz = 1)
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const long long plane = (long long)nx * ny;
   const long long comp = plane * nz;
@@ -87,16 +88,19 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
   double s_r = 0.0, s_f = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
   double um[NC], uc[NC];
   const long long col = (long long)y * nx + x;
+  // 2D problems (and the batched solver, whose z-planes are independent
+  // instances) have no z coupling: never read a neighbouring plane.
+  const bool zc = a.ihz2 != 0.0;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    um[c] = (in_xy && z0 > 0 && z0 - 1 < nz) ? a.U[c * comp + (long long)(z0 - 1) * plane + col] : 0.0;
+    um[c] = (zc && in_xy && z0 > 0 && z0 - 1 < nz) ? a.U[c * comp + (long long)(z0 - 1) * plane + col] : 0.0;
     uc[c] = (in_xy && z0 < nz) ? a.U[c * comp + (long long)z0 * plane + col] : 0.0;
   }
   for (int z = z0; z < z1; ++z) {
     double up[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
-      up[c] = (in_xy && z + 1 < nz) ? a.U[c * comp + (long long)(z + 1) * plane + col] : 0.0;
+      up[c] = (zc && in_xy && z + 1 < nz) ? a.U[c * comp + (long long)(z + 1) * plane + col] : 0.0;
     if (in_xy && z < nz) {
       const long long p = (long long)z * plane + col;
       double r[NC];
@@ -162,7 +166,8 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       um[c] = uc[c];
-      uc[c] = up[c];
+      uc[c] = zc ? up[c]
+                 : ((in_xy && z + 1 < nz) ? a.U[c * comp + (long long)(z + 1) * plane + col] : 0.0);
     }
   }
 
@@ -177,13 +182,12 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
   }
 }
 
-static dim3 residual_grid(int ox, int oy, int oz) {
-  return dim3((ox + RX - 1) / RX, (oy + RY - 1) / RY, (oz + RZ - 1) / RZ);
+static dim3 residual_grid(int ox, int oy, int oz, int rz) {
+  return dim3((ox + RX - 1) / RX, (oy + RY - 1) / RY, (oz + rz - 1) / rz);
 }
 
-int residual_max_blocks(int dim, int ox, int oy, int oz) {
-  (void)dim;
-  const dim3 g = residual_grid(ox, oy, oz);
+int residual_max_blocks(int ox, int oy, int oz, int rz) {
+  const dim3 g = residual_grid(ox, oy, oz, rz);
   return (int)(g.x * g.y * g.z);
 }
 
@@ -196,7 +200,7 @@ static void launch_nl(const ResidualArgs& a, dim3 g, hipStream_t st) {
 }
 
 hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t st) {
-  const dim3 g = residual_grid(a.ox, a.oy, a.oz);
+  const dim3 g = residual_grid(a.ox, a.oy, a.oz, a.rz);
   *nblocks_out = (int)(g.x * g.y * g.z);
   switch (a.nl) {
     case NL_CUBIC: launch_nl<NL_CUBIC>(a, g, st); break;
@@ -246,6 +250,71 @@ hipError_t launch_finalize(const double* partials, int nblocks, DevScalars* sc, 
                            hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, st, partials, nblocks, sc, rule,
                      beta_fixed, lam_min_sum, red_out);
+  return hipGetLastError();
+}
+
+// Batched finalize: block k reduces instance k's partials and applies the
+// stopping rule, then the shift rule (midpoint of the Jacobian-diagonal
+// eigenvalue range, or a fixed beta) for the next solve.
+__global__ __launch_bounds__(256) void k_bfinalize(const double* __restrict__ partials, int bpi,
+                                                   BState* __restrict__ st, int* __restrict__ done,
+                                                   int midpoint, double beta_fixed, double rtol,
+                                                   int max_iter) {
+  BState& s = st[blockIdx.x];
+  if (s.done) return;
+  const double* pp = partials + 4LL * bpi * blockIdx.x;
+  double s0 = 0.0, s1 = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
+  for (int i = threadIdx.x; i < bpi; i += 256) {
+    s0 += pp[4 * i + 0];
+    mn = fmin(mn, pp[4 * i + 1]);
+    mx = fmax(mx, pp[4 * i + 2]);
+    s1 += pp[4 * i + 3];
+  }
+  block_reduce4<4>(s0, mn, mx, s1);
+  if (threadIdx.x == 0) {
+    const double rel = sqrt(s0) / sqrt(s1);
+    if (s.iters == 0) {
+      s.relres0 = rel;
+      s.sumsqF = s1;
+    }
+    s.relres = rel;
+    if (!(rel <= 1e30)) {  // also catches NaN
+      s.done = 1;
+      s.status = 4;  // QN_ERR_DIVERGED
+    } else if (rel <= rtol) {
+      s.done = 1;
+      s.status = 0;
+    } else if (s.iters >= max_iter) {
+      s.done = 1;
+      s.status = 3;  // QN_ERR_NOT_CONVERGED
+    } else {
+      s.scale = 1.0;
+      s.beta = midpoint ? 0.5 * (mn + mx) : beta_fixed;
+      s.iters += 1;
+    }
+    done[blockIdx.x] = s.done;
+  }
+}
+
+hipError_t launch_bfinalize(const double* partials, int bpi, int K, BState* st, int* done,
+                            int midpoint, double beta_fixed, double rtol, int max_iter,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_bfinalize, dim3(K), dim3(256), 0, s, partials, bpi, st, done, midpoint,
+                     beta_fixed, rtol, max_iter);
+  return hipGetLastError();
+}
+
+__global__ void k_breset(BState* st, int* done, int K) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= K) return;
+  BState z{};
+  z.scale = 1.0;
+  st[i] = z;
+  done[i] = 0;
+}
+
+hipError_t launch_breset(BState* st, int* done, int K, hipStream_t s) {
+  hipLaunchKernelGGL(k_breset, dim3((K + 255) / 256), dim3(256), 0, s, st, done, K);
   return hipGetLastError();
 }
 

@@ -1,0 +1,505 @@
+// Kernels of the learned initial-guess network (include/qnn.h): five 3x3
+// convolutions 2 -> 32 -> 32 -> 32 -> 32 -> 1 with exact GELU, MSE loss,
+// backward pass and Adam, all FP32.
+//
+// Activations are NHWC with 32 channels contiguous, so the reduction index
+// k = (tap, channel) of a 32 -> 32 layer is contiguous per pixel.  Those
+// layers (forward, backward-data and weight-gradient) run as implicit GEMMs
+// on v_mfma_f32_16x16x4f32 with the input tile and its one-pixel halo staged
+// in LDS; channel strides in LDS are padded (36 / 48 floats) so the 16 pixels
+// or 16 channels of a fragment fall on distinct banks.  The 2 -> 32 and
+// 32 -> 1 layers are small VALU kernels.  Weight gradients are reduced by
+// writing one partial per workgroup and summing the partials in a fixed order,
+// so every result is bitwise reproducible.
+
+#include <cmath>
+
+#include "qnn_internal.h"
+
+namespace qnn {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ inline float gelu_grad(float x) {
+  const float cdf = 0.5f * (1.0f + erff(x * 0.70710678118654752f));
+  const float pdf = expf(-0.5f * x * x) * 0.39894228040143268f;
+  return cdf + x * pdf;
+}
+
+// ---------------------------------------------------------------- layer 1
+
+// Layer 1: x0 = (f / 50, v0); z1 = b1 + W1 * x0; a1 = gelu(z1).  One thread
+// per pixel; W1 is (32, 2, 3, 3).
+__global__ __launch_bounds__(256) void k_in_fwd(const double* __restrict__ f,
+                                                const double* __restrict__ v,
+                                                const float* __restrict__ p1,
+                                                float* __restrict__ x0, float* __restrict__ z1,
+                                                float* __restrict__ a1, int H, int W, int npix) {
+  __shared__ float sw[L1_SIZE];
+  for (int i = threadIdx.x; i < L1_SIZE; i += 256) sw[i] = p1[i];
+  __syncthreads();
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= npix) return;
+  const int x = p % W, y = (p / W) % H, b = p / (W * H);
+  float nb[CIN0][9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+    const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+    const long long q = ((long long)b * H + yy) * W + xx;
+    nb[0][t] = in ? (float)(f[q] * (1.0 / 50.0)) : 0.0f;
+    nb[1][t] = in ? (float)v[q] : 0.0f;
+  }
+  x0[2LL * p] = nb[0][4];
+  x0[2LL * p + 1] = nb[1][4];
+  float* zo = z1 + (long long)p * 32;
+  float* ao = a1 + (long long)p * 32;
+#pragma unroll 4
+  for (int c = 0; c < 32; ++c) {
+    float s = sw[32 * CIN0 * 9 + c];
+#pragma unroll
+    for (int ci = 0; ci < CIN0; ++ci)
+#pragma unroll
+      for (int t = 0; t < 9; ++t) s += sw[(c * CIN0 + ci) * 9 + t] * nb[ci][t];
+    zo[c] = s;
+    ao[c] = gelu(s);
+  }
+}
+
+// ---------------------------------------------------------------- 32 -> 32 layers
+
+constexpr int CT_Y = 16, CT_X = 32;         // output pixel tile
+constexpr int HY = CT_Y + 2, HX = CT_X + 2;  // with halo
+constexpr int CP = 36;                       // LDS channel stride (floats)
+constexpr int WS = 48;                       // LDS weight row stride (floats)
+
+// MODE 0 (forward):  z = bias + sum_k in[p + tap][ci] * Wk[k][co]; writes z and gelu(z).
+// MODE 1 (backward-data): g = (sum_k dz[p - tap][co] * Wk[k][ci]) * gelu'(zprev[p][ci]).
+// Wk is the k-major weight matrix (288 x 32) prepared by k_prep_weights
+// (flipped taps for MODE 1).  One workgroup = 8 waves = a 16 x 32 pixel tile;
+// wave w owns rows 2w, 2w+1 (4 MFMA row blocks of 16 pixels) x 32 channels.
+template <int MODE>
+__global__ __launch_bounds__(512) void k_conv32(const float* __restrict__ in,
+                                                const float* __restrict__ wk,
+                                                const float* __restrict__ bias,
+                                                const float* __restrict__ zprev,
+                                                float* __restrict__ out0, float* __restrict__ out1,
+                                                int H, int W, int tiles_x, int tiles_y) {
+  __shared__ __attribute__((aligned(16))) float s_in[HY * HX * CP];
+  __shared__ __attribute__((aligned(16))) float s_w[288 * WS];
+  const int tid = threadIdx.x;
+  int t = blockIdx.x;
+  const int tx = t % tiles_x;
+  t /= tiles_x;
+  const int ty = t % tiles_y;
+  const int b = t / tiles_y;
+  const int y0 = ty * CT_Y, x0 = tx * CT_X;
+
+  for (int i = tid; i < 288 * 8; i += 512) {
+    const int k = i >> 3, c4 = i & 7;
+    *reinterpret_cast<float4*>(&s_w[k * WS + c4 * 4]) = reinterpret_cast<const float4*>(wk)[i];
+  }
+  for (int i = tid; i < HY * HX * 8; i += 512) {
+    const int c4 = i & 7, pix = i >> 3;
+    const int hy = pix / HX, hx = pix % HX;
+    const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+      v = reinterpret_cast<const float4*>(in + (((long long)b * H + yy) * W + xx) * 32)[c4];
+    *reinterpret_cast<float4*>(&s_in[pix * CP + c4 * 4]) = v;
+  }
+  __syncthreads();
+
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  f4v acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i][0] = acc[i][1] = f4v{0, 0, 0, 0};
+  for (int tap = 0; tap < 9; ++tap) {
+    const int dy = tap / 3, dx = tap % 3;
+#pragma unroll
+    for (int c0 = 0; c0 < 32; c0 += 4) {
+      const int k = tap * 32 + c0 + lk;
+      const float b0 = s_w[k * WS + lr], b1 = s_w[k * WS + 16 + lr];
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        const int r = 2 * wave + (mb >> 1), xh = (mb & 1) * 16;
+        const float a = s_in[((r + dy) * HX + xh + lr + dx) * CP + c0 + lk];
+        acc[mb][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc[mb][0], 0, 0, 0);
+        acc[mb][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc[mb][1], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+    const int y = y0 + 2 * wave + (mb >> 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int x = x0 + (mb & 1) * 16 + 4 * lk + q;
+      if (y >= H || x >= W) continue;
+      const long long base = (((long long)b * H + y) * W + x) * 32;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int c = j * 16 + lr;
+        const float v = acc[mb][j][q];
+        if (MODE == 0) {
+          const float z = v + bias[c];
+          out0[base + c] = z;
+          out1[base + c] = gelu(z);
+        } else {
+          out0[base + c] = v * gelu_grad(zprev[base + c]);
+        }
+      }
+    }
+  }
+}
+
+constexpr int GT_Y = 8, GT_X = 32;            // weight-gradient pixel tile
+constexpr int GHY = GT_Y + 2, GHX = GT_X + 2;  // with halo
+constexpr int DS = 48;                         // LDS stride of the dz tile
+
+// Partial weight gradient of a 32 -> 32 layer over one 8 x 32 pixel tile:
+// part[co*288 + ci*9 + tap] = sum_p dz[p][co] * act[p + tap][ci] and
+// part[9216 + co] = sum_p dz[p][co].  GEMM M = 32 (co) x N = 288 (tap, ci) x
+// K = 256 pixels; wave w owns row block w&1 and column blocks (w>>1) + 2i.
+__global__ __launch_bounds__(256) void k_conv32_wgrad(const float* __restrict__ act,
+                                                      const float* __restrict__ dz,
+                                                      float* __restrict__ part, int H, int W,
+                                                      int tiles_x, int tiles_y) {
+  __shared__ __attribute__((aligned(16))) float s_a[GHY * GHX * CP];
+  __shared__ __attribute__((aligned(16))) float s_d[GT_Y * GT_X * DS];
+  const int tid = threadIdx.x;
+  int t = blockIdx.x;
+  const int tx = t % tiles_x;
+  t /= tiles_x;
+  const int ty = t % tiles_y;
+  const int b = t / tiles_y;
+  const int y0 = ty * GT_Y, x0 = tx * GT_X;
+  for (int i = tid; i < GHY * GHX * 8; i += 256) {
+    const int c4 = i & 7, pix = i >> 3;
+    const int hy = pix / GHX, hx = pix % GHX;
+    const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+      v = reinterpret_cast<const float4*>(act + (((long long)b * H + yy) * W + xx) * 32)[c4];
+    *reinterpret_cast<float4*>(&s_a[pix * CP + c4 * 4]) = v;
+  }
+  for (int i = tid; i < GT_Y * GT_X * 8; i += 256) {
+    const int c4 = i & 7, pix = i >> 3;
+    const int yy = y0 + pix / GT_X, xx = x0 + pix % GT_X;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (yy < H && xx < W)
+      v = reinterpret_cast<const float4*>(dz + (((long long)b * H + yy) * W + xx) * 32)[c4];
+    *reinterpret_cast<float4*>(&s_d[pix * DS + c4 * 4]) = v;
+  }
+  __syncthreads();
+
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int mb = wave & 1;
+  f4v acc[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) acc[i] = f4v{0, 0, 0, 0};
+  for (int kp = 0; kp < GT_Y * GT_X; kp += 4) {
+    const int p = kp + lk;
+    const int py = p / GT_X, px = p % GT_X;
+    const float a = s_d[p * DS + mb * 16 + lr];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int nb = (wave >> 1) + 2 * i;
+      const int tap = nb >> 1, ci = (nb & 1) * 16 + lr;
+      const float bv = s_a[((py + tap / 3) * GHX + px + tap % 3) * CP + ci];
+      acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[i], 0, 0, 0);
+    }
+  }
+  float* pw = part + (long long)blockIdx.x * QNN_WGRAD_STRIDE;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int nb = (wave >> 1) + 2 * i;
+    const int tap = nb >> 1, ci = (nb & 1) * 16 + lr;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int co = mb * 16 + 4 * lk + q;
+      pw[co * 288 + ci * 9 + tap] = acc[i][q];
+    }
+  }
+  if (tid < 32) {
+    float s = 0.f;
+    for (int p = 0; p < GT_Y * GT_X; ++p) s += s_d[p * DS + tid];
+    pw[9216 + tid] = s;
+  }
+}
+
+// ---------------------------------------------------------------- layer 5
+
+// out = b5 + sum_{tap, ci} W5[ci][tap] * a4[p + tap][ci]
+__global__ __launch_bounds__(256) void k_out_fwd(const float* __restrict__ a4,
+                                                 const float* __restrict__ p5,  // W5 (32x9), b5
+                                                 float* __restrict__ out, int H, int W, int npix) {
+  __shared__ float sw[289];
+  for (int i = threadIdx.x; i < 289; i += 256) sw[i] = p5[i];
+  __syncthreads();
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= npix) return;
+  const int x = p % W, y = (p / W) % H, b = p / (W * H);
+  float s = sw[288];
+  for (int t = 0; t < 9; ++t) {
+    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+    if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+    const float4* src = reinterpret_cast<const float4*>(a4 + (((long long)b * H + yy) * W + xx) * 32);
+#pragma unroll
+    for (int c4 = 0; c4 < 8; ++c4) {
+      const float4 v = src[c4];
+      s += sw[(4 * c4 + 0) * 9 + t] * v.x + sw[(4 * c4 + 1) * 9 + t] * v.y +
+           sw[(4 * c4 + 2) * 9 + t] * v.z + sw[(4 * c4 + 3) * 9 + t] * v.w;
+    }
+  }
+  out[p] = s;
+}
+
+// gout = 2 (out - target) / npix; per-block partial of sum (out - target)^2.
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ out,
+                                             const double* __restrict__ target,
+                                             float* __restrict__ gout, double* __restrict__ lpart,
+                                             int npix) {
+  __shared__ double red[4];
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  double e2 = 0.0;
+  if (p < npix) {
+    const double d = (double)out[p] - target[p];
+    gout[p] = (float)(2.0 * d / (double)npix);
+    e2 = d * d;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) e2 += __shfl_xor(e2, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e2;
+  __syncthreads();
+  if (threadIdx.x == 0) lpart[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict__ lpart, int n,
+                                                       double scale, double* __restrict__ out) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) s += lpart[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < 16; ++i) t += red[i];
+    out[0] = t * scale;
+  }
+}
+
+// dz4[q][ci] = gelu'(z4[q][ci]) * sum_tap gout[q - tap + 1] * W5[ci][tap]
+__global__ __launch_bounds__(256) void k_out_bwd(const float* __restrict__ gout,
+                                                 const float* __restrict__ p5,
+                                                 const float* __restrict__ z4,
+                                                 float* __restrict__ dz4, int H, int W, int npix) {
+  __shared__ float sw[288];
+  for (int i = threadIdx.x; i < 288; i += 256) sw[i] = p5[i];
+  __syncthreads();
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= npix) return;
+  const int x = p % W, y = (p / W) % H, b = p / (W * H);
+  float g[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int yy = y - (t / 3 - 1), xx = x - (t % 3 - 1);
+    g[t] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? gout[((long long)b * H + yy) * W + xx] : 0.f;
+  }
+  const long long base = (long long)p * 32;
+#pragma unroll 4
+  for (int c = 0; c < 32; ++c) {
+    float s = 0.f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) s += g[t] * sw[c * 9 + t];
+    dz4[base + c] = s * gelu_grad(z4[base + c]);
+  }
+}
+
+// Partial weight gradient of the first or last layer over an 8 x 32 pixel
+// tile.  IN1 = 1: layer 1, G = dz1 (32 ch), X = x0 (2 ch):
+//   part[(co*2 + ci)*9 + tap] = sum_p G[p][co] X[p + tap][ci], part[576 + co] = sum_p G[p][co].
+// IN1 = 0: layer 5, G = gout (1 ch), X = a4 (32 ch):
+//   part[ci*9 + tap] = sum_p G[p] X[p + tap][ci], part[288] = sum_p G[p].
+// One thread per output entry.
+template <int IN1>
+__global__ __launch_bounds__(640) void k_small_wgrad(const float* __restrict__ G,
+                                                     const float* __restrict__ X,
+                                                     float* __restrict__ part, int H, int W,
+                                                     int tiles_x, int tiles_y) {
+  constexpr int GC = IN1 ? 32 : 1, XC = IN1 ? CIN0 : 32;
+  constexpr int NW = IN1 ? 32 * CIN0 * 9 : 288;  // weight entries
+  constexpr int NB = IN1 ? 32 : 1;               // bias entries
+  __shared__ float s_g[GT_Y * GT_X * GC];
+  __shared__ float s_x[GHY * GHX * XC];
+  int t = blockIdx.x;
+  const int tx = t % tiles_x;
+  t /= tiles_x;
+  const int ty = t % tiles_y;
+  const int b = t / tiles_y;
+  const int y0 = ty * GT_Y, x0 = tx * GT_X;
+  for (int i = threadIdx.x; i < GT_Y * GT_X * GC; i += 640) {
+    const int c = i % GC, pix = i / GC;
+    const int yy = y0 + pix / GT_X, xx = x0 + pix % GT_X;
+    s_g[i] = (yy < H && xx < W) ? G[(((long long)b * H + yy) * W + xx) * GC + c] : 0.f;
+  }
+  for (int i = threadIdx.x; i < GHY * GHX * XC; i += 640) {
+    const int c = i % XC, pix = i / XC;
+    const int yy = y0 + pix / GHX - 1, xx = x0 + pix % GHX - 1;
+    s_x[i] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? X[(((long long)b * H + yy) * W + xx) * XC + c] : 0.f;
+  }
+  __syncthreads();
+  const int j = threadIdx.x;
+  float* pw = part + (long long)blockIdx.x * QNN_SMALL_STRIDE;
+  if (j < NW) {
+    const int tap = j % 9, dy = tap / 3, dx = tap % 3;
+    const int gc = IN1 ? j / (9 * CIN0) : 0;       // channel of G
+    const int xc = IN1 ? (j / 9) % CIN0 : j / 9;   // channel of X
+    float s = 0.f;
+    for (int p = 0; p < GT_Y * GT_X; ++p) {
+      const int py = p / GT_X, px = p % GT_X;
+      s += s_g[p * GC + gc] * s_x[((py + dy) * GHX + px + dx) * XC + xc];
+    }
+    pw[j] = s;
+  } else if (j < NW + NB) {
+    const int c = j - NW;
+    float s = 0.f;
+    for (int p = 0; p < GT_Y * GT_X; ++p) s += s_g[p * GC + c];
+    pw[j] = s;
+  }
+}
+
+// grads[dst + j] = sum_{w < nparts} part[w * stride + j], j < len (fixed order,
+// accumulated in FP64).
+__global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ part, int nparts,
+                                                      int stride, int len,
+                                                      float* __restrict__ dst) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= len) return;
+  double s = 0.0;
+  for (int w = 0; w < nparts; ++w) s += part[(long long)w * stride + j];
+  dst[j] = (float)s;
+}
+
+// Layer l (2..4) parameters -> k-major forward weights Wf[tap*32 + ci][co] and
+// flipped backward-data weights Wb[tap*32 + co][ci] = W[co][ci][8 - tap].
+__global__ __launch_bounds__(256) void k_prep_weights(const float* __restrict__ wl,
+                                                      float* __restrict__ wf,
+                                                      float* __restrict__ wb) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= 9216) return;
+  const int co = i / 288, ci = (i / 9) % 32, tap = i % 9;
+  const float v = wl[i];
+  wf[(tap * 32 + ci) * 32 + co] = v;
+  wb[((8 - tap) * 32 + co) * 32 + ci] = v;
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, int n,
+                                              float lr, float b1, float b2, float eps, float bc1,
+                                              float bc2) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// out = f - g in FP64: the source corrected by the predicted nonlinear term.
+__global__ __launch_bounds__(256) void k_src_minus(const double* __restrict__ f,
+                                                   const float* __restrict__ g,
+                                                   double* __restrict__ out, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = f[i] - (double)g[i];
+}
+
+// ---------------------------------------------------------------- launchers
+
+static unsigned blocks(long long n, int per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t forward(const Buffers& B, const double* f, const double* v, int batch, hipStream_t st) {
+  const int H = B.H, W = B.W;
+  const int npix = batch * H * W;
+  const int tx = (W + CT_X - 1) / CT_X, ty = (H + CT_Y - 1) / CT_Y;
+  hipLaunchKernelGGL(k_in_fwd, dim3(blocks(npix, 256)), dim3(256), 0, st, f, v, B.params + OFF_L1,
+                     B.x0, B.z[0], B.a[0], H, W, npix);
+  for (int l = 1; l < 4; ++l)
+    hipLaunchKernelGGL((k_conv32<0>), dim3((unsigned)(tx * ty * batch)), dim3(512), 0, st,
+                       B.a[l - 1], B.wf[l - 1], B.params + layer_offset(l) + 9216, (const float*)nullptr,
+                       B.z[l], B.a[l], H, W, tx, ty);
+  hipLaunchKernelGGL(k_out_fwd, dim3(blocks(npix, 256)), dim3(256), 0, st, B.a[3], B.params + OFF_L5,
+                     B.out, H, W, npix);
+  return hipGetLastError();
+}
+
+hipError_t output_f64(const Buffers& B, const double* f, int batch, double* out, hipStream_t st) {
+  const int npix = batch * B.H * B.W;
+  hipLaunchKernelGGL(k_src_minus, dim3(blocks(npix, 256)), dim3(256), 0, st, f, B.out, out, npix);
+  return hipGetLastError();
+}
+
+hipError_t loss_grad(const Buffers& B, const double* f, const double* v, const double* target,
+                     int batch, hipStream_t st) {
+  hipError_t e = forward(B, f, v, batch, st);
+  if (e != hipSuccess) return e;
+  const int H = B.H, W = B.W;
+  const int npix = batch * H * W;
+  const unsigned nb = blocks(npix, 256);
+  hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, st, B.out, target, B.gout, B.lpart, npix);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st, B.lpart, (int)nb,
+                     1.0 / (double)npix, B.loss);
+  // layer 5
+  hipLaunchKernelGGL(k_out_bwd, dim3(nb), dim3(256), 0, st, B.gout, B.params + OFF_L5, B.z[3], B.d[0],
+                     H, W, npix);
+  const int gtx = (W + GT_X - 1) / GT_X, gty = (H + GT_Y - 1) / GT_Y;
+  const int nparts = gtx * gty * batch;
+  hipLaunchKernelGGL((k_small_wgrad<0>), dim3((unsigned)nparts), dim3(640), 0, st, B.gout, B.a[3],
+                     B.part, H, W, gtx, gty);
+  hipLaunchKernelGGL(k_reduce_parts, dim3(blocks(289, 256)), dim3(256), 0, st, B.part, nparts,
+                     QNN_SMALL_STRIDE, 289, B.grads + OFF_L5);
+  // layers 4, 3, 2: weight gradient from (a[l-1], dz_l), then dz_{l-1}
+  const int tx = (W + CT_X - 1) / CT_X, ty = (H + CT_Y - 1) / CT_Y;
+  int cur = 0;
+  for (int l = 3; l >= 1; --l) {
+    hipLaunchKernelGGL(k_conv32_wgrad, dim3((unsigned)nparts), dim3(256), 0, st, B.a[l - 1],
+                       B.d[cur], B.part, H, W, gtx, gty);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(blocks(9248, 256)), dim3(256), 0, st, B.part, nparts,
+                       QNN_WGRAD_STRIDE, 9248, B.grads + layer_offset(l));
+    hipLaunchKernelGGL((k_conv32<1>), dim3((unsigned)(tx * ty * batch)), dim3(512), 0, st,
+                       B.d[cur], B.wb[l - 1], (const float*)nullptr, B.z[l - 1], B.d[cur ^ 1],
+                       (float*)nullptr, H, W, tx, ty);
+    cur ^= 1;
+  }
+  // layer 1
+  hipLaunchKernelGGL((k_small_wgrad<1>), dim3((unsigned)nparts), dim3(640), 0, st, B.d[cur], B.x0,
+                     B.part, H, W, gtx, gty);
+  hipLaunchKernelGGL(k_reduce_parts, dim3(blocks(L1_SIZE, 256)), dim3(256), 0, st, B.part, nparts,
+                     QNN_SMALL_STRIDE, L1_SIZE, B.grads + OFF_L1);
+  return hipGetLastError();
+}
+
+hipError_t prep_weights(const Buffers& B, hipStream_t st) {
+  for (int l = 1; l < 4; ++l)
+    hipLaunchKernelGGL(k_prep_weights, dim3(blocks(9216, 256)), dim3(256), 0, st,
+                       B.params + layer_offset(l), B.wf[l - 1], B.wb[l - 1]);
+  return hipGetLastError();
+}
+
+hipError_t adam(const Buffers& B, float lr, float b1, float b2, float eps, float bc1, float bc2,
+                hipStream_t st) {
+  hipLaunchKernelGGL(k_adam, dim3(blocks(NPARAM, 256)), dim3(256), 0, st, B.params, B.grads, B.m,
+                     B.v, NPARAM, lr, b1, b2, eps, bc1, bc2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return prep_weights(B, st);
+}
+
+}  // namespace qnn

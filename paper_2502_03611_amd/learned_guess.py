@@ -1,0 +1,229 @@
+"""Learned initial guess for the 2D -Lap u + u^3 = f quasi-Newton solve.
+
+Pipeline (include/qnn.h): v0 = A_h^-1 f (tensor-product solve), the network
+predicts g ~ U*^3 from (f / 50, v0), and U_0 = A_h^-1 (f - g) (second solve);
+U_0 = 0 is used instead when the guess's residual is not smaller than that of
+U_0 = 0.  Every step (solves, forward, loss, backward, Adam) runs in libqn's
+HIP kernels.  This module is the thin driver: ctypes marshalling,
+solver-generated training data, the mini-batch loop and the evaluation.
+"""
+
+import ctypes
+import math
+import time
+
+import numpy as np
+import torch
+
+import synth
+
+from ._binding import Solver, c_vp, check, lib
+
+_QNN = None
+
+
+def _qnn():
+    global _QNN
+    if _QNN is not None:
+        return _QNN
+    L = lib()
+    L.qnn_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(c_vp)]
+    L.qnn_workspace_bytes.argtypes = [c_vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.qnn_bind_workspace.argtypes = [c_vp, c_vp, ctypes.c_size_t]
+    L.qnn_set_stream.argtypes = [c_vp, c_vp]
+    L.qnn_param_count.argtypes = []
+    L.qnn_set_params.argtypes = [c_vp, c_vp]
+    L.qnn_get_params.argtypes = [c_vp, c_vp]
+    L.qnn_get_grads.argtypes = [c_vp, c_vp]
+    L.qnn_forward.argtypes = [c_vp, c_vp, c_vp, ctypes.c_int32, c_vp]
+    L.qnn_loss_grad.argtypes = [c_vp, c_vp, c_vp, c_vp, ctypes.c_int32,
+                                ctypes.POINTER(ctypes.c_double)]
+    L.qnn_adam_step.argtypes = [c_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double]
+    L.qnn_destroy.argtypes = [c_vp]
+    L.qnn_destroy.restype = None
+    for n in ("qnn_create", "qnn_workspace_bytes", "qnn_bind_workspace", "qnn_set_stream",
+              "qnn_param_count", "qnn_set_params", "qnn_get_params", "qnn_get_grads",
+              "qnn_forward", "qnn_loss_grad", "qnn_adam_step"):
+        getattr(L, n).restype = ctypes.c_int32
+    _QNN = L
+    return L
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Net:
+    """The initial-guess network for H x W sources, batches up to max_batch."""
+
+    def __init__(self, H, W, max_batch=16, device="cuda"):
+        L = _qnn()
+        self.H, self.W, self.max_batch = int(H), int(W), int(max_batch)
+        self.device = torch.device(device)
+        ctx = c_vp()
+        check(L.qnn_create(self.H, self.W, self.max_batch, ctypes.byref(ctx)))
+        self._ctx = ctx
+        nb = ctypes.c_size_t()
+        check(L.qnn_workspace_bytes(ctx, ctypes.byref(nb)))
+        self._ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        self._stream()
+        check(L.qnn_bind_workspace(ctx, _p(self._ws), nb.value))
+        self.nparam = L.qnn_param_count()
+
+    def _stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        check(_qnn().qnn_set_stream(self._ctx, ctypes.c_void_p(s)))
+
+    def _fields(self, t, name):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.dim() != 3 \
+                or tuple(t.shape[1:]) != (self.H, self.W) or not 1 <= t.shape[0] <= self.max_batch:
+            raise ValueError(f"{name}: need contiguous float64 CUDA (B<= {self.max_batch}, "
+                             f"{self.H}, {self.W}), got {tuple(t.shape)} {t.dtype}")
+        return t
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        assert a.size == self.nparam
+        self._stream()
+        check(_qnn().qnn_set_params(self._ctx, a.ctypes.data_as(ctypes.c_void_p)))
+
+    def get_params(self):
+        a = np.empty(self.nparam, dtype=np.float32)
+        self._stream()
+        check(_qnn().qnn_get_params(self._ctx, a.ctypes.data_as(ctypes.c_void_p)))
+        return a
+
+    def get_grads(self):
+        a = np.empty(self.nparam, dtype=np.float32)
+        self._stream()
+        check(_qnn().qnn_get_grads(self._ctx, a.ctypes.data_as(ctypes.c_void_p)))
+        return a
+
+    def forward(self, f, v, out=None):
+        """f - g with g = net(f / 50, v): the corrected source."""
+        self._fields(f, "f")
+        self._fields(v, "v")
+        out = torch.empty_like(f) if out is None else out
+        self._stream()
+        check(_qnn().qnn_forward(self._ctx, _p(f), _p(v), f.shape[0], _p(out)))
+        return out
+
+    def loss_grad(self, f, v, target, want_loss=True):
+        self._fields(f, "f")
+        self._fields(v, "v")
+        self._fields(target, "target")
+        loss = ctypes.c_double(float("nan"))
+        self._stream()
+        check(_qnn().qnn_loss_grad(self._ctx, _p(f), _p(v), _p(target), f.shape[0],
+                                   ctypes.byref(loss) if want_loss else None))
+        return loss.value
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._stream()
+        check(_qnn().qnn_adam_step(self._ctx, lr, beta1, beta2, eps))
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            _qnn().qnn_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cubic_solver(n):
+    """The solver the learned guess serves: 2D -Lap u + u^3 = f, midpoint shift."""
+    return Solver((n, n), "cubic", beta_mode="midpoint")
+
+
+def generate_pairs(seeds, n=255, rtol=1e-10, solver=None):
+    """Training data from the quasi-Newton solver: sources f =
+    synth.learned_guess_rhs(seed), v0 = A_h^-1 f, converged U* (from U_0 = 0)
+    and the target g* = U*^3.  Returns GPU tensors (F, V, G, U), each (S, n, n)."""
+    solver = solver or cubic_solver(n)
+    F = torch.empty((len(seeds), n, n), dtype=torch.float64, device="cuda")
+    U = torch.zeros_like(F)
+    V = torch.empty_like(F)
+    for i, s in enumerate(seeds):
+        F[i].copy_(torch.from_numpy(synth.learned_guess_rhs(s, n)))
+        solver.fdm_solve(F[i:i + 1], 1.0, 0.0, X=V[i:i + 1])
+        st = solver.iterate(U[i:i + 1], F[i:i + 1], rtol=rtol, max_iter=200)
+        if st["status"] != 0:
+            raise RuntimeError(f"training pair {s} did not converge: {st}")
+    u = U.cpu().numpy()
+    G = torch.from_numpy(u * u * u).cuda()
+    return F, V, G, U
+
+
+def train(net, F, V, G, epochs=40, batch=16, lr=1e-3, seed=0, log=None):
+    """Mini-batch Adam on the MSE between the network's g and g* = U*^3.
+    Returns the per-epoch mean loss (sampled every 25 batches)."""
+    rng = np.random.default_rng(seed)
+    S = F.shape[0]
+    hist = []
+    for ep in range(epochs):
+        perm = rng.permutation(S)
+        tot, cnt = 0.0, 0
+        for b0 in range(0, S - batch + 1, batch):
+            idx = torch.from_numpy(perm[b0:b0 + batch]).cuda()
+            fb = F.index_select(0, idx).contiguous()
+            vb = V.index_select(0, idx).contiguous()
+            gb = G.index_select(0, idx).contiguous()
+            want = (b0 // batch) % 25 == 0
+            loss = net.loss_grad(fb, vb, gb, want_loss=want)
+            net.adam_step(lr)
+            if want:
+                tot += loss
+                cnt += 1
+        hist.append(tot / max(cnt, 1))
+        if log:
+            log(f"epoch {ep + 1}/{epochs} loss {hist[-1]:.4e}")
+    return hist
+
+
+def initial_guess(net, solver, f):
+    """U_0 = A_h^-1 (f - g), g = net(f / 50, A_h^-1 f), unless its residual is
+    non-finite or not smaller than that of U_0 = 0 (which is ||f||); then
+    U_0 = 0.  f: (1, n, n).  Returns (U_0, used_net)."""
+    n = f.shape[-1]
+    f = f.view(1, n, n)
+    v = solver.fdm_solve(f, 1.0, 0.0)
+    w = net.forward(f, v)
+    u0 = solver.fdm_solve(w, 1.0, 0.0, X=v)
+    red = torch.empty(4, dtype=torch.float64, device="cuda")
+    solver.residual(u0, f, R=w, red=red)
+    r2, f2 = red[0].item(), red[3].item()
+    if not math.isfinite(r2) or r2 >= f2:
+        u0.zero_()
+        return u0, False
+    return u0, True
+
+
+def evaluate(net, seeds, n=255, rtol=1e-10):
+    """Iterations and wall time to rtol from U_0 = 0 and from the learned U_0
+    (both solves, the network and the fallback test included) on held-out seeds."""
+    solver = cubic_solver(n)
+    rows = []
+    for s in seeds:
+        f = torch.from_numpy(synth.learned_guess_rhs(s, n)).cuda().view(1, n, n)
+        u = torch.zeros_like(f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st0 = solver.iterate(u, f, rtol=rtol, max_iter=200)
+        torch.cuda.synchronize()
+        t_zero = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        u1, used = initial_guess(net, solver, f)
+        st1 = solver.iterate(u1, f, rtol=rtol, max_iter=200)
+        torch.cuda.synchronize()
+        t_net = time.perf_counter() - t0
+        diff = float((u1 - u).norm() / u.norm())
+        rows.append({"seed": s, "iters_zero": st0["iters"], "iters_net": st1["iters"],
+                     "t_zero": t_zero, "t_net": t_net, "used_net": used,
+                     "relres0_net": st1["relres0"], "rel_diff": diff,
+                     "status": (st0["status"], st1["status"])})
+    return rows

@@ -1,0 +1,94 @@
+"""GPU tests of the batched solver: every instance of a mixed batch (uneven
+sizes, scalar and 2-component) matches the single-instance solver and the CPU
+oracle; tile shapes and graph length do not change results; a diverging
+instance does not disturb the others."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import qn as oqn
+from oracle.spectral import sine_eigenpairs
+from paper_2502_03611_amd import Solver
+from paper_2502_03611_amd.batched import BatchedSolver
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [15, 31, 63, 15, 100, 33, 63, 31, 17, 63, 127, 15]
+NCOMP = [1, 2, 1, 1, 2, 1, 2, 1, 2, 1, 2, 2]
+
+
+def sources(sizes, ncomp, seed0=4000000):
+    out = []
+    for i, (n, c) in enumerate(zip(sizes, ncomp)):
+        rng = np.random.default_rng(seed0 + i)
+        out.append(20.0 * np.stack([synth.gaussian_random_field(n, 0.1, rng) for _ in range(c)]))
+    return out
+
+
+def build(prec, sizes=SIZES, ncomp=NCOMP):
+    b = BatchedSolver(sizes, ncomp, precision=prec, beta_mode="midpoint")
+    F = b.pool()
+    srcs = sources(sizes, ncomp)
+    for i, f in enumerate(srcs):
+        b.fill(F, i, f)
+    return b, F, srcs
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_matches_single_instance_and_oracle(prec):
+    print(f"batched {prec}", flush=True)
+    b, F, srcs = build(prec)
+    U = b.pool()
+    status, res = b.iterate(U, F, rtol=1e-10, max_iter=100, graph_iters=3)
+    assert status == 0, res
+    for i, f in enumerate(srcs):
+        n, c = SIZES[i], NCOMP[i]
+        kind = "system" if c == 2 else "cubic"
+        s = Solver((n, n), kind, beta_mode="midpoint", precision=prec)
+        u1 = torch.zeros((c, n, n), dtype=torch.float64, device="cuda")
+        st = s.iterate(u1, torch.from_numpy(f).cuda(), rtol=1e-10, max_iter=100)
+        ub = b.view(U, i).cpu().numpy()
+        assert res[i]["iters"] == st["iters"], (i, res[i], st)
+        assert np.linalg.norm(ub - u1.cpu().numpy()) <= 1e-12 * np.linalg.norm(ub)
+        ref = oqn.qn_solve(oqn.SYSTEM if c == 2 else oqn.CUBIC, f, midpoint=True, rtol=1e-10)
+        assert abs(res[i]["iters"] - ref["iters"]) <= (0 if prec == "fp64" else 1)
+        # both stopped at relres <= 1e-10: |U_b - U_o| <= 2 rtol |F| / lam_min(J)
+        lam = 2 * sine_eigenpairs(n)[1][0] - (1.0 if c == 2 else 0.0)
+        assert np.linalg.norm(ub - ref["u"]) <= 2e-10 * np.linalg.norm(f) / lam
+
+
+def test_tiles_and_graph_length_do_not_change_results():
+    b, F, _ = build("fp32")
+    U1 = b.pool()
+    b.iterate(U1, F, rtol=1e-10, max_iter=100, graph_iters=1)
+    b.autotune()
+    print("classes", b.classes(), flush=True)
+    U2 = b.pool()
+    b.iterate(U2, F, rtol=1e-10, max_iter=100, graph_iters=5)
+    assert torch.equal(U1, U2)
+
+
+def test_diverging_instance_is_isolated():
+    b, F, _ = build("fp32")
+    U1 = b.pool()
+    _, r1 = b.iterate(U1, F, rtol=1e-10, max_iter=100)
+    bad = 3
+    b.view(F, bad)[0, 2, 2] = float("nan")
+    U2 = b.pool()
+    status, r2 = b.iterate(U2, F, rtol=1e-10, max_iter=100)
+    assert status == 4 and r2[bad]["status"] == 4
+    for i in range(len(SIZES)):
+        if i != bad:
+            assert r2[i] == r1[i]
+            assert torch.equal(b.view(U1, i), b.view(U2, i))
+
+
+def test_max_iter_reported_per_instance():
+    b, F, _ = build("fp64")
+    U = b.pool()
+    status, res = b.iterate(U, F, rtol=1e-10, max_iter=2, graph_iters=4)
+    assert status == 3
+    assert all(r["iters"] <= 2 for r in res)
+    assert any(r["status"] == 3 for r in res)
