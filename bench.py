@@ -42,7 +42,7 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE
 # (read counter scaled x2.0, write x1.0, calibrated on a plain 1 GiB copy), valid
 # only for the GEMM source they were taken on.
-TRAFFIC = {"source": "paper_2502_03611_amd/csrc/qn_gemm.hip", "sha256_prefix": "72739fac18112880",
+TRAFFIC = {"source": "paper_2502_03611_amd/csrc/qn_gemm_fold.hip", "sha256_prefix": "72739fac18112880",
            "bytes_per_launch": 1.560e9 + 1.074e9}
 
 
@@ -76,6 +76,75 @@ def cpu_baseline(n, amp):
                       f"(NumPy FP64 oracle, {dt:.1f} s)"}
 
 
+def bench_batched(count):
+    """Batched workload: `count` 2D instances, N drawn from {63, ..., 1023}, even
+    instances scalar -Lap u + u^3 = f, odd ones the 2-component system, unit-variance
+    GRF sources (length scale 0.1); FP32 transforms, FP64 residual/update, midpoint
+    shift, autotuned tiles, hipGraph replay.  Time to 1e-10 for the whole batch."""
+    from paper_2502_03611_amd.batched import BatchedSolver
+
+    log(f"batched: generating {count} instances")
+    inst = [synth.batched_instance(i) for i in range(count)]
+    b = BatchedSolver([d["n"] for d in inst], [d["ncomp"] for d in inst], precision="fp32",
+                      beta_mode="midpoint")
+    F = b.pool()
+    for i, d in enumerate(inst):
+        b.fill(F, i, d["f"])
+    del inst
+    log("batched: autotune")
+    t0 = time.perf_counter()
+    b.autotune()
+    t_tune = time.perf_counter() - t0
+    U = b.pool()
+    b.iterate(U, F, rtol=1e-10, max_iter=100, graph_iters=4)  # warm-up, graph capture
+    U.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, res = b.iterate(U, F, rtol=1e-10, max_iter=100, graph_iters=4)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # transform work per solve and component: 4 folded mode products of
+    # 2 n (ne^2 + no^2) flops each (dense formula: 2 n^3)
+    flops = sum(r["iters"] * 8.0 * n * (((n + 1) // 2) ** 2 + (n // 2) ** 2) * c
+                for r, n, c in zip(res, b.sizes, b.ncomp))
+    dense = sum(r["iters"] * 8.0 * n ** 3 * c for r, n, c in zip(res, b.sizes, b.ncomp))
+    pts = sum(n * n * c for n, c in zip(b.sizes, b.ncomp))
+    its = np.array([r["iters"] for r in res])
+    sc = np.array(b.ncomp) == 1
+    return {"instances": count, "unknowns": int(pts), "classes": len(b.classes()),
+            "status": status, "all_converged": bool(all(r["status"] == 0 for r in res)),
+            "time_to_tol_s": round(dt, 4), "solves_total": int(its.sum()),
+            "iters_mean_scalar": round(float(its[sc].mean()), 3),
+            "iters_mean_system": round(float(its[~sc].mean()), 3), "iters_max": int(its.max()),
+            "transform_tflops_fp32": round(flops / dt / 1e12, 2),
+            "transform_dense_equivalent_tflops": round(dense / dt / 1e12, 2),
+            "autotune_s": round(t_tune, 2),
+            "precision": "fp32 transforms, fp64 residual/update"}
+
+
+def bench_learned(nseeds=50):
+    """Learned initial guess on 2D 255^2 -Lap u + u^3 = f with the committed
+    trained weights: held-out seeds, iterations and time to 1e-10 from U_0 = 0 and
+    from the learned guess, FP64 and FP32 transforms."""
+    from paper_2502_03611_amd import learned_guess as lg
+
+    if not os.path.exists(lg.WEIGHTS):
+        return {"skipped": "no trained weights at " + os.path.relpath(lg.WEIGHTS, ROOT)}
+    theta = np.load(lg.WEIGHTS, allow_pickle=False)
+    net = lg.Net(255, 255, max_batch=1)
+    net.set_params(theta)
+    lg.compare(net, range(10000, 10002))  # warm-up
+    rows = lg.compare(net, range(10000, 10000 + nseeds))
+    outd = {"held_out_seeds": nseeds, "n": 255}
+    for key in ("fp64_zero", "fp64_net", "fp32_zero", "fp32_net"):
+        outd[key] = {"mean_iters": round(float(np.mean([r[key]["iters"] for r in rows])), 3),
+                     "mean_time_ms": round(1e3 * float(np.mean([r[key]["t"] for r in rows])), 3),
+                     "all_converged": bool(all(r[key]["status"] == 0 for r in rows))}
+    outd["speedup_fp32_net_vs_fp64_zero"] = round(
+        outd["fp64_zero"]["mean_time_ms"] / outd["fp32_net"]["mean_time_ms"], 3)
+    return outd
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +153,9 @@ def main():
     ap.add_argument("--n", type=int, default=511)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-tol", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--batched-count", type=int, default=512)
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (reference kernel "
                          "for scaling HBM traffic counters)")
@@ -124,23 +196,34 @@ def main():
     tim = solver.timing(reset=True)
     value = args.steps / dt
 
-    # dominant kernel: the plain y/z mode product (3 of the 6 products per step)
-    flops_per_product = 2.0 * float(n) ** 4
-    launches, tot_ms = tim["gemm_yz"]
+    # The mode products run reflection-folded: a product along an axis of n
+    # points over L lines does 2 L (ne^2 + no^2) flops (ne = ceil(n/2),
+    # no = floor(n/2)), about half the 2 L n^2 of the dense formula.
+    ne, no = (n + 1) // 2, n // 2
+    flops_per_product = 2.0 * float(n) ** 2 * (ne * ne + no * no)
+    dense_flops = 2.0 * float(n) ** 4
+    names = {"gemm_x": "k_fold_right_fwd<double,128,128>",
+             "gemm_yz": "k_fold_left_fwd<double,128,128,EPI_STORE>",
+             "gemm_divide": "k_fold_left_fwd<double,128,128,EPI_DIVIDE>",
+             "gemm_yz_inv": "k_fold_left_inv<double,64,128>",
+             "gemm_x_update": "k_fold_right_inv<double,128,64,EPI_SUB_DENSE>"}
+    dom = max(names, key=lambda k: tim[k][1])
+    launches, tot_ms = tim[dom]
     avg_ms = tot_ms / max(launches, 1)
     achieved = flops_per_product / (avg_ms * 1e-3) / 1e12
-    roof = {"bound": "mfma", "kernel": "k_gemm_left<double,128,128,EPI_STORE>",
-            "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+    roof = {"bound": "mfma", "kernel": names[dom], "achieved": round(achieved, 3),
+            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic_if_current(),
             "avg_launch_ms": round(avg_ms, 4), "launches": launches,
-            "algorithmic_flops_per_launch": flops_per_product}
+            "algorithmic_flops_per_launch": flops_per_product,
+            "dense_equivalent_tflops": round(dense_flops / (avg_ms * 1e-3) / 1e12, 3)}
     # the residual pass (HBM-bound): read U and F, write R, 8 bytes each
     rl, rms = tim["residual"]
     r_avg = rms / max(rl, 1)
     r_bytes = 24.0 * n ** 3
     kernels = {k: {"launches": v[0], "avg_ms": round(v[1] / max(v[0], 1), 4)} for k, v in tim.items() if v[0]}
-    all_gemm_ms = sum(tim[k][1] for k in ("gemm_x", "gemm_yz", "gemm_divide", "gemm_x_update"))
-    all_gemm_launches = sum(tim[k][0] for k in ("gemm_x", "gemm_yz", "gemm_divide", "gemm_x_update"))
+    all_gemm_ms = sum(tim[k][1] for k in names)
+    all_gemm_launches = sum(tim[k][0] for k in names)
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "iters/s", "n_gpus": 1,
@@ -158,6 +241,8 @@ def main():
                               "algorithmic_bytes_per_launch": r_bytes},
         "all_mode_products_tflops": round(flops_per_product * all_gemm_launches /
                                           (all_gemm_ms * 1e-3) / 1e12, 3),
+        "all_mode_products_dense_equivalent_tflops": round(dense_flops * all_gemm_launches /
+                                                           (all_gemm_ms * 1e-3) / 1e12, 3),
         "kernels": kernels,
     }
 
@@ -193,6 +278,12 @@ def main():
     solver.close()
     del U, F
     torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = bench_batched(args.batched_count)
+        torch.cuda.empty_cache()
+    if not args.no_learned:
+        out["learned_guess"] = bench_learned()
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, amp)
     print(json.dumps(out))

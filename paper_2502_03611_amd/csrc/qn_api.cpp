@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "../../include/qn.h"
+#include "qn_host.h"
 #include "qn_internal.h"
 
 using namespace qn;
@@ -42,31 +43,19 @@ qn_status fail(qn_status s, const char* fmt, ...) {
 enum KernelId {
   K_RESIDUAL = 0,
   K_FINALIZE,
-  K_GEMM_X,
-  K_GEMM_YZ,
-  K_GEMM_DIVIDE,
-  K_GEMM_X_UPDATE,
+  K_GEMM_X,         // forward x product
+  K_GEMM_YZ,        // forward y / z products (plain store)
+  K_GEMM_DIVIDE,    // last forward product with the spectral divide
+  K_GEMM_X_UPDATE,  // inverse x product with U -= dU (or X = dU)
   K_PAD_COPY,
+  K_GEMM_YZ_INV,    // inverse y / z products
   K_COUNT
 };
-const char* const kKernelNames[K_COUNT] = {"residual",     "finalize",      "gemm_x",
-                                           "gemm_yz",      "gemm_divide",   "gemm_x_update",
-                                           "pad_copy"};
+const char* const kKernelNames[K_COUNT] = {"residual",    "finalize",      "gemm_x",
+                                           "gemm_yz",     "gemm_divide",   "gemm_x_update",
+                                           "pad_copy",    "gemm_yz_inv"};
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
-
-uint16_t bf16_rne(float f) {
-  uint32_t u;
-  std::memcpy(&u, &f, 4);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-float bf16_to_float(uint16_t h) {
-  uint32_t u = (uint32_t)h << 16;
-  float f;
-  std::memcpy(&f, &u, 4);
-  return f;
-}
 
 int pick_tile(long long extent) {
   if (extent % 128 == 0) return 128;
@@ -101,7 +90,9 @@ struct qn_ctx_s {
   double beta = 0.0;
   double lam_min_sum = 0.0;
   hipStream_t stream = nullptr;
-  std::vector<double> hS[3], hlam[3];
+  bool fold = true;       // reflection-folded transforms (FP64/FP32); dense for bf16x3
+  FoldAxis ax[3] = {};
+  std::vector<double> hS[3], hlam[3];  // dense S or folded FeT|FoT|Fe|Fo; lam (split if folded)
   // workspace layout (byte offsets)
   size_t off_S[3] = {0, 0, 0}, off_Slo[3] = {0, 0, 0}, off_lam[3] = {0, 0, 0};
   size_t off_W1 = 0, off_W2 = 0, off_part = 0, off_scal = 0, off_coef = 0, need = 0;
@@ -181,32 +172,36 @@ void fold_timing(qn_ctx c) {
   c->pending.clear();
 }
 
-// Closed-form eigenpairs of h^-2 tridiag(-1, 2, -1) of order n (Section 3.2
-// eq. Sy; Section 4.2 with M = I): S[j][k] = sqrt(2/(n+1)) sin(j k pi/(n+1)),
-// lam_k = 4 (n+1)^2 sin^2(k pi / (2(n+1))), stored zero-padded to p x p; the
-// padded eigenvalues repeat lam_n so padded denominators stay positive.
-void eigen_1d(int n, int p, std::vector<double>& S, std::vector<double>& lam) {
-  const long long m = n + 1;
-  const double pi = 3.14159265358979323846;
-  S.assign((size_t)p * p, 0.0);
-  lam.assign((size_t)p, 0.0);
-  const double nrm = std::sqrt(2.0 / (double)m);
-  for (int j = 1; j <= n; ++j)
-    for (int k = 1; k <= n; ++k) {
-      const long long red = ((long long)j * k) % (2 * m);
-      S[(size_t)(j - 1) * p + (k - 1)] = nrm * std::sin(pi * (double)red / (double)m);
-    }
-  for (int k = 1; k <= n; ++k) {
-    const double s = std::sin(pi * k / (2.0 * m));
-    lam[k - 1] = 4.0 * (double)(m * m) * s * s;
-  }
-  for (int k = n; k < p; ++k) lam[k] = lam[n - 1];
-}
-
 int rule_of(qn_ctx c) {
   if (c->nl == QN_NL_QUASILIN) return RULE_COEFF_MID;
   return c->beta_mode == QN_BETA_MIDPOINT ? RULE_MIDPOINT : RULE_FIXED;
 }
+
+FoldOperands fold_ops(qn_ctx c, int axis) {
+  const size_t bb = (size_t)c->ax[axis].bk * c->ax[axis].bk * c->elem();
+  char* base = c->ws + c->off_S[axis];
+  FoldOperands f{};
+  f.FeT = base;
+  f.FoT = base + bb;
+  f.Fe = base + 2 * bb;
+  f.Fo = base + 3 * bb;
+  return f;
+}
+
+// Largest admissible tile (tm, tn) among the instantiated shapes of a fold kernel.
+void pick2(const int (*cand)[2], int ncand, long long mext, long long next, int& tm, int& tn) {
+  for (int i = 0; i < ncand; ++i)
+    if (mext % cand[i][0] == 0 && next % cand[i][1] == 0) {
+      tm = cand[i][0];
+      tn = cand[i][1];
+      return;
+    }
+  tm = tn = 32;
+}
+const int kLfwd[5][2] = {{128, 128}, {64, 128}, {64, 64}, {32, 64}, {32, 32}};
+const int kLinv[4][2] = {{64, 128}, {64, 64}, {32, 64}, {32, 32}};
+const int kRfwd[5][2] = {{128, 128}, {128, 64}, {64, 64}, {64, 32}, {32, 32}};
+const int kRinv[4][2] = {{128, 64}, {64, 64}, {64, 32}, {32, 32}};
 
 GemmOperands operands(qn_ctx c, int axis) {
   GemmOperands g{};
@@ -271,8 +266,70 @@ hipError_t solve_ws(qn_ctx c, const double* coef, double* dense, int epi_last) {
   ep.ny = c->n[1];
   ep.nz = c->n[2];
   ep.lamX = c->at<double>(c->off_lam[0]);
-  const GemmOperands Sx = operands(c, 0), Sy = operands(c, 1), Sz = operands(c, 2);
   const int rows = c->ncomp * pz * py;
+  const long long yslab_f = (long long)py * px;
+  hipError_t ef;
+  if (c->fold) {
+    const FoldOperands Fx = fold_ops(c, 0), Fy = fold_ops(c, 1), Fz = fold_ops(c, 2);
+    int tm, tn;
+#define QN_TRYF(x)                    \
+  do {                                \
+    ef = (x);                         \
+    if (ef != hipSuccess) return ef;  \
+  } while (0)
+    pick2(kRfwd, 5, rows, c->ax[0].bk, tm, tn);
+    QN_TRYF(timed(c, K_GEMM_X, [&] {
+      return launch_fold_right_fwd(pr, Fx, W1, W2, c->ax[0], rows, ep, tm, tn, c->stream);
+    }));
+    if (c->dim == 2) {
+      EpiArgs ed = ep;
+      ed.lamM = c->at<double>(c->off_lam[1]);
+      ed.lamY = nullptr;
+      pick2(kLfwd, 5, c->ax[1].bk, px, tm, tn);
+      QN_TRYF(timed(c, K_GEMM_DIVIDE, [&] {
+        return launch_fold_left_fwd(pr, Fy, W2, W1, c->ax[1], px, c->ncomp, yslab_f, EPI_DIVIDE,
+                                    ed, tm, tn, c->stream);
+      }));
+      pick2(kLinv, 4, c->ax[1].bk, px, tm, tn);
+      QN_TRYF(timed(c, K_GEMM_YZ_INV, [&] {
+        return launch_fold_left_inv(pr, Fy, W1, W2, c->ax[1], px, c->ncomp, yslab_f, ep, tm, tn,
+                                    c->stream);
+      }));
+    } else {
+      const long long zslab = (long long)pz * py * px;
+      pick2(kLfwd, 5, c->ax[1].bk, px, tm, tn);
+      QN_TRYF(timed(c, K_GEMM_YZ, [&] {
+        return launch_fold_left_fwd(pr, Fy, W2, W1, c->ax[1], px, c->ncomp * pz, yslab_f,
+                                    EPI_STORE, ep, tm, tn, c->stream);
+      }));
+      EpiArgs ed = ep;
+      ed.lamM = c->at<double>(c->off_lam[2]);
+      ed.lamY = c->at<double>(c->off_lam[1]);
+      pick2(kLfwd, 5, c->ax[2].bk, yslab_f, tm, tn);
+      QN_TRYF(timed(c, K_GEMM_DIVIDE, [&] {
+        return launch_fold_left_fwd(pr, Fz, W1, W2, c->ax[2], (int)yslab_f, c->ncomp, zslab,
+                                    EPI_DIVIDE, ed, tm, tn, c->stream);
+      }));
+      pick2(kLinv, 4, c->ax[2].bk, yslab_f, tm, tn);
+      QN_TRYF(timed(c, K_GEMM_YZ_INV, [&] {
+        return launch_fold_left_inv(pr, Fz, W2, W1, c->ax[2], (int)yslab_f, c->ncomp, zslab, ep,
+                                    tm, tn, c->stream);
+      }));
+      pick2(kLinv, 4, c->ax[1].bk, px, tm, tn);
+      QN_TRYF(timed(c, K_GEMM_YZ_INV, [&] {
+        return launch_fold_left_inv(pr, Fy, W1, W2, c->ax[1], px, c->ncomp * pz, yslab_f, ep, tm,
+                                    tn, c->stream);
+      }));
+    }
+    pick2(kRinv, 4, rows, c->ax[0].bk, tm, tn);
+    QN_TRYF(timed(c, K_GEMM_X_UPDATE, [&] {
+      return launch_fold_right_inv(pr, Fx, W2, nullptr, c->ax[0], rows, epi_last, ep, tm, tn,
+                                   c->stream);
+    }));
+#undef QN_TRYF
+    return hipSuccess;
+  }
+  const GemmOperands Sx = operands(c, 0), Sy = operands(c, 1), Sz = operands(c, 2);
   const int tmx = pick_tile(rows), tnx = pick_tile(px);
   const int tmy = pick_tile(py), tny = pick_tile(px);
   const long long yslab = (long long)py * px;
@@ -366,11 +423,24 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   c->n[0] = grid->n[0];
   c->n[1] = grid->n[1];
   c->n[2] = grid->dim == 3 ? grid->n[2] : 1;
-  for (int a = 0; a < 3; ++a) c->p[a] = (a < c->dim) ? ((c->n[a] + 31) / 32) * 32 : 1;
+  c->fold = c->prec != QN_PREC_BF16X3;
   c->lam_min_sum = 0.0;
-  for (int a = 0; a < c->dim; ++a) {
-    eigen_1d(c->n[a], c->p[a], c->hS[a], c->hlam[a]);
-    c->lam_min_sum += c->hlam[a][0];
+  for (int a = 0; a < 3; ++a) {
+    if (a >= c->dim) {
+      c->p[a] = 1;
+      continue;
+    }
+    const int n = c->n[a];
+    if (c->fold) {
+      const int bk = fold_block(n);
+      c->ax[a] = FoldAxis{n, n / 2, n & 1, bk};
+      c->p[a] = 2 * bk;
+      fold_eigen(n, bk, c->hS[a], c->hlam[a]);
+    } else {
+      c->p[a] = ((n + 31) / 32) * 32;
+      dense_eigen(n, c->p[a], c->hS[a], c->hlam[a]);
+    }
+    c->lam_min_sum += c->hlam[a][0];  // lam_1 leads both orderings
   }
   // The fixed beta must give a positive definite solve operator (Section 5:
   // beta > -lam_min(A_h)).  The midpoint rules produce beta >= 0 here.
@@ -383,7 +453,7 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
 
   size_t off = 0;
   for (int a = 0; a < c->dim; ++a) {
-    const size_t pp = (size_t)c->p[a] * c->p[a];
+    const size_t pp = c->hS[a].size();  // p*p dense, or 4 bk^2 = p*p folded
     const size_t eb = c->prec == QN_PREC_FP64 ? 8 : (c->prec == QN_PREC_FP32 ? 4 : 2);
     c->off_S[a] = off;
     off += align256(pp * eb);
@@ -398,6 +468,7 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
     c->off_S[2] = c->off_S[1];
     c->off_Slo[2] = c->off_Slo[1];
     c->off_lam[2] = c->off_lam[1];
+    c->ax[2] = c->ax[1];
   }
   c->off_W1 = off;
   off += align256(c->tensor_elems() * c->elem());
@@ -432,7 +503,7 @@ qn_status qn_bind_workspace(qn_ctx c, void* d_ws, size_t bytes) {
   hipError_t e = launch_zero(c->ws, c->need, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "zero workspace");
   for (int a = 0; a < c->dim; ++a) {
-    const size_t pp = (size_t)c->p[a] * c->p[a];
+    const size_t pp = c->hS[a].size();
     if (c->prec == QN_PREC_FP64) {
       e = hipMemcpyAsync(c->ws + c->off_S[a], c->hS[a].data(), pp * 8, hipMemcpyHostToDevice,
                          c->stream);
@@ -446,7 +517,7 @@ qn_status qn_bind_workspace(qn_ctx c, void* d_ws, size_t bytes) {
       for (size_t i = 0; i < pp; ++i) {
         const double v = c->hS[a][i];
         hi[i] = bf16_rne((float)v);
-        lo[i] = bf16_rne((float)(v - (double)bf16_to_float(hi[i])));
+        lo[i] = bf16_rne((float)(v - (double)bf16_value(hi[i])));
       }
       e = hipMemcpyAsync(c->ws + c->off_S[a], hi.data(), pp * 2, hipMemcpyHostToDevice, c->stream);
       if (e == hipSuccess)

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/qn_batched.h"
+#include "qn_host.h"
 #include "qn_internal.h"
 
 namespace qn {
@@ -27,19 +28,6 @@ using namespace qn;
 namespace {
 
 size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
-
-uint16_t bf16_rne(float f) {
-  uint32_t u;
-  std::memcpy(&u, &f, 4);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-float bf16_val(uint16_t h) {
-  uint32_t u = (uint32_t)h << 16;
-  float f;
-  std::memcpy(&f, &u, 4);
-  return f;
-}
 
 int largest_tile(long long extent) {
   if (extent % 128 == 0) return 128;
@@ -54,8 +42,11 @@ struct Cls {
   size_t off_S = 0, off_Slo = 0, off_lam = 0, off_W1 = 0, off_W2 = 0, off_part = 0, off_state = 0,
          off_done = 0;
   int bpi = 0;                // residual workgroups per instance
-  int tmL = 32, tnL = 32;     // y-product tile
-  int tmR = 32, tnR = 32;     // x-product tile
+  int tmL = 32, tnL = 32;     // y-product tile (forward)
+  int tmR = 32, tnR = 32;     // x-product tile (forward)
+  int tmLi = 32, tnLi = 32;   // y-product tile (inverse, folded)
+  int tmRi = 32, tnRi = 32;   // x-product tile (inverse, folded)
+  FoldAxis ax{};
   hipStream_t s = nullptr;    // per-class stream (default priority)
   hipEvent_t ev = nullptr;
   std::vector<double> hS, hlam;
@@ -65,6 +56,7 @@ struct Cls {
 
 struct qnb_ctx_s {
   int count = 0, prec = 0, beta_mode = 0;
+  bool fold = true;  // reflection-folded transforms (FP64/FP32); dense for bf16x3
   double beta = 0.0;
   std::vector<int> n, ncomp, inst_cls, inst_pos;
   std::vector<Cls> cls;
@@ -93,23 +85,22 @@ qn_status hip_bad(qnb_ctx c, hipError_t e, const char* what) {
   return set_error(QN_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-void eigen_1d(int n, int p, std::vector<double>& S, std::vector<double>& lam) {
-  const long long m = n + 1;
-  const double pi = 3.14159265358979323846;
-  S.assign((size_t)p * p, 0.0);
-  lam.assign((size_t)p, 0.0);
-  const double nrm = std::sqrt(2.0 / (double)m);
-  for (int j = 1; j <= n; ++j)
-    for (int k = 1; k <= n; ++k) {
-      const long long red = ((long long)j * k) % (2 * m);
-      S[(size_t)(j - 1) * p + (k - 1)] = nrm * std::sin(pi * (double)red / (double)m);
-    }
-  for (int k = 1; k <= n; ++k) {
-    const double s = std::sin(pi * k / (2.0 * m));
-    lam[k - 1] = 4.0 * (double)(m * m) * s * s;
-  }
-  for (int k = n; k < p; ++k) lam[k] = lam[n - 1];
+FoldOperands fops(qnb_ctx c, const Cls& k) {
+  const size_t bb = (size_t)k.ax.bk * k.ax.bk * c->elem();
+  char* base = c->ws + k.off_S;
+  FoldOperands f{};
+  f.FeT = base;
+  f.FoT = base + bb;
+  f.Fe = base + 2 * bb;
+  f.Fo = base + 3 * bb;
+  return f;
 }
+
+// Instantiated tile shapes of the folded kernels (see qn_gemm_fold.hip).
+const int kLfwd[5][2] = {{128, 128}, {64, 128}, {64, 64}, {32, 64}, {32, 32}};
+const int kLinv[4][2] = {{64, 128}, {64, 64}, {32, 64}, {32, 32}};
+const int kRfwd[5][2] = {{128, 128}, {128, 64}, {64, 64}, {64, 32}, {32, 32}};
+const int kRinv[4][2] = {{128, 64}, {64, 64}, {64, 32}, {32, 32}};
 
 GemmOperands ops(qnb_ctx c, const Cls& k) {
   GemmOperands g{};
@@ -177,6 +168,19 @@ hipError_t class_iteration(qnb_ctx c, Cls& k, double* U, const double* F, double
   const int rows = k.ncomp * k.K * k.p;
   const int slabs = k.ncomp * k.K;
   const long long sl = (long long)k.p * k.p;
+  if (c->fold) {
+    const FoldOperands F = fops(c, k);
+    e = launch_fold_right_fwd(c->prec, F, W1, W2, k.ax, rows, ep, k.tmR, k.tnR, s);
+    if (e == hipSuccess)
+      e = launch_fold_left_fwd(c->prec, F, W2, W1, k.ax, k.p, slabs, sl, EPI_DIVIDE, ep, k.tmL,
+                               k.tnL, s);
+    if (e == hipSuccess)
+      e = launch_fold_left_inv(c->prec, F, W1, W2, k.ax, k.p, slabs, sl, ep, k.tmLi, k.tnLi, s);
+    if (e == hipSuccess)
+      e = launch_fold_right_inv(c->prec, F, W2, nullptr, k.ax, rows, EPI_SUB_DENSE, ep, k.tmRi,
+                                k.tnRi, s);
+    return e;
+  }
   e = launch_gemm_right(c->prec, S, W1, W2, rows, k.p, EPI_STORE, ep, k.tmR, k.tnR, s);
   if (e == hipSuccess)
     e = launch_gemm_left(c->prec, S, W2, W1, k.p, k.p, slabs, sl, EPI_DIVIDE, ep, k.tmL, k.tnL, s);
@@ -243,7 +247,13 @@ qn_status qnb_setup(int32_t count, const int32_t* n, const int32_t* ncomp, int32
       Cls k;
       k.n = n[i];
       k.ncomp = ncomp[i];
-      k.p = ((n[i] + 31) / 32) * 32;
+      if (precision != QN_PREC_BF16X3) {
+        const int bk = fold_block(n[i]);
+        k.ax = FoldAxis{n[i], n[i] / 2, n[i] & 1, bk};
+        k.p = 2 * bk;
+      } else {
+        k.p = ((n[i] + 31) / 32) * 32;
+      }
       c->cls.push_back(k);
     } else {
       ci = it->second;
@@ -255,12 +265,16 @@ qn_status qnb_setup(int32_t count, const int32_t* n, const int32_t* ncomp, int32
   double lam_min = 1e300;
   long long fe = 0;
   size_t off = 0;
+  c->fold = precision != QN_PREC_BF16X3;
   for (auto& k : c->cls) {
-    eigen_1d(k.n, k.p, k.hS, k.hlam);
+    if (c->fold)
+      fold_eigen(k.n, k.ax.bk, k.hS, k.hlam);
+    else
+      dense_eigen(k.n, k.p, k.hS, k.hlam);
     lam_min = std::min(lam_min, 2.0 * k.hlam[0]);
     k.off_field = fe;
     fe += (long long)k.ncomp * k.K * k.n * k.n;
-    const size_t pp = (size_t)k.p * k.p;
+    const size_t pp = k.hS.size();
     const size_t eb = precision == QN_PREC_FP64 ? 8 : (precision == QN_PREC_FP32 ? 4 : 2);
     k.off_S = off;
     off += a256(pp * eb);
@@ -282,12 +296,27 @@ qn_status qnb_setup(int32_t count, const int32_t* n, const int32_t* ncomp, int32
     off += a256((size_t)k.K * sizeof(BState));
     k.off_done = off;
     off += a256((size_t)k.K * sizeof(int));
-    k.tmL = largest_tile(k.p);
-    k.tnL = largest_tile(k.p);
     // An x-product row tile must not straddle two instances (skip flags are
-    // per tile), so its height divides P.
-    k.tmR = largest_tile(k.p);
-    k.tnR = largest_tile(k.p);
+    // per tile), so its height divides P; folded tiles stay inside one half.
+    if (c->fold) {
+      auto first = [&](const int (*cand)[2], int nc, int mext, int next, int& tm, int& tn) {
+        for (int q = 0; q < nc; ++q)
+          if (mext % cand[q][0] == 0 && next % cand[q][1] == 0) {
+            tm = cand[q][0];
+            tn = cand[q][1];
+            return;
+          }
+      };
+      first(kRfwd, 5, k.p, k.ax.bk, k.tmR, k.tnR);
+      first(kLfwd, 5, k.ax.bk, k.p, k.tmL, k.tnL);
+      first(kLinv, 4, k.ax.bk, k.p, k.tmLi, k.tnLi);
+      first(kRinv, 4, k.p, k.ax.bk, k.tmRi, k.tnRi);
+    } else {
+      k.tmL = largest_tile(k.p);
+      k.tnL = largest_tile(k.p);
+      k.tmR = largest_tile(k.p);
+      k.tnR = largest_tile(k.p);
+    }
   }
   if (beta_mode == QN_BETA_FIXED && lam_min + beta <= 0.0) {
     delete c;
@@ -342,7 +371,7 @@ qn_status qnb_bind_workspace(qnb_ctx c, void* d_ws, size_t bytes) {
   }
   if (e == hipSuccess) e = launch_zero(c->ws, c->need, c->stream);
   for (auto& k : c->cls) {
-    const size_t pp = (size_t)k.p * k.p;
+    const size_t pp = k.hS.size();
     if (e != hipSuccess) break;
     if (c->prec == QN_PREC_FP64) {
       e = hipMemcpyAsync(c->ws + k.off_S, k.hS.data(), pp * 8, hipMemcpyHostToDevice, c->stream);
@@ -355,7 +384,7 @@ qn_status qnb_bind_workspace(qnb_ctx c, void* d_ws, size_t bytes) {
       std::vector<uint16_t> hi(pp), lo(pp);
       for (size_t i = 0; i < pp; ++i) {
         hi[i] = bf16_rne((float)k.hS[i]);
-        lo[i] = bf16_rne((float)(k.hS[i] - (double)bf16_val(hi[i])));
+        lo[i] = bf16_rne((float)(k.hS[i] - (double)bf16_value(hi[i])));
       }
       e = hipMemcpyAsync(c->ws + k.off_S, hi.data(), pp * 2, hipMemcpyHostToDevice, c->stream);
       if (e == hipSuccess)
@@ -388,13 +417,40 @@ qn_status qnb_autotune(qnb_ctx c) {
     void* W2 = c->ws + k.off_W2;
     const int rows = k.ncomp * k.K * k.p, slabs = k.ncomp * k.K;
     const long long sl = (long long)k.p * k.p;
-    for (int form = 0; form < 2 && e == hipSuccess; ++form) {
+    const FoldOperands F = c->fold ? fops(c, k) : FoldOperands{};
+    const int nforms = c->fold ? 4 : 2;
+    for (int form = 0; form < nforms && e == hipSuccess; ++form) {
       float best = 1e30f;
       int bm = 32, bn = 32;
       for (int tm : cand)
         for (int tn : cand) {
-          if (k.p % tm || k.p % tn) continue;  // tiles never straddle instances
+          if (!c->fold && (k.p % tm || k.p % tn)) continue;  // tiles never straddle instances
+          if (c->fold) {
+            const int(*cl)[2] = form == 0 ? kLfwd : form == 1 ? kRfwd : form == 2 ? kLinv : kRinv;
+            const int ncl = (form == 0 || form == 1) ? 5 : 4;
+            bool listed = false;
+            for (int q = 0; q < ncl; ++q) listed = listed || (cl[q][0] == tm && cl[q][1] == tn);
+            const int mext = (form == 1 || form == 3) ? k.p : k.ax.bk;
+            const int next = (form == 1 || form == 3) ? k.ax.bk : k.p;
+            if (!listed || mext % tm || next % tn) continue;
+          }
           auto run = [&]() {
+            if (c->fold) {
+              switch (form) {
+                case 0:
+                  return launch_fold_left_fwd(c->prec, F, W1, W2, k.ax, k.p, slabs, sl, EPI_STORE,
+                                              ep, tm, tn, c->stream);
+                case 1:
+                  return launch_fold_right_fwd(c->prec, F, W1, W2, k.ax, rows, ep, tm, tn,
+                                               c->stream);
+                case 2:
+                  return launch_fold_left_inv(c->prec, F, W1, W2, k.ax, k.p, slabs, sl, ep, tm, tn,
+                                              c->stream);
+                default:
+                  return launch_fold_right_inv(c->prec, F, W1, W2, k.ax, rows, EPI_STORE, ep, tm,
+                                               tn, c->stream);
+              }
+            }
             return form == 0 ? launch_gemm_left(c->prec, S, W1, W2, k.p, k.p, slabs, sl, EPI_STORE,
                                                 ep, tm, tn, c->stream)
                              : launch_gemm_right(c->prec, S, W1, W2, rows, k.p, EPI_STORE, ep, tm,
@@ -417,9 +473,15 @@ qn_status qnb_autotune(qnb_ctx c) {
       if (form == 0) {
         k.tmL = bm;
         k.tnL = bn;
-      } else {
+      } else if (form == 1) {
         k.tmR = bm;
         k.tnR = bn;
+      } else if (form == 2) {
+        k.tmLi = bm;
+        k.tnLi = bn;
+      } else {
+        k.tmRi = bm;
+        k.tnRi = bn;
       }
     }
   }

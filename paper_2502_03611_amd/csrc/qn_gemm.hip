@@ -24,37 +24,9 @@
 // tiles, so a panel is fetched into one XCD's L2 and reused there.
 
 #include "qn_internal.h"
+#include "qn_mfma.h"
 
 namespace qn {
-
-template <typename T>
-struct Mfma;
-
-template <>
-struct Mfma<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static constexpr int TK = 16;
-  __device__ static inline v4 op(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  // Output row of accumulator element q held by `lane` (column = lane % 16).
-  __device__ static inline int row(int lane, int q) { return (lane >> 4) + 4 * q; }
-};
-
-template <>
-struct Mfma<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static constexpr int TK = 32;
-  __device__ static inline v4 op(float a, float b, v4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  __device__ static inline int row(int lane, int q) { return 4 * (lane >> 4) + q; }
-};
-
-// Tile index for workgroup w: each XCD (w % 8) gets a contiguous tile range.
-__device__ inline int xcd_tile(int w, int total) {
-  return (total % 8 == 0) ? (w % 8) * (total / 8) + (w / 8) : w;
-}
 
 // Padded row r = (c * pz + z) * py + y of a form-R product -> offset of the
 // dense caller row (c, z, y); false for padding rows.

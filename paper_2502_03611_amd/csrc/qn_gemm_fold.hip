@@ -1,0 +1,727 @@
+// Mode products with the reflection-folded eigenvector matrix.
+//
+// The sine eigenvectors of the 1D stiffness matrix (Section 3.2 eq. Sy) are
+// symmetric or antisymmetric about the grid centre: S[n-1-j][k] = (-1)^k S[j][k]
+// (0-based).  The forward transform y = S^T x therefore splits into
+//   y[2i]   = sum_{j<h} S[j][2i]   (x[j] + x[n-1-j]) + [n odd] S[h][2i] x[h]
+//   y[2i+1] = sum_{j<h} S[j][2i+1] (x[j] - x[n-1-j])
+// (h = n/2), and the inverse x = S y into p = S_even y_even, q = S_odd y_odd,
+// x[j] = p[j] + q[j], x[n-1-j] = p[j] - q[j], x[h] = p[h].  Each mode product
+// of Section 4.1 (eq. fin_inverse) is thus two GEMMs of half the contraction
+// length: the same result with half the matrix-core work.
+//
+// Storage: along a folded axis the spectral index is kept split, even modes
+// in [0, bk) and odd modes in [bk, 2 bk) (bk = ceil(n/2) rounded up to 32);
+// spatial layout is natural with padded extent 2 bk.  Matrices (bk x bk each):
+//   FeT[k][i] = S[k][2i], FoT[k][i] = S[k][2i+1]   (forward: rows k contiguous in i)
+//   Fe[i][k]  = S[k][2i], Fo[i][k]  = S[k][2i+1]   (inverse: rows i contiguous in k)
+// zero outside the valid block.  Forward loaders fold the contracted operand
+// on the fly (two loads per element); inverse kernels keep p and q
+// accumulators for the same fold rows and write both mirrored outputs.  Only
+// rows / columns below n of a spatial axis are ever read or written.
+//
+// Tiling, LDS staging, XCD-aware tile order and epilogues follow the dense
+// kernels (qn_gemm.hip).
+
+#include "qn_internal.h"
+#include "qn_mfma.h"
+
+namespace qn {
+
+// ------------------------------------------------------------------ form L
+
+// Forward, contraction over the slab rows (the folded axis):
+// C[b][m][c] (m in [0, 2 bk)) = sum_{k<bk} F^T_blk[k][i] * fold_blk(B[b])[k][c],
+// blk = m / bk, i = m % bk.
+template <typename T, int TM, int TN, int EPI>
+__global__ __launch_bounds__(256, 2) void k_fold_left_fwd(const T* __restrict__ FeT,
+                                                          const T* __restrict__ FoT,
+                                                          const T* __restrict__ B,
+                                                          T* __restrict__ C, FoldAxis ax, int ncols,
+                                                          int batch, long long bstride, EpiArgs ep) {
+  using MF = Mfma<T>;
+  constexpr int TK = MF::TK;
+  constexpr int VE = 16 / sizeof(T);
+  typedef T V __attribute__((ext_vector_type(VE)));
+  constexpr int WM = TM / 2, WN = TN / 2, BM = WM / 16, BN = WN / 16;
+  constexpr int NA = (TK * TM / VE + 255) / 256, NB = (TK * TN / VE + 255) / 256;
+  __shared__ __attribute__((aligned(16))) T As[2][TK][TM];
+  __shared__ __attribute__((aligned(16))) T Bs[2][TK][TN];
+
+  const int bk = ax.bk, P2 = 2 * bk, na = ax.n, h = ax.h;
+  const int MT = P2 / TM, NT = ncols / TN;
+  const int t = xcd_tile(blockIdx.x, batch * MT * NT);
+  const int mt = t % MT, rest = t / MT, nt = rest % NT, b = rest / NT;
+  const int inst = b % ep.inst_mod;
+  if (ep.skip && ep.skip[inst]) return;
+  const int m0 = mt * TM, n0 = nt * TN;
+  const int blk = m0 / bk, i0 = m0 - blk * bk;
+  const T* F = blk ? FoT : FeT;
+  const T* Bb = B + (long long)b * bstride;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+
+  typename MF::v4 acc[BM][BN];
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int j = 0; j < BN; ++j) acc[i][j] = typename MF::v4{0, 0, 0, 0};
+
+  // The prefetch keeps the raw row pair; the fold (lo +- hi) happens at the LDS
+  // store, so the global loads stay in flight across the MFMA phase.
+  V ra[NA], rlo[NB], rhi[NB];
+  int kpre = 0;
+  auto gload = [&](int k0) {
+    kpre = k0;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TK * TM / VE) {
+        const int kk = v / (TM / VE), mm = (v % (TM / VE)) * VE;
+        ra[i] = *reinterpret_cast<const V*>(F + (long long)(k0 + kk) * bk + i0 + mm);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TK * TN / VE) {
+        const int kk = v / (TN / VE), nn = (v % (TN / VE)) * VE;
+        const int k = k0 + kk;
+        // rows k and n-1-k (the centre row pairs with itself); clamped for k > h
+        const int kl = k <= h ? k : h, kh = k < h ? na - 1 - k : h;
+        rlo[i] = *reinterpret_cast<const V*>(Bb + (long long)kl * ncols + n0 + nn);
+        rhi[i] = *reinterpret_cast<const V*>(Bb + (long long)kh * ncols + n0 + nn);
+      }
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TK * TM / VE) {
+        const int kk = v / (TM / VE), mm = (v % (TM / VE)) * VE;
+        *reinterpret_cast<V*>(&As[buf][kk][mm]) = ra[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TK * TN / VE) {
+        const int kk = v / (TN / VE), nn = (v % (TN / VE)) * VE;
+        const int k = kpre + kk;
+        V val = V{};
+        if (k < h)
+          val = blk ? rlo[i] - rhi[i] : rlo[i] + rhi[i];
+        else if (k == h && ax.odd && !blk)
+          val = rlo[i];
+        *reinterpret_cast<V*>(&Bs[buf][kk][nn]) = val;
+      }
+    }
+  };
+
+  // Fold rows at or beyond ne = h + odd contribute nothing: stop the K loop there.
+  const int kmax = ((h + ax.odd + TK - 1) / TK) * TK;
+  const int nk = kmax / TK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kc = 0; kc < nk; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nk) gload((kc + 1) * TK);
+#pragma unroll
+    for (int ks = 0; ks < TK; ks += 4) {
+      T a[BM], bb[BN];
+#pragma unroll
+      for (int i = 0; i < BM; ++i) a[i] = As[buf][ks + (lane >> 4)][wm + 16 * i + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < BN; ++j) bb[j] = Bs[buf][ks + (lane >> 4)][wn + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) acc[i][j] = MF::op(a[i], bb[j], acc[i][j]);
+    }
+    if (kc + 1 < nk) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  T* Cb = C + (long long)b * bstride;
+  if (EPI == EPI_DIVIDE) {
+    const double* cf = ep.coef + (long long)inst * ep.coef_stride;
+    const double scale = cf[0], beta = cf[1];
+    double cn[BN];
+#pragma unroll
+    for (int j = 0; j < BN; ++j) {
+      const int n = n0 + wn + 16 * j + (lane & 15);
+      const int ny_ = n / ep.px;
+      cn[j] = ep.lamX[n - ny_ * ep.px] + (ep.lamY ? ep.lamY[ny_] : 0.0);
+    }
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + wm + 16 * i + MF::row(lane, q);
+        const double lm = ep.lamM[m];
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          const int n = n0 + wn + 16 * j + (lane & 15);
+          Cb[(long long)m * ncols + n] = (T)((double)acc[i][j][q] / (scale * (lm + cn[j]) + beta));
+        }
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + wm + 16 * i + MF::row(lane, q);
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+          Cb[(long long)m * ncols + n0 + wn + 16 * j + (lane & 15)] = acc[i][j][q];
+      }
+  }
+}
+
+// Inverse, contraction over the split spectral rows, output spatial rows:
+// p[k][c] = sum_{i<bk} Fe[i][k] Y[b][i][c], q[k][c] = sum_{i<bk} Fo[i][k] Y[b][bk+i][c];
+// C[b][k] = p + q, C[b][n-1-k] = p - q (k < h), C[b][h] = p (n odd).
+// A tile owns TMF fold rows (2 TMF output rows) x TN columns.
+template <typename T, int TMF, int TN>
+__global__ __launch_bounds__(256, 2) void k_fold_left_inv(const T* __restrict__ Fe,
+                                                          const T* __restrict__ Fo,
+                                                          const T* __restrict__ Y,
+                                                          T* __restrict__ C, FoldAxis ax, int ncols,
+                                                          int batch, long long bstride, EpiArgs ep) {
+  using MF = Mfma<T>;
+  constexpr int TK = MF::TK / 2;
+  constexpr int VE = 16 / sizeof(T);
+  typedef T V __attribute__((ext_vector_type(VE)));
+  constexpr int WM = TMF / 2, WN = TN / 2, BM = WM / 16, BN = WN / 16;
+  constexpr int NA = (TK * TMF / VE + 255) / 256, NB = (TK * TN / VE + 255) / 256;
+  __shared__ __attribute__((aligned(16))) T Ap[2][TK][TMF];
+  __shared__ __attribute__((aligned(16))) T Aq[2][TK][TMF];
+  __shared__ __attribute__((aligned(16))) T Bp[2][TK][TN];
+  __shared__ __attribute__((aligned(16))) T Bq[2][TK][TN];
+
+  const int bk = ax.bk, na = ax.n, h = ax.h;
+  const int MT = bk / TMF, NT = ncols / TN;
+  const int t = xcd_tile(blockIdx.x, batch * MT * NT);
+  const int mt = t % MT, rest = t / MT, nt = rest % NT, b = rest / NT;
+  const int inst = b % ep.inst_mod;
+  if (ep.skip && ep.skip[inst]) return;
+  const int k0 = mt * TMF, n0 = nt * TN;
+  if (k0 > h) return;  // only padding fold rows: nothing to write
+  const T* Yb = Y + (long long)b * bstride;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+
+  typename MF::v4 accp[BM][BN], accq[BM][BN];
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int j = 0; j < BN; ++j) accp[i][j] = accq[i][j] = typename MF::v4{0, 0, 0, 0};
+
+  V rap[NA], raq[NA], rbp[NB], rbq[NB];
+  auto gload = [&](int i0) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TK * TMF / VE) {
+        const int ii = v / (TMF / VE), mm = (v % (TMF / VE)) * VE;
+        rap[i] = *reinterpret_cast<const V*>(Fe + (long long)(i0 + ii) * bk + k0 + mm);
+        raq[i] = *reinterpret_cast<const V*>(Fo + (long long)(i0 + ii) * bk + k0 + mm);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TK * TN / VE) {
+        const int ii = v / (TN / VE), nn = (v % (TN / VE)) * VE;
+        rbp[i] = *reinterpret_cast<const V*>(Yb + (long long)(i0 + ii) * ncols + n0 + nn);
+        rbq[i] = *reinterpret_cast<const V*>(Yb + (long long)(bk + i0 + ii) * ncols + n0 + nn);
+      }
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TK * TMF / VE) {
+        const int ii = v / (TMF / VE), mm = (v % (TMF / VE)) * VE;
+        *reinterpret_cast<V*>(&Ap[buf][ii][mm]) = rap[i];
+        *reinterpret_cast<V*>(&Aq[buf][ii][mm]) = raq[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TK * TN / VE) {
+        const int ii = v / (TN / VE), nn = (v % (TN / VE)) * VE;
+        *reinterpret_cast<V*>(&Bp[buf][ii][nn]) = rbp[i];
+        *reinterpret_cast<V*>(&Bq[buf][ii][nn]) = rbq[i];
+      }
+    }
+  };
+
+  // Spectral rows at or beyond ne (even) are exactly zero in both operands.
+  const int imax = ((h + ax.odd + TK - 1) / TK) * TK;
+  const int nk = imax / TK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kc = 0; kc < nk; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nk) gload((kc + 1) * TK);
+#pragma unroll
+    for (int ks = 0; ks < TK; ks += 4) {
+      T ap[BM], aq[BM], bp[BN], bq[BN];
+#pragma unroll
+      for (int i = 0; i < BM; ++i) {
+        ap[i] = Ap[buf][ks + (lane >> 4)][wm + 16 * i + (lane & 15)];
+        aq[i] = Aq[buf][ks + (lane >> 4)][wm + 16 * i + (lane & 15)];
+      }
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        bp[j] = Bp[buf][ks + (lane >> 4)][wn + 16 * j + (lane & 15)];
+        bq[j] = Bq[buf][ks + (lane >> 4)][wn + 16 * j + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          accp[i][j] = MF::op(ap[i], bp[j], accp[i][j]);
+          accq[i][j] = MF::op(aq[i], bq[j], accq[i][j]);
+        }
+    }
+    if (kc + 1 < nk) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  T* Cb = C + (long long)b * bstride;
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + wm + 16 * i + MF::row(lane, q);
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        const int n = n0 + wn + 16 * j + (lane & 15);
+        const T p = accp[i][j][q], qq = accq[i][j][q];
+        if (k < h) {
+          Cb[(long long)k * ncols + n] = p + qq;
+          Cb[(long long)(na - 1 - k) * ncols + n] = p - qq;
+        } else if (k == h && ax.odd) {
+          Cb[(long long)k * ncols + n] = p;
+        }
+      }
+    }
+}
+
+// ------------------------------------------------------------------ form R
+
+// Forward along x (contraction over the columns of A's rows):
+// C[r][m] = sum_{k<bk} fold_blk(A[r])[k] F^T_blk[k][i], blk = m / bk, i = m % bk.
+template <typename T, int TM, int TN>
+__global__ __launch_bounds__(256, 2) void k_fold_right_fwd(const T* __restrict__ A,
+                                                           const T* __restrict__ FeT,
+                                                           const T* __restrict__ FoT,
+                                                           T* __restrict__ C, FoldAxis ax, int rows,
+                                                           EpiArgs ep) {
+  using MF = Mfma<T>;
+  constexpr int TK = MF::TK;
+  constexpr int VE = 16 / sizeof(T);
+  typedef T V __attribute__((ext_vector_type(VE)));
+  constexpr int WM = TM / 2, WN = TN / 2, BM = WM / 16, BN = WN / 16;
+  constexpr int NA = (TK * TM / VE + 255) / 256, NB = (TK * TN / VE + 255) / 256;
+  constexpr int AK = TK + VE;
+  __shared__ __attribute__((aligned(16))) T As[2][TM][AK];
+  __shared__ __attribute__((aligned(16))) T Bs[2][TK][TN];
+
+  const int bk = ax.bk, P2 = 2 * bk, na = ax.n, h = ax.h;
+  const int MT = rows / TM, NT = P2 / TN;
+  const int t = xcd_tile(blockIdx.x, MT * NT);
+  const int nt = t % NT, mt = t / NT;
+  const int r0 = mt * TM, n0 = nt * TN;
+  if (ep.skip && ep.skip[(r0 / ep.py / ep.pz) % ep.inst_mod]) return;
+  const int blk = n0 / bk, i0 = n0 - blk * bk;
+  const T* F = blk ? FoT : FeT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+
+  typename MF::v4 acc[BM][BN];
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int j = 0; j < BN; ++j) acc[i][j] = typename MF::v4{0, 0, 0, 0};
+
+  // Raw pairs (row element k and its mirror n-1-k) are prefetched; the fold
+  // happens at the LDS store so the loads overlap the MFMA phase.
+  V rlo[NA], rhi[NA], rb[NB];
+  int kpre = 0;
+  auto gload = [&](int k0) {
+    kpre = k0;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TM * TK / VE) {
+        const int row = v / (TK / VE), kv = (v % (TK / VE)) * VE;
+        const T* src = A + (long long)(r0 + row) * P2;
+        rlo[i] = *reinterpret_cast<const V*>(src + k0 + kv);
+#pragma unroll
+        for (int e = 0; e < VE; ++e) {
+          const int k = k0 + kv + e;
+          rhi[i][e] = src[k < h ? na - 1 - k : 0];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TK * TN / VE) {
+        const int kk = v / (TN / VE), nn = (v % (TN / VE)) * VE;
+        rb[i] = *reinterpret_cast<const V*>(F + (long long)(k0 + kk) * bk + i0 + nn);
+      }
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TM * TK / VE) {
+        const int row = v / (TK / VE), kv = (v % (TK / VE)) * VE;
+        V val;
+#pragma unroll
+        for (int e = 0; e < VE; ++e) {
+          const int k = kpre + kv + e;
+          T x = 0;
+          if (k < h)
+            x = blk ? rlo[i][e] - rhi[i][e] : rlo[i][e] + rhi[i][e];
+          else if (k == h && ax.odd && !blk)
+            x = rlo[i][e];
+          val[e] = x;
+        }
+        *reinterpret_cast<V*>(&As[buf][row][kv]) = val;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TK * TN / VE) {
+        const int kk = v / (TN / VE), nn = (v % (TN / VE)) * VE;
+        *reinterpret_cast<V*>(&Bs[buf][kk][nn]) = rb[i];
+      }
+    }
+  };
+
+  const int kmax = ((h + ax.odd + TK - 1) / TK) * TK;
+  const int nk = kmax / TK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kc = 0; kc < nk; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nk) gload((kc + 1) * TK);
+#pragma unroll
+    for (int ks = 0; ks < TK; ks += 4) {
+      T a[BM], bb[BN];
+#pragma unroll
+      for (int i = 0; i < BM; ++i) a[i] = As[buf][wm + 16 * i + (lane & 15)][ks + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < BN; ++j) bb[j] = Bs[buf][ks + (lane >> 4)][wn + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) acc[i][j] = MF::op(a[i], bb[j], acc[i][j]);
+    }
+    if (kc + 1 < nk) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = r0 + wm + 16 * i + MF::row(lane, q);
+#pragma unroll
+      for (int j = 0; j < BN; ++j)
+        C[(long long)r * P2 + n0 + wn + 16 * j + (lane & 15)] = acc[i][j][q];
+    }
+}
+
+// Inverse along x: p[r][k] = sum_i Y[r][i] Fe[i][k], q[r][k] = sum_i Y[r][bk+i] Fo[i][k];
+// output columns k and n-1-k (p + q, p - q), or h (p).  EPI: store into C
+// (row length 2 bk) or the dense epilogues (U -= dU / X = dU) on ep.dense.
+template <typename T, int TM, int TNF, int EPI>
+__global__ __launch_bounds__(256, 2) void k_fold_right_inv(const T* __restrict__ Y,
+                                                           const T* __restrict__ Fe,
+                                                           const T* __restrict__ Fo,
+                                                           T* __restrict__ C, FoldAxis ax, int rows,
+                                                           EpiArgs ep) {
+  using MF = Mfma<T>;
+  constexpr int TK = MF::TK / 2;
+  constexpr int VE = 16 / sizeof(T);
+  typedef T V __attribute__((ext_vector_type(VE)));
+  constexpr int WM = TM / 2, WN = TNF / 2, BM = WM / 16, BN = WN / 16;
+  constexpr int NA = (TM * TK / VE + 255) / 256, NB = (TK * TNF / VE + 255) / 256;
+  constexpr int AK = TK + VE;
+  __shared__ __attribute__((aligned(16))) T Ap[2][TM][AK];
+  __shared__ __attribute__((aligned(16))) T Aq[2][TM][AK];
+  __shared__ __attribute__((aligned(16))) T Bp[2][TK][TNF];
+  __shared__ __attribute__((aligned(16))) T Bq[2][TK][TNF];
+
+  const int bk = ax.bk, P2 = 2 * bk, na = ax.n, h = ax.h;
+  const int MT = rows / TM, NT = bk / TNF;
+  const int t = xcd_tile(blockIdx.x, MT * NT);
+  const int nt = t % NT, mt = t / NT;
+  const int r0 = mt * TM, k0 = nt * TNF;
+  if (ep.skip && ep.skip[(r0 / ep.py / ep.pz) % ep.inst_mod]) return;
+  if (k0 > h) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+
+  typename MF::v4 accp[BM][BN], accq[BM][BN];
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int j = 0; j < BN; ++j) accp[i][j] = accq[i][j] = typename MF::v4{0, 0, 0, 0};
+
+  V rap[NA], raq[NA], rbp[NB], rbq[NB];
+  auto gload = [&](int i0) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TM * TK / VE) {
+        const int row = v / (TK / VE), kv = (v % (TK / VE)) * VE;
+        const T* src = Y + (long long)(r0 + row) * P2 + i0 + kv;
+        rap[i] = *reinterpret_cast<const V*>(src);
+        raq[i] = *reinterpret_cast<const V*>(src + bk);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TK * TNF / VE) {
+        const int ii = v / (TNF / VE), nn = (v % (TNF / VE)) * VE;
+        rbp[i] = *reinterpret_cast<const V*>(Fe + (long long)(i0 + ii) * bk + k0 + nn);
+        rbq[i] = *reinterpret_cast<const V*>(Fo + (long long)(i0 + ii) * bk + k0 + nn);
+      }
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TM * TK / VE) {
+        const int row = v / (TK / VE), kv = (v % (TK / VE)) * VE;
+        *reinterpret_cast<V*>(&Ap[buf][row][kv]) = rap[i];
+        *reinterpret_cast<V*>(&Aq[buf][row][kv]) = raq[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TK * TNF / VE) {
+        const int ii = v / (TNF / VE), nn = (v % (TNF / VE)) * VE;
+        *reinterpret_cast<V*>(&Bp[buf][ii][nn]) = rbp[i];
+        *reinterpret_cast<V*>(&Bq[buf][ii][nn]) = rbq[i];
+      }
+    }
+  };
+
+  const int imax = ((h + ax.odd + TK - 1) / TK) * TK;
+  const int nk = imax / TK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kc = 0; kc < nk; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nk) gload((kc + 1) * TK);
+#pragma unroll
+    for (int ks = 0; ks < TK; ks += 4) {
+      T ap[BM], aq[BM], bp[BN], bq[BN];
+#pragma unroll
+      for (int i = 0; i < BM; ++i) {
+        ap[i] = Ap[buf][wm + 16 * i + (lane & 15)][ks + (lane >> 4)];
+        aq[i] = Aq[buf][wm + 16 * i + (lane & 15)][ks + (lane >> 4)];
+      }
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        bp[j] = Bp[buf][ks + (lane >> 4)][wn + 16 * j + (lane & 15)];
+        bq[j] = Bq[buf][ks + (lane >> 4)][wn + 16 * j + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          accp[i][j] = MF::op(ap[i], bp[j], accp[i][j]);
+          accq[i][j] = MF::op(aq[i], bq[j], accq[i][j]);
+        }
+    }
+    if (kc + 1 < nk) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = r0 + wm + 16 * i + MF::row(lane, q);
+      long long base = 0;
+      bool row_ok = true;
+      if (EPI != EPI_STORE) {
+        const int y = r % ep.py, zc = r / ep.py, z = zc % ep.pz, c = zc / ep.pz;
+        base = (((long long)c * ep.nz + z) * ep.ny + y) * ep.nx;
+        row_ok = y < ep.ny && z < ep.nz;
+      }
+      if (!row_ok) continue;
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        const int k = k0 + wn + 16 * j + (lane & 15);
+        const T p = accp[i][j][q], qq = accq[i][j][q];
+        const bool pair = k < h, centre = (k == h) && ax.odd;
+        if (!pair && !centre) continue;
+        const T v1 = pair ? p + qq : p;
+        if (EPI == EPI_STORE) {
+          C[(long long)r * P2 + k] = v1;
+          if (pair) C[(long long)r * P2 + na - 1 - k] = p - qq;
+        } else if (EPI == EPI_SUB_DENSE) {
+          ep.dense[base + k] -= (double)v1;
+          if (pair) ep.dense[base + na - 1 - k] -= (double)(p - qq);
+        } else {
+          ep.dense[base + k] = (double)v1;
+          if (pair) ep.dense[base + na - 1 - k] = (double)(p - qq);
+        }
+      }
+    }
+}
+
+// ------------------------------------------------------------------ dispatch
+
+namespace {
+
+template <typename T>
+hipError_t lfwd(const FoldOperands& f, const T* B, T* C, const FoldAxis& ax, int ncols, int batch,
+                long long bstride, int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st) {
+  const T* FeT = (const T*)f.FeT;
+  const T* FoT = (const T*)f.FoT;
+#define QN_LFWD(TM_, TN_)                                                                       \
+  if (tm == TM_ && tn == TN_) {                                                                 \
+    const unsigned g = (unsigned)((long long)batch * (2 * ax.bk / TM_) * (ncols / TN_));        \
+    if (epi == EPI_DIVIDE)                                                                      \
+      hipLaunchKernelGGL((k_fold_left_fwd<T, TM_, TN_, EPI_DIVIDE>), dim3(g), dim3(256), 0, st, \
+                         FeT, FoT, B, C, ax, ncols, batch, bstride, ep);                        \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_fold_left_fwd<T, TM_, TN_, EPI_STORE>), dim3(g), dim3(256), 0, st,  \
+                         FeT, FoT, B, C, ax, ncols, batch, bstride, ep);                        \
+    return hipGetLastError();                                                                   \
+  }
+  QN_LFWD(128, 128)
+  QN_LFWD(64, 128)
+  QN_LFWD(64, 64)
+  QN_LFWD(32, 64)
+  QN_LFWD(32, 32)
+#undef QN_LFWD
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t linv(const FoldOperands& f, const T* Y, T* C, const FoldAxis& ax, int ncols, int batch,
+                long long bstride, const EpiArgs& ep, int tm, int tn, hipStream_t st) {
+  const T* Fe = (const T*)f.Fe;
+  const T* Fo = (const T*)f.Fo;
+#define QN_LINV(TM_, TN_)                                                                       \
+  if (tm == TM_ && tn == TN_) {                                                                 \
+    const unsigned g = (unsigned)((long long)batch * (ax.bk / TM_) * (ncols / TN_));            \
+    hipLaunchKernelGGL((k_fold_left_inv<T, TM_, TN_>), dim3(g), dim3(256), 0, st, Fe, Fo, Y, C, \
+                       ax, ncols, batch, bstride, ep);                                          \
+    return hipGetLastError();                                                                   \
+  }
+  QN_LINV(64, 128)
+  QN_LINV(64, 64)
+  QN_LINV(32, 64)
+  QN_LINV(32, 32)
+#undef QN_LINV
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t rfwd(const FoldOperands& f, const T* A, T* C, const FoldAxis& ax, int rows,
+                const EpiArgs& ep, int tm, int tn, hipStream_t st) {
+  const T* FeT = (const T*)f.FeT;
+  const T* FoT = (const T*)f.FoT;
+#define QN_RFWD(TM_, TN_)                                                                        \
+  if (tm == TM_ && tn == TN_) {                                                                  \
+    const unsigned g = (unsigned)((long long)(rows / TM_) * (2 * ax.bk / TN_));                  \
+    hipLaunchKernelGGL((k_fold_right_fwd<T, TM_, TN_>), dim3(g), dim3(256), 0, st, A, FeT, FoT, \
+                       C, ax, rows, ep);                                                         \
+    return hipGetLastError();                                                                    \
+  }
+  QN_RFWD(128, 128)
+  QN_RFWD(128, 64)
+  QN_RFWD(64, 64)
+  QN_RFWD(64, 32)
+  QN_RFWD(32, 32)
+#undef QN_RFWD
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t rinv(const FoldOperands& f, const T* Y, T* C, const FoldAxis& ax, int rows, int epi,
+                const EpiArgs& ep, int tm, int tn, hipStream_t st) {
+  const T* Fe = (const T*)f.Fe;
+  const T* Fo = (const T*)f.Fo;
+#define QN_RINV(TM_, TN_)                                                                       \
+  if (tm == TM_ && tn == TN_) {                                                                 \
+    const unsigned g = (unsigned)((long long)(rows / TM_) * (ax.bk / TN_));                     \
+    if (epi == EPI_SUB_DENSE)                                                                   \
+      hipLaunchKernelGGL((k_fold_right_inv<T, TM_, TN_, EPI_SUB_DENSE>), dim3(g), dim3(256), 0, \
+                         st, Y, Fe, Fo, C, ax, rows, ep);                                       \
+    else if (epi == EPI_STORE_DENSE)                                                            \
+      hipLaunchKernelGGL((k_fold_right_inv<T, TM_, TN_, EPI_STORE_DENSE>), dim3(g), dim3(256),  \
+                         0, st, Y, Fe, Fo, C, ax, rows, ep);                                    \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_fold_right_inv<T, TM_, TN_, EPI_STORE>), dim3(g), dim3(256), 0, st, \
+                         Y, Fe, Fo, C, ax, rows, ep);                                           \
+    return hipGetLastError();                                                                   \
+  }
+  QN_RINV(128, 64)
+  QN_RINV(64, 64)
+  QN_RINV(64, 32)
+  QN_RINV(32, 32)
+#undef QN_RINV
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_fold_left_fwd(int prec, const FoldOperands& f, const void* B, void* C,
+                                const FoldAxis& ax, int ncols, int batch, long long bstride,
+                                int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st) {
+  if (prec == 0)
+    return lfwd<double>(f, (const double*)B, (double*)C, ax, ncols, batch, bstride, epi, ep, tm,
+                        tn, st);
+  return lfwd<float>(f, (const float*)B, (float*)C, ax, ncols, batch, bstride, epi, ep, tm, tn, st);
+}
+
+hipError_t launch_fold_left_inv(int prec, const FoldOperands& f, const void* Y, void* C,
+                                const FoldAxis& ax, int ncols, int batch, long long bstride,
+                                const EpiArgs& ep, int tm, int tn, hipStream_t st) {
+  if (prec == 0)
+    return linv<double>(f, (const double*)Y, (double*)C, ax, ncols, batch, bstride, ep, tm, tn, st);
+  return linv<float>(f, (const float*)Y, (float*)C, ax, ncols, batch, bstride, ep, tm, tn, st);
+}
+
+hipError_t launch_fold_right_fwd(int prec, const FoldOperands& f, const void* A, void* C,
+                                 const FoldAxis& ax, int rows, const EpiArgs& ep, int tm, int tn,
+                                 hipStream_t st) {
+  if (prec == 0) return rfwd<double>(f, (const double*)A, (double*)C, ax, rows, ep, tm, tn, st);
+  return rfwd<float>(f, (const float*)A, (float*)C, ax, rows, ep, tm, tn, st);
+}
+
+hipError_t launch_fold_right_inv(int prec, const FoldOperands& f, const void* Y, void* C,
+                                 const FoldAxis& ax, int rows, int epi, const EpiArgs& ep, int tm,
+                                 int tn, hipStream_t st) {
+  if (prec == 0)
+    return rinv<double>(f, (const double*)Y, (double*)C, ax, rows, epi, ep, tm, tn, st);
+  return rinv<float>(f, (const float*)Y, (float*)C, ax, rows, epi, ep, tm, tn, st);
+}
+
+}  // namespace qn

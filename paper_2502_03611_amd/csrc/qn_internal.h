@@ -76,6 +76,32 @@ hipError_t launch_gemm_left(int prec, const GemmOperands& s, const void* B, void
 hipError_t launch_gemm_right(int prec, const GemmOperands& s, const void* A, void* C, int rows,
                              int K, int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st);
 
+// Reflection-folded mode products (qn_gemm_fold.hip).  Along a folded axis of
+// n interior points, h = n / 2, odd = n % 2, and the spectral index is stored
+// split: even modes in [0, bk), odd modes in [bk, 2 bk); the padded extent is
+// 2 bk.
+struct FoldAxis {
+  int n, h, odd, bk;
+};
+struct FoldOperands {
+  const void* FeT;  // [k][i] = S[k][2i]    (bk x bk, forward)
+  const void* FoT;  // [k][i] = S[k][2i+1]
+  const void* Fe;   // [i][k] = S[k][2i]    (inverse)
+  const void* Fo;   // [i][k] = S[k][2i+1]
+};
+hipError_t launch_fold_left_fwd(int prec, const FoldOperands& f, const void* B, void* C,
+                                const FoldAxis& ax, int ncols, int batch, long long bstride,
+                                int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st);
+hipError_t launch_fold_left_inv(int prec, const FoldOperands& f, const void* Y, void* C,
+                                const FoldAxis& ax, int ncols, int batch, long long bstride,
+                                const EpiArgs& ep, int tm, int tn, hipStream_t st);
+hipError_t launch_fold_right_fwd(int prec, const FoldOperands& f, const void* A, void* C,
+                                 const FoldAxis& ax, int rows, const EpiArgs& ep, int tm, int tn,
+                                 hipStream_t st);
+hipError_t launch_fold_right_inv(int prec, const FoldOperands& f, const void* Y, void* C,
+                                 const FoldAxis& ax, int rows, int epi, const EpiArgs& ep, int tm,
+                                 int tn, hipStream_t st);
+
 // Residual of the nonlinear problem, written (with zero padding) into the
 // transform workspace or into a dense caller array.  out_prec: 0 fp64, 1 fp32.
 struct ResidualArgs {

@@ -1,0 +1,39 @@
+// Matrix-core traits shared by the mode-product kernels: the 16x16x4 MFMA of
+// each element type and the row of the 16x16 output block that accumulator
+// element q of a lane holds (the column is lane % 16).  The FP64 and FP32
+// instructions differ in that output layout (both checked on the device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace qn {
+
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static constexpr int TK = 16;
+  __device__ static inline v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int q) { return (lane >> 4) + 4 * q; }
+};
+
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static constexpr int TK = 32;
+  __device__ static inline v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int q) { return 4 * (lane >> 4) + q; }
+};
+
+// Tile index for workgroup w: each XCD (w % 8) gets a contiguous tile range.
+__device__ inline int xcd_tile(int w, int total) {
+  return (total % 8 == 0) ? (w % 8) * (total / 8) + (w / 8) : w;
+}
+
+}  // namespace qn

@@ -10,8 +10,9 @@
 //
 // The residual kernel marches along z: each thread owns one (x, y) column of
 // a z-slab and keeps U(z-1), U(z), U(z+1) in registers, so each U value is
-// fetched from memory once for its z-neighbours; x/y neighbours come from the
-// caches.  2D grids are the nz = 1 case with 1/h_z^2 = 0.  Output points
+// fetched once for its z-neighbours; the block's current plane (64 x 16 with
+// a one-point halo) is staged in LDS for the x/y neighbours, so U is re-read
+// only along the halo.  2D grids are the nz = 1 case with 1/h_z^2 = 0.  Output points
 // outside the interior (padding of the transform workspace) are written as
 // zero on every call, so padding never carries stale values.
 
@@ -73,8 +74,12 @@ __device__ inline void put(void* base, long long idx, double v) {
 
 template <int NL, typename TO>
 __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
-  const int x = blockIdx.x * RX + threadIdx.x;
-  const int y = blockIdx.y * RY + threadIdx.y;
+  constexpr int NC = (NL == NL_SYS2) ? 2 : 1;
+  // Current z-plane of the block's 64 x 16 tile plus a one-point x/y halo.
+  __shared__ double s_u[NC][RY + 2][RX + 2];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int x = blockIdx.x * RX + tx;
+  const int y = blockIdx.y * RY + ty;
   const int z0 = blockIdx.z * a.rz;
   const int z1 = min(z0 + a.rz, a.oz);
   if (a.skip && a.skip[z0]) return;  // batched solver: finished instance (rz = 1)
@@ -83,54 +88,67 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
   const long long comp = plane * nz;
   const bool in_xy = (x < nx) && (y < ny);
   const bool out_xy = (x < a.ox) && (y < a.oy);
-  constexpr int NC = (NL == NL_SYS2) ? 2 : 1;
+  // 2D problems (and the batched solver, whose z-planes are independent
+  // instances) have no z coupling: never read a neighbouring plane.
+  const bool zc = a.ihz2 != 0.0;
+  // Halo duty of this thread: one x-neighbour column or one y-neighbour row.
+  int hx = -1, hy = -1, lx = 0, ly = 0;
+  if (tx == 0) { hx = x - 1; hy = y; lx = 0; ly = ty + 1; }
+  else if (tx == RX - 1) { hx = x + 1; hy = y; lx = RX + 1; ly = ty + 1; }
+  int vx = -1, vy = -1, mx_ = 0, my_ = 0;
+  if (ty == 0) { vx = x; vy = y - 1; mx_ = tx + 1; my_ = 0; }
+  else if (ty == RY - 1) { vx = x; vy = y + 1; mx_ = tx + 1; my_ = RY + 1; }
+  const bool has_h = tx == 0 || tx == RX - 1, has_v = ty == 0 || ty == RY - 1;
+  const bool h_ok = hx >= 0 && hx < nx && hy < ny;
+  const bool v_ok = vy >= 0 && vy < ny && vx < nx;
 
   double s_r = 0.0, s_f = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
   double um[NC], uc[NC];
   const long long col = (long long)y * nx + x;
-  // 2D problems (and the batched solver, whose z-planes are independent
-  // instances) have no z coupling: never read a neighbouring plane.
-  const bool zc = a.ihz2 != 0.0;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     um[c] = (zc && in_xy && z0 > 0 && z0 - 1 < nz) ? a.U[c * comp + (long long)(z0 - 1) * plane + col] : 0.0;
     uc[c] = (in_xy && z0 < nz) ? a.U[c * comp + (long long)z0 * plane + col] : 0.0;
   }
   for (int z = z0; z < z1; ++z) {
-    double up[NC];
+    const bool zin = z < nz;
+    double up[NC], f[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-      up[c] = (zc && in_xy && z + 1 < nz) ? a.U[c * comp + (long long)(z + 1) * plane + col] : 0.0;
-    if (in_xy && z < nz) {
-      const long long p = (long long)z * plane + col;
+    for (int c = 0; c < NC; ++c) {
+      up[c] = (in_xy && z + 1 < nz && (zc || z + 1 < z1)) ? a.U[c * comp + (long long)(z + 1) * plane + col] : 0.0;
+      f[c] = (in_xy && zin) ? a.F[c * comp + (long long)z * plane + col] : 0.0;
+      s_u[c][ty + 1][tx + 1] = uc[c];
+      // Halo cells are always written: zero outside the interior (Dirichlet data).
+      if (has_h) s_u[c][ly][lx] = (h_ok && zin) ? a.U[c * comp + (long long)z * plane + (long long)hy * nx + hx] : 0.0;
+      if (has_v) s_u[c][my_][mx_] = (v_ok && zin) ? a.U[c * comp + (long long)z * plane + (long long)vy * nx + vx] : 0.0;
+    }
+    __syncthreads();
+    if (in_xy && zin) {
       double r[NC];
       if (NL == NL_QUASILIN) {
-        const double* U = a.U;
         const double u = uc[0];
         const double ac = 1.0 + u * u;
-        const double n_xm = x > 0 ? U[p - 1] : 0.0, n_xp = x + 1 < nx ? U[p + 1] : 0.0;
-        const double n_ym = y > 0 ? U[p - nx] : 0.0, n_yp = y + 1 < ny ? U[p + nx] : 0.0;
-        const double n_zm = um[0], n_zp = up[0];
+        const double n_xm = s_u[0][ty + 1][tx], n_xp = s_u[0][ty + 1][tx + 2];
+        const double n_ym = s_u[0][ty][tx + 1], n_yp = s_u[0][ty + 2][tx + 1];
+        const double n_zm = zc ? um[0] : 0.0, n_zp = zc ? up[0] : 0.0;
         auto flux = [&](double un) { return 0.5 * (ac + (1.0 + un * un)) * (u - un); };
-        const double lx = (flux(n_xm) + flux(n_xp)) * a.ihx2;
-        const double ly = (flux(n_ym) + flux(n_yp)) * a.ihy2;
-        const double lz = (flux(n_zm) + flux(n_zp)) * a.ihz2;
-        const double f = a.F[p];
-        r[0] = lx + ly + lz - f;
-        s_f += f * f;
+        const double lx_ = (flux(n_xm) + flux(n_xp)) * a.ihx2;
+        const double ly_ = (flux(n_ym) + flux(n_yp)) * a.ihy2;
+        const double lz_ = (flux(n_zm) + flux(n_zp)) * a.ihz2;
+        r[0] = lx_ + ly_ + lz_ - f[0];
+        s_f += f[0] * f[0];
         mn = fmin(mn, ac);
         mx = fmax(mx, ac);
       } else {
-        double lap[NC], f[NC];
+        double lap[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          const double* U = a.U + c * comp;
           const double u = uc[c];
-          const double n_xm = x > 0 ? U[p - 1] : 0.0, n_xp = x + 1 < nx ? U[p + 1] : 0.0;
-          const double n_ym = y > 0 ? U[p - nx] : 0.0, n_yp = y + 1 < ny ? U[p + nx] : 0.0;
+          const double n_xm = s_u[c][ty + 1][tx], n_xp = s_u[c][ty + 1][tx + 2];
+          const double n_ym = s_u[c][ty][tx + 1], n_yp = s_u[c][ty + 2][tx + 1];
+          const double n_zm = zc ? um[c] : 0.0, n_zp = zc ? up[c] : 0.0;
           lap[c] = (2.0 * u - n_xm - n_xp) * a.ihx2 + (2.0 * u - n_ym - n_yp) * a.ihy2 +
-                   (2.0 * u - um[c] - up[c]) * a.ihz2;
-          f[c] = a.F[c * comp + p];
+                   (2.0 * u - n_zm - n_zp) * a.ihz2;
           s_f += f[c] * f[c];
         }
         if (NL == NL_CUBIC) {
@@ -163,11 +181,11 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
         put<TO>(a.R, o, 0.0);
       }
     }
+    __syncthreads();  // the plane in LDS is overwritten next step
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       um[c] = uc[c];
-      uc[c] = zc ? up[c]
-                 : ((in_xy && z + 1 < nz) ? a.U[c * comp + (long long)(z + 1) * plane + col] : 0.0);
+      uc[c] = up[c];
     }
   }
 

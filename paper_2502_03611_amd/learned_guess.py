@@ -10,6 +10,7 @@ solver-generated training data, the mini-batch loop and the evaluation.
 
 import ctypes
 import math
+import os
 import time
 
 import numpy as np
@@ -227,3 +228,97 @@ def evaluate(net, seeds, n=255, rtol=1e-10):
                      "relres0_net": st1["relres0"], "rel_diff": diff,
                      "status": (st0["status"], st1["status"])})
     return rows
+
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "qnn_cubic_255.npy")
+
+
+def compare(net, seeds, n=255, rtol=1e-10):
+    """Per seed: iterations and time to rtol for FP64 / FP32 transforms, each
+    from U_0 = 0 and from the learned guess (network, both solves and the
+    fallback test timed with it)."""
+    solvers = {p: Solver((n, n), "cubic", beta_mode="midpoint", precision=p)
+               for p in ("fp64", "fp32")}
+    rows = []
+    for s in seeds:
+        f = torch.from_numpy(synth.learned_guess_rhs(s, n)).cuda().view(1, n, n)
+        row = {"seed": s}
+        ref = None
+        for p, sol in solvers.items():
+            for mode in ("zero", "net"):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if mode == "zero":
+                    u = torch.zeros_like(f)
+                    used = False
+                else:
+                    u, used = initial_guess(net, sol, f)
+                st = sol.iterate(u, f, rtol=rtol, max_iter=200)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                if ref is None:
+                    ref = u.clone()
+                row[f"{p}_{mode}"] = {"iters": st["iters"], "t": dt, "status": st["status"],
+                                      "used_net": used,
+                                      "rel_diff": float((u - ref).norm() / ref.norm())}
+        rows.append(row)
+    return rows
+
+
+def main(argv=None):
+    import argparse
+    import json
+    import sys
+
+    ap = argparse.ArgumentParser(description="train and evaluate the learned initial guess")
+    ap.add_argument("--n", type=int, default=255)
+    ap.add_argument("--train", type=int, default=4000)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--eval", type=int, default=500)
+    ap.add_argument("--save", default=WEIGHTS)
+    args = ap.parse_args(argv)
+
+    def log(m):
+        print(f"[learned-guess] {m}", file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    F, V, G, _ = generate_pairs(range(args.train), n=args.n)
+    t_data = time.perf_counter() - t0
+    log(f"{args.train} solver pairs at {args.n}^2 in {t_data:.1f} s")
+    net = Net(args.n, args.n, max_batch=args.batch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = train(net, F, V, G, epochs=args.epochs, batch=args.batch, lr=args.lr, seed=0, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del F, V, G
+    theta = net.get_params()
+    if args.save:
+        os.makedirs(os.path.dirname(args.save), exist_ok=True)
+        np.save(args.save, theta, allow_pickle=False)
+    log(f"trained {args.epochs} epochs in {t_train:.1f} s; evaluating {args.eval} held-out seeds")
+    rows = compare(net, range(10000, 10000 + args.eval), n=args.n)
+
+    def agg(key):
+        it = np.array([r[key]["iters"] for r in rows], dtype=np.float64)
+        t = np.array([r[key]["t"] for r in rows])
+        return {"mean_iters": round(float(it.mean()), 3), "median_iters": float(np.median(it)),
+                "max_iters": int(it.max()), "mean_time_ms": round(1e3 * float(t.mean()), 3),
+                "used_net_frac": round(float(np.mean([r[key]["used_net"] for r in rows])), 3),
+                "all_converged": bool(all(r[key]["status"] == 0 for r in rows)),
+                "max_rel_diff_vs_fp64_zero": float(max(r[key]["rel_diff"] for r in rows))}
+
+    out = {"n": args.n, "train_pairs": args.train, "epochs": args.epochs, "batch": args.batch,
+           "lr": args.lr, "params": int(theta.size), "data_s": round(t_data, 2),
+           "train_s": round(t_train, 2), "steps": args.epochs * (args.train // args.batch),
+           "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1], "held_out": args.eval,
+           "fp64_zero": agg("fp64_zero"), "fp64_net": agg("fp64_net"),
+           "fp32_zero": agg("fp32_zero"), "fp32_net": agg("fp32_net")}
+    print(json.dumps(out))
+    return out
+
+
+if __name__ == "__main__":
+    main()
