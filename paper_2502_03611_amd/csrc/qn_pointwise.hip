@@ -103,24 +103,38 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
   const bool v_ok = vy >= 0 && vy < ny && vx < nx;
 
   double s_r = 0.0, s_f = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
-  double um[NC], uc[NC];
   const long long col = (long long)y * nx + x;
+  const long long hoff = (long long)hy * nx + hx, voff = (long long)vy * nx + vx;
+  // Register pipeline one plane deep: while plane z is computed, the loads of
+  // plane z+1 (its U values, F, halo cells and U(z+2)) are already in flight.
+  double um[NC], uc[NC], up[NC], f[NC], hc[NC], vc[NC];
+  double n_up[NC], n_f[NC], n_hc[NC], n_vc[NC];
+  auto load_plane = [&](int z, double* u_next, double* fz, double* hz, double* vz) {
+    const bool zin = z < nz;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double* Uc = a.U + c * comp + (long long)z * plane;
+      u_next[c] = (in_xy && z + 1 < nz && (zc || z + 1 < z1)) ? Uc[plane + col] : 0.0;
+      fz[c] = (in_xy && zin) ? a.F[c * comp + (long long)z * plane + col] : 0.0;
+      hz[c] = (has_h && h_ok && zin) ? Uc[hoff] : 0.0;
+      vz[c] = (has_v && v_ok && zin) ? Uc[voff] : 0.0;
+    }
+  };
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     um[c] = (zc && in_xy && z0 > 0 && z0 - 1 < nz) ? a.U[c * comp + (long long)(z0 - 1) * plane + col] : 0.0;
     uc[c] = (in_xy && z0 < nz) ? a.U[c * comp + (long long)z0 * plane + col] : 0.0;
   }
+  if (z0 < z1) load_plane(z0, up, f, hc, vc);
   for (int z = z0; z < z1; ++z) {
     const bool zin = z < nz;
-    double up[NC], f[NC];
+    if (z + 1 < z1) load_plane(z + 1, n_up, n_f, n_hc, n_vc);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      up[c] = (in_xy && z + 1 < nz && (zc || z + 1 < z1)) ? a.U[c * comp + (long long)(z + 1) * plane + col] : 0.0;
-      f[c] = (in_xy && zin) ? a.F[c * comp + (long long)z * plane + col] : 0.0;
       s_u[c][ty + 1][tx + 1] = uc[c];
       // Halo cells are always written: zero outside the interior (Dirichlet data).
-      if (has_h) s_u[c][ly][lx] = (h_ok && zin) ? a.U[c * comp + (long long)z * plane + (long long)hy * nx + hx] : 0.0;
-      if (has_v) s_u[c][my_][mx_] = (v_ok && zin) ? a.U[c * comp + (long long)z * plane + (long long)vy * nx + vx] : 0.0;
+      if (has_h) s_u[c][ly][lx] = hc[c];
+      if (has_v) s_u[c][my_][mx_] = vc[c];
     }
     __syncthreads();
     if (in_xy && zin) {
@@ -186,6 +200,10 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
     for (int c = 0; c < NC; ++c) {
       um[c] = uc[c];
       uc[c] = up[c];
+      up[c] = n_up[c];
+      f[c] = n_f[c];
+      hc[c] = n_hc[c];
+      vc[c] = n_vc[c];
     }
   }
 
