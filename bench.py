@@ -39,18 +39,31 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE
-# (read counter scaled x2.0, write x1.0, calibrated on a plain 1 GiB copy), valid
-# only for the GEMM source they were taken on.
-TRAFFIC = {"source": "paper_2502_03611_amd/csrc/qn_gemm_fold.hip", "sha256_prefix": "72739fac18112880",
-           "bytes_per_launch": 1.560e9 + 1.074e9}
+# HBM bytes per launch (read, write) from rocprofv3 FETCH_SIZE / WRITE_SIZE at
+# 511^3, the read counter scaled x2.0 and the write counter x1.0 (both
+# calibrated on a plain 1 GiB device copy), keyed by kernel.  Each figure is
+# valid only while the source file it was taken on is unchanged.
+TRAFFIC_SOURCES = {"fold": ("paper_2502_03611_amd/csrc/qn_gemm_fold.hip", "7f993e27e3f378ce"),
+                   "pointwise": ("paper_2502_03611_amd/csrc/qn_pointwise.hip", "f181cfd2d42a4691")}
+TRAFFIC = {"gemm_x": ("fold", 1.2801e9, 1.0737e9),
+           "gemm_yz": ("fold", 1.2168e9, 1.0737e9),
+           "gemm_divide": ("fold", 1.2559e9, 1.0737e9),
+           "gemm_yz_inv": ("fold", 1.3141e9, 1.0716e9),
+           "gemm_x_update": ("fold", 2.3007e9, 1.0687e9),
+           "residual": ("pointwise", 2.7883e9, 1.0739e9)}
 
 
-def traffic_if_current():
+def traffic_if_current(kernel, n):
+    """Measured HBM bytes per launch of `kernel` at 511^3, or None when the
+    workload differs or its source changed since the counters were taken."""
     import hashlib
-    with open(os.path.join(ROOT, TRAFFIC["source"]), "rb") as fh:
+    if n != 511 or kernel not in TRAFFIC:
+        return None
+    src, rd, wr = TRAFFIC[kernel]
+    path, sha_ref = TRAFFIC_SOURCES[src]
+    with open(os.path.join(ROOT, path), "rb") as fh:
         sha = hashlib.sha256(fh.read()).hexdigest()[:16]
-    return TRAFFIC["bytes_per_launch"] if sha == TRAFFIC["sha256_prefix"] else None
+    return rd + wr if sha == sha_ref else None
 
 
 def log(msg):
@@ -213,7 +226,7 @@ def main():
     achieved = flops_per_product / (avg_ms * 1e-3) / 1e12
     roof = {"bound": "mfma", "kernel": names[dom], "achieved": round(achieved, 3),
             "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic_if_current(),
+            "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic_if_current(dom, n),
             "avg_launch_ms": round(avg_ms, 4), "launches": launches,
             "algorithmic_flops_per_launch": flops_per_product,
             "dense_equivalent_tflops": round(dense_flops / (avg_ms * 1e-3) / 1e12, 3)}
@@ -237,6 +250,7 @@ def main():
         "residual_roofline": {"bound": "hbm", "achieved": round(r_bytes / (r_avg * 1e-3) / 1e9, 1),
                               "peak": PEAK_HBM_GBS, "unit": "GB/s",
                               "frac": round(r_bytes / (r_avg * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                              "traffic": traffic_if_current("residual", n),
                               "avg_launch_ms": round(r_avg, 4),
                               "algorithmic_bytes_per_launch": r_bytes},
         "all_mode_products_tflops": round(flops_per_product * all_gemm_launches /
