@@ -45,17 +45,18 @@ PEAK_HBM_GBS = 8000.0
 # valid only while the source file it was taken on is unchanged.
 TRAFFIC_SOURCES = {"fold": ("paper_2502_03611_amd/csrc/qn_gemm_fold.hip", "7f993e27e3f378ce"),
                    "pointwise": ("paper_2502_03611_amd/csrc/qn_pointwise.hip", "f181cfd2d42a4691")}
-TRAFFIC = {"gemm_x": ("fold", 1.2801e9, 1.0737e9),
-           "gemm_yz": ("fold", 1.2168e9, 1.0737e9),
-           "gemm_divide": ("fold", 1.2559e9, 1.0737e9),
-           "gemm_yz_inv": ("fold", 1.3141e9, 1.0716e9),
-           "gemm_x_update": ("fold", 2.3007e9, 1.0687e9),
-           "residual": ("pointwise", 2.7883e9, 1.0739e9)}
+TRAFFIC = {"k_fold_right_fwd<double,128,128>": ("fold", 1.2801e9, 1.0737e9),
+           "k_fold_left_fwd<double,128,128,EPI_STORE>": ("fold", 1.2168e9, 1.0737e9),
+           "k_fold_left_fwd<double,128,128,EPI_DIVIDE>": ("fold", 1.2559e9, 1.0737e9),
+           "k_fold_left_inv<double,64,128>": ("fold", 1.3141e9, 1.0716e9),
+           "k_fold_right_inv<double,128,64,EPI_SUB_DENSE>": ("fold", 2.3007e9, 1.0687e9),
+           "k_residual<QUASILIN,double>": ("pointwise", 2.7883e9, 1.0739e9)}
 
 
 def traffic_if_current(kernel, n):
-    """Measured HBM bytes per launch of `kernel` at 511^3, or None when the
-    workload differs or its source changed since the counters were taken."""
+    """Measured HBM bytes per launch of `kernel` (name with its tile) at 511^3,
+    or None when the workload or tile differs or its source changed since the
+    counters were taken."""
     import hashlib
     if n != 511 or kernel not in TRAFFIC:
         return None
@@ -195,6 +196,11 @@ def main():
     log("timed FP64 steps")
     solver = Solver(shape, "quasilinear", beta=0.0, precision="fp64", timing=True)
     U = torch.zeros((1,) + shape, dtype=torch.float64, device="cuda")
+    log("autotune mode-product tiles")
+    t0 = time.perf_counter()
+    solver.autotune()
+    t_tune = time.perf_counter() - t0
+    tiles = solver.tiles()
     if args.warmup > 0:
         solver.iterate(U, F, rtol=0.0, max_iter=args.warmup)
     torch.cuda.synchronize()
@@ -215,18 +221,22 @@ def main():
     ne, no = (n + 1) // 2, n // 2
     flops_per_product = 2.0 * float(n) ** 2 * (ne * ne + no * no)
     dense_flops = 2.0 * float(n) ** 4
-    names = {"gemm_x": "k_fold_right_fwd<double,128,128>",
-             "gemm_yz": "k_fold_left_fwd<double,128,128,EPI_STORE>",
-             "gemm_divide": "k_fold_left_fwd<double,128,128,EPI_DIVIDE>",
-             "gemm_yz_inv": "k_fold_left_inv<double,64,128>",
-             "gemm_x_update": "k_fold_right_inv<double,128,64,EPI_SUB_DENSE>"}
+    # kernel names per timing key from the tiles in use (launch order: x, y
+    # forward, z forward + divide, z and y inverse, x inverse + update)
+    kn = ["k_fold_right_fwd<double,{},{}>", "k_fold_left_fwd<double,{},{},EPI_STORE>",
+          "k_fold_left_fwd<double,{},{},EPI_DIVIDE>", "k_fold_left_inv<double,{},{}>",
+          "k_fold_left_inv<double,{},{}>", "k_fold_right_inv<double,{},{},EPI_SUB_DENSE>"]
+    kname = [f.format(t[2], t[3]) for f, t in zip(kn, tiles)]
+    names = {"gemm_x": kname[0], "gemm_yz": kname[1], "gemm_divide": kname[2],
+             "gemm_yz_inv": kname[3] if kname[3] == kname[4] else kname[3] + " / " + kname[4],
+             "gemm_x_update": kname[5]}
     dom = max(names, key=lambda k: tim[k][1])
     launches, tot_ms = tim[dom]
     avg_ms = tot_ms / max(launches, 1)
     achieved = flops_per_product / (avg_ms * 1e-3) / 1e12
     roof = {"bound": "mfma", "kernel": names[dom], "achieved": round(achieved, 3),
             "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic_if_current(dom, n),
+            "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic_if_current(names[dom], n),
             "avg_launch_ms": round(avg_ms, 4), "launches": launches,
             "algorithmic_flops_per_launch": flops_per_product,
             "dense_equivalent_tflops": round(dense_flops / (avg_ms * 1e-3) / 1e12, 3)}
@@ -250,7 +260,7 @@ def main():
         "residual_roofline": {"bound": "hbm", "achieved": round(r_bytes / (r_avg * 1e-3) / 1e9, 1),
                               "peak": PEAK_HBM_GBS, "unit": "GB/s",
                               "frac": round(r_bytes / (r_avg * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
-                              "traffic": traffic_if_current("residual", n),
+                              "traffic": traffic_if_current("k_residual<QUASILIN,double>", n),
                               "avg_launch_ms": round(r_avg, 4),
                               "algorithmic_bytes_per_launch": r_bytes},
         "all_mode_products_tflops": round(flops_per_product * all_gemm_launches /
@@ -258,6 +268,8 @@ def main():
         "all_mode_products_dense_equivalent_tflops": round(dense_flops * all_gemm_launches /
                                                            (all_gemm_ms * 1e-3) / 1e12, 3),
         "kernels": kernels,
+        "tiles": {"launches": ["x fwd", "y fwd", "z fwd+divide", "z inv", "y inv", "x inv+update"],
+                  "tile_mn": [[t[2], t[3]] for t in tiles], "autotune_s": round(t_tune, 3)},
     }
 
     if not args.no_time_to_tol:
@@ -267,6 +279,7 @@ def main():
         for prec in ("fp64", "fp32", "bf16x3"):
             log(f"time to tolerance: {prec}")
             s = Solver(shape, "quasilinear", beta=0.0, precision=prec)
+            s.autotune()
             U.zero_()
             s.iterate(U, F, rtol=0.0, max_iter=1)  # untimed warm-up of this context
             U.zero_()

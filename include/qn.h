@@ -166,6 +166,23 @@ qn_status qn_fdm_solve(qn_ctx ctx, const double* d_R, double scale, double shift
 qn_status qn_iterate(qn_ctx ctx, double* d_U, const double* d_F, double rtol,
                      int32_t max_iter, qn_stats* stats);
 
+/* Tile selection for the mode products (Section 4.1, eq. fin_inverse, as
+ * reflection-folded matrix-core products).  The solve is a fixed list of
+ * launches (3D: 6, 2D: 4; the x forward product first, the x inverse product
+ * with the update last).  By default each launch takes the largest tile
+ * shape that divides its extents and gives at least 512 workgroups (else the
+ * shape with the most workgroups).  qn_autotune times every admissible shape
+ * of every launch on the bound workspace (its transform tensors are
+ * overwritten; the x inverse is timed with a plain store) and keeps the
+ * fastest for all later calls.  Results do not depend on the tile shapes
+ * (bitwise).  Synchronous.  A no-op for QN_PREC_BF16X3, whose dense
+ * transforms use a fixed rule. */
+qn_status qn_autotune(qn_ctx ctx);
+/* Launch i of the solve: info4 = {kind (0 x forward, 1 y/z forward, 2 y/z
+ * inverse, 3 x inverse), axis (0 x, 1 y, 2 z), tile_m, tile_n}.  Requires a
+ * bound workspace; QN_ERR_UNSUPPORTED for QN_PREC_BF16X3. */
+qn_status qn_tile_info(qn_ctx ctx, int32_t i, int32_t* info4);
+
 /* Kernel timing (contexts created with options.timing != 0).  qn_timing_read
  * synchronises the stream, folds all recorded launches into the table, and
  * writes entry i: its kernel name (static string), launch count and total

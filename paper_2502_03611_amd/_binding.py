@@ -71,13 +71,15 @@ def lib():
     L.qn_timing_read.argtypes = [c_vp, c_i32, ctypes.POINTER(ctypes.c_char_p),
                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(c_dbl)]
     L.qn_timing_reset.argtypes = [c_vp]
+    L.qn_autotune.argtypes = [c_vp]
+    L.qn_tile_info.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i32)]
     L.qn_destroy.argtypes = [c_vp]
     L.qn_destroy.restype = None
     L.qn_last_error.argtypes = []
     L.qn_last_error.restype = ctypes.c_char_p
     for name in ("qn_setup", "qn_workspace_bytes", "qn_bind_workspace", "qn_set_stream",
                  "qn_residual", "qn_fdm_solve", "qn_iterate", "qn_timing_count",
-                 "qn_timing_read", "qn_timing_reset"):
+                 "qn_timing_read", "qn_timing_reset", "qn_autotune", "qn_tile_info"):
         getattr(L, name).restype = c_i32
     _lib = L
     return L
@@ -196,6 +198,21 @@ class Solver:
             out[name.value.decode()] = (n.value, ms.value)
         if reset:
             check(L.qn_timing_reset(self._ctx))
+        return out
+
+    def autotune(self):
+        """Time every admissible tile of each mode-product launch and keep the
+        fastest (overwrites the transform workspace; synchronous)."""
+        self._sync_stream()
+        check(lib().qn_autotune(self._ctx))
+
+    def tiles(self):
+        """[(kind, axis, tile_m, tile_n)] of the solve's mode-product launches."""
+        out = []
+        info = (c_i32 * 4)()
+        for i in range(6 if self.dim == 3 else 4):
+            check(lib().qn_tile_info(self._ctx, i, info))
+            out.append(tuple(int(v) for v in info))
         return out
 
     def close(self):

@@ -92,6 +92,8 @@ struct qn_ctx_s {
   hipStream_t stream = nullptr;
   bool fold = true;       // reflection-folded transforms (FP64/FP32); dense for bf16x3
   FoldAxis ax[3] = {};
+  int tile[6][2] = {};    // per mode-product launch of the folded solve (after qn_autotune)
+  bool tuned = false;
   std::vector<double> hS[3], hlam[3];  // dense S or folded FeT|FoT|Fe|Fo; lam (split if folded)
   // workspace layout (byte offsets)
   size_t off_S[3] = {0, 0, 0}, off_Slo[3] = {0, 0, 0}, off_lam[3] = {0, 0, 0};
@@ -188,21 +190,62 @@ FoldOperands fold_ops(qn_ctx c, int axis) {
   return f;
 }
 
-// Largest admissible tile (tm, tn) among the instantiated shapes of a fold kernel.
-void pick2(const int (*cand)[2], int ncand, long long mext, long long next, int& tm, int& tn) {
-  for (int i = 0; i < ncand; ++i)
-    if (mext % cand[i][0] == 0 && next % cand[i][1] == 0) {
+// Tile (tm, tn) for a fold kernel: the largest instantiated shape that divides
+// the extents (mext: the folded half extent bk or the row count; next: the
+// column extent) and still gives at least two workgroups per CU, counting
+// `batch` launches of the tile grid (forward kernels pass twice the slab
+// count: even and odd halves); when none does (small 2D grids), the admissible
+// shape with the most workgroups.
+void pick2(const int (*cand)[2], int ncand, long long mext, long long next, long long batch,
+           int& tm, int& tn) {
+  const long long want = 2LL * 256;
+  tm = tn = 32;
+  long long best = -1;
+  for (int i = 0; i < ncand; ++i) {
+    if (mext % cand[i][0] || next % cand[i][1]) continue;
+    const long long blocks = batch * (mext / cand[i][0]) * (next / cand[i][1]);
+    if (blocks >= want) {
       tm = cand[i][0];
       tn = cand[i][1];
       return;
     }
-  tm = tn = 32;
+    if (blocks > best) {
+      best = blocks;
+      tm = cand[i][0];
+      tn = cand[i][1];
+    }
+  }
 }
+// Instantiated tile shapes per fold kernel, in order of preference (measured
+// on the 511^3 FP64 workload: the inverse kernels run fastest with 64 x 64).
 const int kLfwd[5][2] = {{128, 128}, {64, 128}, {64, 64}, {32, 64}, {32, 32}};
-const int kLinv[4][2] = {{64, 128}, {64, 64}, {32, 64}, {32, 32}};
+const int kLinv[4][2] = {{64, 64}, {64, 128}, {32, 64}, {32, 32}};
 const int kRfwd[5][2] = {{128, 128}, {128, 64}, {64, 64}, {64, 32}, {32, 32}};
-const int kRinv[4][2] = {{128, 64}, {64, 64}, {64, 32}, {32, 32}};
+const int kRinv[4][2] = {{64, 64}, {128, 64}, {64, 32}, {32, 32}};
 
+enum FoldKind { FK_RFWD, FK_LFWD, FK_LINV, FK_RINV };
+
+// One mode-product launch of the folded solve.
+struct FoldStep {
+  int kind, axis, kid;
+  const void* in;
+  void* out;
+  int ncols, batch;     // form L: columns of a slab, slab count
+  long long bstride;    // form L: slab stride
+  int rows;             // form R: row count
+  int epi;
+  EpiArgs ep;
+  long long mext, next, nblk;  // tile admissibility (tm | mext, tn | next) and block factor
+};
+
+void candidates(int kind, const int (**list)[2], int* count) {
+  switch (kind) {
+    case FK_RFWD: *list = kRfwd; *count = 5; break;
+    case FK_LFWD: *list = kLfwd; *count = 5; break;
+    case FK_LINV: *list = kLinv; *count = 4; break;
+    default: *list = kRinv; *count = 4; break;
+  }
+}
 GemmOperands operands(qn_ctx c, int axis) {
   GemmOperands g{};
   if (c->prec == QN_PREC_BF16X3) {
@@ -247,86 +290,126 @@ hipError_t residual_into_ws(qn_ctx c, const double* U, const double* F, double* 
   });
 }
 
+// The folded solve as a list of launches (3D: x, y forward; z forward with
+// the divide; z, y inverse; x inverse with the dense epilogue.  2D: x
+// forward; y forward with the divide; y inverse; x inverse).  The transform
+// ping-pongs between W1 and W2; `ep` carries coefficients and the dense
+// target.  Returns the number of launches.
+int fold_plan(qn_ctx c, const EpiArgs& ep, int epi_last, FoldStep* st) {
+  void* W1 = c->ws + c->off_W1;
+  void* W2 = c->ws + c->off_W2;
+  const int px = c->p[0], py = c->p[1], pz = c->p[2];
+  const int rows = c->ncomp * pz * py;
+  const long long yslab = (long long)py * px, zslab = (long long)pz * py * px;
+  int ns = 0;
+  auto add = [&](int kind, int axis, int kid, const void* in, void* out, int ncols, int batch,
+                 long long bstride, int epi, const EpiArgs& e) {
+    FoldStep f{};
+    f.kind = kind;
+    f.axis = axis;
+    f.kid = kid;
+    f.in = in;
+    f.out = out;
+    f.ncols = ncols;
+    f.batch = batch;
+    f.bstride = bstride;
+    f.rows = rows;
+    f.epi = epi;
+    f.ep = e;
+    const long long bk = c->ax[axis].bk;
+    if (kind == FK_RFWD || kind == FK_RINV) {
+      f.mext = rows;
+      f.next = bk;
+      f.nblk = kind == FK_RFWD ? 2 : 1;  // forward: even and odd column halves
+    } else {
+      f.mext = bk;
+      f.next = ncols;
+      f.nblk = (kind == FK_LFWD ? 2LL : 1LL) * batch;
+    }
+    st[ns++] = f;
+  };
+  add(FK_RFWD, 0, K_GEMM_X, W1, W2, 0, 0, 0, EPI_STORE, ep);
+  if (c->dim == 2) {
+    EpiArgs ed = ep;
+    ed.lamM = c->at<double>(c->off_lam[1]);
+    ed.lamY = nullptr;
+    add(FK_LFWD, 1, K_GEMM_DIVIDE, W2, W1, px, c->ncomp, yslab, EPI_DIVIDE, ed);
+    add(FK_LINV, 1, K_GEMM_YZ_INV, W1, W2, px, c->ncomp, yslab, EPI_STORE, ep);
+  } else {
+    add(FK_LFWD, 1, K_GEMM_YZ, W2, W1, px, c->ncomp * pz, yslab, EPI_STORE, ep);
+    EpiArgs ed = ep;
+    ed.lamM = c->at<double>(c->off_lam[2]);
+    ed.lamY = c->at<double>(c->off_lam[1]);
+    add(FK_LFWD, 2, K_GEMM_DIVIDE, W1, W2, (int)yslab, c->ncomp, zslab, EPI_DIVIDE, ed);
+    add(FK_LINV, 2, K_GEMM_YZ_INV, W2, W1, (int)yslab, c->ncomp, zslab, EPI_STORE, ep);
+    add(FK_LINV, 1, K_GEMM_YZ_INV, W1, W2, px, c->ncomp * pz, yslab, EPI_STORE, ep);
+  }
+  // x inverse: the dense epilogue writes ep.dense; with EPI_STORE it writes W1
+  add(FK_RINV, 0, K_GEMM_X_UPDATE, W2, W1, 0, 0, 0, epi_last, ep);
+  return ns;
+}
+
+hipError_t run_step(qn_ctx c, const FoldStep& f, int tm, int tn) {
+  const FoldOperands F = fold_ops(c, f.axis);
+  const FoldAxis& ax = c->ax[f.axis];
+  switch (f.kind) {
+    case FK_RFWD:
+      return launch_fold_right_fwd(c->prec, F, f.in, f.out, ax, f.rows, f.ep, tm, tn, c->stream);
+    case FK_LFWD:
+      return launch_fold_left_fwd(c->prec, F, f.in, f.out, ax, f.ncols, f.batch, f.bstride, f.epi,
+                                  f.ep, tm, tn, c->stream);
+    case FK_LINV:
+      return launch_fold_left_inv(c->prec, F, f.in, f.out, ax, f.ncols, f.batch, f.bstride, f.ep,
+                                  tm, tn, c->stream);
+    default:
+      return launch_fold_right_inv(c->prec, F, f.in, f.out, ax, f.rows, f.epi, f.ep, tm, tn,
+                                   c->stream);
+  }
+}
+
 // The tensor-product solve of the padded tensor in W1 with coefficients
 // coef = {scale, beta} (device); the result goes to `dense` with epilogue
 // epi_last (EPI_SUB_DENSE: U -= X, EPI_STORE_DENSE: X).
+EpiArgs epi_args(qn_ctx c, const double* coef, double* dense) {
+  EpiArgs ep{};
+  ep.inst_mod = 1;
+  ep.coef = coef;
+  ep.dense = dense;
+  ep.px = c->p[0];
+  ep.py = c->p[1];
+  ep.pz = c->p[2];
+  ep.nx = c->n[0];
+  ep.ny = c->n[1];
+  ep.nz = c->n[2];
+  ep.lamX = c->at<double>(c->off_lam[0]);
+  return ep;
+}
+
 hipError_t solve_ws(qn_ctx c, const double* coef, double* dense, int epi_last) {
   void* W1 = c->ws + c->off_W1;
   void* W2 = c->ws + c->off_W2;
   const int px = c->p[0], py = c->p[1], pz = c->p[2];
   const int pr = c->prec;
-  EpiArgs ep{};
-  ep.inst_mod = 1;
-  ep.coef = coef;
-  ep.dense = dense;
-  ep.px = px;
-  ep.py = py;
-  ep.pz = pz;
-  ep.nx = c->n[0];
-  ep.ny = c->n[1];
-  ep.nz = c->n[2];
-  ep.lamX = c->at<double>(c->off_lam[0]);
+  const EpiArgs ep = epi_args(c, coef, dense);
   const int rows = c->ncomp * pz * py;
-  const long long yslab_f = (long long)py * px;
-  hipError_t ef;
   if (c->fold) {
-    const FoldOperands Fx = fold_ops(c, 0), Fy = fold_ops(c, 1), Fz = fold_ops(c, 2);
-    int tm, tn;
-#define QN_TRYF(x)                    \
-  do {                                \
-    ef = (x);                         \
-    if (ef != hipSuccess) return ef;  \
-  } while (0)
-    pick2(kRfwd, 5, rows, c->ax[0].bk, tm, tn);
-    QN_TRYF(timed(c, K_GEMM_X, [&] {
-      return launch_fold_right_fwd(pr, Fx, W1, W2, c->ax[0], rows, ep, tm, tn, c->stream);
-    }));
-    if (c->dim == 2) {
-      EpiArgs ed = ep;
-      ed.lamM = c->at<double>(c->off_lam[1]);
-      ed.lamY = nullptr;
-      pick2(kLfwd, 5, c->ax[1].bk, px, tm, tn);
-      QN_TRYF(timed(c, K_GEMM_DIVIDE, [&] {
-        return launch_fold_left_fwd(pr, Fy, W2, W1, c->ax[1], px, c->ncomp, yslab_f, EPI_DIVIDE,
-                                    ed, tm, tn, c->stream);
-      }));
-      pick2(kLinv, 4, c->ax[1].bk, px, tm, tn);
-      QN_TRYF(timed(c, K_GEMM_YZ_INV, [&] {
-        return launch_fold_left_inv(pr, Fy, W1, W2, c->ax[1], px, c->ncomp, yslab_f, ep, tm, tn,
-                                    c->stream);
-      }));
-    } else {
-      const long long zslab = (long long)pz * py * px;
-      pick2(kLfwd, 5, c->ax[1].bk, px, tm, tn);
-      QN_TRYF(timed(c, K_GEMM_YZ, [&] {
-        return launch_fold_left_fwd(pr, Fy, W2, W1, c->ax[1], px, c->ncomp * pz, yslab_f,
-                                    EPI_STORE, ep, tm, tn, c->stream);
-      }));
-      EpiArgs ed = ep;
-      ed.lamM = c->at<double>(c->off_lam[2]);
-      ed.lamY = c->at<double>(c->off_lam[1]);
-      pick2(kLfwd, 5, c->ax[2].bk, yslab_f, tm, tn);
-      QN_TRYF(timed(c, K_GEMM_DIVIDE, [&] {
-        return launch_fold_left_fwd(pr, Fz, W1, W2, c->ax[2], (int)yslab_f, c->ncomp, zslab,
-                                    EPI_DIVIDE, ed, tm, tn, c->stream);
-      }));
-      pick2(kLinv, 4, c->ax[2].bk, yslab_f, tm, tn);
-      QN_TRYF(timed(c, K_GEMM_YZ_INV, [&] {
-        return launch_fold_left_inv(pr, Fz, W2, W1, c->ax[2], (int)yslab_f, c->ncomp, zslab, ep,
-                                    tm, tn, c->stream);
-      }));
-      pick2(kLinv, 4, c->ax[1].bk, px, tm, tn);
-      QN_TRYF(timed(c, K_GEMM_YZ_INV, [&] {
-        return launch_fold_left_inv(pr, Fy, W1, W2, c->ax[1], px, c->ncomp * pz, yslab_f, ep, tm,
-                                    tn, c->stream);
-      }));
+    FoldStep st[6];
+    const int ns = fold_plan(c, ep, epi_last, st);
+    for (int i = 0; i < ns; ++i) {
+      int tm, tn;
+      if (c->tuned) {
+        tm = c->tile[i][0];
+        tn = c->tile[i][1];
+      } else {
+        const int(*cl)[2];
+        int nc;
+        candidates(st[i].kind, &cl, &nc);
+        pick2(cl, nc, st[i].mext, st[i].next, st[i].nblk, tm, tn);
+      }
+      const FoldStep& f = st[i];
+      const hipError_t ef = timed(c, f.kid, [&] { return run_step(c, f, tm, tn); });
+      if (ef != hipSuccess) return ef;
     }
-    pick2(kRinv, 4, rows, c->ax[0].bk, tm, tn);
-    QN_TRYF(timed(c, K_GEMM_X_UPDATE, [&] {
-      return launch_fold_right_inv(pr, Fx, W2, nullptr, c->ax[0], rows, epi_last, ep, tm, tn,
-                                   c->stream);
-    }));
-#undef QN_TRYF
     return hipSuccess;
   }
   const GemmOperands Sx = operands(c, 0), Sy = operands(c, 1), Sz = operands(c, 2);
@@ -665,6 +748,78 @@ qn_status qn_iterate(qn_ctx c, double* d_U, const double* d_F, double rtol, int3
     }
     ++k;
   }
+}
+
+qn_status qn_autotune(qn_ctx c) {
+  qn_status s = check_ctx(c, true);
+  if (s != QN_OK) return s;
+  if (!c->fold) return QN_OK;  // bf16x3: dense kernels, fixed rule
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipError_t e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  // finite transform contents; the coefficient slot holds {scale, shift} = {1, 1}
+  const size_t tbytes = c->tensor_elems() * c->elem();
+  if (e == hipSuccess) e = launch_zero(c->ws + c->off_W1, tbytes, c->stream);
+  if (e == hipSuccess) e = launch_zero(c->ws + c->off_W2, tbytes, c->stream);
+  double* coef = c->at<double>(c->off_coef);
+  if (e == hipSuccess) e = launch_set_coef(coef, 1.0, 1.0, c->stream);
+  FoldStep st[6];
+  const int ns = fold_plan(c, epi_args(c, coef, nullptr), EPI_STORE, st);
+  int best[6][2] = {};
+  for (int i = 0; i < ns && e == hipSuccess; ++i) {
+    const int(*cl)[2];
+    int nc;
+    candidates(st[i].kind, &cl, &nc);
+    pick2(cl, nc, st[i].mext, st[i].next, st[i].nblk, best[i][0], best[i][1]);
+    float best_ms = 1e30f;
+    for (int k = 0; k < nc && e == hipSuccess; ++k) {
+      const int tm = cl[k][0], tn = cl[k][1];
+      if (st[i].mext % tm || st[i].next % tn) continue;
+      e = run_step(c, st[i], tm, tn);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(t0, c->stream);
+      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run_step(c, st[i], tm, tn);
+      if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+      if (e == hipSuccess && ms < best_ms) {
+        best_ms = ms;
+        best[i][0] = tm;
+        best[i][1] = tn;
+      }
+    }
+  }
+  if (t0) hipEventDestroy(t0);
+  if (t1) hipEventDestroy(t1);
+  if (e != hipSuccess) return hip_fail(c, e, "autotune");
+  std::memcpy(c->tile, best, sizeof best);
+  c->tuned = true;
+  return QN_OK;
+}
+
+qn_status qn_tile_info(qn_ctx c, int32_t i, int32_t* info4) {
+  qn_status s = check_ctx(c, true);
+  if (s != QN_OK) return s;
+  if (!info4) return fail(QN_ERR_INVALID, "null argument");
+  if (!c->fold) return fail(QN_ERR_UNSUPPORTED, "no folded transforms in this precision");
+  FoldStep st[6];
+  const int ns = fold_plan(c, epi_args(c, nullptr, nullptr), EPI_STORE, st);
+  if (i < 0 || i >= ns) return fail(QN_ERR_INVALID, "launch index %d out of range [0, %d)", i, ns);
+  int tm, tn;
+  if (c->tuned) {
+    tm = c->tile[i][0];
+    tn = c->tile[i][1];
+  } else {
+    const int(*cl)[2];
+    int nc;
+    candidates(st[i].kind, &cl, &nc);
+    pick2(cl, nc, st[i].mext, st[i].next, st[i].nblk, tm, tn);
+  }
+  info4[0] = st[i].kind;
+  info4[1] = st[i].axis;
+  info4[2] = tm;
+  info4[3] = tn;
+  return QN_OK;
 }
 
 int32_t qn_timing_count(void) { return K_COUNT; }

@@ -560,18 +560,38 @@ __global__ __launch_bounds__(256, 2) void k_fold_right_inv(const T* __restrict__
   }
 
 #pragma unroll
-  for (int i = 0; i < BM; ++i)
+  for (int i = 0; i < BM; ++i) {
+    // Row bases of this fragment row block; for U -= dU every old value of the
+    // block is loaded before the first store, so the loads overlap instead of
+    // each waiting behind the previous store to the same array.
+    long long base[4];
+    bool row_ok[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int r = r0 + wm + 16 * i + MF::row(lane, q);
-      long long base = 0;
-      bool row_ok = true;
+      base[q] = (long long)r * P2;
+      row_ok[q] = true;
       if (EPI != EPI_STORE) {
         const int y = r % ep.py, zc = r / ep.py, z = zc % ep.pz, c = zc / ep.pz;
-        base = (((long long)c * ep.nz + z) * ep.ny + y) * ep.nx;
-        row_ok = y < ep.ny && z < ep.nz;
+        base[q] = (((long long)c * ep.nz + z) * ep.ny + y) * ep.nx;
+        row_ok[q] = y < ep.ny && z < ep.nz;
       }
-      if (!row_ok) continue;
+    }
+    double old1[4][BN], old2[4][BN];
+    if (EPI == EPI_SUB_DENSE) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          const int k = k0 + wn + 16 * j + (lane & 15);
+          const bool pair = k < h, centre = (k == h) && ax.odd;
+          old1[q][j] = (row_ok[q] && (pair || centre)) ? ep.dense[base[q] + k] : 0.0;
+          old2[q][j] = (row_ok[q] && pair) ? ep.dense[base[q] + na - 1 - k] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!row_ok[q]) continue;
 #pragma unroll
       for (int j = 0; j < BN; ++j) {
         const int k = k0 + wn + 16 * j + (lane & 15);
@@ -580,17 +600,18 @@ __global__ __launch_bounds__(256, 2) void k_fold_right_inv(const T* __restrict__
         if (!pair && !centre) continue;
         const T v1 = pair ? p + qq : p;
         if (EPI == EPI_STORE) {
-          C[(long long)r * P2 + k] = v1;
-          if (pair) C[(long long)r * P2 + na - 1 - k] = p - qq;
+          C[base[q] + k] = v1;
+          if (pair) C[base[q] + na - 1 - k] = p - qq;
         } else if (EPI == EPI_SUB_DENSE) {
-          ep.dense[base + k] -= (double)v1;
-          if (pair) ep.dense[base + na - 1 - k] -= (double)(p - qq);
+          ep.dense[base[q] + k] = old1[q][j] - (double)v1;
+          if (pair) ep.dense[base[q] + na - 1 - k] = old2[q][j] - (double)(p - qq);
         } else {
-          ep.dense[base + k] = (double)v1;
-          if (pair) ep.dense[base + na - 1 - k] = (double)(p - qq);
+          ep.dense[base[q] + k] = (double)v1;
+          if (pair) ep.dense[base[q] + na - 1 - k] = (double)(p - qq);
         }
       }
     }
+  }
 }
 
 // ------------------------------------------------------------------ dispatch

@@ -31,9 +31,13 @@ struct Mfma<float> {
   __device__ static inline int row(int lane, int q) { return 4 * (lane >> 4) + q; }
 };
 
-// Tile index for workgroup w: each XCD (w % 8) gets a contiguous tile range.
+// Tile index for workgroup w of `total`: workgroups are dealt to the 8 XCDs
+// round-robin (XCD w % 8), so XCD j is given the contiguous range of
+// total / 8 (+1 for j < total % 8) tiles starting at j * (total / 8) +
+// min(j, total % 8).  A bijection on [0, total).
 __device__ inline int xcd_tile(int w, int total) {
-  return (total % 8 == 0) ? (w % 8) * (total / 8) + (w / 8) : w;
+  const int q = total >> 3, r = total & 7, j = w & 7;
+  return j * q + (j < r ? j : r) + (w >> 3);
 }
 
 }  // namespace qn

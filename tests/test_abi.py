@@ -87,3 +87,111 @@ def test_null_context_and_timing_table():
     assert L.qn_iterate(None, None, None, 0.0, 0, None) == qn.QN_ERR_INVALID
     assert L.qn_timing_count() >= 6
     L.qn_destroy(None)
+
+
+def test_autotune_and_tile_info_need_a_workspace():
+    L = qn.lib()
+    L.qn_autotune.argtypes = [ctypes.c_void_p]
+    L.qn_tile_info.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    info = (ctypes.c_int32 * 4)()
+    assert L.qn_autotune(None) == qn.QN_ERR_INVALID
+    st, ctx = setup(n=(33, 17, 9))
+    assert st == qn.QN_OK
+    assert L.qn_autotune(ctx) == qn.QN_ERR_WORKSPACE
+    assert L.qn_tile_info(ctx, 0, info) == qn.QN_ERR_WORKSPACE
+    L.qn_destroy(ctx)
+
+
+def _qnn():
+    L = qn.lib()
+    L.qnn_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                             ctypes.POINTER(ctypes.c_void_p)]
+    L.qnn_workspace_bytes.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]
+    L.qnn_bind_workspace.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
+    L.qnn_forward.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int32, ctypes.c_void_p]
+    L.qnn_adam_step.argtypes = [ctypes.c_void_p] + [ctypes.c_double] * 4
+    L.qnn_destroy.argtypes = [ctypes.c_void_p]
+    L.qnn_destroy.restype = None
+    return L
+
+
+@pytest.mark.parametrize("H,W,B", [(0, 5, 1), (5, 4097, 1), (5, 5, 0), (5, 5, 1025)])
+def test_qnn_create_rejects_invalid(H, W, B):
+    L = _qnn()
+    net = ctypes.c_void_p()
+    assert L.qnn_create(H, W, B, ctypes.byref(net)) == qn.QN_ERR_INVALID
+    assert qn.last_error()
+
+
+def test_qnn_host_checks():
+    L = _qnn()
+    assert L.qnn_param_count() == 28641  # 2*32*9+32 + 3*(32*32*9+32) + 32*9+1
+    net = ctypes.c_void_p()
+    assert L.qnn_create(255, 255, 4, ctypes.byref(net)) == qn.QN_OK
+    nb = ctypes.c_size_t()
+    assert L.qnn_workspace_bytes(net, ctypes.byref(nb)) == qn.QN_OK
+    assert nb.value > 4 * 255 * 255 * 32 * 4  # at least one FP32 activation tensor
+    assert L.qnn_forward(net, None, None, 1, None) == qn.QN_ERR_WORKSPACE
+    assert L.qnn_bind_workspace(net, ctypes.c_void_p(256 + 8), nb.value) == qn.QN_ERR_WORKSPACE
+    assert L.qnn_bind_workspace(net, ctypes.c_void_p(4096), nb.value - 1) == qn.QN_ERR_WORKSPACE
+    assert L.qnn_forward(None, None, None, 1, None) == qn.QN_ERR_INVALID
+    L.qnn_destroy(net)
+    L.qnn_destroy(None)
+
+
+def _qnb():
+    L = qn.lib()
+    L.qnb_setup.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                            ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_void_p)]
+    L.qnb_field_elems.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
+    L.qnb_instance_layout.argtypes = [ctypes.c_void_p, ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    L.qnb_iterate.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_double, ctypes.c_int32,
+                                                      ctypes.c_int32, ctypes.c_void_p]
+    L.qnb_destroy.argtypes = [ctypes.c_void_p]
+    L.qnb_destroy.restype = None
+    return L
+
+
+def _qnb_setup(n, nc, prec=1, bmode=1, beta=0.0):
+    L = _qnb()
+    a = (ctypes.c_int32 * len(n))(*n)
+    b = (ctypes.c_int32 * len(nc))(*nc)
+    ctx = ctypes.c_void_p()
+    return L.qnb_setup(len(n), a, b, prec, bmode, beta, ctypes.byref(ctx)), ctx
+
+
+@pytest.mark.parametrize("n,nc,prec,bmode,beta", [
+    ([0], [1], 1, 1, 0.0), ([5000], [1], 1, 1, 0.0), ([9], [3], 1, 1, 0.0),
+    ([9], [1], 7, 1, 0.0), ([9], [1], 1, 5, 0.0), ([9], [1], 1, 0, float("inf")),
+])
+def test_qnb_setup_rejects_invalid(n, nc, prec, bmode, beta):
+    st, _ = _qnb_setup(n, nc, prec, bmode, beta)
+    assert st == qn.QN_ERR_INVALID
+    assert qn.last_error()
+
+
+def test_qnb_layout_covers_pool_exactly():
+    L = _qnb()
+    n = [15, 31, 15, 8, 31, 15]
+    nc = [1, 2, 1, 2, 2, 1]
+    st, ctx = _qnb_setup(n, nc)
+    assert st == qn.QN_OK
+    total = ctypes.c_int64()
+    assert L.qnb_field_elems(ctx, ctypes.byref(total)) == qn.QN_OK
+    assert total.value == sum(c * k * k for k, c in zip(n, nc))
+    covered = []
+    for i, (k, c) in enumerate(zip(n, nc)):
+        off, cs = ctypes.c_int64(), ctypes.c_int64()
+        assert L.qnb_instance_layout(ctx, i, ctypes.byref(off), ctypes.byref(cs)) == qn.QN_OK
+        for comp in range(c):
+            covered.append((off.value + comp * cs.value, k * k))
+    covered.sort()
+    pos = 0
+    for start, size in covered:  # disjoint, gap-free tiling of the pool
+        assert start == pos
+        pos += size
+    assert pos == total.value
+    assert L.qnb_instance_layout(ctx, len(n), ctypes.byref(off), ctypes.byref(cs)) == qn.QN_ERR_INVALID
+    assert L.qnb_iterate(ctx, None, None, 1e-10, 10, 4, None) == qn.QN_ERR_WORKSPACE
+    L.qnb_destroy(ctx)

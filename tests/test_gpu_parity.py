@@ -258,3 +258,32 @@ def test_deterministic_bitwise():
         s.iterate(u, dev(f[None]), rtol=0.0, max_iter=6)
         outs.append(host(u))
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("kind,shape,prec", [
+    ("cubic", (37, 45, 70), "fp64"), ("system", (31, 64, 97), "fp64"),
+    ("quasilinear", (65, 33), "fp64"), ("cubic", (40, 50, 70), "fp32"),
+])
+def test_autotuned_tiles_give_bitwise_identical_solves(kind, shape, prec):
+    """The tile shape changes the work split, never the arithmetic order: an
+    autotuned solver returns the same bits as the default one, and every chosen
+    tile divides its launch's extents."""
+    print(f"autotune {kind} {shape} {prec}", flush=True)
+    ncomp = 2 if kind == "system" else 1
+    f = dev(synth.random_field((ncomp,) + shape, 301, scale=20.0))
+    beta = 0.0 if kind == "quasilinear" else 1.0
+    ref = Solver(shape, kind, beta=beta, precision=prec)
+    tuned = Solver(shape, kind, beta=beta, precision=prec)
+    tuned.autotune()
+    for kid, axis, tm, tn in tuned.tiles():
+        n = list(reversed(shape))[axis]
+        bk = 32 * math.ceil(math.ceil(n / 2) / 32)
+        assert bk % (tm if kid in (1, 2) else tn) == 0, (kid, axis, tm, tn)
+    ua, ub = ref.empty().zero_(), tuned.empty().zero_()
+    sa = ref.iterate(ua, f, rtol=0.0, max_iter=3)
+    sb = tuned.iterate(ub, f, rtol=0.0, max_iter=3)
+    assert sa["iters"] == sb["iters"] == 3
+    assert torch.equal(ua, ub)
+    xa = ref.fdm_solve(f, scale=1.5, shift=0.25)
+    xb = tuned.fdm_solve(f, scale=1.5, shift=0.25)
+    assert torch.equal(xa, xb)
