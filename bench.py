@@ -223,10 +223,17 @@ def main():
     dense_flops = 2.0 * float(n) ** 4
     # kernel names per timing key from the tiles in use (launch order: x, y
     # forward, z forward + divide, z and y inverse, x inverse + update)
-    kn = ["k_fold_right_fwd<double,{},{}>", "k_fold_left_fwd<double,{},{},EPI_STORE>",
-          "k_fold_left_fwd<double,{},{},EPI_DIVIDE>", "k_fold_left_inv<double,{},{}>",
-          "k_fold_left_inv<double,{},{}>", "k_fold_right_inv<double,{},{},EPI_SUB_DENSE>"]
-    kname = [f.format(t[2], t[3]) for f, t in zip(kn, tiles)]
+    def kernel_name(slot, t):
+        kind, _, tm, tn = t
+        if kind == 0:
+            return f"k_fold_right_fwd<double,{tm},{tn}>"
+        if kind in (1, 4):
+            epi = "EPI_DIVIDE" if slot == 2 else "EPI_STORE"
+            return f"k_fold_left_fwd{'2' if kind == 4 else ''}<double,{tm},{tn},{epi}>"
+        if kind == 2:
+            return f"k_fold_left_inv<double,{tm},{tn}>"
+        return f"k_fold_right_inv<double,{tm},{tn},EPI_SUB_DENSE>"
+    kname = [kernel_name(i, t) for i, t in enumerate(tiles)]
     names = {"gemm_x": kname[0], "gemm_yz": kname[1], "gemm_divide": kname[2],
              "gemm_yz_inv": kname[3] if kname[3] == kname[4] else kname[3] + " / " + kname[4],
              "gemm_x_update": kname[5]}
@@ -269,7 +276,7 @@ def main():
                                                            (all_gemm_ms * 1e-3) / 1e12, 3),
         "kernels": kernels,
         "tiles": {"launches": ["x fwd", "y fwd", "z fwd+divide", "z inv", "y inv", "x inv+update"],
-                  "tile_mn": [[t[2], t[3]] for t in tiles], "autotune_s": round(t_tune, 3)},
+                  "kernels": kname, "autotune_s": round(t_tune, 3)},
     }
 
     if not args.no_time_to_tol:

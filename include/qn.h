@@ -179,8 +179,9 @@ qn_status qn_iterate(qn_ctx ctx, double* d_U, const double* d_F, double rtol,
  * transforms use a fixed rule. */
 qn_status qn_autotune(qn_ctx ctx);
 /* Launch i of the solve: info4 = {kind (0 x forward, 1 y/z forward, 2 y/z
- * inverse, 3 x inverse), axis (0 x, 1 y, 2 z), tile_m, tile_n}.  Requires a
- * bound workspace; QN_ERR_UNSUPPORTED for QN_PREC_BF16X3. */
+ * inverse, 3 x inverse, 4 y/z forward with paired even/odd tiles), axis (0 x,
+ * 1 y, 2 z), tile_m, tile_n}.  Requires a bound workspace;
+ * QN_ERR_UNSUPPORTED for QN_PREC_BF16X3. */
 qn_status qn_tile_info(qn_ctx ctx, int32_t i, int32_t* info4);
 
 /* Kernel timing (contexts created with options.timing != 0).  qn_timing_read

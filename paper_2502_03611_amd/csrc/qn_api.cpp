@@ -92,7 +92,7 @@ struct qn_ctx_s {
   hipStream_t stream = nullptr;
   bool fold = true;       // reflection-folded transforms (FP64/FP32); dense for bf16x3
   FoldAxis ax[3] = {};
-  int tile[6][2] = {};    // per mode-product launch of the folded solve (after qn_autotune)
+  FoldTile tile[6] = {};  // per mode-product launch of the folded solve (after qn_autotune)
   bool tuned = false;
   std::vector<double> hS[3], hlam[3];  // dense S or folded FeT|FoT|Fe|Fo; lam (split if folded)
   // workspace layout (byte offsets)
@@ -190,40 +190,29 @@ FoldOperands fold_ops(qn_ctx c, int axis) {
   return f;
 }
 
-// Tile (tm, tn) for a fold kernel: the largest instantiated shape that divides
-// the extents (mext: the folded half extent bk or the row count; next: the
-// column extent) and still gives at least two workgroups per CU, counting
-// `batch` launches of the tile grid (forward kernels pass twice the slab
-// count: even and odd halves); when none does (small 2D grids), the admissible
-// shape with the most workgroups.
-void pick2(const int (*cand)[2], int ncand, long long mext, long long next, long long batch,
-           int& tm, int& tn) {
+// Tile of a fold launch: the first instantiated shape (in order of preference)
+// that divides the launch's extents and gives at least two workgroups per CU;
+// when none does (small 2D grids), the admissible shape with the most
+// workgroups.
+FoldTile pick_fold_tile(int kind, int bk, int ncols, int batch, int rows) {
+  const FoldTile* list;
+  const int nc = fold_tiles(kind, &list);
+  long long mext, next;
+  fold_extents(kind, bk, ncols, rows, &mext, &next);
   const long long want = 2LL * 256;
-  tm = tn = 32;
-  long long best = -1;
-  for (int i = 0; i < ncand; ++i) {
-    if (mext % cand[i][0] || next % cand[i][1]) continue;
-    const long long blocks = batch * (mext / cand[i][0]) * (next / cand[i][1]);
-    if (blocks >= want) {
-      tm = cand[i][0];
-      tn = cand[i][1];
-      return;
-    }
-    if (blocks > best) {
-      best = blocks;
-      tm = cand[i][0];
-      tn = cand[i][1];
+  FoldTile best{32, 32, 0};
+  long long best_blocks = -1;
+  for (int i = 0; i < nc; ++i) {
+    if (mext % list[i].tm || next % list[i].tn) continue;
+    const long long blocks = fold_blocks(kind, list[i], bk, ncols, batch, rows);
+    if (blocks >= want) return list[i];
+    if (blocks > best_blocks) {
+      best_blocks = blocks;
+      best = list[i];
     }
   }
+  return best;
 }
-// Instantiated tile shapes per fold kernel, in order of preference (measured
-// on the 511^3 FP64 workload: the inverse kernels run fastest with 64 x 64).
-const int kLfwd[5][2] = {{128, 128}, {64, 128}, {64, 64}, {32, 64}, {32, 32}};
-const int kLinv[4][2] = {{64, 64}, {64, 128}, {32, 64}, {32, 32}};
-const int kRfwd[5][2] = {{128, 128}, {128, 64}, {64, 64}, {64, 32}, {32, 32}};
-const int kRinv[4][2] = {{64, 64}, {128, 64}, {64, 32}, {32, 32}};
-
-enum FoldKind { FK_RFWD, FK_LFWD, FK_LINV, FK_RINV };
 
 // One mode-product launch of the folded solve.
 struct FoldStep {
@@ -235,17 +224,8 @@ struct FoldStep {
   int rows;             // form R: row count
   int epi;
   EpiArgs ep;
-  long long mext, next, nblk;  // tile admissibility (tm | mext, tn | next) and block factor
 };
 
-void candidates(int kind, const int (**list)[2], int* count) {
-  switch (kind) {
-    case FK_RFWD: *list = kRfwd; *count = 5; break;
-    case FK_LFWD: *list = kLfwd; *count = 5; break;
-    case FK_LINV: *list = kLinv; *count = 4; break;
-    default: *list = kRinv; *count = 4; break;
-  }
-}
 GemmOperands operands(qn_ctx c, int axis) {
   GemmOperands g{};
   if (c->prec == QN_PREC_BF16X3) {
@@ -316,16 +296,6 @@ int fold_plan(qn_ctx c, const EpiArgs& ep, int epi_last, FoldStep* st) {
     f.rows = rows;
     f.epi = epi;
     f.ep = e;
-    const long long bk = c->ax[axis].bk;
-    if (kind == FK_RFWD || kind == FK_RINV) {
-      f.mext = rows;
-      f.next = bk;
-      f.nblk = kind == FK_RFWD ? 2 : 1;  // forward: even and odd column halves
-    } else {
-      f.mext = bk;
-      f.next = ncols;
-      f.nblk = (kind == FK_LFWD ? 2LL : 1LL) * batch;
-    }
     st[ns++] = f;
   };
   add(FK_RFWD, 0, K_GEMM_X, W1, W2, 0, 0, 0, EPI_STORE, ep);
@@ -349,22 +319,15 @@ int fold_plan(qn_ctx c, const EpiArgs& ep, int epi_last, FoldStep* st) {
   return ns;
 }
 
-hipError_t run_step(qn_ctx c, const FoldStep& f, int tm, int tn) {
-  const FoldOperands F = fold_ops(c, f.axis);
-  const FoldAxis& ax = c->ax[f.axis];
-  switch (f.kind) {
-    case FK_RFWD:
-      return launch_fold_right_fwd(c->prec, F, f.in, f.out, ax, f.rows, f.ep, tm, tn, c->stream);
-    case FK_LFWD:
-      return launch_fold_left_fwd(c->prec, F, f.in, f.out, ax, f.ncols, f.batch, f.bstride, f.epi,
-                                  f.ep, tm, tn, c->stream);
-    case FK_LINV:
-      return launch_fold_left_inv(c->prec, F, f.in, f.out, ax, f.ncols, f.batch, f.bstride, f.ep,
-                                  tm, tn, c->stream);
-    default:
-      return launch_fold_right_inv(c->prec, F, f.in, f.out, ax, f.rows, f.epi, f.ep, tm, tn,
-                                   c->stream);
-  }
+hipError_t run_step(qn_ctx c, const FoldStep& f, const FoldTile& t) {
+  return launch_fold(f.kind, c->prec, fold_ops(c, f.axis), f.in, f.out, c->ax[f.axis], f.ncols,
+                     f.batch, f.bstride, f.rows, f.epi, f.ep, t, c->stream);
+}
+
+// Tile of launch i of the plan: the autotuned one, else the default rule.
+FoldTile step_tile(qn_ctx c, const FoldStep& f, int i) {
+  if (c->tuned) return c->tile[i];
+  return pick_fold_tile(f.kind, c->ax[f.axis].bk, f.ncols, f.batch, f.rows);
 }
 
 // The tensor-product solve of the padded tensor in W1 with coefficients
@@ -396,18 +359,9 @@ hipError_t solve_ws(qn_ctx c, const double* coef, double* dense, int epi_last) {
     FoldStep st[6];
     const int ns = fold_plan(c, ep, epi_last, st);
     for (int i = 0; i < ns; ++i) {
-      int tm, tn;
-      if (c->tuned) {
-        tm = c->tile[i][0];
-        tn = c->tile[i][1];
-      } else {
-        const int(*cl)[2];
-        int nc;
-        candidates(st[i].kind, &cl, &nc);
-        pick2(cl, nc, st[i].mext, st[i].next, st[i].nblk, tm, tn);
-      }
       const FoldStep& f = st[i];
-      const hipError_t ef = timed(c, f.kid, [&] { return run_step(c, f, tm, tn); });
+      const FoldTile t = step_tile(c, f, i);
+      const hipError_t ef = timed(c, f.kid, [&] { return run_step(c, f, t); });
       if (ef != hipSuccess) return ef;
     }
     return hipSuccess;
@@ -765,34 +719,36 @@ qn_status qn_autotune(qn_ctx c) {
   if (e == hipSuccess) e = launch_set_coef(coef, 1.0, 1.0, c->stream);
   FoldStep st[6];
   const int ns = fold_plan(c, epi_args(c, coef, nullptr), EPI_STORE, st);
-  int best[6][2] = {};
+  FoldTile best[6] = {};
   for (int i = 0; i < ns && e == hipSuccess; ++i) {
-    const int(*cl)[2];
-    int nc;
-    candidates(st[i].kind, &cl, &nc);
-    pick2(cl, nc, st[i].mext, st[i].next, st[i].nblk, best[i][0], best[i][1]);
+    const FoldStep& f = st[i];
+    const int bk = c->ax[f.axis].bk;
+    best[i] = pick_fold_tile(f.kind, bk, f.ncols, f.batch, f.rows);
+    const FoldTile* list;
+    const int nc = fold_tiles(f.kind, &list);
+    long long mext, next;
+    fold_extents(f.kind, bk, f.ncols, f.rows, &mext, &next);
     float best_ms = 1e30f;
     for (int k = 0; k < nc && e == hipSuccess; ++k) {
-      const int tm = cl[k][0], tn = cl[k][1];
-      if (st[i].mext % tm || st[i].next % tn) continue;
-      e = run_step(c, st[i], tm, tn);  // warm-up
+      const FoldTile t = list[k];
+      if (mext % t.tm || next % t.tn) continue;
+      e = run_step(c, f, t);  // warm-up
       if (e == hipSuccess) e = hipEventRecord(t0, c->stream);
-      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run_step(c, st[i], tm, tn);
+      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run_step(c, f, t);
       if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
       if (e == hipSuccess) e = hipEventSynchronize(t1);
       float ms = 0.f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
       if (e == hipSuccess && ms < best_ms) {
         best_ms = ms;
-        best[i][0] = tm;
-        best[i][1] = tn;
+        best[i] = t;
       }
     }
   }
   if (t0) hipEventDestroy(t0);
   if (t1) hipEventDestroy(t1);
   if (e != hipSuccess) return hip_fail(c, e, "autotune");
-  std::memcpy(c->tile, best, sizeof best);
+  for (int i = 0; i < 6; ++i) c->tile[i] = best[i];
   c->tuned = true;
   return QN_OK;
 }
@@ -805,20 +761,11 @@ qn_status qn_tile_info(qn_ctx c, int32_t i, int32_t* info4) {
   FoldStep st[6];
   const int ns = fold_plan(c, epi_args(c, nullptr, nullptr), EPI_STORE, st);
   if (i < 0 || i >= ns) return fail(QN_ERR_INVALID, "launch index %d out of range [0, %d)", i, ns);
-  int tm, tn;
-  if (c->tuned) {
-    tm = c->tile[i][0];
-    tn = c->tile[i][1];
-  } else {
-    const int(*cl)[2];
-    int nc;
-    candidates(st[i].kind, &cl, &nc);
-    pick2(cl, nc, st[i].mext, st[i].next, st[i].nblk, tm, tn);
-  }
-  info4[0] = st[i].kind;
+  const FoldTile t = step_tile(c, st[i], i);
+  info4[0] = st[i].kind == FK_LFWD && t.paired ? 4 : st[i].kind;
   info4[1] = st[i].axis;
-  info4[2] = tm;
-  info4[3] = tn;
+  info4[2] = t.tm;
+  info4[3] = t.tn;
   return QN_OK;
 }
 

@@ -44,8 +44,9 @@ struct Cls {
   int bpi = 0;                // residual workgroups per instance
   int tmL = 32, tnL = 32;     // y-product tile (forward)
   int tmR = 32, tnR = 32;     // x-product tile (forward)
-  int tmLi = 32, tnLi = 32;   // y-product tile (inverse, folded)
-  int tmRi = 32, tnRi = 32;   // x-product tile (inverse, folded)
+  // folded transforms: tiles of the x forward, y forward (+ divide), y
+  // inverse and x inverse (+ update) launches
+  FoldTile fR{32, 32, 0}, fL{32, 32, 0}, fLi{32, 32, 0}, fRi{32, 32, 0};
   FoldAxis ax{};
   hipStream_t s = nullptr;    // per-class stream (default priority)
   hipEvent_t ev = nullptr;
@@ -97,10 +98,6 @@ FoldOperands fops(qnb_ctx c, const Cls& k) {
 }
 
 // Instantiated tile shapes of the folded kernels (see qn_gemm_fold.hip).
-const int kLfwd[5][2] = {{128, 128}, {64, 128}, {64, 64}, {32, 64}, {32, 32}};
-const int kLinv[4][2] = {{64, 128}, {64, 64}, {32, 64}, {32, 32}};
-const int kRfwd[5][2] = {{128, 128}, {128, 64}, {64, 64}, {64, 32}, {32, 32}};
-const int kRinv[4][2] = {{128, 64}, {64, 64}, {64, 32}, {32, 32}};
 
 GemmOperands ops(qnb_ctx c, const Cls& k) {
   GemmOperands g{};
@@ -170,15 +167,16 @@ hipError_t class_iteration(qnb_ctx c, Cls& k, double* U, const double* F, double
   const long long sl = (long long)k.p * k.p;
   if (c->fold) {
     const FoldOperands F = fops(c, k);
-    e = launch_fold_right_fwd(c->prec, F, W1, W2, k.ax, rows, ep, k.tmR, k.tnR, s);
+    e = launch_fold(FK_RFWD, c->prec, F, W1, W2, k.ax, 0, 0, 0, rows, EPI_STORE, ep, k.fR, s);
     if (e == hipSuccess)
-      e = launch_fold_left_fwd(c->prec, F, W2, W1, k.ax, k.p, slabs, sl, EPI_DIVIDE, ep, k.tmL,
-                               k.tnL, s);
+      e = launch_fold(FK_LFWD, c->prec, F, W2, W1, k.ax, k.p, slabs, sl, rows, EPI_DIVIDE, ep, k.fL,
+                      s);
     if (e == hipSuccess)
-      e = launch_fold_left_inv(c->prec, F, W1, W2, k.ax, k.p, slabs, sl, ep, k.tmLi, k.tnLi, s);
+      e = launch_fold(FK_LINV, c->prec, F, W1, W2, k.ax, k.p, slabs, sl, rows, EPI_STORE, ep, k.fLi,
+                      s);
     if (e == hipSuccess)
-      e = launch_fold_right_inv(c->prec, F, W2, nullptr, k.ax, rows, EPI_SUB_DENSE, ep, k.tmRi,
-                                k.tnRi, s);
+      e = launch_fold(FK_RINV, c->prec, F, W2, nullptr, k.ax, 0, 0, 0, rows, EPI_SUB_DENSE, ep,
+                      k.fRi, s);
     return e;
   }
   e = launch_gemm_right(c->prec, S, W1, W2, rows, k.p, EPI_STORE, ep, k.tmR, k.tnR, s);
@@ -299,18 +297,22 @@ qn_status qnb_setup(int32_t count, const int32_t* n, const int32_t* ncomp, int32
     // An x-product row tile must not straddle two instances (skip flags are
     // per tile), so its height divides P; folded tiles stay inside one half.
     if (c->fold) {
-      auto first = [&](const int (*cand)[2], int nc, int mext, int next, int& tm, int& tn) {
+      // first listed tile that fits (x-product row tiles divide P)
+      auto first = [&](int kind, FoldTile& t) {
+        const FoldTile* list;
+        const int nc = fold_tiles(kind, &list);
+        long long mext, next;
+        fold_extents(kind, k.ax.bk, k.p, k.p, &mext, &next);
         for (int q = 0; q < nc; ++q)
-          if (mext % cand[q][0] == 0 && next % cand[q][1] == 0) {
-            tm = cand[q][0];
-            tn = cand[q][1];
+          if (mext % list[q].tm == 0 && next % list[q].tn == 0) {
+            t = list[q];
             return;
           }
       };
-      first(kRfwd, 5, k.p, k.ax.bk, k.tmR, k.tnR);
-      first(kLfwd, 5, k.ax.bk, k.p, k.tmL, k.tnL);
-      first(kLinv, 4, k.ax.bk, k.p, k.tmLi, k.tnLi);
-      first(kRinv, 4, k.p, k.ax.bk, k.tmRi, k.tnRi);
+      first(FK_RFWD, k.fR);
+      first(FK_LFWD, k.fL);
+      first(FK_LINV, k.fLi);
+      first(FK_RINV, k.fRi);
     } else {
       k.tmL = largest_tile(k.p);
       k.tnL = largest_tile(k.p);
@@ -418,51 +420,55 @@ qn_status qnb_autotune(qnb_ctx c) {
     const int rows = k.ncomp * k.K * k.p, slabs = k.ncomp * k.K;
     const long long sl = (long long)k.p * k.p;
     const FoldOperands F = c->fold ? fops(c, k) : FoldOperands{};
-    const int nforms = c->fold ? 4 : 2;
-    for (int form = 0; form < nforms && e == hipSuccess; ++form) {
+    auto time_run = [&](auto run, float& ms) {
+      hipError_t r = run();  // warm-up
+      if (r == hipSuccess) r = hipEventRecord(t0, c->stream);
+      for (int q = 0; q < 3 && r == hipSuccess; ++q) r = run();
+      if (r == hipSuccess) r = hipEventRecord(t1, c->stream);
+      if (r == hipSuccess) r = hipEventSynchronize(t1);
+      if (r == hipSuccess) r = hipEventElapsedTime(&ms, t0, t1);
+      return r;
+    };
+    if (c->fold) {
+      const int kinds[4] = {FK_LFWD, FK_RFWD, FK_LINV, FK_RINV};
+      FoldTile* dst[4] = {&k.fL, &k.fR, &k.fLi, &k.fRi};
+      for (int fi = 0; fi < 4 && e == hipSuccess; ++fi) {
+        const int kind = kinds[fi];
+        const FoldTile* list;
+        const int nc = fold_tiles(kind, &list);
+        long long mext, next;
+        // x-product row tiles divide P, so they never straddle two instances
+        fold_extents(kind, k.ax.bk, k.p, k.p, &mext, &next);
+        float best = 1e30f;
+        for (int q = 0; q < nc && e == hipSuccess; ++q) {
+          const FoldTile t = list[q];
+          if (mext % t.tm || next % t.tn) continue;
+          float ms = 0.f;
+          e = time_run([&] {
+            return launch_fold(kind, c->prec, F, W1, W2, k.ax, k.p, slabs, sl, rows, EPI_STORE, ep, t,
+                               c->stream);
+          }, ms);
+          if (e == hipSuccess && ms < best) {
+            best = ms;
+            *dst[fi] = t;
+          }
+        }
+      }
+      continue;
+    }
+    for (int form = 0; form < 2 && e == hipSuccess; ++form) {
       float best = 1e30f;
       int bm = 32, bn = 32;
       for (int tm : cand)
         for (int tn : cand) {
-          if (!c->fold && (k.p % tm || k.p % tn)) continue;  // tiles never straddle instances
-          if (c->fold) {
-            const int(*cl)[2] = form == 0 ? kLfwd : form == 1 ? kRfwd : form == 2 ? kLinv : kRinv;
-            const int ncl = (form == 0 || form == 1) ? 5 : 4;
-            bool listed = false;
-            for (int q = 0; q < ncl; ++q) listed = listed || (cl[q][0] == tm && cl[q][1] == tn);
-            const int mext = (form == 1 || form == 3) ? k.p : k.ax.bk;
-            const int next = (form == 1 || form == 3) ? k.ax.bk : k.p;
-            if (!listed || mext % tm || next % tn) continue;
-          }
-          auto run = [&]() {
-            if (c->fold) {
-              switch (form) {
-                case 0:
-                  return launch_fold_left_fwd(c->prec, F, W1, W2, k.ax, k.p, slabs, sl, EPI_STORE,
-                                              ep, tm, tn, c->stream);
-                case 1:
-                  return launch_fold_right_fwd(c->prec, F, W1, W2, k.ax, rows, ep, tm, tn,
-                                               c->stream);
-                case 2:
-                  return launch_fold_left_inv(c->prec, F, W1, W2, k.ax, k.p, slabs, sl, ep, tm, tn,
-                                              c->stream);
-                default:
-                  return launch_fold_right_inv(c->prec, F, W1, W2, k.ax, rows, EPI_STORE, ep, tm,
-                                               tn, c->stream);
-              }
-            }
+          if (k.p % tm || k.p % tn) continue;  // tiles never straddle instances
+          float ms = 0.f;
+          e = time_run([&] {
             return form == 0 ? launch_gemm_left(c->prec, S, W1, W2, k.p, k.p, slabs, sl, EPI_STORE,
                                                 ep, tm, tn, c->stream)
                              : launch_gemm_right(c->prec, S, W1, W2, rows, k.p, EPI_STORE, ep, tm,
                                                  tn, c->stream);
-          };
-          e = run();  // warm-up
-          if (e == hipSuccess) e = hipEventRecord(t0, c->stream);
-          for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run();
-          if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
-          if (e == hipSuccess) e = hipEventSynchronize(t1);
-          float ms = 0.f;
-          if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+          }, ms);
           if (e != hipSuccess) break;
           if (ms < best) {
             best = ms;
@@ -473,15 +479,9 @@ qn_status qnb_autotune(qnb_ctx c) {
       if (form == 0) {
         k.tmL = bm;
         k.tnL = bn;
-      } else if (form == 1) {
+      } else {
         k.tmR = bm;
         k.tnR = bn;
-      } else if (form == 2) {
-        k.tmLi = bm;
-        k.tnLi = bn;
-      } else {
-        k.tmRi = bm;
-        k.tnRi = bn;
       }
     }
   }
@@ -501,7 +501,14 @@ qn_status qnb_class_info(qnb_ctx c, int32_t i, int32_t* info) {
   if (!c || !info) return bad(QN_ERR_INVALID, "null argument");
   if (i < 0 || i >= (int)c->cls.size()) return bad(QN_ERR_INVALID, "class index out of range");
   const Cls& k = c->cls[i];
-  const int32_t v[8] = {k.n, k.ncomp, k.K, k.tmL, k.tnL, k.tmR, k.tnR, k.p};
+  const int32_t v[8] = {k.n,
+                        k.ncomp,
+                        k.K,
+                        c->fold ? k.fL.tm : k.tmL,
+                        c->fold ? k.fL.tn : k.tnL,
+                        c->fold ? k.fR.tm : k.tmR,
+                        c->fold ? k.fR.tn : k.tnR,
+                        k.p};
   std::memcpy(info, v, sizeof v);
   return QN_OK;
 }

@@ -180,6 +180,173 @@ __global__ __launch_bounds__(256, 2) void k_fold_left_fwd(const T* __restrict__ 
   }
 }
 
+// Forward, paired: one tile computes the even spectral rows i and the odd
+// rows bk + i (i in [i0, i0 + TMF)) of the same columns, so the raw rows k and
+// n-1-k are loaded once for both halves:
+//   C[b][i][c]      = sum_{k<ne} FeT[k][i] (B[b][k][c] + B[b][n-1-k][c])
+//   C[b][bk + i][c] = sum_{k<h}  FoT[k][i] (B[b][k][c] - B[b][n-1-k][c])
+// (the centre row k = h of odd n enters the even half alone).
+template <typename T, int TMF, int TN, int EPI>
+__global__ __launch_bounds__(256, 2) void k_fold_left_fwd2(const T* __restrict__ FeT,
+                                                           const T* __restrict__ FoT,
+                                                           const T* __restrict__ B,
+                                                           T* __restrict__ C, FoldAxis ax, int ncols,
+                                                           int batch, long long bstride, EpiArgs ep) {
+  using MF = Mfma<T>;
+  constexpr int TK = MF::TK / 2;
+  constexpr int VE = 16 / sizeof(T);
+  typedef T V __attribute__((ext_vector_type(VE)));
+  constexpr int WM = TMF / 2, WN = TN / 2, BM = WM / 16, BN = WN / 16;
+  constexpr int NA = (TK * TMF / VE + 255) / 256, NB = (TK * TN / VE + 255) / 256;
+  __shared__ __attribute__((aligned(16))) T Ae[2][TK][TMF];
+  __shared__ __attribute__((aligned(16))) T Ao[2][TK][TMF];
+  __shared__ __attribute__((aligned(16))) T Bs[2][TK][TN];
+  __shared__ __attribute__((aligned(16))) T Bd[2][TK][TN];
+
+  const int bk = ax.bk, na = ax.n, h = ax.h;
+  const int MT = bk / TMF, NT = ncols / TN;
+  const int t = xcd_tile(blockIdx.x, batch * MT * NT);
+  const int mt = t % MT, rest = t / MT, nt = rest % NT, b = rest / NT;
+  const int inst = b % ep.inst_mod;
+  if (ep.skip && ep.skip[inst]) return;
+  const int i0 = mt * TMF, n0 = nt * TN;
+  const T* Bb = B + (long long)b * bstride;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+
+  typename MF::v4 acce[BM][BN], acco[BM][BN];
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int j = 0; j < BN; ++j) acce[i][j] = acco[i][j] = typename MF::v4{0, 0, 0, 0};
+
+  V rae[NA], rao[NA], rlo[NB], rhi[NB];
+  int kpre = 0;
+  auto gload = [&](int k0) {
+    kpre = k0;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TK * TMF / VE) {
+        const int kk = v / (TMF / VE), mm = (v % (TMF / VE)) * VE;
+        rae[i] = *reinterpret_cast<const V*>(FeT + (long long)(k0 + kk) * bk + i0 + mm);
+        rao[i] = *reinterpret_cast<const V*>(FoT + (long long)(k0 + kk) * bk + i0 + mm);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TK * TN / VE) {
+        const int kk = v / (TN / VE), nn = (v % (TN / VE)) * VE;
+        const int k = k0 + kk;
+        // rows k and n-1-k (the centre row pairs with itself); clamped for k > h
+        const int kl = k <= h ? k : h, kh = k < h ? na - 1 - k : h;
+        rlo[i] = *reinterpret_cast<const V*>(Bb + (long long)kl * ncols + n0 + nn);
+        rhi[i] = *reinterpret_cast<const V*>(Bb + (long long)kh * ncols + n0 + nn);
+      }
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TK * TMF / VE) {
+        const int kk = v / (TMF / VE), mm = (v % (TMF / VE)) * VE;
+        *reinterpret_cast<V*>(&Ae[buf][kk][mm]) = rae[i];
+        *reinterpret_cast<V*>(&Ao[buf][kk][mm]) = rao[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int v = tid + 256 * i;
+      if (v < TK * TN / VE) {
+        const int kk = v / (TN / VE), nn = (v % (TN / VE)) * VE;
+        const int k = kpre + kk;
+        V sum = V{}, dif = V{};
+        if (k < h) {
+          sum = rlo[i] + rhi[i];
+          dif = rlo[i] - rhi[i];
+        } else if (k == h && ax.odd) {
+          sum = rlo[i];
+        }
+        *reinterpret_cast<V*>(&Bs[buf][kk][nn]) = sum;
+        *reinterpret_cast<V*>(&Bd[buf][kk][nn]) = dif;
+      }
+    }
+  };
+
+  // Fold rows at or beyond ne = h + odd contribute nothing: stop the K loop there.
+  const int kmax = ((h + ax.odd + TK - 1) / TK) * TK;
+  const int nk = kmax / TK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kc = 0; kc < nk; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nk) gload((kc + 1) * TK);
+#pragma unroll
+    for (int ks = 0; ks < TK; ks += 4) {
+      T ae[BM], ao[BM], bs[BN], bd[BN];
+#pragma unroll
+      for (int i = 0; i < BM; ++i) {
+        ae[i] = Ae[buf][ks + (lane >> 4)][wm + 16 * i + (lane & 15)];
+        ao[i] = Ao[buf][ks + (lane >> 4)][wm + 16 * i + (lane & 15)];
+      }
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        bs[j] = Bs[buf][ks + (lane >> 4)][wn + 16 * j + (lane & 15)];
+        bd[j] = Bd[buf][ks + (lane >> 4)][wn + 16 * j + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          acce[i][j] = MF::op(ae[i], bs[j], acce[i][j]);
+          acco[i][j] = MF::op(ao[i], bd[j], acco[i][j]);
+        }
+    }
+    if (kc + 1 < nk) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  T* Cb = C + (long long)b * bstride;
+  double scale = 1.0, beta = 0.0, cn[BN];
+  if (EPI == EPI_DIVIDE) {
+    const double* cf = ep.coef + (long long)inst * ep.coef_stride;
+    scale = cf[0];
+    beta = cf[1];
+#pragma unroll
+    for (int j = 0; j < BN; ++j) {
+      const int n = n0 + wn + 16 * j + (lane & 15);
+      const int ny_ = n / ep.px;
+      cn[j] = ep.lamX[n - ny_ * ep.px] + (ep.lamY ? ep.lamY[ny_] : 0.0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = i0 + wm + 16 * i + MF::row(lane, q);
+      double le = 0.0, lo = 0.0;
+      if (EPI == EPI_DIVIDE) {
+        le = ep.lamM[m];
+        lo = ep.lamM[bk + m];
+      }
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        const int n = n0 + wn + 16 * j + (lane & 15);
+        if (EPI == EPI_DIVIDE) {
+          Cb[(long long)m * ncols + n] = (T)((double)acce[i][j][q] / (scale * (le + cn[j]) + beta));
+          Cb[(long long)(bk + m) * ncols + n] =
+              (T)((double)acco[i][j][q] / (scale * (lo + cn[j]) + beta));
+        } else {
+          Cb[(long long)m * ncols + n] = acce[i][j][q];
+          Cb[(long long)(bk + m) * ncols + n] = acco[i][j][q];
+        }
+      }
+    }
+}
+
 // Inverse, contraction over the split spectral rows, output spatial rows:
 // p[k][c] = sum_{i<bk} Fe[i][k] Y[b][i][c], q[k][c] = sum_{i<bk} Fo[i][k] Y[b][bk+i][c];
 // C[b][k] = p + q, C[b][n-1-k] = p - q (k < h), C[b][h] = p (n odd).
@@ -644,6 +811,29 @@ hipError_t lfwd(const FoldOperands& f, const T* B, T* C, const FoldAxis& ax, int
 }
 
 template <typename T>
+hipError_t lfwd2(const FoldOperands& f, const T* B, T* C, const FoldAxis& ax, int ncols, int batch,
+                 long long bstride, int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st) {
+  const T* FeT = (const T*)f.FeT;
+  const T* FoT = (const T*)f.FoT;
+#define QN_LFWD2(TM_, TN_)                                                                       \
+  if (tm == TM_ && tn == TN_) {                                                                  \
+    const unsigned g = (unsigned)((long long)batch * (ax.bk / TM_) * (ncols / TN_));             \
+    if (epi == EPI_DIVIDE)                                                                       \
+      hipLaunchKernelGGL((k_fold_left_fwd2<T, TM_, TN_, EPI_DIVIDE>), dim3(g), dim3(256), 0, st, \
+                         FeT, FoT, B, C, ax, ncols, batch, bstride, ep);                         \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_fold_left_fwd2<T, TM_, TN_, EPI_STORE>), dim3(g), dim3(256), 0, st,  \
+                         FeT, FoT, B, C, ax, ncols, batch, bstride, ep);                         \
+    return hipGetLastError();                                                                    \
+  }
+  QN_LFWD2(64, 64)
+  QN_LFWD2(128, 64)
+  QN_LFWD2(32, 64)
+#undef QN_LFWD2
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
 hipError_t linv(const FoldOperands& f, const T* Y, T* C, const FoldAxis& ax, int ncols, int batch,
                 long long bstride, const EpiArgs& ep, int tm, int tn, hipStream_t st) {
   const T* Fe = (const T*)f.Fe;
@@ -722,6 +912,15 @@ hipError_t launch_fold_left_fwd(int prec, const FoldOperands& f, const void* B, 
   return lfwd<float>(f, (const float*)B, (float*)C, ax, ncols, batch, bstride, epi, ep, tm, tn, st);
 }
 
+hipError_t launch_fold_left_fwd_paired(int prec, const FoldOperands& f, const void* B, void* C,
+                                       const FoldAxis& ax, int ncols, int batch, long long bstride,
+                                       int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st) {
+  if (prec == 0)
+    return lfwd2<double>(f, (const double*)B, (double*)C, ax, ncols, batch, bstride, epi, ep, tm,
+                         tn, st);
+  return lfwd2<float>(f, (const float*)B, (float*)C, ax, ncols, batch, bstride, epi, ep, tm, tn, st);
+}
+
 hipError_t launch_fold_left_inv(int prec, const FoldOperands& f, const void* Y, void* C,
                                 const FoldAxis& ax, int ncols, int batch, long long bstride,
                                 const EpiArgs& ep, int tm, int tn, hipStream_t st) {
@@ -743,6 +942,61 @@ hipError_t launch_fold_right_inv(int prec, const FoldOperands& f, const void* Y,
   if (prec == 0)
     return rinv<double>(f, (const double*)Y, (double*)C, ax, rows, epi, ep, tm, tn, st);
   return rinv<float>(f, (const float*)Y, (float*)C, ax, rows, epi, ep, tm, tn, st);
+}
+
+namespace {
+const FoldTile kTilesRfwd[] = {{128, 128, 0}, {128, 64, 0}, {64, 64, 0}, {64, 32, 0}, {32, 32, 0}};
+const FoldTile kTilesLfwd[] = {{64, 64, 1},  {128, 128, 0}, {64, 128, 0}, {128, 64, 1},
+                               {64, 64, 0},  {32, 64, 1},   {32, 64, 0},  {32, 32, 0}};
+const FoldTile kTilesLinv[] = {{64, 64, 0}, {64, 128, 0}, {32, 64, 0}, {32, 32, 0}};
+const FoldTile kTilesRinv[] = {{64, 64, 0}, {128, 64, 0}, {64, 32, 0}, {32, 32, 0}};
+}  // namespace
+
+int fold_tiles(int kind, const FoldTile** list) {
+  switch (kind) {
+    case FK_RFWD: *list = kTilesRfwd; return (int)(sizeof kTilesRfwd / sizeof kTilesRfwd[0]);
+    case FK_LFWD: *list = kTilesLfwd; return (int)(sizeof kTilesLfwd / sizeof kTilesLfwd[0]);
+    case FK_LINV: *list = kTilesLinv; return (int)(sizeof kTilesLinv / sizeof kTilesLinv[0]);
+    default: *list = kTilesRinv; return (int)(sizeof kTilesRinv / sizeof kTilesRinv[0]);
+  }
+}
+
+void fold_extents(int kind, int bk, int ncols, int rows, long long* mext, long long* next) {
+  if (kind == FK_RFWD || kind == FK_RINV) {
+    *mext = rows;
+    *next = bk;
+  } else {
+    *mext = bk;
+    *next = ncols;
+  }
+}
+
+long long fold_blocks(int kind, const FoldTile& t, int bk, int ncols, int batch, int rows) {
+  long long mext, next;
+  fold_extents(kind, bk, ncols, rows, &mext, &next);
+  // split forward kernels launch the even and odd halves as separate tiles
+  const long long halves = (kind == FK_RFWD || (kind == FK_LFWD && !t.paired)) ? 2 : 1;
+  const long long nb = (kind == FK_RFWD || kind == FK_RINV) ? 1 : batch;
+  return halves * nb * (mext / t.tm) * (next / t.tn);
+}
+
+hipError_t launch_fold(int kind, int prec, const FoldOperands& f, const void* in, void* out,
+                       const FoldAxis& ax, int ncols, int batch, long long bstride, int rows,
+                       int epi, const EpiArgs& ep, const FoldTile& t, hipStream_t st) {
+  switch (kind) {
+    case FK_RFWD:
+      return launch_fold_right_fwd(prec, f, in, out, ax, rows, ep, t.tm, t.tn, st);
+    case FK_LFWD:
+      if (t.paired)
+        return launch_fold_left_fwd_paired(prec, f, in, out, ax, ncols, batch, bstride, epi, ep,
+                                           t.tm, t.tn, st);
+      return launch_fold_left_fwd(prec, f, in, out, ax, ncols, batch, bstride, epi, ep, t.tm, t.tn,
+                                  st);
+    case FK_LINV:
+      return launch_fold_left_inv(prec, f, in, out, ax, ncols, batch, bstride, ep, t.tm, t.tn, st);
+    default:
+      return launch_fold_right_inv(prec, f, in, out, ax, rows, epi, ep, t.tm, t.tn, st);
+  }
 }
 
 }  // namespace qn
