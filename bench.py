@@ -224,13 +224,15 @@ def main():
     # kernel names per timing key from the tiles in use (launch order: x, y
     # forward, z forward + divide, z and y inverse, x inverse + update)
     def kernel_name(slot, t):
+        # kind: 0 x fwd, 1 y/z fwd, 2 y/z inv, 3 x inv; +4 when the tile is paired
         kind, _, tm, tn = t
-        if kind == 0:
+        base, paired = kind % 4, kind >= 4
+        if base == 0:
             return f"k_fold_right_fwd<double,{tm},{tn}>"
-        if kind in (1, 4):
+        if base == 1:
             epi = "EPI_DIVIDE" if slot == 2 else "EPI_STORE"
-            return f"k_fold_left_fwd{'2' if kind == 4 else ''}<double,{tm},{tn},{epi}>"
-        if kind == 2:
+            return f"k_fold_left_fwd{'2' if paired else ''}<double,{tm},{tn},{epi}>"
+        if base == 2:
             return f"k_fold_left_inv<double,{tm},{tn}>"
         return f"k_fold_right_inv<double,{tm},{tn},EPI_SUB_DENSE>"
     kname = [kernel_name(i, t) for i, t in enumerate(tiles)]

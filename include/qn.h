@@ -178,10 +178,12 @@ qn_status qn_iterate(qn_ctx ctx, double* d_U, const double* d_F, double rtol,
  * (bitwise).  Synchronous.  A no-op for QN_PREC_BF16X3, whose dense
  * transforms use a fixed rule. */
 qn_status qn_autotune(qn_ctx ctx);
-/* Launch i of the solve: info4 = {kind (0 x forward, 1 y/z forward, 2 y/z
- * inverse, 3 x inverse, 4 y/z forward with paired even/odd tiles), axis (0 x,
- * 1 y, 2 z), tile_m, tile_n}.  Requires a bound workspace;
- * QN_ERR_UNSUPPORTED for QN_PREC_BF16X3. */
+/* Launch i of the solve: info4 = {kind, axis (0 x, 1 y, 2 z), tile_m,
+ * tile_n}; kind is 0 x forward, 1 y/z forward, 2 y/z inverse, 3 x inverse,
+ * plus 4 when one tile computes both the even and the odd spectral half
+ * (paired forward tiles; tile_m or tile_n then counts fold indices).
+ * Requires a bound workspace; QN_ERR_UNSUPPORTED for QN_PREC_BF16X3 (dense
+ * transforms). */
 qn_status qn_tile_info(qn_ctx ctx, int32_t i, int32_t* info4);
 
 /* Kernel timing (contexts created with options.timing != 0).  qn_timing_read

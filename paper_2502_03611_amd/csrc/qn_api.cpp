@@ -762,7 +762,7 @@ qn_status qn_tile_info(qn_ctx c, int32_t i, int32_t* info4) {
   const int ns = fold_plan(c, epi_args(c, nullptr, nullptr), EPI_STORE, st);
   if (i < 0 || i >= ns) return fail(QN_ERR_INVALID, "launch index %d out of range [0, %d)", i, ns);
   const FoldTile t = step_tile(c, st[i], i);
-  info4[0] = st[i].kind == FK_LFWD && t.paired ? 4 : st[i].kind;
+  info4[0] = st[i].kind + (t.paired ? 4 : 0);
   info4[1] = st[i].axis;
   info4[2] = t.tm;
   info4[3] = t.tn;

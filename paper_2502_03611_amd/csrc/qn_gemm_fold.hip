@@ -975,7 +975,7 @@ long long fold_blocks(int kind, const FoldTile& t, int bk, int ncols, int batch,
   long long mext, next;
   fold_extents(kind, bk, ncols, rows, &mext, &next);
   // split forward kernels launch the even and odd halves as separate tiles
-  const long long halves = (kind == FK_RFWD || (kind == FK_LFWD && !t.paired)) ? 2 : 1;
+  const long long halves = ((kind == FK_RFWD || kind == FK_LFWD) && !t.paired) ? 2 : 1;
   const long long nb = (kind == FK_RFWD || kind == FK_RINV) ? 1 : batch;
   return halves * nb * (mext / t.tm) * (next / t.tn);
 }

@@ -278,7 +278,7 @@ def test_autotuned_tiles_give_bitwise_identical_solves(kind, shape, prec):
     for kid, axis, tm, tn in tuned.tiles():
         n = list(reversed(shape))[axis]
         bk = 32 * math.ceil(math.ceil(n / 2) / 32)
-        assert bk % (tm if kid in (1, 2, 4) else tn) == 0, (kid, axis, tm, tn)
+        assert bk % (tm if kid % 4 in (1, 2) else tn) == 0, (kid, axis, tm, tn)
     ua, ub = ref.empty().zero_(), tuned.empty().zero_()
     sa = ref.iterate(ua, f, rtol=0.0, max_iter=3)
     sb = tuned.iterate(ub, f, rtol=0.0, max_iter=3)
