@@ -19,6 +19,7 @@
 #include <cfloat>
 
 #include "qn_internal.h"
+#include "qn_mfma.h"
 
 namespace qn {
 
@@ -78,9 +79,16 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
   // Current z-plane of the block's 64 x 16 tile plus a one-point x/y halo.
   __shared__ double s_u[NC][RY + 2][RX + 2];
   const int tx = threadIdx.x, ty = threadIdx.y;
-  const int x = blockIdx.x * RX + tx;
-  const int y = blockIdx.y * RY + ty;
-  const int z0 = blockIdx.z * a.rz;
+  // Workgroups are dealt to the 8 XCDs round-robin in launch order; remapped,
+  // each XCD walks a contiguous range of tiles (x fastest), so the halo lines
+  // a tile shares with its x and y neighbours are fetched once into that
+  // XCD's L2 instead of once per neighbour.
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int tile = xcd_tile((blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x, gx * gy * gridDim.z);
+  const int bx = tile % gx, by = (tile / gx) % gy, bz = tile / (gx * gy);
+  const int x = bx * RX + tx;
+  const int y = by * RY + ty;
+  const int z0 = bz * a.rz;
   const int z1 = min(z0 + a.rz, a.oz);
   if (a.skip && a.skip[z0]) return;  // batched solver: finished instance (rz = 1)
   const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -209,8 +217,7 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
 
   block_reduce4<RX * RY / 64>(s_r, mn, mx, s_f);
   if (threadIdx.x == 0 && threadIdx.y == 0) {
-    const long long bid = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    double* pp = a.partials + 4 * bid;
+    double* pp = a.partials + 4LL * tile;  // tile = (bz * gy + by) * gx + bx
     pp[0] = s_r;
     pp[1] = mn;
     pp[2] = mx;
