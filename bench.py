@@ -307,7 +307,7 @@ def main():
         ttt = {}
         u64 = None
         solver.close()
-        for prec in ("fp64", "fp32", "bf16x3"):
+        for prec in ("fp64", "fp32", "bf16x3", "bf16x6"):
             log(f"time to tolerance: {prec}")
             s = Solver(shape, "quasilinear", beta=0.0, precision=prec)
             s.autotune()
@@ -332,6 +332,7 @@ def main():
         out["time_to_tol"] = ttt
         out["speedup_fp32_vs_fp64"] = round(ttt["fp64"]["time_to_tol_s"] / ttt["fp32"]["time_to_tol_s"], 3)
         out["speedup_bf16x3_vs_fp64"] = round(ttt["fp64"]["time_to_tol_s"] / ttt["bf16x3"]["time_to_tol_s"], 3)
+        out["speedup_bf16x6_vs_fp64"] = round(ttt["fp64"]["time_to_tol_s"] / ttt["bf16x6"]["time_to_tol_s"], 3)
 
     solver.close()
     del U, F

@@ -38,7 +38,9 @@
  * Precision (transforms only; residual, norms, shift rule and the update are
  * always FP64): QN_PREC_FP64 (FP64 MFMA), QN_PREC_FP32 (FP32 MFMA),
  * QN_PREC_BF16X3 (each operand split into bf16 hi + lo parts, three bf16 MFMA
- * products hi*hi + hi*lo + lo*hi accumulated in FP32).
+ * products hi*hi + hi*lo + lo*hi accumulated in FP32), QN_PREC_BF16X6 (three
+ * bf16 parts, the six part products of combined order below 3; FP32-level
+ * accuracy on the bf16 matrix cores).
  *
  * Ownership: the library never allocates or frees device memory.  The caller
  * queries qn_workspace_bytes, allocates that many bytes of device memory
@@ -81,7 +83,12 @@ typedef enum {
 } qn_status;
 
 typedef enum { QN_NL_CUBIC = 0, QN_NL_QUASILIN = 1, QN_NL_SYS2_CUBIC = 2 } qn_nonlinearity;
-typedef enum { QN_PREC_FP64 = 0, QN_PREC_FP32 = 1, QN_PREC_BF16X3 = 2 } qn_precision;
+typedef enum {
+  QN_PREC_FP64 = 0,
+  QN_PREC_FP32 = 1,
+  QN_PREC_BF16X3 = 2,
+  QN_PREC_BF16X6 = 3
+} qn_precision;
 typedef enum { QN_BETA_FIXED = 0, QN_BETA_MIDPOINT = 1 } qn_beta_mode;
 
 /* dim: 2 or 3.  n[0] = nx, n[1] = ny, n[2] = nz (ignored when dim = 2);
@@ -175,15 +182,15 @@ qn_status qn_iterate(qn_ctx ctx, double* d_U, const double* d_F, double rtol,
  * of every launch on the bound workspace (its transform tensors are
  * overwritten; the x inverse is timed with a plain store) and keeps the
  * fastest for all later calls.  Results do not depend on the tile shapes
- * (bitwise).  Synchronous.  A no-op for QN_PREC_BF16X3, whose dense
- * transforms use a fixed rule. */
+ * (bitwise).  Synchronous.  A no-op for the split-bf16 precisions, whose
+ * dense transforms use a fixed rule. */
 qn_status qn_autotune(qn_ctx ctx);
 /* Launch i of the solve: info4 = {kind, axis (0 x, 1 y, 2 z), tile_m,
  * tile_n}; kind is 0 x forward, 1 y/z forward, 2 y/z inverse, 3 x inverse,
  * plus 4 when one tile computes both the even and the odd spectral half
  * (paired forward tiles; tile_m or tile_n then counts fold indices).
- * Requires a bound workspace; QN_ERR_UNSUPPORTED for QN_PREC_BF16X3 (dense
- * transforms). */
+ * Requires a bound workspace; QN_ERR_UNSUPPORTED for the split-bf16
+ * precisions (dense transforms). */
 qn_status qn_tile_info(qn_ctx ctx, int32_t i, int32_t* info4);
 
 /* Kernel timing (contexts created with options.timing != 0).  qn_timing_read

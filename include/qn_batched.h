@@ -47,7 +47,8 @@ typedef struct {
 } qnb_result;
 
 /* count instances (1..65536); n[i] interior points per side (1..4096);
- * ncomp[i] in {1, 2}; precision: qn_precision of the transforms; beta_mode
+ * ncomp[i] in {1, 2}; precision: qn_precision of the transforms (FP64, FP32
+ * or BF16X3; QN_PREC_BF16X6 is rejected with QN_ERR_INVALID); beta_mode
  * and beta as in qn_setup (applied to every instance).  Host only. */
 qn_status qnb_setup(int32_t count, const int32_t* n, const int32_t* ncomp, int32_t precision,
                     int32_t beta_mode, double beta, qnb_ctx* out);

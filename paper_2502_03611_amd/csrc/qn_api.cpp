@@ -57,9 +57,10 @@ const char* const kKernelNames[K_COUNT] = {"residual",    "finalize",      "gemm
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-int pick_tile(long long extent) {
-  if (extent % 128 == 0) return 128;
-  if (extent % 64 == 0) return 64;
+// Largest tile side (up to cap) dividing a padded extent (a multiple of 32).
+int pick_tile(long long extent, int cap) {
+  if (cap >= 128 && extent % 128 == 0) return 128;
+  if (cap >= 64 && extent % 64 == 0) return 64;
   return 32;
 }
 
@@ -90,13 +91,13 @@ struct qn_ctx_s {
   double beta = 0.0;
   double lam_min_sum = 0.0;
   hipStream_t stream = nullptr;
-  bool fold = true;       // reflection-folded transforms (FP64/FP32); dense for bf16x3
+  bool fold = true;       // reflection-folded transforms (FP64/FP32); dense for split-bf16
   FoldAxis ax[3] = {};
   FoldTile tile[6] = {};  // per mode-product launch of the folded solve (after qn_autotune)
   bool tuned = false;
   std::vector<double> hS[3], hlam[3];  // dense S or folded FeT|FoT|Fe|Fo; lam (split if folded)
   // workspace layout (byte offsets)
-  size_t off_S[3] = {0, 0, 0}, off_Slo[3] = {0, 0, 0}, off_lam[3] = {0, 0, 0};
+  size_t off_S[3] = {0, 0, 0}, off_Slo[3] = {0, 0, 0}, off_Slo2[3] = {0, 0, 0}, off_lam[3] = {0, 0, 0};
   size_t off_W1 = 0, off_W2 = 0, off_part = 0, off_scal = 0, off_coef = 0, need = 0;
   int max_blocks = 0;
   char* ws = nullptr;
@@ -149,11 +150,11 @@ hipError_t timed(qn_ctx c, int kid, Fn fn) {
   if (c->timing) {
     a = take_event(c);
     b = take_event(c);
-    if (a) hipEventRecord(a, c->stream);
+    if (a) (void)hipEventRecord(a, c->stream);
   }
   hipError_t e = fn();
   if (c->timing && a && b) {
-    hipEventRecord(b, c->stream);
+    (void)hipEventRecord(b, c->stream);
     c->pending.push_back({kid, a, b});
   }
   return e;
@@ -228,12 +229,9 @@ struct FoldStep {
 
 GemmOperands operands(qn_ctx c, int axis) {
   GemmOperands g{};
-  if (c->prec == QN_PREC_BF16X3) {
-    g.Shi = c->ws + c->off_S[axis];
-    g.Slo = c->ws + c->off_Slo[axis];
-  } else {
-    g.S = c->ws + c->off_S[axis];
-  }
+  g.Shi = c->ws + c->off_S[axis];
+  g.Slo = c->ws + c->off_Slo[axis];
+  g.Slo2 = c->ws + c->off_Slo2[axis];
   return g;
 }
 
@@ -367,8 +365,9 @@ hipError_t solve_ws(qn_ctx c, const double* coef, double* dense, int epi_last) {
     return hipSuccess;
   }
   const GemmOperands Sx = operands(c, 0), Sy = operands(c, 1), Sz = operands(c, 2);
-  const int tmx = pick_tile(rows), tnx = pick_tile(px);
-  const int tmy = pick_tile(py), tny = pick_tile(px);
+  const int cap = gemm_bf_max_tile(pr);
+  const int tmx = pick_tile(rows, cap), tnx = pick_tile(px, cap);
+  const int tmy = pick_tile(py, cap), tny = pick_tile(px, cap);
   const long long yslab = (long long)py * px;
   hipError_t e;
 #define QN_TRY(x)               \
@@ -394,7 +393,7 @@ hipError_t solve_ws(qn_ctx c, const double* coef, double* dense, int epi_last) {
     }));
   } else {
     const long long zslab = (long long)pz * py * px;
-    const int tmz = pick_tile(pz), tnz = pick_tile(yslab);
+    const int tmz = pick_tile(pz, cap), tnz = pick_tile(yslab, cap);
     QN_TRY(timed(c, K_GEMM_YZ, [&] {
       return launch_gemm_left(pr, Sy, W2, W1, py, px, c->ncomp * pz, yslab, EPI_STORE, ep, tmy,
                               tny, c->stream);
@@ -441,7 +440,7 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
                 want_comp);
   qn_options o{};
   if (opt) o = *opt;
-  if (o.precision < 0 || o.precision > 2) return fail(QN_ERR_INVALID, "unknown precision");
+  if (o.precision < 0 || o.precision > 3) return fail(QN_ERR_INVALID, "unknown precision");
   if (o.beta_mode < 0 || o.beta_mode > 1) return fail(QN_ERR_INVALID, "unknown beta_mode");
   if (nonlinearity == QN_NL_QUASILIN && o.beta_mode == QN_BETA_MIDPOINT)
     return fail(QN_ERR_INVALID, "the quasi-linear problem uses the coefficient midpoint rule "
@@ -460,7 +459,7 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   c->n[0] = grid->n[0];
   c->n[1] = grid->n[1];
   c->n[2] = grid->dim == 3 ? grid->n[2] : 1;
-  c->fold = c->prec != QN_PREC_BF16X3;
+  c->fold = c->prec == QN_PREC_FP64 || c->prec == QN_PREC_FP32;
   c->lam_min_sum = 0.0;
   for (int a = 0; a < 3; ++a) {
     if (a >= c->dim) {
@@ -494,9 +493,13 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
     const size_t eb = c->prec == QN_PREC_FP64 ? 8 : (c->prec == QN_PREC_FP32 ? 4 : 2);
     c->off_S[a] = off;
     off += align256(pp * eb);
-    if (c->prec == QN_PREC_BF16X3) {
+    if (!c->fold) {  // further bf16 parts
       c->off_Slo[a] = off;
       off += align256(pp * 2);
+      if (c->prec == QN_PREC_BF16X6) {
+        c->off_Slo2[a] = off;
+        off += align256(pp * 2);
+      }
     }
     c->off_lam[a] = off;
     off += align256((size_t)c->p[a] * 8);
@@ -504,6 +507,7 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   if (c->dim == 2) {  // unused z axis aliases y (never read)
     c->off_S[2] = c->off_S[1];
     c->off_Slo[2] = c->off_Slo[1];
+    c->off_Slo2[2] = c->off_Slo2[1];
     c->off_lam[2] = c->off_lam[1];
     c->ax[2] = c->ax[1];
   }
@@ -550,17 +554,22 @@ qn_status qn_bind_workspace(qn_ctx c, void* d_ws, size_t bytes) {
       e = hipMemcpyAsync(c->ws + c->off_S[a], s32.data(), pp * 4, hipMemcpyHostToDevice, c->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // s32 is a host temporary
     } else {
-      std::vector<uint16_t> hi(pp), lo(pp);
+      // S = s0 + s1 (+ s2), each part the RNE bf16 of what the previous ones leave
+      const int np = c->prec == QN_PREC_BF16X6 ? 3 : 2;
+      std::vector<uint16_t> parts[3];
+      for (int q = 0; q < np; ++q) parts[q].resize(pp);
       for (size_t i = 0; i < pp; ++i) {
-        const double v = c->hS[a][i];
-        hi[i] = bf16_rne((float)v);
-        lo[i] = bf16_rne((float)(v - (double)bf16_value(hi[i])));
+        float r = (float)c->hS[a][i];
+        for (int q = 0; q < np; ++q) {
+          parts[q][i] = bf16_rne(r);
+          r -= bf16_value(parts[q][i]);
+        }
       }
-      e = hipMemcpyAsync(c->ws + c->off_S[a], hi.data(), pp * 2, hipMemcpyHostToDevice, c->stream);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(c->ws + c->off_Slo[a], lo.data(), pp * 2, hipMemcpyHostToDevice,
+      const size_t offs[3] = {c->off_S[a], c->off_Slo[a], c->off_Slo2[a]};
+      for (int q = 0; q < np && e == hipSuccess; ++q)
+        e = hipMemcpyAsync(c->ws + offs[q], parts[q].data(), pp * 2, hipMemcpyHostToDevice,
                            c->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // host temporaries
     }
     if (e == hipSuccess)
       e = hipMemcpyAsync(c->ws + c->off_lam[a], c->hlam[a].data(), (size_t)c->p[a] * 8,
@@ -745,8 +754,8 @@ qn_status qn_autotune(qn_ctx c) {
       }
     }
   }
-  if (t0) hipEventDestroy(t0);
-  if (t1) hipEventDestroy(t1);
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
   if (e != hipSuccess) return hip_fail(c, e, "autotune");
   for (int i = 0; i < 6; ++i) c->tile[i] = best[i];
   c->tuned = true;
@@ -794,9 +803,9 @@ qn_status qn_timing_reset(qn_ctx c) {
 
 void qn_destroy(qn_ctx c) {
   if (!c) return;
-  if (!c->pending.empty()) hipStreamSynchronize(c->stream);
+  if (!c->pending.empty()) (void)hipStreamSynchronize(c->stream);
   for (auto& p : c->pending) {
-    hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.a);
     hipEventDestroy(p.b);
   }
   for (auto e : c->pool) hipEventDestroy(e);

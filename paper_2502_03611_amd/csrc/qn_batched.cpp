@@ -57,7 +57,7 @@ struct Cls {
 
 struct qnb_ctx_s {
   int count = 0, prec = 0, beta_mode = 0;
-  bool fold = true;  // reflection-folded transforms (FP64/FP32); dense for bf16x3
+  bool fold = true;  // reflection-folded transforms (FP64/FP32); dense for split-bf16
   double beta = 0.0;
   std::vector<int> n, ncomp, inst_cls, inst_pos;
   std::vector<Cls> cls;
@@ -97,16 +97,11 @@ FoldOperands fops(qnb_ctx c, const Cls& k) {
   return f;
 }
 
-// Instantiated tile shapes of the folded kernels (see qn_gemm_fold.hip).
-
+// bf16 parts of S for the dense split-bf16 transforms.
 GemmOperands ops(qnb_ctx c, const Cls& k) {
   GemmOperands g{};
-  if (c->prec == QN_PREC_BF16X3) {
-    g.Shi = c->ws + k.off_S;
-    g.Slo = c->ws + k.off_Slo;
-  } else {
-    g.S = c->ws + k.off_S;
-  }
+  g.Shi = c->ws + k.off_S;
+  g.Slo = c->ws + k.off_Slo;
   return g;
 }
 

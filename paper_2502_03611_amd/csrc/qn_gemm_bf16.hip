@@ -1,63 +1,91 @@
-// Split-bf16 mode products ("bf16x3"): each FP32 operand x is split into
-// bf16 parts x = hi + lo (hi = RNE(x), lo = RNE(x - hi)) and the product is
-// formed from three bf16 matrix-core products hi*hi + hi*lo + lo*hi
-// accumulated in FP32 (the lo*lo term, of relative size 2^-16 * 2^-16, is
-// dropped).  The 1D eigenvector matrix is split once at setup; the tensor
-// operand is split while it is staged into LDS.  Same two forms, tiling,
-// XCD-aware tile order and epilogues as the FP64/FP32 kernels.
+// Split-bf16 mode products of the tensor-product solve (Section 4.1,
+// eq. fin_inverse) on the bf16 matrix cores, with the spectral divide and the
+// quasi-Newton update fused into the epilogues.  The FP64 and FP32 forms use
+// the reflection-folded kernels of qn_gemm_fold.hip.
 //
+// Every FP32 operand x is split into NP bf16 parts, x ~ x0 + x1 (+ x2),
+// x0 = RNE(x), x1 = RNE(x - x0), x2 = RNE(x - x0 - x1), and a product keeps
+// the part products x_i y_j with i + j < NP, accumulated in FP32 from the
+// smallest terms up:
+//   NP = 2 ("bf16x3"): x1 y0 + x0 y1 + x0 y0          (dropped: 2^-16 relative)
+//   NP = 3 ("bf16x6"): x2 y0 + x0 y2 + x1 y1 + x1 y0 + x0 y1 + x0 y0
+//                                                      (dropped: 2^-24 relative)
+// The 1D eigenvector matrix S is split once at setup; the tensor operand is
+// split while it is staged into LDS.
+//
+// Two forms cover the three axes of a C-order (.., z, y, x) tensor:
+//   form L  C[b][m][n] = sum_k S[m][k] B[b][k][n]   (y and z products; B rows
+//           are contiguous in n, b runs over the batch of slabs)
+//   form R  C[r][n]    = sum_k A[r][k] S[k][n]      (x product; A rows are the
+//           x-lines of the tensor, contiguous in k)
+// S is P x P (P = padded axis length, a multiple of 32), symmetric and zero
+// outside the N x N block, so padded rows and columns stay exactly zero.
+//
+// Work decomposition: a 256-thread workgroup (four wave64s in a 2 x 2 grid)
+// owns a TM x TN output tile and walks K in chunks of 32 (one matrix-core
+// step), double-buffered in LDS with one barrier per chunk.
 // v_mfma_f32_16x16x32_bf16 takes, per lane, 8 consecutive k values of one row
 // of A (row = lane % 16, k = 8 * (lane / 16) ..) and of one column of B, so
-// both operands are staged in LDS with k contiguous: [m][k] and [n][k], rows
-// padded to 40 elements (80 bytes) so that 16 lanes reading 16 rows hit
-// distinct 16-byte bank groups.
+// both operands are staged with k contiguous, [m][k] and [n][k], rows padded
+// to 40 elements (80 bytes) so that 16 lanes reading 16 rows hit distinct
+// 16-byte bank groups.  Each XCD (workgroups are dealt round-robin) walks a
+// contiguous range of tiles, so operand panels are reused in its L2.
 
 #include "qn_internal.h"
+#include "qn_mfma.h"
 
 namespace qn {
+
+namespace {
 
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
-__device__ inline void split2(float x, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)x;
-  lo = (__bf16)(x - (float)hi);
+constexpr int BTK = 32;  // k per chunk = one matrix-core step
+constexpr int BKP = 40;  // padded LDS row length (bf16 elements)
+
+template <int NP>
+__device__ inline void split(float x, __bf16 (&p)[NP]) {
+  p[0] = (__bf16)x;
+  const float r = x - (float)p[0];
+  p[1] = (__bf16)r;
+  if constexpr (NP > 2) p[2] = (__bf16)(r - (float)p[1]);
 }
 
-__device__ inline f4_t mfma3(const bf8_t& ah, const bf8_t& al, const bf8_t& bh, const bf8_t& bl,
-                             f4_t c) {
-  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+// sum over part pairs i + j < NP, smallest terms first
+template <int NP>
+__device__ inline f4_t mfma_split(const bf8_t (&a)[NP], const bf8_t (&b)[NP], f4_t c) {
+  if constexpr (NP == 3) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], c, 0, 0, 0);
+  }
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], c, 0, 0, 0);
   return c;
 }
 
-__device__ inline int bf_tile(int w, int total) {
-  return (total % 8 == 0) ? (w % 8) * (total / 8) + (w / 8) : w;
+__device__ inline const __bf16* part(const GemmOperands& s, int i) {
+  return (const __bf16*)(i == 0 ? s.Shi : i == 1 ? s.Slo : s.Slo2);
 }
 
-constexpr int BTK = 32;  // k per chunk = one MFMA k-step
-constexpr int BKP = 40;  // padded LDS row length (bf16 elements)
+}  // namespace
 
-template <int TM, int TN, int EPI>
-__global__ __launch_bounds__(256, 2) void k_gemm_left_bf3(const __bf16* __restrict__ Shi,
-                                                          const __bf16* __restrict__ Slo,
-                                                          const float* __restrict__ B,
-                                                          float* __restrict__ C, int M, int ncols,
-                                                          int batch, long long bstride,
-                                                          EpiArgs ep) {
+template <int NP, int TM, int TN, int EPI>
+__global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const float* __restrict__ B,
+                                                         float* __restrict__ C, int M, int ncols,
+                                                         int batch, long long bstride, EpiArgs ep) {
   constexpr int WM = TM / 2, WN = TN / 2, BM = WM / 16, BN = WN / 16;
-  constexpr int NAV = TM * (BTK / 8);        // 16-byte vectors per A part
-  constexpr int NBV = (BTK / 4) * (TN / 4);  // (4 rows x 4 cols) B blocks
+  constexpr int NAV = TM * (BTK / 8);        // 16-byte vectors per S part
+  constexpr int NBV = (BTK / 4) * (TN / 4);  // (4 rows x 4 cols) tensor blocks
   constexpr int PA = (NAV + 255) / 256, PB = (NBV + 255) / 256;
-  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][TM][BKP];
-  __shared__ __attribute__((aligned(16))) __bf16 Al[2][TM][BKP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][TN][BKP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bl[2][TN][BKP];
+  __shared__ __attribute__((aligned(16))) __bf16 As[NP][2][TM][BKP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[NP][2][TN][BKP];
 
   const int MT = M / TM, NT = ncols / TN;
-  const int t = bf_tile(blockIdx.x, batch * MT * NT);
+  const int t = xcd_tile(blockIdx.x, batch * MT * NT);
   const int mt = t % MT, rest = t / MT, nt = rest % NT, b = rest / NT;
   const int inst = b % ep.inst_mod;
   if (ep.skip && ep.skip[inst]) return;  // whole workgroup: finished instance
@@ -72,7 +100,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf3(const __bf16* __restri
 #pragma unroll
     for (int j = 0; j < BN; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
 
-  bf8_t rah[PA], ral[PA];
+  bf8_t ra[NP][PA];
   f4_t rb[PB][4];
   auto gload = [&](int k0) {
 #pragma unroll
@@ -82,8 +110,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf3(const __bf16* __restri
         const int m = v / (BTK / 8), kv = (v % (BTK / 8)) * 8;
         // S[m][k] with S symmetric: row m, 8 consecutive k.
         const long long off = (long long)(m0 + m) * M + k0 + kv;
-        rah[p] = *reinterpret_cast<const bf8_t*>(Shi + off);
-        ral[p] = *reinterpret_cast<const bf8_t*>(Slo + off);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) ra[q][p] = *reinterpret_cast<const bf8_t*>(part(S, q) + off);
       }
     }
 #pragma unroll
@@ -103,8 +131,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf3(const __bf16* __restri
       const int v = tid + 256 * p;
       if (v < NAV) {
         const int m = v / (BTK / 8), kv = (v % (BTK / 8)) * 8;
-        *reinterpret_cast<bf8_t*>(&Ah[buf][m][kv]) = rah[p];
-        *reinterpret_cast<bf8_t*>(&Al[buf][m][kv]) = ral[p];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) *reinterpret_cast<bf8_t*>(&As[q][buf][m][kv]) = ra[q][p];
       }
     }
 #pragma unroll
@@ -114,16 +142,16 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf3(const __bf16* __restri
         const int g = v / (TN / 4), nq = (v % (TN / 4)) * 4;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          bf4_t h, l;
+          bf4_t w[NP];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            __bf16 hh, ll;
-            split2(rb[p][r][e], hh, ll);
-            h[r] = hh;
-            l[r] = ll;
+            __bf16 x[NP];
+            split<NP>(rb[p][r][e], x);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) w[q][r] = x[q];
           }
-          *reinterpret_cast<bf4_t*>(&Bh[buf][nq + e][4 * g]) = h;
-          *reinterpret_cast<bf4_t*>(&Bl[buf][nq + e][4 * g]) = l;
+#pragma unroll
+          for (int q = 0; q < NP; ++q) *reinterpret_cast<bf4_t*>(&Bs[q][buf][nq + e][4 * g]) = w[q];
         }
       }
     }
@@ -137,18 +165,20 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf3(const __bf16* __restri
     const int buf = kc & 1;
     if (kc + 1 < nk) gload((kc + 1) * BTK);
     const int ko = 8 * (lane >> 4);
-    bf8_t ah[BM], al[BM];
+    bf8_t a[BM][NP];
 #pragma unroll
-    for (int i = 0; i < BM; ++i) {
-      ah[i] = *reinterpret_cast<const bf8_t*>(&Ah[buf][wm + 16 * i + (lane & 15)][ko]);
-      al[i] = *reinterpret_cast<const bf8_t*>(&Al[buf][wm + 16 * i + (lane & 15)][ko]);
-    }
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int q = 0; q < NP; ++q)
+        a[i][q] = *reinterpret_cast<const bf8_t*>(&As[q][buf][wm + 16 * i + (lane & 15)][ko]);
 #pragma unroll
     for (int j = 0; j < BN; ++j) {
-      const bf8_t bh = *reinterpret_cast<const bf8_t*>(&Bh[buf][wn + 16 * j + (lane & 15)][ko]);
-      const bf8_t bl = *reinterpret_cast<const bf8_t*>(&Bl[buf][wn + 16 * j + (lane & 15)][ko]);
+      bf8_t bj[NP];
 #pragma unroll
-      for (int i = 0; i < BM; ++i) acc[i][j] = mfma3(ah[i], al[i], bh, bl, acc[i][j]);
+      for (int q = 0; q < NP; ++q)
+        bj[q] = *reinterpret_cast<const bf8_t*>(&Bs[q][buf][wn + 16 * j + (lane & 15)][ko]);
+#pragma unroll
+      for (int i = 0; i < BM; ++i) acc[i][j] = mfma_split<NP>(a[i], bj, acc[i][j]);
     }
     if (kc + 1 < nk) lstore(buf ^ 1);
     __syncthreads();
@@ -179,23 +209,19 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf3(const __bf16* __restri
       }
 }
 
-template <int TM, int TN, int EPI>
-__global__ __launch_bounds__(256, 2) void k_gemm_right_bf3(const float* __restrict__ A,
-                                                           const __bf16* __restrict__ Shi,
-                                                           const __bf16* __restrict__ Slo,
-                                                           float* __restrict__ C, int rows, int K,
-                                                           EpiArgs ep) {
+template <int NP, int TM, int TN, int EPI>
+__global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const float* __restrict__ A,
+                                                          GemmOperands S, float* __restrict__ C,
+                                                          int rows, int K, EpiArgs ep) {
   constexpr int WM = TM / 2, WN = TN / 2, BM = WM / 16, BN = WN / 16;
   constexpr int NAV = TM * (BTK / 8);  // (row, 8 consecutive k) groups of the tensor chunk
   constexpr int NBV = TN * (BTK / 8);  // 16-byte vectors per S part
   constexpr int PA = (NAV + 255) / 256, PB = (NBV + 255) / 256;
-  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][TM][BKP];
-  __shared__ __attribute__((aligned(16))) __bf16 Al[2][TM][BKP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][TN][BKP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bl[2][TN][BKP];
+  __shared__ __attribute__((aligned(16))) __bf16 As[NP][2][TM][BKP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[NP][2][TN][BKP];
 
   const int MT = rows / TM, NT = K / TN;
-  const int t = bf_tile(blockIdx.x, MT * NT);
+  const int t = xcd_tile(blockIdx.x, MT * NT);
   const int nt = t % NT, mt = t / NT;
   const int r0 = mt * TM, n0 = nt * TN;
   if (ep.skip && ep.skip[(r0 / ep.py / ep.pz) % ep.inst_mod]) return;  // finished instance
@@ -209,7 +235,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf3(const float* __restri
     for (int j = 0; j < BN; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
 
   f4_t ra[PA][2];
-  bf8_t rbh[PB], rbl[PB];
+  bf8_t rb[NP][PB];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int p = 0; p < PA; ++p) {
@@ -228,8 +254,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf3(const float* __restri
         const int n = v / (BTK / 8), kv = (v % (BTK / 8)) * 8;
         // S[k][n] = S[n][k]: row n, 8 consecutive k.
         const long long off = (long long)(n0 + n) * K + k0 + kv;
-        rbh[p] = *reinterpret_cast<const bf8_t*>(Shi + off);
-        rbl[p] = *reinterpret_cast<const bf8_t*>(Slo + off);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) rb[q][p] = *reinterpret_cast<const bf8_t*>(part(S, q) + off);
       }
     }
   };
@@ -239,16 +265,16 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf3(const float* __restri
       const int v = tid + 256 * p;
       if (v < NAV) {
         const int r = v / (BTK / 8), kv = (v % (BTK / 8)) * 8;
-        bf8_t h, l;
+        bf8_t w[NP];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          __bf16 hh, ll;
-          split2(ra[p][e >> 2][e & 3], hh, ll);
-          h[e] = hh;
-          l[e] = ll;
+          __bf16 x[NP];
+          split<NP>(ra[p][e >> 2][e & 3], x);
+#pragma unroll
+          for (int q = 0; q < NP; ++q) w[q][e] = x[q];
         }
-        *reinterpret_cast<bf8_t*>(&Ah[buf][r][kv]) = h;
-        *reinterpret_cast<bf8_t*>(&Al[buf][r][kv]) = l;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) *reinterpret_cast<bf8_t*>(&As[q][buf][r][kv]) = w[q];
       }
     }
 #pragma unroll
@@ -256,8 +282,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf3(const float* __restri
       const int v = tid + 256 * p;
       if (v < NBV) {
         const int n = v / (BTK / 8), kv = (v % (BTK / 8)) * 8;
-        *reinterpret_cast<bf8_t*>(&Bh[buf][n][kv]) = rbh[p];
-        *reinterpret_cast<bf8_t*>(&Bl[buf][n][kv]) = rbl[p];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) *reinterpret_cast<bf8_t*>(&Bs[q][buf][n][kv]) = rb[q][p];
       }
     }
   };
@@ -270,123 +296,148 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf3(const float* __restri
     const int buf = kc & 1;
     if (kc + 1 < nk) gload((kc + 1) * BTK);
     const int ko = 8 * (lane >> 4);
-    bf8_t ah[BM], al[BM];
+    bf8_t a[BM][NP];
 #pragma unroll
-    for (int i = 0; i < BM; ++i) {
-      ah[i] = *reinterpret_cast<const bf8_t*>(&Ah[buf][wm + 16 * i + (lane & 15)][ko]);
-      al[i] = *reinterpret_cast<const bf8_t*>(&Al[buf][wm + 16 * i + (lane & 15)][ko]);
-    }
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int q = 0; q < NP; ++q)
+        a[i][q] = *reinterpret_cast<const bf8_t*>(&As[q][buf][wm + 16 * i + (lane & 15)][ko]);
 #pragma unroll
     for (int j = 0; j < BN; ++j) {
-      const bf8_t bh = *reinterpret_cast<const bf8_t*>(&Bh[buf][wn + 16 * j + (lane & 15)][ko]);
-      const bf8_t bl = *reinterpret_cast<const bf8_t*>(&Bl[buf][wn + 16 * j + (lane & 15)][ko]);
+      bf8_t bj[NP];
 #pragma unroll
-      for (int i = 0; i < BM; ++i) acc[i][j] = mfma3(ah[i], al[i], bh, bl, acc[i][j]);
+      for (int q = 0; q < NP; ++q)
+        bj[q] = *reinterpret_cast<const bf8_t*>(&Bs[q][buf][wn + 16 * j + (lane & 15)][ko]);
+#pragma unroll
+      for (int i = 0; i < BM; ++i) acc[i][j] = mfma_split<NP>(a[i], bj, acc[i][j]);
     }
     if (kc + 1 < nk) lstore(buf ^ 1);
     __syncthreads();
   }
 
 #pragma unroll
-  for (int i = 0; i < BM; ++i)
+  for (int i = 0; i < BM; ++i) {
+    // Row bases of this fragment row block; for U -= dU every old value of the
+    // block is loaded before the first store, so the loads overlap instead of
+    // each waiting behind the previous store to the same array.
+    long long base[4];
+    bool row_ok[4];
 #pragma unroll
-    for (int j = 0; j < BN; ++j)
+    for (int q = 0; q < 4; ++q) {
+      const int r = r0 + wm + 16 * i + 4 * (lane >> 4) + q;
+      base[q] = (long long)r * K;
+      row_ok[q] = true;
+      if (EPI != EPI_STORE) {
+        const int y = r % ep.py, zc = r / ep.py, z = zc % ep.pz, c = zc / ep.pz;
+        base[q] = (((long long)c * ep.nz + z) * ep.ny + y) * ep.nx;
+        row_ok[q] = y < ep.ny && z < ep.nz;
+      }
+    }
+    double old[4][BN];
+    if (EPI == EPI_SUB_DENSE) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = r0 + wm + 16 * i + 4 * (lane >> 4) + q;
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          const int n = n0 + wn + 16 * j + (lane & 15);
+          old[q][j] = (row_ok[q] && n < ep.nx) ? ep.dense[base[q] + n] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
         const int n = n0 + wn + 16 * j + (lane & 15);
         const float v = acc[i][j][q];
         if (EPI == EPI_STORE) {
-          C[(long long)r * K + n] = v;
-        } else {
-          const int y = r % ep.py, zc = r / ep.py, z = zc % ep.pz, c = zc / ep.pz;
-          if (n < ep.nx && y < ep.ny && z < ep.nz) {
-            const long long idx = (((long long)c * ep.nz + z) * ep.ny + y) * ep.nx + n;
-            if (EPI == EPI_SUB_DENSE)
-              ep.dense[idx] -= (double)v;
-            else
-              ep.dense[idx] = (double)v;
-          }
+          C[base[q] + n] = v;
+        } else if (row_ok[q] && n < ep.nx) {
+          if (EPI == EPI_SUB_DENSE)
+            ep.dense[base[q] + n] = old[q][j] - (double)v;
+          else
+            ep.dense[base[q] + n] = (double)v;
         }
       }
+  }
 }
 
-template <int TM, int TN>
-static hipError_t bl_tn(const GemmOperands& s, const float* B, float* C, int M, int ncols,
-                        int batch, long long bstride, int epi, const EpiArgs& ep, hipStream_t st) {
-  const long long tiles = (long long)batch * (M / TM) * (ncols / TN);
-  const __bf16* hi = (const __bf16*)s.Shi;
-  const __bf16* lo = (const __bf16*)s.Slo;
+namespace {
+
+int parts_of(int prec) { return prec == 3 ? 3 : 2; }  // 3: bf16x6, else bf16x3
+
+template <int NP, int TM, int TN>
+hipError_t left_tile(const GemmOperands& s, const float* B, float* C, int M, int ncols, int batch,
+                     long long bstride, int epi, const EpiArgs& ep, hipStream_t st) {
+  const unsigned g = (unsigned)((long long)batch * (M / TM) * (ncols / TN));
   if (epi == EPI_DIVIDE)
-    hipLaunchKernelGGL((k_gemm_left_bf3<TM, TN, EPI_DIVIDE>), dim3((unsigned)tiles), dim3(256), 0,
-                       st, hi, lo, B, C, M, ncols, batch, bstride, ep);
+    hipLaunchKernelGGL((k_gemm_left_bf<NP, TM, TN, EPI_DIVIDE>), dim3(g), dim3(256), 0, st, s, B, C,
+                       M, ncols, batch, bstride, ep);
   else
-    hipLaunchKernelGGL((k_gemm_left_bf3<TM, TN, EPI_STORE>), dim3((unsigned)tiles), dim3(256), 0,
-                       st, hi, lo, B, C, M, ncols, batch, bstride, ep);
+    hipLaunchKernelGGL((k_gemm_left_bf<NP, TM, TN, EPI_STORE>), dim3(g), dim3(256), 0, st, s, B, C,
+                       M, ncols, batch, bstride, ep);
   return hipGetLastError();
 }
 
-template <int TM, int TN>
-static hipError_t br_tn(const GemmOperands& s, const float* A, float* C, int rows, int K, int epi,
-                        const EpiArgs& ep, hipStream_t st) {
-  const long long tiles = (long long)(rows / TM) * (K / TN);
-  const __bf16* hi = (const __bf16*)s.Shi;
-  const __bf16* lo = (const __bf16*)s.Slo;
+template <int NP, int TM, int TN>
+hipError_t right_tile(const GemmOperands& s, const float* A, float* C, int rows, int K, int epi,
+                      const EpiArgs& ep, hipStream_t st) {
+  const unsigned g = (unsigned)((long long)(rows / TM) * (K / TN));
   switch (epi) {
     case EPI_SUB_DENSE:
-      hipLaunchKernelGGL((k_gemm_right_bf3<TM, TN, EPI_SUB_DENSE>), dim3((unsigned)tiles),
-                         dim3(256), 0, st, A, hi, lo, C, rows, K, ep);
+      hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_SUB_DENSE>), dim3(g), dim3(256), 0, st,
+                         A, s, C, rows, K, ep);
       break;
     case EPI_STORE_DENSE:
-      hipLaunchKernelGGL((k_gemm_right_bf3<TM, TN, EPI_STORE_DENSE>), dim3((unsigned)tiles),
-                         dim3(256), 0, st, A, hi, lo, C, rows, K, ep);
+      hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_STORE_DENSE>), dim3(g), dim3(256), 0, st,
+                         A, s, C, rows, K, ep);
       break;
     default:
-      hipLaunchKernelGGL((k_gemm_right_bf3<TM, TN, EPI_STORE>), dim3((unsigned)tiles), dim3(256),
-                         0, st, A, hi, lo, C, rows, K, ep);
+      hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_STORE>), dim3(g), dim3(256), 0, st, A,
+                         s, C, rows, K, ep);
   }
   return hipGetLastError();
 }
 
-template <int TM>
-static hipError_t bl_tm(int tn, const GemmOperands& s, const float* B, float* C, int M,
-                        int ncols, int batch, long long bstride, int epi, const EpiArgs& ep,
-                        hipStream_t st) {
-  switch (tn) {
-    case 128: return bl_tn<TM, 128>(s, B, C, M, ncols, batch, bstride, epi, ep, st);
-    case 64: return bl_tn<TM, 64>(s, B, C, M, ncols, batch, bstride, epi, ep, st);
-    default: return bl_tn<TM, 32>(s, B, C, M, ncols, batch, bstride, epi, ep, st);
-  }
+// Instantiated tiles: bf16x3 every side in {32, 64, 128}; bf16x6 (three parts
+// in LDS) every side in {32, 64}.
+#define QN_BF_TILES(FN, NP_, ...)                                          \
+  if (NP_ == 2) {                                                          \
+    if (tm == 128 && tn == 128) return FN<2, 128, 128>(__VA_ARGS__);       \
+    if (tm == 128 && tn == 64) return FN<2, 128, 64>(__VA_ARGS__);         \
+    if (tm == 128 && tn == 32) return FN<2, 128, 32>(__VA_ARGS__);         \
+    if (tm == 64 && tn == 128) return FN<2, 64, 128>(__VA_ARGS__);         \
+    if (tm == 64 && tn == 64) return FN<2, 64, 64>(__VA_ARGS__);           \
+    if (tm == 64 && tn == 32) return FN<2, 64, 32>(__VA_ARGS__);           \
+    if (tm == 32 && tn == 128) return FN<2, 32, 128>(__VA_ARGS__);         \
+    if (tm == 32 && tn == 64) return FN<2, 32, 64>(__VA_ARGS__);           \
+    if (tm == 32 && tn == 32) return FN<2, 32, 32>(__VA_ARGS__);           \
+  } else {                                                                 \
+    if (tm == 64 && tn == 64) return FN<3, 64, 64>(__VA_ARGS__);           \
+    if (tm == 64 && tn == 32) return FN<3, 64, 32>(__VA_ARGS__);           \
+    if (tm == 32 && tn == 64) return FN<3, 32, 64>(__VA_ARGS__);           \
+    if (tm == 32 && tn == 32) return FN<3, 32, 32>(__VA_ARGS__);           \
+  }                                                                        \
+  return hipErrorInvalidValue;
+
+}  // namespace
+
+int gemm_bf_max_tile(int prec) { return parts_of(prec) == 3 ? 64 : 128; }
+
+hipError_t launch_gemm_left(int prec, const GemmOperands& s, const void* B, void* C, int M,
+                            int ncols, int batch, long long bstride, int epi, const EpiArgs& ep,
+                            int tm, int tn, hipStream_t st) {
+  const float* Bf = (const float*)B;
+  float* Cf = (float*)C;
+  QN_BF_TILES(left_tile, parts_of(prec), s, Bf, Cf, M, ncols, batch, bstride, epi, ep, st)
 }
 
-template <int TM>
-static hipError_t br_tm(int tn, const GemmOperands& s, const float* A, float* C, int rows, int K,
-                        int epi, const EpiArgs& ep, hipStream_t st) {
-  switch (tn) {
-    case 128: return br_tn<TM, 128>(s, A, C, rows, K, epi, ep, st);
-    case 64: return br_tn<TM, 64>(s, A, C, rows, K, epi, ep, st);
-    default: return br_tn<TM, 32>(s, A, C, rows, K, epi, ep, st);
-  }
+hipError_t launch_gemm_right(int prec, const GemmOperands& s, const void* A, void* C, int rows,
+                             int K, int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st) {
+  const float* Af = (const float*)A;
+  float* Cf = (float*)C;
+  QN_BF_TILES(right_tile, parts_of(prec), s, Af, Cf, rows, K, epi, ep, st)
 }
 
-hipError_t launch_gemm_bf16x3_left(const GemmOperands& s, const float* B, float* C, int M,
-                                   int ncols, int batch, long long bstride, int epi,
-                                   const EpiArgs& ep, int tm, int tn, hipStream_t st) {
-  switch (tm) {
-    case 128: return bl_tm<128>(tn, s, B, C, M, ncols, batch, bstride, epi, ep, st);
-    case 64: return bl_tm<64>(tn, s, B, C, M, ncols, batch, bstride, epi, ep, st);
-    default: return bl_tm<32>(tn, s, B, C, M, ncols, batch, bstride, epi, ep, st);
-  }
-}
-
-hipError_t launch_gemm_bf16x3_right(const GemmOperands& s, const float* A, float* C, int rows,
-                                    int K, int epi, const EpiArgs& ep, int tm, int tn,
-                                    hipStream_t st) {
-  switch (tm) {
-    case 128: return br_tm<128>(tn, s, A, C, rows, K, epi, ep, st);
-    case 64: return br_tm<64>(tn, s, A, C, rows, K, epi, ep, st);
-    default: return br_tm<32>(tn, s, A, C, rows, K, epi, ep, st);
-  }
-}
+#undef QN_BF_TILES
 
 }  // namespace qn

@@ -58,17 +58,19 @@ struct EpiArgs {
   int coef_stride;
 };
 
-// Host-side launchers (defined in qn_gemm.hip / qn_pointwise.hip).  All take
-// an explicit stream and return the launch status.
+// Dense split-bf16 mode products (qn_gemm_bf16.hip), FP32 tensors.  All
+// launchers take an explicit stream and return the launch status.
 // Form L: C[b][m][n] = sum_k S[m][k] B[b][k][n]  (S symmetric, P x P, ld = P)
 // Form R: C[r][n]    = sum_k A[r][k] S[k][n]     (A rows of length K = P)
-// prec: 0 = fp64 (T = double), 1 = fp32 (T = float), 2 = bf16x3 (T = float,
-// S given as bf16 hi/lo pair in Shi/Slo).
+// prec: QN_PREC_BF16X3 (S as bf16 parts Shi, Slo) or QN_PREC_BF16X6 (Shi,
+// Slo, Slo2).
 struct GemmOperands {
-  const void* S;     // fp64 or fp32 matrix, or NULL for bf16x3
-  const void* Shi;   // bf16x3 only
-  const void* Slo;   // bf16x3 only
+  const void* Shi;
+  const void* Slo;
+  const void* Slo2;  // bf16x6 only
 };
+// Largest tile side instantiated for the precision.
+int gemm_bf_max_tile(int prec);
 
 hipError_t launch_gemm_left(int prec, const GemmOperands& s, const void* B, void* C, int M,
                             int ncols, int batch, long long bstride, int epi, const EpiArgs& ep,

@@ -118,7 +118,7 @@ def test_fdm_solve_max_size_2d():
     assert rel(x[0], otensor.fdm_solve(r[0], 1.0)) <= 1e-12
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 3e-5), ("bf16x3", 3e-4)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 3e-5), ("bf16x3", 3e-4), ("bf16x6", 3e-5)])
 @pytest.mark.parametrize("shape", [(63, 63), (31, 31, 31), (40, 50, 70)])
 def test_fdm_solve_reduced_precision(prec, tol, shape):
     print(f"fdm {prec} {shape}", flush=True)
@@ -128,6 +128,32 @@ def test_fdm_solve_reduced_precision(prec, tol, shape):
     err = rel(x[0], otensor.fdm_solve(r[0], 0.5))
     print(f"  {prec} {shape} rel err {err:.3e}", flush=True)
     assert err <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("kind,shape,beta,mode", [
+    ("cubic", (63, 63), 1.0, "fixed"), ("quasilinear", (31, 33, 35), 0.0, "fixed"),
+    ("system", (40, 45), 0.0, "midpoint"),
+])
+def test_reduced_precision_iterate_reaches_the_fp64_solution(prec, kind, shape, beta, mode):
+    """Transforms in reduced precision with the FP64 residual and update: the
+    outer iteration refines to the same 1e-10 relative residual; the result
+    agrees with the FP64 oracle's converged U to <= 1e-9 relative L2 and takes
+    at most 10% more iterations."""
+    print(f"mixed iterate {prec} {kind} {shape}", flush=True)
+    ncomp = 2 if kind == "system" else 1
+    f = synth.random_field((ncomp,) + shape, 31, scale=30.0)
+    ref = oqn.qn_solve(KIND[kind], f, beta=beta, midpoint=(mode == "midpoint"), rtol=1e-10,
+                       max_iter=300)
+    s = Solver(shape, kind, beta=beta, beta_mode=mode, precision=prec)
+    u = torch.zeros((ncomp,) + shape, dtype=torch.float64, device="cuda")
+    st = s.iterate(u, dev(f), rtol=1e-10, max_iter=300)
+    assert st["status"] == QN_OK, st
+    assert st["relres"] <= 1e-10
+    assert st["iters"] <= math.ceil(1.1 * ref["iters"]), (st["iters"], ref["iters"])
+    err = rel(host(u), ref["u"])
+    print(f"  iters {st['iters']} (oracle {ref['iters']}), rel err {err:.2e}", flush=True)
+    assert err <= 1e-9
 
 
 def run_both(kind, f, shape, beta=0.0, beta_mode="fixed", rtol=1e-10, max_iter=300):
