@@ -176,21 +176,21 @@ qn_status qn_iterate(qn_ctx ctx, double* d_U, const double* d_F, double rtol,
 /* Tile selection for the mode products (Section 4.1, eq. fin_inverse, as
  * reflection-folded matrix-core products).  The solve is a fixed list of
  * launches (3D: 6, 2D: 4; the x forward product first, the x inverse product
- * with the update last).  By default each launch takes the largest tile
- * shape that divides its extents and gives at least 512 workgroups (else the
- * shape with the most workgroups).  qn_autotune times every admissible shape
+ * with the update last).  By default each folded launch takes the first
+ * instantiated tile shape that divides its extents and gives at least 512
+ * workgroups (else the shape with the most workgroups); the dense
+ * split-bf16 launches take the largest side that divides each extent.  qn_autotune times every admissible shape
  * of every launch on the bound workspace (its transform tensors are
  * overwritten; the x inverse is timed with a plain store) and keeps the
  * fastest for all later calls.  Results do not depend on the tile shapes
- * (bitwise).  Synchronous.  A no-op for the split-bf16 precisions, whose
- * dense transforms use a fixed rule. */
+ * (bitwise).  Synchronous.  The split-bf16 precisions use dense
+ * (unfolded) products; their tiles are tuned the same way. */
 qn_status qn_autotune(qn_ctx ctx);
 /* Launch i of the solve: info4 = {kind, axis (0 x, 1 y, 2 z), tile_m,
  * tile_n}; kind is 0 x forward, 1 y/z forward, 2 y/z inverse, 3 x inverse,
  * plus 4 when one tile computes both the even and the odd spectral half
  * (paired forward tiles; tile_m or tile_n then counts fold indices).
- * Requires a bound workspace; QN_ERR_UNSUPPORTED for the split-bf16
- * precisions (dense transforms). */
+ * Requires a bound workspace. */
 qn_status qn_tile_info(qn_ctx ctx, int32_t i, int32_t* info4);
 
 /* Kernel timing (contexts created with options.timing != 0).  qn_timing_read

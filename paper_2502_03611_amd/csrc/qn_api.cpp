@@ -225,7 +225,11 @@ struct FoldStep {
   int rows;             // form R: row count
   int epi;
   EpiArgs ep;
+  int m, k;             // dense split-bf16 steps: contraction length (P of the axis)
 };
+
+// Dense split-bf16 step kinds (the folded ones are FK_*).
+enum DenseKind { DK_RIGHT = 10, DK_LEFT = 11 };
 
 GemmOperands operands(qn_ctx c, int axis) {
   GemmOperands g{};
@@ -317,20 +321,107 @@ int fold_plan(qn_ctx c, const EpiArgs& ep, int epi_last, FoldStep* st) {
   return ns;
 }
 
+// The dense split-bf16 solve as a list of launches (same order and timing
+// keys as the folded one; 3D y/z products are form L over slabs, the x
+// products form R over rows).
+int dense_plan(qn_ctx c, const EpiArgs& ep, int epi_last, FoldStep* st) {
+  void* W1 = c->ws + c->off_W1;
+  void* W2 = c->ws + c->off_W2;
+  const int px = c->p[0], py = c->p[1], pz = c->p[2];
+  const int rows = c->ncomp * pz * py;
+  const long long yslab = (long long)py * px, zslab = (long long)pz * py * px;
+  int ns = 0;
+  auto add = [&](int kind, int axis, int kid, const void* in, void* out, int m, int ncols, int batch,
+                 long long bstride, int epi, const EpiArgs& e) {
+    FoldStep f{};
+    f.kind = kind;
+    f.axis = axis;
+    f.kid = kid;
+    f.in = in;
+    f.out = out;
+    f.m = m;
+    f.k = px;
+    f.ncols = ncols;
+    f.batch = batch;
+    f.bstride = bstride;
+    f.rows = rows;
+    f.epi = epi;
+    f.ep = e;
+    st[ns++] = f;
+  };
+  add(DK_RIGHT, 0, K_GEMM_X, W1, W2, 0, 0, 0, 0, EPI_STORE, ep);
+  if (c->dim == 2) {
+    EpiArgs ed = ep;
+    ed.lamM = c->at<double>(c->off_lam[1]);
+    ed.lamY = nullptr;
+    add(DK_LEFT, 1, K_GEMM_DIVIDE, W2, W1, py, px, c->ncomp, yslab, EPI_DIVIDE, ed);
+    add(DK_LEFT, 1, K_GEMM_YZ_INV, W1, W2, py, px, c->ncomp, yslab, EPI_STORE, ep);
+  } else {
+    add(DK_LEFT, 1, K_GEMM_YZ, W2, W1, py, px, c->ncomp * pz, yslab, EPI_STORE, ep);
+    EpiArgs ed = ep;
+    ed.lamM = c->at<double>(c->off_lam[2]);
+    ed.lamY = c->at<double>(c->off_lam[1]);
+    add(DK_LEFT, 2, K_GEMM_DIVIDE, W1, W2, pz, (int)yslab, c->ncomp, zslab, EPI_DIVIDE, ed);
+    add(DK_LEFT, 2, K_GEMM_YZ_INV, W2, W1, pz, (int)yslab, c->ncomp, zslab, EPI_STORE, ep);
+    add(DK_LEFT, 1, K_GEMM_YZ_INV, W1, W2, py, px, c->ncomp * pz, yslab, EPI_STORE, ep);
+  }
+  add(DK_RIGHT, 0, K_GEMM_X_UPDATE, W2, W1, 0, 0, 0, 0, epi_last, ep);
+  return ns;
+}
+
+int solve_plan(qn_ctx c, const EpiArgs& ep, int epi_last, FoldStep* st) {
+  return c->fold ? fold_plan(c, ep, epi_last, st) : dense_plan(c, ep, epi_last, st);
+}
+
 hipError_t run_step(qn_ctx c, const FoldStep& f, const FoldTile& t) {
+  if (f.kind == DK_RIGHT)
+    return launch_gemm_right(c->prec, operands(c, f.axis), f.in, f.out, f.rows, f.k, f.epi, f.ep,
+                             t.tm, t.tn, c->stream);
+  if (f.kind == DK_LEFT)
+    return launch_gemm_left(c->prec, operands(c, f.axis), f.in, f.out, f.m, f.ncols, f.batch,
+                            f.bstride, f.epi, f.ep, t.tm, t.tn, c->stream);
   return launch_fold(f.kind, c->prec, fold_ops(c, f.axis), f.in, f.out, c->ax[f.axis], f.ncols,
                      f.batch, f.bstride, f.rows, f.epi, f.ep, t, c->stream);
+}
+
+// Extents a dense tile must divide.
+void dense_extents(const FoldStep& f, long long* mext, long long* next) {
+  *mext = f.kind == DK_RIGHT ? f.rows : f.m;
+  *next = f.kind == DK_RIGHT ? f.k : f.ncols;
+}
+
+// Every instantiated tile that fits launch f (at most 16).
+int step_candidates(qn_ctx c, const FoldStep& f, FoldTile* out) {
+  int n = 0;
+  long long mext, next;
+  if (!c->fold) {
+    dense_extents(f, &mext, &next);
+    const int cap = gemm_bf_max_tile(c->prec);
+    for (int tm = 32; tm <= cap; tm *= 2)
+      for (int tn = 32; tn <= cap; tn *= 2)
+        if (mext % tm == 0 && next % tn == 0) out[n++] = FoldTile{tm, tn, 0};
+    return n;
+  }
+  const FoldTile* list;
+  const int nc = fold_tiles(f.kind, &list);
+  fold_extents(f.kind, c->ax[f.axis].bk, f.ncols, f.rows, &mext, &next);
+  for (int i = 0; i < nc && n < 16; ++i)
+    if (mext % list[i].tm == 0 && next % list[i].tn == 0) out[n++] = list[i];
+  return n;
 }
 
 // Tile of launch i of the plan: the autotuned one, else the default rule.
 FoldTile step_tile(qn_ctx c, const FoldStep& f, int i) {
   if (c->tuned) return c->tile[i];
+  if (!c->fold) {
+    long long mext, next;
+    dense_extents(f, &mext, &next);
+    const int cap = gemm_bf_max_tile(c->prec);
+    return FoldTile{pick_tile(mext, cap), pick_tile(next, cap), 0};
+  }
   return pick_fold_tile(f.kind, c->ax[f.axis].bk, f.ncols, f.batch, f.rows);
 }
 
-// The tensor-product solve of the padded tensor in W1 with coefficients
-// coef = {scale, beta} (device); the result goes to `dense` with epilogue
-// epi_last (EPI_SUB_DENSE: U -= X, EPI_STORE_DENSE: X).
 EpiArgs epi_args(qn_ctx c, const double* coef, double* dense) {
   EpiArgs ep{};
   ep.inst_mod = 1;
@@ -347,78 +438,14 @@ EpiArgs epi_args(qn_ctx c, const double* coef, double* dense) {
 }
 
 hipError_t solve_ws(qn_ctx c, const double* coef, double* dense, int epi_last) {
-  void* W1 = c->ws + c->off_W1;
-  void* W2 = c->ws + c->off_W2;
-  const int px = c->p[0], py = c->p[1], pz = c->p[2];
-  const int pr = c->prec;
-  const EpiArgs ep = epi_args(c, coef, dense);
-  const int rows = c->ncomp * pz * py;
-  if (c->fold) {
-    FoldStep st[6];
-    const int ns = fold_plan(c, ep, epi_last, st);
-    for (int i = 0; i < ns; ++i) {
-      const FoldStep& f = st[i];
-      const FoldTile t = step_tile(c, f, i);
-      const hipError_t ef = timed(c, f.kid, [&] { return run_step(c, f, t); });
-      if (ef != hipSuccess) return ef;
-    }
-    return hipSuccess;
+  FoldStep st[6];
+  const int ns = solve_plan(c, epi_args(c, coef, dense), epi_last, st);
+  for (int i = 0; i < ns; ++i) {
+    const FoldStep& f = st[i];
+    const FoldTile t = step_tile(c, f, i);
+    const hipError_t e = timed(c, f.kid, [&] { return run_step(c, f, t); });
+    if (e != hipSuccess) return e;
   }
-  const GemmOperands Sx = operands(c, 0), Sy = operands(c, 1), Sz = operands(c, 2);
-  const int cap = gemm_bf_max_tile(pr);
-  const int tmx = pick_tile(rows, cap), tnx = pick_tile(px, cap);
-  const int tmy = pick_tile(py, cap), tny = pick_tile(px, cap);
-  const long long yslab = (long long)py * px;
-  hipError_t e;
-#define QN_TRY(x)               \
-  do {                          \
-    e = (x);                    \
-    if (e != hipSuccess) return e; \
-  } while (0)
-  // forward x
-  QN_TRY(timed(c, K_GEMM_X, [&] {
-    return launch_gemm_right(pr, Sx, W1, W2, rows, px, EPI_STORE, ep, tmx, tnx, c->stream);
-  }));
-  if (c->dim == 2) {
-    EpiArgs ed = ep;
-    ed.lamM = c->at<double>(c->off_lam[1]);
-    ed.lamY = nullptr;
-    QN_TRY(timed(c, K_GEMM_DIVIDE, [&] {
-      return launch_gemm_left(pr, Sy, W2, W1, py, px, c->ncomp, yslab, EPI_DIVIDE, ed, tmy, tny,
-                              c->stream);
-    }));
-    QN_TRY(timed(c, K_GEMM_YZ, [&] {
-      return launch_gemm_left(pr, Sy, W1, W2, py, px, c->ncomp, yslab, EPI_STORE, ep, tmy, tny,
-                              c->stream);
-    }));
-  } else {
-    const long long zslab = (long long)pz * py * px;
-    const int tmz = pick_tile(pz, cap), tnz = pick_tile(yslab, cap);
-    QN_TRY(timed(c, K_GEMM_YZ, [&] {
-      return launch_gemm_left(pr, Sy, W2, W1, py, px, c->ncomp * pz, yslab, EPI_STORE, ep, tmy,
-                              tny, c->stream);
-    }));
-    EpiArgs ed = ep;
-    ed.lamM = c->at<double>(c->off_lam[2]);
-    ed.lamY = c->at<double>(c->off_lam[1]);
-    QN_TRY(timed(c, K_GEMM_DIVIDE, [&] {
-      return launch_gemm_left(pr, Sz, W1, W2, pz, (int)yslab, c->ncomp, zslab, EPI_DIVIDE, ed,
-                              tmz, tnz, c->stream);
-    }));
-    QN_TRY(timed(c, K_GEMM_YZ, [&] {
-      return launch_gemm_left(pr, Sz, W2, W1, pz, (int)yslab, c->ncomp, zslab, EPI_STORE, ep, tmz,
-                              tnz, c->stream);
-    }));
-    QN_TRY(timed(c, K_GEMM_YZ, [&] {
-      return launch_gemm_left(pr, Sy, W1, W2, py, px, c->ncomp * pz, yslab, EPI_STORE, ep, tmy,
-                              tny, c->stream);
-    }));
-  }
-  // inverse x with the fused dense epilogue
-  QN_TRY(timed(c, K_GEMM_X_UPDATE, [&] {
-    return launch_gemm_right(pr, Sx, W2, nullptr, rows, px, epi_last, ep, tmx, tnx, c->stream);
-  }));
-#undef QN_TRY
   return hipSuccess;
 }
 
@@ -716,7 +743,6 @@ qn_status qn_iterate(qn_ctx c, double* d_U, const double* d_F, double rtol, int3
 qn_status qn_autotune(qn_ctx c) {
   qn_status s = check_ctx(c, true);
   if (s != QN_OK) return s;
-  if (!c->fold) return QN_OK;  // bf16x3: dense kernels, fixed rule
   hipEvent_t t0 = nullptr, t1 = nullptr;
   hipError_t e = hipEventCreate(&t0);
   if (e == hipSuccess) e = hipEventCreate(&t1);
@@ -727,20 +753,18 @@ qn_status qn_autotune(qn_ctx c) {
   double* coef = c->at<double>(c->off_coef);
   if (e == hipSuccess) e = launch_set_coef(coef, 1.0, 1.0, c->stream);
   FoldStep st[6];
-  const int ns = fold_plan(c, epi_args(c, coef, nullptr), EPI_STORE, st);
+  const int ns = solve_plan(c, epi_args(c, coef, nullptr), EPI_STORE, st);
+  const bool was_tuned = c->tuned;
+  c->tuned = false;  // step_tile gives the default rule below
   FoldTile best[6] = {};
   for (int i = 0; i < ns && e == hipSuccess; ++i) {
     const FoldStep& f = st[i];
-    const int bk = c->ax[f.axis].bk;
-    best[i] = pick_fold_tile(f.kind, bk, f.ncols, f.batch, f.rows);
-    const FoldTile* list;
-    const int nc = fold_tiles(f.kind, &list);
-    long long mext, next;
-    fold_extents(f.kind, bk, f.ncols, f.rows, &mext, &next);
+    best[i] = step_tile(c, f, i);
+    FoldTile cand[16];
+    const int nc = step_candidates(c, f, cand);
     float best_ms = 1e30f;
     for (int k = 0; k < nc && e == hipSuccess; ++k) {
-      const FoldTile t = list[k];
-      if (mext % t.tm || next % t.tn) continue;
+      const FoldTile t = cand[k];
       e = run_step(c, f, t);  // warm-up
       if (e == hipSuccess) e = hipEventRecord(t0, c->stream);
       for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run_step(c, f, t);
@@ -756,7 +780,10 @@ qn_status qn_autotune(qn_ctx c) {
   }
   if (t0) (void)hipEventDestroy(t0);
   if (t1) (void)hipEventDestroy(t1);
-  if (e != hipSuccess) return hip_fail(c, e, "autotune");
+  if (e != hipSuccess) {
+    c->tuned = was_tuned;
+    return hip_fail(c, e, "autotune");
+  }
   for (int i = 0; i < 6; ++i) c->tile[i] = best[i];
   c->tuned = true;
   return QN_OK;
@@ -766,12 +793,13 @@ qn_status qn_tile_info(qn_ctx c, int32_t i, int32_t* info4) {
   qn_status s = check_ctx(c, true);
   if (s != QN_OK) return s;
   if (!info4) return fail(QN_ERR_INVALID, "null argument");
-  if (!c->fold) return fail(QN_ERR_UNSUPPORTED, "no folded transforms in this precision");
   FoldStep st[6];
-  const int ns = fold_plan(c, epi_args(c, nullptr, nullptr), EPI_STORE, st);
+  const int ns = solve_plan(c, epi_args(c, nullptr, nullptr), EPI_STORE, st);
   if (i < 0 || i >= ns) return fail(QN_ERR_INVALID, "launch index %d out of range [0, %d)", i, ns);
   const FoldTile t = step_tile(c, st[i], i);
-  info4[0] = st[i].kind + (t.paired ? 4 : 0);
+  const int kid = st[i].kid;
+  const int kind = kid == K_GEMM_X ? 0 : kid == K_GEMM_X_UPDATE ? 3 : kid == K_GEMM_YZ_INV ? 2 : 1;
+  info4[0] = kind + (t.paired ? 4 : 0);
   info4[1] = st[i].axis;
   info4[2] = t.tm;
   info4[3] = t.tn;
