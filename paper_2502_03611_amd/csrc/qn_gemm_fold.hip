@@ -829,6 +829,8 @@ hipError_t lfwd2(const FoldOperands& f, const T* B, T* C, const FoldAxis& ax, in
   QN_LFWD2(64, 64)
   QN_LFWD2(128, 64)
   QN_LFWD2(32, 64)
+  QN_LFWD2(64, 128)
+  QN_LFWD2(32, 128)
 #undef QN_LFWD2
   return hipErrorInvalidValue;
 }
@@ -849,6 +851,7 @@ hipError_t linv(const FoldOperands& f, const T* Y, T* C, const FoldAxis& ax, int
   QN_LINV(64, 64)
   QN_LINV(32, 64)
   QN_LINV(32, 32)
+  QN_LINV(32, 128)
 #undef QN_LINV
   return hipErrorInvalidValue;
 }
@@ -870,6 +873,8 @@ hipError_t rfwd(const FoldOperands& f, const T* A, T* C, const FoldAxis& ax, int
   QN_RFWD(64, 64)
   QN_RFWD(64, 32)
   QN_RFWD(32, 32)
+  QN_RFWD(64, 128)
+  QN_RFWD(32, 64)
 #undef QN_RFWD
   return hipErrorInvalidValue;
 }
@@ -897,6 +902,8 @@ hipError_t rinv(const FoldOperands& f, const T* Y, T* C, const FoldAxis& ax, int
   QN_RINV(64, 64)
   QN_RINV(64, 32)
   QN_RINV(32, 32)
+  QN_RINV(64, 128)
+  QN_RINV(32, 64)
 #undef QN_RINV
   return hipErrorInvalidValue;
 }
@@ -945,11 +952,14 @@ hipError_t launch_fold_right_inv(int prec, const FoldOperands& f, const void* Y,
 }
 
 namespace {
-const FoldTile kTilesRfwd[] = {{128, 128, 0}, {128, 64, 0}, {64, 64, 0}, {64, 32, 0}, {32, 32, 0}};
+const FoldTile kTilesRfwd[] = {{128, 128, 0}, {128, 64, 0}, {64, 128, 0}, {64, 64, 0},
+                               {64, 32, 0},   {32, 64, 0},  {32, 32, 0}};
 const FoldTile kTilesLfwd[] = {{64, 64, 1},  {128, 128, 0}, {64, 128, 0}, {128, 64, 1},
-                               {64, 64, 0},  {32, 64, 1},   {32, 64, 0},  {32, 32, 0}};
-const FoldTile kTilesLinv[] = {{64, 64, 0}, {64, 128, 0}, {32, 64, 0}, {32, 32, 0}};
-const FoldTile kTilesRinv[] = {{64, 64, 0}, {128, 64, 0}, {64, 32, 0}, {32, 32, 0}};
+                               {64, 128, 1}, {32, 128, 1},  {64, 64, 0},  {32, 64, 1},
+                               {32, 64, 0},  {32, 32, 0}};
+const FoldTile kTilesLinv[] = {{64, 64, 0}, {64, 128, 0}, {32, 128, 0}, {32, 64, 0}, {32, 32, 0}};
+const FoldTile kTilesRinv[] = {{64, 64, 0}, {128, 64, 0}, {64, 128, 0}, {64, 32, 0},
+                               {32, 64, 0}, {32, 32, 0}};
 }  // namespace
 
 int fold_tiles(int kind, const FoldTile** list) {
