@@ -542,7 +542,7 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   off += align256(c->tensor_elems() * c->elem());
   c->off_W2 = off;
   off += align256(c->tensor_elems() * c->elem());
-  c->max_blocks = residual_max_blocks(c->p[0], c->p[1], c->p[2], RESIDUAL_RZ);
+  c->max_blocks = residual_max_blocks(c->p[0], c->p[1], c->p[2], RESIDUAL_RZ, c->dim == 2);
   c->off_part = off;
   off += align256((size_t)c->max_blocks * 4 * sizeof(double));
   c->off_scal = off;

@@ -282,7 +282,7 @@ qn_status qnb_setup(int32_t count, const int32_t* n, const int32_t* ncomp, int32
     off += a256(te);
     k.off_W2 = off;
     off += a256(te);
-    k.bpi = residual_max_blocks(k.p, k.p, 1, 1);
+    k.bpi = residual_max_blocks(k.p, k.p, 1, 1, true);
     k.off_part = off;
     off += a256((size_t)k.bpi * k.K * 4 * sizeof(double));
     k.off_state = off;

@@ -145,7 +145,10 @@ struct ResidualArgs {
   const int* skip;         // batched solver: per-z-plane (instance) skip flags, else NULL
 };
 hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t st);
-int residual_max_blocks(int ox, int oy, int oz, int rz);
+// Workgroups (= partial slots) of a residual launch; planar: no z coupling
+// (1/h_z^2 = 0: 2D problems and the batched solver), which uses the planar
+// kernel with oz planes.
+int residual_max_blocks(int ox, int oy, int oz, int rz, bool planar);
 constexpr int RESIDUAL_RZ = 32;  // z-slab depth of a single 3D problem
 
 // Per-instance state of the batched solver.  scale and beta are adjacent so

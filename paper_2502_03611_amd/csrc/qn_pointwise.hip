@@ -225,17 +225,156 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
   }
 }
 
-static dim3 residual_grid(int ox, int oy, int oz, int rz) {
+// Planar residual (2D problems and the batched solver's instances, 1/h_z^2 =
+// 0): each wave owns 64 consecutive x and marches R2Y rows in y, keeping
+// U(y-1), U(y), U(y+1) of its column in registers; x-neighbours come from the
+// adjacent lanes (wave shuffles), the two strip-edge columns from global
+// memory.  No LDS staging and no barriers in the march; the loads of row y+1
+// are issued before row y is computed.  A workgroup (4 waves, 256 columns)
+// stays inside one plane, so its partials belong to one instance.
+constexpr int R2X = 256, R2Y = 16;
+
+template <int NL, typename TO>
+__global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
+  constexpr int NC = (NL == NL_SYS2) ? 2 : 1;
+  const int lane = threadIdx.x & 63;
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int tile = xcd_tile((blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x, gx * gy * gridDim.z);
+  const int bx = tile % gx, by = (tile / gx) % gy, pl = tile / (gx * gy);
+  if (a.skip && a.skip[pl]) return;  // batched solver: finished instance
+  const int nx = a.nx, ny = a.ny;
+  const int x = bx * R2X + threadIdx.x;
+  const int y0 = by * R2Y, y1 = min(y0 + R2Y, a.oy);
+  const long long plane = (long long)nx * ny;
+  const long long comp = plane * a.nz;
+  const bool xin = x < nx, xout = x < a.ox;
+  const bool lh = lane == 0 && x >= 1 && x - 1 < nx;  // left strip edge: load U(x-1)
+  const bool rh = lane == 63 && x + 1 < nx;           // right strip edge: load U(x+1)
+  const double* Up = a.U + (long long)pl * plane;
+  const double* Fp = a.F + (long long)pl * plane;
+  auto ld = [&](const double* p, int c, int y, int xx, bool ok) {
+    return (ok && y >= 0 && y < ny) ? p[c * comp + (long long)y * nx + xx] : 0.0;
+  };
+
+  double s_r = 0.0, s_f = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
+  double um[NC], uc[NC], up[NC], f[NC], hl[NC], hr[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    um[c] = ld(Up, c, y0 - 1, x, xin);
+    uc[c] = ld(Up, c, y0, x, xin);
+    up[c] = ld(Up, c, y0 + 1, x, xin);
+    f[c] = ld(Fp, c, y0, x, xin);
+    hl[c] = ld(Up, c, y0, x - 1, lh);
+    hr[c] = ld(Up, c, y0, x + 1, rh);
+  }
+  for (int y = y0; y < y1; ++y) {
+    // row y + 1 in flight while row y is computed
+    double nup[NC], nf[NC], nhl[NC], nhr[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      nup[c] = ld(Up, c, y + 2, x, xin);
+      nf[c] = ld(Fp, c, y + 1, x, xin);
+      nhl[c] = ld(Up, c, y + 1, x - 1, lh);
+      nhr[c] = ld(Up, c, y + 1, x + 1, rh);
+    }
+    double xm[NC], xp[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double l = __shfl_up(uc[c], 1, 64), r = __shfl_down(uc[c], 1, 64);
+      xm[c] = lane == 0 ? hl[c] : l;
+      xp[c] = lane == 63 ? hr[c] : r;
+    }
+    const bool in = xin && y < ny;
+    if (in) {
+      double r[NC];
+      if (NL == NL_QUASILIN) {
+        const double u = uc[0];
+        const double ac = 1.0 + u * u;
+        auto flux = [&](double un) { return 0.5 * (ac + (1.0 + un * un)) * (u - un); };
+        const double lx_ = (flux(xm[0]) + flux(xp[0])) * a.ihx2;
+        const double ly_ = (flux(um[0]) + flux(up[0])) * a.ihy2;
+        r[0] = lx_ + ly_ - f[0];
+        s_f += f[0] * f[0];
+        mn = fmin(mn, ac);
+        mx = fmax(mx, ac);
+      } else {
+        double lap[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const double u = uc[c];
+          lap[c] = (2.0 * u - xm[c] - xp[c]) * a.ihx2 + (2.0 * u - um[c] - up[c]) * a.ihy2;
+          s_f += f[c] * f[c];
+        }
+        if (NL == NL_CUBIC) {
+          const double u = uc[0];
+          r[0] = lap[0] + u * u * u - f[0];
+          const double fu = 3.0 * u * u;
+          mn = fmin(mn, fu);
+          mx = fmax(mx, fu);
+        } else {
+          const double u = uc[0], v = uc[NC - 1];
+          r[0] = lap[0] + u * u * u - v - f[0];
+          r[NC - 1] = lap[NC - 1] + v * v * v - u - f[NC - 1];
+          // 2x2 block [[3u^2, -1], [-1, 3v^2]]: eigenvalues (a+d -+ sqrt((a-d)^2 + 4)) / 2
+          const double ea = 3.0 * u * u, ed = 3.0 * v * v;
+          const double disc = sqrt((ea - ed) * (ea - ed) + 4.0);
+          mn = fmin(mn, 0.5 * (ea + ed - disc));
+          mx = fmax(mx, 0.5 * (ea + ed + disc));
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        s_r += r[c] * r[c];
+        const long long o = c * a.r_cstride + (long long)pl * a.r_zstride + (long long)y * a.r_ystride + x;
+        put<TO>(a.R, o, r[c]);
+      }
+    } else if (xout) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const long long o = c * a.r_cstride + (long long)pl * a.r_zstride + (long long)y * a.r_ystride + x;
+        put<TO>(a.R, o, 0.0);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      um[c] = uc[c];
+      uc[c] = up[c];
+      up[c] = nup[c];
+      f[c] = nf[c];
+      hl[c] = nhl[c];
+      hr[c] = nhr[c];
+    }
+  }
+
+  block_reduce4<R2X / 64>(s_r, mn, mx, s_f);
+  if (threadIdx.x == 0) {
+    double* pp = a.partials + 4LL * tile;  // tile = (pl * gy + by) * gx + bx
+    pp[0] = s_r;
+    pp[1] = mn;
+    pp[2] = mx;
+    pp[3] = s_f;
+  }
+}
+
+static dim3 residual_grid(int ox, int oy, int oz, int rz, bool planar) {
+  if (planar) return dim3((ox + R2X - 1) / R2X, (oy + R2Y - 1) / R2Y, oz);
   return dim3((ox + RX - 1) / RX, (oy + RY - 1) / RY, (oz + rz - 1) / rz);
 }
 
-int residual_max_blocks(int ox, int oy, int oz, int rz) {
-  const dim3 g = residual_grid(ox, oy, oz, rz);
+int residual_max_blocks(int ox, int oy, int oz, int rz, bool planar) {
+  const dim3 g = residual_grid(ox, oy, oz, rz, planar);
   return (int)(g.x * g.y * g.z);
 }
 
 template <int NL>
-static void launch_nl(const ResidualArgs& a, dim3 g, hipStream_t st) {
+static void launch_nl(const ResidualArgs& a, dim3 g, bool planar, hipStream_t st) {
+  if (planar) {
+    if (a.out_prec == 0)
+      hipLaunchKernelGGL((k_residual2d<NL, double>), g, dim3(R2X), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_residual2d<NL, float>), g, dim3(R2X), 0, st, a);
+    return;
+  }
   if (a.out_prec == 0)
     hipLaunchKernelGGL((k_residual<NL, double>), g, dim3(RX, RY), 0, st, a);
   else
@@ -243,12 +382,14 @@ static void launch_nl(const ResidualArgs& a, dim3 g, hipStream_t st) {
 }
 
 hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t st) {
-  const dim3 g = residual_grid(a.ox, a.oy, a.oz, a.rz);
+  // planes without z coupling (2D problems, batched instances): the planar kernel
+  const bool planar = a.ihz2 == 0.0;
+  const dim3 g = residual_grid(a.ox, a.oy, a.oz, a.rz, planar);
   *nblocks_out = (int)(g.x * g.y * g.z);
   switch (a.nl) {
-    case NL_CUBIC: launch_nl<NL_CUBIC>(a, g, st); break;
-    case NL_QUASILIN: launch_nl<NL_QUASILIN>(a, g, st); break;
-    default: launch_nl<NL_SYS2>(a, g, st); break;
+    case NL_CUBIC: launch_nl<NL_CUBIC>(a, g, planar, st); break;
+    case NL_QUASILIN: launch_nl<NL_QUASILIN>(a, g, planar, st); break;
+    default: launch_nl<NL_SYS2>(a, g, planar, st); break;
   }
   return hipGetLastError();
 }
