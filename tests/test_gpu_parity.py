@@ -18,7 +18,8 @@ import synth
 from oracle import operators as ops
 from oracle import qn as oqn
 from oracle import tensor as otensor
-from paper_2502_03611_amd import Solver, QN_OK, QN_ERR_NOT_CONVERGED, QN_ERR_DIVERGED
+from paper_2502_03611_amd import Solver, QN_OK, QN_ERR_NOT_CONVERGED, QN_ERR_DIVERGED, QN_ERR_INVALID
+from paper_2502_03611_amd._binding import QNError
 
 pytestmark = pytest.mark.gpu
 
@@ -260,6 +261,49 @@ def test_divergence_flagged_on_nan_source():
     u = torch.zeros((1, 31, 31), dtype=torch.float64, device="cuda")
     st = s.iterate(u, dev(f[None]))
     assert st["status"] == QN_ERR_DIVERGED
+
+
+@pytest.mark.parametrize("kind,shape", [("cubic", (31, 33)), ("system", (17, 19, 23)),
+                                        ("quasilinear", (20, 24, 28))])
+def test_max_iter_zero_reports_the_initial_residual(kind, shape):
+    """max_iter = 0: no solve, U untouched, relres = relres0 = ||F^h(U_0)|| / ||F||."""
+    ncomp = 2 if kind == "system" else 1
+    u0 = synth.random_field((ncomp,) + shape, 401, scale=0.5)
+    f = synth.random_field((ncomp,) + shape, 402, scale=10.0)
+    s = Solver(shape, kind, beta=0.0 if kind == "quasilinear" else 1.0)
+    u = dev(u0)
+    st = s.iterate(u, dev(f), rtol=1e-10, max_iter=0)
+    assert st["status"] == QN_ERR_NOT_CONVERGED and st["iters"] == 0
+    assert torch.equal(u, dev(u0))
+    expect = np.linalg.norm(oqn.residual(KIND[kind], u0, f)) / np.linalg.norm(f)
+    assert st["relres"] == pytest.approx(expect, rel=1e-10)
+    assert st["relres0"] == st["relres"]
+
+
+@pytest.mark.parametrize("kind,shape", [("cubic", (63, 63)), ("system", (20, 30, 25)),
+                                        ("quasilinear", (33, 20, 31))])
+def test_exact_discrete_solution_needs_no_solve(kind, shape):
+    """Source built from a discrete field (F := A_h U* + N_h(U*)): starting at U*,
+    the first residual already meets the tolerance."""
+    ncomp = 2 if kind == "system" else 1
+    ue = synth.random_field((ncomp,) + shape, 403, scale=0.5)
+    f = oqn.residual(KIND[kind], ue, np.zeros_like(ue))
+    s = Solver(shape, kind, beta=0.0 if kind == "quasilinear" else 1.0)
+    u = dev(ue)
+    st = s.iterate(u, dev(f), rtol=1e-10, max_iter=50)
+    assert st["status"] == QN_OK and st["iters"] == 0 and st["relres"] <= 1e-10
+    assert torch.equal(u, dev(ue))
+
+
+def test_tolerance_met_at_the_start_and_zero_source():
+    ue, f = synth.manufactured_c1(31)
+    s = Solver((31, 31), "cubic", beta=1.0)
+    u = torch.zeros((1, 31, 31), dtype=torch.float64, device="cuda")
+    st = s.iterate(u, dev(f[None]), rtol=1.0, max_iter=10)  # relres(U_0 = 0) = 1
+    assert st["status"] == QN_OK and st["iters"] == 0 and float(u.abs().max()) == 0.0
+    with pytest.raises(QNError) as err:
+        s.iterate(u, torch.zeros_like(u), rtol=1e-10, max_iter=10)
+    assert err.value.status == QN_ERR_INVALID
 
 
 def test_max_iter_leaves_last_iterate_and_resume_is_bitwise():
