@@ -20,8 +20,16 @@
 // accumulators for the same fold rows and write both mirrored outputs.  Only
 // rows / columns below n of a spatial axis are ever read or written.
 //
-// Tiling, LDS staging, XCD-aware tile order and epilogues follow the dense
-// kernels (qn_gemm.hip).
+// Work decomposition: a 256-thread workgroup (four wave64s in a 2 x 2 grid)
+// owns an output tile and walks the contraction in chunks staged in LDS
+// (double-buffered, one barrier per chunk; the global loads of the next chunk
+// are issued before the current chunk's matrix-core work).  Two forms cover
+// the three axes of a C-order (.., z, y, x) tensor: form L (y and z products,
+// contraction over the rows of slabs whose rows are contiguous) and form R
+// (x product, contraction along contiguous rows).  Each XCD (workgroups are
+// dealt round-robin) walks a contiguous range of tiles, so operand panels
+// are reused in its L2.  FP64 uses v_mfma_f64_16x16x4f64, FP32
+// v_mfma_f32_16x16x4f32.
 
 #include "qn_internal.h"
 #include "qn_mfma.h"
