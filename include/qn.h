@@ -50,8 +50,11 @@
  *
  * Ordering: every call is enqueued on the context's stream (options.stream,
  * NULL = the default stream).  qn_residual and qn_fdm_solve are asynchronous.
- * qn_iterate synchronises the stream once per iteration to read the residual
- * norm, and returns when it has stopped.
+ * qn_iterate reads a few scalars back per iteration (the residual norm and
+ * the shift) while the next iteration is already enqueued (a solve whose
+ * iteration has stopped skips itself on the device), and returns after the
+ * stream has drained.  qn_bind_workspace also creates the iteration's
+ * pinned read-back buffer (two small host slots) and events.
  *
  * Errors: every entry point returns a qn_status; nothing aborts or throws
  * across the ABI.  qn_last_error() gives a thread-local message for the last

@@ -105,6 +105,9 @@ struct qn_ctx_s {
   // timing
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
+  // qn_iterate: pinned two-slot ring of per-iteration scalars and their events
+  DevScalars* hring = nullptr;
+  hipEvent_t ring_ev[2] = {nullptr, nullptr};
   double tot_ms[K_COUNT] = {};
   long long launches[K_COUNT] = {};
 
@@ -241,7 +244,8 @@ GemmOperands operands(qn_ctx c, int axis) {
 
 // Residual of U into the padded transform workspace W1 (+ partials), then
 // the on-device finalize with the context's shift rule.
-hipError_t residual_into_ws(qn_ctx c, const double* U, const double* F, double* red_out) {
+hipError_t residual_into_ws(qn_ctx c, const double* U, const double* F, double* red_out,
+                            double rtol = 0.0, int iter = -1, int max_iter = 0) {
   ResidualArgs a{};
   a.U = U;
   a.F = F;
@@ -268,7 +272,7 @@ hipError_t residual_into_ws(qn_ctx c, const double* U, const double* F, double* 
   if (e != hipSuccess) return e;
   return timed(c, K_FINALIZE, [&] {
     return launch_finalize(a.partials, nb, c->scal(), rule_of(c), c->beta, c->lam_min_sum, red_out,
-                           c->stream);
+                           rtol, iter, max_iter, c->stream);
   });
 }
 
@@ -437,9 +441,14 @@ EpiArgs epi_args(qn_ctx c, const double* coef, double* dense) {
   return ep;
 }
 
-hipError_t solve_ws(qn_ctx c, const double* coef, double* dense, int epi_last) {
+// skip (device int, may be NULL): when set, every launch of the solve exits
+// at once (the quasi-Newton loop has stopped).
+hipError_t solve_ws(qn_ctx c, const double* coef, double* dense, int epi_last,
+                    const int* skip = nullptr) {
+  EpiArgs ep = epi_args(c, coef, dense);
+  ep.skip = skip;
   FoldStep st[6];
-  const int ns = solve_plan(c, epi_args(c, coef, dense), epi_last, st);
+  const int ns = solve_plan(c, ep, epi_last, st);
   for (int i = 0; i < ns; ++i) {
     const FoldStep& f = st[i];
     const FoldTile t = step_tile(c, f, i);
@@ -568,7 +577,12 @@ qn_status qn_bind_workspace(qn_ctx c, void* d_ws, size_t bytes) {
   if (bytes < c->need)
     return fail(QN_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, c->need);
   c->ws = (char*)d_ws;
-  hipError_t e = launch_zero(c->ws, c->need, c->stream);
+  hipError_t e = hipSuccess;
+  if (!c->hring) e = hipHostMalloc((void**)&c->hring, 2 * sizeof(DevScalars), hipHostMallocDefault);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i)
+    if (!c->ring_ev[i]) e = hipEventCreateWithFlags(&c->ring_ev[i], hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(c, e, "iteration read-back buffers");
+  e = launch_zero(c->ws, c->need, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "zero workspace");
   for (int a = 0; a < c->dim; ++a) {
     const size_t pp = c->hS[a].size();
@@ -646,7 +660,7 @@ qn_status qn_residual(qn_ctx c, const double* d_U, const double* d_F, double* d_
   if (e == hipSuccess)
     e = timed(c, K_FINALIZE, [&] {
       return launch_finalize(a.partials, nb, c->scal(), rule_of(c), c->beta, c->lam_min_sum, d_red,
-                             c->stream);
+                             0.0, -1, 0, c->stream);
     });
   if (e != hipSuccess) return hip_fail(c, e, "residual launch");
   return QN_OK;
@@ -692,52 +706,57 @@ qn_status qn_iterate(qn_ctx c, double* d_U, const double* d_F, double rtol, int3
   auto elapsed = [&] {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   };
-  DevScalars h{};
-  int k = 0;
-  for (;;) {
-    hipError_t e = residual_into_ws(c, d_U, d_F, nullptr);
-    if (e == hipSuccess) e = hipMemcpyAsync(&h, c->scal(), sizeof h, hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) {
-      st.seconds = elapsed();
-      return finish(hip_fail(c, e, "iteration"));
-    }
+  // Iteration k = residual + reductions + loop decision (finalize, on the
+  // device), then the solve of step k.  The host runs one iteration ahead: it
+  // enqueues iteration k + 1 (whose solve skips itself on the device once
+  // iteration k decided to stop) before it reads iteration k's scalars, so
+  // the GPU does not idle during the read-back.
+  const int* done = &c->scal()->done;
+  auto enqueue = [&](int k) {
+    hipError_t e = hipSuccess;
+    if (k > 0) e = solve_ws(c, &c->scal()->scale, d_U, EPI_SUB_DENSE, done);
+    if (e == hipSuccess) e = residual_into_ws(c, d_U, d_F, nullptr, rtol, k, max_iter);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&c->hring[k & 1], c->scal(), sizeof(DevScalars), hipMemcpyDeviceToHost,
+                         c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->ring_ev[k & 1], c->stream);
+    return e;
+  };
+  auto drain = [&](qn_status r) {
+    const hipError_t e = hipStreamSynchronize(c->stream);
+    st.seconds = elapsed();
+    if (e != hipSuccess) return finish(hip_fail(c, e, "iteration"));
+    return finish(r);
+  };
+  hipError_t e = enqueue(0);
+  for (int k = 0; e == hipSuccess; ++k) {
+    e = enqueue(k + 1);
+    if (e == hipSuccess) e = hipEventSynchronize(c->ring_ev[k & 1]);
+    if (e != hipSuccess) break;
+    const DevScalars h = c->hring[k & 1];
     if (k == 0) {
-      if (h.sumsqF == 0.0) {
-        st.seconds = elapsed();
-        return finish(fail(QN_ERR_INVALID, "||F|| = 0: the relative stopping rule is undefined"));
-      }
+      if (h.sumsqF == 0.0)
+        return drain(fail(QN_ERR_INVALID, "||F|| = 0: the relative stopping rule is undefined"));
       st.relres0 = h.relres;
     }
     st.relres = h.relres;
     st.iters = k;
-    if (!std::isfinite(h.relres) || h.relres > 1e30) {
-      st.seconds = elapsed();
-      return finish(fail(QN_ERR_DIVERGED, "residual became non-finite or exploded at iteration %d", k));
-    }
+    if (!std::isfinite(h.relres) || h.relres > 1e30)
+      return drain(fail(QN_ERR_DIVERGED, "residual became non-finite or exploded at iteration %d", k));
     if (h.relres <= rtol) {
-      st.seconds = elapsed();
       g_err.clear();
-      return finish(QN_OK);
+      return drain(QN_OK);
     }
-    if (k >= max_iter) {
-      st.seconds = elapsed();
-      return finish(fail(QN_ERR_NOT_CONVERGED, "no convergence in %d solves (relres %.3e)", k,
-                         h.relres));
-    }
-    if (h.flag != 0.0) {
-      st.seconds = elapsed();
-      return finish(fail(QN_ERR_DIVERGED, "shift rule produced a singular operator at iteration %d", k));
-    }
+    if (k >= max_iter)
+      return drain(fail(QN_ERR_NOT_CONVERGED, "no convergence in %d solves (relres %.3e)", k,
+                        h.relres));
+    if (h.flag != 0.0)
+      return drain(fail(QN_ERR_DIVERGED, "shift rule produced a singular operator at iteration %d", k));
     st.beta_last = h.beta;
     st.scale_last = h.scale;
-    e = solve_ws(c, &c->scal()->scale, d_U, EPI_SUB_DENSE);
-    if (e != hipSuccess) {
-      st.seconds = elapsed();
-      return finish(hip_fail(c, e, "solve"));
-    }
-    ++k;
   }
+  st.seconds = elapsed();
+  return finish(hip_fail(c, e, "iteration"));
 }
 
 qn_status qn_autotune(qn_ctx c) {
@@ -834,9 +853,12 @@ void qn_destroy(qn_ctx c) {
   if (!c->pending.empty()) (void)hipStreamSynchronize(c->stream);
   for (auto& p : c->pending) {
     (void)hipEventDestroy(p.a);
-    hipEventDestroy(p.b);
+    (void)hipEventDestroy(p.b);
   }
-  for (auto e : c->pool) hipEventDestroy(e);
+  for (auto e : c->pool) (void)hipEventDestroy(e);
+  for (auto e : c->ring_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->hring) (void)hipHostFree(c->hring);
   delete c;
 }
 

@@ -22,6 +22,8 @@ struct DevScalars {
   double scale;    // c_k of the current solve
   double beta;     // beta_k of the current solve
   double flag;     // 1 if the solve operator is singular / indefinite
+  int done;        // quasi-Newton loop: stop here (the next solve skips itself)
+  int pad;
 };
 
 // Shift rules executed on device after the residual reduction.
@@ -167,9 +169,13 @@ hipError_t launch_bfinalize(const double* partials, int bpi, int K, BState* st, 
 hipError_t launch_breset(BState* st, int* done, int K, hipStream_t s);
 
 // Fixed-order reduction of the residual partials + shift rule.
+// Final fixed-order reduction of the residual partials, the shift rule and,
+// for iter >= 0, the loop decision: done = the relative residual is <= rtol,
+// non-finite or above 1e30, iter >= max_iter, or the shift rule gives a
+// singular operator.
 hipError_t launch_finalize(const double* partials, int nblocks, DevScalars* sc, int rule,
-                           double beta_fixed, double lam_min_sum, double* red_out,
-                           hipStream_t st);
+                           double beta_fixed, double lam_min_sum, double* red_out, double rtol,
+                           int iter, int max_iter, hipStream_t st);
 
 // Dense (ncomp, nz, ny, nx) fp64 -> padded (ncomp, pz, py, px) fp64/fp32, zero pads.
 hipError_t launch_pad_copy(const double* src, void* dst, int out_prec, int ncomp, int nx, int ny,

@@ -399,7 +399,8 @@ constexpr int FIN_THREADS = 1024;
 __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double* __restrict__ partials,
                                                           int nblocks, DevScalars* sc, int rule,
                                                           double beta_fixed, double lam_min_sum,
-                                                          double* red_out) {
+                                                          double* red_out, double rtol, int iter,
+                                                          int max_iter) {
   double s0 = 0.0, s1 = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
   for (int i = threadIdx.x; i < nblocks; i += FIN_THREADS) {
     s0 += partials[4 * i + 0];
@@ -420,6 +421,8 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double* __restri
     sc->scale = scale;
     sc->beta = beta;
     sc->flag = (scale > 0.0 && scale * lam_min_sum + beta > 0.0) ? 0.0 : 1.0;
+    const double rr = sc->relres;
+    sc->done = iter >= 0 && (!(rr <= 1e30) || rr <= rtol || iter >= max_iter || sc->flag != 0.0);
     if (red_out) {
       red_out[0] = s0;
       red_out[1] = mn;
@@ -430,10 +433,10 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double* __restri
 }
 
 hipError_t launch_finalize(const double* partials, int nblocks, DevScalars* sc, int rule,
-                           double beta_fixed, double lam_min_sum, double* red_out,
-                           hipStream_t st) {
+                           double beta_fixed, double lam_min_sum, double* red_out, double rtol,
+                           int iter, int max_iter, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, st, partials, nblocks, sc, rule,
-                     beta_fixed, lam_min_sum, red_out);
+                     beta_fixed, lam_min_sum, red_out, rtol, iter, max_iter);
   return hipGetLastError();
 }
 
