@@ -7,8 +7,9 @@
 //   -> forward mode products x, y(, z) with the spectral divide fused into the
 //   last one -> inverse mode products (z,) y, x with U -= dU fused into the
 //   last one (Section 4.1 eq. fin_inverse, Section 4 eq. identity-method).
-// All work is enqueued on the context's stream; qn_iterate reads four
-// scalars back per iteration to test the stopping rule.
+// All work is enqueued on the context's stream; qn_iterate takes the stopping
+// decision on the device and reads the scalars of each iteration back while
+// the next one is already queued.
 
 #include <hip/hip_runtime.h>
 
@@ -165,7 +166,7 @@ hipError_t timed(qn_ctx c, int kid, Fn fn) {
 
 void fold_timing(qn_ctx c) {
   if (c->pending.empty()) return;
-  hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->stream);
   for (auto& p : c->pending) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
