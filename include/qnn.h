@@ -11,7 +11,8 @@
  * initial guess.  (A U = f - U^3 holds exactly at the solution, so a
  * prediction of U^3 turns into a smooth, globally consistent U_0, which a
  * 3x3 network with an 11 x 11 receptive field cannot produce directly.)
- * Callers fall back to U_0 = 0 when the guess has a larger residual.
+ * Callers fall back to U_0 = 0 when the guess has a larger residual
+ * (qnn_guess_fallback takes that decision on the device).
  *
  * Network: five 3x3 cross-correlation layers with zero "same" padding,
  * channels 2 -> 32 -> 32 -> 32 -> 32 -> 1, exact GELU x*Phi(x) after layers
@@ -67,6 +68,15 @@ qn_status qnn_get_grads(qnn_net net, float* h_grads);
  * the caller's A_h^-1 f (asynchronous).  d_out may not alias d_f or d_v. */
 qn_status qnn_forward(qnn_net net, const double* d_f, const double* d_v, int32_t batch,
                       double* d_out);
+
+/* Fallback to U_0 = 0, stream-ordered and without a host round trip.
+ * d_red is the device[4] reduction that qn_residual wrote for the guess
+ * d_u0 (H x W, FP64): {sum R^2, min mu, max mu, sum F^2}.  When
+ * !(sum R^2 < sum F^2), i.e. the guess's residual is not smaller than that of
+ * U_0 = 0 (whose residual is -F) or is not finite, every entry of d_u0 is set
+ * to zero.  d_used (device int32, may be NULL) receives 1 when the guess is
+ * kept and 0 otherwise.  One image (batch 1); asynchronous. */
+qn_status qnn_guess_fallback(qnn_net net, const double* d_red, double* d_u0, int32_t* d_used);
 
 /* Forward, MSE loss of g against d_target (the nonlinear term at the
  * solution) and backward; gradients are kept in the workspace.  *h_loss (may

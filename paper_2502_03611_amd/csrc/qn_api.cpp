@@ -13,6 +13,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -267,7 +268,7 @@ hipError_t residual_into_ws(qn_ctx c, const double* U, const double* F, double* 
   a.ihy2 = (double)(c->n[1] + 1) * (c->n[1] + 1);
   a.ihz2 = c->dim == 3 ? (double)(c->n[2] + 1) * (c->n[2] + 1) : 0.0;
   a.partials = c->at<double>(c->off_part);
-  a.rz = RESIDUAL_RZ;
+  a.rz = c->dim == 3 ? RESIDUAL_RZ : residual_planar_rows(a.ox, a.oy);
   int nb = 0;
   hipError_t e = timed(c, K_RESIDUAL, [&] { return launch_residual(a, &nb, c->stream); });
   if (e != hipSuccess) return e;
@@ -552,7 +553,14 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   off += align256(c->tensor_elems() * c->elem());
   c->off_W2 = off;
   off += align256(c->tensor_elems() * c->elem());
-  c->max_blocks = residual_max_blocks(c->p[0], c->p[1], c->p[2], RESIDUAL_RZ, c->dim == 2);
+  // partial slots for both residual launches: padded (the iteration) and
+  // interior (qn_residual) extents
+  if (c->dim == 3)
+    c->max_blocks = residual_max_blocks(c->p[0], c->p[1], c->p[2], RESIDUAL_RZ, false);
+  else
+    c->max_blocks = std::max(
+        residual_max_blocks(c->p[0], c->p[1], 1, residual_planar_rows(c->p[0], c->p[1]), true),
+        residual_max_blocks(c->n[0], c->n[1], 1, residual_planar_rows(c->n[0], c->n[1]), true));
   c->off_part = off;
   off += align256((size_t)c->max_blocks * 4 * sizeof(double));
   c->off_scal = off;
@@ -655,7 +663,7 @@ qn_status qn_residual(qn_ctx c, const double* d_U, const double* d_F, double* d_
   a.ihy2 = (double)(c->n[1] + 1) * (c->n[1] + 1);
   a.ihz2 = c->dim == 3 ? (double)(c->n[2] + 1) * (c->n[2] + 1) : 0.0;
   a.partials = c->at<double>(c->off_part);
-  a.rz = RESIDUAL_RZ;
+  a.rz = c->dim == 3 ? RESIDUAL_RZ : residual_planar_rows(a.ox, a.oy);
   int nb = 0;
   hipError_t e = timed(c, K_RESIDUAL, [&] { return launch_residual(a, &nb, c->stream); });
   if (e == hipSuccess)

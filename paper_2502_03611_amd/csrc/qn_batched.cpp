@@ -143,7 +143,7 @@ hipError_t class_iteration(qnb_ctx c, Cls& k, double* U, const double* F, double
   a.ihx2 = a.ihy2 = (double)(k.n + 1) * (k.n + 1);
   a.ihz2 = 0.0;
   a.partials = (double*)(c->ws + k.off_part);
-  a.rz = 1;
+  a.rz = RESIDUAL_PLANAR_ROWS;
   a.skip = (const int*)(c->ws + k.off_done);
   int nb = 0;
   hipError_t e = launch_residual(a, &nb, s);
@@ -282,7 +282,7 @@ qn_status qnb_setup(int32_t count, const int32_t* n, const int32_t* ncomp, int32
     off += a256(te);
     k.off_W2 = off;
     off += a256(te);
-    k.bpi = residual_max_blocks(k.p, k.p, 1, 1, true);
+    k.bpi = residual_max_blocks(k.p, k.p, 1, RESIDUAL_PLANAR_ROWS, true);
     k.off_part = off;
     off += a256((size_t)k.bpi * k.K * 4 * sizeof(double));
     k.off_state = off;

@@ -143,7 +143,7 @@ struct ResidualArgs {
   int dim, nl;
   double ihx2, ihy2, ihz2; // 1/h^2 per axis
   double* partials;        // per-block {sumR2, mumin, mumax, sumF2}
-  int rz;                  // z-planes per workgroup (the batched solver uses 1)
+  int rz;                  // 3D: z-planes per workgroup; planar: y-rows per workgroup
   const int* skip;         // batched solver: per-z-plane (instance) skip flags, else NULL
 };
 hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t st);
@@ -151,7 +151,11 @@ hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t 
 // (1/h_z^2 = 0: 2D problems and the batched solver), which uses the planar
 // kernel with oz planes.
 int residual_max_blocks(int ox, int oy, int oz, int rz, bool planar);
-constexpr int RESIDUAL_RZ = 32;  // z-slab depth of a single 3D problem
+constexpr int RESIDUAL_RZ = 32;          // z-slab depth of a single 3D problem
+constexpr int RESIDUAL_PLANAR_ROWS = 16;  // rows per workgroup, many planes per launch
+// Rows per workgroup of the planar residual over one ox x oy plane: 16,
+// halved until the plane gives at least 1024 workgroups (or 1 row).
+int residual_planar_rows(int ox, int oy);
 
 // Per-instance state of the batched solver.  scale and beta are adjacent so
 // the divide epilogue can read them as {scale, beta}.

@@ -226,13 +226,15 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
 }
 
 // Planar residual (2D problems and the batched solver's instances, 1/h_z^2 =
-// 0): each wave owns 64 consecutive x and marches R2Y rows in y, keeping
+// 0): each wave owns 64 consecutive x and marches a.rz rows in y, keeping
 // U(y-1), U(y), U(y+1) of its column in registers; x-neighbours come from the
 // adjacent lanes (wave shuffles), the two strip-edge columns from global
 // memory.  No LDS staging and no barriers in the march; the loads of row y+1
 // are issued before row y is computed.  A workgroup (4 waves, 256 columns)
-// stays inside one plane, so its partials belong to one instance.
-constexpr int R2X = 256, R2Y = 16;
+// stays inside one plane, so its partials belong to one instance.  Many
+// planes per launch march 16 rows; a single small plane takes fewer rows per
+// workgroup so that it still spreads over about a thousand workgroups.
+constexpr int R2X = 256;
 
 template <int NL, typename TO>
 __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
@@ -244,7 +246,7 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
   if (a.skip && a.skip[pl]) return;  // batched solver: finished instance
   const int nx = a.nx, ny = a.ny;
   const int x = bx * R2X + threadIdx.x;
-  const int y0 = by * R2Y, y1 = min(y0 + R2Y, a.oy);
+  const int y0 = by * a.rz, y1 = min(y0 + a.rz, a.oy);
   const long long plane = (long long)nx * ny;
   const long long comp = plane * a.nz;
   const bool xin = x < nx, xout = x < a.ox;
@@ -357,8 +359,15 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
 }
 
 static dim3 residual_grid(int ox, int oy, int oz, int rz, bool planar) {
-  if (planar) return dim3((ox + R2X - 1) / R2X, (oy + R2Y - 1) / R2Y, oz);
+  if (planar) return dim3((ox + R2X - 1) / R2X, (oy + rz - 1) / rz, oz);
   return dim3((ox + RX - 1) / RX, (oy + RY - 1) / RY, (oz + rz - 1) / rz);
+}
+
+int residual_planar_rows(int ox, int oy) {
+  const long long gx = (ox + R2X - 1) / R2X;
+  int r = RESIDUAL_PLANAR_ROWS;
+  while (r > 1 && gx * ((oy + r - 1) / r) < 1024) r >>= 1;
+  return r;
 }
 
 int residual_max_blocks(int ox, int oy, int oz, int rz, bool planar) {

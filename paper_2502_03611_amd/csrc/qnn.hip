@@ -8,10 +8,11 @@
 // on v_mfma_f32_16x16x4f32 with the input tile and its one-pixel halo staged
 // in LDS; channel strides in LDS are padded (36 / 48 floats) so the 16 pixels
 // or 16 channels of a fragment fall on distinct banks.  The 2 -> 32 and
-// 32 -> 1 layers are small VALU kernels.  Weight gradients are reduced by
+// 32 -> 1 layers are small VALU kernels with coalesced 128-byte channel runs.  Weight gradients are reduced by
 // writing one partial per workgroup and summing the partials in a fixed order,
 // so every result is bitwise reproducible.
 
+#include <algorithm>
 #include <cmath>
 
 #include "qnn_internal.h"
@@ -30,40 +31,61 @@ __device__ inline float gelu_grad(float x) {
 // ---------------------------------------------------------------- layer 1
 
 // Layer 1: x0 = (f / 50, v0); z1 = b1 + W1 * x0; a1 = gelu(z1).  One thread
-// per pixel; W1 is (32, 2, 3, 3).
-__global__ __launch_bounds__(256) void k_in_fwd(const double* __restrict__ f,
-                                                const double* __restrict__ v,
-                                                const float* __restrict__ p1,
-                                                float* __restrict__ x0, float* __restrict__ z1,
-                                                float* __restrict__ a1, int H, int W, int npix) {
+// per pixel computes all 32 channels; the weights (32, 2, 3, 3) are staged in
+// LDS and read at wave-uniform addresses (broadcast).  The 128 x 32 outputs of a workgroup
+// go through LDS (row stride 33: conflict-free columns) so that the stores are
+// one contiguous 16 KB run.  TRAIN also keeps x0 and z1 for the backward pass.
+constexpr int L1_PX = 128;
+template <bool TRAIN>
+__global__ __launch_bounds__(L1_PX) void k_in_fwd(const double* __restrict__ f,
+                                                  const double* __restrict__ v,
+                                                  const float* __restrict__ p1,
+                                                  float* __restrict__ x0, float* __restrict__ z1,
+                                                  float* __restrict__ a1, int H, int W,
+                                                  long long npix) {
   __shared__ float sw[L1_SIZE];
-  for (int i = threadIdx.x; i < L1_SIZE; i += 256) sw[i] = p1[i];
+  __shared__ float sz[TRAIN ? L1_PX * 33 : 1];
+  __shared__ float sa[L1_PX * 33];
+  const int l = threadIdx.x;
+  for (int i = l; i < L1_SIZE; i += L1_PX) sw[i] = p1[i];
   __syncthreads();
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= npix) return;
-  const int x = p % W, y = (p / W) % H, b = p / (W * H);
-  float nb[CIN0][9];
+  const long long p0 = (long long)blockIdx.x * L1_PX, p = p0 + l;
+  if (p < npix) {
+    const int x = (int)(p % W), y = (int)((p / W) % H);
+    const long long b = p / ((long long)W * H);
+    float nb[CIN0][9];
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-    const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
-    const long long q = ((long long)b * H + yy) * W + xx;
-    nb[0][t] = in ? (float)(f[q] * (1.0 / 50.0)) : 0.0f;
-    nb[1][t] = in ? (float)v[q] : 0.0f;
-  }
-  x0[2LL * p] = nb[0][4];
-  x0[2LL * p + 1] = nb[1][4];
-  float* zo = z1 + (long long)p * 32;
-  float* ao = a1 + (long long)p * 32;
+    for (int t = 0; t < 9; ++t) {
+      const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+      const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+      const long long q = (b * H + yy) * W + xx;
+      nb[0][t] = in ? (float)(f[q] * (1.0 / 50.0)) : 0.0f;
+      nb[1][t] = in ? (float)v[q] : 0.0f;
+    }
+    if (TRAIN) {
+      x0[2 * p] = nb[0][4];
+      x0[2 * p + 1] = nb[1][4];
+    }
 #pragma unroll 4
-  for (int c = 0; c < 32; ++c) {
-    float s = sw[32 * CIN0 * 9 + c];
+    for (int c = 0; c < 32; ++c) {
+      float s = sw[32 * CIN0 * 9 + c];
 #pragma unroll
-    for (int ci = 0; ci < CIN0; ++ci)
+      for (int ci = 0; ci < CIN0; ++ci)
 #pragma unroll
-      for (int t = 0; t < 9; ++t) s += sw[(c * CIN0 + ci) * 9 + t] * nb[ci][t];
-    zo[c] = s;
-    ao[c] = gelu(s);
+        for (int t = 0; t < 9; ++t) s += sw[(c * CIN0 + ci) * 9 + t] * nb[ci][t];
+      if (TRAIN) sz[l * 33 + c] = s;
+      sa[l * 33 + c] = gelu(s);
+    }
+  }
+  __syncthreads();
+  const int np = (int)min((long long)L1_PX, npix - p0);
+#pragma unroll 4
+  for (int j = 0; j < 32; ++j) {
+    const int idx = j * L1_PX + l, px = idx >> 5, c = idx & 31;
+    if (px < np) {
+      if (TRAIN) z1[(p0 + px) * 32 + c] = sz[px * 33 + c];
+      a1[(p0 + px) * 32 + c] = sa[px * 33 + c];
+    }
   }
 }
 
@@ -72,13 +94,17 @@ __global__ __launch_bounds__(256) void k_in_fwd(const double* __restrict__ f,
 constexpr int CT_Y = 16, CT_X = 32;         // output pixel tile
 constexpr int HY = CT_Y + 2, HX = CT_X + 2;  // with halo
 constexpr int CP = 36;                       // LDS channel stride (floats)
-constexpr int WS = 48;                       // LDS weight row stride (floats)
+constexpr int CH = 16;                       // output channels per workgroup
 
-// MODE 0 (forward):  z = bias + sum_k in[p + tap][ci] * Wk[k][co]; writes z and gelu(z).
+// MODE 0 (forward):  z = bias + sum_k in[p + tap][ci] * Wk[k][co]; writes gelu(z),
+// and z too when out0 is not null (training keeps it for the backward pass).
 // MODE 1 (backward-data): g = (sum_k dz[p - tap][co] * Wk[k][ci]) * gelu'(zprev[p][ci]).
 // Wk is the k-major weight matrix (288 x 32) prepared by k_prep_weights
-// (flipped taps for MODE 1).  One workgroup = 8 waves = a 16 x 32 pixel tile;
-// wave w owns rows 2w, 2w+1 (4 MFMA row blocks of 16 pixels) x 32 channels.
+// (flipped taps for MODE 1).  One workgroup = 8 waves = a 16 x 32 pixel tile
+// and one half (16) of the 32 output channels, so a single 255 x 255 image
+// still spreads over 256 workgroups; wave w owns rows 2w, 2w+1 (4 MFMA row
+// blocks of 16 pixels).  The weight half sits in LDS with row stride 16: the
+// four k rows of a fragment then fall on distinct banks.
 template <int MODE>
 __global__ __launch_bounds__(512) void k_conv32(const float* __restrict__ in,
                                                 const float* __restrict__ wk,
@@ -87,18 +113,21 @@ __global__ __launch_bounds__(512) void k_conv32(const float* __restrict__ in,
                                                 float* __restrict__ out0, float* __restrict__ out1,
                                                 int H, int W, int tiles_x, int tiles_y) {
   __shared__ __attribute__((aligned(16))) float s_in[HY * HX * CP];
-  __shared__ __attribute__((aligned(16))) float s_w[288 * WS];
+  __shared__ __attribute__((aligned(16))) float s_w[288 * CH];
   const int tid = threadIdx.x;
   int t = blockIdx.x;
+  const int half = t & 1;
+  t >>= 1;
   const int tx = t % tiles_x;
   t /= tiles_x;
   const int ty = t % tiles_y;
   const int b = t / tiles_y;
   const int y0 = ty * CT_Y, x0 = tx * CT_X;
 
-  for (int i = tid; i < 288 * 8; i += 512) {
-    const int k = i >> 3, c4 = i & 7;
-    *reinterpret_cast<float4*>(&s_w[k * WS + c4 * 4]) = reinterpret_cast<const float4*>(wk)[i];
+  for (int i = tid; i < 288 * 4; i += 512) {
+    const int k = i >> 2, c4 = i & 3;
+    *reinterpret_cast<float4*>(&s_w[k * CH + c4 * 4]) =
+        reinterpret_cast<const float4*>(wk)[k * 8 + half * 4 + c4];
   }
   for (int i = tid; i < HY * HX * 8; i += 512) {
     const int c4 = i & 7, pix = i >> 3;
@@ -113,24 +142,23 @@ __global__ __launch_bounds__(512) void k_conv32(const float* __restrict__ in,
 
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  f4v acc[4][2];
+  f4v acc[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) acc[i][0] = acc[i][1] = f4v{0, 0, 0, 0};
+  for (int i = 0; i < 4; ++i) acc[i] = f4v{0, 0, 0, 0};
   for (int tap = 0; tap < 9; ++tap) {
     const int dy = tap / 3, dx = tap % 3;
 #pragma unroll
     for (int c0 = 0; c0 < 32; c0 += 4) {
-      const int k = tap * 32 + c0 + lk;
-      const float b0 = s_w[k * WS + lr], b1 = s_w[k * WS + 16 + lr];
+      const float bw = s_w[(tap * 32 + c0 + lk) * CH + lr];
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb) {
         const int r = 2 * wave + (mb >> 1), xh = (mb & 1) * 16;
         const float a = s_in[((r + dy) * HX + xh + lr + dx) * CP + c0 + lk];
-        acc[mb][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc[mb][0], 0, 0, 0);
-        acc[mb][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b1, acc[mb][1], 0, 0, 0);
+        acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bw, acc[mb], 0, 0, 0);
       }
     }
   }
+  const int c = half * CH + lr;
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb) {
     const int y = y0 + 2 * wave + (mb >> 1);
@@ -139,17 +167,13 @@ __global__ __launch_bounds__(512) void k_conv32(const float* __restrict__ in,
       const int x = x0 + (mb & 1) * 16 + 4 * lk + q;
       if (y >= H || x >= W) continue;
       const long long base = (((long long)b * H + y) * W + x) * 32;
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int c = j * 16 + lr;
-        const float v = acc[mb][j][q];
-        if (MODE == 0) {
-          const float z = v + bias[c];
-          out0[base + c] = z;
-          out1[base + c] = gelu(z);
-        } else {
-          out0[base + c] = v * gelu_grad(zprev[base + c]);
-        }
+      const float v = acc[mb][q];
+      if (MODE == 0) {
+        const float z = v + bias[c];
+        if (out0) out0[base + c] = z;
+        out1[base + c] = gelu(z);
+      } else {
+        out0[base + c] = v * gelu_grad(zprev[base + c]);
       }
     }
   }
@@ -233,29 +257,56 @@ __global__ __launch_bounds__(256) void k_conv32_wgrad(const float* __restrict__ 
 
 // ---------------------------------------------------------------- layer 5
 
-// out = b5 + sum_{tap, ci} W5[ci][tap] * a4[p + tap][ci]
+// g = b5 + sum_{tap, ci} W5[ci][tap] * a4[p + tap][ci].  Eight lanes per pixel,
+// lane c4 over channels 4 c4 .. 4 c4 + 3 of all nine taps (one 16-byte load per
+// tap; the eight lanes of a pixel cover its 128-byte channel run), then a
+// fixed-order butterfly sum over the eight lanes.  Each lane keeps its 36
+// weights in registers (staged through LDS once per workgroup) and walks the
+// pixels with a grid stride.  SRC = false stores g (FP32, training); SRC = true
+// stores the corrected source f - g in FP64.
+template <bool SRC>
 __global__ __launch_bounds__(256) void k_out_fwd(const float* __restrict__ a4,
                                                  const float* __restrict__ p5,  // W5 (32x9), b5
-                                                 float* __restrict__ out, int H, int W, int npix) {
+                                                 const double* __restrict__ f,
+                                                 float* __restrict__ out,
+                                                 double* __restrict__ out64, int H, int W,
+                                                 int npix) {
   __shared__ float sw[289];
   for (int i = threadIdx.x; i < 289; i += 256) sw[i] = p5[i];
   __syncthreads();
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= npix) return;
-  const int x = p % W, y = (p / W) % H, b = p / (W * H);
-  float s = sw[288];
-  for (int t = 0; t < 9; ++t) {
-    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-    if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-    const float4* src = reinterpret_cast<const float4*>(a4 + (((long long)b * H + yy) * W + xx) * 32);
+  const int c4 = threadIdx.x & 7;
+  float w[4][9];
 #pragma unroll
-    for (int c4 = 0; c4 < 8; ++c4) {
-      const float4 v = src[c4];
-      s += sw[(4 * c4 + 0) * 9 + t] * v.x + sw[(4 * c4 + 1) * 9 + t] * v.y +
-           sw[(4 * c4 + 2) * 9 + t] * v.z + sw[(4 * c4 + 3) * 9 + t] * v.w;
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int t = 0; t < 9; ++t) w[j][t] = sw[(4 * c4 + j) * 9 + t];
+  const float bias = sw[288];
+  const long long stride = (long long)gridDim.x * 32;
+  // The trip count is uniform across each group of eight lanes, so the
+  // shuffles below always find their partners.
+  for (long long p = ((long long)blockIdx.x * 256 + threadIdx.x) >> 3; p < npix; p += stride) {
+    const int x = (int)(p % W), y = (int)((p / W) % H);
+    const long long b = p / ((long long)W * H);
+    float s = 0.f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+        v = reinterpret_cast<const float4*>(a4 + ((b * H + yy) * W + xx) * 32)[c4];
+      s += w[0][t] * v.x + w[1][t] * v.y + w[2][t] * v.z + w[3][t] * v.w;
+    }
+    s += __shfl_xor(s, 1, 8);
+    s += __shfl_xor(s, 2, 8);
+    s += __shfl_xor(s, 4, 8);
+    if (c4 == 0) {
+      const float g = bias + s;
+      if (SRC)
+        out64[p] = f[p] - (double)g;
+      else
+        out[p] = g;
     }
   }
-  out[p] = s;
 }
 
 // gout = 2 (out - target) / npix; per-block partial of sum (out - target)^2.
@@ -413,42 +464,59 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
   p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
 }
 
-// out = f - g in FP64: the source corrected by the predicted nonlinear term.
-__global__ __launch_bounds__(256) void k_src_minus(const double* __restrict__ f,
-                                                   const float* __restrict__ g,
-                                                   double* __restrict__ out, int n) {
+// u0 = 0 unless red[0] < red[3] (the guess's sum R^2 below sum F^2, the
+// residual of U_0 = 0); used = whether the guess is kept.
+__global__ __launch_bounds__(256) void k_guess_fallback(const double* __restrict__ red,
+                                                        double* __restrict__ u0,
+                                                        int* __restrict__ used, int n) {
+  const bool keep = red[0] < red[3];
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) out[i] = f[i] - (double)g[i];
+  if (i == 0 && used) used[0] = keep ? 1 : 0;
+  if (!keep && i < n) u0[i] = 0.0;
 }
 
 // ---------------------------------------------------------------- launchers
 
 static unsigned blocks(long long n, int per) { return (unsigned)((n + per - 1) / per); }
 
-hipError_t forward(const Buffers& B, const double* f, const double* v, int batch, hipStream_t st) {
-  const int H = B.H, W = B.W;
-  const int npix = batch * H * W;
+template <int MODE>
+static void launch_conv32(const float* in, const float* wk, const float* bias, const float* zprev,
+                          float* out0, float* out1, int H, int W, int batch, hipStream_t st) {
   const int tx = (W + CT_X - 1) / CT_X, ty = (H + CT_Y - 1) / CT_Y;
-  hipLaunchKernelGGL(k_in_fwd, dim3(blocks(npix, 256)), dim3(256), 0, st, f, v, B.params + OFF_L1,
-                     B.x0, B.z[0], B.a[0], H, W, npix);
-  for (int l = 1; l < 4; ++l)
-    hipLaunchKernelGGL((k_conv32<0>), dim3((unsigned)(tx * ty * batch)), dim3(512), 0, st,
-                       B.a[l - 1], B.wf[l - 1], B.params + layer_offset(l) + 9216, (const float*)nullptr,
-                       B.z[l], B.a[l], H, W, tx, ty);
-  hipLaunchKernelGGL(k_out_fwd, dim3(blocks(npix, 256)), dim3(256), 0, st, B.a[3], B.params + OFF_L5,
-                     B.out, H, W, npix);
-  return hipGetLastError();
+  hipLaunchKernelGGL((k_conv32<MODE>), dim3((unsigned)(2 * tx * ty * batch)), dim3(512), 0, st, in,
+                     wk, bias, zprev, out0, out1, H, W, tx, ty);
 }
 
-hipError_t output_f64(const Buffers& B, const double* f, int batch, double* out, hipStream_t st) {
-  const int npix = batch * B.H * B.W;
-  hipLaunchKernelGGL(k_src_minus, dim3(blocks(npix, 256)), dim3(256), 0, st, f, B.out, out, npix);
+hipError_t forward(const Buffers& B, const double* f, const double* v, int batch, double* out64,
+                   hipStream_t st) {
+  const int H = B.H, W = B.W;
+  const int npix = batch * H * W;
+  const bool train = out64 == nullptr;
+  // Grid-stride kernels: at most eight workgroups per compute unit.
+  const unsigned g1 = blocks(npix, L1_PX);
+  if (train)
+    hipLaunchKernelGGL((k_in_fwd<true>), dim3(g1), dim3(L1_PX), 0, st, f, v, B.params + OFF_L1,
+                       B.x0, B.z[0], B.a[0], H, W, (long long)npix);
+  else
+    hipLaunchKernelGGL((k_in_fwd<false>), dim3(g1), dim3(L1_PX), 0, st, f, v, B.params + OFF_L1,
+                       (float*)nullptr, (float*)nullptr, B.a[0], H, W, (long long)npix);
+  for (int l = 1; l < 4; ++l)
+    launch_conv32<0>(B.a[l - 1], B.wf[l - 1], B.params + layer_offset(l) + 9216,
+                     (const float*)nullptr, train ? B.z[l] : (float*)nullptr, B.a[l], H, W, batch,
+                     st);
+  const unsigned g8 = std::min(blocks(8LL * npix, 256), 2048u);
+  if (train)
+    hipLaunchKernelGGL((k_out_fwd<false>), dim3(g8), dim3(256), 0, st, B.a[3], B.params + OFF_L5,
+                       f, B.out, (double*)nullptr, H, W, npix);
+  else
+    hipLaunchKernelGGL((k_out_fwd<true>), dim3(g8), dim3(256), 0, st, B.a[3], B.params + OFF_L5,
+                       f, (float*)nullptr, out64, H, W, npix);
   return hipGetLastError();
 }
 
 hipError_t loss_grad(const Buffers& B, const double* f, const double* v, const double* target,
                      int batch, hipStream_t st) {
-  hipError_t e = forward(B, f, v, batch, st);
+  hipError_t e = forward(B, f, v, batch, nullptr, st);
   if (e != hipSuccess) return e;
   const int H = B.H, W = B.W;
   const int npix = batch * H * W;
@@ -466,16 +534,14 @@ hipError_t loss_grad(const Buffers& B, const double* f, const double* v, const d
   hipLaunchKernelGGL(k_reduce_parts, dim3(blocks(289, 256)), dim3(256), 0, st, B.part, nparts,
                      QNN_SMALL_STRIDE, 289, B.grads + OFF_L5);
   // layers 4, 3, 2: weight gradient from (a[l-1], dz_l), then dz_{l-1}
-  const int tx = (W + CT_X - 1) / CT_X, ty = (H + CT_Y - 1) / CT_Y;
   int cur = 0;
   for (int l = 3; l >= 1; --l) {
     hipLaunchKernelGGL(k_conv32_wgrad, dim3((unsigned)nparts), dim3(256), 0, st, B.a[l - 1],
                        B.d[cur], B.part, H, W, gtx, gty);
     hipLaunchKernelGGL(k_reduce_parts, dim3(blocks(9248, 256)), dim3(256), 0, st, B.part, nparts,
                        QNN_WGRAD_STRIDE, 9248, B.grads + layer_offset(l));
-    hipLaunchKernelGGL((k_conv32<1>), dim3((unsigned)(tx * ty * batch)), dim3(512), 0, st,
-                       B.d[cur], B.wb[l - 1], (const float*)nullptr, B.z[l - 1], B.d[cur ^ 1],
-                       (float*)nullptr, H, W, tx, ty);
+    launch_conv32<1>(B.d[cur], B.wb[l - 1], (const float*)nullptr, B.z[l - 1], B.d[cur ^ 1],
+                     (float*)nullptr, H, W, batch, st);
     cur ^= 1;
   }
   // layer 1
@@ -483,6 +549,11 @@ hipError_t loss_grad(const Buffers& B, const double* f, const double* v, const d
                      B.part, H, W, gtx, gty);
   hipLaunchKernelGGL(k_reduce_parts, dim3(blocks(L1_SIZE, 256)), dim3(256), 0, st, B.part, nparts,
                      QNN_SMALL_STRIDE, L1_SIZE, B.grads + OFF_L1);
+  return hipGetLastError();
+}
+
+hipError_t guess_fallback(const double* red, double* u0, int* used, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_guess_fallback, dim3(blocks(n, 256)), dim3(256), 0, st, red, u0, used, n);
   return hipGetLastError();
 }
 

@@ -226,9 +226,17 @@ qn_status qnn_forward(qnn_net n, const double* d_f, const double* d_v, int32_t b
   if (s != QN_OK) return s;
   if (!d_f || !d_v || !d_out) return bad(QN_ERR_INVALID, "null f, v or out");
   if (batch < 1 || batch > n->max_batch) return bad(QN_ERR_INVALID, "batch out of range");
-  hipError_t e = qnn::forward(n->B, d_f, d_v, batch, n->stream);
-  if (e == hipSuccess) e = qnn::output_f64(n->B, d_f, batch, d_out, n->stream);
+  hipError_t e = qnn::forward(n->B, d_f, d_v, batch, d_out, n->stream);
   if (e != hipSuccess) return hip_bad(n, e, "forward");
+  return QN_OK;
+}
+
+qn_status qnn_guess_fallback(qnn_net n, const double* d_red, double* d_u0, int32_t* d_used) {
+  qn_status s = check(n, false);
+  if (s != QN_OK) return s;
+  if (!d_red || !d_u0) return bad(QN_ERR_INVALID, "null reduction or guess");
+  hipError_t e = qnn::guess_fallback(d_red, d_u0, d_used, n->H * n->W, n->stream);
+  if (e != hipSuccess) return hip_bad(n, e, "guess fallback");
   return QN_OK;
 }
 

@@ -37,12 +37,15 @@ struct Buffers {
   double* loss;   // 1 double
 };
 
-hipError_t forward(const Buffers& B, const double* f, const double* v, int batch, hipStream_t st);
-// out = f - g (FP64), g = network output.
-hipError_t output_f64(const Buffers& B, const double* f, int batch, double* out, hipStream_t st);
+// Network forward.  out64 == nullptr: training (keeps x0, z and the FP32 output
+// for the backward pass); else inference, writing only out64 = f - g (FP64).
+hipError_t forward(const Buffers& B, const double* f, const double* v, int batch, double* out64,
+                   hipStream_t st);
 hipError_t loss_grad(const Buffers& B, const double* f, const double* v, const double* target,
                      int batch, hipStream_t st);
 hipError_t prep_weights(const Buffers& B, hipStream_t st);
+// u0[0..n) = 0 unless red[0] < red[3]; *used (nullable) = kept.
+hipError_t guess_fallback(const double* red, double* u0, int* used, int n, hipStream_t st);
 hipError_t adam(const Buffers& B, float lr, float b1, float b2, float eps, float bc1, float bc2,
                 hipStream_t st);
 

@@ -41,11 +41,12 @@ def _qnn():
                                 ctypes.POINTER(ctypes.c_double)]
     L.qnn_adam_step.argtypes = [c_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double]
+    L.qnn_guess_fallback.argtypes = [c_vp, c_vp, c_vp, c_vp]
     L.qnn_destroy.argtypes = [c_vp]
     L.qnn_destroy.restype = None
     for n in ("qnn_create", "qnn_workspace_bytes", "qnn_bind_workspace", "qnn_set_stream",
               "qnn_param_count", "qnn_set_params", "qnn_get_params", "qnn_get_grads",
-              "qnn_forward", "qnn_loss_grad", "qnn_adam_step"):
+              "qnn_forward", "qnn_loss_grad", "qnn_adam_step", "qnn_guess_fallback"):
         getattr(L, n).restype = ctypes.c_int32
     _QNN = L
     return L
@@ -120,6 +121,20 @@ class Net:
                                    ctypes.byref(loss) if want_loss else None))
         return loss.value
 
+    def guess_fallback(self, red, u0, used=None):
+        """u0 = 0 on the device unless red[0] < red[3] (the residual sums
+        qn_residual wrote for u0); used (int32[1] CUDA, optional) = kept."""
+        if tuple(u0.shape[-2:]) != (self.H, self.W) or u0.numel() != self.H * self.W \
+                or u0.dtype != torch.float64 or not u0.is_cuda or not u0.is_contiguous():
+            raise ValueError(f"u0: need one contiguous float64 CUDA ({self.H}, {self.W}) image")
+        if red.dtype != torch.float64 or not red.is_cuda or red.numel() < 4:
+            raise ValueError("red: need float64[4] CUDA")
+        if used is not None and (used.dtype != torch.int32 or not used.is_cuda):
+            raise ValueError("used: need int32 CUDA")
+        self._stream()
+        check(_qnn().qnn_guess_fallback(self._ctx, _p(red), _p(u0),
+                                        None if used is None else _p(used)))
+
     def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         self._stream()
         check(_qnn().qnn_adam_step(self._ctx, lr, beta1, beta2, eps))
@@ -189,19 +204,19 @@ def train(net, F, V, G, epochs=40, batch=16, lr=1e-3, seed=0, log=None):
 def initial_guess(net, solver, f):
     """U_0 = A_h^-1 (f - g), g = net(f / 50, A_h^-1 f), unless its residual is
     non-finite or not smaller than that of U_0 = 0 (which is ||f||); then
-    U_0 = 0.  f: (1, n, n).  Returns (U_0, used_net)."""
+    U_0 = 0.  The choice is taken on the device, so nothing here waits for the
+    GPU.  f: (1, n, n).  Returns (U_0, used) with used an int32[1] CUDA tensor
+    (1: the network's guess was kept)."""
     n = f.shape[-1]
     f = f.view(1, n, n)
     v = solver.fdm_solve(f, 1.0, 0.0)
     w = net.forward(f, v)
     u0 = solver.fdm_solve(w, 1.0, 0.0, X=v)
-    red = torch.empty(4, dtype=torch.float64, device="cuda")
+    red = torch.empty(4, dtype=torch.float64, device=f.device)
+    used = torch.empty(1, dtype=torch.int32, device=f.device)
     solver.residual(u0, f, R=w, red=red)
-    r2, f2 = red[0].item(), red[3].item()
-    if not math.isfinite(r2) or r2 >= f2:
-        u0.zero_()
-        return u0, False
-    return u0, True
+    net.guess_fallback(red, u0, used)
+    return u0, used
 
 
 def evaluate(net, seeds, n=255, rtol=1e-10):
@@ -224,7 +239,7 @@ def evaluate(net, seeds, n=255, rtol=1e-10):
         t_net = time.perf_counter() - t0
         diff = float((u1 - u).norm() / u.norm())
         rows.append({"seed": s, "iters_zero": st0["iters"], "iters_net": st1["iters"],
-                     "t_zero": t_zero, "t_net": t_net, "used_net": used,
+                     "t_zero": t_zero, "t_net": t_net, "used_net": bool(used.item()),
                      "relres0_net": st1["relres0"], "rel_diff": diff,
                      "status": (st0["status"], st1["status"])})
     return rows
@@ -259,7 +274,7 @@ def compare(net, seeds, n=255, rtol=1e-10):
                 if ref is None:
                     ref = u.clone()
                 row[f"{p}_{mode}"] = {"iters": st["iters"], "t": dt, "status": st["status"],
-                                      "used_net": used,
+                                      "used_net": bool(used if mode == "zero" else used.item()),
                                       "rel_diff": float((u - ref).norm() / ref.norm())}
         rows.append(row)
     return rows

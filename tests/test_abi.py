@@ -110,6 +110,7 @@ def _qnn():
     L.qnn_bind_workspace.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
     L.qnn_forward.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int32, ctypes.c_void_p]
     L.qnn_adam_step.argtypes = [ctypes.c_void_p] + [ctypes.c_double] * 4
+    L.qnn_guess_fallback.argtypes = [ctypes.c_void_p] * 4
     L.qnn_destroy.argtypes = [ctypes.c_void_p]
     L.qnn_destroy.restype = None
     return L
@@ -135,6 +136,8 @@ def test_qnn_host_checks():
     assert L.qnn_bind_workspace(net, ctypes.c_void_p(256 + 8), nb.value) == qn.QN_ERR_WORKSPACE
     assert L.qnn_bind_workspace(net, ctypes.c_void_p(4096), nb.value - 1) == qn.QN_ERR_WORKSPACE
     assert L.qnn_forward(None, None, None, 1, None) == qn.QN_ERR_INVALID
+    assert L.qnn_guess_fallback(None, None, None, None) == qn.QN_ERR_INVALID
+    assert L.qnn_guess_fallback(net, None, None, None) == qn.QN_ERR_INVALID
     L.qnn_destroy(net)
     L.qnn_destroy(None)
 

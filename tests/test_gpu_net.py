@@ -99,7 +99,24 @@ def test_fallback_to_zero_on_bad_network():
     solver = cubic_solver(n)
     f = torch.from_numpy(synth.learned_guess_rhs(3, n)).cuda()
     u0, used = initial_guess(net, solver, f)
-    assert not used and float(u0.abs().max()) == 0.0
+    assert int(used.item()) == 0 and float(u0.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("red,keep", [((1.0, 0, 0, 2.0), True), ((2.0, 0, 0, 2.0), False),
+                                      ((3.0, 0, 0, 2.0), False),
+                                      ((float("nan"), 0, 0, 2.0), False),
+                                      ((float("inf"), 0, 0, 2.0), False)])
+def test_guess_fallback_decision(red, keep):
+    """The device-side choice keeps the guess only when sum R^2 < sum F^2."""
+    H, W = 19, 23
+    net = Net(H, W, max_batch=1)
+    u0 = dev(np.random.default_rng(4).standard_normal((1, H, W)))
+    ref = u0.clone()
+    used = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    net.guess_fallback(dev(np.array(red, np.float64)), u0, used)
+    assert int(used.item()) == int(keep)
+    assert torch.equal(u0, ref) if keep else float(u0.abs().max()) == 0.0
+    net.guess_fallback(dev(np.array(red, np.float64)), u0)  # used is optional
 
 
 def test_trained_network_saves_iterations():
