@@ -245,17 +245,20 @@ def main():
     # kernel names per timing key from the tiles in use (launch order: x, y
     # forward, z forward + divide, z and y inverse, x inverse + update)
     def kernel_name(slot, t):
-        # kind: 0 x fwd, 1 y/z fwd, 2 y/z inv, 3 x inv; +4 when the tile is paired
+        # kind: 0 x fwd, 1 y/z fwd, 2 y/z inv, 3 x inv; +4 when the tile is
+        # paired, +8 when it stages the contraction deep (last template argument:
+        # 64 rows forward, 32 fold rows inverse and paired, else 0)
         kind, _, tm, tn = t
-        base, paired = kind % 4, kind >= 4
+        base, paired, deep = kind % 4, bool(kind & 4), bool(kind & 8)
+        tk = 0 if not deep else (32 if base in (2, 3) or paired else 64)
         if base == 0:
-            return f"k_fold_right_fwd<double,{tm},{tn}>"
+            return f"k_fold_right_fwd<double,{tm},{tn},{tk}>"
         if base == 1:
             epi = "EPI_DIVIDE" if slot == 2 else "EPI_STORE"
-            return f"k_fold_left_fwd{'2' if paired else ''}<double,{tm},{tn},{epi}>"
+            return f"k_fold_left_fwd{'2' if paired else ''}<double,{tm},{tn},{epi},{tk}>"
         if base == 2:
-            return f"k_fold_left_inv<double,{tm},{tn}>"
-        return f"k_fold_right_inv<double,{tm},{tn},EPI_SUB_DENSE>"
+            return f"k_fold_left_inv<double,{tm},{tn},{tk}>"
+        return f"k_fold_right_inv<double,{tm},{tn},EPI_SUB_DENSE,{tk}>"
     kname = [kernel_name(i, t) for i, t in enumerate(tiles)]
     names = {"gemm_x": kname[0], "gemm_yz": kname[1], "gemm_divide": kname[2],
              "gemm_yz_inv": kname[3] if kname[3] == kname[4] else kname[3] + " / " + kname[4],

@@ -73,13 +73,15 @@ def lib():
     L.qn_timing_reset.argtypes = [c_vp]
     L.qn_autotune.argtypes = [c_vp]
     L.qn_tile_info.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i32)]
+    L.qn_set_tile.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i32)]
     L.qn_destroy.argtypes = [c_vp]
     L.qn_destroy.restype = None
     L.qn_last_error.argtypes = []
     L.qn_last_error.restype = ctypes.c_char_p
     for name in ("qn_setup", "qn_workspace_bytes", "qn_bind_workspace", "qn_set_stream",
                  "qn_residual", "qn_fdm_solve", "qn_iterate", "qn_timing_count",
-                 "qn_timing_read", "qn_timing_reset", "qn_autotune", "qn_tile_info"):
+                 "qn_timing_read", "qn_timing_reset", "qn_autotune", "qn_tile_info",
+                 "qn_set_tile"):
         getattr(L, name).restype = c_i32
     _lib = L
     return L
@@ -206,8 +208,14 @@ class Solver:
         self._sync_stream()
         check(lib().qn_autotune(self._ctx))
 
+    def set_tile(self, i, info):
+        """Pin launch i to the tile info = (kind, axis, tile_m, tile_n) as
+        returned by tiles(); raises QNError when the shape is not admissible."""
+        check(lib().qn_set_tile(self._ctx, int(i), (c_i32 * 4)(*[int(v) for v in info])))
+
     def tiles(self):
-        """[(kind, axis, tile_m, tile_n)] of the solve's mode-product launches."""
+        """[(kind, axis, tile_m, tile_n)] of the solve's mode-product launches
+        (kind: 0 x fwd, 1 y/z fwd, 2 y/z inv, 3 x inv; +4 paired, +8 deep stages)."""
         out = []
         info = (c_i32 * 4)()
         for i in range(6 if self.dim == 3 else 4):

@@ -203,13 +203,11 @@ FoldOperands fold_ops(qn_ctx c, int axis) {
 FoldTile pick_fold_tile(int kind, int bk, int ncols, int batch, int rows) {
   const FoldTile* list;
   const int nc = fold_tiles(kind, &list);
-  long long mext, next;
-  fold_extents(kind, bk, ncols, rows, &mext, &next);
   const long long want = 2LL * 256;
-  FoldTile best{32, 32, 0};
+  FoldTile best{32, 32, 0, 0};
   long long best_blocks = -1;
   for (int i = 0; i < nc; ++i) {
-    if (mext % list[i].tm || next % list[i].tn) continue;
+    if (!fold_tile_fits(kind, list[i], bk, ncols, rows)) continue;
     const long long blocks = fold_blocks(kind, list[i], bk, ncols, batch, rows);
     if (blocks >= want) return list[i];
     if (blocks > best_blocks) {
@@ -405,14 +403,13 @@ int step_candidates(qn_ctx c, const FoldStep& f, FoldTile* out) {
     const int cap = gemm_bf_max_tile(c->prec);
     for (int tm = 32; tm <= cap; tm *= 2)
       for (int tn = 32; tn <= cap; tn *= 2)
-        if (mext % tm == 0 && next % tn == 0) out[n++] = FoldTile{tm, tn, 0};
+        if (mext % tm == 0 && next % tn == 0) out[n++] = FoldTile{tm, tn, 0, 0};
     return n;
   }
   const FoldTile* list;
   const int nc = fold_tiles(f.kind, &list);
-  fold_extents(f.kind, c->ax[f.axis].bk, f.ncols, f.rows, &mext, &next);
   for (int i = 0; i < nc && n < 16; ++i)
-    if (mext % list[i].tm == 0 && next % list[i].tn == 0) out[n++] = list[i];
+    if (fold_tile_fits(f.kind, list[i], c->ax[f.axis].bk, f.ncols, f.rows)) out[n++] = list[i];
   return n;
 }
 
@@ -423,7 +420,7 @@ FoldTile step_tile(qn_ctx c, const FoldStep& f, int i) {
     long long mext, next;
     dense_extents(f, &mext, &next);
     const int cap = gemm_bf_max_tile(c->prec);
-    return FoldTile{pick_tile(mext, cap), pick_tile(next, cap), 0};
+    return FoldTile{pick_tile(mext, cap), pick_tile(next, cap), 0, 0};
   }
   return pick_fold_tile(f.kind, c->ax[f.axis].bk, f.ncols, f.batch, f.rows);
 }
@@ -827,11 +824,39 @@ qn_status qn_tile_info(qn_ctx c, int32_t i, int32_t* info4) {
   const FoldTile t = step_tile(c, st[i], i);
   const int kid = st[i].kid;
   const int kind = kid == K_GEMM_X ? 0 : kid == K_GEMM_X_UPDATE ? 3 : kid == K_GEMM_YZ_INV ? 2 : 1;
-  info4[0] = kind + (t.paired ? 4 : 0);
+  info4[0] = kind + (t.paired ? 4 : 0) + (t.tk ? 8 : 0);
   info4[1] = st[i].axis;
   info4[2] = t.tm;
   info4[3] = t.tn;
   return QN_OK;
+}
+
+qn_status qn_set_tile(qn_ctx c, int32_t i, const int32_t* info4) {
+  qn_status s = check_ctx(c, true);
+  if (s != QN_OK) return s;
+  if (!info4) return fail(QN_ERR_INVALID, "null argument");
+  FoldStep st[6];
+  const int ns = solve_plan(c, epi_args(c, nullptr, nullptr), EPI_STORE, st);
+  if (i < 0 || i >= ns) return fail(QN_ERR_INVALID, "launch index %d out of range [0, %d)", i, ns);
+  const int kid = st[i].kid;
+  const int kind = kid == K_GEMM_X ? 0 : kid == K_GEMM_X_UPDATE ? 3 : kid == K_GEMM_YZ_INV ? 2 : 1;
+  if ((info4[0] & 3) != kind || (info4[0] & ~15) != 0 || info4[1] != st[i].axis)
+    return fail(QN_ERR_INVALID, "launch %d is kind %d on axis %d", i, kind, st[i].axis);
+  FoldTile cand[16];
+  const int nc = step_candidates(c, st[i], cand);
+  for (int k = 0; k < nc; ++k) {
+    const FoldTile& t = cand[k];
+    const int flags = kind + (t.paired ? 4 : 0) + (t.tk ? 8 : 0);
+    if (flags == info4[0] && t.tm == info4[2] && t.tn == info4[3]) {
+      if (!c->tuned)
+        for (int j = 0; j < ns; ++j) c->tile[j] = step_tile(c, st[j], j);
+      c->tile[i] = t;
+      c->tuned = true;
+      return QN_OK;
+    }
+  }
+  return fail(QN_ERR_INVALID, "tile {%d, %d, %d, %d} is not an admissible shape of launch %d",
+              info4[0], info4[1], info4[2], info4[3], i);
 }
 
 int32_t qn_timing_count(void) { return K_COUNT; }

@@ -296,10 +296,8 @@ qn_status qnb_setup(int32_t count, const int32_t* n, const int32_t* ncomp, int32
       auto first = [&](int kind, FoldTile& t) {
         const FoldTile* list;
         const int nc = fold_tiles(kind, &list);
-        long long mext, next;
-        fold_extents(kind, k.ax.bk, k.p, k.p, &mext, &next);
         for (int q = 0; q < nc; ++q)
-          if (mext % list[q].tm == 0 && next % list[q].tn == 0) {
+          if (fold_tile_fits(kind, list[q], k.ax.bk, k.p, k.p)) {
             t = list[q];
             return;
           }
@@ -431,13 +429,11 @@ qn_status qnb_autotune(qnb_ctx c) {
         const int kind = kinds[fi];
         const FoldTile* list;
         const int nc = fold_tiles(kind, &list);
-        long long mext, next;
         // x-product row tiles divide P, so they never straddle two instances
-        fold_extents(kind, k.ax.bk, k.p, k.p, &mext, &next);
         float best = 1e30f;
         for (int q = 0; q < nc && e == hipSuccess; ++q) {
           const FoldTile t = list[q];
-          if (mext % t.tm || next % t.tn) continue;
+          if (!fold_tile_fits(kind, t, k.ax.bk, k.p, k.p)) continue;
           float ms = 0.f;
           e = time_run([&] {
             return launch_fold(kind, c->prec, F, W1, W2, k.ax, k.p, slabs, sl, rows, EPI_STORE, ep, t,

@@ -41,14 +41,14 @@ namespace qn {
 // Forward, contraction over the slab rows (the folded axis):
 // C[b][m][c] (m in [0, 2 bk)) = sum_{k<bk} F^T_blk[k][i] * fold_blk(B[b])[k][c],
 // blk = m / bk, i = m % bk.
-template <typename T, int TM, int TN, int EPI>
+template <typename T, int TM, int TN, int EPI, int TKS>
 __global__ __launch_bounds__(256, 2) void k_fold_left_fwd(const T* __restrict__ FeT,
                                                           const T* __restrict__ FoT,
                                                           const T* __restrict__ B,
                                                           T* __restrict__ C, FoldAxis ax, int ncols,
                                                           int batch, long long bstride, EpiArgs ep) {
   using MF = Mfma<T>;
-  constexpr int TK = MF::TK;
+  constexpr int TK = TKS ? TKS : MF::TK;
   constexpr int VE = 16 / sizeof(T);
   typedef T V __attribute__((ext_vector_type(VE)));
   constexpr int WM = TM / 2, WN = TN / 2, BM = WM / 16, BN = WN / 16;
@@ -194,14 +194,14 @@ __global__ __launch_bounds__(256, 2) void k_fold_left_fwd(const T* __restrict__ 
 //   C[b][i][c]      = sum_{k<ne} FeT[k][i] (B[b][k][c] + B[b][n-1-k][c])
 //   C[b][bk + i][c] = sum_{k<h}  FoT[k][i] (B[b][k][c] - B[b][n-1-k][c])
 // (the centre row k = h of odd n enters the even half alone).
-template <typename T, int TMF, int TN, int EPI>
+template <typename T, int TMF, int TN, int EPI, int TKS>
 __global__ __launch_bounds__(256, 2) void k_fold_left_fwd2(const T* __restrict__ FeT,
                                                            const T* __restrict__ FoT,
                                                            const T* __restrict__ B,
                                                            T* __restrict__ C, FoldAxis ax, int ncols,
                                                            int batch, long long bstride, EpiArgs ep) {
   using MF = Mfma<T>;
-  constexpr int TK = MF::TK / 2;
+  constexpr int TK = TKS ? TKS : MF::TK / 2;
   constexpr int VE = 16 / sizeof(T);
   typedef T V __attribute__((ext_vector_type(VE)));
   constexpr int WM = TMF / 2, WN = TN / 2, BM = WM / 16, BN = WN / 16;
@@ -359,14 +359,14 @@ __global__ __launch_bounds__(256, 2) void k_fold_left_fwd2(const T* __restrict__
 // p[k][c] = sum_{i<bk} Fe[i][k] Y[b][i][c], q[k][c] = sum_{i<bk} Fo[i][k] Y[b][bk+i][c];
 // C[b][k] = p + q, C[b][n-1-k] = p - q (k < h), C[b][h] = p (n odd).
 // A tile owns TMF fold rows (2 TMF output rows) x TN columns.
-template <typename T, int TMF, int TN>
+template <typename T, int TMF, int TN, int TKS>
 __global__ __launch_bounds__(256, 2) void k_fold_left_inv(const T* __restrict__ Fe,
                                                           const T* __restrict__ Fo,
                                                           const T* __restrict__ Y,
                                                           T* __restrict__ C, FoldAxis ax, int ncols,
                                                           int batch, long long bstride, EpiArgs ep) {
   using MF = Mfma<T>;
-  constexpr int TK = MF::TK / 2;
+  constexpr int TK = TKS ? TKS : MF::TK / 2;
   constexpr int VE = 16 / sizeof(T);
   typedef T V __attribute__((ext_vector_type(VE)));
   constexpr int WM = TMF / 2, WN = TN / 2, BM = WM / 16, BN = WN / 16;
@@ -494,14 +494,14 @@ __global__ __launch_bounds__(256, 2) void k_fold_left_inv(const T* __restrict__ 
 
 // Forward along x (contraction over the columns of A's rows):
 // C[r][m] = sum_{k<bk} fold_blk(A[r])[k] F^T_blk[k][i], blk = m / bk, i = m % bk.
-template <typename T, int TM, int TN>
+template <typename T, int TM, int TN, int TKS>
 __global__ __launch_bounds__(256, 2) void k_fold_right_fwd(const T* __restrict__ A,
                                                            const T* __restrict__ FeT,
                                                            const T* __restrict__ FoT,
                                                            T* __restrict__ C, FoldAxis ax, int rows,
                                                            EpiArgs ep) {
   using MF = Mfma<T>;
-  constexpr int TK = MF::TK;
+  constexpr int TK = TKS ? TKS : MF::TK;
   constexpr int VE = 16 / sizeof(T);
   typedef T V __attribute__((ext_vector_type(VE)));
   constexpr int WM = TM / 2, WN = TN / 2, BM = WM / 16, BN = WN / 16;
@@ -624,14 +624,14 @@ __global__ __launch_bounds__(256, 2) void k_fold_right_fwd(const T* __restrict__
 // Inverse along x: p[r][k] = sum_i Y[r][i] Fe[i][k], q[r][k] = sum_i Y[r][bk+i] Fo[i][k];
 // output columns k and n-1-k (p + q, p - q), or h (p).  EPI: store into C
 // (row length 2 bk) or the dense epilogues (U -= dU / X = dU) on ep.dense.
-template <typename T, int TM, int TNF, int EPI>
+template <typename T, int TM, int TNF, int EPI, int TKS>
 __global__ __launch_bounds__(256, 2) void k_fold_right_inv(const T* __restrict__ Y,
                                                            const T* __restrict__ Fe,
                                                            const T* __restrict__ Fo,
                                                            T* __restrict__ C, FoldAxis ax, int rows,
                                                            EpiArgs ep) {
   using MF = Mfma<T>;
-  constexpr int TK = MF::TK / 2;
+  constexpr int TK = TKS ? TKS : MF::TK / 2;
   constexpr int VE = 16 / sizeof(T);
   typedef T V __attribute__((ext_vector_type(VE)));
   constexpr int WM = TM / 2, WN = TNF / 2, BM = WM / 16, BN = WN / 16;
@@ -793,181 +793,175 @@ __global__ __launch_bounds__(256, 2) void k_fold_right_inv(const T* __restrict__
 
 namespace {
 
+// Stage depths of the deep tiles: one LDS stage spans 64 contraction rows in
+// the forward kernels and 32 fold rows in the inverse and paired kernels
+// (against 16 / 8 in FP64 and 32 / 16 in FP32 otherwise), so a short
+// contraction (small grids) waits on two to four global-load round trips
+// instead of eight to sixteen.
+constexpr int kDeepFwd = 64, kDeepInv = 32;
+
 template <typename T>
 hipError_t lfwd(const FoldOperands& f, const T* B, T* C, const FoldAxis& ax, int ncols, int batch,
-                long long bstride, int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st) {
+                long long bstride, int epi, const EpiArgs& ep, const FoldTile& t, hipStream_t st) {
   const T* FeT = (const T*)f.FeT;
   const T* FoT = (const T*)f.FoT;
-#define QN_LFWD(TM_, TN_)                                                                       \
-  if (tm == TM_ && tn == TN_) {                                                                 \
+#define QN_LFWD(TM_, TN_, TK_)                                                                  \
+  if (t.tm == TM_ && t.tn == TN_ && t.tk == TK_) {                                              \
     const unsigned g = (unsigned)((long long)batch * (2 * ax.bk / TM_) * (ncols / TN_));        \
     if (epi == EPI_DIVIDE)                                                                      \
-      hipLaunchKernelGGL((k_fold_left_fwd<T, TM_, TN_, EPI_DIVIDE>), dim3(g), dim3(256), 0, st, \
-                         FeT, FoT, B, C, ax, ncols, batch, bstride, ep);                        \
+      hipLaunchKernelGGL((k_fold_left_fwd<T, TM_, TN_, EPI_DIVIDE, TK_>), dim3(g), dim3(256), 0, \
+                         st, FeT, FoT, B, C, ax, ncols, batch, bstride, ep);                    \
     else                                                                                        \
-      hipLaunchKernelGGL((k_fold_left_fwd<T, TM_, TN_, EPI_STORE>), dim3(g), dim3(256), 0, st,  \
-                         FeT, FoT, B, C, ax, ncols, batch, bstride, ep);                        \
+      hipLaunchKernelGGL((k_fold_left_fwd<T, TM_, TN_, EPI_STORE, TK_>), dim3(g), dim3(256), 0, \
+                         st, FeT, FoT, B, C, ax, ncols, batch, bstride, ep);                    \
     return hipGetLastError();                                                                   \
   }
-  QN_LFWD(128, 128)
-  QN_LFWD(64, 128)
-  QN_LFWD(64, 64)
-  QN_LFWD(32, 64)
-  QN_LFWD(32, 32)
+  QN_LFWD(128, 128, 0)
+  QN_LFWD(64, 128, 0)
+  QN_LFWD(64, 64, 0)
+  QN_LFWD(32, 64, 0)
+  QN_LFWD(32, 32, 0)
+  QN_LFWD(32, 32, kDeepFwd)
 #undef QN_LFWD
   return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t lfwd2(const FoldOperands& f, const T* B, T* C, const FoldAxis& ax, int ncols, int batch,
-                 long long bstride, int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st) {
+                 long long bstride, int epi, const EpiArgs& ep, const FoldTile& t, hipStream_t st) {
   const T* FeT = (const T*)f.FeT;
   const T* FoT = (const T*)f.FoT;
-#define QN_LFWD2(TM_, TN_)                                                                       \
-  if (tm == TM_ && tn == TN_) {                                                                  \
+#define QN_LFWD2(TM_, TN_, TK_)                                                                  \
+  if (t.tm == TM_ && t.tn == TN_ && t.tk == TK_) {                                               \
     const unsigned g = (unsigned)((long long)batch * (ax.bk / TM_) * (ncols / TN_));             \
     if (epi == EPI_DIVIDE)                                                                       \
-      hipLaunchKernelGGL((k_fold_left_fwd2<T, TM_, TN_, EPI_DIVIDE>), dim3(g), dim3(256), 0, st, \
-                         FeT, FoT, B, C, ax, ncols, batch, bstride, ep);                         \
+      hipLaunchKernelGGL((k_fold_left_fwd2<T, TM_, TN_, EPI_DIVIDE, TK_>), dim3(g), dim3(256), 0, \
+                         st, FeT, FoT, B, C, ax, ncols, batch, bstride, ep);                     \
     else                                                                                         \
-      hipLaunchKernelGGL((k_fold_left_fwd2<T, TM_, TN_, EPI_STORE>), dim3(g), dim3(256), 0, st,  \
-                         FeT, FoT, B, C, ax, ncols, batch, bstride, ep);                         \
+      hipLaunchKernelGGL((k_fold_left_fwd2<T, TM_, TN_, EPI_STORE, TK_>), dim3(g), dim3(256), 0, \
+                         st, FeT, FoT, B, C, ax, ncols, batch, bstride, ep);                     \
     return hipGetLastError();                                                                    \
   }
-  QN_LFWD2(64, 64)
-  QN_LFWD2(128, 64)
-  QN_LFWD2(32, 64)
-  QN_LFWD2(64, 128)
-  QN_LFWD2(32, 128)
+  QN_LFWD2(64, 64, 0)
+  QN_LFWD2(128, 64, 0)
+  QN_LFWD2(32, 64, 0)
+  QN_LFWD2(64, 128, 0)
+  QN_LFWD2(32, 128, 0)
+  QN_LFWD2(32, 32, kDeepInv)
 #undef QN_LFWD2
   return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t linv(const FoldOperands& f, const T* Y, T* C, const FoldAxis& ax, int ncols, int batch,
-                long long bstride, const EpiArgs& ep, int tm, int tn, hipStream_t st) {
+                long long bstride, const EpiArgs& ep, const FoldTile& t, hipStream_t st) {
   const T* Fe = (const T*)f.Fe;
   const T* Fo = (const T*)f.Fo;
-#define QN_LINV(TM_, TN_)                                                                       \
-  if (tm == TM_ && tn == TN_) {                                                                 \
+#define QN_LINV(TM_, TN_, TK_)                                                                  \
+  if (t.tm == TM_ && t.tn == TN_ && t.tk == TK_) {                                              \
     const unsigned g = (unsigned)((long long)batch * (ax.bk / TM_) * (ncols / TN_));            \
-    hipLaunchKernelGGL((k_fold_left_inv<T, TM_, TN_>), dim3(g), dim3(256), 0, st, Fe, Fo, Y, C, \
-                       ax, ncols, batch, bstride, ep);                                          \
+    hipLaunchKernelGGL((k_fold_left_inv<T, TM_, TN_, TK_>), dim3(g), dim3(256), 0, st, Fe, Fo, \
+                       Y, C, ax, ncols, batch, bstride, ep);                                    \
     return hipGetLastError();                                                                   \
   }
-  QN_LINV(64, 128)
-  QN_LINV(64, 64)
-  QN_LINV(32, 64)
-  QN_LINV(32, 32)
-  QN_LINV(32, 128)
+  QN_LINV(64, 128, 0)
+  QN_LINV(64, 64, 0)
+  QN_LINV(32, 64, 0)
+  QN_LINV(32, 32, 0)
+  QN_LINV(32, 128, 0)
+  QN_LINV(32, 32, kDeepInv)
+  QN_LINV(32, 64, kDeepInv)
 #undef QN_LINV
   return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t rfwd(const FoldOperands& f, const T* A, T* C, const FoldAxis& ax, int rows,
-                const EpiArgs& ep, int tm, int tn, hipStream_t st) {
+                const EpiArgs& ep, const FoldTile& t, hipStream_t st) {
   const T* FeT = (const T*)f.FeT;
   const T* FoT = (const T*)f.FoT;
-#define QN_RFWD(TM_, TN_)                                                                        \
-  if (tm == TM_ && tn == TN_) {                                                                  \
+#define QN_RFWD(TM_, TN_, TK_)                                                                   \
+  if (t.tm == TM_ && t.tn == TN_ && t.tk == TK_) {                                               \
     const unsigned g = (unsigned)((long long)(rows / TM_) * (2 * ax.bk / TN_));                  \
-    hipLaunchKernelGGL((k_fold_right_fwd<T, TM_, TN_>), dim3(g), dim3(256), 0, st, A, FeT, FoT, \
-                       C, ax, rows, ep);                                                         \
+    hipLaunchKernelGGL((k_fold_right_fwd<T, TM_, TN_, TK_>), dim3(g), dim3(256), 0, st, A, FeT, \
+                       FoT, C, ax, rows, ep);                                                    \
     return hipGetLastError();                                                                    \
   }
-  QN_RFWD(128, 128)
-  QN_RFWD(128, 64)
-  QN_RFWD(64, 64)
-  QN_RFWD(64, 32)
-  QN_RFWD(32, 32)
-  QN_RFWD(64, 128)
-  QN_RFWD(32, 64)
+  QN_RFWD(128, 128, 0)
+  QN_RFWD(128, 64, 0)
+  QN_RFWD(64, 64, 0)
+  QN_RFWD(64, 32, 0)
+  QN_RFWD(32, 32, 0)
+  QN_RFWD(64, 128, 0)
+  QN_RFWD(32, 64, 0)
+  QN_RFWD(32, 32, kDeepFwd)
 #undef QN_RFWD
   return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t rinv(const FoldOperands& f, const T* Y, T* C, const FoldAxis& ax, int rows, int epi,
-                const EpiArgs& ep, int tm, int tn, hipStream_t st) {
+                const EpiArgs& ep, const FoldTile& t, hipStream_t st) {
   const T* Fe = (const T*)f.Fe;
   const T* Fo = (const T*)f.Fo;
-#define QN_RINV(TM_, TN_)                                                                       \
-  if (tm == TM_ && tn == TN_) {                                                                 \
-    const unsigned g = (unsigned)((long long)(rows / TM_) * (ax.bk / TN_));                     \
-    if (epi == EPI_SUB_DENSE)                                                                   \
-      hipLaunchKernelGGL((k_fold_right_inv<T, TM_, TN_, EPI_SUB_DENSE>), dim3(g), dim3(256), 0, \
-                         st, Y, Fe, Fo, C, ax, rows, ep);                                       \
-    else if (epi == EPI_STORE_DENSE)                                                            \
-      hipLaunchKernelGGL((k_fold_right_inv<T, TM_, TN_, EPI_STORE_DENSE>), dim3(g), dim3(256),  \
-                         0, st, Y, Fe, Fo, C, ax, rows, ep);                                    \
-    else                                                                                        \
-      hipLaunchKernelGGL((k_fold_right_inv<T, TM_, TN_, EPI_STORE>), dim3(g), dim3(256), 0, st, \
-                         Y, Fe, Fo, C, ax, rows, ep);                                           \
-    return hipGetLastError();                                                                   \
+#define QN_RINV(TM_, TN_, TK_)                                                                   \
+  if (t.tm == TM_ && t.tn == TN_ && t.tk == TK_) {                                               \
+    const unsigned g = (unsigned)((long long)(rows / TM_) * (ax.bk / TN_));                      \
+    if (epi == EPI_SUB_DENSE)                                                                    \
+      hipLaunchKernelGGL((k_fold_right_inv<T, TM_, TN_, EPI_SUB_DENSE, TK_>), dim3(g), dim3(256), \
+                         0, st, Y, Fe, Fo, C, ax, rows, ep);                                     \
+    else if (epi == EPI_STORE_DENSE)                                                             \
+      hipLaunchKernelGGL((k_fold_right_inv<T, TM_, TN_, EPI_STORE_DENSE, TK_>), dim3(g),         \
+                         dim3(256), 0, st, Y, Fe, Fo, C, ax, rows, ep);                          \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_fold_right_inv<T, TM_, TN_, EPI_STORE, TK_>), dim3(g), dim3(256), 0, \
+                         st, Y, Fe, Fo, C, ax, rows, ep);                                        \
+    return hipGetLastError();                                                                    \
   }
-  QN_RINV(128, 64)
-  QN_RINV(64, 64)
-  QN_RINV(64, 32)
-  QN_RINV(32, 32)
-  QN_RINV(64, 128)
-  QN_RINV(32, 64)
+  QN_RINV(128, 64, 0)
+  QN_RINV(64, 64, 0)
+  QN_RINV(64, 32, 0)
+  QN_RINV(32, 32, 0)
+  QN_RINV(64, 128, 0)
+  QN_RINV(32, 64, 0)
+  QN_RINV(32, 32, kDeepInv)
+  QN_RINV(64, 32, kDeepInv)
 #undef QN_RINV
   return hipErrorInvalidValue;
 }
 
-}  // namespace
-
-hipError_t launch_fold_left_fwd(int prec, const FoldOperands& f, const void* B, void* C,
-                                const FoldAxis& ax, int ncols, int batch, long long bstride,
-                                int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st) {
-  if (prec == 0)
-    return lfwd<double>(f, (const double*)B, (double*)C, ax, ncols, batch, bstride, epi, ep, tm,
-                        tn, st);
-  return lfwd<float>(f, (const float*)B, (float*)C, ax, ncols, batch, bstride, epi, ep, tm, tn, st);
+template <typename T>
+hipError_t fold_typed(int kind, const FoldOperands& f, const void* in, void* out,
+                      const FoldAxis& ax, int ncols, int batch, long long bstride, int rows,
+                      int epi, const EpiArgs& ep, const FoldTile& t, hipStream_t st) {
+  const T* src = (const T*)in;
+  T* dst = (T*)out;
+  switch (kind) {
+    case FK_RFWD: return rfwd<T>(f, src, dst, ax, rows, ep, t, st);
+    case FK_LFWD:
+      if (t.paired) return lfwd2<T>(f, src, dst, ax, ncols, batch, bstride, epi, ep, t, st);
+      return lfwd<T>(f, src, dst, ax, ncols, batch, bstride, epi, ep, t, st);
+    case FK_LINV: return linv<T>(f, src, dst, ax, ncols, batch, bstride, ep, t, st);
+    default: return rinv<T>(f, src, dst, ax, rows, epi, ep, t, st);
+  }
 }
 
-hipError_t launch_fold_left_fwd_paired(int prec, const FoldOperands& f, const void* B, void* C,
-                                       const FoldAxis& ax, int ncols, int batch, long long bstride,
-                                       int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st) {
-  if (prec == 0)
-    return lfwd2<double>(f, (const double*)B, (double*)C, ax, ncols, batch, bstride, epi, ep, tm,
-                         tn, st);
-  return lfwd2<float>(f, (const float*)B, (float*)C, ax, ncols, batch, bstride, epi, ep, tm, tn, st);
-}
-
-hipError_t launch_fold_left_inv(int prec, const FoldOperands& f, const void* Y, void* C,
-                                const FoldAxis& ax, int ncols, int batch, long long bstride,
-                                const EpiArgs& ep, int tm, int tn, hipStream_t st) {
-  if (prec == 0)
-    return linv<double>(f, (const double*)Y, (double*)C, ax, ncols, batch, bstride, ep, tm, tn, st);
-  return linv<float>(f, (const float*)Y, (float*)C, ax, ncols, batch, bstride, ep, tm, tn, st);
-}
-
-hipError_t launch_fold_right_fwd(int prec, const FoldOperands& f, const void* A, void* C,
-                                 const FoldAxis& ax, int rows, const EpiArgs& ep, int tm, int tn,
-                                 hipStream_t st) {
-  if (prec == 0) return rfwd<double>(f, (const double*)A, (double*)C, ax, rows, ep, tm, tn, st);
-  return rfwd<float>(f, (const float*)A, (float*)C, ax, rows, ep, tm, tn, st);
-}
-
-hipError_t launch_fold_right_inv(int prec, const FoldOperands& f, const void* Y, void* C,
-                                 const FoldAxis& ax, int rows, int epi, const EpiArgs& ep, int tm,
-                                 int tn, hipStream_t st) {
-  if (prec == 0)
-    return rinv<double>(f, (const double*)Y, (double*)C, ax, rows, epi, ep, tm, tn, st);
-  return rinv<float>(f, (const float*)Y, (float*)C, ax, rows, epi, ep, tm, tn, st);
-}
-
-namespace {
-const FoldTile kTilesRfwd[] = {{128, 128, 0}, {128, 64, 0}, {64, 128, 0}, {64, 64, 0},
-                               {64, 32, 0},   {32, 64, 0},  {32, 32, 0}};
-const FoldTile kTilesLfwd[] = {{64, 64, 1},  {128, 128, 0}, {64, 128, 0}, {128, 64, 1},
-                               {64, 128, 1}, {32, 128, 1},  {64, 64, 0},  {32, 64, 1},
-                               {32, 64, 0},  {32, 32, 0}};
-const FoldTile kTilesLinv[] = {{64, 64, 0}, {64, 128, 0}, {32, 128, 0}, {32, 64, 0}, {32, 32, 0}};
-const FoldTile kTilesRinv[] = {{64, 64, 0}, {128, 64, 0}, {64, 128, 0}, {64, 32, 0},
-                               {32, 64, 0}, {32, 32, 0}};
+// Instantiated shapes in order of preference.  The deep variants come right
+// before the plain 32-wide shapes of the same extents, so the default rule
+// (most workgroups when no shape fills the chip) prefers them on small grids.
+const FoldTile kTilesRfwd[] = {{128, 128, 0, 0}, {128, 64, 0, 0},       {64, 128, 0, 0},
+                               {64, 64, 0, 0},   {64, 32, 0, 0},        {32, 64, 0, 0},
+                               {32, 32, 0, kDeepFwd}, {32, 32, 0, 0}};
+const FoldTile kTilesLfwd[] = {{64, 64, 1, 0},  {128, 128, 0, 0},      {64, 128, 0, 0},
+                               {128, 64, 1, 0}, {64, 128, 1, 0},       {32, 128, 1, 0},
+                               {64, 64, 0, 0},  {32, 64, 1, 0},        {32, 64, 0, 0},
+                               {32, 32, 1, kDeepInv}, {32, 32, 0, kDeepFwd}, {32, 32, 0, 0}};
+const FoldTile kTilesLinv[] = {{64, 64, 0, 0},  {64, 128, 0, 0},       {32, 128, 0, 0},
+                               {32, 64, 0, kDeepInv}, {32, 64, 0, 0},  {32, 32, 0, kDeepInv},
+                               {32, 32, 0, 0}};
+const FoldTile kTilesRinv[] = {{64, 64, 0, 0}, {128, 64, 0, 0},       {64, 128, 0, 0},
+                               {64, 32, 0, kDeepInv}, {64, 32, 0, 0}, {32, 64, 0, 0},
+                               {32, 32, 0, kDeepInv}, {32, 32, 0, 0}};
 }  // namespace
 
 int fold_tiles(int kind, const FoldTile** list) {
@@ -989,6 +983,13 @@ void fold_extents(int kind, int bk, int ncols, int rows, long long* mext, long l
   }
 }
 
+bool fold_tile_fits(int kind, const FoldTile& t, int bk, int ncols, int rows) {
+  long long mext, next;
+  fold_extents(kind, bk, ncols, rows, &mext, &next);
+  // a deep stage may not run past the bk spectral rows of the fold matrices
+  return mext % t.tm == 0 && next % t.tn == 0 && (t.tk == 0 || bk % t.tk == 0);
+}
+
 long long fold_blocks(int kind, const FoldTile& t, int bk, int ncols, int batch, int rows) {
   long long mext, next;
   fold_extents(kind, bk, ncols, rows, &mext, &next);
@@ -1001,20 +1002,9 @@ long long fold_blocks(int kind, const FoldTile& t, int bk, int ncols, int batch,
 hipError_t launch_fold(int kind, int prec, const FoldOperands& f, const void* in, void* out,
                        const FoldAxis& ax, int ncols, int batch, long long bstride, int rows,
                        int epi, const EpiArgs& ep, const FoldTile& t, hipStream_t st) {
-  switch (kind) {
-    case FK_RFWD:
-      return launch_fold_right_fwd(prec, f, in, out, ax, rows, ep, t.tm, t.tn, st);
-    case FK_LFWD:
-      if (t.paired)
-        return launch_fold_left_fwd_paired(prec, f, in, out, ax, ncols, batch, bstride, epi, ep,
-                                           t.tm, t.tn, st);
-      return launch_fold_left_fwd(prec, f, in, out, ax, ncols, batch, bstride, epi, ep, t.tm, t.tn,
-                                  st);
-    case FK_LINV:
-      return launch_fold_left_inv(prec, f, in, out, ax, ncols, batch, bstride, ep, t.tm, t.tn, st);
-    default:
-      return launch_fold_right_inv(prec, f, in, out, ax, rows, epi, ep, t.tm, t.tn, st);
-  }
+  if (prec == 0)
+    return fold_typed<double>(kind, f, in, out, ax, ncols, batch, bstride, rows, epi, ep, t, st);
+  return fold_typed<float>(kind, f, in, out, ax, ncols, batch, bstride, rows, epi, ep, t, st);
 }
 
 }  // namespace qn

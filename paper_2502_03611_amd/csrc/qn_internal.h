@@ -95,15 +95,19 @@ struct FoldOperands {
 };
 // Folded mode-product kinds and their instantiated tile shapes, in order of
 // preference.  FK_LFWD tiles with paired = 1 compute the even and odd
-// spectral rows of a tile together (tm = fold rows per tile).
+// spectral rows of a tile together (tm = fold rows per tile).  tk: rows of
+// the contraction per LDS stage, 0 for the kernel's own depth, else a deep
+// stage for short contractions (valid when it divides bk).  The stage depth
+// changes neither the order nor the grouping of the accumulation.
 enum FoldKind : int { FK_RFWD = 0, FK_LFWD = 1, FK_LINV = 2, FK_RINV = 3 };
 struct FoldTile {
-  int tm, tn, paired;
+  int tm, tn, paired, tk;
 };
 int fold_tiles(int kind, const FoldTile** list);
 // Extents a tile must divide: (mext, next) = (rows, bk) for the x products,
 // (bk, ncols) for the y/z products; workgroups of one launch with tile t.
 void fold_extents(int kind, int bk, int ncols, int rows, long long* mext, long long* next);
+bool fold_tile_fits(int kind, const FoldTile& t, int bk, int ncols, int rows);
 long long fold_blocks(int kind, const FoldTile& t, int bk, int ncols, int batch, int rows);
 // One folded mode product: form L (y/z) uses ncols, batch, bstride; form R
 // (x) uses rows; epi applies to FK_LFWD (STORE / DIVIDE) and FK_RINV (STORE /
@@ -111,23 +115,6 @@ long long fold_blocks(int kind, const FoldTile& t, int bk, int ncols, int batch,
 hipError_t launch_fold(int kind, int prec, const FoldOperands& f, const void* in, void* out,
                        const FoldAxis& ax, int ncols, int batch, long long bstride, int rows,
                        int epi, const EpiArgs& ep, const FoldTile& t, hipStream_t st);
-hipError_t launch_fold_left_fwd(int prec, const FoldOperands& f, const void* B, void* C,
-                                const FoldAxis& ax, int ncols, int batch, long long bstride,
-                                int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st);
-// Paired forward (the even and odd spectral rows of a tile from one load of
-// the raw mirrored rows); tm = fold rows per tile (must divide bk).
-hipError_t launch_fold_left_fwd_paired(int prec, const FoldOperands& f, const void* B, void* C,
-                                       const FoldAxis& ax, int ncols, int batch, long long bstride,
-                                       int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st);
-hipError_t launch_fold_left_inv(int prec, const FoldOperands& f, const void* Y, void* C,
-                                const FoldAxis& ax, int ncols, int batch, long long bstride,
-                                const EpiArgs& ep, int tm, int tn, hipStream_t st);
-hipError_t launch_fold_right_fwd(int prec, const FoldOperands& f, const void* A, void* C,
-                                 const FoldAxis& ax, int rows, const EpiArgs& ep, int tm, int tn,
-                                 hipStream_t st);
-hipError_t launch_fold_right_inv(int prec, const FoldOperands& f, const void* Y, void* C,
-                                 const FoldAxis& ax, int rows, int epi, const EpiArgs& ep, int tm,
-                                 int tn, hipStream_t st);
 
 // Residual of the nonlinear problem, written (with zero padding) into the
 // transform workspace or into a dense caller array.  out_prec: 0 fp64, 1 fp32.

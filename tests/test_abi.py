@@ -93,12 +93,15 @@ def test_autotune_and_tile_info_need_a_workspace():
     L = qn.lib()
     L.qn_autotune.argtypes = [ctypes.c_void_p]
     L.qn_tile_info.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    L.qn_set_tile.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     info = (ctypes.c_int32 * 4)()
     assert L.qn_autotune(None) == qn.QN_ERR_INVALID
     st, ctx = setup(n=(33, 17, 9))
     assert st == qn.QN_OK
     assert L.qn_autotune(ctx) == qn.QN_ERR_WORKSPACE
     assert L.qn_tile_info(ctx, 0, info) == qn.QN_ERR_WORKSPACE
+    assert L.qn_set_tile(ctx, 0, info) == qn.QN_ERR_WORKSPACE
+    assert L.qn_set_tile(None, 0, info) == qn.QN_ERR_INVALID
     L.qn_destroy(ctx)
 
 

@@ -330,6 +330,40 @@ def test_deterministic_bitwise():
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("shape,prec", [((255, 255), "fp64"), ((63, 63), "fp32"),
+                                        ((40, 70, 130), "fp64")])
+def test_every_admissible_tile_gives_the_same_bits(shape, prec):
+    """Each launch of the solve is pinned in turn to every instantiated tile
+    (plain, paired, deep-staged) that qn_set_tile accepts; every solve returns
+    the bits of the default one.  Shapes that are not admissible are refused."""
+    print(f"all tiles {shape} {prec}", flush=True)
+    f = dev(synth.random_field((1,) + shape, 302, scale=20.0))
+    ref = Solver(shape, "cubic", beta=1.0, precision=prec)
+    want = ref.fdm_solve(f, scale=1.5, shift=0.25)
+    s = Solver(shape, "cubic", beta=1.0, precision=prec)
+    default = s.tiles()
+    tried = 0
+    for i, (kind, axis, _, _) in enumerate(default):
+        base = kind & 3
+        for flags in (0, 4, 8, 12):
+            for tm in (32, 64, 128):
+                for tn in (32, 64, 128):
+                    try:
+                        s.set_tile(i, (base + flags, axis, tm, tn))
+                    except QNError:
+                        continue
+                    tried += 1
+                    assert s.tiles()[i] == (base + flags, axis, tm, tn)
+                    got = s.fdm_solve(f, scale=1.5, shift=0.25)
+                    assert torch.equal(got, want), (i, base + flags, tm, tn)
+        s.set_tile(i, default[i])
+    assert tried > len(default)
+    with pytest.raises(QNError):
+        s.set_tile(0, (3, 0, 32, 32))  # wrong kind for launch 0
+    with pytest.raises(QNError):
+        s.set_tile(0, (0, 0, 48, 32))  # not an instantiated shape
+
+
 @pytest.mark.parametrize("kind,shape,prec", [
     ("cubic", (37, 45, 70), "fp64"), ("system", (31, 64, 97), "fp64"),
     ("quasilinear", (65, 33), "fp64"), ("cubic", (40, 50, 70), "fp32"),
