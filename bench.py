@@ -246,11 +246,10 @@ def main():
     # forward, z forward + divide, z and y inverse, x inverse + update)
     def kernel_name(slot, t):
         # kind: 0 x fwd, 1 y/z fwd, 2 y/z inv, 3 x inv; +4 when the tile is
-        # paired, +8 when it stages the contraction deep (last template argument:
-        # 64 rows forward, 32 fold rows inverse and paired, else 0)
+        # paired; + the LDS stage depth when not the kernel's default (the
+        # last template argument, 0 for the default)
         kind, _, tm, tn = t
-        base, paired, deep = kind % 4, bool(kind & 4), bool(kind & 8)
-        tk = 0 if not deep else (32 if base in (2, 3) or paired else 64)
+        base, paired, tk = kind & 3, bool(kind & 4), kind & ~7
         if base == 0:
             return f"k_fold_right_fwd<double,{tm},{tn},{tk}>"
         if base == 1:

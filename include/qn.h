@@ -192,10 +192,10 @@ qn_status qn_autotune(qn_ctx ctx);
 /* Launch i of the solve: info4 = {kind, axis (0 x, 1 y, 2 z), tile_m,
  * tile_n}; kind is 0 x forward, 1 y/z forward, 2 y/z inverse, 3 x inverse,
  * plus 4 when one tile computes both the even and the odd spectral half
- * (paired forward tiles; tile_m or tile_n then counts fold indices), plus 8
- * when the tile stages the contraction in deep chunks (64 rows in the x and
- * y/z forward kernels, 32 fold rows in the inverse and paired kernels; for
- * short contractions).  Requires a bound workspace. */
+ * (paired forward tiles; tile_m or tile_n then counts fold indices), plus
+ * the tile's LDS stage depth tk when it is not the kernel's default (32 or 64
+ * contraction rows per stage: deep stages for short contractions).
+ * Requires a bound workspace. */
 qn_status qn_tile_info(qn_ctx ctx, int32_t i, int32_t* info4);
 /* Pin launch i to the tile info4 (same encoding as qn_tile_info), e.g. one
  * that qn_autotune chose for another context of the same grid.  The shape must

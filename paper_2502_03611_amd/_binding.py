@@ -215,7 +215,8 @@ class Solver:
 
     def tiles(self):
         """[(kind, axis, tile_m, tile_n)] of the solve's mode-product launches
-        (kind: 0 x fwd, 1 y/z fwd, 2 y/z inv, 3 x inv; +4 paired, +8 deep stages)."""
+        (kind: 0 x fwd, 1 y/z fwd, 2 y/z inv, 3 x inv; +4 paired; + the LDS
+        stage depth when it is not the kernel's default: 32 or 64)."""
         out = []
         info = (c_i32 * 4)()
         for i in range(6 if self.dim == 3 else 4):

@@ -824,7 +824,7 @@ qn_status qn_tile_info(qn_ctx c, int32_t i, int32_t* info4) {
   const FoldTile t = step_tile(c, st[i], i);
   const int kid = st[i].kid;
   const int kind = kid == K_GEMM_X ? 0 : kid == K_GEMM_X_UPDATE ? 3 : kid == K_GEMM_YZ_INV ? 2 : 1;
-  info4[0] = kind + (t.paired ? 4 : 0) + (t.tk ? 8 : 0);
+  info4[0] = kind + (t.paired ? 4 : 0) + t.tk;
   info4[1] = st[i].axis;
   info4[2] = t.tm;
   info4[3] = t.tn;
@@ -840,13 +840,13 @@ qn_status qn_set_tile(qn_ctx c, int32_t i, const int32_t* info4) {
   if (i < 0 || i >= ns) return fail(QN_ERR_INVALID, "launch index %d out of range [0, %d)", i, ns);
   const int kid = st[i].kid;
   const int kind = kid == K_GEMM_X ? 0 : kid == K_GEMM_X_UPDATE ? 3 : kid == K_GEMM_YZ_INV ? 2 : 1;
-  if ((info4[0] & 3) != kind || (info4[0] & ~15) != 0 || info4[1] != st[i].axis)
+  if ((info4[0] & 3) != kind || info4[1] != st[i].axis)
     return fail(QN_ERR_INVALID, "launch %d is kind %d on axis %d", i, kind, st[i].axis);
   FoldTile cand[16];
   const int nc = step_candidates(c, st[i], cand);
   for (int k = 0; k < nc; ++k) {
     const FoldTile& t = cand[k];
-    const int flags = kind + (t.paired ? 4 : 0) + (t.tk ? 8 : 0);
+    const int flags = kind + (t.paired ? 4 : 0) + t.tk;
     if (flags == info4[0] && t.tm == info4[2] && t.tn == info4[3]) {
       if (!c->tuned)
         for (int j = 0; j < ns; ++j) c->tile[j] = step_tile(c, st[j], j);
