@@ -43,14 +43,15 @@ PEAK_HBM_GBS = 8000.0
 # 511^3, the read counter scaled x2.0 and the write counter x1.0 (both
 # calibrated on a plain 1 GiB device copy), keyed by kernel.  Each figure is
 # valid only while the source file it was taken on is unchanged.
-TRAFFIC_SOURCES = {"fold": ("paper_2502_03611_amd/csrc/qn_gemm_fold.hip", "aad94ef5fe11049d"),
-                   "pointwise": ("paper_2502_03611_amd/csrc/qn_pointwise.hip", "d7cdd5253cdee9d8")}
-TRAFFIC = {"k_fold_right_fwd<double,128,128>": ("fold", 1.2720e9, 1.0737e9),
-           "k_fold_left_fwd2<double,64,64,EPI_STORE>": ("fold", 1.4570e9, 1.0737e9),
-           "k_fold_left_fwd2<double,64,64,EPI_DIVIDE>": ("fold", 1.4329e9, 1.0737e9),
-           "k_fold_left_inv<double,64,64>": ("fold", 1.3857e9, 1.0716e9),
-           "k_fold_right_inv<double,64,64,EPI_SUB_DENSE>": ("fold", 2.4337e9, 1.0728e9),
-           "k_residual<QUASILIN,double>": ("pointwise", 2.2935e9, 1.0740e9)}
+TRAFFIC_SOURCES = {"fold": ("paper_2502_03611_amd/csrc/qn_gemm_fold.hip", "5153ba624ac5e5bc"),
+                   "pointwise": ("paper_2502_03611_amd/csrc/qn_pointwise.hip", "77d54b1602859d98")}
+TRAFFIC = {"k_fold_right_fwd<double,64,128,0>": ("fold", 1.4506e9, 1.0737e9),
+           "k_fold_right_fwd<double,128,128,0>": ("fold", 1.2715e9, 1.0737e9),
+           "k_fold_left_fwd2<double,64,64,EPI_STORE,0>": ("fold", 1.4548e9, 1.0737e9),
+           "k_fold_left_fwd2<double,64,64,EPI_DIVIDE,0>": ("fold", 1.4333e9, 1.0737e9),
+           "k_fold_left_inv<double,64,64,0>": ("fold", 1.3847e9, 1.0716e9),
+           "k_fold_right_inv<double,64,64,EPI_SUB_DENSE,0>": ("fold", 2.4423e9, 1.0725e9),
+           "k_residual<QUASILIN,double>": ("pointwise", 2.2754e9, 1.0739e9)}
 
 
 def traffic_if_current(kernel, n):

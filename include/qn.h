@@ -51,9 +51,9 @@
  * Ordering: every call is enqueued on the context's stream (options.stream,
  * NULL = the default stream).  qn_residual and qn_fdm_solve are asynchronous.
  * qn_iterate reads a few scalars back per iteration (the residual norm and
- * the shift) while the next iteration is already enqueued (a solve whose
- * iteration has stopped skips itself on the device), and returns after the
- * stream has drained.  qn_bind_workspace also creates the iteration's
+ * the shift) while the next iteration (up to max_iter) is already enqueued
+ * (the solve and residual of an iteration that has stopped skip themselves on
+ * the device), and returns after the stream has drained.  qn_bind_workspace also creates the iteration's
  * pinned read-back buffer (two small host slots) and events.
  *
  * Errors: every entry point returns a qn_status; nothing aborts or throws

@@ -245,8 +245,10 @@ GemmOperands operands(qn_ctx c, int axis) {
 // Residual of U into the padded transform workspace W1 (+ partials), then
 // the on-device finalize with the context's shift rule.
 hipError_t residual_into_ws(qn_ctx c, const double* U, const double* F, double* red_out,
-                            double rtol = 0.0, int iter = -1, int max_iter = 0) {
+                            double rtol = 0.0, int iter = -1, int max_iter = 0,
+                            const int* stop = nullptr) {
   ResidualArgs a{};
+  a.stop = stop;
   a.U = U;
   a.F = F;
   a.R = c->ws + c->off_W1;
@@ -714,14 +716,17 @@ qn_status qn_iterate(qn_ctx c, double* d_U, const double* d_F, double rtol, int3
   };
   // Iteration k = residual + reductions + loop decision (finalize, on the
   // device), then the solve of step k.  The host runs one iteration ahead: it
-  // enqueues iteration k + 1 (whose solve skips itself on the device once
-  // iteration k decided to stop) before it reads iteration k's scalars, so
-  // the GPU does not idle during the read-back.
+  // enqueues iteration k + 1 (whose solve and residual skip themselves on the
+  // device once iteration k decided to stop) before it reads iteration k's
+  // scalars, so the GPU does not idle during the read-back.  Nothing is
+  // enqueued past max_iter.  (The finalize after a skipped residual recomputes
+  // the previous iteration's scalars from its partials, and nothing reads them.)
   const int* done = &c->scal()->done;
   auto enqueue = [&](int k) {
     hipError_t e = hipSuccess;
     if (k > 0) e = solve_ws(c, &c->scal()->scale, d_U, EPI_SUB_DENSE, done);
-    if (e == hipSuccess) e = residual_into_ws(c, d_U, d_F, nullptr, rtol, k, max_iter);
+    if (e == hipSuccess)
+      e = residual_into_ws(c, d_U, d_F, nullptr, rtol, k, max_iter, k > 0 ? done : nullptr);
     if (e == hipSuccess)
       e = hipMemcpyAsync(&c->hring[k & 1], c->scal(), sizeof(DevScalars), hipMemcpyDeviceToHost,
                          c->stream);
@@ -736,7 +741,7 @@ qn_status qn_iterate(qn_ctx c, double* d_U, const double* d_F, double rtol, int3
   };
   hipError_t e = enqueue(0);
   for (int k = 0; e == hipSuccess; ++k) {
-    e = enqueue(k + 1);
+    if (k < max_iter) e = enqueue(k + 1);
     if (e == hipSuccess) e = hipEventSynchronize(c->ring_ev[k & 1]);
     if (e != hipSuccess) break;
     const DevScalars h = c->hring[k & 1];

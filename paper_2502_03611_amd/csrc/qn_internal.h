@@ -132,6 +132,7 @@ struct ResidualArgs {
   double* partials;        // per-block {sumR2, mumin, mumax, sumF2}
   int rz;                  // 3D: z-planes per workgroup; planar: y-rows per workgroup
   const int* skip;         // batched solver: per-z-plane (instance) skip flags, else NULL
+  const int* stop;         // single problem: the whole launch returns when *stop != 0, or NULL
 };
 hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t st);
 // Workgroups (= partial slots) of a residual launch; planar: no z coupling

@@ -91,6 +91,7 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
   const int z0 = bz * a.rz;
   const int z1 = min(z0 + a.rz, a.oz);
   if (a.skip && a.skip[z0]) return;  // batched solver: finished instance (rz = 1)
+  if (a.stop && *a.stop) return;      // single problem: the iteration has stopped
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const long long plane = (long long)nx * ny;
   const long long comp = plane * nz;
@@ -244,6 +245,7 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
   const int tile = xcd_tile((blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x, gx * gy * gridDim.z);
   const int bx = tile % gx, by = (tile / gx) % gy, pl = tile / (gx * gy);
   if (a.skip && a.skip[pl]) return;  // batched solver: finished instance
+  if (a.stop && *a.stop) return;      // single problem: the iteration has stopped
   const int nx = a.nx, ny = a.ny;
   const int x = bx * R2X + threadIdx.x;
   const int y0 = by * a.rz, y1 = min(y0 + a.rz, a.oy);
