@@ -173,11 +173,14 @@ def bench_learned(nseeds=50):
     rows = lg.compare(net, range(10000, 10000 + nseeds))
     outd = {"held_out_seeds": nseeds, "n": 255}
     for key in ("fp64_zero", "fp64_net", "fp32_zero", "fp32_net"):
+        t = np.array([r[key]["t"] for r in rows])
         outd[key] = {"mean_iters": round(float(np.mean([r[key]["iters"] for r in rows])), 3),
-                     "mean_time_ms": round(1e3 * float(np.mean([r[key]["t"] for r in rows])), 3),
+                     "mean_time_ms": round(1e3 * float(t.mean()), 3),
+                     "median_time_ms": round(1e3 * float(np.median(t)), 3),
                      "all_converged": bool(all(r[key]["status"] == 0 for r in rows))}
+    # medians: single slow solves (host hiccups) move the means
     outd["speedup_fp32_net_vs_fp64_zero"] = round(
-        outd["fp64_zero"]["mean_time_ms"] / outd["fp32_net"]["mean_time_ms"], 3)
+        outd["fp64_zero"]["median_time_ms"] / outd["fp32_net"]["median_time_ms"], 3)
     return outd
 
 
