@@ -32,9 +32,10 @@ __device__ inline float gelu_grad(float x) {
 
 // Layer 1: x0 = (f / 50, v0); z1 = b1 + W1 * x0; a1 = gelu(z1).  One thread
 // per pixel computes all 32 channels; the weights (32, 2, 3, 3) are staged in
-// LDS and read at wave-uniform addresses (broadcast).  The 128 x 32 outputs of a workgroup
-// go through LDS (row stride 33: conflict-free columns) so that the stores are
-// one contiguous 16 KB run.  TRAIN also keeps x0 and z1 for the backward pass.
+// LDS and read at wave-uniform addresses (broadcast).  The 128 x 32 outputs
+// of a workgroup go through LDS (row stride 33: conflict-free columns) so that
+// the stores are one contiguous 16 KB run.  TRAIN also keeps x0 and z1 for the
+// backward pass.
 constexpr int L1_PX = 128;
 template <bool TRAIN>
 __global__ __launch_bounds__(L1_PX) void k_in_fwd(const double* __restrict__ f,

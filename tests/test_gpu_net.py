@@ -46,6 +46,21 @@ def test_forward_parity(B, H, W):
     assert rel(f - out, g_ref) <= 2e-5
 
 
+def test_forward_batch_matches_single_images_bitwise():
+    """Per-pixel arithmetic does not depend on the batch: a batch of two 255^2
+    images (130050 pixels, so the output layer walks its grid-stride loop)
+    returns the bits of the two images run one at a time."""
+    H = W = 255
+    theta = onet.he_init(9).astype(np.float32).astype(np.float64)
+    f, v, _ = inputs(2, H, W, 5)
+    net = Net(H, W, max_batch=2)
+    net.set_params(theta)
+    both = net.forward(dev(f), dev(v))
+    for b in range(2):
+        one = net.forward(dev(f[b:b + 1]), dev(v[b:b + 1]))
+        assert torch.equal(both[b:b + 1], one), b
+
+
 @pytest.mark.parametrize("B,H,W", [(2, 20, 37), (1, 17, 40)])
 def test_loss_and_gradient_parity(B, H, W):
     print(f"net grad {B}x{H}x{W}", flush=True)
