@@ -185,28 +185,42 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const f
   }
 
   float* Cb = C + (long long)b * bstride;
-  double scale = 0.0, beta = 0.0;
   if (EPI == EPI_DIVIDE) {
+    // denominator scale (lam_m + lam_x + lam_y) + beta: the column part once
+    // per column block, the row part once per row, one FP64 divide per entry
     const double* cf = ep.coef + (long long)inst * ep.coef_stride;
-    scale = cf[0];
-    beta = cf[1];
-  }
+    const double scale = cf[0], beta = cf[1];
+    double cn[BN];
 #pragma unroll
-  for (int i = 0; i < BM; ++i)
+    for (int j = 0; j < BN; ++j) {
+      const int n = n0 + wn + 16 * j + (lane & 15);
+      const int ny_ = n / ep.px;
+      cn[j] = ep.lamX[n - ny_ * ep.px] + (ep.lamY ? ep.lamY[ny_] : 0.0);
+    }
 #pragma unroll
-    for (int j = 0; j < BN; ++j)
+    for (int i = 0; i < BM; ++i)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
-        const int n = n0 + wn + 16 * j + (lane & 15);
-        float v = acc[i][j][q];
-        if (EPI == EPI_DIVIDE) {
-          const double ly = ep.lamY ? ep.lamY[n / ep.px] : 0.0;
-          const double d = scale * (ep.lamM[m] + ep.lamX[n % ep.px] + ly) + beta;
-          v = (float)((double)v / d);
+        const double lm = ep.lamM[m];
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          const int n = n0 + wn + 16 * j + (lane & 15);
+          Cb[(long long)m * ncols + n] =
+              (float)((double)acc[i][j][q] / (scale * (lm + cn[j]) + beta));
         }
-        Cb[(long long)m * ncols + n] = v;
       }
+  } else {
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+          Cb[(long long)m * ncols + n0 + wn + 16 * j + (lane & 15)] = acc[i][j][q];
+      }
+  }
 }
 
 template <int NP, int TM, int TN, int EPI>
