@@ -53,8 +53,9 @@
  * qn_iterate reads a few scalars back per iteration (the residual norm and
  * the shift) while the next iteration (up to max_iter) is already enqueued
  * (the solve and residual of an iteration that has stopped skip themselves on
- * the device), and returns after the stream has drained.  qn_bind_workspace also creates the iteration's
- * pinned read-back buffer (two small host slots) and events.
+ * the device), and returns after the stream has drained.  qn_bind_workspace
+ * also creates the iteration's read-back buffer (two small slots of pinned,
+ * coherent host memory that the device writes directly) and events.
  *
  * Errors: every entry point returns a qn_status; nothing aborts or throws
  * across the ABI.  qn_last_error() gives a thread-local message for the last

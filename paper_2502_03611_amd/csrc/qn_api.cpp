@@ -108,7 +108,8 @@ struct qn_ctx_s {
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
   // qn_iterate: pinned two-slot ring of per-iteration scalars and their events
-  DevScalars* hring = nullptr;
+  DevScalars* hring = nullptr;  // host address
+  DevScalars* dring = nullptr;  // the same slots' device address
   hipEvent_t ring_ev[2] = {nullptr, nullptr};
   double tot_ms[K_COUNT] = {};
   long long launches[K_COUNT] = {};
@@ -246,7 +247,7 @@ GemmOperands operands(qn_ctx c, int axis) {
 // the on-device finalize with the context's shift rule.
 hipError_t residual_into_ws(qn_ctx c, const double* U, const double* F, double* red_out,
                             double rtol = 0.0, int iter = -1, int max_iter = 0,
-                            const int* stop = nullptr) {
+                            const int* stop = nullptr, DevScalars* mirror = nullptr) {
   ResidualArgs a{};
   a.stop = stop;
   a.U = U;
@@ -274,7 +275,7 @@ hipError_t residual_into_ws(qn_ctx c, const double* U, const double* F, double* 
   if (e != hipSuccess) return e;
   return timed(c, K_FINALIZE, [&] {
     return launch_finalize(a.partials, nb, c->scal(), rule_of(c), c->beta, c->lam_min_sum, red_out,
-                           rtol, iter, max_iter, c->stream);
+                           rtol, iter, max_iter, c->stream, mirror);
   });
 }
 
@@ -586,7 +587,12 @@ qn_status qn_bind_workspace(qn_ctx c, void* d_ws, size_t bytes) {
     return fail(QN_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, c->need);
   c->ws = (char*)d_ws;
   hipError_t e = hipSuccess;
-  if (!c->hring) e = hipHostMalloc((void**)&c->hring, 2 * sizeof(DevScalars), hipHostMallocDefault);
+  if (!c->hring) {
+    // coherent: the finalize kernel writes the slots directly, the host reads
+    // them once the slot's event has completed
+    e = hipHostMalloc((void**)&c->hring, 2 * sizeof(DevScalars), hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->dring, c->hring, 0);
+  }
   for (int i = 0; i < 2 && e == hipSuccess; ++i)
     if (!c->ring_ev[i]) e = hipEventCreateWithFlags(&c->ring_ev[i], hipEventDisableTiming);
   if (e != hipSuccess) return hip_fail(c, e, "iteration read-back buffers");
@@ -725,11 +731,10 @@ qn_status qn_iterate(qn_ctx c, double* d_U, const double* d_F, double rtol, int3
   auto enqueue = [&](int k) {
     hipError_t e = hipSuccess;
     if (k > 0) e = solve_ws(c, &c->scal()->scale, d_U, EPI_SUB_DENSE, done);
+    // the finalize kernel also writes the scalars into host slot k & 1
     if (e == hipSuccess)
-      e = residual_into_ws(c, d_U, d_F, nullptr, rtol, k, max_iter, k > 0 ? done : nullptr);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(&c->hring[k & 1], c->scal(), sizeof(DevScalars), hipMemcpyDeviceToHost,
-                         c->stream);
+      e = residual_into_ws(c, d_U, d_F, nullptr, rtol, k, max_iter, k > 0 ? done : nullptr,
+                           c->dring + (k & 1));
     if (e == hipSuccess) e = hipEventRecord(c->ring_ev[k & 1], c->stream);
     return e;
   };

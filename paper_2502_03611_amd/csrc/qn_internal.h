@@ -165,9 +165,11 @@ hipError_t launch_breset(BState* st, int* done, int K, hipStream_t s);
 // for iter >= 0, the loop decision: done = the relative residual is <= rtol,
 // non-finite or above 1e30, iter >= max_iter, or the shift rule gives a
 // singular operator.
+// mirror (nullable): a second copy of the scalars, e.g. the device address of
+// a pinned host slot that the host reads after an event.
 hipError_t launch_finalize(const double* partials, int nblocks, DevScalars* sc, int rule,
                            double beta_fixed, double lam_min_sum, double* red_out, double rtol,
-                           int iter, int max_iter, hipStream_t st);
+                           int iter, int max_iter, hipStream_t st, DevScalars* mirror = nullptr);
 
 // Dense (ncomp, nz, ny, nx) fp64 -> padded (ncomp, pz, py, px) fp64/fp32, zero pads.
 hipError_t launch_pad_copy(const double* src, void* dst, int out_prec, int ncomp, int nx, int ny,

@@ -411,7 +411,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double* __restri
                                                           int nblocks, DevScalars* sc, int rule,
                                                           double beta_fixed, double lam_min_sum,
                                                           double* red_out, double rtol, int iter,
-                                                          int max_iter) {
+                                                          int max_iter, DevScalars* mirror) {
   double s0 = 0.0, s1 = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
   for (int i = threadIdx.x; i < nblocks; i += FIN_THREADS) {
     s0 += partials[4 * i + 0];
@@ -421,19 +421,21 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double* __restri
   }
   block_reduce4<FIN_THREADS / 64>(s0, mn, mx, s1);
   if (threadIdx.x == 0) {
-    double scale = 1.0, beta = beta_fixed;
-    if (rule == RULE_MIDPOINT) beta = 0.5 * (mn + mx);
-    if (rule == RULE_COEFF_MID) scale = 0.5 * (mn + mx);
-    sc->sumsqR = s0;
-    sc->mumin = mn;
-    sc->mumax = mx;
-    sc->sumsqF = s1;
-    sc->relres = sqrt(s0) / sqrt(s1);
-    sc->scale = scale;
-    sc->beta = beta;
-    sc->flag = (scale > 0.0 && scale * lam_min_sum + beta > 0.0) ? 0.0 : 1.0;
-    const double rr = sc->relres;
-    sc->done = iter >= 0 && (!(rr <= 1e30) || rr <= rtol || iter >= max_iter || sc->flag != 0.0);
+    DevScalars r{};
+    r.scale = 1.0;
+    r.beta = beta_fixed;
+    if (rule == RULE_MIDPOINT) r.beta = 0.5 * (mn + mx);
+    if (rule == RULE_COEFF_MID) r.scale = 0.5 * (mn + mx);
+    r.sumsqR = s0;
+    r.mumin = mn;
+    r.mumax = mx;
+    r.sumsqF = s1;
+    r.relres = sqrt(s0) / sqrt(s1);
+    r.flag = (r.scale > 0.0 && r.scale * lam_min_sum + r.beta > 0.0) ? 0.0 : 1.0;
+    const double rr = r.relres;
+    r.done = iter >= 0 && (!(rr <= 1e30) || rr <= rtol || iter >= max_iter || r.flag != 0.0);
+    *sc = r;
+    if (mirror) *mirror = r;  // the host's read-back slot (pinned, coherent)
     if (red_out) {
       red_out[0] = s0;
       red_out[1] = mn;
@@ -445,9 +447,9 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double* __restri
 
 hipError_t launch_finalize(const double* partials, int nblocks, DevScalars* sc, int rule,
                            double beta_fixed, double lam_min_sum, double* red_out, double rtol,
-                           int iter, int max_iter, hipStream_t st) {
+                           int iter, int max_iter, hipStream_t st, DevScalars* mirror) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, st, partials, nblocks, sc, rule,
-                     beta_fixed, lam_min_sum, red_out, rtol, iter, max_iter);
+                     beta_fixed, lam_min_sum, red_out, rtol, iter, max_iter, mirror);
   return hipGetLastError();
 }
 
