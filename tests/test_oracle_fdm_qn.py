@@ -143,3 +143,23 @@ def test_config2_iterations():
     ue, f = synth.manufactured_c2(31)
     res = qn.qn_solve(qn.CUBIC, f[None], beta=0.1007)
     assert res["converged"] and res["iters"] == 4
+
+
+def test_config2_beta_sweep():
+    """The fixed shift of the 3D cubic workload: the oracle's sweep over
+    beta in {0, b_mid, 2 b_mid, 5 b_mid}, b_mid = 1.5 max(U*^2) (the midpoint
+    of f_u = 3u^2 at the exact solution, Section 4), recorded at 63^3.  The
+    fixed beta = 0.1007 is b_mid and needs no more iterations than any other
+    point of the sweep."""
+    ue, f = synth.manufactured_c2(63)
+    b_mid = 1.5 * float(np.max(ue ** 2))
+    assert b_mid == pytest.approx(0.1007, abs=5e-4)
+    sweep = {}
+    for b in (0.0, b_mid, 2.0 * b_mid, 5.0 * b_mid):
+        res = qn.qn_solve(qn.CUBIC, f[None], beta=b)
+        assert res["converged"]
+        sweep[round(b, 4)] = res["iters"]
+    print("beta sweep (beta: iterations):", sweep)
+    assert list(sweep.values()) == [4, 4, 5, 6]
+    fixed = qn.qn_solve(qn.CUBIC, f[None], beta=0.1007)
+    assert fixed["iters"] == min(sweep.values())
