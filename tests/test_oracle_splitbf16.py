@@ -1,0 +1,65 @@
+"""Pins for oracle.splitbf16: round-to-nearest-even to bfloat16 against brute
+force, the exactness of the parts, and the error of the split products
+against the FP64 product (bounds from the splitting: each RNE step to an
+8-bit significand leaves a remainder <= 2^-8 of its input)."""
+
+import numpy as np
+import pytest
+
+from oracle import splitbf16 as sb
+
+
+def brute_bf16(x):
+    """Nearest bfloat16 by enumerating the two neighbours on the bf16 grid."""
+    out = np.empty_like(x)
+    for i, v in enumerate(x):
+        bits = int(np.float32(v).view(np.uint32))
+        lo = np.uint32(bits & 0xFFFF0000).view(np.float32)
+        hi = np.uint32((bits & 0xFFFF0000) + 0x10000).view(np.float32)
+        dlo, dhi = abs(float(v) - float(lo)), abs(float(hi) - float(v))
+        if dlo < dhi:
+            out[i] = lo
+        elif dhi < dlo:
+            out[i] = hi
+        else:  # tie: the even significand
+            out[i] = lo if ((bits >> 16) & 1) == 0 else hi
+    return out
+
+
+def test_rne_matches_brute_force():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([(rng.standard_normal(4000) * 10.0 ** rng.integers(-6, 6, 4000)).astype(np.float32),
+                        # exact ties: bf16 grid value + half an ulp, both parities
+                        (np.arange(1, 200, dtype=np.uint32) << 16 | 0x8000).view(np.float32),
+                        np.array([0.0, -0.0, 1.0, -3.5], np.float32)])
+    assert np.array_equal(sb.bf16_rne(x).view(np.uint32), brute_bf16(x).view(np.uint32))
+
+
+def test_parts_are_bf16_and_reconstruct():
+    rng = np.random.default_rng(1)
+    x = (rng.standard_normal(10000) * 3.0).astype(np.float32)
+    for parts, bound in ((2, 2.0 ** -16), (3, 2.0 ** -24)):
+        p = sb.split(x, parts)
+        for q in p:  # every part is representable in bf16: low 16 bits zero
+            assert np.all(q.view(np.uint32) & 0xFFFF == 0)
+        rec = sum(q.astype(np.float64) for q in p)
+        err = np.abs(rec - x.astype(np.float64))
+        assert np.all(err <= bound * np.abs(x.astype(np.float64)) * 1.0001)
+
+
+@pytest.mark.parametrize("parts,coef", [(2, 3 * 2.0 ** -16), (3, 6 * 2.0 ** -24)])
+def test_split_product_error_bound(parts, coef):
+    """|C_split - A B| <= coef * (|A| |B|) entrywise: bf16x3 drops A1 B1 and the
+    remainders below the two parts (each <= 2^-16 of an operand); bf16x6 drops
+    the pairs with i + j >= 3 and the remainders below three parts (2^-24)."""
+    rng = np.random.default_rng(2 + parts)
+    a = rng.standard_normal((64, 512)).astype(np.float32)
+    b = rng.standard_normal((512, 48)).astype(np.float32)
+    a64, b64 = a.astype(np.float64), b.astype(np.float64)
+    c = sb.split_matmul(a, b, parts)
+    ref = a64 @ b64
+    bound = coef * (np.abs(a64) @ np.abs(b64))
+    assert np.all(np.abs(c - ref) <= bound)
+    # and the split is not trivially exact: one part alone is far less accurate
+    c1 = sb.split_matmul(a, b, 1)
+    assert np.max(np.abs(c1 - ref) / bound) > 10.0
