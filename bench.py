@@ -89,6 +89,34 @@ def stream_reference(n):
             "achieved": round(24.0 * n ** 3 / (ms * 1e-3) / 1e9, 1), "unit": "GB/s"}
 
 
+def library_gemm_reference():
+    """Matrix-core rate the vendor GEMM library reaches on this device: one
+    square 8192^3 product through torch.matmul (hipBLASLt / rocBLAS) in FP64
+    and in FP32, 2 n^3 flops each.  Context for the mode-product kernels,
+    whose roofline fraction stays against the published peak."""
+    out = {}
+    n = 8192
+    for name, dt, peak in (("fp64", torch.float64, PEAK_FP64_TFLOPS),
+                           ("fp32", torch.float32, PEAK_FP32_TFLOPS)):
+        a = torch.rand((n, n), dtype=dt, device="cuda")
+        b = torch.rand((n, n), dtype=dt, device="cuda")
+        c = torch.empty((n, n), dtype=dt, device="cuda")
+        for _ in range(2):
+            torch.matmul(a, b, out=c)
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(5):
+            torch.matmul(a, b, out=c)
+        e.record()
+        e.synchronize()
+        ms = s.elapsed_time(e) / 5
+        tf = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+        out[name] = {"avg_ms": round(ms, 3), "tflops": round(tf, 1), "frac_of_peak": round(tf / peak, 3)}
+        del a, b, c
+    torch.cuda.empty_cache()
+    return {"kernel": "torch.matmul, 8192 x 8192 x 8192", **out}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -302,6 +330,7 @@ def main():
                               "avg_launch_ms": round(r_avg, 4),
                               "algorithmic_bytes_per_launch": r_bytes,
                               "stream_reference": stream_reference(n)},
+        "library_gemm_reference": library_gemm_reference(),
         "all_mode_products_tflops": round(flops_per_product * all_gemm_launches /
                                           (all_gemm_ms * 1e-3) / 1e12, 3),
         "all_mode_products_dense_equivalent_tflops": round(dense_flops * all_gemm_launches /
