@@ -121,6 +121,62 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def solve_to_tol(shape, U, F, u_ex, precisions, runs, u64=None):
+    """Per precision: a fresh solver (autotuned, one untimed step), then `runs`
+    full solves from U_0 = 0 to relres 1e-10; the median time, the iteration
+    count, the error against the exact solution and (not FP64) the relative
+    L2 difference from the FP64 result `u64` (the FP64 run sets it when
+    listed first).  Returns (records, u64)."""
+    out = {}
+    for prec in precisions:
+        s = Solver(shape, "quasilinear", beta=0.0, precision=prec)
+        s.autotune()
+        U.zero_()
+        s.iterate(U, F, rtol=0.0, max_iter=1)  # untimed warm-up of this context
+        times = []
+        for _ in range(runs):  # median of several full solves from U_0 = 0
+            U.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = s.iterate(U, F, rtol=1e-10, max_iter=400)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        tt = float(np.median(times))
+        Uh = U[0].cpu().numpy()
+        rec = {"status": st["status"], "iters": st["iters"], "time_to_tol_s": round(tt, 4),
+               "runs_s": [round(r, 4) for r in times],
+               "iters_per_s": round(st["iters"] / tt, 2), "relres": st["relres"],
+               "max_err_vs_exact": float(np.abs(Uh - u_ex).max())}
+        if prec == "fp64":
+            u64 = Uh
+        elif u64 is not None:
+            rec["rel_l2_vs_fp64"] = float(np.linalg.norm(Uh - u64) / np.linalg.norm(u64))
+        out[prec] = rec
+        s.close()
+    return out, u64
+
+
+def amplitude_sweep(n, runs):
+    """Time to tolerance at n^3 for the seeded amplitudes of seeds 0-4 and the
+    worst case A = 2 (FP64, FP32 and bf16x3 transforms)."""
+    shape = (n, n, n)
+    U = torch.zeros((1,) + shape, dtype=torch.float64, device="cuda")
+    cases = [(f"seed {k}", synth.amplitude_c3(k)) for k in range(5)] + [("A = 2", 2.0)]
+    out = []
+    for name, amp in cases:
+        log(f"amplitude sweep: {name} (A = {amp:.4f})")
+        u_ex, f = synth.manufactured_c3(n, amp)
+        F = torch.from_numpy(f[None]).cuda()
+        del f
+        rec, _ = solve_to_tol(shape, U, F, u_ex, ("fp64", "fp32", "bf16x3"), runs)
+        out.append({"case": name, "amplitude": round(amp, 4), **rec})
+        del F, u_ex
+        torch.cuda.empty_cache()
+    del U
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(n, amp):
     """The CPU oracle, as it stands, on a bounded sample: one quasi-Newton
     iteration (residual, shift rule, tensor-product solve, residual) at the
@@ -222,6 +278,8 @@ def main():
     ap.add_argument("--no-time-to-tol", action="store_true")
     ap.add_argument("--ttt-runs", type=int, default=5,
                     help="timed solves per precision for time to tolerance (median reported)")
+    ap.add_argument("--amp-sweep", action="store_true",
+                    help="also report time to tolerance for the amplitudes of seeds 0-4 and A = 2")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--batched-count", type=int, default=512)
@@ -341,35 +399,10 @@ def main():
     }
 
     if not args.no_time_to_tol:
-        ttt = {}
-        u64 = None
         solver.close()
-        for prec in ("fp64", "fp32", "bf16x3", "bf16x6"):
-            log(f"time to tolerance: {prec}")
-            s = Solver(shape, "quasilinear", beta=0.0, precision=prec)
-            s.autotune()
-            U.zero_()
-            s.iterate(U, F, rtol=0.0, max_iter=1)  # untimed warm-up of this context
-            runs = []
-            for _ in range(args.ttt_runs):  # median of several full solves from U_0 = 0
-                U.zero_()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                st = s.iterate(U, F, rtol=1e-10, max_iter=400)
-                torch.cuda.synchronize()
-                runs.append(time.perf_counter() - t0)
-            tt = float(np.median(runs))
-            Uh = U[0].cpu().numpy()
-            rec = {"status": st["status"], "iters": st["iters"], "time_to_tol_s": round(tt, 4),
-                   "runs_s": [round(r, 4) for r in runs],
-                   "iters_per_s": round(st["iters"] / tt, 2), "relres": st["relres"],
-                   "max_err_vs_exact": float(np.abs(Uh - u_ex).max())}
-            if prec == "fp64":
-                u64 = Uh
-            else:
-                rec["rel_l2_vs_fp64"] = float(np.linalg.norm(Uh - u64) / np.linalg.norm(u64))
-            ttt[prec] = rec
-            s.close()
+        log("time to tolerance: fp64, fp32, bf16x3, bf16x6")
+        ttt, _ = solve_to_tol(shape, U, F, u_ex, ("fp64", "fp32", "bf16x3", "bf16x6"),
+                              args.ttt_runs)
         out["time_to_tol"] = ttt
         out["speedup_fp32_vs_fp64"] = round(ttt["fp64"]["time_to_tol_s"] / ttt["fp32"]["time_to_tol_s"], 3)
         out["speedup_bf16x3_vs_fp64"] = round(ttt["fp64"]["time_to_tol_s"] / ttt["bf16x3"]["time_to_tol_s"], 3)
@@ -378,6 +411,8 @@ def main():
     solver.close()
     del U, F
     torch.cuda.empty_cache()
+    if args.amp_sweep:
+        out["amplitude_sweep"] = amplitude_sweep(n, args.ttt_runs)
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_count)
         torch.cuda.empty_cache()
