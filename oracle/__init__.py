@@ -25,6 +25,9 @@ Contents, each following the cited passage of Hao, Lee & Zhang,
   only to pin fixed points at tiny sizes.
 * ``net``       - direct-loop FP64 convolution network pieces (forward,
   gradients, Adam) for the learned initial guess.
+* ``splitbf16`` - the split-bf16 products of the reduced-precision transforms.
+* ``neumann``   - the homogeneous-Neumann (ghost-point) variant of Section 3.2:
+  stiffness matrix, cosine eigenpairs, mirrored stencil, solve and iteration.
 
 Pins: every function here is checked in ``tests/test_oracle_*.py`` against
 closed forms, invariants, brute force or library routines (see each test).

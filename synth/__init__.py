@@ -10,7 +10,8 @@ Array convention everywhere: C-order ``(nz, ny, nx)`` in 3D and ``(ny, nx)`` in
 2D, x fastest, which is the paper's ``vec`` order (first index fastest,
 Section 3.1, eq. vec-property).  ``n`` interior points per axis on (0, 1) with
 spacing ``h = 1/(n+1)`` (Section 3.2, with the boundary nodes removed for
-Dirichlet data).
+Dirichlet data); the Neumann workloads use all ``n`` nodes of ``[-1, 1]``,
+``h = 2/(n-1)``.
 """
 
 from .fields import (  # noqa: F401
@@ -23,5 +24,8 @@ from .fields import (  # noqa: F401
     gaussian_random_field,
     batched_instance,
     learned_guess_rhs,
+    node_coords,
+    neumann_2d,
+    neumann_3d,
     BATCH_SIZES,
 )

@@ -124,3 +124,26 @@ def learned_guess_rhs(seed, n=255):
     ell = float(rng.uniform(0.05, 0.3))
     amp = float(rng.uniform(1.0, 50.0))
     return amp * gaussian_random_field(n, ell, rng)
+
+
+def node_coords(n, a=-1.0, b=1.0):
+    """All n nodes x_j = a + j (b - a)/(n - 1), j = 0..n-1 (boundary included)."""
+    return a + (b - a) * np.arange(n, dtype=np.float64) / (n - 1)
+
+
+def neumann_2d(n):
+    """2D -Lap u + u^3 + u = f on [-1, 1]^2 with zero normal derivative,
+    u = cos(pi x) cos(2 pi y): -Lap u = 5 pi^2 u.  Sampled on all n x n nodes
+    (boundary included).  Returns (u_exact, f), shape (ny, nx)."""
+    x = node_coords(n)
+    u = np.cos(2.0 * math.pi * x)[:, None] * np.cos(math.pi * x)[None, :]
+    return u, 5.0 * math.pi ** 2 * u + u ** 3 + u
+
+
+def neumann_3d(n):
+    """3D -Lap u + u^3 + u = f on [-1, 1]^3 with zero normal derivative,
+    u = cos(pi x) + cos(pi y) + cos(pi z): -Lap u = pi^2 u.  All n^3 nodes.
+    Returns (u_exact, f), shape (nz, ny, nx)."""
+    c = np.cos(math.pi * node_coords(n))
+    u = c[:, None, None] + c[None, :, None] + c[None, None, :]
+    return u, math.pi ** 2 * u + u ** 3 + u
