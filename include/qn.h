@@ -103,15 +103,33 @@ typedef struct {
   int32_t ncomp;
 } qn_grid;
 
+/* Boundary data (Section 3.2), homogeneous in both cases:
+ * QN_BC_DIRICHLET: u = 0 on the boundary; the unknowns are the n interior
+ *   nodes per axis of an interval of length L, h = L / (n + 1).
+ * QN_BC_NEUMANN: zero normal derivative by ghost nodes (the ghost value is the
+ *   mirror image of the first interior neighbour); the unknowns are all n
+ *   nodes including both ends, h = L / (n - 1), n >= 2.  The 1D stiffness
+ *   matrix has the rows h^-2 (2, -2) and h^-2 (-2, 2) at the ends and the
+ *   cosine eigenvectors cos(j k pi / (n - 1)); its lowest eigenvalue is 0, so
+ *   solves need a positive shift.  Supported for QN_NL_CUBIC with the FP64
+ *   and FP32 precisions. */
+typedef enum { QN_BC_DIRICHLET = 0, QN_BC_NEUMANN = 1 } qn_boundary;
+
 /* precision: qn_precision; beta_mode: qn_beta_mode; timing: nonzero records
- * HIP events around every kernel launch (see qn_timing_*); stream: a
- * hipStream_t, NULL = default stream. */
+ * HIP events around every kernel launch (see qn_timing_*); boundary:
+ * qn_boundary; stream: a hipStream_t, NULL = default stream; length: the
+ * side L of the domain (every axis), 0 = 1.0; lin: the linear coefficient
+ * lambda of the paper's -Lap u + lambda u + f(x, u) = 0 (Section 2) for
+ * QN_NL_CUBIC, i.e. F^h(U) = A_h U + lambda U + U^3 - F with Jacobian diagonal
+ * 3 U^2 + lambda (must be 0 for the other nonlinearities). */
 typedef struct {
   int32_t precision;
   int32_t beta_mode;
   int32_t timing;
-  int32_t reserved;
+  int32_t boundary;
   void* stream;
+  double length;
+  double lin;
 } qn_options;
 
 /* iters: solves performed; status: the qn_status qn_iterate returned;
@@ -130,14 +148,18 @@ typedef struct {
 
 typedef struct qn_ctx_s* qn_ctx;
 
-/* Create a context: validates the grid, computes the closed-form sine
- * eigenpairs of the 1D stiffness matrix h^-2 tridiag(-1,2,-1) per axis
- * (Section 3.2 eq. Sy; Section 4.2 with M = I) on the host.  beta: the fixed
+/* Create a context: validates the grid, computes the closed-form eigenpairs
+ * of the 1D stiffness matrix per axis on the host: sine modes of
+ * h^-2 tridiag(-1,2,-1) (Section 3.2 eq. Sy; Section 4.2 with M = I) for
+ * Dirichlet data, cosine modes of the ghost-point matrix for Neumann data.  beta: the fixed
  * shift (must satisfy beta + sum_a lam_min,a > 0).  opt may be NULL (FP64,
  * fixed beta, no timing, default stream).  No device memory is touched.
  * Errors: QN_ERR_INVALID for dim not in {2,3}, n out of range, ncomp
- * inconsistent with nonlinearity, unknown enum values, a singular shift or
- * QN_BETA_MIDPOINT with QN_NL_QUASILIN. */
+ * inconsistent with nonlinearity, unknown enum values, a singular shift,
+ * QN_BETA_MIDPOINT with QN_NL_QUASILIN, a non-positive or non-finite length,
+ * a non-finite lin or a nonzero lin with a nonlinearity other than
+ * QN_NL_CUBIC, n < 2 with QN_BC_NEUMANN; QN_ERR_UNSUPPORTED for QN_BC_NEUMANN
+ * with another nonlinearity than QN_NL_CUBIC or a split-bf16 precision. */
 qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity,
                    const qn_options* opt, qn_ctx* out);
 

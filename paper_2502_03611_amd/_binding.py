@@ -33,7 +33,10 @@ class QNGrid(ctypes.Structure):
 
 class QNOptions(ctypes.Structure):
     _fields_ = [("precision", c_i32), ("beta_mode", c_i32), ("timing", c_i32),
-                ("reserved", c_i32), ("stream", c_vp)]
+                ("boundary", c_i32), ("stream", c_vp), ("length", c_dbl), ("lin", c_dbl)]
+
+
+BOUNDARIES = {"dirichlet": 0, "neumann": 1}
 
 
 class QNStats(ctypes.Structure):
@@ -109,7 +112,13 @@ class Solver:
     """
 
     def __init__(self, shape, nonlinearity="cubic", beta=0.0, beta_mode="fixed",
-                 precision="fp64", timing=False, device="cuda"):
+                 precision="fp64", timing=False, device="cuda", boundary="dirichlet",
+                 length=None, lin=0.0):
+        """boundary: "dirichlet" (n interior nodes per axis, h = L/(n+1)) or
+        "neumann" (n nodes including both ends, zero normal derivative,
+        h = L/(n-1)); length: the domain side L (default 1 for Dirichlet, 2 for
+        Neumann, i.e. [-1, 1]); lin: the linear coefficient lambda of
+        -Lap u + lambda u + u^3 = f (cubic problem only)."""
         L = lib()
         self.shape = tuple(int(s) for s in shape)
         self.dim = len(self.shape)
@@ -126,7 +135,11 @@ class Solver:
         o.precision = PRECISIONS[precision]
         o.beta_mode = BETA_MODES[beta_mode]
         o.timing = 1 if timing else 0
+        o.boundary = BOUNDARIES[boundary]
+        o.length = float(length if length is not None else (2.0 if boundary == "neumann" else 1.0))
+        o.lin = float(lin)
         o.stream = None
+        self.boundary = boundary
         ctx = c_vp()
         check(L.qn_setup(ctypes.byref(g), float(beta), NONLINEARITIES[nonlinearity],
                          ctypes.byref(o), ctypes.byref(ctx)))

@@ -92,6 +92,9 @@ struct qn_ctx_s {
   int p[3] = {32, 32, 1};
   double beta = 0.0;
   double lam_min_sum = 0.0;
+  int bc = QN_BC_DIRICHLET;
+  double length = 1.0, lin = 0.0;
+  double ih2[3] = {1.0, 1.0, 0.0};  // h^-2 per axis (0 for the missing z of 2D)
   hipStream_t stream = nullptr;
   bool fold = true;       // reflection-folded transforms (FP64/FP32); dense for split-bf16
   FoldAxis ax[3] = {};
@@ -265,9 +268,11 @@ hipError_t residual_into_ws(qn_ctx c, const double* U, const double* F, double* 
   a.nz = c->n[2];
   a.dim = c->dim;
   a.nl = c->nl;
-  a.ihx2 = (double)(c->n[0] + 1) * (c->n[0] + 1);
-  a.ihy2 = (double)(c->n[1] + 1) * (c->n[1] + 1);
-  a.ihz2 = c->dim == 3 ? (double)(c->n[2] + 1) * (c->n[2] + 1) : 0.0;
+  a.ihx2 = c->ih2[0];
+  a.ihy2 = c->ih2[1];
+  a.ihz2 = c->ih2[2];
+  a.lin = c->lin;
+  a.bc = c->bc;
   a.partials = c->at<double>(c->off_part);
   a.rz = c->dim == 3 ? RESIDUAL_RZ : residual_planar_rows(a.ox, a.oy);
   int nb = 0;
@@ -484,6 +489,22 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
     return fail(QN_ERR_INVALID, "the quasi-linear problem uses the coefficient midpoint rule "
                                 "and a fixed beta; QN_BETA_MIDPOINT is not accepted");
   if (!std::isfinite(beta)) return fail(QN_ERR_INVALID, "beta is not finite");
+  if (o.boundary != QN_BC_DIRICHLET && o.boundary != QN_BC_NEUMANN)
+    return fail(QN_ERR_INVALID, "unknown boundary condition");
+  const double length = o.length == 0.0 ? 1.0 : o.length;
+  if (!(length > 0.0) || !std::isfinite(length))
+    return fail(QN_ERR_INVALID, "length must be positive and finite");
+  if (!std::isfinite(o.lin)) return fail(QN_ERR_INVALID, "lin is not finite");
+  if (o.lin != 0.0 && nonlinearity != QN_NL_CUBIC)
+    return fail(QN_ERR_INVALID, "a linear coefficient is supported for QN_NL_CUBIC only");
+  if (o.boundary == QN_BC_NEUMANN) {
+    if (nonlinearity != QN_NL_CUBIC)
+      return fail(QN_ERR_UNSUPPORTED, "Neumann data is supported for QN_NL_CUBIC only");
+    if (o.precision != QN_PREC_FP64 && o.precision != QN_PREC_FP32)
+      return fail(QN_ERR_UNSUPPORTED, "Neumann data is supported with FP64 and FP32 transforms");
+    for (int a = 0; a < grid->dim; ++a)
+      if (grid->n[a] < 2) return fail(QN_ERR_INVALID, "Neumann data needs n >= 2 per axis");
+  }
 
   qn_ctx c = new qn_ctx_s();
   c->dim = grid->dim;
@@ -498,6 +519,9 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   c->n[1] = grid->n[1];
   c->n[2] = grid->dim == 3 ? grid->n[2] : 1;
   c->fold = c->prec == QN_PREC_FP64 || c->prec == QN_PREC_FP32;
+  c->bc = o.boundary;
+  c->length = length;
+  c->lin = o.lin;
   c->lam_min_sum = 0.0;
   for (int a = 0; a < 3; ++a) {
     if (a >= c->dim) {
@@ -505,16 +529,26 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
       continue;
     }
     const int n = c->n[a];
+    // 1 / h: n interior nodes (Dirichlet, h = L/(n+1)) or n nodes with both
+    // ends (Neumann, h = L/(n-1)); exact integers on the unit interval
+    const double ih = (c->bc == QN_BC_NEUMANN ? n - 1 : n + 1) / length;
+    c->ih2[a] = ih * ih;
     if (c->fold) {
       const int bk = fold_block(n);
       c->ax[a] = FoldAxis{n, n / 2, n & 1, bk};
       c->p[a] = 2 * bk;
-      fold_eigen(n, bk, c->hS[a], c->hlam[a]);
+      if (c->bc == QN_BC_NEUMANN)
+        fold_cosine(n, c->ih2[a], bk, c->hS[a], c->hlam[a]);
+      else
+        fold_eigen(n, bk, c->hS[a], c->hlam[a]);
     } else {
       c->p[a] = ((n + 31) / 32) * 32;
       dense_eigen(n, c->p[a], c->hS[a], c->hlam[a]);
     }
-    c->lam_min_sum += c->hlam[a][0];  // lam_1 leads both orderings
+    // the sine eigenvalues are for the unit interval: h = 1 / (n + 1)
+    if (c->bc == QN_BC_DIRICHLET && length != 1.0)
+      for (double& l : c->hlam[a]) l /= length * length;
+    c->lam_min_sum += c->hlam[a][0];  // lam_1 (Dirichlet) or 0 (Neumann) leads both orderings
   }
   // The fixed beta must give a positive definite solve operator (Section 5:
   // beta > -lam_min(A_h)).  The midpoint rules produce beta >= 0 here.
@@ -664,9 +698,11 @@ qn_status qn_residual(qn_ctx c, const double* d_U, const double* d_F, double* d_
   a.nz = c->n[2];
   a.dim = c->dim;
   a.nl = c->nl;
-  a.ihx2 = (double)(c->n[0] + 1) * (c->n[0] + 1);
-  a.ihy2 = (double)(c->n[1] + 1) * (c->n[1] + 1);
-  a.ihz2 = c->dim == 3 ? (double)(c->n[2] + 1) * (c->n[2] + 1) : 0.0;
+  a.ihx2 = c->ih2[0];
+  a.ihy2 = c->ih2[1];
+  a.ihz2 = c->ih2[2];
+  a.lin = c->lin;
+  a.bc = c->bc;
   a.partials = c->at<double>(c->off_part);
   a.rz = c->dim == 3 ? RESIDUAL_RZ : residual_planar_rows(a.ox, a.oy);
   int nb = 0;

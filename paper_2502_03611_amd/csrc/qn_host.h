@@ -72,6 +72,54 @@ inline void fold_eigen(int n, int bk, std::vector<double>& F4, std::vector<doubl
   for (int i = 0; i < no; ++i) ls[bk + i] = lam[2 * i + 1];
 }
 
+// Homogeneous Neumann data (ghost nodes, Section 3.2): the 1D stiffness
+// matrix S = h^-2 [2 -2; -1 2 -1; ...; -2 2] of order n is W^-1 K with K
+// symmetric and W = diag(1/2, 1, .., 1, 1/2) (Section 4.2 with a diagonal
+// mass); its eigenvectors T[j][k] = cos(j k pi / (n - 1)) (integer-reduced
+// argument), eigenvalues lam_k = 4 h^-2 sin^2(k pi / (2 (n - 1))) (ih2 = h^-2), and
+// T^-1 = diag(1 / c_k) T^T W with c_k = (n - 1) / 2, or n - 1 for k = 0 and
+// k = n - 1.  Folded like fold_eigen, with the forward blocks taken from T^-1
+// (FeT[j][i] = T^-1[2i][j]) and the inverse blocks from T (Fe[i][j] =
+// T[j][2i]): both have the reflection parity of the sine case, because W is
+// symmetric about the centre.
+inline void fold_cosine(int n, double ih2, int bk, std::vector<double>& F4,
+                        std::vector<double>& ls) {
+  const long long m = n - 1;
+  const double pi = 3.14159265358979323846;
+  auto T = [&](int j, int k) {
+    const long long red = ((long long)j * k) % (2 * m);
+    return std::cos(pi * (double)red / (double)m);
+  };
+  auto w = [&](int j) { return (j == 0 || j == n - 1) ? 0.5 : 1.0; };
+  auto c = [&](int k) { return (k == 0 || k == n - 1) ? (double)m : 0.5 * (double)m; };
+  auto Tinv = [&](int k, int j) { return T(j, k) * w(j) / c(k); };
+  const int h = n / 2, ne = h + (n & 1), no = h;
+  const size_t bb = (size_t)bk * bk;
+  F4.assign(4 * bb, 0.0);
+  double* FeT = F4.data();
+  double* FoT = FeT + bb;
+  double* Fe = FoT + bb;
+  double* Fo = Fe + bb;
+  for (int j = 0; j < ne; ++j)
+    for (int i = 0; i < ne; ++i) {
+      FeT[(size_t)j * bk + i] = Tinv(2 * i, j);
+      Fe[(size_t)i * bk + j] = T(j, 2 * i);
+    }
+  for (int j = 0; j < h; ++j)
+    for (int i = 0; i < no; ++i) {
+      FoT[(size_t)j * bk + i] = Tinv(2 * i + 1, j);
+      Fo[(size_t)i * bk + j] = T(j, 2 * i + 1);
+    }
+  std::vector<double> lam((size_t)n);
+  for (int k = 0; k < n; ++k) {
+    const double s = std::sin(pi * (double)k / (2.0 * (double)m));
+    lam[k] = 4.0 * ih2 * s * s;
+  }
+  ls.assign((size_t)2 * bk, lam[n - 1]);
+  for (int i = 0; i < ne; ++i) ls[i] = lam[2 * i];
+  for (int i = 0; i < no; ++i) ls[bk + i] = lam[2 * i + 1];
+}
+
 inline uint16_t bf16_rne(float f) {
   uint32_t u;
   std::memcpy(&u, &f, 4);

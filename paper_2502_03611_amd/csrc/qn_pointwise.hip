@@ -73,7 +73,10 @@ __device__ inline void put(void* base, long long idx, double v) {
   reinterpret_cast<TO*>(base)[idx] = (TO)v;
 }
 
-template <int NL, typename TO>
+// BC = 1: homogeneous Neumann data by ghost nodes: a neighbour beyond either
+// end of an axis is the mirror image of the one on the other side (first and
+// last rows h^-2 (2, -2)); BC = 0: zero outside (Dirichlet).
+template <int NL, typename TO, int BC>
 __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
   constexpr int NC = (NL == NL_SYS2) ? 2 : 1;
   // Current z-plane of the block's 64 x 16 tile plus a one-point x/y halo.
@@ -167,17 +170,25 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           const double u = uc[c];
-          const double n_xm = s_u[c][ty + 1][tx], n_xp = s_u[c][ty + 1][tx + 2];
-          const double n_ym = s_u[c][ty][tx + 1], n_yp = s_u[c][ty + 2][tx + 1];
-          const double n_zm = zc ? um[c] : 0.0, n_zp = zc ? up[c] : 0.0;
+          double n_xm = s_u[c][ty + 1][tx], n_xp = s_u[c][ty + 1][tx + 2];
+          double n_ym = s_u[c][ty][tx + 1], n_yp = s_u[c][ty + 2][tx + 1];
+          double n_zm = zc ? um[c] : 0.0, n_zp = zc ? up[c] : 0.0;
+          if constexpr (BC == 1) {  // n >= 2 per axis: an end has one real neighbour
+            if (x == 0) n_xm = n_xp;
+            if (x == nx - 1) n_xp = n_xm;
+            if (y == 0) n_ym = n_yp;
+            if (y == ny - 1) n_yp = n_ym;
+            if (z == 0) n_zm = n_zp;
+            if (z == nz - 1) n_zp = n_zm;
+          }
           lap[c] = (2.0 * u - n_xm - n_xp) * a.ihx2 + (2.0 * u - n_ym - n_yp) * a.ihy2 +
                    (2.0 * u - n_zm - n_zp) * a.ihz2;
           s_f += f[c] * f[c];
         }
         if (NL == NL_CUBIC) {
           const double u = uc[0];
-          r[0] = lap[0] + u * u * u - f[0];
-          const double fu = 3.0 * u * u;
+          r[0] = lap[0] + u * u * u + a.lin * u - f[0];
+          const double fu = 3.0 * u * u + a.lin;
           mn = fmin(mn, fu);
           mx = fmax(mx, fu);
         } else {
@@ -237,7 +248,7 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
 // workgroup so that it still spreads over about a thousand workgroups.
 constexpr int R2X = 256;
 
-template <int NL, typename TO>
+template <int NL, typename TO, int BC>
 __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
   constexpr int NC = (NL == NL_SYS2) ? 2 : 1;
   const int lane = threadIdx.x & 63;
@@ -281,12 +292,20 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
       nhl[c] = ld(Up, c, y + 1, x - 1, lh);
       nhr[c] = ld(Up, c, y + 1, x + 1, rh);
     }
-    double xm[NC], xp[NC];
+    double xm[NC], xp[NC], ym[NC], yp[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const double l = __shfl_up(uc[c], 1, 64), r = __shfl_down(uc[c], 1, 64);
       xm[c] = lane == 0 ? hl[c] : l;
       xp[c] = lane == 63 ? hr[c] : r;
+      ym[c] = um[c];
+      yp[c] = up[c];
+      if constexpr (BC == 1) {  // mirrored ghost nodes (n >= 2 per axis)
+        if (x == 0) xm[c] = xp[c];
+        if (x == nx - 1) xp[c] = xm[c];
+        if (y == 0) ym[c] = yp[c];
+        if (y == ny - 1) yp[c] = ym[c];
+      }
     }
     const bool in = xin && y < ny;
     if (in) {
@@ -296,7 +315,7 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
         const double ac = 1.0 + u * u;
         auto flux = [&](double un) { return 0.5 * (ac + (1.0 + un * un)) * (u - un); };
         const double lx_ = (flux(xm[0]) + flux(xp[0])) * a.ihx2;
-        const double ly_ = (flux(um[0]) + flux(up[0])) * a.ihy2;
+        const double ly_ = (flux(ym[0]) + flux(yp[0])) * a.ihy2;
         r[0] = lx_ + ly_ - f[0];
         s_f += f[0] * f[0];
         mn = fmin(mn, ac);
@@ -306,13 +325,13 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           const double u = uc[c];
-          lap[c] = (2.0 * u - xm[c] - xp[c]) * a.ihx2 + (2.0 * u - um[c] - up[c]) * a.ihy2;
+          lap[c] = (2.0 * u - xm[c] - xp[c]) * a.ihx2 + (2.0 * u - ym[c] - yp[c]) * a.ihy2;
           s_f += f[c] * f[c];
         }
         if (NL == NL_CUBIC) {
           const double u = uc[0];
-          r[0] = lap[0] + u * u * u - f[0];
-          const double fu = 3.0 * u * u;
+          r[0] = lap[0] + u * u * u + a.lin * u - f[0];
+          const double fu = 3.0 * u * u + a.lin;
           mn = fmin(mn, fu);
           mx = fmax(mx, fu);
         } else {
@@ -377,19 +396,24 @@ int residual_max_blocks(int ox, int oy, int oz, int rz, bool planar) {
   return (int)(g.x * g.y * g.z);
 }
 
-template <int NL>
-static void launch_nl(const ResidualArgs& a, dim3 g, bool planar, hipStream_t st) {
+template <int NL, int BC>
+static void launch_nl_bc(const ResidualArgs& a, dim3 g, bool planar, hipStream_t st) {
   if (planar) {
     if (a.out_prec == 0)
-      hipLaunchKernelGGL((k_residual2d<NL, double>), g, dim3(R2X), 0, st, a);
+      hipLaunchKernelGGL((k_residual2d<NL, double, BC>), g, dim3(R2X), 0, st, a);
     else
-      hipLaunchKernelGGL((k_residual2d<NL, float>), g, dim3(R2X), 0, st, a);
+      hipLaunchKernelGGL((k_residual2d<NL, float, BC>), g, dim3(R2X), 0, st, a);
     return;
   }
   if (a.out_prec == 0)
-    hipLaunchKernelGGL((k_residual<NL, double>), g, dim3(RX, RY), 0, st, a);
+    hipLaunchKernelGGL((k_residual<NL, double, BC>), g, dim3(RX, RY), 0, st, a);
   else
-    hipLaunchKernelGGL((k_residual<NL, float>), g, dim3(RX, RY), 0, st, a);
+    hipLaunchKernelGGL((k_residual<NL, float, BC>), g, dim3(RX, RY), 0, st, a);
+}
+
+template <int NL>
+static void launch_nl(const ResidualArgs& a, dim3 g, bool planar, hipStream_t st) {
+  launch_nl_bc<NL, 0>(a, g, planar, st);
 }
 
 hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t st) {
@@ -398,7 +422,12 @@ hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t 
   const dim3 g = residual_grid(a.ox, a.oy, a.oz, a.rz, planar);
   *nblocks_out = (int)(g.x * g.y * g.z);
   switch (a.nl) {
-    case NL_CUBIC: launch_nl<NL_CUBIC>(a, g, planar, st); break;
+    case NL_CUBIC:  // the only nonlinearity with Neumann data
+      if (a.bc == 1)
+        launch_nl_bc<NL_CUBIC, 1>(a, g, planar, st);
+      else
+        launch_nl<NL_CUBIC>(a, g, planar, st);
+      break;
     case NL_QUASILIN: launch_nl<NL_QUASILIN>(a, g, planar, st); break;
     default: launch_nl<NL_SYS2>(a, g, planar, st); break;
   }

@@ -64,6 +64,39 @@ def test_setup_rejects_midpoint_for_quasilinear_and_bad_enums():
     assert setup(opt=o)[0] == qn.QN_ERR_INVALID
 
 
+def opts(**kw):
+    o = QNOptions()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+@pytest.mark.parametrize("kw,nl,ncomp,n,beta,want", [
+    (dict(boundary=1), 0, 1, (9, 9, 9), 1.0, "ok"),
+    (dict(boundary=1, lin=1.0), 0, 1, (9, 9, 1), 0.0, "ok"),  # 2D, beta 0 + lin: see below
+    (dict(boundary=2), 0, 1, (9, 9, 9), 1.0, "invalid"),
+    (dict(boundary=1), 0, 1, (1, 9, 9), 1.0, "invalid"),       # n < 2
+    (dict(boundary=1), 0, 1, (9, 9, 9), 0.0, "invalid"),       # lam_min = 0: beta must be > 0
+    (dict(boundary=1), 2, 2, (9, 9, 9), 1.0, "unsupported"),   # system
+    (dict(boundary=1), 1, 1, (9, 9, 9), 1.0, "unsupported"),   # quasi-linear
+    (dict(boundary=1, precision=2), 0, 1, (9, 9, 9), 1.0, "unsupported"),  # bf16x3
+    (dict(length=-1.0), 0, 1, (9, 9, 9), 0.0, "invalid"),
+    (dict(length=float("inf")), 0, 1, (9, 9, 9), 0.0, "invalid"),
+    (dict(lin=float("nan")), 0, 1, (9, 9, 9), 0.0, "invalid"),
+    (dict(lin=1.0), 2, 2, (9, 9, 9), 0.0, "invalid"),          # lin only for the cubic problem
+    (dict(length=2.0, lin=0.5), 0, 1, (9, 9, 9), 0.0, "ok"),
+])
+def test_setup_boundary_length_and_lin(kw, nl, ncomp, n, beta, want):
+    dim = 2 if n[2] == 1 else 3
+    if dim == 2 and want == "ok" and kw.get("boundary") == 1:
+        beta = 0.5  # a fixed shift must still be positive with Neumann data (lam_min = 0)
+    st, ctx = setup(dim=dim, n=n, ncomp=ncomp, nl=nl, beta=beta, opt=opts(**kw))
+    expect = {"ok": qn.QN_OK, "invalid": qn.QN_ERR_INVALID, "unsupported": qn.QN_ERR_UNSUPPORTED}
+    assert st == expect[want], (st, qn.last_error())
+    if st == qn.QN_OK:
+        qn.lib().qn_destroy(ctx)
+
+
 def test_workspace_size_and_unbound_errors():
     st, ctx = setup(n=(511, 511, 511), nl=1)
     assert st == qn.QN_OK

@@ -1,0 +1,139 @@
+"""GPU parity of the homogeneous-Neumann path (ghost nodes, Section 3.2; cosine
+eigenpairs; -Lap u + lambda u + u^3 = f) against the FP64 oracle
+(oracle/neumann.py).  Tolerances as for the Dirichlet path: residual
+<= 1e-13 of the cancelling terms, FDM solve <= 1e-12 rel L2 (FP64) and
+<= 3e-5 (FP32 transforms), iterate: equal counts, then exactly K solves on
+both sides to <= 1e-12 rel L2."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import neumann as nm
+from paper_2502_03611_amd import Solver, QN_OK, QN_ERR_NOT_CONVERGED
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def solver(shape, **kw):
+    kw.setdefault("beta", 1.0)  # lam_min = 0: a fixed shift must be positive
+    return Solver(shape, "cubic", boundary="neumann", **kw)
+
+
+@pytest.mark.parametrize("shape,lin", [((33, 47), 0.0), ((33, 47), 1.0), ((2, 5), 1.0),
+                                       ((300, 2), 0.5), ((17, 20, 23), 1.0), ((2, 3, 4), 0.0),
+                                       ((5, 70, 3), 2.0)])
+def test_residual_parity(shape, lin):
+    print(f"neumann residual {shape} lin {lin}", flush=True)
+    u = synth.random_field((1,) + shape, 201)
+    f = synth.random_field((1,) + shape, 202, scale=10.0)
+    s = solver(shape, beta=1.0, lin=lin)
+    red = torch.zeros(4, dtype=torch.float64, device="cuda")
+    r = host(s.residual(dev(u), dev(f), red=red))[0]
+    hs = nm.spacing(shape)
+    ref = nm.residual_cubic(u[0], f[0], hs, lin)
+    scale = (np.linalg.norm(nm.apply_laplacian(u[0], hs)) + np.linalg.norm(u[0] ** 3) +
+             lin * np.linalg.norm(u[0]) + np.linalg.norm(f[0]))
+    assert np.linalg.norm(r - ref) / scale <= 1e-13
+    red = red.cpu().numpy()
+    fu = nm.fu_cubic(u[0], lin)
+    assert red[0] == pytest.approx(float(np.sum(ref * ref)), rel=1e-12)
+    assert red[1] == pytest.approx(float(fu.min()), rel=1e-14, abs=1e-15)
+    assert red[2] == pytest.approx(float(fu.max()), rel=1e-14)
+
+
+@pytest.mark.parametrize("shape,scale,shift", [((33, 47), 1.0, 1.0), ((65, 65), 2.0, 0.5),
+                                               ((2, 2), 1.0, 3.0), ((129, 64), 1.0, 1e-3),
+                                               ((17, 20, 23), 1.0, 1.0), ((2, 3, 4), 1.5, 0.25),
+                                               ((40, 33, 65), 1.0, 10.0)])
+def test_fdm_solve_parity_fp64(shape, scale, shift):
+    print(f"neumann fdm {shape}", flush=True)
+    r = synth.random_field((1,) + shape, 203)
+    x = host(solver(shape).fdm_solve(dev(r), scale, shift))[0]
+    ref = nm.fdm_solve(r[0], nm.spacing(shape), shift, scale)
+    assert rel(x, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("shape", [(65, 65), (17, 20, 23)])
+def test_fdm_solve_fp32_transforms(shape):
+    r = synth.random_field((1,) + shape, 204)
+    x = host(solver(shape, precision="fp32").fdm_solve(dev(r), 1.0, 0.5))[0]
+    err = rel(x, nm.fdm_solve(r[0], nm.spacing(shape), 0.5))
+    print(f"  fp32 {shape} rel err {err:.2e}", flush=True)
+    assert err <= 3e-5
+
+
+def test_fdm_solve_full_size_255_property():
+    """255^3 solve: (A_h + sigma I) X = R checked with the oracle's stencil."""
+    n = 255
+    shape = (n, n, n)
+    r = synth.random_field((1,) + shape, 205)
+    x = host(solver(shape).fdm_solve(dev(r), 1.0, 2.0))[0]
+    hs = nm.spacing(shape)
+    back = nm.apply_laplacian(x, hs) + 2.0 * x
+    assert rel(back, r[0]) <= 1e-11
+
+
+@pytest.mark.parametrize("gen,n", [(synth.neumann_2d, 65), (synth.neumann_2d, 128),
+                                   (synth.neumann_3d, 17), (synth.neumann_3d, 30)])
+def test_iterate_parity(gen, n):
+    """The paper's 2D Neumann example (-Lap u + u^3 + u, u = cos(pi x) cos(2 pi y)
+    on [-1, 1]^2) and its 3D analogue, midpoint shift: equal iteration counts,
+    then exactly K solves on both sides."""
+    print(f"neumann iterate {gen.__name__} {n}", flush=True)
+    u_ex, f = gen(n)
+    shape = f.shape
+    hs = nm.spacing(shape)
+    ref = nm.qn_solve(f, hs, lin=1.0)
+    s = solver(shape, beta_mode="midpoint", lin=1.0)
+    u = torch.zeros((1,) + shape, dtype=torch.float64, device="cuda")
+    st = s.iterate(u, dev(f[None]), rtol=1e-10, max_iter=200)
+    assert st["status"] == QN_OK, st
+    assert st["iters"] == ref["iters"], (st["iters"], ref["iters"])
+    k = ref["iters"]
+    ug = torch.zeros_like(u)
+    st2 = s.iterate(ug, dev(f[None]), rtol=0.0, max_iter=k)
+    assert st2["status"] == QN_ERR_NOT_CONVERGED and st2["iters"] == k
+    assert rel(host(ug)[0], ref["u"]) <= 1e-12
+    # second order against the continuous solution (the discretisation error)
+    assert np.abs(host(u)[0] - u_ex).max() <= 0.3 * math.pi ** 2 * max(hs) ** 2 * 4
+
+
+def test_fp32_transforms_reach_the_fp64_solution():
+    u_ex, f = synth.neumann_2d(129)
+    ref = nm.qn_solve(f, nm.spacing(f.shape), lin=1.0)
+    s = solver(f.shape, beta_mode="midpoint", lin=1.0, precision="fp32")
+    u = torch.zeros((1,) + f.shape, dtype=torch.float64, device="cuda")
+    st = s.iterate(u, dev(f[None]), rtol=1e-10, max_iter=200)
+    assert st["status"] == QN_OK and st["iters"] <= math.ceil(1.1 * ref["iters"])
+    assert rel(host(u)[0], ref["u"]) <= 1e-9
+
+
+def test_zero_shift_is_refused_and_midpoint_from_zero_needs_lin():
+    """lam_min = 0 with Neumann data: a fixed beta of 0 is rejected at setup;
+    with the midpoint rule and lin = 0 the first shift (U_0 = 0) is 0 and the
+    iteration reports the singular operator instead of dividing by zero."""
+    from paper_2502_03611_amd._binding import QNError
+    with pytest.raises(QNError):
+        solver((9, 9), beta=0.0)
+    u_ex, f = synth.neumann_2d(9)
+    s = solver((9, 9), beta_mode="midpoint", lin=0.0)
+    u = torch.zeros((1, 9, 9), dtype=torch.float64, device="cuda")
+    st = s.iterate(u, dev(f[None]), rtol=1e-10, max_iter=20)
+    assert st["status"] != QN_OK and float(u.abs().max()) == 0.0
