@@ -17,8 +17,10 @@ for k = 0 and k = n - 1.  lam_0 = 0 (constants), so a solve needs a positive
 shift.
 
 Problem (the paper's model -Lap u + lambda u + f(x, u) = 0 of Section 2 with
-f(x, u) = u^3 - f_src(x)): F^h(U) = A_h U + lambda U + U^3 - F, Jacobian
-diagonal f_u = 3 U^2 + lambda.  The tensor-product solve of Section 4.1
+f(x, u) = b u^3 + V(x) u - f_src(x), b = 1 and V = 0 unless given; the 3D
+example of Section 6.3 has lambda = b = 10 and a potential V):
+F^h(U) = A_h U + lambda U + b U^3 + V U - F, Jacobian diagonal
+f_u = 3 b U^2 + lambda + V.  The tensor-product solve of Section 4.1
 (eq. fin_inverse) applies T^-1 along every axis, divides by
 scale (lam_i + lam_j (+ lam_k)) + shift and applies T; the quasi-Newton loop
 is the one of Section 4 (eq. identity-method) with the midpoint shift.
@@ -98,14 +100,16 @@ def assemble_laplacian(shape, hs):
     return total
 
 
-def residual_cubic(u, f, hs, lin=0.0):
-    """F^h(U) = A_h U + lin U + U^3 - F."""
-    return apply_laplacian(u, hs) + lin * u + u ** 3 - f
+def residual_cubic(u, f, hs, lin=0.0, cub=1.0, pot=None):
+    """F^h(U) = A_h U + lin U + cub U^3 + V U - F (pot = V on the nodes, None = 0)."""
+    r = apply_laplacian(u, hs) + lin * u + cub * u ** 3 - f
+    return r if pot is None else r + pot * u
 
 
-def fu_cubic(u, lin=0.0):
-    """Jacobian diagonal of the pointwise part: 3 U^2 + lin."""
-    return 3.0 * u * u + lin
+def fu_cubic(u, lin=0.0, cub=1.0, pot=None):
+    """Jacobian diagonal of the pointwise part: 3 cub U^2 + lin + V."""
+    d = 3.0 * cub * u * u + lin
+    return d if pot is None else d + pot
 
 
 def fdm_solve(r, hs, shift, scale=1.0):
@@ -136,24 +140,25 @@ def direct_solve(r, hs, shift, scale=1.0):
 
 
 def qn_solve(f, hs, lin=0.0, u0=None, beta=0.0, midpoint=True, rtol=1e-10, max_iter=200,
-             solver=fdm_solve):
+             solver=fdm_solve, cub=1.0, pot=None):
     """The quasi-Newton iteration for the cubic problem: R_k = F^h(U_k); stop
     when ||R_k|| / ||F|| <= rtol (or after max_iter solves); beta_k = the fixed
-    beta or the midpoint of 3 U_k^2 + lin; U_{k+1} = U_k - (A_h + beta_k I)^-1 R_k.
-    f, u0: arrays of the grid's shape.  Returns dict(u, iters, relres, beta)."""
+    beta or the midpoint of 3 cub U_k^2 + lin + V; U_{k+1} = U_k - (A_h +
+    beta_k I)^-1 R_k.  f, u0, pot: arrays of the grid's shape.  Returns
+    dict(u, iters, relres, beta)."""
     f = np.asarray(f, dtype=np.float64)
     u = np.zeros_like(f) if u0 is None else np.array(u0, dtype=np.float64, copy=True)
     fnorm = math.sqrt(float(np.sum(f * f)))
     hist, betas = [], []
     k = 0
     while True:
-        r = residual_cubic(u, f, hs, lin)
+        r = residual_cubic(u, f, hs, lin, cub, pot)
         rel = math.sqrt(float(np.sum(r * r))) / fnorm
         hist.append(rel)
         if rel <= rtol or k >= max_iter or not math.isfinite(rel):
             break
         if midpoint:
-            fu = fu_cubic(u, lin)
+            fu = fu_cubic(u, lin, cub, pot)
             b = 0.5 * (float(fu.min()) + float(fu.max()))
         else:
             b = beta

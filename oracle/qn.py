@@ -30,10 +30,12 @@ SYSTEM = "system"
 QUASILINEAR = "quasilinear"
 
 
-def residual(kind, u, f):
-    """F^h(U) for the problem kind; u, f carry a leading component axis."""
+def residual(kind, u, f, lin=0.0, cub=1.0, pot=None):
+    """F^h(U) for the problem kind; u, f carry a leading component axis.
+    lin, cub, pot: the cubic problem's linear coefficient, cubic coefficient
+    and potential field (see operators.residual_cubic)."""
     if kind == CUBIC:
-        return ops.residual_cubic(u[0], f[0])[None]
+        return ops.residual_cubic(u[0], f[0], lin, cub, pot)[None]
     if kind == SYSTEM:
         r1, r2 = ops.residual_system(u[0], u[1], f[0], f[1])
         return np.stack([r1, r2])
@@ -42,7 +44,7 @@ def residual(kind, u, f):
     raise ValueError(kind)
 
 
-def shift_rule(kind, u, beta, midpoint):
+def shift_rule(kind, u, beta, midpoint, lin=0.0, cub=1.0, pot=None):
     """Return (scale c_k, shift beta_k) of the Jacobian approximation."""
     if kind == QUASILINEAR:
         a = ops.coeff_quasilinear(u[0])
@@ -50,14 +52,14 @@ def shift_rule(kind, u, beta, midpoint):
     if not midpoint:
         return 1.0, beta
     if kind == CUBIC:
-        fu = ops.fu_cubic(u[0])
+        fu = ops.fu_cubic(u[0], lin, cub, pot)
         return 1.0, 0.5 * (float(fu.min()) + float(fu.max()))
     lm, lp = ops.system_jacobian_eigs(u[0], u[1])
     return 1.0, 0.5 * (float(lm.min()) + float(lp.max()))
 
 
 def qn_solve(kind, f, u0=None, beta=0.0, midpoint=False, rtol=1e-10,
-             max_iter=200, solver=fdm_solve):
+             max_iter=200, solver=fdm_solve, lin=0.0, cub=1.0, pot=None):
     """Run the quasi-Newton iteration.
 
     f, u0: arrays of shape (ncomp, .., ny, nx).  Runs until relres <= rtol or
@@ -70,12 +72,12 @@ def qn_solve(kind, f, u0=None, beta=0.0, midpoint=False, rtol=1e-10,
     hist, betas, scales = [], [], []
     k = 0
     while True:
-        r = residual(kind, u, f)
+        r = residual(kind, u, f, lin, cub, pot)
         rel = math.sqrt(float(np.sum(r * r))) / fnorm
         hist.append(rel)
         if rel <= rtol or k >= max_iter or not math.isfinite(rel):
             break
-        c, b = shift_rule(kind, u, beta, midpoint)
+        c, b = shift_rule(kind, u, beta, midpoint, lin, cub, pot)
         betas.append(b)
         scales.append(c)
         for comp in range(u.shape[0]):
@@ -85,7 +87,7 @@ def qn_solve(kind, f, u0=None, beta=0.0, midpoint=False, rtol=1e-10,
             "converged": hist[-1] <= rtol}
 
 
-def newton_solve(kind, f, u0=None, tol=1e-13, max_iter=30):
+def newton_solve(kind, f, u0=None, tol=1e-13, max_iter=30, lin=0.0, cub=1.0, pot=None):
     """Dense Newton's method (Section 4, eq. newton) for tiny grids: the
     Jacobian A_h + (N_h)_U is assembled and solved directly.  Used only to pin
     the fixed point of the quasi-Newton iteration."""
@@ -96,11 +98,11 @@ def newton_solve(kind, f, u0=None, tol=1e-13, max_iter=30):
     n = a.shape[0]
     fnorm = math.sqrt(float(np.sum(f * f)))
     for _ in range(max_iter):
-        r = residual(kind, u, f)
+        r = residual(kind, u, f, lin, cub, pot)
         if math.sqrt(float(np.sum(r * r))) / fnorm <= tol:
             break
         if kind == CUBIC:
-            jac = a + np.diag(ops.fu_cubic(u[0]).ravel())
+            jac = a + np.diag(ops.fu_cubic(u[0], lin, cub, pot).ravel())
             u[0] -= np.linalg.solve(jac, r[0].ravel()).reshape(shape)
         elif kind == SYSTEM:
             jac = np.zeros((2 * n, 2 * n))

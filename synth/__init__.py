@@ -27,5 +27,7 @@ from .fields import (  # noqa: F401
     node_coords,
     neumann_2d,
     neumann_3d,
+    neumann_potential_3d,
+    polynomial_perturbation,
     BATCH_SIZES,
 )

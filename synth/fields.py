@@ -147,3 +147,35 @@ def neumann_3d(n):
     c = np.cos(math.pi * node_coords(n))
     u = c[:, None, None] + c[None, :, None] + c[None, None, :]
     return u, math.pi ** 2 * u + u ** 3 + u
+
+
+def neumann_potential_3d(n, a=10.0, b=10.0):
+    """3D -Lap u + a u + b u^3 + V u = f on [-1, 1]^3 with zero normal
+    derivative (Section 6.3, Example 1, eq. ex3d1): u = cos(pi x) + cos(pi y) +
+    cos(pi z), -Lap u = pi^2 u, V = 100 (sin^2(pi x/4) + sin^2(pi y/4) +
+    sin^2(pi z/4)) + x^2 + y^2 + z^2.  All n^3 nodes.  Returns (u_exact, f, V),
+    shape (nz, ny, nx)."""
+    x = node_coords(n)
+    c = np.cos(math.pi * x)
+    w = 100.0 * np.sin(math.pi * x / 4.0) ** 2 + x * x
+    u = c[:, None, None] + c[None, :, None] + c[None, None, :]
+    v = w[:, None, None] + w[None, :, None] + w[None, None, :]
+    f = math.pi ** 2 * u + a * u + b * u ** 3 + v * u
+    return u, f, v
+
+
+def polynomial_perturbation(n, dim, seed, degree=4):
+    """Section 6.2 / 6.3 initial-guess perturbation p on all n^dim nodes of
+    [-1, 1]^dim: sum of a_{i..} x^i y^j (z^k) over exponents 0..degree with
+    coefficients a ~ U(-1, 1) from default_rng(seed), divided by its largest
+    magnitude over the nodes (so max |p| = 1 on the grid).  Shape (ny, nx) or
+    (nz, ny, nx); the coefficient array is indexed (x, y[, z]) exponents."""
+    rng = np.random.default_rng(seed)
+    coef = rng.uniform(-1.0, 1.0, size=(degree + 1,) * dim)
+    x = node_coords(n)
+    powers = np.stack([x ** e for e in range(degree + 1)])  # (degree+1, n)
+    if dim == 2:
+        p = np.einsum("ij,iX,jY->YX", coef, powers, powers)
+    else:
+        p = np.einsum("ijk,iX,jY,kZ->ZYX", coef, powers, powers, powers)
+    return p / np.abs(p).max()
