@@ -118,10 +118,19 @@ typedef enum { QN_BC_DIRICHLET = 0, QN_BC_NEUMANN = 1 } qn_boundary;
 /* precision: qn_precision; beta_mode: qn_beta_mode; timing: nonzero records
  * HIP events around every kernel launch (see qn_timing_*); boundary:
  * qn_boundary; stream: a hipStream_t, NULL = default stream; length: the
- * side L of the domain (every axis), 0 = 1.0; lin: the linear coefficient
- * lambda of the paper's -Lap u + lambda u + f(x, u) = 0 (Section 2) for
- * QN_NL_CUBIC, i.e. F^h(U) = A_h U + lambda U + U^3 - F with Jacobian diagonal
- * 3 U^2 + lambda (must be 0 for the other nonlinearities). */
+ * side L of the domain (every axis), 0 = 1.0.
+ * The pointwise term of QN_NL_CUBIC is the paper's model
+ * -Lap u + lambda u + f(x, u) = 0 (Section 2) with f(x, u) = b u^3 + V(x) u
+ * - f_src(x) (Section 6.3, eq. ex3d1, has lambda = b = 10 and a potential V):
+ * F^h(U) = A_h U + lambda U + b U^3 + V U - F, Jacobian diagonal
+ * 3 b U^2 + lambda + V.
+ * lin: lambda (finite), default 0.
+ * cub: b (finite), 0 = 1.0.
+ * potential: NULL (V = 0) or a device array V of one component in the grid's
+ *   layout ([nz,] ny, nx); read by every qn_residual and qn_iterate call;
+ *   owned by the caller, who keeps it valid and unchanged while the context
+ *   is in use.
+ * The other nonlinearities need lin = 0, cub in {0, 1} and potential = NULL. */
 typedef struct {
   int32_t precision;
   int32_t beta_mode;
@@ -130,6 +139,8 @@ typedef struct {
   void* stream;
   double length;
   double lin;
+  double cub;
+  const double* potential;
 } qn_options;
 
 /* iters: solves performed; status: the qn_status qn_iterate returned;
@@ -157,8 +168,9 @@ typedef struct qn_ctx_s* qn_ctx;
  * Errors: QN_ERR_INVALID for dim not in {2,3}, n out of range, ncomp
  * inconsistent with nonlinearity, unknown enum values, a singular shift,
  * QN_BETA_MIDPOINT with QN_NL_QUASILIN, a non-positive or non-finite length,
- * a non-finite lin or a nonzero lin with a nonlinearity other than
- * QN_NL_CUBIC, n < 2 with QN_BC_NEUMANN; QN_ERR_UNSUPPORTED for QN_BC_NEUMANN
+ * a non-finite lin or cub, a nonzero lin, a cub other than 0 or 1 or a
+ * potential with a nonlinearity other than QN_NL_CUBIC, n < 2 with
+ * QN_BC_NEUMANN; QN_ERR_UNSUPPORTED for QN_BC_NEUMANN
  * with another nonlinearity than QN_NL_CUBIC or a split-bf16 precision. */
 qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity,
                    const qn_options* opt, qn_ctx* out);
@@ -178,8 +190,8 @@ qn_status qn_set_stream(qn_ctx ctx, void* stream);
 /* Residual F^h(U) = A_h vec(U) + N_h(U) (Section 4, eq. F_u; system:
  * Section 4.3) with its reductions.  d_U, d_F: inputs; d_R: output (may not
  * alias d_U); all (ncomp, [nz,] ny, nx).  d_red: NULL or device double[4]
- * receiving { sum R^2, min mu, max mu, sum F^2 }, where mu is f_u = 3U^2
- * (cubic), the block eigenvalues lam_- (min) / lam_+ (max) (system), or
+ * receiving { sum R^2, min mu, max mu, sum F^2 }, where mu is f_u =
+ * 3 b U^2 + lambda + V (cubic), the block eigenvalues lam_- (min) / lam_+ (max) (system), or
  * a = 1 + U^2 (quasi-linear).  Asynchronous. */
 qn_status qn_residual(qn_ctx ctx, const double* d_U, const double* d_F, double* d_R,
                       double* d_red);

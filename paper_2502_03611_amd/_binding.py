@@ -33,7 +33,8 @@ class QNGrid(ctypes.Structure):
 
 class QNOptions(ctypes.Structure):
     _fields_ = [("precision", c_i32), ("beta_mode", c_i32), ("timing", c_i32),
-                ("boundary", c_i32), ("stream", c_vp), ("length", c_dbl), ("lin", c_dbl)]
+                ("boundary", c_i32), ("stream", c_vp), ("length", c_dbl), ("lin", c_dbl),
+                ("cub", c_dbl), ("potential", c_vp)]
 
 
 BOUNDARIES = {"dirichlet": 0, "neumann": 1}
@@ -113,12 +114,14 @@ class Solver:
 
     def __init__(self, shape, nonlinearity="cubic", beta=0.0, beta_mode="fixed",
                  precision="fp64", timing=False, device="cuda", boundary="dirichlet",
-                 length=None, lin=0.0):
+                 length=None, lin=0.0, cub=1.0, potential=None):
         """boundary: "dirichlet" (n interior nodes per axis, h = L/(n+1)) or
         "neumann" (n nodes including both ends, zero normal derivative,
         h = L/(n-1)); length: the domain side L (default 1 for Dirichlet, 2 for
-        Neumann, i.e. [-1, 1]); lin: the linear coefficient lambda of
-        -Lap u + lambda u + u^3 = f (cubic problem only)."""
+        Neumann, i.e. [-1, 1]).  Cubic problem only: lin, cub, potential give
+        -Lap u + lin u + cub u^3 + V u = f; potential: None or a float64
+        device tensor V of the grid's shape, kept referenced by the solver
+        (the library reads it on every residual)."""
         L = lib()
         self.shape = tuple(int(s) for s in shape)
         self.dim = len(self.shape)
@@ -138,6 +141,15 @@ class Solver:
         o.boundary = BOUNDARIES[boundary]
         o.length = float(length if length is not None else (2.0 if boundary == "neumann" else 1.0))
         o.lin = float(lin)
+        o.cub = float(cub)
+        self._potential = None
+        if potential is not None:
+            if (potential.dtype != torch.float64 or tuple(potential.shape) != self.shape
+                    or not potential.is_contiguous() or potential.device.type != "cuda"):
+                raise ValueError("potential must be a contiguous float64 CUDA tensor of shape "
+                                 f"{self.shape}")
+            self._potential = potential
+            o.potential = potential.data_ptr()
         o.stream = None
         self.boundary = boundary
         ctx = c_vp()

@@ -93,7 +93,8 @@ struct qn_ctx_s {
   double beta = 0.0;
   double lam_min_sum = 0.0;
   int bc = QN_BC_DIRICHLET;
-  double length = 1.0, lin = 0.0;
+  double length = 1.0, lin = 0.0, cub = 1.0;
+  const double* pot = nullptr;  // caller-owned potential V, or NULL
   double ih2[3] = {1.0, 1.0, 0.0};  // h^-2 per axis (0 for the missing z of 2D)
   hipStream_t stream = nullptr;
   bool fold = true;       // reflection-folded transforms (FP64/FP32); dense for split-bf16
@@ -272,6 +273,8 @@ hipError_t residual_into_ws(qn_ctx c, const double* U, const double* F, double* 
   a.ihy2 = c->ih2[1];
   a.ihz2 = c->ih2[2];
   a.lin = c->lin;
+  a.cub = c->cub;
+  a.pot = c->pot;
   a.bc = c->bc;
   a.partials = c->at<double>(c->off_part);
   a.rz = c->dim == 3 ? RESIDUAL_RZ : residual_planar_rows(a.ox, a.oy);
@@ -497,6 +500,10 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   if (!std::isfinite(o.lin)) return fail(QN_ERR_INVALID, "lin is not finite");
   if (o.lin != 0.0 && nonlinearity != QN_NL_CUBIC)
     return fail(QN_ERR_INVALID, "a linear coefficient is supported for QN_NL_CUBIC only");
+  if (!std::isfinite(o.cub)) return fail(QN_ERR_INVALID, "cub is not finite");
+  const double cub = o.cub == 0.0 ? 1.0 : o.cub;
+  if ((cub != 1.0 || o.potential) && nonlinearity != QN_NL_CUBIC)
+    return fail(QN_ERR_INVALID, "a cubic coefficient or a potential is supported for QN_NL_CUBIC only");
   if (o.boundary == QN_BC_NEUMANN) {
     if (nonlinearity != QN_NL_CUBIC)
       return fail(QN_ERR_UNSUPPORTED, "Neumann data is supported for QN_NL_CUBIC only");
@@ -522,6 +529,8 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   c->bc = o.boundary;
   c->length = length;
   c->lin = o.lin;
+  c->cub = cub;
+  c->pot = o.potential;
   c->lam_min_sum = 0.0;
   for (int a = 0; a < 3; ++a) {
     if (a >= c->dim) {
@@ -702,6 +711,8 @@ qn_status qn_residual(qn_ctx c, const double* d_U, const double* d_F, double* d_
   a.ihy2 = c->ih2[1];
   a.ihz2 = c->ih2[2];
   a.lin = c->lin;
+  a.cub = c->cub;
+  a.pot = c->pot;
   a.bc = c->bc;
   a.partials = c->at<double>(c->off_part);
   a.rz = c->dim == 3 ? RESIDUAL_RZ : residual_planar_rows(a.ox, a.oy);

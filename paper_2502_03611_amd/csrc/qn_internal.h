@@ -133,8 +133,12 @@ struct ResidualArgs {
   int rz;                  // 3D: z-planes per workgroup; planar: y-rows per workgroup
   const int* skip;         // batched solver: per-z-plane (instance) skip flags, else NULL
   const int* stop;         // single problem: the whole launch returns when *stop != 0, or NULL
-  double lin;              // cubic problem: linear coefficient (F^h = A U + lin U + U^3 - F)
+  // Cubic problem: F^h = A U + lin U + cub U^3 + V U - F, V = pot (one
+  // component, interior layout of U) or 0 when pot is NULL.
+  double lin;
   int bc;                  // 0 Dirichlet (zero outside), 1 Neumann (mirrored neighbours)
+  double cub = 1.0;
+  const double* pot = nullptr;
 };
 hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t st);
 // Workgroups (= partial slots) of a residual launch; planar: no z coupling

@@ -121,7 +121,8 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
   // plane z+1 (its U values, F, halo cells and U(z+2)) are already in flight.
   double um[NC], uc[NC], up[NC], f[NC], hc[NC], vc[NC];
   double n_up[NC], n_f[NC], n_hc[NC], n_vc[NC];
-  auto load_plane = [&](int z, double* u_next, double* fz, double* hz, double* vz) {
+  double pv = 0.0, n_pv = 0.0;  // cubic problem: potential V at (x, y, z) and (x, y, z+1)
+  auto load_plane = [&](int z, double* u_next, double* fz, double* hz, double* vz, double& pz) {
     const bool zin = z < nz;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -131,16 +132,17 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
       hz[c] = (has_h && h_ok && zin) ? Uc[hoff] : 0.0;
       vz[c] = (has_v && v_ok && zin) ? Uc[voff] : 0.0;
     }
+    if constexpr (NL == NL_CUBIC) pz = (a.pot && in_xy && zin) ? a.pot[(long long)z * plane + col] : 0.0;
   };
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     um[c] = (zc && in_xy && z0 > 0 && z0 - 1 < nz) ? a.U[c * comp + (long long)(z0 - 1) * plane + col] : 0.0;
     uc[c] = (in_xy && z0 < nz) ? a.U[c * comp + (long long)z0 * plane + col] : 0.0;
   }
-  if (z0 < z1) load_plane(z0, up, f, hc, vc);
+  if (z0 < z1) load_plane(z0, up, f, hc, vc, pv);
   for (int z = z0; z < z1; ++z) {
     const bool zin = z < nz;
-    if (z + 1 < z1) load_plane(z + 1, n_up, n_f, n_hc, n_vc);
+    if (z + 1 < z1) load_plane(z + 1, n_up, n_f, n_hc, n_vc, n_pv);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       s_u[c][ty + 1][tx + 1] = uc[c];
@@ -187,8 +189,9 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
         }
         if (NL == NL_CUBIC) {
           const double u = uc[0];
-          r[0] = lap[0] + u * u * u + a.lin * u - f[0];
-          const double fu = 3.0 * u * u + a.lin;
+          const double m = a.lin + pv;
+          r[0] = lap[0] + a.cub * (u * u * u) + m * u - f[0];
+          const double fu = 3.0 * a.cub * (u * u) + m;
           mn = fmin(mn, fu);
           mx = fmax(mx, fu);
         } else {
@@ -225,6 +228,7 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
       hc[c] = n_hc[c];
       vc[c] = n_vc[c];
     }
+    pv = n_pv;
   }
 
   block_reduce4<RX * RY / 64>(s_r, mn, mx, s_f);
@@ -270,6 +274,9 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
   auto ld = [&](const double* p, int c, int y, int xx, bool ok) {
     return (ok && y >= 0 && y < ny) ? p[c * comp + (long long)y * nx + xx] : 0.0;
   };
+  // Cubic problem: potential V of the plane (single problems only: pl = 0).
+  const bool has_pot = NL == NL_CUBIC && a.pot != nullptr;
+  const double* Pp = has_pot ? a.pot + (long long)pl * plane : nullptr;
 
   double s_r = 0.0, s_f = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
   double um[NC], uc[NC], up[NC], f[NC], hl[NC], hr[NC];
@@ -282,6 +289,7 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
     hl[c] = ld(Up, c, y0, x - 1, lh);
     hr[c] = ld(Up, c, y0, x + 1, rh);
   }
+  double pv = has_pot ? ld(Pp, 0, y0, x, xin) : 0.0;
   for (int y = y0; y < y1; ++y) {
     // row y + 1 in flight while row y is computed
     double nup[NC], nf[NC], nhl[NC], nhr[NC];
@@ -292,6 +300,7 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
       nhl[c] = ld(Up, c, y + 1, x - 1, lh);
       nhr[c] = ld(Up, c, y + 1, x + 1, rh);
     }
+    const double npv = has_pot ? ld(Pp, 0, y + 1, x, xin) : 0.0;
     double xm[NC], xp[NC], ym[NC], yp[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -330,8 +339,9 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
         }
         if (NL == NL_CUBIC) {
           const double u = uc[0];
-          r[0] = lap[0] + u * u * u + a.lin * u - f[0];
-          const double fu = 3.0 * u * u + a.lin;
+          const double m = a.lin + pv;
+          r[0] = lap[0] + a.cub * (u * u * u) + m * u - f[0];
+          const double fu = 3.0 * a.cub * (u * u) + m;
           mn = fmin(mn, fu);
           mx = fmax(mx, fu);
         } else {
@@ -367,6 +377,7 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
       hl[c] = nhl[c];
       hr[c] = nhr[c];
     }
+    pv = npv;
   }
 
   block_reduce4<R2X / 64>(s_r, mn, mx, s_f);

@@ -85,8 +85,16 @@ def opts(**kw):
     (dict(lin=float("nan")), 0, 1, (9, 9, 9), 0.0, "invalid"),
     (dict(lin=1.0), 2, 2, (9, 9, 9), 0.0, "invalid"),          # lin only for the cubic problem
     (dict(length=2.0, lin=0.5), 0, 1, (9, 9, 9), 0.0, "ok"),
+    # cubic coefficient and potential (never dereferenced by setup)
+    (dict(cub=float("nan")), 0, 1, (9, 9, 9), 0.0, "invalid"),
+    (dict(cub=-0.5), 0, 1, (9, 9, 9), 0.0, "ok"),
+    (dict(cub=2.0), 2, 2, (9, 9, 9), 0.0, "invalid"),          # cub != 1 only for cubic
+    (dict(cub=1.0), 2, 2, (9, 9, 9), 0.0, "ok"),
+    (dict(potential=4096), 1, 1, (9, 9, 9), 0.0, "invalid"),   # potential only for cubic
+    (dict(potential=4096), 2, 2, (9, 9, 9), 0.0, "invalid"),
+    (dict(boundary=1, lin=10.0, cub=10.0, potential=4096), 0, 1, (9, 9, 9), 1.0, "ok"),
 ])
-def test_setup_boundary_length_and_lin(kw, nl, ncomp, n, beta, want):
+def test_setup_boundary_length_and_pointwise_terms(kw, nl, ncomp, n, beta, want):
     dim = 2 if n[2] == 1 else 3
     if dim == 2 and want == "ok" and kw.get("boundary") == 1:
         beta = 0.5  # a fixed shift must still be positive with Neumann data (lam_min = 0)

@@ -1,0 +1,136 @@
+"""GPU parity of the general pointwise term lambda U + b U^3 + V U of the cubic
+problem (Section 2 model with f(x, u) = b u^3 + V(x) u - f_src; Section 6.3,
+Example 1, eq. ex3d1: lambda = b = 10 and a potential V on [-1, 1]^3 with
+Neumann data) against the FP64 oracle, for both boundary types.  Tolerances
+as for the other residual and iterate tests: residual <= 1e-13 of the
+cancelling terms; iterate: equal counts, then exactly K solves on both sides
+to <= 1e-12 rel L2."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import neumann as nm
+from oracle import operators as ops
+from oracle import qn as oqn
+from paper_2502_03611_amd import Solver, QN_OK, QN_ERR_NOT_CONVERGED
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+CASES = [("neumann", (33, 47)), ("neumann", (2, 5)), ("neumann", (17, 20, 23)),
+         ("neumann", (5, 70, 3)), ("dirichlet", (31, 45)), ("dirichlet", (1, 70)),
+         ("dirichlet", (19, 33, 40)), ("dirichlet", (3, 1, 65))]
+
+
+@pytest.mark.parametrize("bc,shape", CASES)
+@pytest.mark.parametrize("lin,cub", [(10.0, 10.0), (0.0, -0.5)])
+def test_residual_parity_with_potential(bc, shape, lin, cub):
+    print(f"pointwise residual {bc} {shape} lin {lin} cub {cub}", flush=True)
+    u = synth.random_field((1,) + shape, 301)
+    f = synth.random_field((1,) + shape, 302, scale=10.0)
+    v = np.abs(synth.random_field(shape, 303, scale=50.0))
+    pot = dev(v)
+    s = Solver(shape, "cubic", beta=1.0, boundary=bc, lin=lin, cub=cub, potential=pot)
+    red = torch.zeros(4, dtype=torch.float64, device="cuda")
+    r = host(s.residual(dev(u), dev(f), red=red))[0]
+    if bc == "neumann":
+        hs = nm.spacing(shape)
+        ref = nm.residual_cubic(u[0], f[0], hs, lin, cub, v)
+        lap = nm.apply_laplacian(u[0], hs)
+        fu = nm.fu_cubic(u[0], lin, cub, v)
+    else:
+        ref = ops.residual_cubic(u[0], f[0], lin, cub, v)
+        lap = ops.apply_laplacian(u[0])
+        fu = ops.fu_cubic(u[0], lin, cub, v)
+    scale = (np.linalg.norm(lap) + abs(cub) * np.linalg.norm(u[0] ** 3) +
+             abs(lin) * np.linalg.norm(u[0]) + np.linalg.norm(v * u[0]) + np.linalg.norm(f[0]))
+    assert np.linalg.norm(r - ref) / scale <= 1e-13
+    red = red.cpu().numpy()
+    assert red[0] == pytest.approx(float(np.sum(ref * ref)), rel=1e-12)
+    assert red[1] == pytest.approx(float(fu.min()), rel=1e-13, abs=1e-13)
+    assert red[2] == pytest.approx(float(fu.max()), rel=1e-13)
+
+
+@pytest.mark.parametrize("n", [17, 30])
+def test_e7_iterate_parity(n):
+    """Section 6.3 Example 1 (eq. ex3d1) from U_0 = 0 with the midpoint
+    shift: equal counts, then exactly K solves on both sides."""
+    print(f"pointwise iterate e7 {n}", flush=True)
+    u_ex, f, v = synth.neumann_potential_3d(n)
+    hs = nm.spacing(f.shape)
+    ref = nm.qn_solve(f, hs, lin=10.0, cub=10.0, pot=v)
+    s = Solver(f.shape, "cubic", beta_mode="midpoint", boundary="neumann", lin=10.0, cub=10.0,
+               potential=dev(v))
+    u = torch.zeros((1,) + f.shape, dtype=torch.float64, device="cuda")
+    st = s.iterate(u, dev(f[None]), rtol=1e-10, max_iter=300)
+    assert st["status"] == QN_OK, st
+    assert st["iters"] == ref["iters"], (st["iters"], ref["iters"])
+    k = ref["iters"]
+    ug = torch.zeros_like(u)
+    st2 = s.iterate(ug, dev(f[None]), rtol=0.0, max_iter=k)
+    assert st2["status"] == QN_ERR_NOT_CONVERGED and st2["iters"] == k
+    assert rel(host(ug)[0], ref["u"]) <= 1e-12
+
+
+def test_e7_perturbed_start_fp32_transforms():
+    """The paper's experiment shape: start from the discrete solution plus a
+    0.1-scaled polynomial perturbation (Section 6.3); FP32 transforms reach
+    the FP64 oracle's solution within 1e-9 in at most 10 % more iterations."""
+    n = 33
+    u_ex, f, v = synth.neumann_potential_3d(n)
+    hs = nm.spacing(f.shape)
+    u_star = nm.qn_solve(f, hs, lin=10.0, cub=10.0, pot=v, rtol=1e-13, max_iter=500)["u"]
+    u0 = u_star + 0.1 * synth.polynomial_perturbation(n, 3, 0)
+    ref = nm.qn_solve(f, hs, lin=10.0, cub=10.0, pot=v, u0=u0)
+    s = Solver(f.shape, "cubic", beta_mode="midpoint", boundary="neumann", lin=10.0, cub=10.0,
+               potential=dev(v), precision="fp32")
+    u = dev(u0[None])
+    st = s.iterate(u, dev(f[None]), rtol=1e-10, max_iter=300)
+    assert st["status"] == QN_OK and st["iters"] <= int(np.ceil(1.1 * ref["iters"])), \
+        (st["iters"], ref["iters"])
+    assert rel(host(u)[0], ref["u"]) <= 1e-9
+
+
+def test_dirichlet_iterate_parity_with_pointwise_terms():
+    print("pointwise iterate dirichlet 31x33x35", flush=True)
+    shape = (31, 33, 35)
+    v = np.abs(synth.random_field(shape, 311, scale=20.0))
+    f = 50.0 * synth.random_field((1,) + shape, 312)
+    ref = oqn.qn_solve(oqn.CUBIC, f, midpoint=True, lin=1.5, cub=3.0, pot=v)
+    s = Solver(shape, "cubic", beta_mode="midpoint", lin=1.5, cub=3.0, potential=dev(v))
+    u = torch.zeros((1,) + shape, dtype=torch.float64, device="cuda")
+    st = s.iterate(u, dev(f), rtol=1e-10, max_iter=300)
+    assert st["status"] == QN_OK and st["iters"] == ref["iters"], (st["iters"], ref["iters"])
+    k = ref["iters"]
+    ug = torch.zeros_like(u)
+    st2 = s.iterate(ug, dev(f), rtol=0.0, max_iter=k)
+    assert st2["iters"] == k
+    assert rel(host(ug)[0], ref["u"][0]) <= 1e-12
+
+
+def test_potential_is_validated():
+    from paper_2502_03611_amd._binding import QNError
+    v = torch.zeros((9, 9), dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        Solver((9, 9), "cubic", beta=1.0, potential=v)
+    with pytest.raises(ValueError):
+        Solver((9, 9), "cubic", beta=1.0, potential=torch.zeros((9, 8), dtype=torch.float64,
+                                                                 device="cuda"))
+    with pytest.raises(QNError):
+        Solver((9, 9), "system", beta=1.0,
+               potential=torch.zeros((9, 9), dtype=torch.float64, device="cuda"))
