@@ -177,6 +177,148 @@ def amplitude_sweep(n, runs):
     return out
 
 
+# ---------------------------------------------------------------------------
+# The paper's own Neumann examples (Section 6.2 Example 1, eq. ex2d1, and
+# Section 6.3 Example 1, eq. ex3d1) at the sizes of its mesh tables
+# (results2d_space: 200^2 .. 1600^2 nodes; results3D_mesh: 200^3 .. 800^3),
+# started like the paper's experiments from the discrete solution plus a
+# 0.1-scaled random degree-4 polynomial.  Large inputs are evaluated on the
+# device from the same definitions as synth's generators (checked against
+# them on the CPU in the tests).
+
+
+def e4_inputs(n, device="cuda"):
+    """synth.neumann_2d on `device`: (u_exact, f), shape (n, n)."""
+    x = torch.from_numpy(synth.node_coords(n)).to(device)
+    u = torch.cos(2.0 * math.pi * x)[:, None] * torch.cos(math.pi * x)[None, :]
+    return u, 5.0 * math.pi ** 2 * u + u ** 3 + u
+
+
+def e7_inputs(n, a=10.0, b=10.0, device="cuda"):
+    """synth.neumann_potential_3d on `device`: (u_exact, f, V), shape (n, n, n)."""
+    x = torch.from_numpy(synth.node_coords(n)).to(device)
+    c = torch.cos(math.pi * x)
+    w = 100.0 * torch.sin(math.pi * x / 4.0) ** 2 + x * x
+    u = c[:, None, None] + c[None, :, None] + c[None, None, :]
+    v = w[:, None, None] + w[None, :, None] + w[None, None, :]
+    f = (math.pi ** 2 + a) * u
+    f += b * u ** 3
+    f += v * u
+    return u, f, v
+
+
+def perturbation(n, dim, seed, device="cuda"):
+    """synth.polynomial_perturbation on `device` (same coefficients and nodes)."""
+    coef = torch.from_numpy(synth.polynomial_coefficients(dim, seed)).to(device)
+    x = torch.from_numpy(synth.node_coords(n)).to(device)
+    powers = torch.stack([x ** e for e in range(coef.shape[0])])  # (degree+1, n)
+    pt = powers.t().contiguous()                                   # (n, degree+1)
+    if dim == 2:
+        yx = pt @ (coef.t().contiguous() @ powers)                 # sum_j y^j sum_i a_ij x^i
+    else:
+        k = coef.shape[0]
+        kyx = torch.stack([pt @ (coef[:, :, kk].t().contiguous() @ powers) for kk in range(k)])
+        yx = (pt @ kyx.reshape(k, n * n)).reshape(n, n, n)
+    return yx / yx.abs().max()
+
+
+def neumann_table_row(shape, F, V, u_ex, lin, cub, fixed_beta, seeds, timing=False):
+    """One size of a mesh table: the discrete solution U* (midpoint iteration
+    from the sampled exact solution to relres 1e-12, or 60 iterations at its
+    rounding floor),
+    then for each seed a timed solve from U* + 0.1 p to relres 1e-10 with the
+    midpoint shift (FP64 and FP32 transforms) and with the fixed shift
+    `fixed_beta` (FP64).  Iterations and seconds: mean, std, median."""
+    n, dim = shape[0], len(shape)
+    s = Solver(shape, "cubic", beta_mode="midpoint", boundary="neumann", lin=lin, cub=cub,
+               potential=V)
+    s.autotune()
+    Ustar = u_ex[None].clone()
+    st = s.iterate(Ustar, F, rtol=1e-12, max_iter=60)  # the floor at 1600^2 is ~2e-12
+    s.close()
+    rec = {"n": n, "unknowns": n ** dim,
+           "discrete_solution": {"iters": st["iters"], "relres": st["relres"],
+                                 "max_err_vs_exact": float((Ustar[0] - u_ex).abs().max())}}
+    U = torch.empty_like(Ustar)
+    kernels = None
+    for label, mode, beta, prec in (("midpoint_fp64", "midpoint", 0.0, "fp64"),
+                                    ("midpoint_fp32", "midpoint", 0.0, "fp32"),
+                                    (f"beta{fixed_beta:g}_fp64", "fixed", fixed_beta, "fp64")):
+        tm = timing and label == "midpoint_fp64"
+        solver = Solver(shape, "cubic", beta=beta, beta_mode=mode, boundary="neumann", lin=lin,
+                        cub=cub, potential=V, precision=prec, timing=tm)
+        solver.autotune()
+        U.copy_(Ustar)
+        solver.iterate(U, F, rtol=0.0, max_iter=1)  # untimed warm-up of this context
+        if tm:
+            torch.cuda.synchronize()
+            solver.timing(reset=True)
+        iters, times, bad = [], [], 0
+        for seed in seeds:
+            U.copy_(Ustar)
+            U[0].add_(perturbation(n, dim, seed), alpha=0.1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = solver.iterate(U, F, rtol=1e-10, max_iter=500)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            iters.append(st["iters"])
+            bad += st["status"] != 0
+        if tm:
+            kernels = {k: {"launches": v[0], "avg_ms": round(v[1] / max(v[0], 1), 4)}
+                       for k, v in solver.timing(reset=True).items() if v[0]}
+        solver.close()
+        rec[label] = {"iters_mean": round(float(np.mean(iters)), 2),
+                      "iters_std": round(float(np.std(iters)), 2),
+                      "time_mean_s": round(float(np.mean(times)), 4),
+                      "time_std_s": round(float(np.std(times)), 4),
+                      "time_median_s": round(float(np.median(times)), 4),
+                      "not_converged": bad, "seeds": len(seeds),
+                      "max_err_vs_exact": float((U[0] - u_ex).abs().max())}
+        log(f"  n={n} {label}: iters {rec[label]['iters_mean']} +- {rec[label]['iters_std']}, "
+            f"median {rec[label]['time_median_s']} s")
+    if kernels is not None:
+        rec["kernels_midpoint_fp64"] = kernels
+        if "residual" in kernels:
+            # residual pass: read U, F, V on the nodes, write R into the padded transform tensor
+            pts = float(n) ** dim
+            padded = 1.0
+            for t in shape:
+                padded *= 2 * (-(-((t + 1) // 2) // 32) * 32)
+            r_bytes = 24.0 * pts + 8.0 * padded if V is not None else 16.0 * pts + 8.0 * padded
+            gbs = r_bytes / (kernels["residual"]["avg_ms"] * 1e-3) / 1e9
+            rec["residual_hbm"] = {"algorithmic_bytes": r_bytes, "achieved_gbs": round(gbs, 1),
+                                   "frac": round(gbs / PEAK_HBM_GBS, 4)}
+        ne, no = (n + 1) // 2, n // 2
+        fl = 2.0 * float(n) ** (dim - 1) * (ne * ne + no * no)
+        prods = [k for k in kernels if k.startswith("gemm")]
+        tot_ms = sum(kernels[k]["avg_ms"] * kernels[k]["launches"] for k in prods)
+        tot_launch = sum(kernels[k]["launches"] for k in prods)
+        rec["mode_products_folded_tflops"] = round(fl * tot_launch / (tot_ms * 1e-3) / 1e12, 2)
+    return rec
+
+
+def paper_tables(seeds2d, seeds3d):
+    """Rows of Tables results2d_space (eq. ex2d1: lambda = 1, b = 1, midpoint
+    and beta = 3) and results3D_mesh (eq. ex3d1: lambda = b = 10, V, midpoint
+    and beta = 200)."""
+    out = {"e4_2d": [], "e7_3d": []}
+    for n in (200, 400, 800, 1600):
+        log(f"paper table 2D n={n}")
+        u_ex, f = e4_inputs(n)
+        out["e4_2d"].append(neumann_table_row((n, n), f[None].contiguous(), None, u_ex, 1.0, 1.0,
+                                              3.0, range(seeds2d)))
+        del u_ex, f
+    for n, k in ((200, seeds3d), (400, max(seeds3d // 2, 2)), (800, max(seeds3d // 6, 2))):
+        log(f"paper table 3D n={n}")
+        u_ex, f, v = e7_inputs(n)
+        out["e7_3d"].append(neumann_table_row((n, n, n), f[None].contiguous(), v, u_ex, 10.0,
+                                              10.0, 200.0, range(k), timing=(n == 800)))
+        del u_ex, f, v
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(n, amp):
     """The CPU oracle, as it stands, on a bounded sample: one quasi-Newton
     iteration (residual, shift rule, tensor-product solve, residual) at the
@@ -280,6 +422,11 @@ def main():
                     help="timed solves per precision for time to tolerance (median reported)")
     ap.add_argument("--amp-sweep", action="store_true",
                     help="also report time to tolerance for the amplitudes of seeds 0-4 and A = 2")
+    ap.add_argument("--paper-tables", action="store_true",
+                    help="also run the paper's Neumann mesh tables (2D 200^2-1600^2, "
+                         "3D 200^3-800^3, perturbed starts)")
+    ap.add_argument("--table-seeds", type=int, default=20,
+                    help="perturbations per 2D size and at 200^3 (fewer at 400^3 and 800^3)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--batched-count", type=int, default=512)
@@ -413,6 +560,9 @@ def main():
     torch.cuda.empty_cache()
     if args.amp_sweep:
         out["amplitude_sweep"] = amplitude_sweep(n, args.ttt_runs)
+    if args.paper_tables:
+        out["paper_tables"] = paper_tables(args.table_seeds, args.table_seeds)
+        torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_count)
         torch.cuda.empty_cache()

@@ -28,6 +28,7 @@ from .fields import (  # noqa: F401
     neumann_2d,
     neumann_3d,
     neumann_potential_3d,
+    polynomial_coefficients,
     polynomial_perturbation,
     BATCH_SIZES,
 )

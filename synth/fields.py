@@ -164,18 +164,25 @@ def neumann_potential_3d(n, a=10.0, b=10.0):
     return u, f, v
 
 
+def polynomial_coefficients(dim, seed, degree=4):
+    """Coefficients a ~ U(-1, 1) of the perturbation polynomial, from
+    default_rng(seed), shape (degree + 1,) * dim, indexed (x, y[, z]) exponents."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, size=(degree + 1,) * dim)
+
+
 def polynomial_perturbation(n, dim, seed, degree=4):
     """Section 6.2 / 6.3 initial-guess perturbation p on all n^dim nodes of
     [-1, 1]^dim: sum of a_{i..} x^i y^j (z^k) over exponents 0..degree with
     coefficients a ~ U(-1, 1) from default_rng(seed), divided by its largest
     magnitude over the nodes (so max |p| = 1 on the grid).  Shape (ny, nx) or
     (nz, ny, nx); the coefficient array is indexed (x, y[, z]) exponents."""
-    rng = np.random.default_rng(seed)
-    coef = rng.uniform(-1.0, 1.0, size=(degree + 1,) * dim)
+    coef = polynomial_coefficients(dim, seed, degree)
     x = node_coords(n)
     powers = np.stack([x ** e for e in range(degree + 1)])  # (degree+1, n)
     if dim == 2:
-        p = np.einsum("ij,iX,jY->YX", coef, powers, powers)
-    else:
-        p = np.einsum("ijk,iX,jY,kZ->ZYX", coef, powers, powers, powers)
-    return p / np.abs(p).max()
+        p = np.einsum("ij,iX,jY->YX", coef, powers, powers, optimize=True)
+    else:  # one axis at a time: (k, Y, X) first, then the z-planes (no n^3 temporaries)
+        kyx = np.einsum("ijk,iX,jY->kYX", coef, powers, powers, optimize=True)
+        p = np.einsum("kZ,kYX->ZYX", powers, kyx, optimize=True)
+    p /= max(float(p.max()), -float(p.min()))
+    return p
