@@ -30,5 +30,7 @@ from .fields import (  # noqa: F401
     neumann_potential_3d,
     polynomial_coefficients,
     polynomial_perturbation,
+    interior_coords,
+    schrodinger_3d,
     BATCH_SIZES,
 )

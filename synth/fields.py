@@ -170,14 +170,15 @@ def polynomial_coefficients(dim, seed, degree=4):
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=(degree + 1,) * dim)
 
 
-def polynomial_perturbation(n, dim, seed, degree=4):
-    """Section 6.2 / 6.3 initial-guess perturbation p on all n^dim nodes of
-    [-1, 1]^dim: sum of a_{i..} x^i y^j (z^k) over exponents 0..degree with
-    coefficients a ~ U(-1, 1) from default_rng(seed), divided by its largest
-    magnitude over the nodes (so max |p| = 1 on the grid).  Shape (ny, nx) or
-    (nz, ny, nx); the coefficient array is indexed (x, y[, z]) exponents."""
+def polynomial_perturbation(n, dim, seed, degree=4, coords=None):
+    """Section 6.2 / 6.3 initial-guess perturbation p on the n^dim nodes with
+    per-axis coordinates `coords` (default: all n nodes of [-1, 1]): sum of
+    a_{i..} x^i y^j (z^k) over exponents 0..degree with coefficients
+    a ~ U(-1, 1) from default_rng(seed), divided by its largest magnitude over
+    the nodes (so max |p| = 1 on the grid).  Shape (ny, nx) or (nz, ny, nx);
+    the coefficient array is indexed (x, y[, z]) exponents."""
     coef = polynomial_coefficients(dim, seed, degree)
-    x = node_coords(n)
+    x = node_coords(n) if coords is None else np.asarray(coords, dtype=np.float64)
     powers = np.stack([x ** e for e in range(degree + 1)])  # (degree+1, n)
     if dim == 2:
         p = np.einsum("ij,iX,jY->YX", coef, powers, powers, optimize=True)
@@ -186,3 +187,21 @@ def polynomial_perturbation(n, dim, seed, degree=4):
         p = np.einsum("kZ,kYX->ZYX", powers, kyx, optimize=True)
     p /= max(float(p.max()), -float(p.min()))
     return p
+
+
+def interior_coords(n, a, b):
+    """Interior nodes x_i = a + i (b - a)/(n + 1), i = 1..n (Dirichlet grid on (a, b))."""
+    return a + (b - a) * np.arange(1, n + 1, dtype=np.float64) / (n + 1)
+
+
+def schrodinger_3d(n, half=8.0):
+    """Section 6.3, Example 2 (eq. ex3d2) on the n^3 interior nodes of
+    (-half, half)^3 with Dirichlet data: the potential V = 100 (sin^2(pi x/4) +
+    sin^2(pi y/4) + sin^2(pi z/4)) + x^2 + y^2 + z^2 and a start
+    exp(-|x|^2 / 2) (not normalised).  Returns (V, u_start), shape (nz, ny, nx)."""
+    x = interior_coords(n, -half, half)
+    w = 100.0 * np.sin(math.pi * x / 4.0) ** 2 + x * x
+    g = np.exp(-0.5 * x * x)
+    v = w[:, None, None] + w[None, :, None] + w[None, None, :]
+    u = g[:, None, None] * g[None, :, None] * g[None, None, :]
+    return v, u
