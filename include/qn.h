@@ -211,6 +211,38 @@ qn_status qn_fdm_solve(qn_ctx ctx, const double* d_R, double scale, double shift
 qn_status qn_iterate(qn_ctx ctx, double* d_U, const double* d_F, double rtol,
                      int32_t max_iter, qn_stats* stats);
 
+/* Nonlinear eigenproblem (Section 4.4, eqs. Eigenvalue_p, system_qusi and
+ * system_normal; Section 6.3 Example 2, eq. ex3d2 with b = 1600, lambda = 0 and
+ * a potential V on (-8, 8)^3) for a QN_NL_CUBIC context with FP64 or FP32
+ * transforms: find U and lam with A_h U + f(U) = lam U and ||U||_M = 1, where
+ * f(U) = b U^3 + (lambda + V) U takes the context's cub, lin and potential, and
+ * <X, Y>_M = h^d sum W X Y is the lumped mass inner product (W = 1 for
+ * Dirichlet data; trapezoid weights, 1/2 at each end of an axis, for Neumann
+ * data).  The context's source-free parts only are used (no F).
+ * Errors: QN_ERR_UNSUPPORTED for another nonlinearity or a split-bf16
+ * precision; QN_ERR_WORKSPACE when unbound; QN_ERR_INVALID for null or
+ * misaligned pointers. */
+
+/* For the stored d_U (not modified): U = d_U / ||d_U||_M, the Rayleigh
+ * quotient lam = <A_h U + f(U), U>_M and d_R = A_h U + f(U) - lam U (output,
+ * interior layout, may not alias d_U).  d_out: NULL or device double[6]
+ * receiving {lam, 1 / ||d_U||_M, ||R||_M^2, min mu, max mu, ||R||_M / |lam|}
+ * with mu = 3 b U^2 + lambda + V - lam.  Asynchronous. */
+qn_status qn_eigen_residual(qn_ctx ctx, const double* d_U, double* d_R, double* d_out);
+
+/* The iteration from d_U (in: U_0, any nonzero multiple; out: the last
+ * iterate U_n, normalised): lam_n and R_n = A_h U_n + f(U_n) - lam_n U_n; stop
+ * when ||R_n||_M / |lam_n| <= rtol (rtol = 0: exactly max_iter solves) or
+ * after max_iter solves; beta_n = the context's fixed beta, or with
+ * QN_BETA_MIDPOINT (min mu + max mu) / 2 at U_n; U~ = U_n - (A_h + beta_n I)^-1
+ * R_n; U_{n+1} = U~ / ||U~||_M.  Returns QN_OK, QN_ERR_NOT_CONVERGED or
+ * QN_ERR_DIVERGED (a non-finite residual, or a shift with
+ * lam_min(A_h) + beta_n <= 0).  *stats (may be NULL) as for qn_iterate
+ * (relres = ||R||_M / |lam|); *lam_out (host, may be NULL) receives the last
+ * lam.  Synchronous on return. */
+qn_status qn_eigen_iterate(qn_ctx ctx, double* d_U, double rtol, int32_t max_iter,
+                           qn_stats* stats, double* lam_out);
+
 /* Tile selection for the mode products (Section 4.1, eq. fin_inverse, as
  * reflection-folded matrix-core products).  The solve is a fixed list of
  * launches (3D: 6, 2D: 4; the x forward product first, the x inverse product

@@ -75,6 +75,9 @@ def lib():
     L.qn_timing_read.argtypes = [c_vp, c_i32, ctypes.POINTER(ctypes.c_char_p),
                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(c_dbl)]
     L.qn_timing_reset.argtypes = [c_vp]
+    L.qn_eigen_residual.argtypes = [c_vp, c_vp, c_vp, c_vp]
+    L.qn_eigen_iterate.argtypes = [c_vp, c_vp, c_dbl, c_i32, ctypes.POINTER(QNStats),
+                                   ctypes.POINTER(c_dbl)]
     L.qn_autotune.argtypes = [c_vp]
     L.qn_tile_info.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i32)]
     L.qn_set_tile.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i32)]
@@ -85,7 +88,7 @@ def lib():
     for name in ("qn_setup", "qn_workspace_bytes", "qn_bind_workspace", "qn_set_stream",
                  "qn_residual", "qn_fdm_solve", "qn_iterate", "qn_timing_count",
                  "qn_timing_read", "qn_timing_reset", "qn_autotune", "qn_tile_info",
-                 "qn_set_tile"):
+                 "qn_set_tile", "qn_eigen_residual", "qn_eigen_iterate"):
         getattr(L, name).restype = c_i32
     _lib = L
     return L
@@ -210,6 +213,32 @@ class Solver:
             check(status)
         return {"status": status, "iters": st.iters, "relres": st.relres, "relres0": st.relres0,
                 "beta_last": st.beta_last, "scale_last": st.scale_last, "seconds": st.seconds,
+                "message": last_error() if status != QN_OK else ""}
+
+    def eigen_residual(self, U, R=None, out=None):
+        """Eigenproblem residual at U / ||U||_M (U unchanged): R = A_h U + f(U) - lam U;
+        out (optional, float64[6] CUDA) gets {lam, 1/||U||_M, ||R||_M^2, min mu,
+        max mu, ||R||_M / |lam|}."""
+        self._field(U, "U")
+        R = self.empty() if R is None else self._field(R, "R")
+        self._sync_stream()
+        check(lib().qn_eigen_residual(self._ctx, _ptr(U), _ptr(R), _ptr(out)))
+        return R
+
+    def eigen_iterate(self, U, rtol=1e-10, max_iter=2000, raise_on_error=False):
+        """Nonlinear eigenproblem iteration in place on U (normalised on return);
+        returns a stats dict with the eigenvalue under "lam"."""
+        self._field(U, "U")
+        self._sync_stream()
+        st = QNStats()
+        lam = c_dbl()
+        status = lib().qn_eigen_iterate(self._ctx, _ptr(U), float(rtol), int(max_iter),
+                                        ctypes.byref(st), ctypes.byref(lam))
+        if status in (QN_ERR_INVALID, QN_ERR_HIP, QN_ERR_WORKSPACE, QN_ERR_UNSUPPORTED) or (
+                raise_on_error and status != QN_OK):
+            check(status)
+        return {"status": status, "iters": st.iters, "relres": st.relres, "relres0": st.relres0,
+                "beta_last": st.beta_last, "lam": lam.value, "seconds": st.seconds,
                 "message": last_error() if status != QN_OK else ""}
 
     def timing(self, reset=False):

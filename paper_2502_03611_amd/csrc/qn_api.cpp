@@ -51,11 +51,14 @@ enum KernelId {
   K_GEMM_X_UPDATE,  // inverse x product with U -= dU (or X = dU)
   K_PAD_COPY,
   K_GEMM_YZ_INV,    // inverse y / z products
+  K_EIG_SUMS,       // eigenproblem: sums over the stored iterate
+  K_EIG_FINALIZE,   // eigenproblem: Rayleigh quotient and normalising factor
   K_COUNT
 };
 const char* const kKernelNames[K_COUNT] = {"residual",    "finalize",      "gemm_x",
                                            "gemm_yz",     "gemm_divide",   "gemm_x_update",
-                                           "pad_copy",    "gemm_yz_inv"};
+                                           "pad_copy",    "gemm_yz_inv",   "eig_sums",
+                                           "eig_finalize"};
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -94,6 +97,7 @@ struct qn_ctx_s {
   double lam_min_sum = 0.0;
   int bc = QN_BC_DIRICHLET;
   double length = 1.0, lin = 0.0, cub = 1.0;
+  double hvol = 1.0;  // h^d: the mass of one interior node
   const double* pot = nullptr;  // caller-owned potential V, or NULL
   double ih2[3] = {1.0, 1.0, 0.0};  // h^-2 per axis (0 for the missing z of 2D)
   hipStream_t stream = nullptr;
@@ -247,23 +251,22 @@ GemmOperands operands(qn_ctx c, int axis) {
   return g;
 }
 
-// Residual of U into the padded transform workspace W1 (+ partials), then
-// the on-device finalize with the context's shift rule.
-hipError_t residual_into_ws(qn_ctx c, const double* U, const double* F, double* red_out,
-                            double rtol = 0.0, int iter = -1, int max_iter = 0,
-                            const int* stop = nullptr, DevScalars* mirror = nullptr) {
+// Residual arguments for U (and F) with the output R either the padded
+// transform workspace W1 in the context's precision (into_ws) or a caller
+// array of the interior layout in FP64.
+ResidualArgs residual_args(qn_ctx c, const double* U, const double* F, double* R_caller) {
   ResidualArgs a{};
-  a.stop = stop;
   a.U = U;
   a.F = F;
-  a.R = c->ws + c->off_W1;
-  a.out_prec = c->prec == QN_PREC_FP64 ? 0 : 1;
-  a.r_cstride = (long long)c->p[2] * c->p[1] * c->p[0];
-  a.r_zstride = c->p[1] * c->p[0];
-  a.r_ystride = c->p[0];
-  a.ox = c->p[0];
-  a.oy = c->p[1];
-  a.oz = c->p[2];
+  const int* ext = R_caller ? c->n : c->p;
+  a.R = R_caller ? (void*)R_caller : (void*)(c->ws + c->off_W1);
+  a.out_prec = (R_caller || c->prec == QN_PREC_FP64) ? 0 : 1;
+  a.r_cstride = (long long)ext[2] * ext[1] * ext[0];
+  a.r_zstride = ext[1] * ext[0];
+  a.r_ystride = ext[0];
+  a.ox = ext[0];
+  a.oy = ext[1];
+  a.oz = ext[2];
   a.nx = c->n[0];
   a.ny = c->n[1];
   a.nz = c->n[2];
@@ -278,6 +281,16 @@ hipError_t residual_into_ws(qn_ctx c, const double* U, const double* F, double* 
   a.bc = c->bc;
   a.partials = c->at<double>(c->off_part);
   a.rz = c->dim == 3 ? RESIDUAL_RZ : residual_planar_rows(a.ox, a.oy);
+  return a;
+}
+
+// Residual of U into the padded transform workspace W1 (+ partials), then
+// the on-device finalize with the context's shift rule.
+hipError_t residual_into_ws(qn_ctx c, const double* U, const double* F, double* red_out,
+                            double rtol = 0.0, int iter = -1, int max_iter = 0,
+                            const int* stop = nullptr, DevScalars* mirror = nullptr) {
+  ResidualArgs a = residual_args(c, U, F, nullptr);
+  a.stop = stop;
   int nb = 0;
   hipError_t e = timed(c, K_RESIDUAL, [&] { return launch_residual(a, &nb, c->stream); });
   if (e != hipSuccess) return e;
@@ -285,6 +298,33 @@ hipError_t residual_into_ws(qn_ctx c, const double* U, const double* F, double* 
     return launch_finalize(a.partials, nb, c->scal(), rule_of(c), c->beta, c->lam_min_sum, red_out,
                            rtol, iter, max_iter, c->stream, mirror);
   });
+}
+
+// Eigenproblem residual (Section 4.4) of the stored iterate U~: the sums
+// pass and its finalize (lam, s into the device scalars), then R at U = s U~
+// into W1 (R_caller == NULL) or the caller's array, and the stopping / shift
+// finalize.  U~ itself is not modified.
+hipError_t eigen_residual(qn_ctx c, const double* U, double* R_caller, double* red_out,
+                          double rtol, int iter, int max_iter, const int* stop,
+                          DevScalars* mirror) {
+  ResidualArgs a = residual_args(c, U, nullptr, R_caller);
+  a.stop = stop;
+  a.mode = 1;
+  int nb = 0;
+  hipError_t e = timed(c, K_EIG_SUMS, [&] { return launch_residual(a, &nb, c->stream); });
+  if (e == hipSuccess)
+    e = timed(c, K_EIG_FINALIZE, [&] {
+      return launch_eig_finalize1(a.partials, nb, c->scal(), c->cub, c->hvol, stop, c->stream);
+    });
+  a.mode = 2;
+  a.eig = &c->scal()->eig;
+  if (e == hipSuccess) e = timed(c, K_RESIDUAL, [&] { return launch_residual(a, &nb, c->stream); });
+  if (e == hipSuccess)
+    e = timed(c, K_FINALIZE, [&] {
+      return launch_eig_finalize2(a.partials, nb, c->scal(), rule_of(c), c->beta, c->lam_min_sum,
+                                  c->hvol, red_out, rtol, iter, max_iter, stop, c->stream, mirror);
+    });
+  return e;
 }
 
 // The folded solve as a list of launches (3D: x, y forward; z forward with
@@ -454,9 +494,10 @@ EpiArgs epi_args(qn_ctx c, const double* coef, double* dense) {
 // skip (device int, may be NULL): when set, every launch of the solve exits
 // at once (the quasi-Newton loop has stopped).
 hipError_t solve_ws(qn_ctx c, const double* coef, double* dense, int epi_last,
-                    const int* skip = nullptr) {
+                    const int* skip = nullptr, const double* uscale = nullptr) {
   EpiArgs ep = epi_args(c, coef, dense);
   ep.skip = skip;
+  ep.uscale = uscale;
   FoldStep st[6];
   const int ns = solve_plan(c, ep, epi_last, st);
   for (int i = 0; i < ns; ++i) {
@@ -542,6 +583,7 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
     // ends (Neumann, h = L/(n-1)); exact integers on the unit interval
     const double ih = (c->bc == QN_BC_NEUMANN ? n - 1 : n + 1) / length;
     c->ih2[a] = ih * ih;
+    c->hvol /= ih;
     if (c->fold) {
       const int bk = fold_block(n);
       c->ax[a] = FoldAxis{n, n / 2, n & 1, bk};
@@ -691,31 +733,7 @@ qn_status qn_residual(qn_ctx c, const double* d_U, const double* d_F, double* d_
   if (!aligned8(d_U) || !aligned8(d_F) || !aligned8(d_R) || (d_red && !aligned8(d_red)))
     return fail(QN_ERR_INVALID, "pointers must be 8-byte aligned");
   if (d_R == d_U) return fail(QN_ERR_INVALID, "R may not alias U");
-  ResidualArgs a{};
-  a.U = d_U;
-  a.F = d_F;
-  a.R = d_R;
-  a.out_prec = 0;
-  a.r_cstride = (long long)c->n[2] * c->n[1] * c->n[0];
-  a.r_zstride = c->n[1] * c->n[0];
-  a.r_ystride = c->n[0];
-  a.ox = c->n[0];
-  a.oy = c->n[1];
-  a.oz = c->n[2];
-  a.nx = c->n[0];
-  a.ny = c->n[1];
-  a.nz = c->n[2];
-  a.dim = c->dim;
-  a.nl = c->nl;
-  a.ihx2 = c->ih2[0];
-  a.ihy2 = c->ih2[1];
-  a.ihz2 = c->ih2[2];
-  a.lin = c->lin;
-  a.cub = c->cub;
-  a.pot = c->pot;
-  a.bc = c->bc;
-  a.partials = c->at<double>(c->off_part);
-  a.rz = c->dim == 3 ? RESIDUAL_RZ : residual_planar_rows(a.ox, a.oy);
+  ResidualArgs a = residual_args(c, d_U, d_F, d_R);
   int nb = 0;
   hipError_t e = timed(c, K_RESIDUAL, [&] { return launch_residual(a, &nb, c->stream); });
   if (e == hipSuccess)
@@ -820,6 +838,97 @@ qn_status qn_iterate(qn_ctx c, double* d_U, const double* d_F, double rtol, int3
   }
   st.seconds = elapsed();
   return finish(hip_fail(c, e, "iteration"));
+}
+
+static qn_status eigen_check(qn_ctx c) {
+  qn_status s = check_ctx(c, true);
+  if (s != QN_OK) return s;
+  if (c->nl != QN_NL_CUBIC || !c->fold)
+    return fail(QN_ERR_UNSUPPORTED, "the eigenproblem needs QN_NL_CUBIC with FP64 or FP32 transforms");
+  return QN_OK;
+}
+
+qn_status qn_eigen_residual(qn_ctx c, const double* d_U, double* d_R, double* d_out) {
+  qn_status s = eigen_check(c);
+  if (s != QN_OK) return s;
+  if (!d_U || !d_R) return fail(QN_ERR_INVALID, "null U or R");
+  if (!aligned8(d_U) || !aligned8(d_R) || (d_out && !aligned8(d_out)))
+    return fail(QN_ERR_INVALID, "pointers must be 8-byte aligned");
+  if (d_R == d_U) return fail(QN_ERR_INVALID, "R may not alias U");
+  const hipError_t e = eigen_residual(c, d_U, d_R, d_out, 0.0, -1, 0, nullptr, nullptr);
+  if (e != hipSuccess) return hip_fail(c, e, "eigen residual launch");
+  return QN_OK;
+}
+
+qn_status qn_eigen_iterate(qn_ctx c, double* d_U, double rtol, int32_t max_iter, qn_stats* stats,
+                           double* lam_out) {
+  qn_stats st{};
+  st.status = QN_ERR_INVALID;
+  double lam = std::nan("");
+  auto finish = [&](qn_status s) {
+    st.status = s;
+    if (stats) *stats = st;
+    if (lam_out) *lam_out = lam;
+    return s;
+  };
+  qn_status s = eigen_check(c);
+  if (s != QN_OK) return finish(s);
+  if (!d_U) return finish(fail(QN_ERR_INVALID, "null U"));
+  if (!aligned8(d_U)) return finish(fail(QN_ERR_INVALID, "pointers must be 8-byte aligned"));
+  if (!(rtol >= 0.0) || max_iter < 0) return finish(fail(QN_ERR_INVALID, "rtol < 0 or max_iter < 0"));
+  const auto t0 = std::chrono::steady_clock::now();
+  // Same pipelining as qn_iterate.  Iteration k: the solve of step k - 1,
+  // whose update epilogue forms U~_k = s_{k-1} U~_{k-1} - dU (the stored
+  // iterate stays unnormalised), then the two residual passes at
+  // U_k = s_k U~_k and the loop decision.  On return the stored iterate is
+  // scaled once by the last s, so d_U holds the normalised U_k.
+  const int* done = &c->scal()->done;
+  auto enqueue = [&](int k) {
+    hipError_t e = hipSuccess;
+    if (k > 0)
+      e = solve_ws(c, &c->scal()->scale, d_U, EPI_SUB_DENSE, done, &c->scal()->uscale);
+    if (e == hipSuccess)
+      e = eigen_residual(c, d_U, nullptr, nullptr, rtol, k, max_iter, k > 0 ? done : nullptr,
+                         c->dring + (k & 1));
+    if (e == hipSuccess) e = hipEventRecord(c->ring_ev[k & 1], c->stream);
+    return e;
+  };
+  auto drain = [&](qn_status r) {
+    const long long n = (long long)c->ncomp * c->n[2] * c->n[1] * c->n[0];
+    hipError_t e = launch_scale(d_U, n, &c->scal()->uscale, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (e != hipSuccess) return finish(hip_fail(c, e, "eigen iteration"));
+    return finish(r);
+  };
+  hipError_t e = enqueue(0);
+  for (int k = 0; e == hipSuccess; ++k) {
+    if (k < max_iter) e = enqueue(k + 1);
+    if (e == hipSuccess) e = hipEventSynchronize(c->ring_ev[k & 1]);
+    if (e != hipSuccess) break;
+    const DevScalars h = c->hring[k & 1];
+    if (k == 0) st.relres0 = h.relres;
+    st.relres = h.relres;
+    st.iters = k;
+    lam = h.eig;
+    if (!std::isfinite(h.relres) || h.relres > 1e30)
+      return drain(fail(QN_ERR_DIVERGED, "eigen residual became non-finite at iteration %d", k));
+    if (h.relres <= rtol) {
+      g_err.clear();
+      return drain(QN_OK);
+    }
+    if (k >= max_iter)
+      return drain(fail(QN_ERR_NOT_CONVERGED, "no convergence in %d solves (relres %.3e)", k,
+                        h.relres));
+    if (h.flag != 0.0)
+      return drain(fail(QN_ERR_DIVERGED,
+                        "shift %.6g with lam_min(A_h) = %.6g is singular or indefinite at "
+                        "iteration %d", h.beta, c->lam_min_sum, k));
+    st.beta_last = h.beta;
+    st.scale_last = h.scale;
+  }
+  st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return finish(hip_fail(c, e, "eigen iteration"));
 }
 
 qn_status qn_autotune(qn_ctx c) {

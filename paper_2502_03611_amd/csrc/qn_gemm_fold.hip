@@ -753,6 +753,7 @@ __global__ __launch_bounds__(256, 2) void k_fold_right_inv(const T* __restrict__
       }
     }
     double old1[4][BN], old2[4][BN];
+    const double us = (EPI == EPI_SUB_DENSE && ep.uscale) ? *ep.uscale : 1.0;
     if (EPI == EPI_SUB_DENSE) {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -778,8 +779,8 @@ __global__ __launch_bounds__(256, 2) void k_fold_right_inv(const T* __restrict__
           C[base[q] + k] = v1;
           if (pair) C[base[q] + na - 1 - k] = p - qq;
         } else if (EPI == EPI_SUB_DENSE) {
-          ep.dense[base[q] + k] = old1[q][j] - (double)v1;
-          if (pair) ep.dense[base[q] + na - 1 - k] = old2[q][j] - (double)(p - qq);
+          ep.dense[base[q] + k] = us * old1[q][j] - (double)v1;
+          if (pair) ep.dense[base[q] + na - 1 - k] = us * old2[q][j] - (double)(p - qq);
         } else {
           ep.dense[base[q] + k] = (double)v1;
           if (pair) ep.dense[base[q] + na - 1 - k] = (double)(p - qq);

@@ -24,6 +24,10 @@ struct DevScalars {
   double flag;     // 1 if the solve operator is singular / indefinite
   int done;        // quasi-Newton loop: stop here (the next solve skips itself)
   int pad;
+  // Eigenproblem: the Rayleigh quotient lam_n and the normalising factor
+  // s_n = 1 / ||U~_n||_M of the stored iterate (adjacent: read as {lam, s}).
+  double eig;
+  double uscale;
 };
 
 // Shift rules executed on device after the residual reduction.
@@ -58,6 +62,9 @@ struct EpiArgs {
   const int* skip;
   int inst_mod;
   int coef_stride;
+  // EPI_SUB_DENSE of the folded kernels: the old values are multiplied by
+  // *uscale before the subtraction (the eigenproblem's normalisation), NULL: 1.
+  const double* uscale;
 };
 
 // Dense split-bf16 mode products (qn_gemm_bf16.hip), FP32 tensors.  All
@@ -139,8 +146,31 @@ struct ResidualArgs {
   int bc;                  // 0 Dirichlet (zero outside), 1 Neumann (mirrored neighbours)
   double cub = 1.0;
   const double* pot = nullptr;
+  // Eigenproblem passes (cubic problem only; F is not read):
+  // mode 1: no output; per-block sums {W (A U) U, W U^2, W U^4, W (lin + V) U^2}
+  //   over the stored iterate U, W = trapezoid end weights for Neumann data
+  //   (1 for Dirichlet);
+  // mode 2: with {lam, s} = eig[0..1], R = A (sU) + cub (sU)^3 + (lin + V - lam) sU,
+  //   partials {sum W R^2, min mu, max mu, 0}, mu = 3 cub (sU)^2 + lin + V - lam.
+  int mode = 0;
+  const double* eig = nullptr;
 };
 hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t st);
+// Eigenproblem finalizes (one workgroup each; return at once when *stop != 0).
+// Phase 1 reduces the mode-1 sums into sc->eig = lam and sc->uscale = s
+// (hvol = h^d, the mass of one interior node).  Phase 2 reduces the mode-2
+// partials: relres = sqrt(hvol sum W R^2) / |lam|, the shift rule (the midpoint
+// of mu, or beta_fixed), the singularity flag and the stop decision, written
+// to *sc and *mirror; red_out (may be NULL) receives
+// {lam, s, hvol sum W R^2, min mu, max mu, relres}.
+hipError_t launch_eig_finalize1(const double* partials, int nblocks, DevScalars* sc, double cub,
+                                double hvol, const int* stop, hipStream_t st);
+hipError_t launch_eig_finalize2(const double* partials, int nblocks, DevScalars* sc, int rule,
+                                double beta_fixed, double lam_min_sum, double hvol,
+                                double* red_out, double rtol, int iter, int max_iter,
+                                const int* stop, hipStream_t st, DevScalars* mirror = nullptr);
+// u[i] *= *s for i < n.
+hipError_t launch_scale(double* u, long long n, const double* s, hipStream_t st);
 // Workgroups (= partial slots) of a residual launch; planar: no z coupling
 // (1/h_z^2 = 0: 2D problems and the batched solver), which uses the planar
 // kernel with oz planes.

@@ -16,6 +16,7 @@
 // outside the interior (padding of the transform workspace) are written as
 // zero on every call, so padding never carries stale values.
 
+#include <algorithm>
 #include <cfloat>
 
 #include "qn_internal.h"
@@ -42,14 +43,15 @@ __device__ inline double wave_max(double v) {
 }
 
 // Reduce (s0, mn, mx, s1) over a block of NW wave64s; thread 0 gets the result.
-template <int NW>
+// ALLSUM: the middle two are sums as well.
+template <int NW, bool ALLSUM = false>
 __device__ inline void block_reduce4(double& s0, double& mn, double& mx, double& s1) {
   __shared__ double red[NW][4];
   const int lane = threadIdx.x + blockDim.x * threadIdx.y;
   const int w = lane >> 6, l = lane & 63;
   s0 = wave_sum(s0);
-  mn = wave_min(mn);
-  mx = wave_max(mx);
+  mn = ALLSUM ? wave_sum(mn) : wave_min(mn);
+  mx = ALLSUM ? wave_sum(mx) : wave_max(mx);
   s1 = wave_sum(s1);
   if (l == 0) {
     red[w][0] = s0;
@@ -61,8 +63,8 @@ __device__ inline void block_reduce4(double& s0, double& mn, double& mx, double&
   if (lane == 0) {
     for (int i = 1; i < NW; ++i) {
       s0 += red[i][0];
-      mn = fmin(mn, red[i][1]);
-      mx = fmax(mx, red[i][2]);
+      mn = ALLSUM ? mn + red[i][1] : fmin(mn, red[i][1]);
+      mx = ALLSUM ? mx + red[i][2] : fmax(mx, red[i][2]);
       s1 += red[i][3];
     }
   }
@@ -73,10 +75,15 @@ __device__ inline void put(void* base, long long idx, double v) {
   reinterpret_cast<TO*>(base)[idx] = (TO)v;
 }
 
+// Trapezoid weight of node i of n along an axis with Neumann data.
+__device__ inline double end_weight(int i, int n) { return (i == 0 || i == n - 1) ? 0.5 : 1.0; }
+
 // BC = 1: homogeneous Neumann data by ghost nodes: a neighbour beyond either
 // end of an axis is the mirror image of the one on the other side (first and
-// last rows h^-2 (2, -2)); BC = 0: zero outside (Dirichlet).
-template <int NL, typename TO, int BC>
+// last rows h^-2 (2, -2)); BC = 0: zero outside (Dirichlet).  MODE 1 and 2:
+// the two passes of the eigenproblem residual (cubic problem only; see
+// ResidualArgs), which read no F.
+template <int NL, typename TO, int BC, int MODE = 0>
 __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
   constexpr int NC = (NL == NL_SYS2) ? 2 : 1;
   // Current z-plane of the block's 64 x 16 tile plus a one-point x/y halo.
@@ -115,6 +122,7 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
   const bool v_ok = vy >= 0 && vy < ny && vx < nx;
 
   double s_r = 0.0, s_f = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
+  if constexpr (MODE == 1) mn = mx = 0.0;  // four sums
   const long long col = (long long)y * nx + x;
   const long long hoff = (long long)hy * nx + hx, voff = (long long)vy * nx + vx;
   // Register pipeline one plane deep: while plane z is computed, the loads of
@@ -128,7 +136,7 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
     for (int c = 0; c < NC; ++c) {
       const double* Uc = a.U + c * comp + (long long)z * plane;
       u_next[c] = (in_xy && z + 1 < nz && (zc || z + 1 < z1)) ? Uc[plane + col] : 0.0;
-      fz[c] = (in_xy && zin) ? a.F[c * comp + (long long)z * plane + col] : 0.0;
+      fz[c] = (MODE == 0 && in_xy && zin) ? a.F[c * comp + (long long)z * plane + col] : 0.0;
       hz[c] = (has_h && h_ok && zin) ? Uc[hoff] : 0.0;
       vz[c] = (has_v && v_ok && zin) ? Uc[voff] : 0.0;
     }
@@ -153,6 +161,7 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
     __syncthreads();
     if (in_xy && zin) {
       double r[NC];
+      double rw = 1.0;  // mode 2: mass weight of the node in sum W R^2
       if (NL == NL_QUASILIN) {
         const double u = uc[0];
         const double ac = 1.0 + u * u;
@@ -190,10 +199,30 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
         if (NL == NL_CUBIC) {
           const double u = uc[0];
           const double m = a.lin + pv;
-          r[0] = lap[0] + a.cub * (u * u * u) + m * u - f[0];
-          const double fu = 3.0 * a.cub * (u * u) + m;
-          mn = fmin(mn, fu);
-          mx = fmax(mx, fu);
+          if constexpr (MODE == 0) {
+            r[0] = lap[0] + a.cub * (u * u * u) + m * u - f[0];
+            const double fu = 3.0 * a.cub * (u * u) + m;
+            mn = fmin(mn, fu);
+            mx = fmax(mx, fu);
+          } else {
+            double wt = 1.0;
+            if constexpr (BC == 1) wt = end_weight(x, nx) * end_weight(y, ny) * end_weight(z, nz);
+            if constexpr (MODE == 1) {
+              const double wu = wt * u;
+              s_r += wu * lap[0];
+              mn += wu * u;
+              mx += wu * u * (u * u);
+              s_f += wu * (m * u);
+            } else {
+              const double lam = a.eig[0], sc = a.eig[1];
+              const double us = sc * u;
+              r[0] = sc * lap[0] + a.cub * (us * us * us) + (m - lam) * us;
+              const double fu = 3.0 * a.cub * (us * us) + (m - lam);
+              mn = fmin(mn, fu);
+              mx = fmax(mx, fu);
+              rw = wt;
+            }
+          }
         } else {
           const double u = uc[0], v = uc[NC - 1];
           r[0] = lap[0] + u * u * u - v - f[0];
@@ -205,13 +234,15 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
           mx = fmax(mx, 0.5 * (ea + ed + disc));
         }
       }
+      if constexpr (MODE != 1) {
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        s_r += r[c] * r[c];
-        const long long o = c * a.r_cstride + (long long)z * a.r_zstride + (long long)y * a.r_ystride + x;
-        put<TO>(a.R, o, r[c]);
+        for (int c = 0; c < NC; ++c) {
+          s_r += rw * (r[c] * r[c]);
+          const long long o = c * a.r_cstride + (long long)z * a.r_zstride + (long long)y * a.r_ystride + x;
+          put<TO>(a.R, o, r[c]);
+        }
       }
-    } else if (out_xy) {
+    } else if (MODE != 1 && out_xy) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const long long o = c * a.r_cstride + (long long)z * a.r_zstride + (long long)y * a.r_ystride + x;
@@ -231,7 +262,7 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
     pv = n_pv;
   }
 
-  block_reduce4<RX * RY / 64>(s_r, mn, mx, s_f);
+  block_reduce4<RX * RY / 64, MODE == 1>(s_r, mn, mx, s_f);
   if (threadIdx.x == 0 && threadIdx.y == 0) {
     double* pp = a.partials + 4LL * tile;  // tile = (bz * gy + by) * gx + bx
     pp[0] = s_r;
@@ -252,7 +283,7 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
 // workgroup so that it still spreads over about a thousand workgroups.
 constexpr int R2X = 256;
 
-template <int NL, typename TO, int BC>
+template <int NL, typename TO, int BC, int MODE = 0>
 __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
   constexpr int NC = (NL == NL_SYS2) ? 2 : 1;
   const int lane = threadIdx.x & 63;
@@ -270,7 +301,7 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
   const bool lh = lane == 0 && x >= 1 && x - 1 < nx;  // left strip edge: load U(x-1)
   const bool rh = lane == 63 && x + 1 < nx;           // right strip edge: load U(x+1)
   const double* Up = a.U + (long long)pl * plane;
-  const double* Fp = a.F + (long long)pl * plane;
+  const double* Fp = MODE == 0 ? a.F + (long long)pl * plane : nullptr;
   auto ld = [&](const double* p, int c, int y, int xx, bool ok) {
     return (ok && y >= 0 && y < ny) ? p[c * comp + (long long)y * nx + xx] : 0.0;
   };
@@ -279,13 +310,14 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
   const double* Pp = has_pot ? a.pot + (long long)pl * plane : nullptr;
 
   double s_r = 0.0, s_f = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
+  if constexpr (MODE == 1) mn = mx = 0.0;  // four sums
   double um[NC], uc[NC], up[NC], f[NC], hl[NC], hr[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     um[c] = ld(Up, c, y0 - 1, x, xin);
     uc[c] = ld(Up, c, y0, x, xin);
     up[c] = ld(Up, c, y0 + 1, x, xin);
-    f[c] = ld(Fp, c, y0, x, xin);
+    f[c] = MODE == 0 ? ld(Fp, c, y0, x, xin) : 0.0;
     hl[c] = ld(Up, c, y0, x - 1, lh);
     hr[c] = ld(Up, c, y0, x + 1, rh);
   }
@@ -296,7 +328,7 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       nup[c] = ld(Up, c, y + 2, x, xin);
-      nf[c] = ld(Fp, c, y + 1, x, xin);
+      nf[c] = MODE == 0 ? ld(Fp, c, y + 1, x, xin) : 0.0;
       nhl[c] = ld(Up, c, y + 1, x - 1, lh);
       nhr[c] = ld(Up, c, y + 1, x + 1, rh);
     }
@@ -319,6 +351,7 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
     const bool in = xin && y < ny;
     if (in) {
       double r[NC];
+      double rw = 1.0;  // mode 2: mass weight of the node in sum W R^2
       if (NL == NL_QUASILIN) {
         const double u = uc[0];
         const double ac = 1.0 + u * u;
@@ -340,10 +373,30 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
         if (NL == NL_CUBIC) {
           const double u = uc[0];
           const double m = a.lin + pv;
-          r[0] = lap[0] + a.cub * (u * u * u) + m * u - f[0];
-          const double fu = 3.0 * a.cub * (u * u) + m;
-          mn = fmin(mn, fu);
-          mx = fmax(mx, fu);
+          if constexpr (MODE == 0) {
+            r[0] = lap[0] + a.cub * (u * u * u) + m * u - f[0];
+            const double fu = 3.0 * a.cub * (u * u) + m;
+            mn = fmin(mn, fu);
+            mx = fmax(mx, fu);
+          } else {
+            double wt = 1.0;
+            if constexpr (BC == 1) wt = end_weight(x, nx) * end_weight(y, ny);
+            if constexpr (MODE == 1) {
+              const double wu = wt * u;
+              s_r += wu * lap[0];
+              mn += wu * u;
+              mx += wu * u * (u * u);
+              s_f += wu * (m * u);
+            } else {
+              const double lam = a.eig[0], sc = a.eig[1];
+              const double us = sc * u;
+              r[0] = sc * lap[0] + a.cub * (us * us * us) + (m - lam) * us;
+              const double fu = 3.0 * a.cub * (us * us) + (m - lam);
+              mn = fmin(mn, fu);
+              mx = fmax(mx, fu);
+              rw = wt;
+            }
+          }
         } else {
           const double u = uc[0], v = uc[NC - 1];
           r[0] = lap[0] + u * u * u - v - f[0];
@@ -357,11 +410,13 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
       }
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        s_r += r[c] * r[c];
-        const long long o = c * a.r_cstride + (long long)pl * a.r_zstride + (long long)y * a.r_ystride + x;
-        put<TO>(a.R, o, r[c]);
+        if constexpr (MODE != 1) {
+          s_r += rw * (r[c] * r[c]);
+          const long long o = c * a.r_cstride + (long long)pl * a.r_zstride + (long long)y * a.r_ystride + x;
+          put<TO>(a.R, o, r[c]);
+        }
       }
-    } else if (xout) {
+    } else if (MODE != 1 && xout) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const long long o = c * a.r_cstride + (long long)pl * a.r_zstride + (long long)y * a.r_ystride + x;
@@ -380,7 +435,7 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
     pv = npv;
   }
 
-  block_reduce4<R2X / 64>(s_r, mn, mx, s_f);
+  block_reduce4<R2X / 64, MODE == 1>(s_r, mn, mx, s_f);
   if (threadIdx.x == 0) {
     double* pp = a.partials + 4LL * tile;  // tile = (pl * gy + by) * gx + bx
     pp[0] = s_r;
@@ -407,19 +462,29 @@ int residual_max_blocks(int ox, int oy, int oz, int rz, bool planar) {
   return (int)(g.x * g.y * g.z);
 }
 
-template <int NL, int BC>
+template <int NL, int BC, int MODE = 0>
 static void launch_nl_bc(const ResidualArgs& a, dim3 g, bool planar, hipStream_t st) {
   if (planar) {
-    if (a.out_prec == 0)
-      hipLaunchKernelGGL((k_residual2d<NL, double, BC>), g, dim3(R2X), 0, st, a);
+    if (a.out_prec == 0 || MODE == 1)
+      hipLaunchKernelGGL((k_residual2d<NL, double, BC, MODE>), g, dim3(R2X), 0, st, a);
     else
-      hipLaunchKernelGGL((k_residual2d<NL, float, BC>), g, dim3(R2X), 0, st, a);
+      hipLaunchKernelGGL((k_residual2d<NL, float, BC, MODE>), g, dim3(R2X), 0, st, a);
     return;
   }
-  if (a.out_prec == 0)
-    hipLaunchKernelGGL((k_residual<NL, double, BC>), g, dim3(RX, RY), 0, st, a);
+  if (a.out_prec == 0 || MODE == 1)
+    hipLaunchKernelGGL((k_residual<NL, double, BC, MODE>), g, dim3(RX, RY), 0, st, a);
   else
-    hipLaunchKernelGGL((k_residual<NL, float, BC>), g, dim3(RX, RY), 0, st, a);
+    hipLaunchKernelGGL((k_residual<NL, float, BC, MODE>), g, dim3(RX, RY), 0, st, a);
+}
+
+template <int BC>
+static void launch_cubic(const ResidualArgs& a, dim3 g, bool planar, hipStream_t st) {
+  if (a.mode == 1)
+    launch_nl_bc<NL_CUBIC, BC, 1>(a, g, planar, st);
+  else if (a.mode == 2)
+    launch_nl_bc<NL_CUBIC, BC, 2>(a, g, planar, st);
+  else
+    launch_nl_bc<NL_CUBIC, BC, 0>(a, g, planar, st);
 }
 
 template <int NL>
@@ -433,11 +498,11 @@ hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t 
   const dim3 g = residual_grid(a.ox, a.oy, a.oz, a.rz, planar);
   *nblocks_out = (int)(g.x * g.y * g.z);
   switch (a.nl) {
-    case NL_CUBIC:  // the only nonlinearity with Neumann data
+    case NL_CUBIC:  // the only nonlinearity with Neumann data and eigenproblem passes
       if (a.bc == 1)
-        launch_nl_bc<NL_CUBIC, 1>(a, g, planar, st);
+        launch_cubic<1>(a, g, planar, st);
       else
-        launch_nl<NL_CUBIC>(a, g, planar, st);
+        launch_cubic<0>(a, g, planar, st);
       break;
     case NL_QUASILIN: launch_nl<NL_QUASILIN>(a, g, planar, st); break;
     default: launch_nl<NL_SYS2>(a, g, planar, st); break;
@@ -490,6 +555,101 @@ hipError_t launch_finalize(const double* partials, int nblocks, DevScalars* sc, 
                            int iter, int max_iter, hipStream_t st, DevScalars* mirror) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, st, partials, nblocks, sc, rule,
                      beta_fixed, lam_min_sum, red_out, rtol, iter, max_iter, mirror);
+  return hipGetLastError();
+}
+
+// Eigenproblem, phase 1: from the sums over the stored iterate U~ (Section
+// 4.4) the normalised iterate is U = s U~ with s = 1 / sqrt(h^d sum W U~^2),
+// and, f(u) = cub u^3 + (lin + V) u being a polynomial in s,
+//   lam = <A U + f(U), U>_M = (sum W (A U~) U~ + sum W (lin + V) U~^2) / sum W U~^2
+//         + cub sum W U~^4 / (h^d (sum W U~^2)^2).
+__global__ __launch_bounds__(FIN_THREADS) void k_eig_finalize1(const double* __restrict__ partials,
+                                                               int nblocks, DevScalars* sc,
+                                                               double cub, double hvol,
+                                                               const int* stop) {
+  if (stop && *stop) return;
+  double au = 0.0, uu = 0.0, u4 = 0.0, vu = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += FIN_THREADS) {
+    au += partials[4 * i + 0];
+    uu += partials[4 * i + 1];
+    u4 += partials[4 * i + 2];
+    vu += partials[4 * i + 3];
+  }
+  block_reduce4<FIN_THREADS / 64, true>(au, uu, u4, vu);
+  if (threadIdx.x == 0) {
+    sc->uscale = 1.0 / sqrt(hvol * uu);
+    sc->eig = (au + vu) / uu + cub * u4 / (hvol * uu * uu);
+  }
+}
+
+hipError_t launch_eig_finalize1(const double* partials, int nblocks, DevScalars* sc, double cub,
+                                double hvol, const int* stop, hipStream_t st) {
+  hipLaunchKernelGGL(k_eig_finalize1, dim3(1), dim3(FIN_THREADS), 0, st, partials, nblocks, sc,
+                     cub, hvol, stop);
+  return hipGetLastError();
+}
+
+// Eigenproblem, phase 2: stopping rule ||F^h(U)||_M / |lam| and the shift.
+__global__ __launch_bounds__(FIN_THREADS) void k_eig_finalize2(
+    const double* __restrict__ partials, int nblocks, DevScalars* sc, int rule, double beta_fixed,
+    double lam_min_sum, double hvol, double* red_out, double rtol, int iter, int max_iter,
+    const int* stop, DevScalars* mirror) {
+  if (stop && *stop) return;
+  double s0 = 0.0, s1 = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
+  for (int i = threadIdx.x; i < nblocks; i += FIN_THREADS) {
+    s0 += partials[4 * i + 0];
+    mn = fmin(mn, partials[4 * i + 1]);
+    mx = fmax(mx, partials[4 * i + 2]);
+    s1 += partials[4 * i + 3];
+  }
+  block_reduce4<FIN_THREADS / 64>(s0, mn, mx, s1);
+  if (threadIdx.x == 0) {
+    DevScalars r = *sc;  // keeps lam and s from phase 1
+    r.scale = 1.0;
+    r.beta = rule == RULE_MIDPOINT ? 0.5 * (mn + mx) : beta_fixed;
+    r.sumsqR = hvol * s0;
+    r.mumin = mn;
+    r.mumax = mx;
+    r.sumsqF = r.eig * r.eig;
+    r.relres = sqrt(hvol * s0) / fabs(r.eig);
+    r.flag = (lam_min_sum + r.beta > 0.0) ? 0.0 : 1.0;
+    const double rr = r.relres;
+    r.done = iter >= 0 && (!(rr <= 1e30) || rr <= rtol || iter >= max_iter || r.flag != 0.0);
+    *sc = r;
+    if (mirror) *mirror = r;
+    if (red_out) {
+      red_out[0] = r.eig;
+      red_out[1] = r.uscale;
+      red_out[2] = r.sumsqR;
+      red_out[3] = mn;
+      red_out[4] = mx;
+      red_out[5] = rr;
+    }
+  }
+}
+
+hipError_t launch_eig_finalize2(const double* partials, int nblocks, DevScalars* sc, int rule,
+                                double beta_fixed, double lam_min_sum, double hvol,
+                                double* red_out, double rtol, int iter, int max_iter,
+                                const int* stop, hipStream_t st, DevScalars* mirror) {
+  hipLaunchKernelGGL(k_eig_finalize2, dim3(1), dim3(FIN_THREADS), 0, st, partials, nblocks, sc,
+                     rule, beta_fixed, lam_min_sum, hvol, red_out, rtol, iter, max_iter, stop,
+                     mirror);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_scale(double* __restrict__ u, long long n,
+                                               const double* s) {
+  const double f = *s;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    u[i] *= f;
+}
+
+hipError_t launch_scale(double* u, long long n, const double* s, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const long long blocks = std::min<long long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(256), 0, st, u, n, s);
   return hipGetLastError();
 }
 
