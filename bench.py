@@ -207,10 +207,10 @@ def e7_inputs(n, a=10.0, b=10.0, device="cuda"):
     return u, f, v
 
 
-def perturbation(n, dim, seed, device="cuda"):
+def perturbation(n, dim, seed, device="cuda", coords=None):
     """synth.polynomial_perturbation on `device` (same coefficients and nodes)."""
     coef = torch.from_numpy(synth.polynomial_coefficients(dim, seed)).to(device)
-    x = torch.from_numpy(synth.node_coords(n)).to(device)
+    x = torch.from_numpy(synth.node_coords(n) if coords is None else coords).to(device)
     powers = torch.stack([x ** e for e in range(coef.shape[0])])  # (degree+1, n)
     pt = powers.t().contiguous()                                   # (n, degree+1)
     if dim == 2:
@@ -317,6 +317,80 @@ def paper_tables(seeds2d, seeds3d):
         del u_ex, f, v
         torch.cuda.empty_cache()
     return out
+
+
+def e8_inputs(n, device="cuda"):
+    """synth.schrodinger_3d on `device`: (V, u_start), shape (n, n, n)."""
+    x = torch.from_numpy(synth.interior_coords(n, -8.0, 8.0)).to(device)
+    w = 100.0 * torch.sin(math.pi * x / 4.0) ** 2 + x * x
+    g = torch.exp(-0.5 * x * x)
+    v = w[:, None, None] + w[None, :, None] + w[None, None, :]
+    u = g[:, None, None] * g[None, :, None] * g[None, None, :]
+    return v, u
+
+
+def eigen_table(seeds):
+    """Table results3D_2 of the paper (Section 6.3 Example 2, eq. ex3d2:
+    alpha = 1600, the lattice-plus-harmonic potential on (-8, 8)^3, Dirichlet
+    data) with the midpoint shift: per size the converged pair U* (from the
+    Gaussian start to ||R||_M/|lam| <= 1e-11), then timed solves from
+    U* + eps p (normalised by the iteration) to 1e-10: eps = 0.1 at 200^3,
+    400^3 and 800^3, and eps = 0.2, 0.3 at 200^3; FP64 transforms, and FP32
+    transforms at 200^3 and 400^3."""
+    rows = []
+    plan = [(200, [0.1, 0.2, 0.3], seeds, ("fp64", "fp32")),
+            (400, [0.1], max(seeds // 3, 2), ("fp64", "fp32")),
+            (800, [0.1], 2, ("fp64",))]
+    for n, epss, k, precs in plan:
+        log(f"eigen table n={n}")
+        shape = (n, n, n)
+        V, u0 = e8_inputs(n)
+        coords = synth.interior_coords(n, -8.0, 8.0)
+        s = Solver(shape, "cubic", beta_mode="midpoint", length=16.0, cub=1600.0, potential=V)
+        s.autotune()
+        Ustar = u0[None].clone()
+        t0 = time.perf_counter()
+        st = s.eigen_iterate(Ustar, rtol=1e-11, max_iter=4000)
+        torch.cuda.synchronize()
+        rec = {"n": n, "unknowns": n ** 3,
+               "converged_pair": {"iters_from_gaussian": st["iters"], "relres": st["relres"],
+                                  "lam": st["lam"], "seconds": round(time.perf_counter() - t0, 3)}}
+        log(f"  n={n} U*: {st['iters']} iterations, lam {st['lam']:.10f}")
+        s.close()
+        U = torch.empty_like(Ustar)
+        for prec in precs:
+            solver = Solver(shape, "cubic", beta_mode="midpoint", length=16.0, cub=1600.0,
+                            potential=V, precision=prec)
+            solver.autotune()
+            U.copy_(Ustar)
+            solver.eigen_iterate(U, rtol=0.0, max_iter=1)  # untimed warm-up of this context
+            for eps in epss:
+                iters, times, lams, bad = [], [], [], 0
+                for seed in range(k):
+                    U.copy_(Ustar)
+                    U[0].add_(perturbation(n, 3, seed, coords=coords), alpha=eps)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    st = solver.eigen_iterate(U, rtol=1e-10, max_iter=6000)
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t0)
+                    iters.append(st["iters"])
+                    lams.append(st["lam"])
+                    bad += st["status"] != 0
+                key = f"eps{eps:g}_{prec}"
+                rec[key] = {"iters_mean": round(float(np.mean(iters)), 2),
+                            "iters_std": round(float(np.std(iters)), 2),
+                            "time_mean_s": round(float(np.mean(times)), 4),
+                            "time_median_s": round(float(np.median(times)), 4),
+                            "lam_spread": float(max(lams) - min(lams)), "lam": lams[0],
+                            "not_converged": bad, "seeds": k}
+                log(f"  n={n} {key}: iters {rec[key]['iters_mean']} +- {rec[key]['iters_std']}, "
+                    f"median {rec[key]['time_median_s']} s, lam {lams[0]:.10f}")
+            solver.close()
+        rows.append(rec)
+        del V, u0, Ustar, U
+        torch.cuda.empty_cache()
+    return rows
 
 
 def cpu_baseline(n, amp):
@@ -427,6 +501,11 @@ def main():
                          "3D 200^3-800^3, perturbed starts)")
     ap.add_argument("--table-seeds", type=int, default=20,
                     help="perturbations per 2D size and at 200^3 (fewer at 400^3 and 800^3)")
+    ap.add_argument("--eigen-table", action="store_true",
+                    help="also run the paper's nonlinear eigenproblem table (eq. ex3d2 at "
+                         "200^3, 400^3 and 800^3 from perturbed converged pairs)")
+    ap.add_argument("--eigen-seeds", type=int, default=10,
+                    help="perturbations per scale at 200^3 (a third at 400^3, 2 at 800^3)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--batched-count", type=int, default=512)
@@ -562,6 +641,9 @@ def main():
         out["amplitude_sweep"] = amplitude_sweep(n, args.ttt_runs)
     if args.paper_tables:
         out["paper_tables"] = paper_tables(args.table_seeds, args.table_seeds)
+        torch.cuda.empty_cache()
+    if args.eigen_table:
+        out["eigen_table"] = eigen_table(args.eigen_seeds)
         torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_count)

@@ -27,3 +27,15 @@ def test_device_generators_match_synth(n):
             np.testing.assert_allclose(bench.perturbation(n, dim, seed, device="cpu").numpy(),
                                        synth.polynomial_perturbation(n, dim, seed),
                                        rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("n", [5, 12])
+def test_eigen_inputs_match_synth(n):
+    v, u = bench.e8_inputs(n, device="cpu")
+    v2, u2 = synth.schrodinger_3d(n)
+    np.testing.assert_allclose(v.numpy(), v2, rtol=1e-15, atol=1e-12)
+    np.testing.assert_allclose(u.numpy(), u2, rtol=1e-15, atol=1e-300)
+    c = synth.interior_coords(n, -8.0, 8.0)
+    np.testing.assert_allclose(bench.perturbation(n, 3, 2, device="cpu", coords=c).numpy(),
+                               synth.polynomial_perturbation(n, 3, 2, coords=c),
+                               rtol=0, atol=1e-14)
