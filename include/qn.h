@@ -115,6 +115,20 @@ typedef struct {
  *   and FP32 precisions. */
 typedef enum { QN_BC_DIRICHLET = 0, QN_BC_NEUMANN = 1 } qn_boundary;
 
+/* Discretisation of -Lap:
+ * QN_DISC_FD: second-order finite differences (Section 3.2), as above.
+ * QN_DISC_SEM: Q^k spectral elements with Gauss-Lobatto nodes (Section 3.1 and
+ *   its remark on Gauss-Lobatto integration): per axis E equal elements of
+ *   order k = sem_order (1..8) on the side L; the unknowns are the E k - 1
+ *   interior nodes (Dirichlet) or all E k + 1 nodes (Neumann), so n must be of
+ *   that form (n <= 1025).  The mass matrix is diagonal and the nonlinearity
+ *   acts node by node, so F^h(U) = A_h U + f(U) - F with A_h the Kronecker sum
+ *   of H = M^-1 S; H = T Lam T^-1 through the symmetric M^-1/2 S M^-1/2
+ *   (Section 4.2), computed on the host at setup by Jacobi rotations on its
+ *   even and odd halves.  QN_NL_CUBIC with FP64 or FP32 transforms only; not
+ *   for the eigenproblem. */
+typedef enum { QN_DISC_FD = 0, QN_DISC_SEM = 1 } qn_discretization;
+
 /* precision: qn_precision; beta_mode: qn_beta_mode; timing: nonzero records
  * HIP events around every kernel launch (see qn_timing_*); boundary:
  * qn_boundary; stream: a hipStream_t, NULL = default stream; length: the
@@ -130,7 +144,9 @@ typedef enum { QN_BC_DIRICHLET = 0, QN_BC_NEUMANN = 1 } qn_boundary;
  *   layout ([nz,] ny, nx); read by every qn_residual and qn_iterate call;
  *   owned by the caller, who keeps it valid and unchanged while the context
  *   is in use.
- * The other nonlinearities need lin = 0, cub in {0, 1} and potential = NULL. */
+ * The other nonlinearities need lin = 0, cub in {0, 1} and potential = NULL.
+ * discretization: qn_discretization (0: finite differences); sem_order: the
+ *   element order k of QN_DISC_SEM. */
 typedef struct {
   int32_t precision;
   int32_t beta_mode;
@@ -141,6 +157,8 @@ typedef struct {
   double lin;
   double cub;
   const double* potential;
+  int32_t discretization;
+  int32_t sem_order;
 } qn_options;
 
 /* iters: solves performed; status: the qn_status qn_iterate returned;
@@ -170,8 +188,10 @@ typedef struct qn_ctx_s* qn_ctx;
  * QN_BETA_MIDPOINT with QN_NL_QUASILIN, a non-positive or non-finite length,
  * a non-finite lin or cub, a nonzero lin, a cub other than 0 or 1 or a
  * potential with a nonlinearity other than QN_NL_CUBIC, n < 2 with
- * QN_BC_NEUMANN; QN_ERR_UNSUPPORTED for QN_BC_NEUMANN
- * with another nonlinearity than QN_NL_CUBIC or a split-bf16 precision. */
+ * QN_BC_NEUMANN, an unknown discretization, a sem_order outside 1..8 or an n
+ * that is not a spectral element grid; QN_ERR_UNSUPPORTED for QN_BC_NEUMANN
+ * or QN_DISC_SEM with another nonlinearity than QN_NL_CUBIC or a split-bf16
+ * precision. */
 qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity,
                    const qn_options* opt, qn_ctx* out);
 

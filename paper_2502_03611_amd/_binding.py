@@ -34,10 +34,12 @@ class QNGrid(ctypes.Structure):
 class QNOptions(ctypes.Structure):
     _fields_ = [("precision", c_i32), ("beta_mode", c_i32), ("timing", c_i32),
                 ("boundary", c_i32), ("stream", c_vp), ("length", c_dbl), ("lin", c_dbl),
-                ("cub", c_dbl), ("potential", c_vp)]
+                ("cub", c_dbl), ("potential", c_vp), ("discretization", c_i32),
+                ("sem_order", c_i32)]
 
 
 BOUNDARIES = {"dirichlet": 0, "neumann": 1}
+DISCRETIZATIONS = {"fd": 0, "sem": 1}
 
 
 class QNStats(ctypes.Structure):
@@ -117,14 +119,17 @@ class Solver:
 
     def __init__(self, shape, nonlinearity="cubic", beta=0.0, beta_mode="fixed",
                  precision="fp64", timing=False, device="cuda", boundary="dirichlet",
-                 length=None, lin=0.0, cub=1.0, potential=None):
+                 length=None, lin=0.0, cub=1.0, potential=None, discretization="fd",
+                 sem_order=0):
         """boundary: "dirichlet" (n interior nodes per axis, h = L/(n+1)) or
         "neumann" (n nodes including both ends, zero normal derivative,
         h = L/(n-1)); length: the domain side L (default 1 for Dirichlet, 2 for
         Neumann, i.e. [-1, 1]).  Cubic problem only: lin, cub, potential give
         -Lap u + lin u + cub u^3 + V u = f; potential: None or a float64
         device tensor V of the grid's shape, kept referenced by the solver
-        (the library reads it on every residual)."""
+        (the library reads it on every residual).  discretization: "fd" or "sem"
+        (Q^k spectral elements of order sem_order; n = E k - 1 interior nodes for
+        Dirichlet data, E k + 1 for Neumann data)."""
         L = lib()
         self.shape = tuple(int(s) for s in shape)
         self.dim = len(self.shape)
@@ -145,6 +150,8 @@ class Solver:
         o.length = float(length if length is not None else (2.0 if boundary == "neumann" else 1.0))
         o.lin = float(lin)
         o.cub = float(cub)
+        o.discretization = DISCRETIZATIONS[discretization]
+        o.sem_order = int(sem_order)
         self._potential = None
         if potential is not None:
             if (potential.dtype != torch.float64 or tuple(potential.shape) != self.shape

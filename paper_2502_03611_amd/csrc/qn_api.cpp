@@ -98,6 +98,10 @@ struct qn_ctx_s {
   int bc = QN_BC_DIRICHLET;
   double length = 1.0, lin = 0.0, cub = 1.0;
   double hvol = 1.0;  // h^d: the mass of one interior node
+  int sem_k = 0;      // spectral elements: element order (0: finite differences)
+  std::vector<double> hHb[3];  // spectral elements: banded H per axis
+  size_t off_Hb[3] = {0, 0, 0};
+  double sem_lmin[3] = {0.0, 0.0, 0.0};
   const double* pot = nullptr;  // caller-owned potential V, or NULL
   double ih2[3] = {1.0, 1.0, 0.0};  // h^-2 per axis (0 for the missing z of 2D)
   hipStream_t stream = nullptr;
@@ -281,7 +285,14 @@ ResidualArgs residual_args(qn_ctx c, const double* U, const double* F, double* R
   a.bc = c->bc;
   a.partials = c->at<double>(c->off_part);
   a.rz = c->dim == 3 ? RESIDUAL_RZ : residual_planar_rows(a.ox, a.oy);
+  a.sem_k = c->sem_k;
+  for (int i = 0; i < c->dim && c->sem_k > 0; ++i) a.hb[i] = c->at<double>(c->off_Hb[i]);
   return a;
+}
+
+// The residual launch of the context's discretization.
+hipError_t launch_any_residual(const ResidualArgs& a, int* nb, hipStream_t st) {
+  return a.sem_k > 0 ? launch_sem_residual(a, nb, st) : launch_residual(a, nb, st);
 }
 
 // Residual of U into the padded transform workspace W1 (+ partials), then
@@ -292,7 +303,7 @@ hipError_t residual_into_ws(qn_ctx c, const double* U, const double* F, double* 
   ResidualArgs a = residual_args(c, U, F, nullptr);
   a.stop = stop;
   int nb = 0;
-  hipError_t e = timed(c, K_RESIDUAL, [&] { return launch_residual(a, &nb, c->stream); });
+  hipError_t e = timed(c, K_RESIDUAL, [&] { return launch_any_residual(a, &nb, c->stream); });
   if (e != hipSuccess) return e;
   return timed(c, K_FINALIZE, [&] {
     return launch_finalize(a.partials, nb, c->scal(), rule_of(c), c->beta, c->lam_min_sum, red_out,
@@ -553,6 +564,26 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
     for (int a = 0; a < grid->dim; ++a)
       if (grid->n[a] < 2) return fail(QN_ERR_INVALID, "Neumann data needs n >= 2 per axis");
   }
+  if (o.discretization != QN_DISC_FD && o.discretization != QN_DISC_SEM)
+    return fail(QN_ERR_INVALID, "unknown discretization");
+  if (o.discretization == QN_DISC_SEM) {
+    if (nonlinearity != QN_NL_CUBIC)
+      return fail(QN_ERR_UNSUPPORTED, "spectral elements are supported for QN_NL_CUBIC only");
+    if (o.precision != QN_PREC_FP64 && o.precision != QN_PREC_FP32)
+      return fail(QN_ERR_UNSUPPORTED, "spectral elements need FP64 or FP32 transforms");
+    const int k = o.sem_order;
+    if (k < 1 || k > 8) return fail(QN_ERR_INVALID, "sem_order = %d out of range [1, 8]", k);
+    for (int a = 0; a < grid->dim; ++a) {
+      const int n = grid->n[a];
+      const bool neu = o.boundary == QN_BC_NEUMANN;
+      const int rem = neu ? (n - 1) % k : (n + 1) % k;
+      const int elements = neu ? (n - 1) / k : (n + 1) / k;
+      if (rem != 0 || elements < 1 || n < 1 || n > 1025)
+        return fail(QN_ERR_INVALID,
+                    "n[%d] = %d is not E k %s 1 nodes with E >= 1 elements of order %d "
+                    "(and at most 1025)", a, n, neu ? "+" : "-", k);
+    }
+  }
 
   qn_ctx c = new qn_ctx_s();
   c->dim = grid->dim;
@@ -572,6 +603,7 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   c->lin = o.lin;
   c->cub = cub;
   c->pot = o.potential;
+  c->sem_k = o.discretization == QN_DISC_SEM ? o.sem_order : 0;
   c->lam_min_sum = 0.0;
   for (int a = 0; a < 3; ++a) {
     if (a >= c->dim) {
@@ -584,6 +616,29 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
     const double ih = (c->bc == QN_BC_NEUMANN ? n - 1 : n + 1) / length;
     c->ih2[a] = ih * ih;
     c->hvol /= ih;
+    if (c->sem_k > 0) {  // spectral elements: Jacobi on the even and odd halves
+      const int k = c->sem_k, bk = fold_block(n);
+      const int elements = c->bc == QN_BC_NEUMANN ? (n - 1) / k : (n + 1) / k;
+      c->ax[a] = FoldAxis{n, n / 2, n & 1, bk};
+      c->p[a] = 2 * bk;
+      int same = -1;  // an earlier axis of the same length has the same data
+      for (int b = 0; b < a; ++b)
+        if (c->n[b] == n) same = b;
+      if (same >= 0) {
+        c->hS[a] = c->hS[same];
+        c->hlam[a] = c->hlam[same];
+        c->hHb[a] = c->hHb[same];
+        c->lam_min_sum += c->sem_lmin[same];
+        c->sem_lmin[a] = c->sem_lmin[same];
+        continue;
+      }
+      std::vector<double> m, S;
+      sem_axis(elements, k, length, c->bc == QN_BC_NEUMANN, m, S);
+      c->sem_lmin[a] = fold_sem(n, m, S, bk, c->hS[a], c->hlam[a]);
+      c->lam_min_sum += c->sem_lmin[a];
+      sem_band(n, k, m, S, c->hHb[a]);
+      continue;
+    }
     if (c->fold) {
       const int bk = fold_block(n);
       c->ax[a] = FoldAxis{n, n / 2, n & 1, bk};
@@ -626,6 +681,10 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
     }
     c->off_lam[a] = off;
     off += align256((size_t)c->p[a] * 8);
+    if (c->sem_k > 0) {
+      c->off_Hb[a] = off;
+      off += align256(c->hHb[a].size() * 8);
+    }
   }
   if (c->dim == 2) {  // unused z axis aliases y (never read)
     c->off_S[2] = c->off_S[1];
@@ -646,6 +705,9 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
     c->max_blocks = std::max(
         residual_max_blocks(c->p[0], c->p[1], 1, residual_planar_rows(c->p[0], c->p[1]), true),
         residual_max_blocks(c->n[0], c->n[1], 1, residual_planar_rows(c->n[0], c->n[1]), true));
+  if (c->sem_k > 0)
+    c->max_blocks = std::max({c->max_blocks, sem_residual_blocks(c->p[0], c->p[1], c->p[2]),
+                              sem_residual_blocks(c->n[0], c->n[1], c->n[2])});
   c->off_part = off;
   off += align256((size_t)c->max_blocks * 4 * sizeof(double));
   c->off_scal = off;
@@ -714,6 +776,9 @@ qn_status qn_bind_workspace(qn_ctx c, void* d_ws, size_t bytes) {
     if (e == hipSuccess)
       e = hipMemcpyAsync(c->ws + c->off_lam[a], c->hlam[a].data(), (size_t)c->p[a] * 8,
                          hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && c->sem_k > 0)
+      e = hipMemcpyAsync(c->ws + c->off_Hb[a], c->hHb[a].data(), c->hHb[a].size() * 8,
+                         hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "upload eigen-data");
   }
   // hS/hlam stay alive in the context, so the async uploads above are safe.
@@ -735,7 +800,7 @@ qn_status qn_residual(qn_ctx c, const double* d_U, const double* d_F, double* d_
   if (d_R == d_U) return fail(QN_ERR_INVALID, "R may not alias U");
   ResidualArgs a = residual_args(c, d_U, d_F, d_R);
   int nb = 0;
-  hipError_t e = timed(c, K_RESIDUAL, [&] { return launch_residual(a, &nb, c->stream); });
+  hipError_t e = timed(c, K_RESIDUAL, [&] { return launch_any_residual(a, &nb, c->stream); });
   if (e == hipSuccess)
     e = timed(c, K_FINALIZE, [&] {
       return launch_finalize(a.partials, nb, c->scal(), rule_of(c), c->beta, c->lam_min_sum, d_red,
@@ -843,8 +908,9 @@ qn_status qn_iterate(qn_ctx c, double* d_U, const double* d_F, double rtol, int3
 static qn_status eigen_check(qn_ctx c) {
   qn_status s = check_ctx(c, true);
   if (s != QN_OK) return s;
-  if (c->nl != QN_NL_CUBIC || !c->fold)
-    return fail(QN_ERR_UNSUPPORTED, "the eigenproblem needs QN_NL_CUBIC with FP64 or FP32 transforms");
+  if (c->nl != QN_NL_CUBIC || !c->fold || c->sem_k > 0)
+    return fail(QN_ERR_UNSUPPORTED, "the eigenproblem needs QN_NL_CUBIC with finite "
+                                    "differences and FP64 or FP32 transforms");
   return QN_OK;
 }
 

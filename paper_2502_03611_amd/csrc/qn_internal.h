@@ -154,8 +154,17 @@ struct ResidualArgs {
   //   partials {sum W R^2, min mu, max mu, 0}, mu = 3 cub (sU)^2 + lin + V - lam.
   int mode = 0;
   const double* eig = nullptr;
+  // Spectral elements (sem_k > 0: element order): banded H = M^-1 S per axis,
+  // hb[a][j * (2k + 1) + d + k] = H[j][j + d]; the cubic problem only.
+  int sem_k = 0;
+  const double* hb[3] = {nullptr, nullptr, nullptr};
 };
 hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t st);
+// Spectral element residual (qn_sem.hip): same outputs and partials as
+// launch_residual for the cubic problem; SEM_ROWS rows of 256 nodes per workgroup.
+constexpr int SEM_ROWS = 8;
+hipError_t launch_sem_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t st);
+int sem_residual_blocks(int ox, int oy, int oz);
 // Eigenproblem finalizes (one workgroup each; return at once when *stop != 0).
 // Phase 1 reduces the mode-1 sums into sc->eig = lam and sc->uscale = s
 // (hvol = h^d, the mass of one interior node).  Phase 2 reduces the mode-2

@@ -93,6 +93,15 @@ def opts(**kw):
     (dict(potential=4096), 1, 1, (9, 9, 9), 0.0, "invalid"),   # potential only for cubic
     (dict(potential=4096), 2, 2, (9, 9, 9), 0.0, "invalid"),
     (dict(boundary=1, lin=10.0, cub=10.0, potential=4096), 0, 1, (9, 9, 9), 1.0, "ok"),
+    # spectral elements (host-side setup: Gauss-Lobatto nodes, Jacobi eigen-data)
+    (dict(discretization=1, sem_order=2), 0, 1, (11, 11, 11), 0.0, "ok"),
+    (dict(discretization=1, sem_order=3, boundary=1), 0, 1, (10, 13, 7), 1.0, "ok"),
+    (dict(discretization=1, sem_order=2), 0, 1, (10, 11, 11), 0.0, "invalid"),  # 10 + 1 odd
+    (dict(discretization=1, sem_order=9), 0, 1, (17, 17, 17), 0.0, "invalid"),
+    (dict(discretization=1, sem_order=2), 0, 1, (1027, 11, 11), 0.0, "invalid"),  # > 1025
+    (dict(discretization=2), 0, 1, (9, 9, 9), 0.0, "invalid"),
+    (dict(discretization=1, sem_order=2), 1, 1, (11, 11, 11), 0.0, "unsupported"),
+    (dict(discretization=1, sem_order=2, precision=2), 0, 1, (11, 11, 11), 0.0, "unsupported"),
 ])
 def test_setup_boundary_length_and_pointwise_terms(kw, nl, ncomp, n, beta, want):
     dim = 2 if n[2] == 1 else 3

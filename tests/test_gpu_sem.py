@@ -1,0 +1,144 @@
+"""GPU parity of the Q^k spectral element path (Section 3.1; Section 4.2) against
+the FP64 oracle (oracle/sem.py).  The tensor-product solve reuses the folded
+mode-product kernels with eigen-data from the even and odd halves of
+M^-1/2 S M^-1/2; the residual is the banded H = M^-1 S kernel.  Tolerances as
+for the finite-difference path: residual <= 1e-13 of the cancelling terms,
+solve rel L2 <= max(1e-12, 1e-15 kappa) (FP64; kappa the condition number of
+the shifted operator) and <= 3e-5 (FP32 transforms), iterate equal counts
+then exactly K solves to <= 1e-12."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import sem
+from paper_2502_03611_amd import Solver, QN_OK, QN_ERR_NOT_CONVERGED
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def elements(n, k, bc):
+    return (n - 1) // k if bc == "neumann" else (n + 1) // k
+
+
+def ops_for(shape, k, bc, length):
+    return [sem.axis_operator(elements(n, k, bc), k, length, bc) for n in shape]
+
+
+def solver(shape, k, bc, length, **kw):
+    kw.setdefault("beta", 1.0)
+    return Solver(shape, "cubic", boundary=bc, length=length, discretization="sem", sem_order=k,
+                  **kw)
+
+
+CASES = [("dirichlet", (11, 15), 2, 1.0), ("dirichlet", (31, 7), 4, 2.0),
+         ("neumann", (13, 10), 3, 2.0), ("neumann", (9, 17, 21), 4, 1.0),
+         ("dirichlet", (5, 11, 23), 3, 1.0), ("dirichlet", (9, 9, 9), 1, 1.0),
+         ("neumann", (65, 33), 2, 1.0)]
+
+
+@pytest.mark.parametrize("bc,shape,k,length", CASES)
+def test_sem_residual_parity(bc, shape, k, length):
+    print(f"sem residual {bc} {shape} k={k}", flush=True)
+    u = synth.random_field((1,) + shape, 501)
+    f = synth.random_field((1,) + shape, 502, scale=10.0)
+    v = np.abs(synth.random_field(shape, 503, scale=20.0))
+    s = solver(shape, k, bc, length, lin=0.5, cub=2.0, potential=dev(v))
+    red = torch.zeros(4, dtype=torch.float64, device="cuda")
+    r = host(s.residual(dev(u), dev(f), red=red))[0]
+    ops_ = ops_for(shape, k, bc, length)
+    ref = sem.residual_cubic(u[0], f[0], ops_, 0.5, 2.0, v)
+    scale = (np.linalg.norm(sem.apply_a(u[0], ops_)) + 2.0 * np.linalg.norm(u[0] ** 3) +
+             np.linalg.norm((v + 0.5) * u[0]) + np.linalg.norm(f[0]))
+    assert np.linalg.norm(r - ref) / scale <= 1e-13
+    red = red.cpu().numpy()
+    fu = sem.fu_cubic(u[0], 0.5, 2.0, v)
+    assert red[0] == pytest.approx(float(np.sum(ref * ref)), rel=1e-10)
+    assert red[1] == pytest.approx(float(fu.min()), rel=1e-13)
+    assert red[2] == pytest.approx(float(fu.max()), rel=1e-13)
+    assert red[3] == pytest.approx(float(np.sum(f[0] ** 2)), rel=1e-12)
+
+
+@pytest.mark.parametrize("bc,shape,k,length", CASES)
+def test_sem_fdm_solve_parity(bc, shape, k, length):
+    print(f"sem solve {bc} {shape} k={k}", flush=True)
+    r = synth.random_field((1,) + shape, 504)
+    x = host(solver(shape, k, bc, length).fdm_solve(dev(r), 1.5, 0.75))[0]
+    ops_ = ops_for(shape, k, bc, length)
+    ref = sem.fdm_solve(r[0], ops_, 0.75, 1.5)
+    # Two backward-stable eigenbases give solutions that differ by about
+    # u kappa(1.5 A_h + 0.75 I); with Neumann data (lam_0 = 0) and the large
+    # lam_max of Q^k, kappa reaches 6e4 here (the oracle itself is 6e-12 from a
+    # dense direct solve at that kappa).
+    kappa = ((1.5 * sum(o[4].max() for o in ops_) + 0.75) /
+             (1.5 * sum(o[4].min() for o in ops_) + 0.75))
+    assert rel(x, ref) <= max(1e-12, 1e-15 * kappa)
+    x32 = host(solver(shape, k, bc, length, precision="fp32").fdm_solve(dev(r), 1.5, 0.75))[0]
+    assert rel(x32, ref) <= 3e-5
+
+
+@pytest.mark.parametrize("bc,n,k", [("dirichlet", 31, 2), ("dirichlet", 23, 4),
+                                    ("neumann", 28, 3)])
+def test_sem_iterate_parity(bc, n, k):
+    """-Lap u + u^3 = f with a smooth manufactured u on the spectral element
+    nodes (3D), midpoint shift (Dirichlet) or beta = 1 (Neumann, lin = 1):
+    equal counts, then exactly K solves."""
+    print(f"sem iterate {bc} {n} k={k}", flush=True)
+    ops_ = ops_for((n, n, n), k, bc, 1.0)
+    x = ops_[0][0]
+    if bc == "dirichlet":
+        g = np.sin(math.pi * x)
+        u = g[:, None, None] * g[None, :, None] * g[None, None, :] * 2.0
+        f = 3 * math.pi ** 2 * u + u ** 3
+        kw, okw = dict(beta_mode="midpoint"), dict(midpoint=True)
+    else:
+        g = np.cos(math.pi * x)
+        u = g[:, None, None] + g[None, :, None] + g[None, None, :]
+        f = math.pi ** 2 * u + u ** 3 + u
+        kw, okw = dict(beta_mode="midpoint", lin=1.0), dict(midpoint=True, lin=1.0)
+    ref = sem.qn_solve(f, ops_, **okw)
+    assert ref["converged"]
+    s = solver((n, n, n), k, bc, 1.0, **kw)
+    U = torch.zeros((1, n, n, n), dtype=torch.float64, device="cuda")
+    st = s.iterate(U, dev(f[None]), rtol=1e-10, max_iter=200)
+    assert st["status"] == QN_OK and st["iters"] == ref["iters"], (st, ref["iters"])
+    kk = ref["iters"]
+    U.zero_()
+    st2 = s.iterate(U, dev(f[None]), rtol=0.0, max_iter=kk)
+    assert st2["status"] == QN_ERR_NOT_CONVERGED and st2["iters"] == kk
+    assert rel(host(U)[0], ref["u"]) <= 1e-12
+    # high order: the nodal error of Q^k is far below second-order FD at this size
+    assert np.abs(host(U)[0] - u).max() <= 0.05 * (1.0 / n) ** 2
+
+
+def test_sem_validation():
+    from paper_2502_03611_amd._binding import QNError
+    for shape, k, bc in [((10, 11), 2, "dirichlet"),   # 10 + 1 not a multiple of 2
+                         ((11, 12), 2, "neumann"),     # 12 - 1 not a multiple of 2
+                         ((11, 11), 9, "dirichlet"),   # order out of range
+                         ((11, 11), 0, "dirichlet")]:
+        with pytest.raises(QNError):
+            solver(shape, k, bc, 1.0)
+    with pytest.raises(QNError):
+        solver((11, 11), 2, "dirichlet", 1.0, precision="bf16x3")
+    with pytest.raises(QNError):
+        Solver((11, 11), "quasilinear", discretization="sem", sem_order=2)
+    s = solver((11, 11, 11), 2, "dirichlet", 1.0)
+    with pytest.raises(QNError):
+        s.eigen_iterate(torch.ones((1, 11, 11, 11), dtype=torch.float64, device="cuda"))
