@@ -195,6 +195,12 @@ typedef struct qn_ctx_s* qn_ctx;
 qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity,
                    const qn_options* opt, qn_ctx* out);
 
+/* Coordinates of the unknowns along one axis (0 x, 1 y, 2 z), measured from
+ * one end of the side L: Dirichlet finite differences (i + 1) h, Neumann
+ * finite differences i h, spectral elements the Gauss-Lobatto nodes of the
+ * elements (Section 3.1).  x: host array of n[axis] doubles.  Host only. */
+qn_status qn_nodes(qn_ctx ctx, int32_t axis, double* x);
+
 /* Bytes of device workspace the context needs (written to *bytes). */
 qn_status qn_workspace_bytes(qn_ctx ctx, size_t* bytes);
 

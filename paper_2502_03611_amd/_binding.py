@@ -5,6 +5,7 @@ device memory (caller tensors and the workspace) and the current stream."""
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -80,6 +81,7 @@ def lib():
     L.qn_eigen_residual.argtypes = [c_vp, c_vp, c_vp, c_vp]
     L.qn_eigen_iterate.argtypes = [c_vp, c_vp, c_dbl, c_i32, ctypes.POINTER(QNStats),
                                    ctypes.POINTER(c_dbl)]
+    L.qn_nodes.argtypes = [c_vp, c_i32, c_vp]
     L.qn_autotune.argtypes = [c_vp]
     L.qn_tile_info.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i32)]
     L.qn_set_tile.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i32)]
@@ -90,7 +92,7 @@ def lib():
     for name in ("qn_setup", "qn_workspace_bytes", "qn_bind_workspace", "qn_set_stream",
                  "qn_residual", "qn_fdm_solve", "qn_iterate", "qn_timing_count",
                  "qn_timing_read", "qn_timing_reset", "qn_autotune", "qn_tile_info",
-                 "qn_set_tile", "qn_eigen_residual", "qn_eigen_iterate"):
+                 "qn_set_tile", "qn_eigen_residual", "qn_eigen_iterate", "qn_nodes"):
         getattr(L, name).restype = c_i32
     _lib = L
     return L
@@ -221,6 +223,14 @@ class Solver:
         return {"status": status, "iters": st.iters, "relres": st.relres, "relres0": st.relres0,
                 "beta_last": st.beta_last, "scale_last": st.scale_last, "seconds": st.seconds,
                 "message": last_error() if status != QN_OK else ""}
+
+    def nodes(self, axis):
+        """Coordinates of the unknowns along array axis `axis` (C order: the last
+        axis is x), measured from one end of the side."""
+        n = self.shape[axis]
+        x = (c_dbl * n)()
+        check(lib().qn_nodes(self._ctx, self.dim - 1 - axis, x))
+        return np.frombuffer(x, dtype=np.float64).copy()
 
     def eigen_residual(self, U, R=None, out=None):
         """Eigenproblem residual at U / ||U||_M (U unchanged): R = A_h U + f(U) - lam U;

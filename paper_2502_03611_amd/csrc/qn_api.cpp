@@ -102,6 +102,7 @@ struct qn_ctx_s {
   std::vector<double> hHb[3];  // spectral elements: banded H per axis
   size_t off_Hb[3] = {0, 0, 0};
   double sem_lmin[3] = {0.0, 0.0, 0.0};
+  std::vector<double> hx[3];  // node coordinates per axis, from one end of the side
   const double* pot = nullptr;  // caller-owned potential V, or NULL
   double ih2[3] = {1.0, 1.0, 0.0};  // h^-2 per axis (0 for the missing z of 2D)
   hipStream_t stream = nullptr;
@@ -625,6 +626,7 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
       for (int b = 0; b < a; ++b)
         if (c->n[b] == n) same = b;
       if (same >= 0) {
+        c->hx[a] = c->hx[same];
         c->hS[a] = c->hS[same];
         c->hlam[a] = c->hlam[same];
         c->hHb[a] = c->hHb[same];
@@ -633,12 +635,14 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
         continue;
       }
       std::vector<double> m, S;
-      sem_axis(elements, k, length, c->bc == QN_BC_NEUMANN, m, S);
+      sem_axis(elements, k, length, c->bc == QN_BC_NEUMANN, m, S, &c->hx[a]);
       c->sem_lmin[a] = fold_sem(n, m, S, bk, c->hS[a], c->hlam[a]);
       c->lam_min_sum += c->sem_lmin[a];
       sem_band(n, k, m, S, c->hHb[a]);
       continue;
     }
+    c->hx[a].resize((size_t)n);
+    for (int i = 0; i < n; ++i) c->hx[a][i] = (c->bc == QN_BC_NEUMANN ? i : i + 1) / ih;
     if (c->fold) {
       const int bk = fold_block(n);
       c->ax[a] = FoldAxis{n, n / 2, n & 1, bk};
@@ -903,6 +907,13 @@ qn_status qn_iterate(qn_ctx c, double* d_U, const double* d_F, double rtol, int3
   }
   st.seconds = elapsed();
   return finish(hip_fail(c, e, "iteration"));
+}
+
+qn_status qn_nodes(qn_ctx c, int32_t axis, double* x) {
+  if (!c || !x) return fail(QN_ERR_INVALID, "null argument");
+  if (axis < 0 || axis >= c->dim) return fail(QN_ERR_INVALID, "axis %d out of range", axis);
+  std::memcpy(x, c->hx[axis].data(), c->hx[axis].size() * sizeof(double));
+  return QN_OK;
 }
 
 static qn_status eigen_check(qn_ctx c) {

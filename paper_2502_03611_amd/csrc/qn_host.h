@@ -174,7 +174,7 @@ inline void gl_nodes(int k, std::vector<double>& x, std::vector<double>& w) {
 // stiffness S of the unknown nodes (Dirichlet: the E k - 1 interior nodes;
 // Neumann: all E k + 1).
 inline void sem_axis(int elements, int k, double length, bool neumann, std::vector<double>& m,
-                     std::vector<double>& S) {
+                     std::vector<double>& S, std::vector<double>* nodes = nullptr) {
   std::vector<double> xi, w;
   gl_nodes(k, xi, w);
   const int nq = k + 1;
@@ -209,6 +209,13 @@ inline void sem_axis(int elements, int k, double length, bool neumann, std::vect
       }
     }
   const int lo = neumann ? 0 : 1, n = neumann ? ntot : ntot - 2;
+  if (nodes) {
+    nodes->assign((size_t)n, 0.0);
+    for (int i = 0; i < n; ++i) {
+      const int g = lo + i, e = std::min(g / k, elements - 1), q = g - e * k;
+      (*nodes)[i] = (2.0 * e + 1.0 + xi[q]) * jac;
+    }
+  }
   m.assign((size_t)n, 0.0);
   S.assign((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i) {

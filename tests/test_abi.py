@@ -251,3 +251,35 @@ def test_qnb_layout_covers_pool_exactly():
     assert L.qnb_instance_layout(ctx, len(n), ctypes.byref(off), ctypes.byref(cs)) == qn.QN_ERR_INVALID
     assert L.qnb_iterate(ctx, None, None, 1e-10, 10, 4, None) == qn.QN_ERR_WORKSPACE
     L.qnb_destroy(ctx)
+
+
+@pytest.mark.parametrize("kw,n,bc", [(dict(), (9, 12, 7), "dirichlet"),
+                                     (dict(boundary=1, length=2.0), (9, 12, 7), "neumann"),
+                                     (dict(discretization=1, sem_order=3), (11, 8, 5), "dirichlet"),
+                                     (dict(discretization=1, sem_order=2, boundary=1,
+                                           length=3.0), (9, 13, 5), "neumann")])
+def test_node_coordinates(kw, n, bc):
+    """qn_nodes (host only) against the definitions: finite-difference nodes
+    (i + 1) h or i h, and the spectral element Gauss-Lobatto nodes of the
+    oracle."""
+    import numpy as np
+    from oracle import sem
+    st, ctx = setup(dim=3, n=n, nl=0, beta=1.0, opt=opts(**kw))
+    assert st == qn.QN_OK, qn.last_error()
+    L = kw.get("length", 1.0)
+    for a in range(3):
+        x = (ctypes.c_double * n[a])()
+        assert qn.lib().qn_nodes(ctx, a, x) == qn.QN_OK
+        x = np.array(x)
+        if kw.get("discretization") == 1:
+            k = kw["sem_order"]
+            e = (n[a] - 1) // k if bc == "neumann" else (n[a] + 1) // k
+            ref = sem.nodes_and_matrices(e, k, L, bc)[0]
+        elif bc == "neumann":
+            ref = np.arange(n[a]) * L / (n[a] - 1)
+        else:
+            ref = np.arange(1, n[a] + 1) * L / (n[a] + 1)
+        np.testing.assert_allclose(x, ref, rtol=0, atol=1e-14)
+    x = (ctypes.c_double * 4)()
+    assert qn.lib().qn_nodes(ctx, 3, x) == qn.QN_ERR_INVALID
+    qn.lib().qn_destroy(ctx)
