@@ -329,7 +329,7 @@ def e8_inputs(n, device="cuda"):
     return v, u
 
 
-def eigen_table(seeds):
+def eigen_table(seeds, max_n=800):
     """Table results3D_2 of the paper (Section 6.3 Example 2, eq. ex3d2:
     alpha = 1600, the lattice-plus-harmonic potential on (-8, 8)^3, Dirichlet
     data) with the midpoint shift: per size the converged pair U* (from the
@@ -342,6 +342,8 @@ def eigen_table(seeds):
             (400, [0.1], max(seeds // 3, 2), ("fp64", "fp32")),
             (800, [0.1], 2, ("fp64",))]
     for n, epss, k, precs in plan:
+        if n > max_n:
+            continue
         log(f"eigen table n={n}")
         shape = (n, n, n)
         V, u0 = e8_inputs(n)
@@ -556,6 +558,8 @@ def main():
     ap.add_argument("--eigen-table", action="store_true",
                     help="also run the paper's nonlinear eigenproblem table (eq. ex3d2 at "
                          "200^3, 400^3 and 800^3 from perturbed converged pairs)")
+    ap.add_argument("--eigen-max-n", type=int, default=800,
+                    help="largest size of the eigenproblem table (200, 400 or 800)")
     ap.add_argument("--eigen-seeds", type=int, default=10,
                     help="perturbations per scale at 200^3 (a third at 400^3, 2 at 800^3)")
     ap.add_argument("--sem", action="store_true",
@@ -701,7 +705,7 @@ def main():
         out["sem_comparison"] = sem_comparison(n, args.ttt_runs)
         torch.cuda.empty_cache()
     if args.eigen_table:
-        out["eigen_table"] = eigen_table(args.eigen_seeds)
+        out["eigen_table"] = eigen_table(args.eigen_seeds, args.eigen_max_n)
         torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_count)

@@ -139,3 +139,24 @@ def test_eigen_zero_solves_and_error_paths():
         Solver(u0.shape, "quasilinear").eigen_iterate(dev(u0[None]))
     with pytest.raises(QNError):
         Solver(u0.shape, "cubic", beta=1.0, precision="bf16x3").eigen_iterate(dev(u0[None]))
+
+
+def test_eigen_full_size_200_property():
+    """Section 6.3 Example 2 at 200^3 (the smallest size of the paper's table):
+    the GPU's returned pair, checked with the oracle's formulas: lam is the
+    Rayleigh quotient of the returned U to 1e-12, ||U||_M = 1, and the
+    oracle's residual at U meets the stopping rule to within rounding."""
+    n = 200
+    print("eigen full size 200^3", flush=True)
+    v, u0 = synth.schrodinger_3d(n)
+    s = solver(u0.shape, "dirichlet", 16.0, v, **E8)
+    U = dev(u0[None])
+    st = s.eigen_iterate(U, rtol=1e-10, max_iter=3000)
+    assert st["status"] == QN_OK, st
+    u = host(U)[0]
+    w = eg.mass_weights(u.shape, "dirichlet", 16.0)
+    assert float(np.sum(w * u * u)) == pytest.approx(1.0, rel=1e-12)
+    lam = eg.rayleigh(u, "dirichlet", 16.0, 1600.0, 0.0, v)
+    assert st["lam"] == pytest.approx(lam, rel=1e-12)
+    r = eg.residual(u, lam, "dirichlet", 16.0, 1600.0, 0.0, v)
+    assert math.sqrt(float(np.sum(w * r * r))) / lam <= 1.5e-10

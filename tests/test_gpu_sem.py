@@ -142,3 +142,36 @@ def test_sem_validation():
     s = solver((11, 11, 11), 2, "dirichlet", 1.0)
     with pytest.raises(QNError):
         s.eigen_iterate(torch.ones((1, 11, 11, 11), dtype=torch.float64, device="cuda"))
+
+
+def _apply_banded(x, h, k, axis, out):
+    """out += H applied along `axis` using only H's 2k + 1 diagonals (test-side
+    application of the oracle's dense H; slices, no dense product)."""
+    n = x.shape[axis]
+    for d in range(-k, k + 1):
+        lo, hi = max(0, -d), min(n, n - d)
+        coef = np.array([h[i, i + d] for i in range(lo, hi)])
+        shape = [1] * x.ndim
+        shape[axis] = hi - lo
+        so = [slice(None)] * x.ndim
+        si = [slice(None)] * x.ndim
+        so[axis] = slice(lo, hi)
+        si[axis] = slice(lo + d, hi + d)
+        out[tuple(so)] += coef.reshape(shape) * x[tuple(si)]
+
+
+def test_sem_full_size_511_solve():
+    """Q^2 at 511^3 (the measured workload's size): X_true seeded, R = (A_h +
+    sigma I) X_true applied on the CPU with the oracle's H, and the GPU solve
+    returns X_true to the conditioning bound (kappa ~ 3e4 here)."""
+    n, k, sigma = 511, 2, 2.0
+    print("sem full size 511^3 solve", flush=True)
+    op = sem.axis_operator((n + 1) // k, k, 1.0, "dirichlet")
+    x_true = synth.random_field((n, n, n), 601)
+    r = sigma * x_true
+    for ax in range(3):
+        _apply_banded(x_true, op[2], k, ax, r)
+    s = solver((n, n, n), k, "dirichlet", 1.0, beta=sigma)
+    x = host(s.fdm_solve(dev(r[None]), 1.0, sigma))[0]
+    kappa = (3 * op[4].max() + sigma) / (3 * op[4].min() + sigma)
+    assert rel(x, x_true) <= max(1e-12, 1e-15 * kappa), (rel(x, x_true), kappa)
