@@ -710,8 +710,9 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
         residual_max_blocks(c->p[0], c->p[1], 1, residual_planar_rows(c->p[0], c->p[1]), true),
         residual_max_blocks(c->n[0], c->n[1], 1, residual_planar_rows(c->n[0], c->n[1]), true));
   if (c->sem_k > 0)
-    c->max_blocks = std::max({c->max_blocks, sem_residual_blocks(c->p[0], c->p[1], c->p[2]),
-                              sem_residual_blocks(c->n[0], c->n[1], c->n[2])});
+    c->max_blocks =
+        std::max({c->max_blocks, sem_residual_blocks(c->dim, c->p[0], c->p[1], c->p[2]),
+                  sem_residual_blocks(c->dim, c->n[0], c->n[1], c->n[2])});
   c->off_part = off;
   off += align256((size_t)c->max_blocks * 4 * sizeof(double));
   c->off_scal = off;

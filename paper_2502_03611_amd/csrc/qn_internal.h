@@ -165,7 +165,7 @@ hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t 
 constexpr int SEM_ROWS = 8;
 constexpr int SEM_RZ = 32;  // 3D: z-planes per workgroup
 hipError_t launch_sem_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t st);
-int sem_residual_blocks(int ox, int oy, int oz);
+int sem_residual_blocks(int dim, int ox, int oy, int oz);  // workgroups = partial slots
 // Eigenproblem finalizes (one workgroup each; return at once when *stop != 0).
 // Phase 1 reduces the mode-1 sums into sc->eig = lam and sc->uscale = s
 // (hvol = h^d, the mass of one interior node).  Phase 2 reduces the mode-2

@@ -253,8 +253,8 @@ void launch3(const ResidualArgs& a, dim3 g, hipStream_t st) {
 
 }  // namespace
 
-int sem_residual_blocks(int ox, int oy, int oz) {
-  const dim3 g = oz > 1 ? sem_grid3(ox, oy, oz) : sem_grid(ox, oy, oz);
+int sem_residual_blocks(int dim, int ox, int oy, int oz) {
+  const dim3 g = dim == 3 ? sem_grid3(ox, oy, oz) : sem_grid(ox, oy, oz);
   return (int)(g.x * g.y * g.z);
 }
 

@@ -50,7 +50,7 @@ def solver(shape, k, bc, length, **kw):
 CASES = [("dirichlet", (11, 15), 2, 1.0), ("dirichlet", (31, 7), 4, 2.0),
          ("neumann", (13, 10), 3, 2.0), ("neumann", (9, 17, 21), 4, 1.0),
          ("dirichlet", (5, 11, 23), 3, 1.0), ("dirichlet", (9, 9, 9), 1, 1.0),
-         ("neumann", (65, 33), 2, 1.0)]
+         ("neumann", (65, 33), 2, 1.0), ("dirichlet", (1, 11, 15), 2, 1.0)]
 
 
 @pytest.mark.parametrize("bc,shape,k,length", CASES)
