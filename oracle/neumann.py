@@ -139,12 +139,20 @@ def direct_solve(r, hs, shift, scale=1.0):
     return np.asarray(x).reshape(r.shape)
 
 
+def shift_of(rule, fu, beta):
+    """beta_k by the rule: "mid" (min + max)/2, "max", "sum" (min + max), "min"
+    of the Jacobian diagonal fu, or "fixed" (the rules compared in the tables
+    of Sections 6.2-6.3)."""
+    lo, hi = float(fu.min()), float(fu.max())
+    return {"mid": 0.5 * (lo + hi), "max": hi, "sum": lo + hi, "min": lo, "fixed": beta}[rule]
+
+
 def qn_solve(f, hs, lin=0.0, u0=None, beta=0.0, midpoint=True, rtol=1e-10, max_iter=200,
-             solver=fdm_solve, cub=1.0, pot=None):
+             solver=fdm_solve, cub=1.0, pot=None, rule=None):
     """The quasi-Newton iteration for the cubic problem: R_k = F^h(U_k); stop
     when ||R_k|| / ||F|| <= rtol (or after max_iter solves); beta_k = the fixed
-    beta or the midpoint of 3 cub U_k^2 + lin + V; U_{k+1} = U_k - (A_h +
-    beta_k I)^-1 R_k.  f, u0, pot: arrays of the grid's shape.  Returns
+    beta or the midpoint of 3 cub U_k^2 + lin + V (rule: another shift rule of
+    shift_of); U_{k+1} = U_k - (A_h + beta_k I)^-1 R_k.  f, u0, pot: arrays of the grid's shape.  Returns
     dict(u, iters, relres, beta)."""
     f = np.asarray(f, dtype=np.float64)
     u = np.zeros_like(f) if u0 is None else np.array(u0, dtype=np.float64, copy=True)
@@ -157,11 +165,8 @@ def qn_solve(f, hs, lin=0.0, u0=None, beta=0.0, midpoint=True, rtol=1e-10, max_i
         hist.append(rel)
         if rel <= rtol or k >= max_iter or not math.isfinite(rel):
             break
-        if midpoint:
-            fu = fu_cubic(u, lin, cub, pot)
-            b = 0.5 * (float(fu.min()) + float(fu.max()))
-        else:
-            b = beta
+        r_ = rule if rule is not None else ("mid" if midpoint else "fixed")
+        b = shift_of(r_, fu_cubic(u, lin, cub, pot), beta)
         betas.append(b)
         u = u - solver(r, hs, b)
         k += 1
