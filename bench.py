@@ -222,13 +222,16 @@ def perturbation(n, dim, seed, device="cuda", coords=None):
     return yx / yx.abs().max()
 
 
-def neumann_table_row(shape, F, V, u_ex, lin, cub, fixed_beta, seeds, timing=False):
+def neumann_table_row(shape, F, V, u_ex, lin, cub, fixed_beta, seeds, timing=False,
+                      rules=("sum", "max")):
     """One size of a mesh table: the discrete solution U* (midpoint iteration
     from the sampled exact solution to relres 1e-12, or 60 iterations at its
     rounding floor),
     then for each seed a timed solve from U* + 0.1 p to relres 1e-10 with the
     midpoint shift (FP64 and FP32 transforms) and with the fixed shift
-    `fixed_beta` (FP64).  Iterations and seconds: mean, std, median."""
+    `fixed_beta` and with the other shift rules of the tables (`rules`: min +
+    max, max, min of the Jacobian diagonal; FP64).  Iterations and seconds:
+    mean, std, median."""
     n, dim = shape[0], len(shape)
     s = Solver(shape, "cubic", beta_mode="midpoint", boundary="neumann", lin=lin, cub=cub,
                potential=V)
@@ -241,9 +244,11 @@ def neumann_table_row(shape, F, V, u_ex, lin, cub, fixed_beta, seeds, timing=Fal
                                  "max_err_vs_exact": float((Ustar[0] - u_ex).abs().max())}}
     U = torch.empty_like(Ustar)
     kernels = None
-    for label, mode, beta, prec in (("midpoint_fp64", "midpoint", 0.0, "fp64"),
-                                    ("midpoint_fp32", "midpoint", 0.0, "fp32"),
-                                    (f"beta{fixed_beta:g}_fp64", "fixed", fixed_beta, "fp64")):
+    configs = [("midpoint_fp64", "midpoint", 0.0, "fp64"),
+               ("midpoint_fp32", "midpoint", 0.0, "fp32"),
+               (f"beta{fixed_beta:g}_fp64", "fixed", fixed_beta, "fp64")]
+    configs += [(f"{r}_fp64", r, 0.0, "fp64") for r in rules]
+    for label, mode, beta, prec in configs:
         tm = timing and label == "midpoint_fp64"
         solver = Solver(shape, "cubic", beta=beta, beta_mode=mode, boundary="neumann", lin=lin,
                         cub=cub, potential=V, precision=prec, timing=tm)
@@ -299,15 +304,16 @@ def neumann_table_row(shape, F, V, u_ex, lin, cub, fixed_beta, seeds, timing=Fal
 
 
 def paper_tables(seeds2d, seeds3d):
-    """Rows of Tables results2d_space (eq. ex2d1: lambda = 1, b = 1, midpoint
-    and beta = 3) and results3D_mesh (eq. ex3d1: lambda = b = 10, V, midpoint
-    and beta = 200)."""
+    """Rows of Tables results2d_space (eq. ex2d1: lambda = 1, b = 1; midpoint,
+    min + max, max, min and beta = 3) and results3D_mesh (eq. ex3d1:
+    lambda = b = 10, V; midpoint, min + max, max and beta = 200)."""
     out = {"e4_2d": [], "e7_3d": []}
     for n in (200, 400, 800, 1600):
         log(f"paper table 2D n={n}")
         u_ex, f = e4_inputs(n)
         out["e4_2d"].append(neumann_table_row((n, n), f[None].contiguous(), None, u_ex, 1.0, 1.0,
-                                              3.0, range(seeds2d)))
+                                              3.0, range(seeds2d),
+                                              rules=("sum", "max", "min")))
         del u_ex, f
     for n, k in ((200, seeds3d), (400, max(seeds3d // 2, 2)), (800, max(seeds3d // 6, 2))):
         log(f"paper table 3D n={n}")

@@ -32,8 +32,11 @@
  *                     where mu = f_u = 3U^2 (Section 4, midpoint rule) or,
  *                     for the system, mu ranges over the 2x2-block
  *                     eigenvalues of Section 4.3 eq. eigenvalues.
+ *   QN_BETA_MAX, QN_BETA_SUM, QN_BETA_MIN  beta_k = max mu, min mu + max mu,
+ *                     min mu: the alternatives the paper's tables compare
+ *                     the midpoint with (Sections 6.2-6.3), c_k = 1.
  *   QN_NL_QUASILIN always uses c_k = (min a + max a)/2, a = 1 + U^2, and the
- *   fixed beta; QN_BETA_MIDPOINT is rejected for it.
+ *   fixed beta; every other beta_mode is rejected for it.
  *
  * Precision (transforms only; residual, norms, shift rule and the update are
  * always FP64): QN_PREC_FP64 (FP64 MFMA), QN_PREC_FP32 (FP32 MFMA),
@@ -93,7 +96,13 @@ typedef enum {
   QN_PREC_BF16X3 = 2,
   QN_PREC_BF16X6 = 3
 } qn_precision;
-typedef enum { QN_BETA_FIXED = 0, QN_BETA_MIDPOINT = 1 } qn_beta_mode;
+typedef enum {
+  QN_BETA_FIXED = 0,
+  QN_BETA_MIDPOINT = 1,
+  QN_BETA_MAX = 2,  /* beta_k = max mu: an alternative the paper's tables compare */
+  QN_BETA_SUM = 3,  /* beta_k = min mu + max mu: likewise                        */
+  QN_BETA_MIN = 4   /* beta_k = min mu: likewise                                 */
+} qn_beta_mode;
 
 /* dim: 2 or 3.  n[0] = nx, n[1] = ny, n[2] = nz (ignored when dim = 2);
  * 1 <= n[a] <= 4096.  ncomp: 1, or 2 for QN_NL_SYS2_CUBIC. */

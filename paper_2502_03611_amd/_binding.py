@@ -21,7 +21,7 @@ QN_ERR_UNSUPPORTED = 6
 
 NONLINEARITIES = {"cubic": 0, "quasilinear": 1, "system": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
-BETA_MODES = {"fixed": 0, "midpoint": 1}
+BETA_MODES = {"fixed": 0, "midpoint": 1, "max": 2, "sum": 3, "min": 4}
 
 c_i32 = ctypes.c_int32
 c_dbl = ctypes.c_double

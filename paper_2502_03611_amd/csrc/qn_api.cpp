@@ -196,7 +196,13 @@ void fold_timing(qn_ctx c) {
 
 int rule_of(qn_ctx c) {
   if (c->nl == QN_NL_QUASILIN) return RULE_COEFF_MID;
-  return c->beta_mode == QN_BETA_MIDPOINT ? RULE_MIDPOINT : RULE_FIXED;
+  switch (c->beta_mode) {
+    case QN_BETA_MIDPOINT: return RULE_MIDPOINT;
+    case QN_BETA_MAX: return RULE_MAX;
+    case QN_BETA_SUM: return RULE_SUM;
+    case QN_BETA_MIN: return RULE_MIN;
+    default: return RULE_FIXED;
+  }
 }
 
 FoldOperands fold_ops(qn_ctx c, int axis) {
@@ -540,10 +546,10 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   qn_options o{};
   if (opt) o = *opt;
   if (o.precision < 0 || o.precision > 3) return fail(QN_ERR_INVALID, "unknown precision");
-  if (o.beta_mode < 0 || o.beta_mode > 1) return fail(QN_ERR_INVALID, "unknown beta_mode");
-  if (nonlinearity == QN_NL_QUASILIN && o.beta_mode == QN_BETA_MIDPOINT)
+  if (o.beta_mode < 0 || o.beta_mode > 4) return fail(QN_ERR_INVALID, "unknown beta_mode");
+  if (nonlinearity == QN_NL_QUASILIN && o.beta_mode != QN_BETA_FIXED)
     return fail(QN_ERR_INVALID, "the quasi-linear problem uses the coefficient midpoint rule "
-                                "and a fixed beta; QN_BETA_MIDPOINT is not accepted");
+                                "and a fixed beta; only QN_BETA_FIXED is accepted");
   if (!std::isfinite(beta)) return fail(QN_ERR_INVALID, "beta is not finite");
   if (o.boundary != QN_BC_DIRICHLET && o.boundary != QN_BC_NEUMANN)
     return fail(QN_ERR_INVALID, "unknown boundary condition");

@@ -35,6 +35,9 @@ enum ShiftRule : int {
   RULE_FIXED = 0,      // c = 1, beta fixed
   RULE_MIDPOINT = 1,   // c = 1, beta = (mumin + mumax)/2
   RULE_COEFF_MID = 2,  // c = (mumin + mumax)/2, beta fixed (quasi-linear)
+  RULE_MAX = 3,        // c = 1, beta = mumax
+  RULE_SUM = 4,        // c = 1, beta = mumin + mumax
+  RULE_MIN = 5,        // c = 1, beta = mumin
 };
 
 enum Nonlin : int { NL_CUBIC = 0, NL_QUASILIN = 1, NL_SYS2 = 2 };

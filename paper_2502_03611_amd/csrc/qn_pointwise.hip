@@ -512,6 +512,18 @@ hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t 
 
 constexpr int FIN_THREADS = 1024;
 
+// beta_k of the shift rules (the midpoint of Section 4 and the alternatives
+// the paper's tables compare it with), c_k = 1.
+__device__ inline double rule_beta(int rule, double mn, double mx, double beta_fixed) {
+  switch (rule) {
+    case RULE_MIDPOINT: return 0.5 * (mn + mx);
+    case RULE_MAX: return mx;
+    case RULE_SUM: return mn + mx;
+    case RULE_MIN: return mn;
+    default: return beta_fixed;
+  }
+}
+
 __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double* __restrict__ partials,
                                                           int nblocks, DevScalars* sc, int rule,
                                                           double beta_fixed, double lam_min_sum,
@@ -528,8 +540,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double* __restri
   if (threadIdx.x == 0) {
     DevScalars r{};
     r.scale = 1.0;
-    r.beta = beta_fixed;
-    if (rule == RULE_MIDPOINT) r.beta = 0.5 * (mn + mx);
+    r.beta = rule_beta(rule, mn, mx, beta_fixed);
     if (rule == RULE_COEFF_MID) r.scale = 0.5 * (mn + mx);
     r.sumsqR = s0;
     r.mumin = mn;
@@ -606,7 +617,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_eig_finalize2(
   if (threadIdx.x == 0) {
     DevScalars r = *sc;  // keeps lam and s from phase 1
     r.scale = 1.0;
-    r.beta = rule == RULE_MIDPOINT ? 0.5 * (mn + mx) : beta_fixed;
+    r.beta = rule_beta(rule, mn, mx, beta_fixed);
     r.sumsqR = hvol * s0;
     r.mumin = mn;
     r.mumax = mx;

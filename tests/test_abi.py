@@ -283,3 +283,15 @@ def test_node_coordinates(kw, n, bc):
     x = (ctypes.c_double * 4)()
     assert qn.lib().qn_nodes(ctx, 3, x) == qn.QN_ERR_INVALID
     qn.lib().qn_destroy(ctx)
+
+
+@pytest.mark.parametrize("mode,nl,want", [(2, 0, "ok"), (3, 0, "ok"), (4, 2, "ok"),
+                                          (5, 0, "invalid"), (2, 1, "invalid"),
+                                          (3, 1, "invalid")])
+def test_shift_rule_modes(mode, nl, want):
+    """QN_BETA_MAX / SUM / MIN: accepted for the cubic problem and the system,
+    refused for the quasi-linear problem (coefficient rule); 5 is unknown."""
+    st, ctx = setup(nl=nl, ncomp=2 if nl == 2 else 1, beta=0.0, opt=opts(beta_mode=mode))
+    assert st == (qn.QN_OK if want == "ok" else qn.QN_ERR_INVALID), qn.last_error()
+    if st == qn.QN_OK:
+        qn.lib().qn_destroy(ctx)

@@ -137,3 +137,34 @@ def test_zero_shift_is_refused_and_midpoint_from_zero_needs_lin():
     u = torch.zeros((1, 9, 9), dtype=torch.float64, device="cuda")
     st = s.iterate(u, dev(f[None]), rtol=1e-10, max_iter=20)
     assert st["status"] != QN_OK and float(u.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("gen,n,rule", [("2d", 65, "midpoint"), ("2d", 65, "sum"),
+                                        ("2d", 65, "max"), ("2d", 65, "min"),
+                                        ("3d", 17, "sum"), ("3d", 17, "max")])
+def test_shift_rules_parity(gen, n, rule):
+    """The shift rules of the paper's tables (Sections 6.2-6.3) from the
+    perturbed discrete solution: equal counts with the oracle, then exactly K
+    solves on both sides."""
+    print(f"neumann shift rule {gen} {n} {rule}", flush=True)
+    orule = {"midpoint": "mid", "sum": "sum", "max": "max", "min": "min"}[rule]
+    if gen == "2d":
+        _, f = synth.neumann_2d(n)
+        kw, skw = dict(lin=1.0), dict(lin=1.0)
+    else:
+        _, f, v = synth.neumann_potential_3d(n)
+        kw, skw = dict(lin=10.0, cub=10.0, pot=v), dict(lin=10.0, cub=10.0, potential=dev(v))
+    hs = nm.spacing(f.shape)
+    u_star = nm.qn_solve(f, hs, rtol=1e-13, max_iter=500, **kw)["u"]
+    u0 = u_star + 0.1 * synth.polynomial_perturbation(n, f.ndim, 0)
+    ref = nm.qn_solve(f, hs, u0=u0, rule=orule, max_iter=2000, **kw)
+    assert ref["converged"]
+    s = solver(f.shape, beta_mode=rule, **skw)
+    U = dev(u0[None])
+    st = s.iterate(U, dev(f[None]), rtol=1e-10, max_iter=2000)
+    assert st["status"] == QN_OK and st["iters"] == ref["iters"], (st, ref["iters"])
+    k = ref["iters"]
+    U = dev(u0[None])
+    s.iterate(U, dev(f[None]), rtol=0.0, max_iter=k)
+    assert rel(host(U)[0], ref["u"]) <= 1e-12
+    assert st["beta_last"] == pytest.approx(ref["beta"][-1], rel=1e-10)
