@@ -325,6 +325,65 @@ def paper_tables(seeds2d, seeds3d):
     return out
 
 
+def beta_tables(seeds2d, seeds3d):
+    """Tables results2d1 (eq. ex2d1 on 50^2 nodes) and results3D (eq. ex3d1 on
+    200^3 nodes) of the paper: for each perturbation scale eps in {0.1, 0.2,
+    0.5, 1.0} and each shift rule of the table (the midpoint, min + max, max,
+    min in 2D, and the fixed shifts), the mean and std of the iterations from
+    U* + eps p to relres 1e-10 and the median time per solve (FP64)."""
+    out = {}
+    for label, n, dim, rules, fixed in (
+            ("e4_2d_50", 50, 2, ("midpoint", "sum", "max", "min"), (3.0, 5.0, 7.0, 9.0, 11.0)),
+            ("e7_3d_200", 200, 3, ("midpoint", "sum", "max"), (175.0, 200.0, 250.0, 300.0, 350.0))):
+        log(f"beta table {label}")
+        shape = (n,) * dim
+        if dim == 2:
+            u_ex, f = e4_inputs(n)
+            V, lin, cub = None, 1.0, 1.0
+        else:
+            u_ex, f, V = e7_inputs(n)
+            lin, cub = 10.0, 10.0
+        F = f[None].contiguous()
+        s = Solver(shape, "cubic", beta_mode="midpoint", boundary="neumann", lin=lin, cub=cub,
+                   potential=V)
+        s.autotune()
+        Ustar = u_ex[None].clone()
+        s.iterate(Ustar, F, rtol=1e-12, max_iter=60)
+        s.close()
+        seeds = seeds2d if dim == 2 else seeds3d
+        U = torch.empty_like(Ustar)
+        rows = {}
+        for rule in rules + tuple(f"beta{b:g}" for b in fixed):
+            mode, beta = (rule, 0.0) if not rule.startswith("beta") else ("fixed", float(rule[4:]))
+            solver = Solver(shape, "cubic", beta=beta, beta_mode=mode, boundary="neumann", lin=lin,
+                            cub=cub, potential=V)
+            solver.autotune()
+            rows[rule] = {}
+            for eps in (0.1, 0.2, 0.5, 1.0):
+                iters, times, bad = [], [], 0
+                for seed in range(seeds):
+                    U.copy_(Ustar)
+                    U[0].add_(perturbation(n, dim, seed), alpha=eps)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    st = solver.iterate(U, F, rtol=1e-10, max_iter=3000)
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t0)
+                    iters.append(st["iters"])
+                    bad += st["status"] != 0
+                rows[rule][f"{eps:g}"] = {"iters_mean": round(float(np.mean(iters)), 2),
+                                          "iters_std": round(float(np.std(iters)), 2),
+                                          "time_median_s": round(float(np.median(times)), 5),
+                                          "not_converged": bad}
+            solver.close()
+            log(f"  {label} {rule}: " + ", ".join(f"eps {e}: {v['iters_mean']}"
+                                                 for e, v in rows[rule].items()))
+        out[label] = {"n": n, "seeds": seeds, "rows": rows}
+        del u_ex, f, F, Ustar, U
+        torch.cuda.empty_cache()
+    return out
+
+
 def e8_inputs(n, device="cuda"):
     """synth.schrodinger_3d on `device`: (V, u_start), shape (n, n, n)."""
     x = torch.from_numpy(synth.interior_coords(n, -8.0, 8.0)).to(device)
@@ -559,6 +618,9 @@ def main():
     ap.add_argument("--paper-tables", action="store_true",
                     help="also run the paper's Neumann mesh tables (2D 200^2-1600^2, "
                          "3D 200^3-800^3, perturbed starts)")
+    ap.add_argument("--beta-tables", action="store_true",
+                    help="also run the paper's shift-rule tables over perturbation scales "
+                         "(eq. ex2d1 at 50^2, eq. ex3d1 at 200^3)")
     ap.add_argument("--table-seeds", type=int, default=20,
                     help="perturbations per 2D size and at 200^3 (fewer at 400^3 and 800^3)")
     ap.add_argument("--eigen-table", action="store_true",
@@ -706,6 +768,9 @@ def main():
         out["amplitude_sweep"] = amplitude_sweep(n, args.ttt_runs)
     if args.paper_tables:
         out["paper_tables"] = paper_tables(args.table_seeds, args.table_seeds)
+        torch.cuda.empty_cache()
+    if args.beta_tables:
+        out["beta_tables"] = beta_tables(args.table_seeds, max(args.table_seeds // 3, 2))
         torch.cuda.empty_cache()
     if args.sem:
         out["sem_comparison"] = sem_comparison(n, args.ttt_runs)
