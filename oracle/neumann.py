@@ -100,15 +100,16 @@ def assemble_laplacian(shape, hs):
     return total
 
 
-def residual_cubic(u, f, hs, lin=0.0, cub=1.0, pot=None):
-    """F^h(U) = A_h U + lin U + cub U^3 + V U - F (pot = V on the nodes, None = 0)."""
-    r = apply_laplacian(u, hs) + lin * u + cub * u ** 3 - f
+def residual_cubic(u, f, hs, lin=0.0, cub=1.0, pot=None, quad=0.0):
+    """F^h(U) = A_h U + lin U + quad U^2 + cub U^3 + V U - F (pot = V on the
+    nodes, None = 0)."""
+    r = apply_laplacian(u, hs) + lin * u + quad * u ** 2 + cub * u ** 3 - f
     return r if pot is None else r + pot * u
 
 
-def fu_cubic(u, lin=0.0, cub=1.0, pot=None):
-    """Jacobian diagonal of the pointwise part: 3 cub U^2 + lin + V."""
-    d = 3.0 * cub * u * u + lin
+def fu_cubic(u, lin=0.0, cub=1.0, pot=None, quad=0.0):
+    """Jacobian diagonal of the pointwise part: 3 cub U^2 + 2 quad U + lin + V."""
+    d = 3.0 * cub * u * u + 2.0 * quad * u + lin
     return d if pot is None else d + pot
 
 
@@ -148,7 +149,7 @@ def shift_of(rule, fu, beta):
 
 
 def qn_solve(f, hs, lin=0.0, u0=None, beta=0.0, midpoint=True, rtol=1e-10, max_iter=200,
-             solver=fdm_solve, cub=1.0, pot=None, rule=None):
+             solver=fdm_solve, cub=1.0, pot=None, rule=None, quad=0.0):
     """The quasi-Newton iteration for the cubic problem: R_k = F^h(U_k); stop
     when ||R_k|| / ||F|| <= rtol (or after max_iter solves); beta_k = the fixed
     beta or the midpoint of 3 cub U_k^2 + lin + V (rule: another shift rule of
@@ -160,13 +161,13 @@ def qn_solve(f, hs, lin=0.0, u0=None, beta=0.0, midpoint=True, rtol=1e-10, max_i
     hist, betas = [], []
     k = 0
     while True:
-        r = residual_cubic(u, f, hs, lin, cub, pot)
+        r = residual_cubic(u, f, hs, lin, cub, pot, quad)
         rel = math.sqrt(float(np.sum(r * r))) / fnorm
         hist.append(rel)
         if rel <= rtol or k >= max_iter or not math.isfinite(rel):
             break
         r_ = rule if rule is not None else ("mid" if midpoint else "fixed")
-        b = shift_of(r_, fu_cubic(u, lin, cub, pot), beta)
+        b = shift_of(r_, fu_cubic(u, lin, cub, pot, quad), beta)
         betas.append(b)
         u = u - solver(r, hs, b)
         k += 1

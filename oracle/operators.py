@@ -61,17 +61,18 @@ def assemble_laplacian(shape):
     return total.tocsr()
 
 
-def residual_cubic(u, f, lin=0.0, cub=1.0, pot=None):
-    """F^h(U) = A_h U + lin U + cub U^3 + V U - F (Section 4 eq. F_u with the
-    model of Section 2: lambda = lin, f(x, u) = cub u^3 + V(x) u - f_src(x);
-    pot = V sampled on the grid, None = 0)."""
-    r = apply_laplacian(u) + lin * u + cub * u ** 3 - f
+def residual_cubic(u, f, lin=0.0, cub=1.0, pot=None, quad=0.0):
+    """F^h(U) = A_h U + lin U + quad U^2 + cub U^3 + V U - F (Section 4 eq. F_u
+    with the model of Section 2: lambda = lin, f(x, u) = cub u^3 + quad u^2 +
+    V(x) u - f_src(x); pot = V sampled on the grid, None = 0)."""
+    r = apply_laplacian(u) + lin * u + quad * u ** 2 + cub * u ** 3 - f
     return r if pot is None else r + pot * u
 
 
-def fu_cubic(u, lin=0.0, cub=1.0, pot=None):
-    """Diagonal of the Jacobian (N_h)_U of the pointwise part: 3 cub U^2 + lin + V."""
-    d = 3.0 * cub * u * u + lin
+def fu_cubic(u, lin=0.0, cub=1.0, pot=None, quad=0.0):
+    """Diagonal of the Jacobian (N_h)_U of the pointwise part:
+    3 cub U^2 + 2 quad U + lin + V."""
+    d = 3.0 * cub * u * u + 2.0 * quad * u + lin
     return d if pot is None else d + pot
 
 

@@ -30,12 +30,12 @@ SYSTEM = "system"
 QUASILINEAR = "quasilinear"
 
 
-def residual(kind, u, f, lin=0.0, cub=1.0, pot=None):
+def residual(kind, u, f, lin=0.0, cub=1.0, pot=None, quad=0.0):
     """F^h(U) for the problem kind; u, f carry a leading component axis.
     lin, cub, pot: the cubic problem's linear coefficient, cubic coefficient
     and potential field (see operators.residual_cubic)."""
     if kind == CUBIC:
-        return ops.residual_cubic(u[0], f[0], lin, cub, pot)[None]
+        return ops.residual_cubic(u[0], f[0], lin, cub, pot, quad)[None]
     if kind == SYSTEM:
         r1, r2 = ops.residual_system(u[0], u[1], f[0], f[1])
         return np.stack([r1, r2])
@@ -44,7 +44,7 @@ def residual(kind, u, f, lin=0.0, cub=1.0, pot=None):
     raise ValueError(kind)
 
 
-def shift_rule(kind, u, beta, midpoint, lin=0.0, cub=1.0, pot=None):
+def shift_rule(kind, u, beta, midpoint, lin=0.0, cub=1.0, pot=None, quad=0.0):
     """Return (scale c_k, shift beta_k) of the Jacobian approximation."""
     if kind == QUASILINEAR:
         a = ops.coeff_quasilinear(u[0])
@@ -52,14 +52,14 @@ def shift_rule(kind, u, beta, midpoint, lin=0.0, cub=1.0, pot=None):
     if not midpoint:
         return 1.0, beta
     if kind == CUBIC:
-        fu = ops.fu_cubic(u[0], lin, cub, pot)
+        fu = ops.fu_cubic(u[0], lin, cub, pot, quad)
         return 1.0, 0.5 * (float(fu.min()) + float(fu.max()))
     lm, lp = ops.system_jacobian_eigs(u[0], u[1])
     return 1.0, 0.5 * (float(lm.min()) + float(lp.max()))
 
 
 def qn_solve(kind, f, u0=None, beta=0.0, midpoint=False, rtol=1e-10,
-             max_iter=200, solver=fdm_solve, lin=0.0, cub=1.0, pot=None):
+             max_iter=200, solver=fdm_solve, lin=0.0, cub=1.0, pot=None, quad=0.0):
     """Run the quasi-Newton iteration.
 
     f, u0: arrays of shape (ncomp, .., ny, nx).  Runs until relres <= rtol or
@@ -72,12 +72,12 @@ def qn_solve(kind, f, u0=None, beta=0.0, midpoint=False, rtol=1e-10,
     hist, betas, scales = [], [], []
     k = 0
     while True:
-        r = residual(kind, u, f, lin, cub, pot)
+        r = residual(kind, u, f, lin, cub, pot, quad)
         rel = math.sqrt(float(np.sum(r * r))) / fnorm
         hist.append(rel)
         if rel <= rtol or k >= max_iter or not math.isfinite(rel):
             break
-        c, b = shift_rule(kind, u, beta, midpoint, lin, cub, pot)
+        c, b = shift_rule(kind, u, beta, midpoint, lin, cub, pot, quad)
         betas.append(b)
         scales.append(c)
         for comp in range(u.shape[0]):

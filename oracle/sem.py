@@ -19,7 +19,7 @@ Section 4.2: H = M^-1/2 (M^-1/2 S M^-1/2) M^1/2 with a symmetric middle
 factor, so H = T Lam T^-1 with T = M^-1/2 T~ (T~ orthonormal); here the pair
 comes from scipy's generalised symmetric eigensolver S T = M T Lam
 (T^T M T = I, so T^-1 = T^T M).  The solve and the quasi-Newton loop are
-those of Sections 4 and 4.1.  Problem: -Lap u + lin u + cub u^3 + V u = f.
+those of Sections 4 and 4.1.  Problem: -Lap u + lin u + quad u^2 + cub u^3 + V u = f.
 Pinned in tests/test_oracle_sem.py.
 """
 
@@ -104,13 +104,13 @@ def apply_a(u, ops_):
     return out
 
 
-def residual_cubic(u, f, ops_, lin=0.0, cub=1.0, pot=None):
-    r = apply_a(u, ops_) + lin * u + cub * u ** 3 - f
+def residual_cubic(u, f, ops_, lin=0.0, cub=1.0, pot=None, quad=0.0):
+    r = apply_a(u, ops_) + lin * u + quad * u ** 2 + cub * u ** 3 - f
     return r if pot is None else r + pot * u
 
 
-def fu_cubic(u, lin=0.0, cub=1.0, pot=None):
-    d = 3.0 * cub * u * u + lin
+def fu_cubic(u, lin=0.0, cub=1.0, pot=None, quad=0.0):
+    d = 3.0 * cub * u * u + 2.0 * quad * u + lin
     return d if pot is None else d + pot
 
 
@@ -131,21 +131,22 @@ def fdm_solve(r, ops_, shift, scale=1.0):
 
 
 def qn_solve(f, ops_, lin=0.0, cub=1.0, pot=None, u0=None, beta=0.0, midpoint=True,
-             rtol=1e-10, max_iter=200):
+             rtol=1e-10, max_iter=200, quad=0.0):
     """The quasi-Newton loop of Section 4 on the SEM operator: stop when
-    ||R||_2 / ||F||_2 <= rtol; beta_k = midpoint of 3 cub U^2 + lin + V or fixed."""
+    ||R||_2 / ||F||_2 <= rtol; beta_k = midpoint of 3 cub U^2 + 2 quad U + lin + V
+    or fixed."""
     u = np.zeros_like(f) if u0 is None else np.array(u0, dtype=np.float64, copy=True)
     fnorm = math.sqrt(float(np.sum(f * f)))
     hist, betas = [], []
     k = 0
     while True:
-        r = residual_cubic(u, f, ops_, lin, cub, pot)
+        r = residual_cubic(u, f, ops_, lin, cub, pot, quad)
         rel = math.sqrt(float(np.sum(r * r))) / fnorm
         hist.append(rel)
         if rel <= rtol or k >= max_iter or not math.isfinite(rel):
             break
         if midpoint:
-            fu = fu_cubic(u, lin, cub, pot)
+            fu = fu_cubic(u, lin, cub, pot, quad)
             b = 0.5 * (float(fu.min()) + float(fu.max()))
         else:
             b = beta

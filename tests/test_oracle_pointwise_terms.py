@@ -1,6 +1,7 @@
-"""Pins of the oracle's general pointwise term lambda U + b U^3 + V U (the model
-of Section 2 with f(x, u) = b u^3 + V(x) u - f_src; Section 6.3, Example 1,
-eq. ex3d1 has lambda = b = 10 and a potential V), for both boundary types.
+"""Pins of the oracle's general pointwise term lambda U + q U^2 + b U^3 + V U
+(the model of Section 2 with f(x, u) = b u^3 + q u^2 + V(x) u - f_src;
+Section 6.3, Example 1, eq. ex3d1 has lambda = b = 10 and a potential V;
+Section 6.2, Example 2, eq. 2dex has q = -1), for both boundary types.
 
 Each pin goes through something other than the oracle's own formulas: the
 continuous manufactured solution (truncation error O(h^2)), central
@@ -54,10 +55,11 @@ def _fd_diagonal(res, u, eps=1e-4):
     return d.reshape(u.shape)
 
 
-@pytest.mark.parametrize("bc", ["dirichlet", "neumann"])
-def test_jacobian_diagonal_matches_central_differences(bc):
-    """fu = 3 b U^2 + lambda + V is the diagonal of dF^h/dU minus diag(A_h):
-    for a cubic in U_i the central difference is exact up to b eps^2."""
+@pytest.mark.parametrize("bc,quad", [("dirichlet", 0.0), ("neumann", 0.0),
+                                     ("dirichlet", -1.3), ("neumann", 0.8)])
+def test_jacobian_diagonal_matches_central_differences(bc, quad):
+    """fu = 3 b U^2 + 2 q U + lambda + V is the diagonal of dF^h/dU minus
+    diag(A_h): for a cubic in U_i the central difference is exact up to b eps^2."""
     rng = np.random.default_rng(11)
     shape = (4, 5, 6)
     u = rng.standard_normal(shape)
@@ -65,14 +67,14 @@ def test_jacobian_diagonal_matches_central_differences(bc):
     v = rng.uniform(0.0, 50.0, shape)
     lin, cub = 0.7, 2.5
     if bc == "dirichlet":
-        res = lambda w: ops.residual_cubic(w, f, lin, cub, v)
+        res = lambda w: ops.residual_cubic(w, f, lin, cub, v, quad)
         adiag = ops.assemble_laplacian(shape).diagonal().reshape(shape)
-        fu = ops.fu_cubic(u, lin, cub, v)
+        fu = ops.fu_cubic(u, lin, cub, v, quad)
     else:
         hs = nm.spacing(shape)
-        res = lambda w: nm.residual_cubic(w, f, hs, lin, cub, v)
+        res = lambda w: nm.residual_cubic(w, f, hs, lin, cub, v, quad)
         adiag = nm.assemble_laplacian(shape, hs).diagonal().reshape(shape)
-        fu = nm.fu_cubic(u, lin, cub, v)
+        fu = nm.fu_cubic(u, lin, cub, v, quad)
     d = _fd_diagonal(res, u) - adiag
     np.testing.assert_allclose(d, fu, rtol=1e-7, atol=1e-7 * np.abs(adiag).max())
 
@@ -134,3 +136,21 @@ def test_polynomial_perturbation_is_normalised_and_seeded():
     assert np.abs(np.diff(p, n=5, axis=2)).max() < 1e-10
     np.testing.assert_array_equal(p, synth.polynomial_perturbation(12, 3, 7))
     assert not np.array_equal(p, synth.polynomial_perturbation(12, 3, 8))
+
+
+def test_quadratic_term_manufactured_residual_is_second_order():
+    """-Lap u - u^2 = f (the nonlinearity of Section 6.2, Example 2, eq. 2dex)
+    with u = sin(pi x) sin(2 pi y) on (0, 1)^2, Dirichlet data: the residual of
+    the sampled exact solution is the O(h^2) truncation error; a dropped or
+    sign-flipped quadratic term leaves an O(1) residual."""
+    errs = []
+    for n in (15, 31, 63):
+        x = synth.grid_coords(n)
+        u = np.sin(2 * np.pi * x)[:, None] * np.sin(np.pi * x)[None, :]
+        f = 5 * np.pi ** 2 * u - u * u
+        errs.append(float(np.abs(ops.residual_cubic(u, f, 0.0, 0.0, None, -1.0)).max()))
+        if n == 31:
+            assert np.abs(ops.residual_cubic(u, f, 0.0, 0.0, None, 0.0)).max() > 0.5
+            assert np.abs(ops.residual_cubic(u, f, 0.0, 0.0, None, 1.0)).max() > 0.5
+    for coarse, fine in zip(errs, errs[1:]):
+        assert 3.5 < coarse / fine < 4.5, errs
