@@ -44,14 +44,14 @@ PEAK_HBM_GBS = 8000.0
 # calibrated on a plain 1 GiB device copy), keyed by kernel.  Each figure is
 # valid only while the source file it was taken on is unchanged.
 TRAFFIC_SOURCES = {"fold": ("paper_2502_03611_amd/csrc/qn_gemm_fold.hip", "c13f02002af662fc"),
-                   "pointwise": ("paper_2502_03611_amd/csrc/qn_pointwise.hip", "dd15109814ab9565")}
+                   "pointwise": ("paper_2502_03611_amd/csrc/qn_pointwise.hip", "7ee66e9d31cc72f5")}
 TRAFFIC = {"k_fold_right_fwd<double,64,128,0>": ("fold", 1.4505e+09, 1.0737e+09),
            "k_fold_right_fwd<double,128,128,0>": ("fold", 1.2723e+09, 1.0737e+09),
            "k_fold_left_fwd2<double,64,64,EPI_STORE,0>": ("fold", 1.4559e+09, 1.0737e+09),
            "k_fold_left_fwd2<double,64,64,EPI_DIVIDE,0>": ("fold", 1.4324e+09, 1.0737e+09),
            "k_fold_left_inv<double,64,64,0>": ("fold", 1.3846e+09, 1.0716e+09),
            "k_fold_right_inv<double,64,64,EPI_SUB_DENSE,0>": ("fold", 2.4518e+09, 1.0725e+09),
-           "k_residual<QUASILIN,double>": ("pointwise", 2.2802e+09, 1.0739e+09)}
+           "k_residual<QUASILIN,double>": ("pointwise", 2.2814e+09, 1.0739e+09)}
 
 
 def traffic_if_current(kernel, n):
@@ -384,6 +384,60 @@ def beta_tables(seeds2d, seeds3d):
     return out
 
 
+def e5_table(seeds):
+    """Table results2D_2 of the paper (Section 6.2 Example 2, eq. 2dex:
+    -Lap u - u^2 = -1600 sin(pi x) sin(pi y) on (0, 1)^2, Dirichlet data): the
+    stable solution U* from U_0 = 0 (midpoint shift), then timed solves from
+    U* + eps p (p on the interior nodes) to relres 1e-10: eps in {0.1, 0.2,
+    0.5, 1.0} at 200^2 and eps = 0.1 at 400^2 .. 1600^2; FP64 and FP32
+    transforms, midpoint shift."""
+    out = []
+    for n in (200, 400, 800, 1600):
+        log(f"e5 table n={n}")
+        shape = (n, n)
+        xs = synth.grid_coords(n)
+        x = torch.from_numpy(xs).cuda()
+        F = (-1600.0 * torch.sin(math.pi * x)[:, None] * torch.sin(math.pi * x)[None, :])[None]
+        F = F.contiguous()
+        s = Solver(shape, "cubic", beta_mode="midpoint", cub=1e-300, quad=-1.0)
+        s.autotune()
+        Ustar = torch.zeros_like(F)
+        st = s.iterate(Ustar, F, rtol=1e-12, max_iter=100)
+        s.close()
+        rec = {"n": n, "stable_solution": {"iters_from_zero": st["iters"], "relres": st["relres"],
+                                           "min": float(Ustar.min()), "max": float(Ustar.max())}}
+        U = torch.empty_like(Ustar)
+        for prec in ("fp64", "fp32"):
+            solver = Solver(shape, "cubic", beta_mode="midpoint", cub=1e-300, quad=-1.0,
+                            precision=prec)
+            solver.autotune()
+            U.copy_(Ustar)
+            solver.iterate(U, F, rtol=0.0, max_iter=1)  # untimed warm-up of this context
+            for eps in ((0.1, 0.2, 0.5, 1.0) if n == 200 else (0.1,)):
+                iters, times, bad = [], [], 0
+                for seed in range(seeds):
+                    U.copy_(Ustar)
+                    U[0].add_(perturbation(n, 2, seed, coords=xs), alpha=eps)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    st = solver.iterate(U, F, rtol=1e-10, max_iter=500)
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t0)
+                    iters.append(st["iters"])
+                    bad += st["status"] != 0
+                rec[f"eps{eps:g}_{prec}"] = {"iters_mean": round(float(np.mean(iters)), 2),
+                                             "iters_std": round(float(np.std(iters)), 2),
+                                             "time_median_s": round(float(np.median(times)), 5),
+                                             "not_converged": bad, "seeds": seeds}
+                log(f"  n={n} eps {eps} {prec}: iters {np.mean(iters):.2f} +- {np.std(iters):.2f}, "
+                    f"median {np.median(times):.5f} s")
+            solver.close()
+        out.append(rec)
+        del F, Ustar, U
+        torch.cuda.empty_cache()
+    return out
+
+
 def e8_inputs(n, device="cuda"):
     """synth.schrodinger_3d on `device`: (V, u_start), shape (n, n, n)."""
     x = torch.from_numpy(synth.interior_coords(n, -8.0, 8.0)).to(device)
@@ -618,6 +672,9 @@ def main():
     ap.add_argument("--paper-tables", action="store_true",
                     help="also run the paper's Neumann mesh tables (2D 200^2-1600^2, "
                          "3D 200^3-800^3, perturbed starts)")
+    ap.add_argument("--e5-table", action="store_true",
+                    help="also run the paper's table for -Lap u - u^2 = -1600 sin sin (2D, "
+                         "Dirichlet; 200^2 .. 1600^2, perturbed stable solution)")
     ap.add_argument("--beta-tables", action="store_true",
                     help="also run the paper's shift-rule tables over perturbation scales "
                          "(eq. ex2d1 at 50^2, eq. ex3d1 at 200^3)")
@@ -768,6 +825,9 @@ def main():
         out["amplitude_sweep"] = amplitude_sweep(n, args.ttt_runs)
     if args.paper_tables:
         out["paper_tables"] = paper_tables(args.table_seeds, args.table_seeds)
+        torch.cuda.empty_cache()
+    if args.e5_table:
+        out["e5_table"] = e5_table(args.table_seeds)
         torch.cuda.empty_cache()
     if args.beta_tables:
         out["beta_tables"] = beta_tables(args.table_seeds, max(args.table_seeds // 3, 2))

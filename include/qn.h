@@ -143,17 +143,21 @@ typedef enum { QN_DISC_FD = 0, QN_DISC_SEM = 1 } qn_discretization;
  * qn_boundary; stream: a hipStream_t, NULL = default stream; length: the
  * side L of the domain (every axis), 0 = 1.0.
  * The pointwise term of QN_NL_CUBIC is the paper's model
- * -Lap u + lambda u + f(x, u) = 0 (Section 2) with f(x, u) = b u^3 + V(x) u
- * - f_src(x) (Section 6.3, eq. ex3d1, has lambda = b = 10 and a potential V):
- * F^h(U) = A_h U + lambda U + b U^3 + V U - F, Jacobian diagonal
- * 3 b U^2 + lambda + V.
+ * -Lap u + lambda u + f(x, u) = 0 (Section 2) with f(x, u) = b u^3 + q u^2 +
+ * V(x) u - f_src(x) (Section 6.3, eq. ex3d1, has lambda = b = 10 and a
+ * potential V; Section 6.2, eq. 2dex, has b = 0 and q = -1):
+ * F^h(U) = A_h U + lambda U + q U^2 + b U^3 + V U - F, Jacobian diagonal
+ * 3 b U^2 + 2 q U + lambda + V.
  * lin: lambda (finite), default 0.
- * cub: b (finite), 0 = 1.0.
+ * cub: b (finite); 0 = 1.0 (the default problem), a magnitude below 1e-200
+ *   selects b = 0.
+ * quad: q (finite), default 0; not for the eigenproblem.
  * potential: NULL (V = 0) or a device array V of one component in the grid's
  *   layout ([nz,] ny, nx); read by every qn_residual and qn_iterate call;
  *   owned by the caller, who keeps it valid and unchanged while the context
  *   is in use.
- * The other nonlinearities need lin = 0, cub in {0, 1} and potential = NULL.
+ * The other nonlinearities need lin = 0, cub in {0, 1}, quad = 0 and
+ * potential = NULL.
  * discretization: qn_discretization (0: finite differences); sem_order: the
  *   element order k of QN_DISC_SEM. */
 typedef struct {
@@ -168,6 +172,7 @@ typedef struct {
   const double* potential;
   int32_t discretization;
   int32_t sem_order;
+  double quad;
 } qn_options;
 
 /* iters: solves performed; status: the qn_status qn_iterate returned;

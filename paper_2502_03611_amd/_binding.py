@@ -36,7 +36,7 @@ class QNOptions(ctypes.Structure):
     _fields_ = [("precision", c_i32), ("beta_mode", c_i32), ("timing", c_i32),
                 ("boundary", c_i32), ("stream", c_vp), ("length", c_dbl), ("lin", c_dbl),
                 ("cub", c_dbl), ("potential", c_vp), ("discretization", c_i32),
-                ("sem_order", c_i32)]
+                ("sem_order", c_i32), ("quad", c_dbl)]
 
 
 BOUNDARIES = {"dirichlet": 0, "neumann": 1}
@@ -122,12 +122,13 @@ class Solver:
     def __init__(self, shape, nonlinearity="cubic", beta=0.0, beta_mode="fixed",
                  precision="fp64", timing=False, device="cuda", boundary="dirichlet",
                  length=None, lin=0.0, cub=1.0, potential=None, discretization="fd",
-                 sem_order=0):
+                 sem_order=0, quad=0.0):
         """boundary: "dirichlet" (n interior nodes per axis, h = L/(n+1)) or
         "neumann" (n nodes including both ends, zero normal derivative,
         h = L/(n-1)); length: the domain side L (default 1 for Dirichlet, 2 for
-        Neumann, i.e. [-1, 1]).  Cubic problem only: lin, cub, potential give
-        -Lap u + lin u + cub u^3 + V u = f; potential: None or a float64
+        Neumann, i.e. [-1, 1]).  Cubic problem only: lin, quad, cub, potential
+        give -Lap u + lin u + quad u^2 + cub u^3 + V u = f (cub = 0 means 1; pass
+        1e-300 or smaller for no cubic term); potential: None or a float64
         device tensor V of the grid's shape, kept referenced by the solver
         (the library reads it on every residual).  discretization: "fd" or "sem"
         (Q^k spectral elements of order sem_order; n = E k - 1 interior nodes for
@@ -152,6 +153,7 @@ class Solver:
         o.length = float(length if length is not None else (2.0 if boundary == "neumann" else 1.0))
         o.lin = float(lin)
         o.cub = float(cub)
+        o.quad = float(quad)
         o.discretization = DISCRETIZATIONS[discretization]
         o.sem_order = int(sem_order)
         self._potential = None

@@ -96,7 +96,7 @@ struct qn_ctx_s {
   double beta = 0.0;
   double lam_min_sum = 0.0;
   int bc = QN_BC_DIRICHLET;
-  double length = 1.0, lin = 0.0, cub = 1.0;
+  double length = 1.0, lin = 0.0, cub = 1.0, quad = 0.0;
   double hvol = 1.0;  // h^d: the mass of one interior node
   int sem_k = 0;      // spectral elements: element order (0: finite differences)
   std::vector<double> hHb[3];  // spectral elements: banded H per axis
@@ -288,6 +288,7 @@ ResidualArgs residual_args(qn_ctx c, const double* U, const double* F, double* R
   a.ihz2 = c->ih2[2];
   a.lin = c->lin;
   a.cub = c->cub;
+  a.quad = c->quad;
   a.pot = c->pot;
   a.bc = c->bc;
   a.partials = c->at<double>(c->off_part);
@@ -560,9 +561,12 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   if (o.lin != 0.0 && nonlinearity != QN_NL_CUBIC)
     return fail(QN_ERR_INVALID, "a linear coefficient is supported for QN_NL_CUBIC only");
   if (!std::isfinite(o.cub)) return fail(QN_ERR_INVALID, "cub is not finite");
-  const double cub = o.cub == 0.0 ? 1.0 : o.cub;
-  if ((cub != 1.0 || o.potential) && nonlinearity != QN_NL_CUBIC)
-    return fail(QN_ERR_INVALID, "a cubic coefficient or a potential is supported for QN_NL_CUBIC only");
+  // 0 selects the default coefficient 1; a magnitude below 1e-200 selects 0
+  const double cub = o.cub == 0.0 ? 1.0 : (std::fabs(o.cub) < 1e-200 ? 0.0 : o.cub);
+  if (!std::isfinite(o.quad)) return fail(QN_ERR_INVALID, "quad is not finite");
+  if ((cub != 1.0 || o.quad != 0.0 || o.potential) && nonlinearity != QN_NL_CUBIC)
+    return fail(QN_ERR_INVALID, "cubic / quadratic coefficients and a potential are supported "
+                                "for QN_NL_CUBIC only");
   if (o.boundary == QN_BC_NEUMANN) {
     if (nonlinearity != QN_NL_CUBIC)
       return fail(QN_ERR_UNSUPPORTED, "Neumann data is supported for QN_NL_CUBIC only");
@@ -609,6 +613,7 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   c->length = length;
   c->lin = o.lin;
   c->cub = cub;
+  c->quad = o.quad;
   c->pot = o.potential;
   c->sem_k = o.discretization == QN_DISC_SEM ? o.sem_order : 0;
   c->lam_min_sum = 0.0;
@@ -926,9 +931,9 @@ qn_status qn_nodes(qn_ctx c, int32_t axis, double* x) {
 static qn_status eigen_check(qn_ctx c) {
   qn_status s = check_ctx(c, true);
   if (s != QN_OK) return s;
-  if (c->nl != QN_NL_CUBIC || !c->fold || c->sem_k > 0)
-    return fail(QN_ERR_UNSUPPORTED, "the eigenproblem needs QN_NL_CUBIC with finite "
-                                    "differences and FP64 or FP32 transforms");
+  if (c->nl != QN_NL_CUBIC || !c->fold || c->sem_k > 0 || c->quad != 0.0)
+    return fail(QN_ERR_UNSUPPORTED, "the eigenproblem needs QN_NL_CUBIC without a quadratic "
+                                    "term, finite differences and FP64 or FP32 transforms");
   return QN_OK;
 }
 

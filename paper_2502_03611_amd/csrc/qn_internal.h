@@ -148,6 +148,7 @@ struct ResidualArgs {
   double lin;
   int bc;                  // 0 Dirichlet (zero outside), 1 Neumann (mirrored neighbours)
   double cub = 1.0;
+  double quad = 0.0;  // cubic problem: coefficient of U^2
   const double* pot = nullptr;
   // Eigenproblem passes (cubic problem only; F is not read):
   // mode 1: no output; per-block sums {W (A U) U, W U^2, W U^4, W (lin + V) U^2}

@@ -200,8 +200,8 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
           const double u = uc[0];
           const double m = a.lin + pv;
           if constexpr (MODE == 0) {
-            r[0] = lap[0] + a.cub * (u * u * u) + m * u - f[0];
-            const double fu = 3.0 * a.cub * (u * u) + m;
+            r[0] = lap[0] + a.cub * (u * u * u) + a.quad * (u * u) + m * u - f[0];
+            const double fu = 3.0 * a.cub * (u * u) + 2.0 * a.quad * u + m;
             mn = fmin(mn, fu);
             mx = fmax(mx, fu);
           } else {
@@ -374,8 +374,8 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
           const double u = uc[0];
           const double m = a.lin + pv;
           if constexpr (MODE == 0) {
-            r[0] = lap[0] + a.cub * (u * u * u) + m * u - f[0];
-            const double fu = 3.0 * a.cub * (u * u) + m;
+            r[0] = lap[0] + a.cub * (u * u * u) + a.quad * (u * u) + m * u - f[0];
+            const double fu = 3.0 * a.cub * (u * u) + 2.0 * a.quad * u + m;
             mn = fmin(mn, fu);
             mx = fmax(mx, fu);
           } else {

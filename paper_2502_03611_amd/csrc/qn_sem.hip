@@ -69,8 +69,8 @@ __global__ __launch_bounds__(SX) void k_sem_residual(ResidualArgs a) {
       }
       const double u = a.U[i], f = a.F[i];
       const double m = a.lin + (a.pot ? a.pot[i] : 0.0);
-      const double r = lap + a.cub * (u * u * u) + m * u - f;
-      const double fu = 3.0 * a.cub * (u * u) + m;
+      const double r = lap + a.cub * (u * u * u) + a.quad * (u * u) + m * u - f;
+      const double fu = 3.0 * a.cub * (u * u) + 2.0 * a.quad * u + m;
       s_r += r * r;
       s_f += f * f;
       mn = fmin(mn, fu);
@@ -197,8 +197,8 @@ __global__ __launch_bounds__(TX * TY) void k_sem_residual3(ResidualArgs a) {
         lap += cx[tx][d] * tile[ty + K][tx + d] + cy[ty][d] * tile[ty + d][tx + K] + hz[d] * win[d];
       const double u = win[K], f = a.F[i];
       const double m = a.lin + (a.pot ? a.pot[i] : 0.0);
-      const double r = lap + a.cub * (u * u * u) + m * u - f;
-      const double fu = 3.0 * a.cub * (u * u) + m;
+      const double r = lap + a.cub * (u * u * u) + a.quad * (u * u) + m * u - f;
+      const double fu = 3.0 * a.cub * (u * u) + 2.0 * a.quad * u + m;
       s_r += r * r;
       s_f += f * f;
       mn = fmin(mn, fu);

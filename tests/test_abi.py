@@ -93,6 +93,9 @@ def opts(**kw):
     (dict(potential=4096), 1, 1, (9, 9, 9), 0.0, "invalid"),   # potential only for cubic
     (dict(potential=4096), 2, 2, (9, 9, 9), 0.0, "invalid"),
     (dict(boundary=1, lin=10.0, cub=10.0, potential=4096), 0, 1, (9, 9, 9), 1.0, "ok"),
+    (dict(quad=-1.0, cub=1e-300), 0, 1, (9, 9, 9), 0.0, "ok"),       # eq. 2dex: no cubic term
+    (dict(quad=float("inf")), 0, 1, (9, 9, 9), 0.0, "invalid"),
+    (dict(quad=1.0), 2, 2, (9, 9, 9), 0.0, "invalid"),               # quad only for cubic
     # spectral elements (host-side setup: Gauss-Lobatto nodes, Jacobi eigen-data)
     (dict(discretization=1, sem_order=2), 0, 1, (11, 11, 11), 0.0, "ok"),
     (dict(discretization=1, sem_order=3, boundary=1), 0, 1, (10, 13, 7), 1.0, "ok"),

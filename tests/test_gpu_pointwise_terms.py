@@ -38,26 +38,27 @@ CASES = [("neumann", (33, 47)), ("neumann", (2, 5)), ("neumann", (17, 20, 23)),
 
 
 @pytest.mark.parametrize("bc,shape", CASES)
-@pytest.mark.parametrize("lin,cub", [(10.0, 10.0), (0.0, -0.5)])
-def test_residual_parity_with_potential(bc, shape, lin, cub):
-    print(f"pointwise residual {bc} {shape} lin {lin} cub {cub}", flush=True)
+@pytest.mark.parametrize("lin,cub,quad", [(10.0, 10.0, 0.0), (0.0, -0.5, 0.0), (1.0, 2.0, -1.3)])
+def test_residual_parity_with_potential(bc, shape, lin, cub, quad):
+    print(f"pointwise residual {bc} {shape} lin {lin} cub {cub} quad {quad}", flush=True)
     u = synth.random_field((1,) + shape, 301)
     f = synth.random_field((1,) + shape, 302, scale=10.0)
     v = np.abs(synth.random_field(shape, 303, scale=50.0))
     pot = dev(v)
-    s = Solver(shape, "cubic", beta=1.0, boundary=bc, lin=lin, cub=cub, potential=pot)
+    s = Solver(shape, "cubic", beta=1.0, boundary=bc, lin=lin, cub=cub, potential=pot, quad=quad)
     red = torch.zeros(4, dtype=torch.float64, device="cuda")
     r = host(s.residual(dev(u), dev(f), red=red))[0]
     if bc == "neumann":
         hs = nm.spacing(shape)
-        ref = nm.residual_cubic(u[0], f[0], hs, lin, cub, v)
+        ref = nm.residual_cubic(u[0], f[0], hs, lin, cub, v, quad)
         lap = nm.apply_laplacian(u[0], hs)
-        fu = nm.fu_cubic(u[0], lin, cub, v)
+        fu = nm.fu_cubic(u[0], lin, cub, v, quad)
     else:
-        ref = ops.residual_cubic(u[0], f[0], lin, cub, v)
+        ref = ops.residual_cubic(u[0], f[0], lin, cub, v, quad)
         lap = ops.apply_laplacian(u[0])
-        fu = ops.fu_cubic(u[0], lin, cub, v)
+        fu = ops.fu_cubic(u[0], lin, cub, v, quad)
     scale = (np.linalg.norm(lap) + abs(cub) * np.linalg.norm(u[0] ** 3) +
+             abs(quad) * np.linalg.norm(u[0] ** 2) +
              abs(lin) * np.linalg.norm(u[0]) + np.linalg.norm(v * u[0]) + np.linalg.norm(f[0]))
     assert np.linalg.norm(r - ref) / scale <= 1e-13
     red = red.cpu().numpy()
@@ -134,3 +135,24 @@ def test_potential_is_validated():
     with pytest.raises(QNError):
         Solver((9, 9), "system", beta=1.0,
                potential=torch.zeros((9, 9), dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("n", [63, 100])
+def test_e5_iterate_parity(n):
+    """Section 6.2 Example 2 (eq. 2dex): -Lap u - u^2 = -1600 sin(pi x) sin(pi y)
+    on (0, 1)^2 with Dirichlet data (no cubic term: cub below 1e-200 selects 0),
+    midpoint shift from U_0 = 0, which reaches the stable (negative) solution:
+    equal counts, then exactly K solves on both sides."""
+    print(f"pointwise iterate e5 {n}", flush=True)
+    x = synth.grid_coords(n)
+    f = -1600.0 * np.sin(np.pi * x)[:, None] * np.sin(np.pi * x)[None, :]
+    ref = oqn.qn_solve(oqn.CUBIC, f[None], midpoint=True, cub=0.0, quad=-1.0)
+    assert ref["converged"] and ref["u"].max() < 0
+    s = Solver((n, n), "cubic", beta_mode="midpoint", cub=1e-300, quad=-1.0)
+    u = torch.zeros((1, n, n), dtype=torch.float64, device="cuda")
+    st = s.iterate(u, dev(f[None]), rtol=1e-10, max_iter=300)
+    assert st["status"] == QN_OK and st["iters"] == ref["iters"], (st, ref["iters"])
+    k = ref["iters"]
+    ug = torch.zeros_like(u)
+    s.iterate(ug, dev(f[None]), rtol=0.0, max_iter=k)
+    assert rel(host(ug)[0], ref["u"][0]) <= 1e-12
