@@ -117,6 +117,20 @@ def library_gemm_reference():
     return {"kernel": "torch.matmul, 8192 x 8192 x 8192", **out}
 
 
+def mfma_probe():
+    """Dense rates of register-only MFMA chains (qn_probe_mfma) in TFLOP/s,
+    beside the published peaks: a lower bound of the device's matrix-core
+    ceiling (the compiler moves the accumulators between register files every
+    four rounds; the vendor GEMM reference can exceed it)."""
+    from paper_2502_03611_amd._binding import probe_mfma
+    out = {}
+    for prec, key, peak in (("fp64", "fp64", PEAK_FP64_TFLOPS), ("fp32", "fp32", PEAK_FP32_TFLOPS),
+                            ("bf16x3", "bf16", PEAK_BF16_TFLOPS)):
+        v = probe_mfma(prec)
+        out[key] = {"tflops": round(v, 1), "frac_of_published": round(v / peak, 3)}
+    return out
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -799,6 +813,7 @@ def main():
                               "algorithmic_bytes_per_launch": r_bytes,
                               "stream_reference": stream_reference(n)},
         "library_gemm_reference": library_gemm_reference(),
+        "mfma_probe": mfma_probe(),
         "all_mode_products_tflops": round(flops_per_product * all_gemm_launches /
                                           (all_gemm_ms * 1e-3) / 1e12, 3),
         "all_mode_products_dense_equivalent_tflops": round(dense_flops * all_gemm_launches /
@@ -846,6 +861,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, amp)
+    probe64 = out["mfma_probe"]["fp64"]["tflops"]
+    out["roofline"]["frac_of_fp64_mfma_probe"] = round(out["roofline"]["achieved"] / probe64, 4)
     print(json.dumps(out))
 
 

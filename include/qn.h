@@ -283,6 +283,18 @@ qn_status qn_eigen_residual(qn_ctx ctx, const double* d_U, double* d_R, double* 
 qn_status qn_eigen_iterate(qn_ctx ctx, double* d_U, double rtol, int32_t max_iter,
                            qn_stats* stats, double* lam_out);
 
+/* Matrix-core throughput probe (measurement only, not a step of the solver):
+ * a register-only chain of 16x16x4 FP64 (QN_PREC_FP64), 16x16x4 FP32
+ * (QN_PREC_FP32) or 16x16x32 bf16 (QN_PREC_BF16X3) MFMA instructions on
+ * 8192 waves, timed with HIP events on `stream` (NULL = default); *tflops
+ * receives the dense rate reached, the ceiling the mode-product kernels are
+ * compared with beside the published peak.  d_sink: caller-owned device
+ * memory of at least qn_probe_sink_bytes() bytes (overwritten).  Synchronous.
+ * Errors: QN_ERR_INVALID (null or short sink, other precision), QN_ERR_HIP. */
+size_t qn_probe_sink_bytes(void);
+qn_status qn_probe_mfma(int32_t precision, void* d_sink, size_t bytes, void* stream,
+                        double* tflops);
+
 /* Tile selection for the mode products (Section 4.1, eq. fin_inverse, as
  * reflection-folded matrix-core products).  The solve is a fixed list of
  * launches (3D: 6, 2D: 4; the x forward product first, the x inverse product

@@ -82,6 +82,10 @@ def lib():
     L.qn_eigen_iterate.argtypes = [c_vp, c_vp, c_dbl, c_i32, ctypes.POINTER(QNStats),
                                    ctypes.POINTER(c_dbl)]
     L.qn_nodes.argtypes = [c_vp, c_i32, c_vp]
+    L.qn_probe_sink_bytes.argtypes = []
+    L.qn_probe_sink_bytes.restype = ctypes.c_size_t
+    L.qn_probe_mfma.argtypes = [c_i32, c_vp, ctypes.c_size_t, c_vp, ctypes.POINTER(c_dbl)]
+    L.qn_probe_mfma.restype = c_i32
     L.qn_autotune.argtypes = [c_vp]
     L.qn_tile_info.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i32)]
     L.qn_set_tile.argtypes = [c_vp, c_i32, ctypes.POINTER(c_i32)]
@@ -307,3 +311,15 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def probe_mfma(precision="fp64", device="cuda"):
+    """Dense MFMA rate (TFLOP/s) of a register-only instruction chain (see
+    qn_probe_mfma): the measured matrix-core ceiling of this device."""
+    L = lib()
+    sink = torch.empty(L.qn_probe_sink_bytes(), dtype=torch.uint8, device=device)
+    out = c_dbl()
+    stream = torch.cuda.current_stream(device).cuda_stream
+    check(L.qn_probe_mfma(PRECISIONS[precision], c_vp(sink.data_ptr()), sink.numel(),
+                          c_vp(stream), ctypes.byref(out)))
+    return out.value

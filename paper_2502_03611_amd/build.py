@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libqn.so")
 
-SOURCES = ["qn_gemm_fold.hip", "qn_gemm_bf16.hip", "qn_pointwise.hip", "qn_sem.hip", "qn_api.cpp", "qnn.hip", "qnn_api.cpp", "qn_batched.cpp"]
+SOURCES = ["qn_gemm_fold.hip", "qn_gemm_bf16.hip", "qn_pointwise.hip", "qn_sem.hip", "qn_probe.hip", "qn_api.cpp", "qnn.hip", "qnn_api.cpp", "qn_batched.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
