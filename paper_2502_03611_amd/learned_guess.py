@@ -4,7 +4,7 @@ Pipeline (include/qnn.h): v0 = A_h^-1 f (tensor-product solve), the network
 predicts g ~ U*^3 from (f / 50, v0), and U_0 = A_h^-1 (f - g) (second solve);
 U_0 = 0 is used instead when the guess's residual is not smaller than that of
 U_0 = 0.  Every step (solves, forward, loss, backward, Adam) runs in libqn's
-HIP kernels.  This module is the thin driver: ctypes marshalling,
+HIP kernels.  This module is a thin wrapper: ctypes marshalling,
 solver-generated training data, the mini-batch loop and the evaluation.
 """
 
