@@ -320,6 +320,8 @@ def probe_mfma(precision="fp64", device="cuda"):
     sink = torch.empty(L.qn_probe_sink_bytes(), dtype=torch.uint8, device=device)
     out = c_dbl()
     stream = torch.cuda.current_stream(device).cuda_stream
-    check(L.qn_probe_mfma(PRECISIONS[precision], c_vp(sink.data_ptr()), sink.numel(),
-                          c_vp(stream), ctypes.byref(out)))
+    st = L.qn_probe_mfma(PRECISIONS[precision], c_vp(sink.data_ptr()), sink.numel(),
+                         c_vp(stream), ctypes.byref(out))
+    if st != QN_OK:  # the probe records no message of its own
+        raise QNError(st, "qn_probe_mfma failed: precision must be fp64, fp32 or bf16x3")
     return out.value
