@@ -599,6 +599,25 @@ def cpu_baseline(n, amp):
                       f"(NumPy FP64 oracle, {dt:.1f} s)"}
 
 
+def cpu_baseline_one_thread(n=127):
+    """The same oracle on one host thread (BLAS limited to 1), on a smaller
+    bounded sample: one quasi-Newton iteration of the quasi-linear workload at
+    n^3 = 127^3 (1/64 of the unknowns).  Returns iterations per second."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import qn as oqn
+
+    _, f = synth.manufactured_c3(n, synth.amplitude_c3(0))
+    log(f"cpu baseline: one oracle iteration on one thread at {n}^3")
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        oqn.qn_solve(oqn.QUASILINEAR, f[None], rtol=0.0, max_iter=1)
+        dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 quasi-Newton iteration of the quasi-linear workload at {n}^3 "
+                      f"(NumPy FP64 oracle, BLAS on one thread, {dt:.1f} s)"}
+
+
 def bench_batched(count):
     """Batched workload: `count` 2D instances, N drawn from {63, ..., 1023}, even
     instances scalar -Lap u + u^3 = f, odd ones the 2-component system, unit-variance
@@ -861,6 +880,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, amp)
+        out["cpu_baseline_one_thread"] = cpu_baseline_one_thread()
     probe64 = out["mfma_probe"]["fp64"]["tflops"]
     out["roofline"]["frac_of_fp64_mfma_probe"] = round(out["roofline"]["achieved"] / probe64, 4)
     print(json.dumps(out))
