@@ -339,6 +339,81 @@ def paper_tables(seeds2d, seeds3d):
     return out
 
 
+def batched_tables(seeds):
+    """The 2D rows of Table results2d_space (eq. ex2d1, midpoint shift) with
+    all perturbed starts of one size solved together by the batched solver
+    (one instance per seed, Neumann data, FP64 and FP32 transforms), against
+    the same starts solved one after another by the single-problem solver.
+    Seconds: the whole batch, inputs resident in HBM, after an untimed solve
+    of the same batch (graph capture, autotuning)."""
+    from paper_2502_03611_amd.batched import BatchedSolver
+    out = []
+    for n in (200, 400, 800, 1600):
+        log(f"batched table 2D n={n}, {seeds} starts")
+        u_ex, f = e4_inputs(n)
+        s = Solver((n, n), "cubic", beta_mode="midpoint", boundary="neumann", length=2.0, lin=1.0)
+        s.autotune()
+        Ustar = u_ex[None].clone()
+        s.iterate(Ustar, f[None].contiguous(), rtol=1e-12, max_iter=60)
+        starts = [Ustar[0] + 0.1 * perturbation(n, 2, seed) for seed in range(seeds)]
+        rec = {"n": n, "instances": seeds}
+        # one after another (the single-problem solver, FP64)
+        U1 = torch.empty_like(Ustar)
+        F1 = f[None].contiguous()
+        U1.copy_(starts[0][None])
+        s.iterate(U1, F1, rtol=1e-10, max_iter=500)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        seq_iters = []
+        for u0 in starts:
+            U1.copy_(u0[None])
+            seq_iters.append(s.iterate(U1, F1, rtol=1e-10, max_iter=500)["iters"])
+        torch.cuda.synchronize()
+        rec["sequential_fp64"] = {"seconds": round(time.perf_counter() - t0, 4),
+                                  "iters_mean": round(float(np.mean(seq_iters)), 2)}
+        s.close()
+        for prec in ("fp64", "fp32"):
+            b = BatchedSolver([n] * seeds, [1] * seeds, precision=prec, beta_mode="midpoint",
+                              boundary="neumann", length=2.0, lin=1.0)
+            U, F = b.pool(), b.pool()
+            for i in range(seeds):
+                b.view(F, i)[0].copy_(f)
+            b.autotune()
+
+            def fill():
+                for i, u0 in enumerate(starts):
+                    b.view(U, i)[0].copy_(u0)
+
+            fill()
+            b.iterate(U, F, rtol=1e-10, max_iter=500, graph_iters=4)  # capture + warm-up
+            fill()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            status, res = b.iterate(U, F, rtol=1e-10, max_iter=500, graph_iters=4)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            its = [r["iters"] for r in res]
+            err = max(float((b.view(U, i)[0] - u_ex).abs().max()) for i in range(seeds))
+            rec[f"batched_{prec}"] = {"seconds": round(dt, 4),
+                                      "seconds_per_start": round(dt / seeds, 6),
+                                      "iters_mean": round(float(np.mean(its)), 2),
+                                      "iters_std": round(float(np.std(its)), 2),
+                                      "not_converged": sum(r["status"] != 0 for r in res),
+                                      "iters_equal_sequential": int(sum(
+                                          a == c for a, c in zip(its, seq_iters))),
+                                      "max_err_vs_exact": err}
+            log(f"  n={n} batched {prec}: {dt:.4f} s for {seeds} starts "
+                f"(sequential fp64 {rec['sequential_fp64']['seconds']} s), "
+                f"iters {rec[f'batched_{prec}']['iters_mean']}")
+            b.close()
+            del U, F, b
+            torch.cuda.empty_cache()
+        out.append(rec)
+        del u_ex, f, Ustar, U1, F1, starts
+        torch.cuda.empty_cache()
+    return out
+
+
 def beta_tables(seeds2d, seeds3d):
     """Tables results2d1 (eq. ex2d1 on 50^2 nodes) and results3D (eq. ex3d1 on
     200^3 nodes) of the paper: for each perturbation scale eps in {0.1, 0.2,
@@ -708,6 +783,9 @@ def main():
     ap.add_argument("--e5-table", action="store_true",
                     help="also run the paper's table for -Lap u - u^2 = -1600 sin sin (2D, "
                          "Dirichlet; 200^2 .. 1600^2, perturbed stable solution)")
+    ap.add_argument("--batched-tables", action="store_true",
+                    help="also solve the 2D rows of the paper's Neumann mesh table with all "
+                         "perturbed starts of a size in one batch (--table-seeds starts)")
     ap.add_argument("--beta-tables", action="store_true",
                     help="also run the paper's shift-rule tables over perturbation scales "
                          "(eq. ex2d1 at 50^2, eq. ex3d1 at 200^3)")
@@ -859,6 +937,9 @@ def main():
         out["amplitude_sweep"] = amplitude_sweep(n, args.ttt_runs)
     if args.paper_tables:
         out["paper_tables"] = paper_tables(args.table_seeds, args.table_seeds)
+        torch.cuda.empty_cache()
+    if args.batched_tables:
+        out["batched_tables"] = batched_tables(args.table_seeds)
         torch.cuda.empty_cache()
     if args.e5_table:
         out["e5_table"] = e5_table(args.table_seeds)

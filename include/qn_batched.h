@@ -1,6 +1,6 @@
 /*
  * qn_batched.h - C ABI of the batched quasi-Newton solver: many independent
- * 2D instances of uneven size, scalar -Lap u + u^3 = f and 2-component
+ * 2D instances of uneven size, scalar -Lap u + lin u + u^3 = f and 2-component
  * systems -Lap u + u^3 - v = f1, -Lap v + v^3 - u = f2 (Section 4.3,
  * eq. system), each iterated with the quasi-Newton step of Section 4
  * (eq. identity-method) and the tensor-product solve of Section 4.1
@@ -49,9 +49,39 @@ typedef struct {
 /* count instances (1..65536); n[i] interior points per side (1..4096);
  * ncomp[i] in {1, 2}; precision: qn_precision of the transforms (FP64, FP32
  * or BF16X3; QN_PREC_BF16X6 is rejected with QN_ERR_INVALID); beta_mode
- * and beta as in qn_setup (applied to every instance).  Host only. */
+ * (QN_BETA_FIXED or QN_BETA_MIDPOINT) and beta as in qn_setup (applied to
+ * every instance).  Every instance lives on the unit square with Dirichlet
+ * data.  Host only. */
 qn_status qnb_setup(int32_t count, const int32_t* n, const int32_t* ncomp, int32_t precision,
                     int32_t beta_mode, double beta, qnb_ctx* out);
+
+/* Problem options shared by every instance of a batch (qnb_setup_ex):
+ *   boundary  qn_boundary.  QN_BC_DIRICHLET: n[i] interior points per side,
+ *             h = length / (n[i] + 1).  QN_BC_NEUMANN: zero normal derivative
+ *             by ghost nodes (Section 3.2), all n[i] nodes of the closed
+ *             square are unknowns, h = length / (n[i] - 1); the 1D factors are
+ *             the cosine eigenpairs, whose lowest eigenvalue is 0.
+ *   length    side of the square (0 means 1).
+ *   lin       coefficient of the linear term of the scalar problem
+ *             -Lap u + lin u + u^3 = f (Section 6.2, Example 1, eq. ex2d1 has
+ *             lin = 1 with Neumann data); its Jacobian diagonal is 3 u^2 + lin.
+ */
+typedef struct {
+  int32_t boundary;
+  double length;
+  double lin;
+} qnb_options;
+
+/* qnb_setup with options (NULL: the defaults of qnb_setup).  Besides the
+ * checks of qnb_setup, QN_ERR_INVALID for: an unknown boundary; a length
+ * that is negative or not finite; a lin that is not finite; lin != 0 with a
+ * 2-component instance; Neumann data with n[i] < 2, a 2-component instance
+ * or BF16X3 transforms; and a shift that can reach the zero eigenvalue of
+ * the Neumann operator: a fixed beta <= 0, or the midpoint rule with
+ * lin <= 0 (with lin > 0 the midpoint of 3 u^2 + lin is at least lin).
+ * Host only. */
+qn_status qnb_setup_ex(int32_t count, const int32_t* n, const int32_t* ncomp, int32_t precision,
+                       int32_t beta_mode, double beta, const qnb_options* opt, qnb_ctx* out);
 qn_status qnb_field_elems(qnb_ctx ctx, int64_t* elems);
 qn_status qnb_instance_layout(qnb_ctx ctx, int32_t i, int64_t* offset, int64_t* comp_stride);
 qn_status qnb_workspace_bytes(qnb_ctx ctx, size_t* bytes);

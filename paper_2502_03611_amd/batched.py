@@ -7,9 +7,13 @@ import ctypes
 import numpy as np
 import torch
 
-from ._binding import BETA_MODES, PRECISIONS, c_vp, check, lib, last_error
+from ._binding import BETA_MODES, BOUNDARIES, PRECISIONS, c_vp, check, lib, last_error
 
 _B = None
+
+
+class QNBOptions(ctypes.Structure):
+    _fields_ = [("boundary", ctypes.c_int32), ("length", ctypes.c_double), ("lin", ctypes.c_double)]
 
 
 class QNBResult(ctypes.Structure):
@@ -26,6 +30,8 @@ def _qnb():
     i64p = ctypes.POINTER(ctypes.c_int64)
     L.qnb_setup.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int32, ctypes.c_int32,
                             ctypes.c_double, ctypes.POINTER(c_vp)]
+    L.qnb_setup_ex.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int32, ctypes.c_int32,
+                               ctypes.c_double, ctypes.POINTER(QNBOptions), ctypes.POINTER(c_vp)]
     L.qnb_field_elems.argtypes = [c_vp, i64p]
     L.qnb_instance_layout.argtypes = [c_vp, ctypes.c_int32, i64p, i64p]
     L.qnb_workspace_bytes.argtypes = [c_vp, ctypes.POINTER(ctypes.c_size_t)]
@@ -38,7 +44,7 @@ def _qnb():
                               ctypes.POINTER(QNBResult)]
     L.qnb_destroy.argtypes = [c_vp]
     L.qnb_destroy.restype = None
-    for n in ("qnb_setup", "qnb_field_elems", "qnb_instance_layout", "qnb_workspace_bytes",
+    for n in ("qnb_setup", "qnb_setup_ex", "qnb_field_elems", "qnb_instance_layout", "qnb_workspace_bytes",
               "qnb_bind_workspace", "qnb_set_stream", "qnb_autotune", "qnb_class_count",
               "qnb_class_info", "qnb_iterate"):
         getattr(L, n).restype = ctypes.c_int32
@@ -47,11 +53,15 @@ def _qnb():
 
 
 class BatchedSolver:
-    """Independent 2D instances: sizes[i] interior points per side, ncomp[i]
-    in {1 (cubic), 2 (system)}; one U pool and one F pool of FP64 on the GPU."""
+    """Independent 2D instances: sizes[i] points per side (interior points
+    with Dirichlet data, all nodes with Neumann data), ncomp[i] in {1 (cubic),
+    2 (system)}; one U pool and one F pool of FP64 on the GPU.  boundary,
+    length (the side of the square; default 1 for Dirichlet, 2 for Neumann
+    data, as for the single-problem solver) and lin apply to every instance
+    (qnb_options)."""
 
     def __init__(self, sizes, ncomp, precision="fp32", beta_mode="midpoint", beta=0.0,
-                 device="cuda"):
+                 device="cuda", boundary="dirichlet", length=None, lin=0.0):
         L = _qnb()
         self.count = len(sizes)
         self.sizes = [int(s) for s in sizes]
@@ -60,8 +70,12 @@ class BatchedSolver:
         n_arr = (ctypes.c_int32 * self.count)(*self.sizes)
         c_arr = (ctypes.c_int32 * self.count)(*self.ncomp)
         ctx = c_vp()
-        check(L.qnb_setup(self.count, n_arr, c_arr, PRECISIONS[precision], BETA_MODES[beta_mode],
-                          float(beta), ctypes.byref(ctx)))
+        if length is None:
+            length = 2.0 if boundary == "neumann" else 1.0
+        opt = QNBOptions(BOUNDARIES[boundary], float(length), float(lin))
+        check(L.qnb_setup_ex(self.count, n_arr, c_arr, PRECISIONS[precision],
+                             BETA_MODES[beta_mode], float(beta), ctypes.byref(opt),
+                             ctypes.byref(ctx)))
         self._ctx = ctx
         fe = ctypes.c_int64()
         check(L.qnb_field_elems(ctx, ctypes.byref(fe)))

@@ -48,6 +48,7 @@ struct Cls {
   // inverse and x inverse (+ update) launches
   FoldTile fR{32, 32, 0}, fL{32, 32, 0}, fLi{32, 32, 0}, fRi{32, 32, 0};
   FoldAxis ax{};
+  double ih2 = 0.0;           // 1 / h^2 of both axes
   hipStream_t s = nullptr;    // per-class stream (default priority)
   hipEvent_t ev = nullptr;
   std::vector<double> hS, hlam;
@@ -59,6 +60,8 @@ struct qnb_ctx_s {
   int count = 0, prec = 0, beta_mode = 0;
   bool fold = true;  // reflection-folded transforms (FP64/FP32); dense for split-bf16
   double beta = 0.0;
+  int bc = QN_BC_DIRICHLET;
+  double length = 1.0, lin = 0.0;
   std::vector<int> n, ncomp, inst_cls, inst_pos;
   std::vector<Cls> cls;
   long long field_elems = 0;
@@ -140,7 +143,9 @@ hipError_t class_iteration(qnb_ctx c, Cls& k, double* U, const double* F, double
   a.nz = k.K;
   a.dim = 2;
   a.nl = k.ncomp == 2 ? NL_SYS2 : NL_CUBIC;
-  a.ihx2 = a.ihy2 = (double)(k.n + 1) * (k.n + 1);
+  a.bc = c->bc;
+  a.lin = c->lin;
+  a.ihx2 = a.ihy2 = k.ih2;
   a.ihz2 = 0.0;
   a.partials = (double*)(c->ws + k.off_part);
   a.rz = RESIDUAL_PLANAR_ROWS;
@@ -211,17 +216,49 @@ extern "C" {
 
 qn_status qnb_setup(int32_t count, const int32_t* n, const int32_t* ncomp, int32_t precision,
                     int32_t beta_mode, double beta, qnb_ctx* out) {
+  return qnb_setup_ex(count, n, ncomp, precision, beta_mode, beta, nullptr, out);
+}
+
+qn_status qnb_setup_ex(int32_t count, const int32_t* n, const int32_t* ncomp, int32_t precision,
+                       int32_t beta_mode, double beta, const qnb_options* opt, qnb_ctx* out) {
   if (!out || !n || !ncomp) return bad(QN_ERR_INVALID, "null argument");
   if (count < 1 || count > 65536) return bad(QN_ERR_INVALID, "count must be in [1, 65536]");
   if (precision < 0 || precision > 2) return bad(QN_ERR_INVALID, "unknown precision");
   if (beta_mode < 0 || beta_mode > 1) return bad(QN_ERR_INVALID, "unknown beta_mode");
   if (!std::isfinite(beta)) return bad(QN_ERR_INVALID, "beta not finite");
+  qnb_options o{QN_BC_DIRICHLET, 1.0, 0.0};
+  if (opt) o = *opt;
+  if (o.boundary != QN_BC_DIRICHLET && o.boundary != QN_BC_NEUMANN)
+    return bad(QN_ERR_INVALID, "unknown boundary");
+  if (!std::isfinite(o.length) || o.length < 0.0)
+    return bad(QN_ERR_INVALID, "length must be finite and >= 0 (0 means 1)");
+  if (o.length == 0.0) o.length = 1.0;
+  if (!std::isfinite(o.lin)) return bad(QN_ERR_INVALID, "lin not finite");
+  const bool neu = o.boundary == QN_BC_NEUMANN;
+  if (neu && precision == QN_PREC_BF16X3)
+    return bad(QN_ERR_INVALID, "Neumann data needs FP64 or FP32 transforms");
+  // The Neumann operator has the eigenvalue 0 (constant mode): the shift must
+  // stay positive.  The midpoint of 3 u^2 + lin is at least lin.
+  if (neu && beta_mode == QN_BETA_FIXED && !(beta > 0.0))
+    return bad(QN_ERR_INVALID, "Neumann data needs a fixed beta > 0");
+  if (neu && beta_mode == QN_BETA_MIDPOINT && !(o.lin > 0.0))
+    return bad(QN_ERR_INVALID, "Neumann data with the midpoint rule needs lin > 0");
   std::map<std::pair<int, int>, int> key;
+  for (int i = 0; i < count; ++i) {
+    if (ncomp[i] == 2 && (neu || o.lin != 0.0))
+      return set_error(QN_ERR_INVALID, "instance %d: the 2-component system takes neither "
+                                       "Neumann data nor lin", i);
+    if (neu && n[i] < 2)
+      return set_error(QN_ERR_INVALID, "instance %d: Neumann data needs n >= 2", i);
+  }
   qnb_ctx c = new qnb_ctx_s();
   c->count = count;
   c->prec = precision;
   c->beta_mode = beta_mode;
   c->beta = beta;
+  c->bc = o.boundary;
+  c->length = o.length;
+  c->lin = o.lin;
   c->n.assign(n, n + count);
   c->ncomp.assign(ncomp, ncomp + count);
   c->inst_cls.resize(count);
@@ -260,10 +297,19 @@ qn_status qnb_setup(int32_t count, const int32_t* n, const int32_t* ncomp, int32
   size_t off = 0;
   c->fold = precision != QN_PREC_BF16X3;
   for (auto& k : c->cls) {
-    if (c->fold)
-      fold_eigen(k.n, k.ax.bk, k.hS, k.hlam);
-    else
-      dense_eigen(k.n, k.p, k.hS, k.hlam);
+    const double ih = (c->bc == QN_BC_NEUMANN ? k.n - 1 : k.n + 1) / c->length;
+    k.ih2 = ih * ih;
+    if (c->bc == QN_BC_NEUMANN) {
+      fold_cosine(k.n, k.ih2, k.ax.bk, k.hS, k.hlam);
+    } else {
+      if (c->fold)
+        fold_eigen(k.n, k.ax.bk, k.hS, k.hlam);
+      else
+        dense_eigen(k.n, k.p, k.hS, k.hlam);
+      // the sine eigenvalues are for the unit interval
+      if (c->length != 1.0)
+        for (double& l : k.hlam) l /= c->length * c->length;
+    }
     lam_min = std::min(lam_min, 2.0 * k.hlam[0]);
     k.off_field = fe;
     fe += (long long)k.ncomp * k.K * k.n * k.n;

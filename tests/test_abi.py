@@ -230,6 +230,55 @@ def test_qnb_setup_rejects_invalid(n, nc, prec, bmode, beta):
     assert qn.last_error()
 
 
+class _QNBOptions(ctypes.Structure):
+    _fields_ = [("boundary", ctypes.c_int32), ("length", ctypes.c_double), ("lin", ctypes.c_double)]
+
+
+def _qnb_setup_ex(n, nc, opt, prec=1, bmode=1, beta=0.0):
+    L = qn.lib()
+    L.qnb_setup_ex.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                               ctypes.c_int32, ctypes.c_double, ctypes.c_void_p,
+                               ctypes.POINTER(ctypes.c_void_p)]
+    L.qnb_destroy.argtypes = [ctypes.c_void_p]
+    L.qnb_destroy.restype = None
+    a = (ctypes.c_int32 * len(n))(*n)
+    b = (ctypes.c_int32 * len(nc))(*nc)
+    ctx = ctypes.c_void_p()
+    o = ctypes.byref(_QNBOptions(*opt)) if opt is not None else None
+    st = L.qnb_setup_ex(len(n), a, b, prec, bmode, beta, o, ctypes.byref(ctx))
+    if st == qn.QN_OK:
+        L.qnb_destroy(ctx)
+    return st
+
+
+@pytest.mark.parametrize("n,nc,opt,prec,bmode,beta", [
+    ([9], [1], (2, 1.0, 0.0), 1, 1, 0.0),                      # unknown boundary
+    ([9], [1], (0, -1.0, 0.0), 1, 1, 0.0),                     # negative length
+    ([9], [1], (0, float("nan"), 0.0), 1, 1, 0.0),
+    ([9], [1], (0, 1.0, float("inf")), 1, 1, 0.0),             # lin not finite
+    ([9], [2], (0, 1.0, 1.0), 1, 1, 0.0),                      # lin on the system
+    ([9], [2], (1, 1.0, 1.0), 1, 1, 0.0),                      # Neumann system
+    ([1], [1], (1, 1.0, 1.0), 1, 1, 0.0),                      # Neumann n = 1
+    ([9], [1], (1, 1.0, 1.0), 2, 1, 0.0),                      # Neumann with bf16x3
+    ([9], [1], (1, 1.0, 1.0), 1, 0, 0.0),                      # Neumann fixed beta = 0
+    ([9], [1], (1, 1.0, 0.0), 1, 1, 0.0),                      # Neumann midpoint, lin = 0
+    ([9, 12], [1, 1], (0, 1.0, 0.0), 1, 0, -2.0 * 9.8),        # fixed beta below -lam_min
+])
+def test_qnb_setup_ex_rejects_invalid(n, nc, opt, prec, bmode, beta):
+    assert _qnb_setup_ex(n, nc, opt, prec, bmode, beta) == qn.QN_ERR_INVALID
+    assert qn.last_error()
+
+
+@pytest.mark.parametrize("n,nc,opt,prec,bmode,beta", [
+    ([9, 12, 9], [1, 1, 1], (1, 2.0, 1.0), 1, 1, 0.0),
+    ([9, 12], [1, 1], (1, 2.0, 0.0), 0, 0, 3.0),
+    ([9, 12], [1, 2], (0, 2.0, 0.0), 2, 1, 0.0),
+    ([9], [1], None, 1, 1, 0.0),
+])
+def test_qnb_setup_ex_accepts(n, nc, opt, prec, bmode, beta):
+    assert _qnb_setup_ex(n, nc, opt, prec, bmode, beta) == qn.QN_OK
+
+
 def test_qnb_layout_covers_pool_exactly():
     L = _qnb()
     n = [15, 31, 15, 8, 31, 15]

@@ -92,3 +92,47 @@ def test_max_iter_reported_per_instance():
     assert status == 3
     assert all(r["iters"] <= 2 for r in res)
     assert any(r["status"] == 3 for r in res)
+
+
+NEU_SIZES = [17, 33, 40, 64, 17, 33, 129, 40]
+
+
+@pytest.mark.parametrize("prec,mode,beta", [("fp64", "midpoint", 0.0), ("fp32", "midpoint", 0.0),
+                                            ("fp64", "fixed", 3.0)])
+def test_batched_neumann_matches_single_instance_and_oracle(prec, mode, beta):
+    """Section 6.2, Example 1 (eq. ex2d1): -Lap u + u + u^3 = f on [-1, 1]^2
+    with zero normal derivative, every instance started from the sampled
+    exact solution plus 0.1 times its own seeded degree-4 polynomial (the
+    paper's perturbed starts, here one batch instead of one solve each).
+    Against the single-problem solver: equal counts and iterates to 1e-12;
+    against the oracle: equal counts (FP64) and the rtol bound."""
+    from oracle import neumann as nm
+    print(f"batched neumann {prec} {mode}", flush=True)
+    b = BatchedSolver(NEU_SIZES, [1] * len(NEU_SIZES), precision=prec, beta_mode=mode, beta=beta,
+                      boundary="neumann", length=2.0, lin=1.0)
+    U, F = b.pool(), b.pool()
+    starts, srcs = [], []
+    for i, n in enumerate(NEU_SIZES):
+        u, f = synth.neumann_2d(n)
+        u0 = u + 0.1 * synth.polynomial_perturbation(n, 2, i)
+        starts.append(u0)
+        srcs.append(f)
+        b.fill(U, i, u0[None])
+        b.fill(F, i, f[None])
+    status, res = b.iterate(U, F, rtol=1e-10, max_iter=200, graph_iters=4)
+    assert status == 0, res
+    for i, n in enumerate(NEU_SIZES):
+        ub = b.view(U, i).cpu().numpy()[0]
+        s = Solver((n, n), "cubic", boundary="neumann", length=2.0, lin=1.0, beta_mode=mode,
+                   beta=beta, precision=prec)
+        u1 = torch.from_numpy(starts[i][None].copy()).cuda()
+        st = s.iterate(u1, torch.from_numpy(srcs[i][None].copy()).cuda(), rtol=1e-10, max_iter=200)
+        assert res[i]["iters"] == st["iters"], (i, res[i], st)
+        assert np.linalg.norm(ub - u1.cpu().numpy()[0]) <= 1e-12 * np.linalg.norm(ub)
+        ref = nm.qn_solve(srcs[i], nm.spacing((n, n)), lin=1.0, u0=starts[i], beta=beta,
+                          midpoint=mode == "midpoint", rtol=1e-10, max_iter=200)
+        assert ref["converged"]
+        assert abs(res[i]["iters"] - ref["iters"]) <= (0 if prec == "fp64" else 1), (i, res[i])
+        # both stopped at relres <= 1e-10 and the Jacobian is >= lin = 1:
+        # |U_b - U_o| <= 2 rtol |F| / 1
+        assert np.linalg.norm(ub - ref["u"]) <= 2e-10 * np.linalg.norm(srcs[i])
