@@ -44,14 +44,14 @@ PEAK_HBM_GBS = 8000.0
 # calibrated on a plain 1 GiB device copy), keyed by kernel.  Each figure is
 # valid only while the source file it was taken on is unchanged.
 TRAFFIC_SOURCES = {"fold": ("paper_2502_03611_amd/csrc/qn_gemm_fold.hip", "c13f02002af662fc"),
-                   "pointwise": ("paper_2502_03611_amd/csrc/qn_pointwise.hip", "7ee66e9d31cc72f5")}
+                   "pointwise": ("paper_2502_03611_amd/csrc/qn_pointwise.hip", "8bb0643855198d0a")}
 TRAFFIC = {"k_fold_right_fwd<double,64,128,0>": ("fold", 1.4505e+09, 1.0737e+09),
            "k_fold_right_fwd<double,128,128,0>": ("fold", 1.2723e+09, 1.0737e+09),
            "k_fold_left_fwd2<double,64,64,EPI_STORE,0>": ("fold", 1.4559e+09, 1.0737e+09),
            "k_fold_left_fwd2<double,64,64,EPI_DIVIDE,0>": ("fold", 1.4324e+09, 1.0737e+09),
            "k_fold_left_inv<double,64,64,0>": ("fold", 1.3846e+09, 1.0716e+09),
            "k_fold_right_inv<double,64,64,EPI_SUB_DENSE,0>": ("fold", 2.4518e+09, 1.0725e+09),
-           "k_residual<QUASILIN,double>": ("pointwise", 2.2814e+09, 1.0739e+09)}
+           "k_residual<QUASILIN,double>": ("pointwise", 2.2840e+09, 1.0739e+09)}
 
 
 def traffic_if_current(kernel, n):
@@ -340,10 +340,12 @@ def paper_tables(seeds2d, seeds3d):
 
 
 def batched_tables(seeds):
-    """The 2D rows of Table results2d_space (eq. ex2d1, midpoint shift) with
-    all perturbed starts of one size solved together by the batched solver
-    (one instance per seed, Neumann data, FP64 and FP32 transforms), against
-    the same starts solved one after another by the single-problem solver.
+    """The 2D rows of Table results2d_space (eq. ex2d1) with all perturbed
+    starts of one size solved together by the batched solver (one instance
+    per seed, Neumann data): the midpoint shift with FP64 and FP32 transforms
+    and the table's other rules (beta = 3, min + max, max, min; FP64); the
+    midpoint FP64 batch against the same starts solved one after another by
+    the single-problem solver.
     Seconds: the whole batch, inputs resident in HBM, after an untimed solve
     of the same batch (graph capture, autotuning)."""
     from paper_2502_03611_amd.batched import BatchedSolver
@@ -372,8 +374,12 @@ def batched_tables(seeds):
         rec["sequential_fp64"] = {"seconds": round(time.perf_counter() - t0, 4),
                                   "iters_mean": round(float(np.mean(seq_iters)), 2)}
         s.close()
-        for prec in ("fp64", "fp32"):
-            b = BatchedSolver([n] * seeds, [1] * seeds, precision=prec, beta_mode="midpoint",
+        for mode, beta, prec in (("midpoint", 0.0, "fp64"), ("midpoint", 0.0, "fp32"),
+                                 ("fixed", 3.0, "fp64"), ("sum", 0.0, "fp64"),
+                                 ("max", 0.0, "fp64"), ("min", 0.0, "fp64")):
+            label = prec if mode == "midpoint" else f"{mode}{beta:g}_{prec}" if beta else \
+                f"{mode}_{prec}"
+            b = BatchedSolver([n] * seeds, [1] * seeds, precision=prec, beta_mode=mode, beta=beta,
                               boundary="neumann", length=2.0, lin=1.0)
             U, F = b.pool(), b.pool()
             for i in range(seeds):
@@ -394,17 +400,18 @@ def batched_tables(seeds):
             dt = time.perf_counter() - t0
             its = [r["iters"] for r in res]
             err = max(float((b.view(U, i)[0] - u_ex).abs().max()) for i in range(seeds))
-            rec[f"batched_{prec}"] = {"seconds": round(dt, 4),
+            rec[f"batched_{label}"] = {"seconds": round(dt, 4),
                                       "seconds_per_start": round(dt / seeds, 6),
                                       "iters_mean": round(float(np.mean(its)), 2),
                                       "iters_std": round(float(np.std(its)), 2),
                                       "not_converged": sum(r["status"] != 0 for r in res),
                                       "iters_equal_sequential": int(sum(
-                                          a == c for a, c in zip(its, seq_iters))),
+                                          a == c for a, c in zip(its, seq_iters)))
+                                      if mode == "midpoint" else None,
                                       "max_err_vs_exact": err}
-            log(f"  n={n} batched {prec}: {dt:.4f} s for {seeds} starts "
-                f"(sequential fp64 {rec['sequential_fp64']['seconds']} s), "
-                f"iters {rec[f'batched_{prec}']['iters_mean']}")
+            log(f"  n={n} batched {label}: {dt:.4f} s for {seeds} starts "
+                f"(sequential midpoint fp64 {rec['sequential_fp64']['seconds']} s), "
+                f"iters {rec[f'batched_{label}']['iters_mean']}")
             b.close()
             del U, F, b
             torch.cuda.empty_cache()

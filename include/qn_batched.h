@@ -4,9 +4,10 @@
  * systems -Lap u + u^3 - v = f1, -Lap v + v^3 - u = f2 (Section 4.3,
  * eq. system), each iterated with the quasi-Newton step of Section 4
  * (eq. identity-method) and the tensor-product solve of Section 4.1
- * (eq. fin_inverse), with one shift beta per instance (midpoint of the
- * Jacobian-diagonal / 2x2-block eigenvalue range, Section 4.3 eq. eigenvalues,
- * or a fixed value).
+ * (eq. fin_inverse), with one shift beta per instance from the range of the
+ * Jacobian-diagonal / 2x2-block eigenvalues (Section 4.3 eq. eigenvalues):
+ * its midpoint, max, min + max or min (the rules the tables of Sections
+ * 6.2-6.3 compare), or a fixed value.
  *
  * Execution: instances of equal (n, ncomp) form a class.  One iteration is,
  * per class, a residual launch, a finalize launch (stopping and shift rules on
@@ -49,9 +50,11 @@ typedef struct {
 /* count instances (1..65536); n[i] interior points per side (1..4096);
  * ncomp[i] in {1, 2}; precision: qn_precision of the transforms (FP64, FP32
  * or BF16X3; QN_PREC_BF16X6 is rejected with QN_ERR_INVALID); beta_mode
- * (QN_BETA_FIXED or QN_BETA_MIDPOINT) and beta as in qn_setup (applied to
- * every instance).  Every instance lives on the unit square with Dirichlet
- * data.  Host only. */
+ * (any qn_beta_mode) and beta as in qn_setup (applied to every instance);
+ * QN_ERR_INVALID also for a fixed beta <= -lam_min(A_h) of some instance and
+ * for QN_BETA_MIN with a 2-component instance whose lam_min(A_h) <= 1 (that
+ * rule can give beta = -1 there).  Every instance lives on the unit square
+ * with Dirichlet data.  Host only. */
 qn_status qnb_setup(int32_t count, const int32_t* n, const int32_t* ncomp, int32_t precision,
                     int32_t beta_mode, double beta, qnb_ctx* out);
 
@@ -76,9 +79,11 @@ typedef struct {
  * checks of qnb_setup, QN_ERR_INVALID for: an unknown boundary; a length
  * that is negative or not finite; a lin that is not finite; lin != 0 with a
  * 2-component instance; Neumann data with n[i] < 2, a 2-component instance
- * or BF16X3 transforms; and a shift that can reach the zero eigenvalue of
- * the Neumann operator: a fixed beta <= 0, or the midpoint rule with
- * lin <= 0 (with lin > 0 the midpoint of 3 u^2 + lin is at least lin).
+ * or BF16X3 transforms; and a shift rule whose beta can reach -lam_min(A_h)
+ * of a scalar instance: every rule on the range of 3 u^2 + lin gives at least
+ * lin (min + max: 2 lin when lin < 0), so lam_min(A_h) + that bound must be
+ * positive.  With Neumann data lam_min(A_h) = 0: a fixed beta must be > 0
+ * and a shift rule needs lin > 0.
  * Host only. */
 qn_status qnb_setup_ex(int32_t count, const int32_t* n, const int32_t* ncomp, int32_t precision,
                        int32_t beta_mode, double beta, const qnb_options* opt, qnb_ctx* out);

@@ -126,6 +126,17 @@ EpiArgs epi_for(qnb_ctx c, const Cls& k, double* dense_base) {
   return ep;
 }
 
+// Shift rule of the finalize kernel for a qn_beta_mode.
+int batch_rule(int beta_mode) {
+  switch (beta_mode) {
+    case QN_BETA_MIDPOINT: return RULE_MIDPOINT;
+    case QN_BETA_MAX: return RULE_MAX;
+    case QN_BETA_SUM: return RULE_SUM;
+    case QN_BETA_MIN: return RULE_MIN;
+    default: return RULE_FIXED;
+  }
+}
+
 // One quasi-Newton iteration of class k on stream s.
 hipError_t class_iteration(qnb_ctx c, Cls& k, double* U, const double* F, double rtol, int max_iter,
                            hipStream_t s) {
@@ -155,8 +166,8 @@ hipError_t class_iteration(qnb_ctx c, Cls& k, double* U, const double* F, double
   if (e != hipSuccess) return e;
   BState* st = (BState*)(c->ws + k.off_state);
   int* done = (int*)(c->ws + k.off_done);
-  e = launch_bfinalize(a.partials, k.bpi, k.K, st, done, c->beta_mode == QN_BETA_MIDPOINT, c->beta,
-                       rtol, max_iter, s);
+  e = launch_bfinalize(a.partials, k.bpi, k.K, st, done, batch_rule(c->beta_mode), c->beta, rtol,
+                       max_iter, s);
   if (e != hipSuccess) return e;
   void* W1 = c->ws + k.off_W1;
   void* W2 = c->ws + k.off_W2;
@@ -224,7 +235,8 @@ qn_status qnb_setup_ex(int32_t count, const int32_t* n, const int32_t* ncomp, in
   if (!out || !n || !ncomp) return bad(QN_ERR_INVALID, "null argument");
   if (count < 1 || count > 65536) return bad(QN_ERR_INVALID, "count must be in [1, 65536]");
   if (precision < 0 || precision > 2) return bad(QN_ERR_INVALID, "unknown precision");
-  if (beta_mode < 0 || beta_mode > 1) return bad(QN_ERR_INVALID, "unknown beta_mode");
+  if (beta_mode < QN_BETA_FIXED || beta_mode > QN_BETA_MIN)
+    return bad(QN_ERR_INVALID, "unknown beta_mode");
   if (!std::isfinite(beta)) return bad(QN_ERR_INVALID, "beta not finite");
   qnb_options o{QN_BC_DIRICHLET, 1.0, 0.0};
   if (opt) o = *opt;
@@ -238,11 +250,11 @@ qn_status qnb_setup_ex(int32_t count, const int32_t* n, const int32_t* ncomp, in
   if (neu && precision == QN_PREC_BF16X3)
     return bad(QN_ERR_INVALID, "Neumann data needs FP64 or FP32 transforms");
   // The Neumann operator has the eigenvalue 0 (constant mode): the shift must
-  // stay positive.  The midpoint of 3 u^2 + lin is at least lin.
+  // stay positive.  Every rule on the range of 3 u^2 + lin is at least lin.
   if (neu && beta_mode == QN_BETA_FIXED && !(beta > 0.0))
     return bad(QN_ERR_INVALID, "Neumann data needs a fixed beta > 0");
-  if (neu && beta_mode == QN_BETA_MIDPOINT && !(o.lin > 0.0))
-    return bad(QN_ERR_INVALID, "Neumann data with the midpoint rule needs lin > 0");
+  if (neu && beta_mode != QN_BETA_FIXED && !(o.lin > 0.0))
+    return bad(QN_ERR_INVALID, "Neumann data with a shift rule needs lin > 0");
   std::map<std::pair<int, int>, int> key;
   for (int i = 0; i < count; ++i) {
     if (ncomp[i] == 2 && (neu || o.lin != 0.0))
@@ -292,7 +304,7 @@ qn_status qnb_setup_ex(int32_t count, const int32_t* n, const int32_t* ncomp, in
     c->inst_pos[i] = c->cls[ci].K++;
     c->cls[ci].members.push_back(i);
   }
-  double lam_min = 1e300;
+  double lam_min = 1e300, lam_min1 = 1e300;  // all classes; scalar classes
   long long fe = 0;
   size_t off = 0;
   c->fold = precision != QN_PREC_BF16X3;
@@ -311,6 +323,16 @@ qn_status qnb_setup_ex(int32_t count, const int32_t* n, const int32_t* ncomp, in
         for (double& l : k.hlam) l /= c->length * c->length;
     }
     lam_min = std::min(lam_min, 2.0 * k.hlam[0]);
+    if (k.ncomp == 1) lam_min1 = std::min(lam_min1, 2.0 * k.hlam[0]);
+    // The min rule on a 2-component system can give beta down to -1 (the
+    // smallest eigenvalue of the 2x2 block at u = v = 0); every other rule
+    // gives beta >= 0 on these problems.
+    if (beta_mode == QN_BETA_MIN && k.ncomp == 2 && 2.0 * k.hlam[0] <= 1.0) {
+      const int nn = k.n;
+      delete c;
+      return set_error(QN_ERR_INVALID, "n = %d: the min rule on a system can make the solve "
+                                       "singular (lam_min(A_h) <= 1)", nn);
+    }
     k.off_field = fe;
     fe += (long long)k.ncomp * k.K * k.n * k.n;
     const size_t pp = k.hS.size();
@@ -362,6 +384,14 @@ qn_status qnb_setup_ex(int32_t count, const int32_t* n, const int32_t* ncomp, in
   if (beta_mode == QN_BETA_FIXED && lam_min + beta <= 0.0) {
     delete c;
     return bad(QN_ERR_INVALID, "fixed beta makes some instance's operator singular or indefinite");
+  }
+  // Scalar instances under a shift rule: 3 u^2 + lin >= lin, so beta >= lin
+  // (>= 2 lin for min + max when lin < 0).
+  const double beta_low = o.lin >= 0.0 ? o.lin : (beta_mode == QN_BETA_SUM ? 2.0 : 1.0) * o.lin;
+  if (beta_mode != QN_BETA_FIXED && lam_min1 < 1e300 && lam_min1 + beta_low <= 0.0) {
+    delete c;
+    return bad(QN_ERR_INVALID, "lin makes the shift rule's solve singular or indefinite for some "
+                               "instance (lin <= -lam_min(A_h))");
   }
   c->field_elems = fe;
   c->need = off;

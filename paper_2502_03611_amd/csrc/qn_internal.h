@@ -203,10 +203,11 @@ struct BState {
 };
 static_assert(sizeof(BState) % sizeof(double) == 0, "BState must be a whole number of doubles");
 // Batched finalize: workgroup k reduces partials [k*bpi, (k+1)*bpi) of one
-// class and updates st[k] (stopping rule, shift rule, iteration count).
-// done[k] mirrors st[k].done as a plain int array (the GEMM/residual skip flags).
+// class and updates st[k] (stopping rule, shift rule `rule` of ShiftRule
+// other than RULE_COEFF_MID, iteration count).  done[k] mirrors st[k].done as
+// a plain int array (the GEMM/residual skip flags).
 hipError_t launch_bfinalize(const double* partials, int bpi, int K, BState* st, int* done,
-                            int midpoint, double beta_fixed, double rtol, int max_iter,
+                            int rule, double beta_fixed, double rtol, int max_iter,
                             hipStream_t s);
 hipError_t launch_breset(BState* st, int* done, int K, hipStream_t s);
 

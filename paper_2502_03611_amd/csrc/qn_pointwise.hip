@@ -665,11 +665,12 @@ hipError_t launch_scale(double* u, long long n, const double* s, hipStream_t st)
 }
 
 // Batched finalize: block k reduces instance k's partials and applies the
-// stopping rule, then the shift rule (midpoint of the Jacobian-diagonal
-// eigenvalue range, or a fixed beta) for the next solve.
+// stopping rule, then the shift rule for the next solve (rule_beta: a fixed
+// beta, or the midpoint, max, min + max or min of the Jacobian-diagonal
+// eigenvalue range).
 __global__ __launch_bounds__(256) void k_bfinalize(const double* __restrict__ partials, int bpi,
                                                    BState* __restrict__ st, int* __restrict__ done,
-                                                   int midpoint, double beta_fixed, double rtol,
+                                                   int rule, double beta_fixed, double rtol,
                                                    int max_iter) {
   BState& s = st[blockIdx.x];
   if (s.done) return;
@@ -700,7 +701,7 @@ __global__ __launch_bounds__(256) void k_bfinalize(const double* __restrict__ pa
       s.status = 3;  // QN_ERR_NOT_CONVERGED
     } else {
       s.scale = 1.0;
-      s.beta = midpoint ? 0.5 * (mn + mx) : beta_fixed;
+      s.beta = rule_beta(rule, mn, mx, beta_fixed);
       s.iters += 1;
     }
     done[blockIdx.x] = s.done;
@@ -708,9 +709,9 @@ __global__ __launch_bounds__(256) void k_bfinalize(const double* __restrict__ pa
 }
 
 hipError_t launch_bfinalize(const double* partials, int bpi, int K, BState* st, int* done,
-                            int midpoint, double beta_fixed, double rtol, int max_iter,
+                            int rule, double beta_fixed, double rtol, int max_iter,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_bfinalize, dim3(K), dim3(256), 0, s, partials, bpi, st, done, midpoint,
+  hipLaunchKernelGGL(k_bfinalize, dim3(K), dim3(256), 0, s, partials, bpi, st, done, rule,
                      beta_fixed, rtol, max_iter);
   return hipGetLastError();
 }

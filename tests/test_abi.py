@@ -263,6 +263,11 @@ def _qnb_setup_ex(n, nc, opt, prec=1, bmode=1, beta=0.0):
     ([9], [1], (1, 1.0, 1.0), 1, 0, 0.0),                      # Neumann fixed beta = 0
     ([9], [1], (1, 1.0, 0.0), 1, 1, 0.0),                      # Neumann midpoint, lin = 0
     ([9, 12], [1, 1], (0, 1.0, 0.0), 1, 0, -2.0 * 9.8),        # fixed beta below -lam_min
+    ([9], [1], (1, 1.0, 0.0), 1, 2, 0.0),                      # Neumann max rule, lin = 0
+    ([9], [2], (0, 10.0, 0.0), 1, 4, 0.0),                     # min rule, system, lam_min < 1
+    ([9], [1], (0, 1.0, -25.0), 1, 1, 0.0),                    # lin below -lam_min = -19.6
+    ([9], [1], (0, 1.0, -12.0), 1, 3, 0.0),                    # min + max: 2 lin below it
+    ([9], [1], None, 1, 5, 0.0),                               # unknown rule
 ])
 def test_qnb_setup_ex_rejects_invalid(n, nc, opt, prec, bmode, beta):
     assert _qnb_setup_ex(n, nc, opt, prec, bmode, beta) == qn.QN_ERR_INVALID
@@ -274,6 +279,11 @@ def test_qnb_setup_ex_rejects_invalid(n, nc, opt, prec, bmode, beta):
     ([9, 12], [1, 1], (1, 2.0, 0.0), 0, 0, 3.0),
     ([9, 12], [1, 2], (0, 2.0, 0.0), 2, 1, 0.0),
     ([9], [1], None, 1, 1, 0.0),
+    ([9, 12], [1, 2], None, 0, 2, 0.0),                        # max
+    ([9, 12], [1, 2], None, 1, 3, 0.0),                        # min + max
+    ([9, 12], [1, 2], None, 1, 4, 0.0),                        # min (lam_min > 1 here)
+    ([9], [1], (0, 1.0, -12.0), 1, 1, 0.0),                    # midpoint: lin > -lam_min
+    ([9, 12], [1, 1], (1, 2.0, 1.0), 1, 4, 0.0),               # Neumann min rule, lin > 0
 ])
 def test_qnb_setup_ex_accepts(n, nc, opt, prec, bmode, beta):
     assert _qnb_setup_ex(n, nc, opt, prec, bmode, beta) == qn.QN_OK

@@ -98,13 +98,14 @@ NEU_SIZES = [17, 33, 40, 64, 17, 33, 129, 40]
 
 
 @pytest.mark.parametrize("prec,mode,beta", [("fp64", "midpoint", 0.0), ("fp32", "midpoint", 0.0),
-                                            ("fp64", "fixed", 3.0)])
+                                            ("fp64", "fixed", 3.0), ("fp64", "max", 0.0),
+                                            ("fp64", "sum", 0.0), ("fp64", "min", 0.0)])
 def test_batched_neumann_matches_single_instance_and_oracle(prec, mode, beta):
     """Section 6.2, Example 1 (eq. ex2d1): -Lap u + u + u^3 = f on [-1, 1]^2
     with zero normal derivative, every instance started from the sampled
     exact solution plus 0.1 times its own seeded degree-4 polynomial (the
-    paper's perturbed starts, here one batch instead of one solve each).
-    Against the single-problem solver: equal counts and iterates to 1e-12;
+    paper's perturbed starts, here one batch instead of one solve each), under
+    each shift rule of the paper's table.  Against the single-problem solver: equal counts and iterates to 1e-12;
     against the oracle: equal counts (FP64) and the rtol bound."""
     from oracle import neumann as nm
     print(f"batched neumann {prec} {mode}", flush=True)
@@ -130,7 +131,8 @@ def test_batched_neumann_matches_single_instance_and_oracle(prec, mode, beta):
         assert res[i]["iters"] == st["iters"], (i, res[i], st)
         assert np.linalg.norm(ub - u1.cpu().numpy()[0]) <= 1e-12 * np.linalg.norm(ub)
         ref = nm.qn_solve(srcs[i], nm.spacing((n, n)), lin=1.0, u0=starts[i], beta=beta,
-                          midpoint=mode == "midpoint", rtol=1e-10, max_iter=200)
+                          midpoint=mode == "midpoint", rtol=1e-10, max_iter=200,
+                          rule=mode if mode in ("max", "sum", "min") else None)
         assert ref["converged"]
         assert abs(res[i]["iters"] - ref["iters"]) <= (0 if prec == "fp64" else 1), (i, res[i])
         # both stopped at relres <= 1e-10 and the Jacobian is >= lin = 1:
