@@ -44,23 +44,32 @@ def residual(kind, u, f, lin=0.0, cub=1.0, pot=None, quad=0.0):
     raise ValueError(kind)
 
 
-def shift_rule(kind, u, beta, midpoint, lin=0.0, cub=1.0, pot=None, quad=0.0):
-    """Return (scale c_k, shift beta_k) of the Jacobian approximation."""
+def shift_rule(kind, u, beta, midpoint, lin=0.0, cub=1.0, pot=None, quad=0.0, rule=None):
+    """Return (scale c_k, shift beta_k) of the Jacobian approximation.  The
+    shift comes from the range [lo, hi] of the Jacobian diagonal (cubic) or of
+    the 2x2 block eigenvalues (system, Section 4.3 eq. eigenvalues): its
+    midpoint (Section 4), or by `rule` "max" (hi), "sum" (lo + hi), "min" (lo),
+    the alternatives the tables of Sections 6.2-6.3 compare; else the fixed
+    beta."""
     if kind == QUASILINEAR:
         a = ops.coeff_quasilinear(u[0])
         return 0.5 * (float(a.min()) + float(a.max())), beta
-    if not midpoint:
+    if rule is None and not midpoint:
         return 1.0, beta
     if kind == CUBIC:
         fu = ops.fu_cubic(u[0], lin, cub, pot, quad)
-        return 1.0, 0.5 * (float(fu.min()) + float(fu.max()))
-    lm, lp = ops.system_jacobian_eigs(u[0], u[1])
-    return 1.0, 0.5 * (float(lm.min()) + float(lp.max()))
+        lo, hi = float(fu.min()), float(fu.max())
+    else:
+        lm, lp = ops.system_jacobian_eigs(u[0], u[1])
+        lo, hi = float(lm.min()), float(lp.max())
+    r = "mid" if rule is None else rule
+    return 1.0, {"mid": 0.5 * (lo + hi), "max": hi, "sum": lo + hi, "min": lo}[r]
 
 
 def qn_solve(kind, f, u0=None, beta=0.0, midpoint=False, rtol=1e-10,
-             max_iter=200, solver=fdm_solve, lin=0.0, cub=1.0, pot=None, quad=0.0):
-    """Run the quasi-Newton iteration.
+             max_iter=200, solver=fdm_solve, lin=0.0, cub=1.0, pot=None, quad=0.0, rule=None):
+    """Run the quasi-Newton iteration (shift: see shift_rule; rule overrides
+    midpoint).
 
     f, u0: arrays of shape (ncomp, .., ny, nx).  Runs until relres <= rtol or
     max_iter solves.  Returns dict(u, iters, relres (history, one entry per
@@ -77,7 +86,7 @@ def qn_solve(kind, f, u0=None, beta=0.0, midpoint=False, rtol=1e-10,
         hist.append(rel)
         if rel <= rtol or k >= max_iter or not math.isfinite(rel):
             break
-        c, b = shift_rule(kind, u, beta, midpoint, lin, cub, pot, quad)
+        c, b = shift_rule(kind, u, beta, midpoint, lin, cub, pot, quad, rule)
         betas.append(b)
         scales.append(c)
         for comp in range(u.shape[0]):

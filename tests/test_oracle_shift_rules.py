@@ -44,3 +44,40 @@ def test_shift_of_values():
     assert nm.shift_of("mid", fu, 0) == 3.5 and nm.shift_of("sum", fu, 0) == 7.0
     assert nm.shift_of("max", fu, 0) == 5.0 and nm.shift_of("min", fu, 0) == 2.0
     assert nm.shift_of("fixed", fu, 9.0) == 9.0
+
+
+def test_dirichlet_rule_shifts_match_pointwise_jacobian_blocks():
+    """The Dirichlet oracle's shift rules against the Jacobian blocks built
+    node by node: the cubic diagonal 3 u^2 + lin (a 1x1 block) and the
+    system's [[3u^2, -1], [-1, 3v^2]] (Section 4.3), eigenvalues by LAPACK's
+    symmetric solver; each rule is the named function of their range."""
+    from oracle import qn as oqn
+    rng = np.random.default_rng(21)
+    u = rng.standard_normal((2, 5, 6))
+    eig = np.array([np.linalg.eigvalsh(np.array([[3 * a * a, -1.0], [-1.0, 3 * b * b]]))
+                    for a, b in zip(u[0].ravel(), u[1].ravel())])
+    lo, hi = eig[:, 0].min(), eig[:, 1].max()
+    d = 3 * u[0] ** 2 + 0.7
+    want = {"mid": (0.5 * (lo + hi), 0.5 * (d.min() + d.max())), "max": (hi, d.max()),
+            "sum": (lo + hi, d.min() + d.max()), "min": (lo, d.min())}
+    for rule, (w_sys, w_cub) in want.items():
+        assert oqn.shift_rule(oqn.SYSTEM, u, 0.0, False, rule=rule)[1] == pytest.approx(w_sys, rel=1e-14)
+        assert oqn.shift_rule(oqn.CUBIC, u[:1], 0.0, False, lin=0.7, rule=rule)[1] == \
+            pytest.approx(w_cub, rel=1e-14)
+    # no rule: the midpoint flag, else the fixed beta
+    assert oqn.shift_rule(oqn.CUBIC, u[:1], 2.5, False, lin=0.7)[1] == 2.5
+    assert oqn.shift_rule(oqn.CUBIC, u[:1], 2.5, True, lin=0.7)[1] == pytest.approx(want["mid"][1])
+
+
+@pytest.mark.parametrize("rule", ["max", "sum", "min"])
+def test_dirichlet_rules_reach_the_dense_newton_root(rule):
+    """Every rule's iteration (Dirichlet data, cubic problem and system)
+    converges to the root that dense Newton's method finds."""
+    from oracle import qn as oqn
+    rng = np.random.default_rng(1)
+    for kind, c in ((oqn.CUBIC, 1), (oqn.SYSTEM, 2)):
+        f = 30.0 * rng.standard_normal((c, 6, 7))
+        root = oqn.newton_solve(kind, f)
+        out = oqn.qn_solve(kind, f, rule=rule, rtol=1e-13, max_iter=500)
+        assert out["converged"]
+        assert np.linalg.norm(out["u"] - root) <= 1e-11 * np.linalg.norm(root)
