@@ -339,7 +339,7 @@ def paper_tables(seeds2d, seeds3d):
     return out
 
 
-def batched_tables(seeds):
+def batched_tables(seeds, sizes=(200, 400, 800, 1600), all_rules=True):
     """The 2D rows of Table results2d_space (eq. ex2d1) with all perturbed
     starts of one size solved together by the batched solver (one instance
     per seed, Neumann data): the midpoint shift with FP64 and FP32 transforms
@@ -350,7 +350,7 @@ def batched_tables(seeds):
     of the same batch (graph capture, autotuning)."""
     from paper_2502_03611_amd.batched import BatchedSolver
     out = []
-    for n in (200, 400, 800, 1600):
+    for n in sizes:
         log(f"batched table 2D n={n}, {seeds} starts")
         u_ex, f = e4_inputs(n)
         s = Solver((n, n), "cubic", beta_mode="midpoint", boundary="neumann", length=2.0, lin=1.0)
@@ -374,9 +374,9 @@ def batched_tables(seeds):
         rec["sequential_fp64"] = {"seconds": round(time.perf_counter() - t0, 4),
                                   "iters_mean": round(float(np.mean(seq_iters)), 2)}
         s.close()
-        for mode, beta, prec in (("midpoint", 0.0, "fp64"), ("midpoint", 0.0, "fp32"),
-                                 ("fixed", 3.0, "fp64"), ("sum", 0.0, "fp64"),
-                                 ("max", 0.0, "fp64"), ("min", 0.0, "fp64")):
+        configs = (("midpoint", 0.0, "fp64"), ("midpoint", 0.0, "fp32"), ("fixed", 3.0, "fp64"),
+                   ("sum", 0.0, "fp64"), ("max", 0.0, "fp64"), ("min", 0.0, "fp64"))
+        for mode, beta, prec in configs if all_rules else configs[:1]:
             label = prec if mode == "midpoint" else f"{mode}{beta:g}_{prec}" if beta else \
                 f"{mode}_{prec}"
             b = BatchedSolver([n] * seeds, [1] * seeds, precision=prec, beta_mode=mode, beta=beta,
@@ -809,6 +809,9 @@ def main():
                     help="also compare finite differences with Q^2 and Q^4 spectral elements on "
                          "the same n^3 unknowns (3D cubic problem, Dirichlet data)")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-batched-neumann", action="store_true",
+                    help="skip the 100 perturbed 200^2 Neumann starts (eq. ex2d1) solved as one "
+                         "batch against one after another (--no-batched skips it too)")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--batched-count", type=int, default=512)
     ap.add_argument("--copy-probe", action="store_true",
@@ -962,6 +965,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_count)
+        torch.cuda.empty_cache()
+    if not (args.no_batched or args.no_batched_neumann):
+        out["batched_neumann_200"] = batched_tables(100, sizes=(200,), all_rules=False)[0]
         torch.cuda.empty_cache()
     if not args.no_learned:
         out["learned_guess"] = bench_learned()
