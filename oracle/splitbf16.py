@@ -51,3 +51,35 @@ def split_matmul(a, b, parts):
         for j in range(parts - i):
             c += pa[i].astype(np.float64) @ pb[j].astype(np.float64)
     return c
+
+
+def split_mode_product(x, m, axis, parts):
+    """Y = X x_axis M (Y[.., i, ..] = sum_k M[i, k] X[.., k, ..]) with every
+    scalar product taken as the split-bf16 product of the FP32-rounded
+    operands, summed exactly, the result rounded to FP32 (the storage of the
+    reduced-precision transforms)."""
+    xm = np.moveaxis(np.asarray(x), axis, 0)
+    shp = xm.shape
+    y = split_matmul(m, xm.reshape(shp[0], -1), parts)
+    return np.moveaxis(y.astype(np.float32).reshape((m.shape[0],) + shp[1:]), 0, axis)
+
+
+def split_fdm_solve(r, shift, parts, scale=1.0):
+    """X = (scale A_h + shift I)^-1 R by the tensor-product formula (Section 4.1,
+    eq. fin_inverse) with split-bf16 mode products: R rounded to FP32, the
+    forward sine transform along every axis, the divide by scale (lam_i + lam_j
+    (+ lam_k)) + shift in FP64 rounded to FP32, the inverse transforms.  Every
+    product and the divide see FP32 inputs and store FP32 results; the only
+    difference from the matrix cores is their FP32 accumulation order.
+    Dirichlet finite differences (sine eigenvectors, T^-1 = T)."""
+    from .spectral import sine_eigenpairs
+    from .tensor import spectral_denominator
+
+    ts = [sine_eigenpairs(n)[0] for n in r.shape]
+    y = np.asarray(r, dtype=np.float32)
+    for ax, t in enumerate(ts):
+        y = split_mode_product(y, t.T, ax, parts)
+    y = (y.astype(np.float64) / spectral_denominator(r.shape, shift, scale)).astype(np.float32)
+    for ax, t in enumerate(ts):
+        y = split_mode_product(y, t, ax, parts)
+    return y.astype(np.float64)

@@ -3,6 +3,8 @@ force, the exactness of the parts, and the error of the split products
 against the FP64 product (bounds from the splitting: each RNE step to an
 8-bit significand leaves a remainder <= 2^-8 of its input)."""
 
+import math
+
 import numpy as np
 import pytest
 
@@ -63,3 +65,36 @@ def test_split_product_error_bound(parts, coef):
     # and the split is not trivially exact: one part alone is far less accurate
     c1 = sb.split_matmul(a, b, 1)
     assert np.max(np.abs(c1 - ref) / bound) > 10.0
+
+
+@pytest.mark.parametrize("shape", [(31, 31), (9, 12, 17)])
+def test_split_solve_against_the_fp64_solve_and_a_direct_solve(shape):
+    """The split-bf16 tensor-product solve carries the splitting error and
+    nothing else: bf16x6 (three parts) is within FP32 storage error of the
+    FP64 solve (and of a dense direct solve, which shares no step with it);
+    bf16x3 (two parts) is within sqrt(6) 2^-16 of it but clearly not at FP32
+    level; a one-part product (plain bf16) misses the bf16x3 bound."""
+    from oracle import tensor as ot
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal(shape)
+    ref = ot.direct_solve(r, 0.7)
+    assert np.linalg.norm(ot.fdm_solve(r, 0.7) - ref) <= 1e-13 * np.linalg.norm(ref)
+    err = {p: np.linalg.norm(sb.split_fdm_solve(r, 0.7, p) - ref) / np.linalg.norm(ref)
+           for p in (1, 2, 3)}
+    assert err[3] <= 3e-7
+    assert 3e-7 < err[2] <= math.sqrt(6) * 2.0 ** -16
+    assert err[1] > 10 * math.sqrt(6) * 2.0 ** -16
+
+
+def test_split_solve_scale_and_exact_modes():
+    """A single sine mode: the FP64 solve returns it divided by its
+    eigenvalue sum plus the shift; the split solve within its bound, and the
+    scale multiplies the eigenvalue sum (not the shift)."""
+    from oracle.spectral import sine_eigenpairs
+    n = (15, 20)
+    (ty, ly), (tx, lx) = sine_eigenpairs(n[0]), sine_eigenpairs(n[1])
+    r = np.outer(ty[:, 2], tx[:, 5])
+    for scale, shift in ((1.0, 0.0), (2.5, 3.0)):
+        want = r / (scale * (ly[2] + lx[5]) + shift)
+        got = sb.split_fdm_solve(r, shift, 2, scale=scale)
+        assert np.linalg.norm(got - want) <= math.sqrt(6) * 2.0 ** -16 * np.linalg.norm(want)
