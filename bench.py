@@ -170,6 +170,54 @@ def solve_to_tol(shape, U, F, u_ex, precisions, runs, u64=None):
     return out, u64
 
 
+def mixed_steps(shape, U, F, steps, precisions=("fp32", "bf16x3")):
+    """Per reduced-precision form: `steps` timed quasi-Newton steps at n^3 with
+    HIP events around every launch (autotuned tiles, one untimed step first).
+    Per launch key the average time; the mode products against their roofline:
+    FP32 on the folded count (2 n^2 (ne^2 + no^2) flops per product) against
+    the FP32 peak, split-bf16 on the dense count times the part products (3
+    for bf16x3, 6 for bf16x6) against the bf16 peak, and both against HBM for
+    one FP32 read and one FP32 write of the tensor (8 bytes per point)."""
+    n = shape[0]
+    ne, no = (n + 1) // 2, n // 2
+    out = {}
+    for prec in precisions:
+        s = Solver(shape, "quasilinear", beta=0.0, precision=prec, timing=True)
+        s.autotune()
+        U.zero_()
+        s.iterate(U, F, rtol=0.0, max_iter=1)
+        torch.cuda.synchronize()
+        s.timing(reset=True)
+        U.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.iterate(U, F, rtol=0.0, max_iter=steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tim = s.timing(reset=True)
+        rec = {"ms_per_step": round(dt / steps * 1e3, 3), "kernels": {}}
+        for k, (cnt, ms) in tim.items():
+            if not cnt:
+                continue
+            avg = ms / cnt
+            e = {"launches": cnt, "avg_ms": round(avg, 4)}
+            if k.startswith("gemm"):
+                if prec == "fp32":
+                    fl, peak = 2.0 * n ** 2 * (ne * ne + no * no), PEAK_FP32_TFLOPS
+                else:
+                    fl = 2.0 * float(n) ** 4 * (3 if prec == "bf16x3" else 6)
+                    peak = PEAK_BF16_TFLOPS
+                tf = fl / (avg * 1e-3) / 1e12
+                gbs = 8.0 * n ** 3 / (avg * 1e-3) / 1e9
+                e.update({"tflops": round(tf, 1), "frac_mfma": round(tf / peak, 4),
+                          "gbs_fp32_io": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)})
+            rec["kernels"][k] = e
+        rec["tiles"] = s.tiles()
+        out[prec] = rec
+        s.close()
+    return out
+
+
 def amplitude_sweep(n, runs):
     """Time to tolerance at n^3 for the seeded amplitudes of seeds 0-4 and the
     worst case A = 2 (FP64, FP32 and bf16x3 transforms)."""
@@ -780,6 +828,8 @@ def main():
     ap.add_argument("--n", type=int, default=511)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-tol", action="store_true")
+    ap.add_argument("--no-mixed-steps", action="store_true",
+                    help="skip the timed FP32 / bf16x3 steps with per-kernel times")
     ap.add_argument("--ttt-runs", type=int, default=5,
                     help="timed solves per precision for time to tolerance (median reported)")
     ap.add_argument("--amp-sweep", action="store_true",
@@ -809,9 +859,9 @@ def main():
                     help="also compare finite differences with Q^2 and Q^4 spectral elements on "
                          "the same n^3 unknowns (3D cubic problem, Dirichlet data)")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--no-batched-neumann", action="store_true",
-                    help="skip the 100 perturbed 200^2 Neumann starts (eq. ex2d1) solved as one "
-                         "batch against one after another (--no-batched skips it too)")
+    ap.add_argument("--batched-neumann", action="store_true",
+                    help="also solve the 100 perturbed 200^2 Neumann starts (eq. ex2d1) as one "
+                         "batch against one after another")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--batched-count", type=int, default=512)
     ap.add_argument("--copy-probe", action="store_true",
@@ -930,6 +980,10 @@ def main():
                   "kernels": kname, "autotune_s": round(t_tune, 3)},
     }
 
+    if not args.no_mixed_steps:
+        log("timed steps with reduced-precision transforms")
+        out["mixed_steps"] = mixed_steps(shape, U, F, args.steps)
+
     if not args.no_time_to_tol:
         solver.close()
         log("time to tolerance: fp64, fp32, bf16x3, bf16x6")
@@ -966,7 +1020,7 @@ def main():
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_count)
         torch.cuda.empty_cache()
-    if not (args.no_batched or args.no_batched_neumann):
+    if args.batched_neumann:
         out["batched_neumann_200"] = batched_tables(100, sizes=(200,), all_rules=False)[0]
         torch.cuda.empty_cache()
     if not args.no_learned:

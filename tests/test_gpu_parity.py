@@ -119,7 +119,12 @@ def test_fdm_solve_max_size_2d():
     assert rel(x[0], otensor.fdm_solve(r[0], 1.0)) <= 1e-12
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 3e-5), ("bf16x3", 3e-4), ("bf16x6", 3e-5)])
+# Reduced-precision solve bounds against the FP64 solve (six chained mode
+# products, contractions of at most 70 terms here): FP32 about
+# sqrt(K) 2^-24 sqrt(6) = 1.2e-6, hence 3e-6; bf16x3 carries the split error
+# sqrt(6) 2^-16 = 3.7e-5 (the oracle's own split-bf16 solve lands at 1.1e-5);
+# bf16x6 drops only terms below 2^-24 and is bounded like FP32.
+@pytest.mark.parametrize("prec,tol", [("fp32", 3e-6), ("bf16x3", 4e-5), ("bf16x6", 3e-6)])
 @pytest.mark.parametrize("shape", [(63, 63), (31, 31, 31), (40, 50, 70)])
 def test_fdm_solve_reduced_precision(prec, tol, shape):
     print(f"fdm {prec} {shape}", flush=True)
@@ -129,6 +134,27 @@ def test_fdm_solve_reduced_precision(prec, tol, shape):
     err = rel(x[0], otensor.fdm_solve(r[0], 0.5))
     print(f"  {prec} {shape} rel err {err:.3e}", flush=True)
     assert err <= tol
+
+
+@pytest.mark.parametrize("prec,parts", [("bf16x3", 2), ("bf16x6", 3)])
+@pytest.mark.parametrize("shape,scale,shift", [((63, 63), 1.0, 0.5), ((31, 31, 31), 1.7, 0.0),
+                                               ((40, 50, 70), 1.0, 2.0)])
+def test_split_bf16_solve_matches_the_split_oracle(prec, parts, shape, scale, shift):
+    """The split-bf16 solve against the oracle's own split-bf16 solve (the same
+    part products, summed exactly, FP32 storage between products): they differ
+    only by the matrix cores' FP32 accumulation order, about sqrt(K) 2^-24 per
+    product, so 2e-6 relative.  A lost or doubled part product moves the
+    result by 2^-9 or more."""
+    from oracle import splitbf16 as osb
+    print(f"split oracle {prec} {shape}", flush=True)
+    r = synth.random_field((1,) + shape, 11)
+    s = Solver(shape, "cubic", precision=prec)
+    x = host(s.fdm_solve(dev(r), scale, shift))
+    ref = osb.split_fdm_solve(r[0], shift, parts, scale=scale)
+    err = rel(x[0], ref)
+    print(f"  {prec} {shape}: rel diff vs split oracle {err:.3e}, vs FP64 oracle "
+          f"{rel(x[0], otensor.fdm_solve(r[0], shift, scale)):.3e}", flush=True)
+    assert err <= 2e-6
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
