@@ -71,15 +71,22 @@ def split_fdm_solve(r, shift, parts, scale=1.0):
     (+ lam_k)) + shift in FP64 rounded to FP32, the inverse transforms.  Every
     product and the divide see FP32 inputs and store FP32 results; the only
     difference from the matrix cores is their FP32 accumulation order.
-    Dirichlet finite differences (sine eigenvectors, T^-1 = T)."""
+    Dirichlet finite differences (sine eigenvectors, T^-1 = T).
+
+    In exact arithmetic the order of the mode products is immaterial; with a
+    rounding after every product it is not (two orders differ by about the
+    split error itself), so it is fixed here: the forward products from the
+    x axis (the last array axis, the innermost Kronecker factor of the vec
+    order) outwards, the inverse products in the reverse order."""
     from .spectral import sine_eigenpairs
     from .tensor import spectral_denominator
 
     ts = [sine_eigenpairs(n)[0] for n in r.shape]
+    axes = list(range(r.ndim))
     y = np.asarray(r, dtype=np.float32)
-    for ax, t in enumerate(ts):
-        y = split_mode_product(y, t.T, ax, parts)
+    for ax in reversed(axes):
+        y = split_mode_product(y, ts[ax].T, ax, parts)
     y = (y.astype(np.float64) / spectral_denominator(r.shape, shift, scale)).astype(np.float32)
-    for ax, t in enumerate(ts):
-        y = split_mode_product(y, t, ax, parts)
+    for ax in axes:
+        y = split_mode_product(y, ts[ax], ax, parts)
     return y.astype(np.float64)

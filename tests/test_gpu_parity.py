@@ -141,7 +141,8 @@ def test_fdm_solve_reduced_precision(prec, tol, shape):
                                                ((40, 50, 70), 1.0, 2.0)])
 def test_split_bf16_solve_matches_the_split_oracle(prec, parts, shape, scale, shift):
     """The split-bf16 solve against the oracle's own split-bf16 solve (the same
-    part products, summed exactly, FP32 storage between products): they differ
+    part products in the same product order, summed exactly, FP32 storage between
+    products): they differ
     only by the matrix cores' FP32 accumulation order, about sqrt(K) 2^-24 per
     product, so 2e-6 relative.  A lost or doubled part product moves the
     result by 2^-9 or more."""

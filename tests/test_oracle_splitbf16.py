@@ -98,3 +98,25 @@ def test_split_solve_scale_and_exact_modes():
         want = r / (scale * (ly[2] + lx[5]) + shift)
         got = sb.split_fdm_solve(r, shift, 2, scale=scale)
         assert np.linalg.norm(got - want) <= math.sqrt(6) * 2.0 ** -16 * np.linalg.norm(want)
+
+
+def test_split_solve_product_order_matters_at_the_split_error_level():
+    """With a rounding after every product the axis order changes the result
+    by about the split error (so a reference must fix it), while in FP64 it
+    does not."""
+    from oracle import tensor as ot
+    from oracle.spectral import sine_eigenpairs
+    rng = np.random.default_rng(6)
+    r = rng.standard_normal((21, 26))
+    got = sb.split_fdm_solve(r, 0.3, 2)
+    ty, tx = sine_eigenpairs(21)[0], sine_eigenpairs(26)[0]
+    # the other order: y first forward, x first inverse
+    y = np.asarray(r, dtype=np.float32)
+    y = sb.split_mode_product(y, ty.T, 0, 2)
+    y = sb.split_mode_product(y, tx.T, 1, 2)
+    y = (y.astype(np.float64) / ot.spectral_denominator(r.shape, 0.3)).astype(np.float32)
+    y = sb.split_mode_product(y, tx, 1, 2)
+    y = sb.split_mode_product(y, ty, 0, 2).astype(np.float64)
+    ref = ot.fdm_solve(r, 0.3)
+    d = np.linalg.norm(y - got) / np.linalg.norm(ref)
+    assert 1e-6 < d < math.sqrt(6) * 2.0 ** -16
