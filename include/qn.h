@@ -236,6 +236,26 @@ qn_status qn_set_stream(qn_ctx ctx, void* stream);
 qn_status qn_residual(qn_ctx ctx, const double* d_U, const double* d_F, double* d_R,
                       double* d_red);
 
+/* Allocation-free residual, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same F^h(U) and reductions as qn_residual, the same
+ * arguments and error behaviour, but the context needs no bound workspace
+ * (qn_setup alone suffices) and the call allocates nothing: the workgroup
+ * partials and the finalize scalars live in a fixed array of the library,
+ * QN_NOALLOC_MAX_BLOCKS * 32 bytes plus 256, which each device holds from the
+ * first call on it until the process ends.  Every call on a device shares
+ * that array, so calls that overlap on one device (other streams, other
+ * threads) race; calls on one stream are ordered.  Call with the context's
+ * device current.  Finite differences only.
+ * Errors: as qn_residual, plus QN_ERR_WORKSPACE when the grid needs more
+ * than QN_NOALLOC_MAX_BLOCKS workgroup partials (3D grids up to about 1024^3,
+ * 2D grids up to 4096^2 fit; see residual launch shape: 64 x 16 x 32-plane
+ * tiles in 3D, 256-column strips in 2D) and QN_ERR_UNSUPPORTED for spectral
+ * elements. */
+#define QN_NOALLOC_MAX_BLOCKS 65536
+qn_status qn_residual_noalloc(qn_ctx ctx, const double* d_U, const double* d_F, double* d_R,
+                              double* d_red);
+
 /* Tensor-product solve X = (scale A_h + shift I)^-1 R per component
  * (Section 4.1, eq. fin_inverse), in the context's precision.  d_X may alias
  * d_R.  Errors: QN_ERR_INVALID if scale <= 0 or scale*sum lam_min + shift <= 0.

@@ -72,6 +72,7 @@ def lib():
     L.qn_bind_workspace.argtypes = [c_vp, c_vp, ctypes.c_size_t]
     L.qn_set_stream.argtypes = [c_vp, c_vp]
     L.qn_residual.argtypes = [c_vp, c_vp, c_vp, c_vp, c_vp]
+    L.qn_residual_noalloc.argtypes = [c_vp, c_vp, c_vp, c_vp, c_vp]
     L.qn_fdm_solve.argtypes = [c_vp, c_vp, c_dbl, c_dbl, c_vp]
     L.qn_iterate.argtypes = [c_vp, c_vp, c_vp, c_dbl, c_i32, ctypes.POINTER(QNStats)]
     L.qn_timing_count.argtypes = []
@@ -94,7 +95,7 @@ def lib():
     L.qn_last_error.argtypes = []
     L.qn_last_error.restype = ctypes.c_char_p
     for name in ("qn_setup", "qn_workspace_bytes", "qn_bind_workspace", "qn_set_stream",
-                 "qn_residual", "qn_fdm_solve", "qn_iterate", "qn_timing_count",
+                 "qn_residual", "qn_residual_noalloc", "qn_fdm_solve", "qn_iterate", "qn_timing_count",
                  "qn_timing_read", "qn_timing_reset", "qn_autotune", "qn_tile_info",
                  "qn_set_tile", "qn_eigen_residual", "qn_eigen_iterate", "qn_nodes"):
         getattr(L, name).restype = c_i32
@@ -126,7 +127,7 @@ class Solver:
     def __init__(self, shape, nonlinearity="cubic", beta=0.0, beta_mode="fixed",
                  precision="fp64", timing=False, device="cuda", boundary="dirichlet",
                  length=None, lin=0.0, cub=1.0, potential=None, discretization="fd",
-                 sem_order=0, quad=0.0):
+                 sem_order=0, quad=0.0, workspace=True):
         """boundary: "dirichlet" (n interior nodes per axis, h = L/(n+1)) or
         "neumann" (n nodes including both ends, zero normal derivative,
         h = L/(n-1)); length: the domain side L (default 1 for Dirichlet, 2 for
@@ -136,7 +137,8 @@ class Solver:
         device tensor V of the grid's shape, kept referenced by the solver
         (the library reads it on every residual).  discretization: "fd" or "sem"
         (Q^k spectral elements of order sem_order; n = E k - 1 interior nodes for
-        Dirichlet data, E k + 1 for Neumann data)."""
+        Dirichlet data, E k + 1 for Neumann data).  workspace=False skips the
+        device workspace (only residual_noalloc may then be called)."""
         L = lib()
         self.shape = tuple(int(s) for s in shape)
         self.dim = len(self.shape)
@@ -177,9 +179,11 @@ class Solver:
         nbytes = ctypes.c_size_t()
         check(L.qn_workspace_bytes(ctx, ctypes.byref(nbytes)))
         self.workspace_bytes = nbytes.value
-        self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
-        self._sync_stream()
-        check(L.qn_bind_workspace(ctx, _ptr(self._ws), self.workspace_bytes))
+        self._ws = None
+        if workspace:
+            self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+            self._sync_stream()
+            check(L.qn_bind_workspace(ctx, _ptr(self._ws), self.workspace_bytes))
 
     # -- helpers
     def _sync_stream(self):
@@ -205,6 +209,17 @@ class Solver:
         R = self.empty() if R is None else self._field(R, "R")
         self._sync_stream()
         check(lib().qn_residual(self._ctx, _ptr(U), _ptr(F), _ptr(R), _ptr(red)))
+        return R
+
+    def residual_noalloc(self, U, F, R, red=None):
+        """qn_residual_noalloc: as residual(), with the reduction scratch in the
+        library's fixed device array (no workspace needed, nothing allocated;
+        R and red are caller-provided)."""
+        self._field(U, "U")
+        self._field(F, "F")
+        self._field(R, "R")
+        self._sync_stream()
+        check(lib().qn_residual_noalloc(self._ctx, _ptr(U), _ptr(F), _ptr(R), _ptr(red)))
         return R
 
     def fdm_solve(self, R, scale=1.0, shift=0.0, X=None):

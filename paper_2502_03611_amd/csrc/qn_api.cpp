@@ -19,6 +19,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -530,6 +531,43 @@ hipError_t solve_ws(qn_ctx c, const double* coef, double* dense, int epi_last,
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Allocation-free residual.  The workgroup partials of the residual launch
+// and the finalize kernel's scalars live in `scratch`, a fixed array of this
+// library's code object (each device holds its own copy from the first call
+// on it until the process ends), instead of the bound workspace.  Host code
+// never uses the array's name as a device address: the address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+namespace {
+constexpr size_t kNoAllocSlots = QN_NOALLOC_MAX_BLOCKS;  // workgroups of one residual launch
+constexpr size_t kNoAllocPartialBytes = kNoAllocSlots * 4 * sizeof(double);
+constexpr size_t kNoAllocBytes = kNoAllocPartialBytes + ((sizeof(DevScalars) + 255) / 256) * 256;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+namespace {
+// Device address of `scratch` on the current device (resolved once per device).
+hipError_t noalloc_scratch(char** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
 extern "C" {
 
 qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const qn_options* opt,
@@ -823,6 +861,40 @@ qn_status qn_residual(qn_ctx c, const double* d_U, const double* d_F, double* d_
                              0.0, -1, 0, c->stream);
     });
   if (e != hipSuccess) return hip_fail(c, e, "residual launch");
+  return QN_OK;
+}
+
+qn_status qn_residual_noalloc(qn_ctx c, const double* d_U, const double* d_F, double* d_R,
+                              double* d_red) {
+  qn_status s = check_ctx(c, false);
+  if (s != QN_OK) return s;
+  if (c->sem_k > 0)
+    return fail(QN_ERR_UNSUPPORTED,
+                "qn_residual_noalloc: spectral elements keep their operator bands in the workspace");
+  if (!d_U || !d_F || !d_R) return fail(QN_ERR_INVALID, "null U, F or R");
+  if (!aligned8(d_U) || !aligned8(d_F) || !aligned8(d_R) || (d_red && !aligned8(d_red)))
+    return fail(QN_ERR_INVALID, "pointers must be 8-byte aligned");
+  if (d_R == d_U) return fail(QN_ERR_INVALID, "R may not alias U");
+  ResidualArgs a = residual_args(c, d_U, d_F, d_R);
+  // the launch's workgroup count, as launch_residual forms it
+  const int blocks = residual_max_blocks(a.ox, a.oy, a.oz, a.rz, a.ihz2 == 0.0);
+  if (blocks < 0 || (size_t)blocks > kNoAllocSlots)
+    return fail(QN_ERR_WORKSPACE,
+                "qn_residual_noalloc: the grid needs %d workgroup partials, the static scratch "
+                "holds %zu (use qn_residual with a bound workspace)",
+                blocks, kNoAllocSlots);
+  char* base = nullptr;
+  hipError_t e = noalloc_scratch(&base);
+  if (e != hipSuccess) return hip_fail(c, e, "qn_residual_noalloc: scratch address");
+  a.partials = reinterpret_cast<double*>(base);
+  DevScalars* sc = reinterpret_cast<DevScalars*>(base + kNoAllocPartialBytes);
+  // launched without the timing events of qn_residual (they would be created on demand)
+  int nb = 0;
+  e = launch_any_residual(a, &nb, c->stream);
+  if (e == hipSuccess)
+    e = launch_finalize(a.partials, nb, sc, rule_of(c), c->beta, c->lam_min_sum, d_red, 0.0, -1, 0,
+                        c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "qn_residual_noalloc launch");
   return QN_OK;
 }
 
