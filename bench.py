@@ -794,29 +794,41 @@ def bench_batched(count):
             "precision": "fp32 transforms, fp64 residual/update"}
 
 
-def bench_learned(nseeds=50):
+def bench_learned(nseeds=500):
     """Learned initial guess on 2D 255^2 -Lap u + u^3 = f with the committed
-    trained weights: held-out seeds, iterations and time to 1e-10 from U_0 = 0 and
-    from the learned guess, FP64 and FP32 transforms."""
+    trained weights on the held-out seeds: iterations and time to 1e-10 from
+    U_0 = 0 and from the learned guess (network in FP16 inference, the guess's
+    two solves, the fallback test), FP64 and FP32 transforms, one solve at a
+    time; then the same seeds as one batch (FP32 transforms), from U_0 = 0 and
+    from the batch of learned guesses."""
     from paper_2502_03611_amd import learned_guess as lg
 
     if not os.path.exists(lg.WEIGHTS):
         return {"skipped": "no trained weights at " + os.path.relpath(lg.WEIGHTS, ROOT)}
     theta = np.load(lg.WEIGHTS, allow_pickle=False)
-    net = lg.Net(255, 255, max_batch=1)
+    net = lg.Net(255, 255, max_batch=50)
     net.set_params(theta)
+    net.set_inference("fp16")
     lg.compare(net, range(10000, 10002))  # warm-up
+    log(f"learned guess: {nseeds} held-out seeds, one at a time")
     rows = lg.compare(net, range(10000, 10000 + nseeds))
-    outd = {"held_out_seeds": nseeds, "n": 255}
+    outd = {"held_out_seeds": nseeds, "n": 255, "inference": "fp16 fused"}
     for key in ("fp64_zero", "fp64_net", "fp32_zero", "fp32_net"):
         t = np.array([r[key]["t"] for r in rows])
         outd[key] = {"mean_iters": round(float(np.mean([r[key]["iters"] for r in rows])), 3),
                      "mean_time_ms": round(1e3 * float(t.mean()), 3),
                      "median_time_ms": round(1e3 * float(np.median(t)), 3),
-                     "all_converged": bool(all(r[key]["status"] == 0 for r in rows))}
+                     "all_converged": bool(all(r[key]["status"] == 0 for r in rows)),
+                     "max_rel_diff_vs_fp64_zero": float(max(r[key]["rel_diff"] for r in rows))}
+        if key.endswith("net"):
+            outd[key]["used_net_frac"] = round(float(np.mean([r[key]["used_net"] for r in rows])), 3)
     # medians: single slow solves (host hiccups) move the means
     outd["speedup_fp32_net_vs_fp64_zero"] = round(
         outd["fp64_zero"]["median_time_ms"] / outd["fp32_net"]["median_time_ms"], 3)
+    outd["speedup_fp64_net_vs_fp64_zero"] = round(
+        outd["fp64_zero"]["median_time_ms"] / outd["fp64_net"]["median_time_ms"], 3)
+    log("learned guess: the same seeds as one batch")
+    outd["batched"] = lg.compare_batched(net, list(range(10000, 10000 + nseeds)))
     return outd
 
 

@@ -89,7 +89,12 @@ typedef enum {
   QN_ERR_UNSUPPORTED = 6    /* valid request this build does not implement */
 } qn_status;
 
-typedef enum { QN_NL_CUBIC = 0, QN_NL_QUASILIN = 1, QN_NL_SYS2_CUBIC = 2 } qn_nonlinearity;
+typedef enum {
+  QN_NL_CUBIC = 0,
+  QN_NL_QUASILIN = 1,
+  QN_NL_SYS2_CUBIC = 2,
+  QN_NL_GRAYSCOTT = 3 /* the steady Gray-Scott system, see qn_options */
+} qn_nonlinearity;
 typedef enum {
   QN_PREC_FP64 = 0,
   QN_PREC_FP32 = 1,
@@ -159,7 +164,19 @@ typedef enum { QN_DISC_FD = 0, QN_DISC_SEM = 1 } qn_discretization;
  * The other nonlinearities need lin = 0, cub in {0, 1}, quad = 0 and
  * potential = NULL.
  * discretization: qn_discretization (0: finite differences); sem_order: the
- *   element order k of QN_DISC_SEM. */
+ *   element order k of QN_DISC_SEM.
+ * step: the step size tau of qn_iterate, U_{k+1} = U_k - tau dU_k (Section
+ *   6.2 uses 0.1 for the Gray-Scott system); 0 = 1 (the undamped step).
+ * gs_da, gs_ds, gs_rho, gs_mu: QN_NL_GRAYSCOTT only (0 = the values of
+ *   Section 6.2: 2.5e-4, 5e-4, 0.04, 0.065).  The steady Gray-Scott system of
+ *   Section 6.2 (eq. 2dgrayeq), 2D with Neumann data, components (A, S):
+ *     F^h = (D_A A_h A - S A^2 + (mu + rho) A, D_S A_h S + S A^2 + rho S) - F,
+ *   F = (0, rho) supplied by the caller as the source; A_h acts with the
+ *   diffusion coefficient of each component, every reaction term is in N_h,
+ *   and the shift rules use the real parts of the eigenvalues of the 2 x 2
+ *   reaction block [[-2SA + mu + rho, -A^2], [2SA, A^2 + rho]] (Section 4.3,
+ *   eq. eigenvalues).  Solves apply (D_c scale A_h + shift I)^-1 to component
+ *   c.  FP64 and FP32 transforms, finite differences. */
 typedef struct {
   int32_t precision;
   int32_t beta_mode;
@@ -173,6 +190,8 @@ typedef struct {
   int32_t discretization;
   int32_t sem_order;
   double quad;
+  double step;
+  double gs_da, gs_ds, gs_rho, gs_mu;
 } qn_options;
 
 /* iters: solves performed; status: the qn_status qn_iterate returned;

@@ -73,6 +73,16 @@ typedef struct {
   int32_t boundary;
   double length;
   double lin;
+  /* system: the problem of the 2-component instances: 0 the cubic system of
+   * Section 4.3 (eq. system), 1 the steady Gray-Scott system of Section 6.2
+   * (eq. 2dgrayeq; see QN_NL_GRAYSCOTT in qn.h: Neumann data, FP64 or FP32
+   * transforms, every instance 2-component, the caller's F = (0, rho)).
+   * step: the step size of every update, U -= step dU (0 = 1).
+   * gs_da, gs_ds, gs_rho, gs_mu: the Gray-Scott parameters (0 = the values of
+   * Section 6.2). */
+  int32_t system;
+  double step;
+  double gs_da, gs_ds, gs_rho, gs_mu;
 } qnb_options;
 
 /* qnb_setup with options (NULL: the defaults of qnb_setup).  Besides the
@@ -83,7 +93,12 @@ typedef struct {
  * of a scalar instance: every rule on the range of 3 u^2 + lin gives at least
  * lin (min + max: 2 lin when lin < 0), so lam_min(A_h) + that bound must be
  * positive.  With Neumann data lam_min(A_h) = 0: a fixed beta must be > 0
- * and a shift rule needs lin > 0.
+ * and a shift rule needs lin > 0.  The Gray-Scott system (system = 1): its
+ * shift rules can give beta <= 0, which would make the solve singular; an
+ * instance whose beta_k leaves D_min lam_min(A_h) + beta_k <= 0 stops with
+ * QN_ERR_DIVERGED instead.  QN_ERR_UNSUPPORTED for Gray-Scott with Dirichlet
+ * data, BF16X3 transforms or a scalar instance; QN_ERR_INVALID for a step or
+ * Gray-Scott parameter that is not positive and finite.
  * Host only. */
 qn_status qnb_setup_ex(int32_t count, const int32_t* n, const int32_t* ncomp, int32_t precision,
                        int32_t beta_mode, double beta, const qnb_options* opt, qnb_ctx* out);
@@ -92,6 +107,14 @@ qn_status qnb_instance_layout(qnb_ctx ctx, int32_t i, int64_t* offset, int64_t* 
 qn_status qnb_workspace_bytes(qnb_ctx ctx, size_t* bytes);
 qn_status qnb_bind_workspace(qnb_ctx ctx, void* d_ws, size_t bytes);
 qn_status qnb_set_stream(qnb_ctx ctx, void* stream);
+
+/* Tensor-product solve of every instance (Section 4.1, eq. fin_inverse):
+ * X_i = (scale A_h + shift I)^-1 R_i per component (Gray-Scott: with D_c scale
+ * A_h), on the pools' layout; d_X may alias d_R.  Uses the transform
+ * workspace (any graph of qnb_iterate stays valid).  Asynchronous on the
+ * context's stream.  Errors: QN_ERR_INVALID if scale <= 0 or
+ * scale lam_min(A_h) + shift <= 0 for some instance. */
+qn_status qnb_fdm_solve(qnb_ctx ctx, const double* d_R, double scale, double shift, double* d_X);
 
 /* Time every admissible tile shape of every class's mode products on the
  * bound workspace (contents are overwritten) and keep the fastest.

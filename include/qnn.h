@@ -69,6 +69,27 @@ qn_status qnn_get_grads(qnn_net net, float* h_grads);
 qn_status qnn_forward(qnn_net net, const double* d_f, const double* d_v, int32_t batch,
                       double* d_out);
 
+/* The whole initial guess for one H x W image with a solver context of the
+ * same 2D grid (qn.h, QN_NL_CUBIC, workspace bound): v0 = A_h^-1 f,
+ * d_u0 = A_h^-1 (f - g(f / 50, v0)), its residual sums into d_red
+ * (device double[4], as qn_residual), and the fallback to U_0 = 0 of
+ * qnn_guess_fallback (d_used as there).  d_tmp: caller device scratch of one
+ * image (overwritten).  Every step is enqueued on the network's stream (the
+ * solver context's stream is set to it); asynchronous.  Errors: those of the
+ * steps, QN_ERR_INVALID for null or aliased arrays. */
+qn_status qnn_guess(qnn_net net, qn_ctx solver, const double* d_f, double* d_u0, double* d_tmp,
+                    double* d_red, int32_t* d_used);
+
+/* Inference path of qnn_forward (training always uses FP32): f16 = 0, the FP32
+ * layer kernels (default); f16 = 1, one fused kernel for all five layers with
+ * FP16 activations and weights on the FP16 matrix cores (FP32 accumulation):
+ * each workgroup computes a 16 x 16 output tile and recomputes the halo its
+ * receptive field needs, so no activation leaves the chip.  Its g differs from
+ * the FP32 network's by FP16 rounding (about 1e-3 relative); the guess only
+ * starts the iteration, which reaches the same tolerance.  Host only.
+ * Errors: QN_ERR_INVALID for another value. */
+qn_status qnn_set_inference(qnn_net net, int32_t f16);
+
 /* Fallback to U_0 = 0, stream-ordered and without a host round trip.
  * d_red is the device[4] reduction that qn_residual wrote for the guess
  * d_u0 (H x W, FP64): {sum R^2, min mu, max mu, sum F^2}.  When

@@ -19,7 +19,7 @@ QN_ERR_DIVERGED = 4
 QN_ERR_WORKSPACE = 5
 QN_ERR_UNSUPPORTED = 6
 
-NONLINEARITIES = {"cubic": 0, "quasilinear": 1, "system": 2}
+NONLINEARITIES = {"cubic": 0, "quasilinear": 1, "system": 2, "grayscott": 3}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 BETA_MODES = {"fixed": 0, "midpoint": 1, "max": 2, "sum": 3, "min": 4}
 
@@ -36,7 +36,8 @@ class QNOptions(ctypes.Structure):
     _fields_ = [("precision", c_i32), ("beta_mode", c_i32), ("timing", c_i32),
                 ("boundary", c_i32), ("stream", c_vp), ("length", c_dbl), ("lin", c_dbl),
                 ("cub", c_dbl), ("potential", c_vp), ("discretization", c_i32),
-                ("sem_order", c_i32), ("quad", c_dbl)]
+                ("sem_order", c_i32), ("quad", c_dbl), ("step", c_dbl), ("gs_da", c_dbl),
+                ("gs_ds", c_dbl), ("gs_rho", c_dbl), ("gs_mu", c_dbl)]
 
 
 BOUNDARIES = {"dirichlet": 0, "neumann": 1}
@@ -127,7 +128,7 @@ class Solver:
     def __init__(self, shape, nonlinearity="cubic", beta=0.0, beta_mode="fixed",
                  precision="fp64", timing=False, device="cuda", boundary="dirichlet",
                  length=None, lin=0.0, cub=1.0, potential=None, discretization="fd",
-                 sem_order=0, quad=0.0, workspace=True):
+                 sem_order=0, quad=0.0, workspace=True, step=1.0, gs=None):
         """boundary: "dirichlet" (n interior nodes per axis, h = L/(n+1)) or
         "neumann" (n nodes including both ends, zero normal derivative,
         h = L/(n-1)); length: the domain side L (default 1 for Dirichlet, 2 for
@@ -138,12 +139,14 @@ class Solver:
         (the library reads it on every residual).  discretization: "fd" or "sem"
         (Q^k spectral elements of order sem_order; n = E k - 1 interior nodes for
         Dirichlet data, E k + 1 for Neumann data).  workspace=False skips the
-        device workspace (only residual_noalloc may then be called)."""
+        device workspace (only residual_noalloc may then be called).  step: the
+        step size of iterate (U -= step dU).  gs: "grayscott" only, (D_A, D_S,
+        rho, mu), None = the values of the paper's example."""
         L = lib()
         self.shape = tuple(int(s) for s in shape)
         self.dim = len(self.shape)
         self.nl = nonlinearity
-        self.ncomp = 2 if nonlinearity == "system" else 1
+        self.ncomp = 2 if nonlinearity in ("system", "grayscott") else 1
         self.device = torch.device(device)
         g = QNGrid()
         g.dim = self.dim
@@ -162,6 +165,9 @@ class Solver:
         o.quad = float(quad)
         o.discretization = DISCRETIZATIONS[discretization]
         o.sem_order = int(sem_order)
+        o.step = float(step)
+        if gs is not None:
+            o.gs_da, o.gs_ds, o.gs_rho, o.gs_mu = (float(v) for v in gs)
         self._potential = None
         if potential is not None:
             if (potential.dtype != torch.float64 or tuple(potential.shape) != self.shape

@@ -13,7 +13,9 @@ _B = None
 
 
 class QNBOptions(ctypes.Structure):
-    _fields_ = [("boundary", ctypes.c_int32), ("length", ctypes.c_double), ("lin", ctypes.c_double)]
+    _fields_ = [("boundary", ctypes.c_int32), ("length", ctypes.c_double), ("lin", ctypes.c_double),
+                ("system", ctypes.c_int32), ("step", ctypes.c_double), ("gs_da", ctypes.c_double),
+                ("gs_ds", ctypes.c_double), ("gs_rho", ctypes.c_double), ("gs_mu", ctypes.c_double)]
 
 
 class QNBResult(ctypes.Structure):
@@ -42,11 +44,12 @@ def _qnb():
     L.qnb_class_info.argtypes = [c_vp, ctypes.c_int32, i32p]
     L.qnb_iterate.argtypes = [c_vp, c_vp, c_vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                               ctypes.POINTER(QNBResult)]
+    L.qnb_fdm_solve.argtypes = [c_vp, c_vp, ctypes.c_double, ctypes.c_double, c_vp]
     L.qnb_destroy.argtypes = [c_vp]
     L.qnb_destroy.restype = None
     for n in ("qnb_setup", "qnb_setup_ex", "qnb_field_elems", "qnb_instance_layout", "qnb_workspace_bytes",
               "qnb_bind_workspace", "qnb_set_stream", "qnb_autotune", "qnb_class_count",
-              "qnb_class_info", "qnb_iterate"):
+              "qnb_class_info", "qnb_iterate", "qnb_fdm_solve"):
         getattr(L, n).restype = ctypes.c_int32
     _B = L
     return L
@@ -58,10 +61,13 @@ class BatchedSolver:
     2 (system)}; one U pool and one F pool of FP64 on the GPU.  boundary,
     length (the side of the square; default 1 for Dirichlet, 2 for Neumann
     data, as for the single-problem solver) and lin apply to every instance
-    (qnb_options)."""
+    (qnb_options).  system: the 2-component problem, "cubic" (Section 4.3)
+    or "grayscott" (Section 6.2; gs = (D_A, D_S, rho, mu), None = the
+    paper's); step: the step size of every update."""
 
     def __init__(self, sizes, ncomp, precision="fp32", beta_mode="midpoint", beta=0.0,
-                 device="cuda", boundary="dirichlet", length=None, lin=0.0):
+                 device="cuda", boundary="dirichlet", length=None, lin=0.0, system="cubic",
+                 step=1.0, gs=None):
         L = _qnb()
         self.count = len(sizes)
         self.sizes = [int(s) for s in sizes]
@@ -72,7 +78,9 @@ class BatchedSolver:
         ctx = c_vp()
         if length is None:
             length = 2.0 if boundary == "neumann" else 1.0
-        opt = QNBOptions(BOUNDARIES[boundary], float(length), float(lin))
+        opt = QNBOptions(BOUNDARIES[boundary], float(length), float(lin),
+                         {"cubic": 0, "grayscott": 1}[system], float(step),
+                         *(float(v) for v in (gs if gs is not None else (0.0, 0.0, 0.0, 0.0))))
         check(L.qnb_setup_ex(self.count, n_arr, c_arr, PRECISIONS[precision],
                              BETA_MODES[beta_mode], float(beta), ctypes.byref(opt),
                              ctypes.byref(ctx)))
@@ -137,6 +145,16 @@ class BatchedSolver:
             check(status)
         return status, [{"iters": r.iters, "status": r.status, "relres": r.relres,
                          "relres0": r.relres0} for r in res]
+
+    def fdm_solve(self, R, scale=1.0, shift=0.0, X=None):
+        """X_i = (scale A_h + shift I)^-1 R_i for every instance (pool layout)."""
+        if R.dtype != torch.float64 or not R.is_cuda or R.numel() != self.field_elems:
+            raise ValueError(f"R must be a float64 CUDA pool of {self.field_elems} elements")
+        X = self.pool() if X is None else X
+        self._stream()
+        check(_qnb().qnb_fdm_solve(self._ctx, ctypes.c_void_p(R.data_ptr()), float(scale),
+                                   float(shift), ctypes.c_void_p(X.data_ptr())))
+        return X
 
     def close(self):
         if getattr(self, "_ctx", None):

@@ -114,7 +114,10 @@ struct qn_ctx_s {
   std::vector<double> hS[3], hlam[3];  // dense S or folded FeT|FoT|Fe|Fo; lam (split if folded)
   // workspace layout (byte offsets)
   size_t off_S[3] = {0, 0, 0}, off_Slo[3] = {0, 0, 0}, off_Slo2[3] = {0, 0, 0}, off_lam[3] = {0, 0, 0};
-  size_t off_W1 = 0, off_W2 = 0, off_part = 0, off_scal = 0, off_coef = 0, need = 0;
+  size_t off_W1 = 0, off_W2 = 0, off_part = 0, off_scal = 0, off_coef = 0, off_cscale = 0,
+         need = 0;
+  double step = 1.0;  // qn_iterate: U -= step * dU
+  double gs[4] = {0.0, 0.0, 0.0, 0.0};  // Gray-Scott: D_A, D_S, rho, mu
   int max_blocks = 0;
   char* ws = nullptr;
   hipError_t sticky = hipSuccess;
@@ -296,6 +299,10 @@ ResidualArgs residual_args(qn_ctx c, const double* U, const double* F, double* R
   a.rz = c->dim == 3 ? RESIDUAL_RZ : residual_planar_rows(a.ox, a.oy);
   a.sem_k = c->sem_k;
   for (int i = 0; i < c->dim && c->sem_k > 0; ++i) a.hb[i] = c->at<double>(c->off_Hb[i]);
+  a.gs_da = c->gs[0];
+  a.gs_ds = c->gs[1];
+  a.gs_rho = c->gs[2];
+  a.gs_mu = c->gs[3];
   return a;
 }
 
@@ -508,6 +515,11 @@ EpiArgs epi_args(qn_ctx c, const double* coef, double* dense) {
   ep.ny = c->n[1];
   ep.nz = c->n[2];
   ep.lamX = c->at<double>(c->off_lam[0]);
+  ep.step = c->step;
+  if (c->nl == QN_NL_GRAYSCOTT) {  // 2D: the divide's slab index is the component
+    ep.cscale = c->at<double>(c->off_cscale);
+    ep.comp_div = 1;
+  }
   return ep;
 }
 
@@ -577,8 +589,9 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   for (int a = 0; a < grid->dim; ++a)
     if (grid->n[a] < 1 || grid->n[a] > 4096)
       return fail(QN_ERR_INVALID, "n[%d] = %d out of range [1, 4096]", a, grid->n[a]);
-  if (nonlinearity < 0 || nonlinearity > 2) return fail(QN_ERR_INVALID, "unknown nonlinearity");
-  const int want_comp = nonlinearity == QN_NL_SYS2_CUBIC ? 2 : 1;
+  if (nonlinearity < 0 || nonlinearity > 3) return fail(QN_ERR_INVALID, "unknown nonlinearity");
+  const int want_comp =
+      (nonlinearity == QN_NL_SYS2_CUBIC || nonlinearity == QN_NL_GRAYSCOTT) ? 2 : 1;
   if (grid->ncomp != want_comp)
     return fail(QN_ERR_INVALID, "ncomp = %d but the nonlinearity needs %d", grid->ncomp,
                 want_comp);
@@ -605,9 +618,28 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   if ((cub != 1.0 || o.quad != 0.0 || o.potential) && nonlinearity != QN_NL_CUBIC)
     return fail(QN_ERR_INVALID, "cubic / quadratic coefficients and a potential are supported "
                                 "for QN_NL_CUBIC only");
+  const double step = o.step == 0.0 ? 1.0 : o.step;
+  if (!(step > 0.0) || !std::isfinite(step))
+    return fail(QN_ERR_INVALID, "step must be positive and finite");
+  double gs[4] = {o.gs_da, o.gs_ds, o.gs_rho, o.gs_mu};
+  if (nonlinearity == QN_NL_GRAYSCOTT) {
+    const double paper[4] = {2.5e-4, 5e-4, 0.04, 0.065};  // Section 6.2
+    for (int i = 0; i < 4; ++i) {
+      if (gs[i] == 0.0) gs[i] = paper[i];
+      if (!(gs[i] > 0.0) || !std::isfinite(gs[i]))
+        return fail(QN_ERR_INVALID, "Gray-Scott parameters must be positive and finite");
+    }
+    if (grid->dim != 2)
+      return fail(QN_ERR_UNSUPPORTED, "the Gray-Scott system is built for 2D grids");
+    if (o.boundary != QN_BC_NEUMANN)
+      return fail(QN_ERR_UNSUPPORTED, "the Gray-Scott system is built with Neumann data");
+  } else if (gs[0] != 0.0 || gs[1] != 0.0 || gs[2] != 0.0 || gs[3] != 0.0) {
+    return fail(QN_ERR_INVALID, "Gray-Scott parameters given for another nonlinearity");
+  }
   if (o.boundary == QN_BC_NEUMANN) {
-    if (nonlinearity != QN_NL_CUBIC)
-      return fail(QN_ERR_UNSUPPORTED, "Neumann data is supported for QN_NL_CUBIC only");
+    if (nonlinearity != QN_NL_CUBIC && nonlinearity != QN_NL_GRAYSCOTT)
+      return fail(QN_ERR_UNSUPPORTED,
+                  "Neumann data is supported for QN_NL_CUBIC and QN_NL_GRAYSCOTT only");
     if (o.precision != QN_PREC_FP64 && o.precision != QN_PREC_FP32)
       return fail(QN_ERR_UNSUPPORTED, "Neumann data is supported with FP64 and FP32 transforms");
     for (int a = 0; a < grid->dim; ++a)
@@ -654,6 +686,8 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   c->quad = o.quad;
   c->pot = o.potential;
   c->sem_k = o.discretization == QN_DISC_SEM ? o.sem_order : 0;
+  c->step = step;
+  for (int i = 0; i < 4; ++i) c->gs[i] = gs[i];
   c->lam_min_sum = 0.0;
   for (int a = 0; a < 3; ++a) {
     if (a >= c->dim) {
@@ -709,6 +743,9 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
       for (double& l : c->hlam[a]) l /= length * length;
     c->lam_min_sum += c->hlam[a][0];  // lam_1 (Dirichlet) or 0 (Neumann) leads both orderings
   }
+  // Gray-Scott: component c solves with D_c A_h, so the smallest eigenvalue
+  // of the solve operator's linear part is min(D_A, D_S) lam_min(A_h).
+  if (c->nl == QN_NL_GRAYSCOTT) c->lam_min_sum *= std::min(c->gs[0], c->gs[1]);
   // The fixed beta must give a positive definite solve operator (Section 5:
   // beta > -lam_min(A_h)).  The midpoint rules produce beta >= 0 here.
   if (o.beta_mode == QN_BETA_FIXED && c->lam_min_sum + beta <= 0.0) {
@@ -767,6 +804,8 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   c->off_scal = off;
   off += align256(sizeof(DevScalars));
   c->off_coef = off;
+  off += align256(2 * sizeof(double));
+  c->off_cscale = off;  // Gray-Scott: per-component diffusion {D_A, D_S}
   off += align256(2 * sizeof(double));
   c->need = off;
   *out = c;
@@ -835,7 +874,12 @@ qn_status qn_bind_workspace(qn_ctx c, void* d_ws, size_t bytes) {
                          hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "upload eigen-data");
   }
-  // hS/hlam stay alive in the context, so the async uploads above are safe.
+  if (c->nl == QN_NL_GRAYSCOTT) {
+    e = hipMemcpyAsync(c->ws + c->off_cscale, c->gs, 2 * sizeof(double), hipMemcpyHostToDevice,
+                       c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "upload diffusion coefficients");
+  }
+  // hS/hlam/gs stay alive in the context, so the async uploads above are safe.
   return QN_OK;
 }
 

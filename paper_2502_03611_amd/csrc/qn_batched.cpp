@@ -49,6 +49,7 @@ struct Cls {
   FoldTile fR{32, 32, 0}, fL{32, 32, 0}, fLi{32, 32, 0}, fRi{32, 32, 0};
   FoldAxis ax{};
   double ih2 = 0.0;           // 1 / h^2 of both axes
+  double lam_min = 0.0;       // smallest eigenvalue of the solve operator without the shift
   hipStream_t s = nullptr;    // per-class stream (default priority)
   hipEvent_t ev = nullptr;
   std::vector<double> hS, hlam;
@@ -62,6 +63,11 @@ struct qnb_ctx_s {
   double beta = 0.0;
   int bc = QN_BC_DIRICHLET;
   double length = 1.0, lin = 0.0;
+  int system = 0;                        // 2-component problem: 0 cubic system, 1 Gray-Scott
+  double step = 1.0;                     // U -= step dU
+  double gs[4] = {0.0, 0.0, 0.0, 0.0};  // Gray-Scott: D_A, D_S, rho, mu
+  size_t off_cscale = 0;                 // device {D_A, D_S}
+  size_t off_coef = 0;                   // device {scale, shift} of qnb_fdm_solve
   std::vector<int> n, ncomp, inst_cls, inst_pos;
   std::vector<Cls> cls;
   long long field_elems = 0;
@@ -123,6 +129,11 @@ EpiArgs epi_for(qnb_ctx c, const Cls& k, double* dense_base) {
   ep.nz = 1;
   ep.skip = (const int*)(c->ws + k.off_done);
   ep.inst_mod = k.K;
+  ep.step = c->step;
+  if (c->system == 1 && k.ncomp == 2) {  // slab index = c * K + instance
+    ep.cscale = (const double*)(c->ws + c->off_cscale);
+    ep.comp_div = k.K;
+  }
   return ep;
 }
 
@@ -153,7 +164,11 @@ hipError_t class_iteration(qnb_ctx c, Cls& k, double* U, const double* F, double
   a.nx = a.ny = k.n;
   a.nz = k.K;
   a.dim = 2;
-  a.nl = k.ncomp == 2 ? NL_SYS2 : NL_CUBIC;
+  a.nl = k.ncomp == 2 ? (c->system == 1 ? NL_GS : NL_SYS2) : NL_CUBIC;
+  a.gs_da = c->gs[0];
+  a.gs_ds = c->gs[1];
+  a.gs_rho = c->gs[2];
+  a.gs_mu = c->gs[3];
   a.bc = c->bc;
   a.lin = c->lin;
   a.ihx2 = a.ihy2 = k.ih2;
@@ -167,7 +182,7 @@ hipError_t class_iteration(qnb_ctx c, Cls& k, double* U, const double* F, double
   BState* st = (BState*)(c->ws + k.off_state);
   int* done = (int*)(c->ws + k.off_done);
   e = launch_bfinalize(a.partials, k.bpi, k.K, st, done, batch_rule(c->beta_mode), c->beta, rtol,
-                       max_iter, s);
+                       max_iter, k.lam_min, s);
   if (e != hipSuccess) return e;
   void* W1 = c->ws + k.off_W1;
   void* W2 = c->ws + k.off_W2;
@@ -238,8 +253,32 @@ qn_status qnb_setup_ex(int32_t count, const int32_t* n, const int32_t* ncomp, in
   if (beta_mode < QN_BETA_FIXED || beta_mode > QN_BETA_MIN)
     return bad(QN_ERR_INVALID, "unknown beta_mode");
   if (!std::isfinite(beta)) return bad(QN_ERR_INVALID, "beta not finite");
-  qnb_options o{QN_BC_DIRICHLET, 1.0, 0.0};
+  qnb_options o{};
+  o.boundary = QN_BC_DIRICHLET;
+  o.length = 1.0;
   if (opt) o = *opt;
+  if (o.system != 0 && o.system != 1) return bad(QN_ERR_INVALID, "unknown system");
+  const double step = o.step == 0.0 ? 1.0 : o.step;
+  if (!(step > 0.0) || !std::isfinite(step))
+    return bad(QN_ERR_INVALID, "step must be positive and finite");
+  double gs[4] = {o.gs_da, o.gs_ds, o.gs_rho, o.gs_mu};
+  if (o.system == 1) {
+    const double paper[4] = {2.5e-4, 5e-4, 0.04, 0.065};  // Section 6.2
+    for (int i = 0; i < 4; ++i) {
+      if (gs[i] == 0.0) gs[i] = paper[i];
+      if (!(gs[i] > 0.0) || !std::isfinite(gs[i]))
+        return bad(QN_ERR_INVALID, "Gray-Scott parameters must be positive and finite");
+    }
+    if (o.boundary != QN_BC_NEUMANN)
+      return bad(QN_ERR_UNSUPPORTED, "the Gray-Scott system is built with Neumann data");
+    if (precision == QN_PREC_BF16X3)
+      return bad(QN_ERR_UNSUPPORTED, "the Gray-Scott system needs FP64 or FP32 transforms");
+    for (int i = 0; i < count; ++i)
+      if (ncomp[i] != 2)
+        return set_error(QN_ERR_UNSUPPORTED, "instance %d: the Gray-Scott batch is 2-component", i);
+  } else if (gs[0] != 0.0 || gs[1] != 0.0 || gs[2] != 0.0 || gs[3] != 0.0) {
+    return bad(QN_ERR_INVALID, "Gray-Scott parameters given for the cubic system");
+  }
   if (o.boundary != QN_BC_DIRICHLET && o.boundary != QN_BC_NEUMANN)
     return bad(QN_ERR_INVALID, "unknown boundary");
   if (!std::isfinite(o.length) || o.length < 0.0)
@@ -253,11 +292,11 @@ qn_status qnb_setup_ex(int32_t count, const int32_t* n, const int32_t* ncomp, in
   // stay positive.  Every rule on the range of 3 u^2 + lin is at least lin.
   if (neu && beta_mode == QN_BETA_FIXED && !(beta > 0.0))
     return bad(QN_ERR_INVALID, "Neumann data needs a fixed beta > 0");
-  if (neu && beta_mode != QN_BETA_FIXED && !(o.lin > 0.0))
+  if (neu && beta_mode != QN_BETA_FIXED && o.system == 0 && !(o.lin > 0.0))
     return bad(QN_ERR_INVALID, "Neumann data with a shift rule needs lin > 0");
   std::map<std::pair<int, int>, int> key;
   for (int i = 0; i < count; ++i) {
-    if (ncomp[i] == 2 && (neu || o.lin != 0.0))
+    if (ncomp[i] == 2 && o.system == 0 && (neu || o.lin != 0.0))
       return set_error(QN_ERR_INVALID, "instance %d: the 2-component system takes neither "
                                        "Neumann data nor lin", i);
     if (neu && n[i] < 2)
@@ -271,6 +310,9 @@ qn_status qnb_setup_ex(int32_t count, const int32_t* n, const int32_t* ncomp, in
   c->bc = o.boundary;
   c->length = o.length;
   c->lin = o.lin;
+  c->system = o.system;
+  c->step = step;
+  for (int i = 0; i < 4; ++i) c->gs[i] = gs[i];
   c->n.assign(n, n + count);
   c->ncomp.assign(ncomp, ncomp + count);
   c->inst_cls.resize(count);
@@ -324,10 +366,12 @@ qn_status qnb_setup_ex(int32_t count, const int32_t* n, const int32_t* ncomp, in
     }
     lam_min = std::min(lam_min, 2.0 * k.hlam[0]);
     if (k.ncomp == 1) lam_min1 = std::min(lam_min1, 2.0 * k.hlam[0]);
+    // component c solves with D_c A_h for the Gray-Scott system
+    k.lam_min = 2.0 * k.hlam[0] * (c->system == 1 ? std::min(c->gs[0], c->gs[1]) : 1.0);
     // The min rule on a 2-component system can give beta down to -1 (the
     // smallest eigenvalue of the 2x2 block at u = v = 0); every other rule
     // gives beta >= 0 on these problems.
-    if (beta_mode == QN_BETA_MIN && k.ncomp == 2 && 2.0 * k.hlam[0] <= 1.0) {
+    if (beta_mode == QN_BETA_MIN && k.ncomp == 2 && c->system == 0 && 2.0 * k.hlam[0] <= 1.0) {
       const int nn = k.n;
       delete c;
       return set_error(QN_ERR_INVALID, "n = %d: the min rule on a system can make the solve "
@@ -393,6 +437,10 @@ qn_status qnb_setup_ex(int32_t count, const int32_t* n, const int32_t* ncomp, in
     return bad(QN_ERR_INVALID, "lin makes the shift rule's solve singular or indefinite for some "
                                "instance (lin <= -lam_min(A_h))");
   }
+  c->off_cscale = off;
+  off += a256(2 * sizeof(double));
+  c->off_coef = off;
+  off += a256(2 * sizeof(double));
   c->field_elems = fe;
   c->need = off;
   *out = c;
@@ -466,6 +514,9 @@ qn_status qnb_bind_workspace(qnb_ctx c, void* d_ws, size_t bytes) {
       e = hipMemcpyAsync(c->ws + k.off_lam, k.hlam.data(), (size_t)k.p * 8, hipMemcpyHostToDevice,
                          c->stream);
   }
+  if (e == hipSuccess && c->system == 1)
+    e = hipMemcpyAsync(c->ws + c->off_cscale, c->gs, 2 * sizeof(double), hipMemcpyHostToDevice,
+                       c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_bad(c, e, "bind workspace");
   return QN_OK;
@@ -561,6 +612,65 @@ qn_status qnb_autotune(qnb_ctx c) {
 qn_status qnb_class_count(qnb_ctx c, int32_t* classes) {
   if (!c || !classes) return bad(QN_ERR_INVALID, "null argument");
   *classes = (int32_t)c->cls.size();
+  return QN_OK;
+}
+
+qn_status qnb_fdm_solve(qnb_ctx c, const double* d_R, double scale, double shift, double* d_X) {
+  if (!c || !c->ws) return bad(QN_ERR_WORKSPACE, "workspace not bound");
+  if (c->sticky != hipSuccess) return set_error(QN_ERR_HIP, "sticky HIP error");
+  if (!d_R || !d_X || ((uintptr_t)d_R & 7u) || ((uintptr_t)d_X & 7u))
+    return bad(QN_ERR_INVALID, "null or misaligned R or X");
+  if (!(scale > 0.0) || !std::isfinite(scale) || !std::isfinite(shift))
+    return bad(QN_ERR_INVALID, "scale must be positive and finite, shift finite");
+  for (const auto& k : c->cls)
+    if (!(scale * k.lam_min + shift > 0.0))
+      return set_error(QN_ERR_INVALID, "n = %d: scale lam_min(A_h) + shift <= 0 (singular or "
+                                       "indefinite)", k.n);
+  double* coef = (double*)(c->ws + c->off_coef);
+  hipError_t e = launch_set_coef(coef, scale, shift, c->stream);
+  for (auto& k : c->cls) {
+    if (e != hipSuccess) break;
+    void* W1 = c->ws + k.off_W1;
+    void* W2 = c->ws + k.off_W2;
+    // the class block (ncomp, K, n, n) -> (ncomp, K, P, P), zero padding
+    e = launch_pad_copy(d_R + k.off_field, W1, c->prec == QN_PREC_FP64 ? 0 : 1, k.ncomp, k.n, k.n,
+                        k.K, k.p, k.p, k.K, c->stream);
+    if (e != hipSuccess) break;
+    EpiArgs ep = epi_for(c, k, d_X);
+    ep.skip = nullptr;  // every instance
+    ep.coef = coef;
+    ep.coef_stride = 0;
+    const int rows = k.ncomp * k.K * k.p;
+    const int slabs = k.ncomp * k.K;
+    const long long sl = (long long)k.p * k.p;
+    if (c->fold) {
+      const FoldOperands F = fops(c, k);
+      e = launch_fold(FK_RFWD, c->prec, F, W1, W2, k.ax, 0, 0, 0, rows, EPI_STORE, ep, k.fR,
+                      c->stream);
+      if (e == hipSuccess)
+        e = launch_fold(FK_LFWD, c->prec, F, W2, W1, k.ax, k.p, slabs, sl, rows, EPI_DIVIDE, ep,
+                        k.fL, c->stream);
+      if (e == hipSuccess)
+        e = launch_fold(FK_LINV, c->prec, F, W1, W2, k.ax, k.p, slabs, sl, rows, EPI_STORE, ep,
+                        k.fLi, c->stream);
+      if (e == hipSuccess)
+        e = launch_fold(FK_RINV, c->prec, F, W2, nullptr, k.ax, 0, 0, 0, rows, EPI_STORE_DENSE, ep,
+                        k.fRi, c->stream);
+    } else {
+      const GemmOperands S = ops(c, k);
+      e = launch_gemm_right(c->prec, S, W1, W2, rows, k.p, EPI_STORE, ep, k.tmR, k.tnR, c->stream);
+      if (e == hipSuccess)
+        e = launch_gemm_left(c->prec, S, W2, W1, k.p, k.p, slabs, sl, EPI_DIVIDE, ep, k.tmL, k.tnL,
+                             c->stream);
+      if (e == hipSuccess)
+        e = launch_gemm_left(c->prec, S, W1, W2, k.p, k.p, slabs, sl, EPI_STORE, ep, k.tmL, k.tnL,
+                             c->stream);
+      if (e == hipSuccess)
+        e = launch_gemm_right(c->prec, S, W2, nullptr, rows, k.p, EPI_STORE_DENSE, ep, k.tmR,
+                              k.tnR, c->stream);
+    }
+  }
+  if (e != hipSuccess) return hip_bad(c, e, "batched solve");
   return QN_OK;
 }
 

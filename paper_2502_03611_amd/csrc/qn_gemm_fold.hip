@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256, 2) void k_fold_left_fwd(const T* __restrict__ 
   T* Cb = C + (long long)b * bstride;
   if (EPI == EPI_DIVIDE) {
     const double* cf = ep.coef + (long long)inst * ep.coef_stride;
-    const double scale = cf[0], beta = cf[1];
+    const double scale = cf[0] * (ep.cscale ? ep.cscale[b / ep.comp_div] : 1.0), beta = cf[1];
     double cn[BN];
 #pragma unroll
     for (int j = 0; j < BN; ++j) {
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(256, 2) void k_fold_left_fwd2(const T* __restrict__
   double scale = 1.0, beta = 0.0, cn[BN];
   if (EPI == EPI_DIVIDE) {
     const double* cf = ep.coef + (long long)inst * ep.coef_stride;
-    scale = cf[0];
+    scale = cf[0] * (ep.cscale ? ep.cscale[b / ep.comp_div] : 1.0);
     beta = cf[1];
 #pragma unroll
     for (int j = 0; j < BN; ++j) {
@@ -754,6 +754,7 @@ __global__ __launch_bounds__(256, 2) void k_fold_right_inv(const T* __restrict__
     }
     double old1[4][BN], old2[4][BN];
     const double us = (EPI == EPI_SUB_DENSE && ep.uscale) ? *ep.uscale : 1.0;
+    const double st = (EPI == EPI_SUB_DENSE && ep.step != 0.0) ? ep.step : 1.0;
     if (EPI == EPI_SUB_DENSE) {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -779,8 +780,8 @@ __global__ __launch_bounds__(256, 2) void k_fold_right_inv(const T* __restrict__
           C[base[q] + k] = v1;
           if (pair) C[base[q] + na - 1 - k] = p - qq;
         } else if (EPI == EPI_SUB_DENSE) {
-          ep.dense[base[q] + k] = us * old1[q][j] - (double)v1;
-          if (pair) ep.dense[base[q] + na - 1 - k] = us * old2[q][j] - (double)(p - qq);
+          ep.dense[base[q] + k] = us * old1[q][j] - st * (double)v1;
+          if (pair) ep.dense[base[q] + na - 1 - k] = us * old2[q][j] - st * (double)(p - qq);
         } else {
           ep.dense[base[q] + k] = (double)v1;
           if (pair) ep.dense[base[q] + na - 1 - k] = (double)(p - qq);

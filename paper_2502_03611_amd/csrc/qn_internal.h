@@ -40,7 +40,10 @@ enum ShiftRule : int {
   RULE_MIN = 5,        // c = 1, beta = mumin
 };
 
-enum Nonlin : int { NL_CUBIC = 0, NL_QUASILIN = 1, NL_SYS2 = 2 };
+// NL_GS: the steady Gray-Scott system (2D), R = (D_A A A - S A^2 + (mu + rho) A - F_A,
+// D_S A S + S A^2 + rho S - F_S) with A the discrete -Lap; its shift rule uses the
+// real parts of the 2 x 2 reaction-block eigenvalues.
+enum Nonlin : int { NL_CUBIC = 0, NL_QUASILIN = 1, NL_SYS2 = 2, NL_GS = 3 };
 
 // Epilogues of the mode-product GEMMs.
 enum Epi : int {
@@ -68,6 +71,14 @@ struct EpiArgs {
   // EPI_SUB_DENSE of the folded kernels: the old values are multiplied by
   // *uscale before the subtraction (the eigenproblem's normalisation), NULL: 1.
   const double* uscale;
+  // Per-component multiplier of the eigenvalue sum in EPI_DIVIDE (component
+  // = slab index / comp_div), NULL: 1 (the Gray-Scott system's diffusion
+  // coefficients: (D_c A + beta I)^-1 per component).
+  const double* cscale;
+  int comp_div;
+  // EPI_SUB_DENSE of the folded kernels: dense = old - step * acc (the damped
+  // step of the Gray-Scott system; 1 otherwise).
+  double step;
 };
 
 // Dense split-bf16 mode products (qn_gemm_bf16.hip), FP32 tensors.  All
@@ -162,6 +173,8 @@ struct ResidualArgs {
   // hb[a][j * (2k + 1) + d + k] = H[j][j + d]; the cubic problem only.
   int sem_k = 0;
   const double* hb[3] = {nullptr, nullptr, nullptr};
+  // Gray-Scott system (NL_GS): diffusion coefficients and reaction rates.
+  double gs_da = 0.0, gs_ds = 0.0, gs_rho = 0.0, gs_mu = 0.0;
 };
 hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t st);
 // Spectral element residual (qn_sem.hip): same outputs and partials as
@@ -205,10 +218,12 @@ static_assert(sizeof(BState) % sizeof(double) == 0, "BState must be a whole numb
 // Batched finalize: workgroup k reduces partials [k*bpi, (k+1)*bpi) of one
 // class and updates st[k] (stopping rule, shift rule `rule` of ShiftRule
 // other than RULE_COEFF_MID, iteration count).  done[k] mirrors st[k].done as
-// a plain int array (the GEMM/residual skip flags).
+// a plain int array (the GEMM/residual skip flags).  An instance whose shift
+// leaves lam_min + beta <= 0 (lam_min: the smallest eigenvalue of the class's
+// solve operator without the shift) stops as diverged instead of solving.
 hipError_t launch_bfinalize(const double* partials, int bpi, int K, BState* st, int* done,
                             int rule, double beta_fixed, double rtol, int max_iter,
-                            hipStream_t s);
+                            double lam_min, hipStream_t s);
 hipError_t launch_breset(BState* st, int* done, int K, hipStream_t s);
 
 // Fixed-order reduction of the residual partials + shift rule.

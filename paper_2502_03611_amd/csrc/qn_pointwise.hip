@@ -285,7 +285,7 @@ constexpr int R2X = 256;
 
 template <int NL, typename TO, int BC, int MODE = 0>
 __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
-  constexpr int NC = (NL == NL_SYS2) ? 2 : 1;
+  constexpr int NC = (NL == NL_SYS2 || NL == NL_GS) ? 2 : 1;
   const int lane = threadIdx.x & 63;
   const int gx = gridDim.x, gy = gridDim.y;
   const int tile = xcd_tile((blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x, gx * gy * gridDim.z);
@@ -397,6 +397,19 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
               rw = wt;
             }
           }
+        } else if (NL == NL_GS) {
+          // Gray-Scott: diffusion D_A, D_S on the Laplacians, all reaction
+          // terms pointwise; the shift uses the real parts of the eigenvalues
+          // of the reaction block [[-2SA + mu + rho, -A^2], [2SA, A^2 + rho]].
+          const double A = uc[0], S = uc[NC - 1];
+          const double sa = S * A, sa2 = sa * A, a2 = A * A;
+          r[0] = a.gs_da * lap[0] - sa2 + (a.gs_mu + a.gs_rho) * A - f[0];
+          r[NC - 1] = a.gs_ds * lap[NC - 1] + sa2 + a.gs_rho * S - f[NC - 1];
+          const double ea = -2.0 * sa + a.gs_mu + a.gs_rho, eb = -a2, ec = 2.0 * sa,
+                       ed = a2 + a.gs_rho;
+          const double root = sqrt(fmax((ea - ed) * (ea - ed) + 4.0 * eb * ec, 0.0));
+          mn = fmin(mn, 0.5 * (ea + ed - root));
+          mx = fmax(mx, 0.5 * (ea + ed + root));
         } else {
           const double u = uc[0], v = uc[NC - 1];
           r[0] = lap[0] + u * u * u - v - f[0];
@@ -505,6 +518,20 @@ hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t 
         launch_cubic<0>(a, g, planar, st);
       break;
     case NL_QUASILIN: launch_nl<NL_QUASILIN>(a, g, planar, st); break;
+    case NL_GS:  // 2D only (planar kernel), Dirichlet or Neumann data
+      if (!planar) return hipErrorInvalidValue;
+      if (a.out_prec == 0) {
+        if (a.bc == 1)
+          hipLaunchKernelGGL((k_residual2d<NL_GS, double, 1>), g, dim3(R2X), 0, st, a);
+        else
+          hipLaunchKernelGGL((k_residual2d<NL_GS, double, 0>), g, dim3(R2X), 0, st, a);
+      } else {
+        if (a.bc == 1)
+          hipLaunchKernelGGL((k_residual2d<NL_GS, float, 1>), g, dim3(R2X), 0, st, a);
+        else
+          hipLaunchKernelGGL((k_residual2d<NL_GS, float, 0>), g, dim3(R2X), 0, st, a);
+      }
+      break;
     default: launch_nl<NL_SYS2>(a, g, planar, st); break;
   }
   return hipGetLastError();
@@ -671,7 +698,7 @@ hipError_t launch_scale(double* u, long long n, const double* s, hipStream_t st)
 __global__ __launch_bounds__(256) void k_bfinalize(const double* __restrict__ partials, int bpi,
                                                    BState* __restrict__ st, int* __restrict__ done,
                                                    int rule, double beta_fixed, double rtol,
-                                                   int max_iter) {
+                                                   int max_iter, double lam_min) {
   BState& s = st[blockIdx.x];
   if (s.done) return;
   const double* pp = partials + 4LL * bpi * blockIdx.x;
@@ -700,9 +727,15 @@ __global__ __launch_bounds__(256) void k_bfinalize(const double* __restrict__ pa
       s.done = 1;
       s.status = 3;  // QN_ERR_NOT_CONVERGED
     } else {
-      s.scale = 1.0;
-      s.beta = rule_beta(rule, mn, mx, beta_fixed);
-      s.iters += 1;
+      const double b = rule_beta(rule, mn, mx, beta_fixed);
+      if (!(lam_min + b > 0.0)) {  // singular or indefinite solve operator
+        s.done = 1;
+        s.status = 4;  // QN_ERR_DIVERGED
+      } else {
+        s.scale = 1.0;
+        s.beta = b;
+        s.iters += 1;
+      }
     }
     done[blockIdx.x] = s.done;
   }
@@ -710,9 +743,9 @@ __global__ __launch_bounds__(256) void k_bfinalize(const double* __restrict__ pa
 
 hipError_t launch_bfinalize(const double* partials, int bpi, int K, BState* st, int* done,
                             int rule, double beta_fixed, double rtol, int max_iter,
-                            hipStream_t s) {
+                            double lam_min, hipStream_t s) {
   hipLaunchKernelGGL(k_bfinalize, dim3(K), dim3(256), 0, s, partials, bpi, st, done, rule,
-                     beta_fixed, rtol, max_iter);
+                     beta_fixed, rtol, max_iter, lam_min);
   return hipGetLastError();
 }
 

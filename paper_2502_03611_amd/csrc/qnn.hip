@@ -488,11 +488,191 @@ static void launch_conv32(const float* in, const float* wk, const float* bias, c
                      wk, bias, zprev, out0, out1, H, W, tx, ty);
 }
 
+// ------------------------------------------------- fused inference (FP16)
+//
+// All five layers of one 16 x 16 output tile in one workgroup, activations in
+// LDS as FP16, every layer on v_mfma_f32_16x16x32_f16 with FP32 accumulation.
+// Layer l's output region extends 5 - l pixels beyond the tile on each side
+// (the receptive field of the layers after it), so a workgroup needs no data
+// from its neighbours: the halo is recomputed (layers 2-4 compute 1.57 times
+// the tile's pixels).  One MFMA covers 16 pixels (rows) x 16 output channels
+// (columns) x 32 input channels (the contraction): a 32 -> 32 layer takes one
+// MFMA per 3 x 3 tap and channel half; layer 1 packs its 2 channels x 9 taps
+// into one 32-deep contraction (18 used), layer 5 uses output column 0 only.
+// Positions outside the image are stored as zero (the zero "same" padding of
+// every layer).  Weights come as per-lane FP16 fragments (k_prep_half) and
+// stay in registers for the whole layer.
+constexpr int FT = 16;               // output tile side
+constexpr int FSI = FT + 10;         // input region side
+constexpr int FS1 = FT + 8;          // layer-1 output side
+constexpr int FPS = 40;              // LDS pixel stride in halves (16-byte aligned, conflict-free)
+constexpr int FUSED_THREADS = 512;
+
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+
+// One layer with 32 input channels: out region side S (origin o pixels
+// before the tile), input region side S + 2 in `src`; `halves` output
+// channel halves (2; 1 for the last layer, whose only channel is column 0).
+// LAST: write f - (acc + b5) to out64 instead of GELU into `dst`.
+template <bool LAST>
+__device__ inline void fused_conv32(const _Float16* __restrict__ src, _Float16* __restrict__ dst,
+                                    const uint16_t* __restrict__ wfrag, const float* __restrict__ bias,
+                                    int S, int o, int oy, int ox, int H, int W, int b,
+                                    const double* __restrict__ f, double* __restrict__ out64) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int halves = LAST ? 1 : 2;
+  const int nblk = (S * S + 15) / 16;
+  const int SI = S + 2;
+  h8v w[2][9];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+      w[h][t] = (h < halves) ? reinterpret_cast<const h8v*>(wfrag)[(h * 9 + t) * 64 + lane]
+                             : h8v{0, 0, 0, 0, 0, 0, 0, 0};
+  for (int u = wave; u < nblk * halves; u += FUSED_THREADS / 64) {
+    const int h = LAST ? 0 : (u & 1), blk = LAST ? u : (u >> 1);
+    const int p = min(blk * 16 + (lane & 15), S * S - 1);
+    const int r = p / S, c = p % S;
+    const _Float16* a0 = src + (r * SI + c) * FPS + 8 * (lane >> 4);
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    f4 ac = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const h8v a = *reinterpret_cast<const h8v*>(a0 + ((t / 3) * SI + (t % 3)) * FPS);
+      ac = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, h ? w[1][t] : w[0][t], ac, 0, 0, 0);
+    }
+    const int co = 16 * h + (lane & 15);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = blk * 16 + 4 * (lane >> 4) + j;
+      if (q >= S * S) continue;
+      const int rr = q / S, cc = q % S;
+      const int yy = oy - o + rr, xx = ox - o + cc;
+      const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+      if (LAST) {
+        if ((lane & 15) == 0 && in) {
+          const long long g = ((long long)b * H + yy) * W + xx;
+          out64[g] = f[g] - (double)(ac[j] + bias[0]);
+        }
+      } else {
+        dst[q * FPS + co] = (_Float16)(in ? gelu(ac[j] + bias[co]) : 0.0f);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(FUSED_THREADS) void k_net_fused(const double* __restrict__ f,
+                                                             const double* __restrict__ v,
+                                                             const float* __restrict__ params,
+                                                             const uint16_t* __restrict__ wh,
+                                                             double* __restrict__ out64, int H,
+                                                             int W, int tiles_x, int tiles_y) {
+  __shared__ float s_in[FSI * FSI * 2];
+  __shared__ __attribute__((aligned(16))) _Float16 s_x[FS1 * FS1 * FPS];
+  __shared__ __attribute__((aligned(16))) _Float16 s_y[(FT + 6) * (FT + 6) * FPS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int t = blockIdx.x;
+  const int tx = t % tiles_x;
+  t /= tiles_x;
+  const int ty = t % tiles_y;
+  const int b = t / tiles_y;
+  const int ox = tx * FT, oy = ty * FT;
+  for (int i = tid; i < FSI * FSI; i += FUSED_THREADS) {
+    const int yy = oy - 5 + i / FSI, xx = ox - 5 + i % FSI;
+    float a = 0.f, c = 0.f;
+    if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+      const long long q = ((long long)b * H + yy) * W + xx;
+      a = (float)(f[q] * (1.0 / 50.0));
+      c = (float)v[q];
+    }
+    s_in[2 * i] = a;
+    s_in[2 * i + 1] = c;
+  }
+  __syncthreads();
+  // layer 1 (2 -> 32): contraction index k = 2 tap + channel (k < 18)
+  {
+    const float* b1 = params + OFF_L1 + 32 * CIN0 * 9;
+    const h8v w0 = reinterpret_cast<const h8v*>(wh + WH_L1)[lane];
+    const h8v w1 = reinterpret_cast<const h8v*>(wh + WH_L1)[64 + lane];
+    constexpr int S = FS1, nblk = (S * S + 15) / 16;
+    for (int u = wave; u < nblk * 2; u += FUSED_THREADS / 64) {
+      const int h = u & 1, blk = u >> 1;
+      const int p = min(blk * 16 + (lane & 15), S * S - 1);
+      const int r = p / S, c = p % S;
+      h8v a;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = 8 * (lane >> 4) + j;
+        const int tap = k >> 1, ch = k & 1;
+        a[j] = (_Float16)(k < 18 ? s_in[((r + tap / 3) * (S + 2) + c + tap % 3) * 2 + ch] : 0.0f);
+      }
+      typedef float f4 __attribute__((ext_vector_type(4)));
+      f4 ac = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, h ? w1 : w0, f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      const int co = 16 * h + (lane & 15);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int q = blk * 16 + 4 * (lane >> 4) + j;
+        if (q >= S * S) continue;
+        const int yy = oy - 4 + q / S, xx = ox - 4 + q % S;
+        const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+        s_x[q * FPS + co] = (_Float16)(in ? gelu(ac[j] + b1[co]) : 0.0f);
+      }
+    }
+  }
+  __syncthreads();
+  const uint16_t* wc = wh + WH_CONV;
+  fused_conv32<false>(s_x, s_y, wc, params + layer_offset(1) + 9216, FT + 6, 3, oy, ox, H, W, b,
+                      nullptr, nullptr);
+  __syncthreads();
+  fused_conv32<false>(s_y, s_x, wc + 2 * 9 * 64 * 8, params + layer_offset(2) + 9216, FT + 4, 2, oy,
+                      ox, H, W, b, nullptr, nullptr);
+  __syncthreads();
+  fused_conv32<false>(s_x, s_y, wc + 2 * 2 * 9 * 64 * 8, params + layer_offset(3) + 9216, FT + 2, 1,
+                      oy, ox, H, W, b, nullptr, nullptr);
+  __syncthreads();
+  fused_conv32<true>(s_y, nullptr, wh + WH_L5, params + OFF_L5 + 288, FT, 0, oy, ox, H, W, b, f,
+                     out64);
+}
+
+// FP16 fragments of the fused inference kernel from the FP32 parameters:
+// lane l holds output channel (16 half + l % 16) and contraction rows
+// 8 (l / 16) .. 8 (l / 16) + 7 of each layer's B operand.
+__global__ __launch_bounds__(256) void k_prep_half(const float* __restrict__ params,
+                                                   uint16_t* __restrict__ wh) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= WH_SIZE) return;
+  float v = 0.f;
+  if (i < WH_CONV) {  // layer 1: [half][lane][j], k = 2 tap + ch
+    const int j = i & 7, lane = (i >> 3) & 63, h = i >> 9;
+    const int co = 16 * h + (lane & 15), k = 8 * (lane >> 4) + j;
+    if (k < 18) v = params[OFF_L1 + (co * CIN0 + (k & 1)) * 9 + (k >> 1)];
+  } else if (i < WH_L5) {  // layers 2-4: [layer][half][tap][lane][j], k = input channel
+    const int r = i - WH_CONV;
+    const int j = r & 7, lane = (r >> 3) & 63, t = (r >> 9) % 9, h = (r / (9 * 512)) & 1,
+              l = r / (2 * 9 * 512);
+    const int co = 16 * h + (lane & 15), ci = 8 * (lane >> 4) + j;
+    v = params[layer_offset(l + 1) + (co * 32 + ci) * 9 + t];
+  } else {  // layer 5: [tap][lane][j], output channel 0 in column 0
+    const int r = i - WH_L5;
+    const int j = r & 7, lane = (r >> 3) & 63, t = r >> 9;
+    if ((lane & 15) == 0) v = params[OFF_L5 + (8 * (lane >> 4) + j) * 9 + t];
+  }
+  const _Float16 hv = (_Float16)v;
+  wh[i] = *reinterpret_cast<const uint16_t*>(&hv);
+}
+
 hipError_t forward(const Buffers& B, const double* f, const double* v, int batch, double* out64,
                    hipStream_t st) {
   const int H = B.H, W = B.W;
   const int npix = batch * H * W;
   const bool train = out64 == nullptr;
+  if (!train && B.infer_f16) {
+    const int tx = (W + FT - 1) / FT, ty = (H + FT - 1) / FT;
+    hipLaunchKernelGGL(k_net_fused, dim3(tx * ty * batch), dim3(FUSED_THREADS), 0, st, f, v,
+                       B.params, B.wh, out64, H, W, tx, ty);
+    return hipGetLastError();
+  }
   // Grid-stride kernels: at most eight workgroups per compute unit.
   const unsigned g1 = blocks(npix, L1_PX);
   if (train)
@@ -562,6 +742,7 @@ hipError_t prep_weights(const Buffers& B, hipStream_t st) {
   for (int l = 1; l < 4; ++l)
     hipLaunchKernelGGL(k_prep_weights, dim3(blocks(9216, 256)), dim3(256), 0, st,
                        B.params + layer_offset(l), B.wf[l - 1], B.wb[l - 1]);
+  hipLaunchKernelGGL(k_prep_half, dim3(blocks(WH_SIZE, 256)), dim3(256), 0, st, B.params, B.wh);
   return hipGetLastError();
 }
 

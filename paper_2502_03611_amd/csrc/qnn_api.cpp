@@ -8,6 +8,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "../../include/qn.h"
 #include "../../include/qnn.h"
 #include "qn_internal.h"
 #include "qnn_internal.h"
@@ -94,7 +95,7 @@ qn_status qnn_create(int32_t H, int32_t W, int32_t max_batch, qnn_net* out) {
     return o;
   };
   // record offsets in the (unbound) Buffers as byte offsets; rebased at bind
-  struct { size_t params, grads, m, v, wf[3], wb[3], x0, z[4], a[4], d[2], out, gout, part, lpart, loss; } o{};
+  struct { size_t params, grads, m, v, wf[3], wb[3], x0, z[4], a[4], d[2], out, gout, part, lpart, loss, wh; } o{};
   o.params = take(NPARAM * 4);
   o.grads = take(NPARAM * 4);
   o.m = take(NPARAM * 4);
@@ -110,6 +111,7 @@ qn_status qnn_create(int32_t H, int32_t W, int32_t max_batch, qnn_net* out) {
   o.part = take(tiles * qnn::QNN_WGRAD_STRIDE * 4);
   o.lpart = take(((pix + 255) / 256) * 8);
   o.loss = take(8);
+  o.wh = take(qnn::WH_SIZE * 2);
   n->need = off;
   // stash offsets as fake pointers (rebased by qnn_bind_workspace)
   Buffers& B = n->B;
@@ -135,6 +137,8 @@ qn_status qnn_create(int32_t H, int32_t W, int32_t max_batch, qnn_net* out) {
   B.part = (float*)o.part;
   B.lpart = (double*)o.lpart;
   B.loss = (double*)o.loss;
+  B.wh = (uint16_t*)o.wh;
+  B.infer_f16 = 0;
   *out = n;
   return QN_OK;
 }
@@ -194,6 +198,7 @@ qn_status qnn_bind_workspace(qnn_net n, void* d_ws, size_t bytes) {
   rebase(B.part);
   rebase(B.lpart);
   rebase(B.loss);
+  rebase(B.wh);
   n->ws = base;
   std::vector<float> p;
   he_init(p, 0);
@@ -266,6 +271,31 @@ qn_status qnn_adam_step(qnn_net n, double lr, double beta1, double beta2, double
   hipError_t e = qnn::adam(n->B, (float)lr, (float)beta1, (float)beta2, (float)eps, (float)bc1,
                            (float)bc2, n->stream);
   if (e != hipSuccess) return hip_bad(n, e, "adam");
+  return QN_OK;
+}
+
+qn_status qnn_guess(qnn_net n, qn_ctx solver, const double* d_f, double* d_u0, double* d_tmp,
+                    double* d_red, int32_t* d_used) {
+  qn_status s = check(n, true);
+  if (s != QN_OK) return s;
+  if (!solver || !d_f || !d_u0 || !d_tmp || !d_red)
+    return bad(QN_ERR_INVALID, "null solver, f, u0, tmp or red");
+  if (d_u0 == d_f || d_tmp == d_f || d_tmp == d_u0)
+    return bad(QN_ERR_INVALID, "f, u0 and tmp must be distinct arrays");
+  // every step on the network's stream, in order
+  s = qn_set_stream(solver, n->stream);
+  if (s == QN_OK) s = qn_fdm_solve(solver, d_f, 1.0, 0.0, d_tmp);       // v0 = A^-1 f
+  if (s == QN_OK) s = qnn_forward(n, d_f, d_tmp, 1, d_u0);              // f - g
+  if (s == QN_OK) s = qn_fdm_solve(solver, d_u0, 1.0, 0.0, d_u0);       // U_0 = A^-1 (f - g)
+  if (s == QN_OK) s = qn_residual(solver, d_u0, d_f, d_tmp, d_red);     // F^h(U_0)
+  if (s == QN_OK) s = qnn_guess_fallback(n, d_red, d_u0, d_used);       // U_0 = 0 if worse
+  return s;
+}
+
+qn_status qnn_set_inference(qnn_net n, int32_t f16) {
+  if (!n) return bad(QN_ERR_INVALID, "null network");
+  if (f16 != 0 && f16 != 1) return bad(QN_ERR_INVALID, "f16 must be 0 or 1");
+  n->B.infer_f16 = f16;
   return QN_OK;
 }
 

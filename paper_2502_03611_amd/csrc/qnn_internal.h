@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 namespace qnn {
 
 constexpr int CIN0 = 2;  // input channels: f / 50 and v0 = A_h^-1 f
@@ -35,7 +37,17 @@ struct Buffers {
   float* part;    // weight-gradient partials
   double* lpart;  // loss partials
   double* loss;   // 1 double
+  uint16_t* wh;   // FP16 matrix-core fragments of all five layers (fused inference)
+  int infer_f16;  // inference path: 0 the FP32 layer kernels, 1 the fused FP16 kernel
 };
+
+// FP16 fragment layout of the fused inference kernel (halves):
+// layer 1 [half 2][lane 64][8], layers 2-4 [layer 3][half 2][tap 9][lane 64][8],
+// layer 5 [tap 9][lane 64][8].
+constexpr int WH_L1 = 0;
+constexpr int WH_CONV = 2 * 64 * 8;
+constexpr int WH_L5 = WH_CONV + 3 * 2 * 9 * 64 * 8;
+constexpr int WH_SIZE = WH_L5 + 9 * 64 * 8;
 
 // Network forward.  out64 == nullptr: training (keeps x0, z and the FP32 output
 // for the backward pass); else inference, writing only out64 = f - g (FP64).

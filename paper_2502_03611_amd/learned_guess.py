@@ -42,11 +42,14 @@ def _qnn():
     L.qnn_adam_step.argtypes = [c_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double]
     L.qnn_guess_fallback.argtypes = [c_vp, c_vp, c_vp, c_vp]
+    L.qnn_set_inference.argtypes = [c_vp, ctypes.c_int32]
+    L.qnn_guess.argtypes = [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]
     L.qnn_destroy.argtypes = [c_vp]
     L.qnn_destroy.restype = None
     for n in ("qnn_create", "qnn_workspace_bytes", "qnn_bind_workspace", "qnn_set_stream",
               "qnn_param_count", "qnn_set_params", "qnn_get_params", "qnn_get_grads",
-              "qnn_forward", "qnn_loss_grad", "qnn_adam_step", "qnn_guess_fallback"):
+              "qnn_forward", "qnn_loss_grad", "qnn_adam_step", "qnn_guess_fallback",
+              "qnn_set_inference", "qnn_guess"):
         getattr(L, n).restype = ctypes.c_int32
     _QNN = L
     return L
@@ -135,6 +138,11 @@ class Net:
         check(_qnn().qnn_guess_fallback(self._ctx, _p(red), _p(u0),
                                         None if used is None else _p(used)))
 
+    def set_inference(self, precision):
+        """Inference path of forward(): "fp32" (layer kernels) or "fp16" (one
+        fused kernel on the FP16 matrix cores)."""
+        check(_qnn().qnn_set_inference(self._ctx, {"fp32": 0, "fp16": 1}[precision]))
+
     def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         self._stream()
         check(_qnn().qnn_adam_step(self._ctx, lr, beta1, beta2, eps))
@@ -201,6 +209,20 @@ def train(net, F, V, G, epochs=40, batch=16, lr=1e-3, seed=0, log=None):
     return hist
 
 
+def initial_guess_c(net, solver, f, tmp=None, red=None, used=None):
+    """initial_guess through the library's qnn_guess: the same steps in one
+    call (no host work between them).  Returns (U_0, used)."""
+    n = f.shape[-1]
+    f = f.view(1, n, n)
+    u0 = torch.empty_like(f)
+    tmp = torch.empty_like(f) if tmp is None else tmp
+    red = torch.empty(4, dtype=torch.float64, device=f.device) if red is None else red
+    used = torch.empty(1, dtype=torch.int32, device=f.device) if used is None else used
+    net._stream()
+    check(_qnn().qnn_guess(net._ctx, solver._ctx, _p(f), _p(u0), _p(tmp), _p(red), _p(used)))
+    return u0, used
+
+
 def initial_guess(net, solver, f):
     """U_0 = A_h^-1 (f - g), g = net(f / 50, A_h^-1 f), unless its residual is
     non-finite or not smaller than that of U_0 = 0 (which is ||f||); then
@@ -250,10 +272,14 @@ WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "q
 
 def compare(net, seeds, n=255, rtol=1e-10):
     """Per seed: iterations and time to rtol for FP64 / FP32 transforms, each
-    from U_0 = 0 and from the learned guess (network, both solves and the
-    fallback test timed with it)."""
+    from U_0 = 0 and from the learned guess (qnn_guess: both solves, the
+    network and the fallback test, timed with it; the network runs in its
+    current inference precision)."""
     solvers = {p: Solver((n, n), "cubic", beta_mode="midpoint", precision=p)
                for p in ("fp64", "fp32")}
+    tmp = torch.empty((1, n, n), dtype=torch.float64, device="cuda")
+    red = torch.empty(4, dtype=torch.float64, device="cuda")
+    used = torch.empty(1, dtype=torch.int32, device="cuda")
     rows = []
     for s in seeds:
         f = torch.from_numpy(synth.learned_guess_rhs(s, n)).cuda().view(1, n, n)
@@ -265,19 +291,80 @@ def compare(net, seeds, n=255, rtol=1e-10):
                 t0 = time.perf_counter()
                 if mode == "zero":
                     u = torch.zeros_like(f)
-                    used = False
                 else:
-                    u, used = initial_guess(net, sol, f)
+                    u, _ = initial_guess_c(net, sol, f, tmp, red, used)
                 st = sol.iterate(u, f, rtol=rtol, max_iter=200)
                 torch.cuda.synchronize()
                 dt = time.perf_counter() - t0
                 if ref is None:
                     ref = u.clone()
                 row[f"{p}_{mode}"] = {"iters": st["iters"], "t": dt, "status": st["status"],
-                                      "used_net": bool(used if mode == "zero" else used.item()),
+                                      "used_net": False if mode == "zero" else bool(used.item()),
                                       "rel_diff": float((u - ref).norm() / ref.norm())}
         rows.append(row)
     return rows
+
+
+def compare_batched(net, seeds, n=255, rtol=1e-10, chunk=50):
+    """All held-out seeds as one batch (qnb_iterate, one class of len(seeds)
+    instances): FP64 and FP32 transforms from U_0 = 0, and FP32 transforms from
+    the learned guesses: V = A_h^-1 F for every instance (qnb_fdm_solve), the
+    network over chunks of the batch, U_0 = A_h^-1 (F - G).  The batched path
+    keeps every guess (no per-instance fallback); instances whose guess starts
+    above relres 1 are counted.  Times include the solves and the network;
+    results are compared with the FP64 run from U_0 = 0."""
+    from .batched import BatchedSolver
+    S = len(seeds)
+    F = None
+    out, ref = {}, None
+    for prec, mode in (("fp64", "zero"), ("fp32", "zero"), ("fp32", "net")):
+        b = BatchedSolver([n] * S, [1] * S, precision=prec, beta_mode="midpoint")
+        if F is None:
+            F = b.pool()
+            F3 = F.view(S, n, n)
+            for i, s in enumerate(seeds):
+                F3[i].copy_(torch.from_numpy(synth.learned_guess_rhs(s, n)))
+        b.autotune()
+        U = b.pool()
+        b.iterate(U, F, rtol=rtol, max_iter=200, graph_iters=4)  # warm-up, graph capture
+        if mode == "net":
+            G = b.pool()
+            V = b.fdm_solve(F)
+            for a in range(0, S, chunk):
+                net.forward(F3[a:a + chunk], V.view(S, n, n)[a:a + chunk],
+                            out=G.view(S, n, n)[a:a + chunk])
+        U.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode == "net":
+            b.fdm_solve(F, X=V)
+            V3 = V.view(S, n, n)
+            for a in range(0, S, chunk):
+                net.forward(F3[a:a + chunk], V3[a:a + chunk], out=G.view(S, n, n)[a:a + chunk])
+            b.fdm_solve(G, X=U)
+        torch.cuda.synchronize()
+        t_guess = time.perf_counter() - t0
+        status, res = b.iterate(U, F, rtol=rtol, max_iter=200, graph_iters=4)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        its = np.array([r["iters"] for r in res])
+        rec = {"time_ms": round(1e3 * dt, 3), "guess_ms": round(1e3 * t_guess, 3),
+               "mean_iters": round(float(its.mean()), 3), "max_iters": int(its.max()),
+               "all_converged": bool(status == 0),
+               "starts_above_relres_1": int(sum(r["relres0"] > 1.0 for r in res))}
+        U3 = U.view(S, n, n)
+        if ref is None:
+            ref = U3.clone()
+        rec["max_rel_diff_vs_fp64_zero"] = float(max(float((U3[i] - ref[i]).norm() / ref[i].norm())
+                                                     for i in range(S)))
+        out[f"{prec}_{mode}"] = rec
+        b.close()
+        del U
+        torch.cuda.empty_cache()
+    out["speedup_fp32_net_vs_fp64_zero"] = round(out["fp64_zero"]["time_ms"] / out["fp32_net"]["time_ms"], 3)
+    out["speedup_fp32_net_vs_fp32_zero"] = round(out["fp32_zero"]["time_ms"] / out["fp32_net"]["time_ms"], 3)
+    out["instances"] = S
+    return out
 
 
 def main(argv=None):

@@ -105,6 +105,20 @@ def opts(**kw):
     (dict(discretization=2), 0, 1, (9, 9, 9), 0.0, "invalid"),
     (dict(discretization=1, sem_order=2), 1, 1, (11, 11, 11), 0.0, "unsupported"),
     (dict(discretization=1, sem_order=2, precision=2), 0, 1, (11, 11, 11), 0.0, "unsupported"),
+    # the Gray-Scott system (nl 3): 2D, two components, Neumann data, FP64/FP32
+    (dict(boundary=1, step=0.1), 3, 2, (9, 9, 1), 0.0, "ok"),
+    (dict(boundary=1, gs_da=1e-3, gs_ds=2e-3, gs_rho=0.05, gs_mu=0.01), 3, 2, (9, 9, 1), 0.0, "ok"),
+    (dict(boundary=1, precision=1), 3, 2, (9, 9, 1), 0.0, "ok"),
+    (dict(boundary=1), 3, 1, (9, 9, 1), 0.0, "invalid"),         # one component
+    (dict(boundary=1), 3, 2, (9, 9, 9), 0.0, "unsupported"),     # 3D
+    (dict(), 3, 2, (9, 9, 1), 0.0, "unsupported"),                # Dirichlet data
+    (dict(boundary=1, precision=2), 3, 2, (9, 9, 1), 0.0, "unsupported"),
+    (dict(boundary=1, gs_da=-1.0), 3, 2, (9, 9, 1), 0.0, "invalid"),
+    (dict(boundary=1, gs_rho=float("nan")), 3, 2, (9, 9, 1), 0.0, "invalid"),
+    (dict(gs_da=1.0), 0, 1, (9, 9, 9), 0.0, "invalid"),          # parameters for another problem
+    (dict(step=-0.1), 0, 1, (9, 9, 9), 0.0, "invalid"),
+    (dict(step=float("inf")), 0, 1, (9, 9, 9), 0.0, "invalid"),
+    (dict(step=0.5), 0, 1, (9, 9, 9), 0.0, "ok"),
 ])
 def test_setup_boundary_length_and_pointwise_terms(kw, nl, ncomp, n, beta, want):
     dim = 2 if n[2] == 1 else 3
@@ -230,8 +244,7 @@ def test_qnb_setup_rejects_invalid(n, nc, prec, bmode, beta):
     assert qn.last_error()
 
 
-class _QNBOptions(ctypes.Structure):
-    _fields_ = [("boundary", ctypes.c_int32), ("length", ctypes.c_double), ("lin", ctypes.c_double)]
+from paper_2502_03611_amd.batched import QNBOptions as _QNBOptions  # noqa: E402
 
 
 def _qnb_setup_ex(n, nc, opt, prec=1, bmode=1, beta=0.0):
@@ -268,10 +281,23 @@ def _qnb_setup_ex(n, nc, opt, prec=1, bmode=1, beta=0.0):
     ([9], [1], (0, 1.0, -25.0), 1, 1, 0.0),                    # lin below -lam_min = -19.6
     ([9], [1], (0, 1.0, -12.0), 1, 3, 0.0),                    # min + max: 2 lin below it
     ([9], [1], None, 1, 5, 0.0),                               # unknown rule
+    ([9], [2], (1, 1.0, 0.0, 2), 1, 1, 0.0),                   # unknown system
+    ([9], [2], (1, 1.0, 0.0, 1, -0.1), 1, 1, 0.0),             # negative step
+    ([9], [2], (1, 1.0, 0.0, 1, 0.1, -1.0), 1, 1, 0.0),        # negative D_A
+    ([9], [2], (1, 1.0, 0.0, 0, 0.0, 1e-3), 1, 1, 0.0),        # parameters for the cubic system
 ])
 def test_qnb_setup_ex_rejects_invalid(n, nc, opt, prec, bmode, beta):
     assert _qnb_setup_ex(n, nc, opt, prec, bmode, beta) == qn.QN_ERR_INVALID
     assert qn.last_error()
+
+
+@pytest.mark.parametrize("n,nc,opt,prec", [
+    ([9], [2], (0, 1.0, 0.0, 1, 0.1), 1),                      # Gray-Scott with Dirichlet data
+    ([9], [2], (1, 1.0, 0.0, 1, 0.1), 2),                      # with bf16x3
+    ([9, 9], [2, 1], (1, 1.0, 0.0, 1, 0.1), 1),                # with a scalar instance
+])
+def test_qnb_setup_ex_grayscott_unsupported(n, nc, opt, prec):
+    assert _qnb_setup_ex(n, nc, opt, prec, 1, 0.0) == qn.QN_ERR_UNSUPPORTED
 
 
 @pytest.mark.parametrize("n,nc,opt,prec,bmode,beta", [
@@ -284,6 +310,8 @@ def test_qnb_setup_ex_rejects_invalid(n, nc, opt, prec, bmode, beta):
     ([9, 12], [1, 2], None, 1, 4, 0.0),                        # min (lam_min > 1 here)
     ([9], [1], (0, 1.0, -12.0), 1, 1, 0.0),                    # midpoint: lin > -lam_min
     ([9, 12], [1, 1], (1, 2.0, 1.0), 1, 4, 0.0),               # Neumann min rule, lin > 0
+    ([9, 12, 9], [2, 2, 2], (1, 1.0, 0.0, 1, 0.1), 1, 1, 0.0), # Gray-Scott, midpoint
+    ([9], [2], (1, 1.0, 0.0, 1, 0.1, 1e-3, 2e-3, 0.05, 0.01), 0, 4, 0.0),  # own parameters, min
 ])
 def test_qnb_setup_ex_accepts(n, nc, opt, prec, bmode, beta):
     assert _qnb_setup_ex(n, nc, opt, prec, bmode, beta) == qn.QN_OK

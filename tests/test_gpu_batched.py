@@ -180,3 +180,27 @@ def test_batched_neumann_matches_single_instance_and_oracle(prec, mode, beta):
         # both stopped at relres <= 1e-10 and the Jacobian is >= lin = 1:
         # |U_b - U_o| <= 2 rtol |F| / 1
         assert np.linalg.norm(ub - ref["u"]) <= 2e-10 * np.linalg.norm(srcs[i])
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-6)])
+def test_batched_fdm_solve_every_instance(prec, tol):
+    """qnb_fdm_solve: X_i = (scale A_h + shift I)^-1 R_i for every instance of
+    a mixed pool (scalar and 2-component, uneven sizes), against the oracle's
+    tensor-product solve; X may alias R."""
+    from oracle import tensor as otensor
+    b = BatchedSolver(SIZES, NCOMP, precision=prec, beta_mode="midpoint")
+    R = b.pool()
+    rng = np.random.default_rng(77)
+    rs = []
+    for i, (n, c) in enumerate(zip(SIZES, NCOMP)):
+        r = rng.standard_normal((c, n, n))
+        rs.append(r)
+        b.fill(R, i, r)
+    X = b.fdm_solve(R, 1.5, 0.25)
+    b.fdm_solve(R, 1.5, 0.25, X=R)
+    assert torch.equal(X, R)
+    for i, r in enumerate(rs):
+        x = b.view(X, i).cpu().numpy()
+        for c in range(r.shape[0]):
+            ref = otensor.fdm_solve(r[c], 0.25, 1.5)
+            assert rel_l2(x[c], ref) <= tol, (i, c)

@@ -141,11 +141,12 @@ def test_fdm_solve_reduced_precision(prec, tol, shape):
                                                ((40, 50, 70), 1.0, 2.0)])
 def test_split_bf16_solve_matches_the_split_oracle(prec, parts, shape, scale, shift):
     """The split-bf16 solve against the oracle's own split-bf16 solve (the same
-    part products in the same product order, summed exactly, FP32 storage between
-    products): they differ
-    only by the matrix cores' FP32 accumulation order, about sqrt(K) 2^-24 per
-    product, so 2e-6 relative.  A lost or doubled part product moves the
-    result by 2^-9 or more."""
+    part products in the same product order, summed exactly, FP32 storage
+    between products): they differ only by the matrix cores' FP32
+    accumulation, at most K 2^-24 relative per product for K-term sums (K <= 96
+    here, six chained products), measured 0.8e-6 to 4e-6; the bound 1e-5 is
+    about 200 times below what a lost or doubled part product (2^-9 relative)
+    does to the result, and 4 times below the split error itself."""
     from oracle import splitbf16 as osb
     print(f"split oracle {prec} {shape}", flush=True)
     r = synth.random_field((1,) + shape, 11)
@@ -155,7 +156,7 @@ def test_split_bf16_solve_matches_the_split_oracle(prec, parts, shape, scale, sh
     err = rel(x[0], ref)
     print(f"  {prec} {shape}: rel diff vs split oracle {err:.3e}, vs FP64 oracle "
           f"{rel(x[0], otensor.fdm_solve(r[0], shift, scale)):.3e}", flush=True)
-    assert err <= 2e-6
+    assert err <= 1e-5
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
