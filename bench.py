@@ -794,6 +794,78 @@ def bench_batched(count):
             "precision": "fp32 transforms, fp64 residual/update"}
 
 
+def bench_gray_scott(sizes=(200, 400, 800, 1600), batch_radii=(0.18, 0.19, 0.2, 0.21, 0.22, 0.23,
+                                                                 0.24, 0.25)):
+    """The steady Gray-Scott system of Section 6.2 (eq. 2dgrayeq; the paper's
+    parameters, Neumann data on [0, 1]^2, step size 0.1, midpoint shift, FP64
+    transforms) at the sizes of the paper's table: per size one damped solve
+    to relres 1e-10 from a centred spot (radius 0.2), which reaches a
+    non-trivial steady state; then the same spot of eight radii at the
+    smallest size as one batch against one after another."""
+    from paper_2502_03611_amd.batched import BatchedSolver
+
+    out = {"params": {"da": 2.5e-4, "ds": 5e-4, "rho": 0.04, "mu": 0.065}, "step": 0.1,
+           "start": "spot radius 0.2 (A = 0.25, S = 0.5 inside)", "sizes": []}
+    for n in sizes:
+        log(f"gray-scott {n}^2")
+        s = Solver((n, n), "grayscott", beta_mode="midpoint", boundary="neumann", length=1.0,
+                   step=0.1)
+        s.autotune()
+        u0 = torch.from_numpy(synth.grayscott_spot(n)).cuda()
+        F = torch.from_numpy(synth.grayscott_source(n)).cuda()
+        U = u0.clone()
+        s.iterate(U, F, rtol=0.0, max_iter=2)  # warm-up
+        U.copy_(u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = s.iterate(U, F, rtol=1e-10, max_iter=20000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["sizes"].append({"n": n, "status": st["status"], "iters": st["iters"],
+                             "time_s": round(dt, 4), "ms_per_iter": round(1e3 * dt / max(st["iters"], 1), 4),
+                             "relres": st["relres"], "max_A": float(U[0].max()),
+                             "mean_A": float(U[0].mean())})
+        s.close()
+        del U, u0, F
+        torch.cuda.empty_cache()
+    n = sizes[0]
+    log(f"gray-scott batch of {len(batch_radii)} at {n}^2")
+    starts = [synth.grayscott_spot(n, radius=r) for r in batch_radii]
+    Fh = synth.grayscott_source(n)
+    s = Solver((n, n), "grayscott", beta_mode="midpoint", boundary="neumann", length=1.0, step=0.1)
+    s.autotune()
+    F1 = torch.from_numpy(Fh).cuda()
+    seq_t, seq_it = 0.0, []
+    for u0 in starts:
+        U = torch.from_numpy(u0).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = s.iterate(U, F1, rtol=1e-10, max_iter=20000)
+        torch.cuda.synchronize()
+        seq_t += time.perf_counter() - t0
+        seq_it.append(st["iters"])
+    b = BatchedSolver([n] * len(starts), [2] * len(starts), precision="fp64", beta_mode="midpoint",
+                      boundary="neumann", length=1.0, system="grayscott", step=0.1)
+    b.autotune()
+    U, F = b.pool(), b.pool()
+    for i, u0 in enumerate(starts):
+        b.fill(F, i, Fh)
+    for rep in range(2):  # the first replay builds the graph
+        for i, u0 in enumerate(starts):
+            b.fill(U, i, u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status, res = b.iterate(U, F, rtol=1e-10, max_iter=20000, graph_iters=16)
+        torch.cuda.synchronize()
+        bt = time.perf_counter() - t0
+    out["batched"] = {"n": n, "instances": len(starts), "radii": list(batch_radii),
+                      "sequential_s": round(seq_t, 4), "sequential_iters": seq_it,
+                      "batched_s": round(bt, 4), "batched_iters": [r["iters"] for r in res],
+                      "iters_equal_sequential": int(sum(r["iters"] == q for r, q in zip(res, seq_it))),
+                      "status": status, "speedup": round(seq_t / bt, 3)}
+    return out
+
+
 def bench_learned(nseeds=500):
     """Learned initial guess on 2D 255^2 -Lap u + u^3 = f with the committed
     trained weights on the held-out seeds: iterations and time to 1e-10 from
@@ -875,6 +947,8 @@ def main():
                     help="also solve the 100 perturbed 200^2 Neumann starts (eq. ex2d1) as one "
                          "batch against one after another")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-gray-scott", action="store_true",
+                    help="skip the damped Gray-Scott solves (200^2 .. 1600^2 and a batch of 8)")
     ap.add_argument("--batched-count", type=int, default=512)
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (reference kernel "
@@ -1034,6 +1108,9 @@ def main():
         torch.cuda.empty_cache()
     if args.batched_neumann:
         out["batched_neumann_200"] = batched_tables(100, sizes=(200,), all_rules=False)[0]
+        torch.cuda.empty_cache()
+    if not args.no_gray_scott:
+        out["gray_scott"] = bench_gray_scott()
         torch.cuda.empty_cache()
     if not args.no_learned:
         out["learned_guess"] = bench_learned()

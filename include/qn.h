@@ -4,19 +4,26 @@
  * Method: Hao, Lee & Zhang, "An Efficient Quasi-Newton Method with Tensor
  * Product Implementation for Solving Quasi-Linear Elliptic Equations and
  * Systems" (arXiv 2502.03611).  The library runs the quasi-Newton iteration
- *     vec(U_{k+1}) = vec(U_k) - [c_k A_h + beta_k I]^-1 F^h(U_k)
- * (Section 4, eq. identity-method) on a finite-difference grid with
- * homogeneous Dirichlet data (Section 3.2), applying the inverse by the
- * tensor-product (fast diagonalisation) formula of Section 4.1
- * (eq. fin_inverse): mode-n products with the 1D eigenvector matrix along
- * every axis, a pointwise divide by c(lam_i + lam_j (+ lam_k)) + beta, and
- * the inverse mode-n products.
+ *     vec(U_{k+1}) = vec(U_k) - tau [c_k A_h + beta_k I]^-1 F^h(U_k)
+ * (Section 4, eq. identity-method; tau = 1 unless a step size is set, as for
+ * the Gray-Scott system of Section 6.2) on 2D and 3D grids: finite differences
+ * with homogeneous Dirichlet or Neumann data (Section 3.2) or Q^k spectral
+ * elements (Section 3.1), applying the inverse by the tensor-product (fast
+ * diagonalisation) formula of Section 4.1 (eq. fin_inverse): mode-n products
+ * with the 1D eigenvector matrix along every axis, a pointwise divide by
+ * c (lam_i + lam_j (+ lam_k)) + beta, and the inverse mode-n products.  It
+ * also solves the nonlinear eigenproblem of Section 4.4 (qn_eigen_*).  Which
+ * combinations of problem, data, discretisation and precision are built is
+ * stated at qn_setup and in the option comments below.
  *
  * Data layout (all device arrays): FP64, contiguous, C-order
  * (ncomp, nz, ny, nx) in 3D and (ncomp, ny, nx) in 2D, x fastest; this is the
- * paper's vec order (first index fastest).  n[a] counts INTERIOR nodes on
- * (0,1) along axis a, h_a = 1/(n[a]+1); boundary values are zero and are not
- * stored.  The source F is the PDE right-hand side sampled at interior nodes.
+ * paper's vec order (first index fastest).  n[a] counts the unknowns along
+ * axis a: with Dirichlet data the INTERIOR nodes of the side L,
+ * h_a = L/(n[a]+1), boundary values zero and not stored; with Neumann data
+ * all nodes, h_a = L/(n[a]-1) (see qn_boundary); spectral elements see
+ * qn_discretization.  The source F is the PDE right-hand side sampled at the
+ * unknowns.
  *
  * Problems (the paper's model -Lap u + lambda u + f(x,u) = 0, Section 2, with
  * lambda = 0):
@@ -25,6 +32,8 @@
  *                     -Lap v + v^3 - u = f2 (Section 4.3)     (ncomp = 2)
  *   QN_NL_QUASILIN    -div((1+u^2) grad u) = f, conservative flux form with
  *                     arithmetic-mean face coefficients       (ncomp = 1)
+ *   QN_NL_GRAYSCOTT   the steady Gray-Scott system of Section 6.2 (ncomp = 2,
+ *                     2D, Neumann data; see qn_options)
  *
  * Shift rules (beta_mode):
  *   QN_BETA_FIXED     beta_k = beta (the value given to qn_setup), c_k = 1.

@@ -25,11 +25,14 @@
 // owns a TM x TN output tile and walks K in chunks of 32 (one matrix-core
 // step), double-buffered in LDS with one barrier per chunk.
 // v_mfma_f32_16x16x32_bf16 takes, per lane, 8 consecutive k values of one row
-// of A (row = lane % 16, k = 8 * (lane / 16) ..) and of one column of B, so
-// both operands are staged with k contiguous, [m][k] and [n][k], rows padded
-// to 40 elements (80 bytes) so that 16 lanes reading 16 rows hit distinct
-// 16-byte bank groups.  Each XCD (workgroups are dealt round-robin) walks a
-// contiguous range of tiles, so operand panels are reused in its L2.
+// of A (row = lane % 16, k = 8 * (lane / 16) ..) and of one column of B;
+// the S parts and the x-product data are staged k-contiguous, [row][k], and
+// the y/z-product data keeps its [k][n] layout and is read k-wise with the
+// transposing LDS load; the [row][k] tiles are chunk-major (cmaj) and the
+// [k][n] tile XOR-swizzled (tswz), so that fragment reads and staging stores
+// are free of bank conflicts.  Each XCD
+// (workgroups are dealt round-robin) walks a contiguous range of tiles, so
+// operand panels are reused in its L2.
 
 #include "qn_internal.h"
 #include "qn_mfma.h"
@@ -43,7 +46,53 @@ typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
 constexpr int BTK = 32;  // k per chunk = one matrix-core step
-constexpr int BKP = 40;  // padded LDS row length (bf16 elements)
+constexpr int RBK = BTK * 2;  // bytes of the 32 k values of one row of a part
+
+// LDS tiles of rows with 32 k values ([row][k]: the S parts, and the
+// x-product data) are stored chunk-major: the 16-byte chunk c (k = 8c .. 8c+7)
+// of row r sits at (c * ROWS + r) * 16.  A matrix-core fragment read (16
+// lanes take chunk c of 16 consecutive rows) and a staging store (16 lanes
+// write chunk c of 16 consecutive rows) then each cover one aligned 256-byte
+// block, the only 16-byte-per-lane pattern the LDS serves without bank
+// conflicts (measured: 3.9 conflict cycles per read when the 16 chunks are
+// spread over several 256-byte blocks, even on distinct banks).  Staging
+// threads are mapped row-fastest to match: thread v takes row
+// 16 (v / 64) + v % 16, chunk (v / 16) % 4.
+template <int ROWS>
+__device__ __forceinline__ int cmaj(int row, int chunk) {
+  return (chunk * ROWS + row) * 16;
+}
+__device__ __forceinline__ int stage_row(int v) { return ((v >> 6) << 4) | (v & 15); }
+__device__ __forceinline__ int stage_chunk(int v) { return (v >> 4) & 3; }
+
+// The y/z products' data tile stays in its global layout, [k][n] with n
+// contiguous (TN bf16 per k-row), and the MFMA B fragments (8 consecutive k of
+// one column n per lane) are read with the transposing LDS load: in each group
+// of 16 lanes, lane 4a + e receives element e of the 8-byte words of lanes
+// a, a + 4, a + 8, a + 12.  Lane i of group g therefore addresses row
+// 8 g + 4 h + i / 4, columns n0 + 4 (i % 4) .. + 3 (h = 0, 1: k 0-3 and 4-7 of
+// the group).  Its 32-byte segments are XOR-permuted per row so that the
+// four rows of a group, and the rows of the group read in the same cycle,
+// fall on distinct banks.
+template <int TN>
+__device__ __forceinline__ int tswz(int k, int col_bytes) {
+  constexpr int RB = TN * 2;  // bytes per k-row
+  int f;
+  if constexpr (RB >= 256)
+    f = (k & 3) | (((k >> 3) & 1) << 2);
+  else if constexpr (RB == 128)
+    f = ((k >> 1) & 1) | (((k >> 3) & 1) << 1);
+  else
+    f = (k >> 3) & 1;
+  return k * RB + ((((col_bytes >> 5) ^ f) << 5) | (col_bytes & 31));
+}
+
+typedef short s4v_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ bf4_t lds_tr4(const char* base, int off) {
+  const s4v_t v = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+      (__attribute__((address_space(3))) s4v_t*)(base + off));
+  return __builtin_bit_cast(bf4_t, v);
+}
 
 template <int NP>
 __device__ inline void split(float x, __bf16 (&p)[NP]) {
@@ -79,10 +128,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const f
                                                          int batch, long long bstride, EpiArgs ep) {
   constexpr int WM = TM / 2, WN = TN / 2, BM = WM / 16, BN = WN / 16;
   constexpr int NAV = TM * (BTK / 8);        // 16-byte vectors per S part
-  constexpr int NBV = (BTK / 4) * (TN / 4);  // (4 rows x 4 cols) tensor blocks
+  constexpr int NBV = BTK * (TN / 4);        // float4 runs (4 consecutive n) of the tensor chunk
   constexpr int PA = (NAV + 255) / 256, PB = (NBV + 255) / 256;
-  __shared__ __attribute__((aligned(16))) __bf16 As[NP][2][TM][BKP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[NP][2][TN][BKP];
+  __shared__ __attribute__((aligned(16))) char As[NP][2][TM * RBK];
+  __shared__ __attribute__((aligned(16))) char Bs[NP][2][BTK * TN * 2];
 
   const int MT = M / TM, NT = ncols / TN;
   const int t = xcd_tile(blockIdx.x, batch * MT * NT);
@@ -101,13 +150,13 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const f
     for (int j = 0; j < BN; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
 
   bf8_t ra[NP][PA];
-  f4_t rb[PB][4];
+  f4_t rb[PB];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int p = 0; p < PA; ++p) {
       const int v = tid + 256 * p;
       if (v < NAV) {
-        const int m = v / (BTK / 8), kv = (v % (BTK / 8)) * 8;
+        const int m = stage_row(v), kv = 8 * stage_chunk(v);
         // S[m][k] with S symmetric: row m, 8 consecutive k.
         const long long off = (long long)(m0 + m) * M + k0 + kv;
 #pragma unroll
@@ -118,10 +167,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const f
     for (int p = 0; p < PB; ++p) {
       const int v = tid + 256 * p;
       if (v < NBV) {
-        const int g = v / (TN / 4), nq = (v % (TN / 4)) * 4;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          rb[p][r] = *reinterpret_cast<const f4_t*>(Bb + (long long)(k0 + 4 * g + r) * ncols + n0 + nq);
+        const int k = v / (TN / 4), nq = (v % (TN / 4)) * 4;
+        rb[p] = *reinterpret_cast<const f4_t*>(Bb + (long long)(k0 + k) * ncols + n0 + nq);
       }
     }
   };
@@ -130,29 +177,27 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const f
     for (int p = 0; p < PA; ++p) {
       const int v = tid + 256 * p;
       if (v < NAV) {
-        const int m = v / (BTK / 8), kv = (v % (BTK / 8)) * 8;
 #pragma unroll
-        for (int q = 0; q < NP; ++q) *reinterpret_cast<bf8_t*>(&As[q][buf][m][kv]) = ra[q][p];
+        for (int q = 0; q < NP; ++q)
+          *reinterpret_cast<bf8_t*>(&As[q][buf][cmaj<TM>(stage_row(v), stage_chunk(v))]) = ra[q][p];
       }
     }
 #pragma unroll
     for (int p = 0; p < PB; ++p) {
       const int v = tid + 256 * p;
       if (v < NBV) {
-        const int g = v / (TN / 4), nq = (v % (TN / 4)) * 4;
+        const int k = v / (TN / 4), nq = (v % (TN / 4)) * 4;
+        bf4_t w[NP];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          bf4_t w[NP];
+          __bf16 x[NP];
+          split<NP>(rb[p][e], x);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            __bf16 x[NP];
-            split<NP>(rb[p][r][e], x);
-#pragma unroll
-            for (int q = 0; q < NP; ++q) w[q][r] = x[q];
-          }
-#pragma unroll
-          for (int q = 0; q < NP; ++q) *reinterpret_cast<bf4_t*>(&Bs[q][buf][nq + e][4 * g]) = w[q];
+          for (int q = 0; q < NP; ++q) w[q][e] = x[q];
         }
+#pragma unroll
+        for (int q = 0; q < NP; ++q)
+          *reinterpret_cast<bf4_t*>(&Bs[q][buf][tswz<TN>(k, 2 * nq)]) = w[q];
       }
     }
   };
@@ -161,22 +206,27 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const f
   gload(0);
   lstore(0);
   __syncthreads();
+  // transposed-read addresses of this lane (group g, position i)
+  const int g = lane >> 4, li = lane & 15;
   for (int kc = 0; kc < nk; ++kc) {
     const int buf = kc & 1;
     if (kc + 1 < nk) gload((kc + 1) * BTK);
-    const int ko = 8 * (lane >> 4);
     bf8_t a[BM][NP];
 #pragma unroll
     for (int i = 0; i < BM; ++i)
 #pragma unroll
       for (int q = 0; q < NP; ++q)
-        a[i][q] = *reinterpret_cast<const bf8_t*>(&As[q][buf][wm + 16 * i + (lane & 15)][ko]);
+        a[i][q] = *reinterpret_cast<const bf8_t*>(&As[q][buf][cmaj<TM>(wm + 16 * i + (lane & 15), lane >> 4)]);
 #pragma unroll
     for (int j = 0; j < BN; ++j) {
       bf8_t bj[NP];
+      const int ncol = wn + 16 * j + 4 * (li & 3);
 #pragma unroll
-      for (int q = 0; q < NP; ++q)
-        bj[q] = *reinterpret_cast<const bf8_t*>(&Bs[q][buf][wn + 16 * j + (lane & 15)][ko]);
+      for (int q = 0; q < NP; ++q) {
+        const bf4_t lo4 = lds_tr4(&Bs[q][buf][0], tswz<TN>(8 * g + (li >> 2), 2 * ncol));
+        const bf4_t hi4 = lds_tr4(&Bs[q][buf][0], tswz<TN>(8 * g + 4 + (li >> 2), 2 * ncol));
+        bj[q] = bf8_t{lo4[0], lo4[1], lo4[2], lo4[3], hi4[0], hi4[1], hi4[2], hi4[3]};
+      }
 #pragma unroll
       for (int i = 0; i < BM; ++i) acc[i][j] = mfma_split<NP>(a[i], bj, acc[i][j]);
     }
@@ -231,8 +281,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const float* __restric
   constexpr int NAV = TM * (BTK / 8);  // (row, 8 consecutive k) groups of the tensor chunk
   constexpr int NBV = TN * (BTK / 8);  // 16-byte vectors per S part
   constexpr int PA = (NAV + 255) / 256, PB = (NBV + 255) / 256;
-  __shared__ __attribute__((aligned(16))) __bf16 As[NP][2][TM][BKP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[NP][2][TN][BKP];
+  __shared__ __attribute__((aligned(16))) char As[NP][2][TM * RBK];
+  __shared__ __attribute__((aligned(16))) char Bs[NP][2][TN * RBK];
 
   const int MT = rows / TM, NT = K / TN;
   const int t = xcd_tile(blockIdx.x, MT * NT);
@@ -255,7 +305,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const float* __restric
     for (int p = 0; p < PA; ++p) {
       const int v = tid + 256 * p;
       if (v < NAV) {
-        const int r = v / (BTK / 8), kv = (v % (BTK / 8)) * 8;
+        const int r = stage_row(v), kv = 8 * stage_chunk(v);
         const float* src = A + (long long)(r0 + r) * K + k0 + kv;
         ra[p][0] = *reinterpret_cast<const f4_t*>(src);
         ra[p][1] = *reinterpret_cast<const f4_t*>(src + 4);
@@ -265,7 +315,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const float* __restric
     for (int p = 0; p < PB; ++p) {
       const int v = tid + 256 * p;
       if (v < NBV) {
-        const int n = v / (BTK / 8), kv = (v % (BTK / 8)) * 8;
+        const int n = stage_row(v), kv = 8 * stage_chunk(v);
         // S[k][n] = S[n][k]: row n, 8 consecutive k.
         const long long off = (long long)(n0 + n) * K + k0 + kv;
 #pragma unroll
@@ -278,7 +328,6 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const float* __restric
     for (int p = 0; p < PA; ++p) {
       const int v = tid + 256 * p;
       if (v < NAV) {
-        const int r = v / (BTK / 8), kv = (v % (BTK / 8)) * 8;
         bf8_t w[NP];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -288,16 +337,17 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const float* __restric
           for (int q = 0; q < NP; ++q) w[q][e] = x[q];
         }
 #pragma unroll
-        for (int q = 0; q < NP; ++q) *reinterpret_cast<bf8_t*>(&As[q][buf][r][kv]) = w[q];
+        for (int q = 0; q < NP; ++q)
+          *reinterpret_cast<bf8_t*>(&As[q][buf][cmaj<TM>(stage_row(v), stage_chunk(v))]) = w[q];
       }
     }
 #pragma unroll
     for (int p = 0; p < PB; ++p) {
       const int v = tid + 256 * p;
       if (v < NBV) {
-        const int n = v / (BTK / 8), kv = (v % (BTK / 8)) * 8;
 #pragma unroll
-        for (int q = 0; q < NP; ++q) *reinterpret_cast<bf8_t*>(&Bs[q][buf][n][kv]) = rb[q][p];
+        for (int q = 0; q < NP; ++q)
+          *reinterpret_cast<bf8_t*>(&Bs[q][buf][cmaj<TN>(stage_row(v), stage_chunk(v))]) = rb[q][p];
       }
     }
   };
@@ -309,19 +359,18 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const float* __restric
   for (int kc = 0; kc < nk; ++kc) {
     const int buf = kc & 1;
     if (kc + 1 < nk) gload((kc + 1) * BTK);
-    const int ko = 8 * (lane >> 4);
     bf8_t a[BM][NP];
 #pragma unroll
     for (int i = 0; i < BM; ++i)
 #pragma unroll
       for (int q = 0; q < NP; ++q)
-        a[i][q] = *reinterpret_cast<const bf8_t*>(&As[q][buf][wm + 16 * i + (lane & 15)][ko]);
+        a[i][q] = *reinterpret_cast<const bf8_t*>(&As[q][buf][cmaj<TM>(wm + 16 * i + (lane & 15), lane >> 4)]);
 #pragma unroll
     for (int j = 0; j < BN; ++j) {
       bf8_t bj[NP];
 #pragma unroll
       for (int q = 0; q < NP; ++q)
-        bj[q] = *reinterpret_cast<const bf8_t*>(&Bs[q][buf][wn + 16 * j + (lane & 15)][ko]);
+        bj[q] = *reinterpret_cast<const bf8_t*>(&Bs[q][buf][cmaj<TN>(wn + 16 * j + (lane & 15), lane >> 4)]);
 #pragma unroll
       for (int i = 0; i < BM; ++i) acc[i][j] = mfma_split<NP>(a[i], bj, acc[i][j]);
     }
@@ -348,6 +397,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const float* __restric
       }
     }
     double old[4][BN];
+    const double st = ep.step != 0 ? ep.step : 1.0;  // U -= step dU
     if (EPI == EPI_SUB_DENSE) {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -367,7 +417,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const float* __restric
           C[base[q] + n] = v;
         } else if (row_ok[q] && n < ep.nx) {
           if (EPI == EPI_SUB_DENSE)
-            ep.dense[base[q] + n] = old[q][j] - (double)v;
+            ep.dense[base[q] + n] = old[q][j] - st * (double)v;
           else
             ep.dense[base[q] + n] = (double)v;
         }

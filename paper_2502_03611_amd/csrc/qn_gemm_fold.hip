@@ -36,6 +36,22 @@
 
 namespace qn {
 
+// Row-major LDS tiles whose rows are the contraction (k) and whose readers
+// take one k column of 16 consecutive rows per quarter wave: the 16-byte
+// chunks of a row are permuted by an XOR with the row's index within its
+// bank group, so both those column reads and the row-wise 16-byte stores hit
+// 16 distinct chunks of the LDS banks.  The row's 16-row block (bits 4-5)
+// enters the XOR as well: fragment rows 16 apart then sit at a lane-dependent
+// distance, which keeps the compiler from pairing their reads into one
+// two-address LDS read whose halves fall on the same banks (measured: 8
+// conflict cycles per such read).  RB: bytes per row (a power of two).
+template <int RB>
+__device__ __forceinline__ int swz(int row, int col_bytes) {
+  constexpr int NCH = RB / 16, SR = RB >= 256 ? 1 : 256 / RB;
+  const int t = ((row / SR) % NCH) ^ ((row >> 4) & 3);
+  return row * RB + ((((col_bytes >> 4) ^ t) << 4) | (col_bytes & 15));
+}
+
 // ------------------------------------------------------------------ form L
 
 // Forward, contraction over the slab rows (the folded axis):
@@ -506,8 +522,8 @@ __global__ __launch_bounds__(256, 2) void k_fold_right_fwd(const T* __restrict__
   typedef T V __attribute__((ext_vector_type(VE)));
   constexpr int WM = TM / 2, WN = TN / 2, BM = WM / 16, BN = WN / 16;
   constexpr int NA = (TK * TM / VE + 255) / 256, NB = (TK * TN / VE + 255) / 256;
-  constexpr int AK = TK + VE;
-  __shared__ __attribute__((aligned(16))) T As[2][TM][AK];
+  constexpr int RB = TK * (int)sizeof(T);  // bytes per A row (swizzled chunks)
+  __shared__ __attribute__((aligned(16))) char As[2][TM * RB];
   __shared__ __attribute__((aligned(16))) T Bs[2][TK][TN];
 
   const int bk = ax.bk, P2 = 2 * bk, na = ax.n, h = ax.h;
@@ -573,7 +589,7 @@ __global__ __launch_bounds__(256, 2) void k_fold_right_fwd(const T* __restrict__
             x = rlo[i][e];
           val[e] = x;
         }
-        *reinterpret_cast<V*>(&As[buf][row][kv]) = val;
+        *reinterpret_cast<V*>(&As[buf][swz<RB>(row, kv * (int)sizeof(T))]) = val;
       }
     }
 #pragma unroll
@@ -598,7 +614,9 @@ __global__ __launch_bounds__(256, 2) void k_fold_right_fwd(const T* __restrict__
     for (int ks = 0; ks < TK; ks += 4) {
       T a[BM], bb[BN];
 #pragma unroll
-      for (int i = 0; i < BM; ++i) a[i] = As[buf][wm + 16 * i + (lane & 15)][ks + (lane >> 4)];
+      for (int i = 0; i < BM; ++i)
+        a[i] = *reinterpret_cast<const T*>(
+            &As[buf][swz<RB>(wm + 16 * i + (lane & 15), (ks + (lane >> 4)) * (int)sizeof(T))]);
 #pragma unroll
       for (int j = 0; j < BN; ++j) bb[j] = Bs[buf][ks + (lane >> 4)][wn + 16 * j + (lane & 15)];
 #pragma unroll
@@ -636,9 +654,9 @@ __global__ __launch_bounds__(256, 2) void k_fold_right_inv(const T* __restrict__
   typedef T V __attribute__((ext_vector_type(VE)));
   constexpr int WM = TM / 2, WN = TNF / 2, BM = WM / 16, BN = WN / 16;
   constexpr int NA = (TM * TK / VE + 255) / 256, NB = (TK * TNF / VE + 255) / 256;
-  constexpr int AK = TK + VE;
-  __shared__ __attribute__((aligned(16))) T Ap[2][TM][AK];
-  __shared__ __attribute__((aligned(16))) T Aq[2][TM][AK];
+  constexpr int RB = TK * (int)sizeof(T);  // bytes per A row (swizzled chunks)
+  __shared__ __attribute__((aligned(16))) char Ap[2][TM * RB];
+  __shared__ __attribute__((aligned(16))) char Aq[2][TM * RB];
   __shared__ __attribute__((aligned(16))) T Bp[2][TK][TNF];
   __shared__ __attribute__((aligned(16))) T Bq[2][TK][TNF];
 
@@ -686,8 +704,8 @@ __global__ __launch_bounds__(256, 2) void k_fold_right_inv(const T* __restrict__
       const int v = tid + 256 * i;
       if (v < TM * TK / VE) {
         const int row = v / (TK / VE), kv = (v % (TK / VE)) * VE;
-        *reinterpret_cast<V*>(&Ap[buf][row][kv]) = rap[i];
-        *reinterpret_cast<V*>(&Aq[buf][row][kv]) = raq[i];
+        *reinterpret_cast<V*>(&Ap[buf][swz<RB>(row, kv * (int)sizeof(T))]) = rap[i];
+        *reinterpret_cast<V*>(&Aq[buf][swz<RB>(row, kv * (int)sizeof(T))]) = raq[i];
       }
     }
 #pragma unroll
@@ -714,8 +732,9 @@ __global__ __launch_bounds__(256, 2) void k_fold_right_inv(const T* __restrict__
       T ap[BM], aq[BM], bp[BN], bq[BN];
 #pragma unroll
       for (int i = 0; i < BM; ++i) {
-        ap[i] = Ap[buf][wm + 16 * i + (lane & 15)][ks + (lane >> 4)];
-        aq[i] = Aq[buf][wm + 16 * i + (lane & 15)][ks + (lane >> 4)];
+        const int off = swz<RB>(wm + 16 * i + (lane & 15), (ks + (lane >> 4)) * (int)sizeof(T));
+        ap[i] = *reinterpret_cast<const T*>(&Ap[buf][off]);
+        aq[i] = *reinterpret_cast<const T*>(&Aq[buf][off]);
       }
 #pragma unroll
       for (int j = 0; j < BN; ++j) {

@@ -506,63 +506,82 @@ constexpr int FT = 16;               // output tile side
 constexpr int FSI = FT + 10;         // input region side
 constexpr int FS1 = FT + 8;          // layer-1 output side
 constexpr int FPS = 40;              // LDS pixel stride in halves (16-byte aligned, conflict-free)
-constexpr int FUSED_THREADS = 512;
+constexpr int FUSED_THREADS = 1024;
 
 typedef _Float16 h8v __attribute__((ext_vector_type(8)));
 
 // One layer with 32 input channels: out region side S (origin o pixels
-// before the tile), input region side S + 2 in `src`; `halves` output
-// channel halves (2; 1 for the last layer, whose only channel is column 0).
-// LAST: write f - (acc + b5) to out64 instead of GELU into `dst`.
-template <bool LAST>
+// before the tile), input region side S + 2 in `src`.  A wave takes pairs of
+// 16-pixel blocks and computes both output-channel halves of each from one
+// load of its A fragment per tap: four independent accumulation chains.
+// LAST (32 -> 1): only output column 0 of the first half is real; writes
+// f - (acc + b5) to out64 instead of GELU into `dst`.
+template <int NT, int S, int O, bool LAST>
 __device__ inline void fused_conv32(const _Float16* __restrict__ src, _Float16* __restrict__ dst,
                                     const uint16_t* __restrict__ wfrag, const float* __restrict__ bias,
-                                    int S, int o, int oy, int ox, int H, int W, int b,
+                                    int oy, int ox, int H, int W, int b,
                                     const double* __restrict__ f, double* __restrict__ out64) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  constexpr int NH = LAST ? 1 : 2;  // output-channel halves
+  constexpr int nblk = (S * S + 15) / 16, SI = S + 2, o = O;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int halves = LAST ? 1 : 2;
-  const int nblk = (S * S + 15) / 16;
-  const int SI = S + 2;
-  h8v w[2][9];
+  h8v w[NH][9];
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < NH; ++h)
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
-      w[h][t] = (h < halves) ? reinterpret_cast<const h8v*>(wfrag)[(h * 9 + t) * 64 + lane]
-                             : h8v{0, 0, 0, 0, 0, 0, 0, 0};
-  for (int u = wave; u < nblk * halves; u += FUSED_THREADS / 64) {
-    const int h = LAST ? 0 : (u & 1), blk = LAST ? u : (u >> 1);
-    const int p = min(blk * 16 + (lane & 15), S * S - 1);
-    const int r = p / S, c = p % S;
-    const _Float16* a0 = src + (r * SI + c) * FPS + 8 * (lane >> 4);
-    typedef float f4 __attribute__((ext_vector_type(4)));
-    f4 ac = {0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 9; ++t) w[h][t] = reinterpret_cast<const h8v*>(wfrag)[(h * 9 + t) * 64 + lane];
+  for (int blk0 = 2 * wave; blk0 < nblk; blk0 += 2 * (NT / 64)) {
+    const _Float16* a0[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int p = min((blk0 + q) * 16 + (lane & 15), S * S - 1);
+      a0[q] = src + ((p / S) * SI + p % S) * FPS + 8 * (lane >> 4);
+    }
+    f4 ac[2][NH];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int h = 0; h < NH; ++h) ac[q][h] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      const h8v a = *reinterpret_cast<const h8v*>(a0 + ((t / 3) * SI + (t % 3)) * FPS);
-      ac = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, h ? w[1][t] : w[0][t], ac, 0, 0, 0);
-    }
-    const int co = 16 * h + (lane & 15);
+      const int off = ((t / 3) * SI + (t % 3)) * FPS;
+      const h8v a_0 = *reinterpret_cast<const h8v*>(a0[0] + off);
+      const h8v a_1 = *reinterpret_cast<const h8v*>(a0[1] + off);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int q = blk * 16 + 4 * (lane >> 4) + j;
-      if (q >= S * S) continue;
-      const int rr = q / S, cc = q % S;
-      const int yy = oy - o + rr, xx = ox - o + cc;
-      const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
-      if (LAST) {
-        if ((lane & 15) == 0 && in) {
-          const long long g = ((long long)b * H + yy) * W + xx;
-          out64[g] = f[g] - (double)(ac[j] + bias[0]);
+      for (int h = 0; h < NH; ++h) {
+        ac[0][h] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_0, w[h][t], ac[0][h], 0, 0, 0);
+        ac[1][h] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_1, w[h][t], ac[1][h], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int blk = blk0 + q;
+      if (blk >= nblk) break;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int px = blk * 16 + 4 * (lane >> 4) + j;
+        if (px >= S * S) continue;
+        const int yy = oy - o + px / S, xx = ox - o + px % S;
+        const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+        if (LAST) {
+          if ((lane & 15) == 0 && in) {
+            const long long g = ((long long)b * H + yy) * W + xx;
+            out64[g] = f[g] - (double)(ac[q][0][j] + bias[0]);
+          }
+        } else {
+#pragma unroll
+          for (int h = 0; h < NH; ++h) {
+            const int co = 16 * h + (lane & 15);
+            dst[px * FPS + co] = (_Float16)(in ? gelu(ac[q][h][j] + bias[co]) : 0.0f);
+          }
         }
-      } else {
-        dst[q * FPS + co] = (_Float16)(in ? gelu(ac[j] + bias[co]) : 0.0f);
       }
     }
   }
 }
 
-__global__ __launch_bounds__(FUSED_THREADS) void k_net_fused(const double* __restrict__ f,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_net_fused(const double* __restrict__ f,
                                                              const double* __restrict__ v,
                                                              const float* __restrict__ params,
                                                              const uint16_t* __restrict__ wh,
@@ -578,7 +597,7 @@ __global__ __launch_bounds__(FUSED_THREADS) void k_net_fused(const double* __res
   const int ty = t % tiles_y;
   const int b = t / tiles_y;
   const int ox = tx * FT, oy = ty * FT;
-  for (int i = tid; i < FSI * FSI; i += FUSED_THREADS) {
+  for (int i = tid; i < FSI * FSI; i += NT) {
     const int yy = oy - 5 + i / FSI, xx = ox - 5 + i % FSI;
     float a = 0.f, c = 0.f;
     if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
@@ -592,12 +611,12 @@ __global__ __launch_bounds__(FUSED_THREADS) void k_net_fused(const double* __res
   __syncthreads();
   // layer 1 (2 -> 32): contraction index k = 2 tap + channel (k < 18)
   {
+    typedef float f4 __attribute__((ext_vector_type(4)));
     const float* b1 = params + OFF_L1 + 32 * CIN0 * 9;
     const h8v w0 = reinterpret_cast<const h8v*>(wh + WH_L1)[lane];
     const h8v w1 = reinterpret_cast<const h8v*>(wh + WH_L1)[64 + lane];
     constexpr int S = FS1, nblk = (S * S + 15) / 16;
-    for (int u = wave; u < nblk * 2; u += FUSED_THREADS / 64) {
-      const int h = u & 1, blk = u >> 1;
+    for (int blk = wave; blk < nblk; blk += NT / 64) {
       const int p = min(blk * 16 + (lane & 15), S * S - 1);
       const int r = p / S, c = p % S;
       h8v a;
@@ -607,32 +626,35 @@ __global__ __launch_bounds__(FUSED_THREADS) void k_net_fused(const double* __res
         const int tap = k >> 1, ch = k & 1;
         a[j] = (_Float16)(k < 18 ? s_in[((r + tap / 3) * (S + 2) + c + tap % 3) * 2 + ch] : 0.0f);
       }
-      typedef float f4 __attribute__((ext_vector_type(4)));
-      f4 ac = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, h ? w1 : w0, f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-      const int co = 16 * h + (lane & 15);
+      const f4 z = {0.f, 0.f, 0.f, 0.f};
+      const f4 ac0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, w0, z, 0, 0, 0);
+      const f4 ac1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, w1, z, 0, 0, 0);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int q = blk * 16 + 4 * (lane >> 4) + j;
         if (q >= S * S) continue;
         const int yy = oy - 4 + q / S, xx = ox - 4 + q % S;
         const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
-        s_x[q * FPS + co] = (_Float16)(in ? gelu(ac[j] + b1[co]) : 0.0f);
+        const int co = lane & 15;
+        s_x[q * FPS + co] = (_Float16)(in ? gelu(ac0[j] + b1[co]) : 0.0f);
+        s_x[q * FPS + 16 + co] = (_Float16)(in ? gelu(ac1[j] + b1[16 + co]) : 0.0f);
       }
     }
   }
   __syncthreads();
   const uint16_t* wc = wh + WH_CONV;
-  fused_conv32<false>(s_x, s_y, wc, params + layer_offset(1) + 9216, FT + 6, 3, oy, ox, H, W, b,
-                      nullptr, nullptr);
+  fused_conv32<NT, FT + 6, 3, false>(s_x, s_y, wc, params + layer_offset(1) + 9216, oy, ox, H, W,
+                                     b, nullptr, nullptr);
   __syncthreads();
-  fused_conv32<false>(s_y, s_x, wc + 2 * 9 * 64 * 8, params + layer_offset(2) + 9216, FT + 4, 2, oy,
-                      ox, H, W, b, nullptr, nullptr);
+  fused_conv32<NT, FT + 4, 2, false>(s_y, s_x, wc + 2 * 9 * 64 * 8, params + layer_offset(2) + 9216,
+                                     oy, ox, H, W, b, nullptr, nullptr);
   __syncthreads();
-  fused_conv32<false>(s_x, s_y, wc + 2 * 2 * 9 * 64 * 8, params + layer_offset(3) + 9216, FT + 2, 1,
-                      oy, ox, H, W, b, nullptr, nullptr);
+  fused_conv32<NT, FT + 2, 1, false>(s_x, s_y, wc + 2 * 2 * 9 * 64 * 8,
+                                     params + layer_offset(3) + 9216, oy, ox, H, W, b, nullptr,
+                                     nullptr);
   __syncthreads();
-  fused_conv32<true>(s_y, nullptr, wh + WH_L5, params + OFF_L5 + 288, FT, 0, oy, ox, H, W, b, f,
-                     out64);
+  fused_conv32<NT, FT, 0, true>(s_y, nullptr, wh + WH_L5, params + OFF_L5 + 288, oy, ox, H, W, b, f,
+                                out64);
 }
 
 // FP16 fragments of the fused inference kernel from the FP32 parameters:
@@ -669,8 +691,8 @@ hipError_t forward(const Buffers& B, const double* f, const double* v, int batch
   const bool train = out64 == nullptr;
   if (!train && B.infer_f16) {
     const int tx = (W + FT - 1) / FT, ty = (H + FT - 1) / FT;
-    hipLaunchKernelGGL(k_net_fused, dim3(tx * ty * batch), dim3(FUSED_THREADS), 0, st, f, v,
-                       B.params, B.wh, out64, H, W, tx, ty);
+    hipLaunchKernelGGL(k_net_fused<FUSED_THREADS>, dim3(tx * ty * batch), dim3(FUSED_THREADS), 0, st,
+                       f, v, B.params, B.wh, out64, H, W, tx, ty);
     return hipGetLastError();
   }
   // Grid-stride kernels: at most eight workgroups per compute unit.

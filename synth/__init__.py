@@ -32,5 +32,7 @@ from .fields import (  # noqa: F401
     polynomial_perturbation,
     interior_coords,
     schrodinger_3d,
+    grayscott_spot,
+    grayscott_source,
     BATCH_SIZES,
 )

@@ -205,3 +205,20 @@ def schrodinger_3d(n, half=8.0):
     v = w[:, None, None] + w[None, :, None] + w[None, None, :]
     u = g[:, None, None] * g[None, :, None] * g[None, None, :]
     return v, u
+
+
+def grayscott_spot(n, radius=0.2, amp=0.25, center=(0.5, 0.5)):
+    """Start for the steady Gray-Scott system on the n x n nodes of [0, 1]^2
+    (both ends included): (A, S) = (amp, 0.5) inside a disc of the given
+    radius, the trivial state (0, 1) outside.  Shape (2, n, n)."""
+    x = np.linspace(0.0, 1.0, n)
+    X, Y = np.meshgrid(x, x)
+    m = ((X - center[0]) ** 2 + (Y - center[1]) ** 2 < radius ** 2).astype(np.float64)
+    return np.stack([amp * m, 1.0 - 0.5 * m])
+
+
+def grayscott_source(n, rho=0.04):
+    """The constant source F = (0, rho) of the steady Gray-Scott system."""
+    f = np.zeros((2, n, n))
+    f[1] = rho
+    return f

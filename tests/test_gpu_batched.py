@@ -204,3 +204,23 @@ def test_batched_fdm_solve_every_instance(prec, tol):
         for c in range(r.shape[0]):
             ref = otensor.fdm_solve(r[c], 0.25, 1.5)
             assert rel_l2(x[c], ref) <= tol, (i, c)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_batched_step_size_in_every_precision(prec):
+    """step = 1/2 halves every instance's first correction, in the update
+    epilogue of each transform precision the batch offers."""
+    print(f"batched step {prec}", flush=True)
+    sizes, ncomp = [31, 64, 17, 100], [1, 2, 2, 1]
+    srcs = sources(sizes, ncomp)
+    out = []
+    for step in (1.0, 0.5):
+        b = BatchedSolver(sizes, ncomp, precision=prec, beta_mode="midpoint", step=step)
+        F, U = b.pool(), b.pool()
+        for i, f in enumerate(srcs):
+            b.fill(F, i, f)
+        b.iterate(U, F, rtol=0.0, max_iter=1, graph_iters=1)
+        out.append([b.view(U, i).cpu().numpy() for i in range(len(sizes))])
+    for full, half in zip(*out):
+        assert np.linalg.norm(full) > 0
+        assert np.linalg.norm(half - 0.5 * full) <= 1e-14 * np.linalg.norm(full)

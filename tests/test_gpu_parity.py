@@ -435,3 +435,21 @@ def test_mfma_probe_is_plausible():
         v = probe_mfma(prec)
         print(f"mfma probe {prec}: {v:.1f} TFLOP/s", flush=True)
         assert 0.3 * peak <= v <= 1.1 * peak, (prec, v)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("kind,shape", [("cubic", (45, 70)), ("system", (17, 19, 23))])
+def test_step_size_scales_the_correction_in_every_precision(prec, kind, shape):
+    """U_1 = U_0 - step dU: with step 1/2 the first update is half the undamped
+    one (dU is the same bits, so the two differ by the rounding of the
+    subtraction only), in the update epilogue of every transform precision."""
+    print(f"step {kind} {shape} {prec}", flush=True)
+    ncomp = 2 if kind == "system" else 1
+    u0 = synth.random_field((ncomp,) + shape, 7)
+    f = dev(synth.random_field((ncomp,) + shape, 8, scale=10.0))
+    ua, ub = dev(u0), dev(u0)
+    Solver(shape, kind, beta=1.0, precision=prec).iterate(ua, f, rtol=0.0, max_iter=1)
+    Solver(shape, kind, beta=1.0, precision=prec, step=0.5).iterate(ub, f, rtol=0.0, max_iter=1)
+    d_full, d_half = host(ua) - u0, host(ub) - u0
+    assert np.linalg.norm(d_full) > 0
+    assert np.linalg.norm(d_half - 0.5 * d_full) <= 1e-14 * (np.linalg.norm(d_full) + np.linalg.norm(u0))
