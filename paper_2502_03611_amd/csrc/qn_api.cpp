@@ -275,10 +275,12 @@ ResidualArgs residual_args(qn_ctx c, const double* U, const double* F, double* R
   a.F = F;
   const int* ext = R_caller ? c->n : c->p;
   a.R = R_caller ? (void*)R_caller : (void*)(c->ws + c->off_W1);
-  a.out_prec = (R_caller || c->prec == QN_PREC_FP64) ? 0 : 1;
+  // split-bf16 two-part transforms keep their tensors as bf16 part planes
+  a.out_prec = (R_caller || c->prec == QN_PREC_FP64) ? 0 : c->prec == QN_PREC_BF16X3 ? 2 : 1;
   a.r_cstride = (long long)ext[2] * ext[1] * ext[0];
   a.r_zstride = ext[1] * ext[0];
   a.r_ystride = ext[0];
+  a.r_plane = (long long)c->ncomp * a.r_cstride;
   a.ox = ext[0];
   a.oy = ext[1];
   a.oz = ext[2];
@@ -956,7 +958,7 @@ qn_status qn_fdm_solve(qn_ctx c, const double* d_R, double scale, double shift, 
   hipError_t e = launch_set_coef(coef, scale, shift, c->stream);
   if (e == hipSuccess)
     e = timed(c, K_PAD_COPY, [&] {
-      return launch_pad_copy(d_R, c->ws + c->off_W1, c->prec == QN_PREC_FP64 ? 0 : 1, c->ncomp,
+      return launch_pad_copy(d_R, c->ws + c->off_W1, transform_storage(c->prec), c->ncomp,
                              c->n[0], c->n[1], c->n[2], c->p[0], c->p[1], c->p[2], c->stream);
     });
   if (e == hipSuccess) e = solve_ws(c, coef, d_X, EPI_STORE_DENSE);

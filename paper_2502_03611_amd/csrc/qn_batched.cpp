@@ -155,7 +155,7 @@ hipError_t class_iteration(qnb_ctx c, Cls& k, double* U, const double* F, double
   a.U = U + k.off_field;
   a.F = F + k.off_field;
   a.R = c->ws + k.off_W1;
-  a.out_prec = c->prec == QN_PREC_FP64 ? 0 : 1;
+  a.out_prec = transform_storage(c->prec);
   a.r_cstride = (long long)k.K * k.p * k.p;
   a.r_zstride = k.p * k.p;
   a.r_ystride = k.p;
@@ -633,7 +633,7 @@ qn_status qnb_fdm_solve(qnb_ctx c, const double* d_R, double scale, double shift
     void* W1 = c->ws + k.off_W1;
     void* W2 = c->ws + k.off_W2;
     // the class block (ncomp, K, n, n) -> (ncomp, K, P, P), zero padding
-    e = launch_pad_copy(d_R + k.off_field, W1, c->prec == QN_PREC_FP64 ? 0 : 1, k.ncomp, k.n, k.n,
+    e = launch_pad_copy(d_R + k.off_field, W1, transform_storage(c->prec), k.ncomp, k.n, k.n,
                         k.K, k.p, k.p, k.K, c->stream);
     if (e != hipSuccess) break;
     EpiArgs ep = epi_for(c, k, d_X);

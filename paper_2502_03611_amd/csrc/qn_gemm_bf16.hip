@@ -10,8 +10,11 @@
 //   NP = 2 ("bf16x3"): x1 y0 + x0 y1 + x0 y0          (dropped: 2^-16 relative)
 //   NP = 3 ("bf16x6"): x2 y0 + x0 y2 + x1 y1 + x1 y0 + x0 y1 + x0 y0
 //                                                      (dropped: 2^-24 relative)
-// The 1D eigenvector matrix S is split once at setup; the tensor operand is
-// split while it is staged into LDS.
+// The 1D eigenvector matrix S is split once at setup.  bf16x3 keeps every
+// tensor between products as its two part planes (written by the residual,
+// the pad copy and each product's epilogue), so both operands travel from
+// global memory straight into LDS; bf16x6 keeps FP32 tensors and splits the
+// tensor operand while staging it through registers.
 //
 // Two forms cover the three axes of a C-order (.., z, y, x) tensor:
 //   form L  C[b][m][n] = sum_k S[m][k] B[b][k][n]   (y and z products; B rows
@@ -23,14 +26,14 @@
 //
 // Work decomposition: a 256-thread workgroup (four wave64s in a 2 x 2 grid)
 // owns a TM x TN output tile and walks K in chunks of 32 (one matrix-core
-// step), double-buffered in LDS with one barrier per chunk.
+// step), double-buffered in LDS with one barrier per chunk (the next chunk's
+// direct-to-LDS loads, or global loads into registers, are issued before the
+// current chunk's matrix-core work).
 // v_mfma_f32_16x16x32_bf16 takes, per lane, 8 consecutive k values of one row
 // of A (row = lane % 16, k = 8 * (lane / 16) ..) and of one column of B;
 // the S parts and the x-product data are staged k-contiguous, [row][k], and
 // the y/z-product data keeps its [k][n] layout and is read k-wise with the
-// transposing LDS load; the [row][k] tiles are chunk-major (cmaj) and the
-// [k][n] tile XOR-swizzled (tswz), so that fragment reads and staging stores
-// are free of bank conflicts.  Each XCD
+// transposing LDS load; both layouts are XOR-swizzled (kswz, tswz).  Each XCD
 // (workgroups are dealt round-robin) walks a contiguous range of tiles, so
 // operand panels are reused in its L2.
 
@@ -49,21 +52,16 @@ constexpr int BTK = 32;  // k per chunk = one matrix-core step
 constexpr int RBK = BTK * 2;  // bytes of the 32 k values of one row of a part
 
 // LDS tiles of rows with 32 k values ([row][k]: the S parts, and the
-// x-product data) are stored chunk-major: the 16-byte chunk c (k = 8c .. 8c+7)
-// of row r sits at (c * ROWS + r) * 16.  A matrix-core fragment read (16
-// lanes take chunk c of 16 consecutive rows) and a staging store (16 lanes
-// write chunk c of 16 consecutive rows) then each cover one aligned 256-byte
-// block, the only 16-byte-per-lane pattern the LDS serves without bank
-// conflicts (measured: 3.9 conflict cycles per read when the 16 chunks are
-// spread over several 256-byte blocks, even on distinct banks).  Staging
-// threads are mapped row-fastest to match: thread v takes row
-// 16 (v / 64) + v % 16, chunk (v / 16) % 4.
-template <int ROWS>
-__device__ __forceinline__ int cmaj(int row, int chunk) {
-  return (chunk * ROWS + row) * 16;
+// x-product data; 64 bytes per row and part): the four 16-byte chunks of a
+// row are XOR-permuted by the row's index within its 256-byte bank line, so
+// the row-wise staging stores and the fragment reads (chunk c of 16
+// consecutive rows) spread over all 16 chunks of a bank line.  (A
+// chunk-major layout, whose fragment reads are free of bank conflicts, was
+// measured slower: its staging threads, mapped row-fastest, lose the
+// coalescing of the global loads.)
+__device__ __forceinline__ int kswz(int row, int col_bytes) {
+  return row * RBK + ((((col_bytes >> 4) ^ ((row >> 2) & 3)) << 4) | (col_bytes & 15));
 }
-__device__ __forceinline__ int stage_row(int v) { return ((v >> 6) << 4) | (v & 15); }
-__device__ __forceinline__ int stage_chunk(int v) { return (v >> 4) & 3; }
 
 // The y/z products' data tile stays in its global layout, [k][n] with n
 // contiguous (TN bf16 per k-row), and the MFMA B fragments (8 consecutive k of
@@ -75,16 +73,41 @@ __device__ __forceinline__ int stage_chunk(int v) { return (v >> 4) & 3; }
 // four rows of a group, and the rows of the group read in the same cycle,
 // fall on distinct banks.
 template <int TN>
-__device__ __forceinline__ int tswz(int k, int col_bytes) {
+__device__ __forceinline__ int tperm(int k) {
   constexpr int RB = TN * 2;  // bytes per k-row
-  int f;
   if constexpr (RB >= 256)
-    f = (k & 3) | (((k >> 3) & 1) << 2);
+    return (k & 3) | (((k >> 3) & 1) << 2);
   else if constexpr (RB == 128)
-    f = ((k >> 1) & 1) | (((k >> 3) & 1) << 1);
+    return ((k >> 1) & 1) | (((k >> 3) & 1) << 1);
   else
-    f = (k >> 3) & 1;
-  return k * RB + ((((col_bytes >> 5) ^ f) << 5) | (col_bytes & 31));
+    return (k >> 3) & 1;
+}
+template <int TN>
+__device__ __forceinline__ int tswz(int k, int col_bytes) {
+  return k * TN * 2 + ((((col_bytes >> 5) ^ tperm<TN>(k)) << 5) | (col_bytes & 31));
+}
+
+// bf16x3 keeps every intermediate tensor of the solve as its two bf16 parts,
+// hi = RNE(x) and lo = RNE(x - hi) of the FP32 value x, in two planes (hi at
+// the tensor's base, lo one tensor size further): the parts a kernel would
+// split from x, so the results are the same bits, while the products load
+// both operands straight into LDS (global_load_lds: a wave fills 1 KiB of LDS
+// per instruction, lane p the 16 bytes at p * 16, from a global address the
+// lane chooses, so the lanes gather the swizzled layout) with no register
+// staging and no split on the load path.
+typedef __attribute__((address_space(3))) void lds_void;
+__device__ __forceinline__ void put_pair(__bf16* hi, long long plane, long long idx, float v) {
+  const __bf16 h = (__bf16)v;
+  hi[idx] = h;
+  hi[plane + idx] = (__bf16)(v - (float)h);
+}
+// One KiB block of a [row][k] tile (16 rows of 32 k): lane p fetches row
+// row0 + p / 4, the logical chunk that the XOR permutation puts at slot p % 4.
+__device__ __forceinline__ void dload_rows(const __bf16* src, long long ld, int row0, int k0, int lane,
+                                           char* dst) {
+  const int row = lane >> 2, c = (lane & 3) ^ (((row0 + row) >> 2) & 3);
+  __builtin_amdgcn_global_load_lds(src + (long long)(row0 + row) * ld + k0 + 8 * c, (lds_void*)dst,
+                                   16, 0, 0);
 }
 
 typedef short s4v_t __attribute__((ext_vector_type(4)));
@@ -123,9 +146,14 @@ __device__ inline const __bf16* part(const GemmOperands& s, int i) {
 }  // namespace
 
 template <int NP, int TM, int TN, int EPI>
-__global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const float* __restrict__ B,
-                                                         float* __restrict__ C, int M, int ncols,
+__global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const void* __restrict__ Bv,
+                                                         void* __restrict__ Cv, int M, int ncols,
                                                          int batch, long long bstride, EpiArgs ep) {
+  // NP = 2: B and C are bf16 part planes; NP = 3: FP32 tensors
+  constexpr bool PS = NP == 2;
+  const float* B = (const float*)Bv;
+  float* C = (float*)Cv;
+  const long long plane = (long long)batch * bstride;
   constexpr int WM = TM / 2, WN = TN / 2, BM = WM / 16, BN = WN / 16;
   constexpr int NAV = TM * (BTK / 8);        // 16-byte vectors per S part
   constexpr int NBV = BTK * (TN / 4);        // float4 runs (4 consecutive n) of the tensor chunk
@@ -149,92 +177,146 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const f
 #pragma unroll
     for (int j = 0; j < BN; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
 
-  bf8_t ra[NP][PA];
-  f4_t rb[PB];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int p = 0; p < PA; ++p) {
-      const int v = tid + 256 * p;
-      if (v < NAV) {
-        const int m = stage_row(v), kv = 8 * stage_chunk(v);
-        // S[m][k] with S symmetric: row m, 8 consecutive k.
-        const long long off = (long long)(m0 + m) * M + k0 + kv;
-#pragma unroll
-        for (int q = 0; q < NP; ++q) ra[q][p] = *reinterpret_cast<const bf8_t*>(part(S, q) + off);
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < PB; ++p) {
-      const int v = tid + 256 * p;
-      if (v < NBV) {
-        const int k = v / (TN / 4), nq = (v % (TN / 4)) * 4;
-        rb[p] = *reinterpret_cast<const f4_t*>(Bb + (long long)(k0 + k) * ncols + n0 + nq);
-      }
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int p = 0; p < PA; ++p) {
-      const int v = tid + 256 * p;
-      if (v < NAV) {
-#pragma unroll
-        for (int q = 0; q < NP; ++q)
-          *reinterpret_cast<bf8_t*>(&As[q][buf][cmaj<TM>(stage_row(v), stage_chunk(v))]) = ra[q][p];
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < PB; ++p) {
-      const int v = tid + 256 * p;
-      if (v < NBV) {
-        const int k = v / (TN / 4), nq = (v % (TN / 4)) * 4;
-        bf4_t w[NP];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          __bf16 x[NP];
-          split<NP>(rb[p][e], x);
-#pragma unroll
-          for (int q = 0; q < NP; ++q) w[q][e] = x[q];
-        }
-#pragma unroll
-        for (int q = 0; q < NP; ++q)
-          *reinterpret_cast<bf4_t*>(&Bs[q][buf][tswz<TN>(k, 2 * nq)]) = w[q];
-      }
-    }
-  };
-
-  const int nk = M / BTK;
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  // transposed-read addresses of this lane (group g, position i)
   const int g = lane >> 4, li = lane & 15;
-  for (int kc = 0; kc < nk; ++kc) {
-    const int buf = kc & 1;
-    if (kc + 1 < nk) gload((kc + 1) * BTK);
-    bf8_t a[BM][NP];
+  // all matrix-core fragments of chunk buf: a[i][part], bj[j][part]
+  auto read_frags = [&](int buf, bf8_t (&a)[BM][NP], bf8_t (&bj)[BN][NP]) {
 #pragma unroll
     for (int i = 0; i < BM; ++i)
 #pragma unroll
       for (int q = 0; q < NP; ++q)
-        a[i][q] = *reinterpret_cast<const bf8_t*>(&As[q][buf][cmaj<TM>(wm + 16 * i + (lane & 15), lane >> 4)]);
+        a[i][q] = *reinterpret_cast<const bf8_t*>(&As[q][buf][kswz(wm + 16 * i + li, 16 * g)]);
 #pragma unroll
     for (int j = 0; j < BN; ++j) {
-      bf8_t bj[NP];
       const int ncol = wn + 16 * j + 4 * (li & 3);
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
         const bf4_t lo4 = lds_tr4(&Bs[q][buf][0], tswz<TN>(8 * g + (li >> 2), 2 * ncol));
         const bf4_t hi4 = lds_tr4(&Bs[q][buf][0], tswz<TN>(8 * g + 4 + (li >> 2), 2 * ncol));
-        bj[q] = bf8_t{lo4[0], lo4[1], lo4[2], lo4[3], hi4[0], hi4[1], hi4[2], hi4[3]};
+        bj[j][q] = bf8_t{lo4[0], lo4[1], lo4[2], lo4[3], hi4[0], hi4[1], hi4[2], hi4[3]};
+      }
+    }
+  };
+  auto mma = [&](const bf8_t (&a)[BM][NP], const bf8_t (&bj)[BN][NP]) {
+#pragma unroll
+    for (int j = 0; j < BN; ++j)
+#pragma unroll
+      for (int i = 0; i < BM; ++i) acc[i][j] = mfma_split<NP>(a[i], bj[j], acc[i][j]);
+  };
+  const int nk = M / BTK;
+  if constexpr (PS) {
+    const __bf16* Bh = (const __bf16*)Bv + (long long)b * bstride;
+    // chunk k0 into LDS buffer buf: the S parts' rows (TM / 16 KiB blocks per
+    // part) and the data's k-rows (TN / 16 blocks per part, 512 / TN rows each)
+    auto dload = [&](int k0, int buf) {
+#pragma unroll
+      for (int blk = wave; blk < TM / 16; blk += 4)
+#pragma unroll
+        for (int q = 0; q < NP; ++q) dload_rows(part(S, q), M, m0 + 16 * blk, k0, lane, &As[q][buf][blk * 1024]);
+      constexpr int RPB = 512 / TN, SPR = TN / 8;  // rows per block, 16-byte slots per row
+#pragma unroll
+      for (int blk = wave; blk < BTK / RPB; blk += 4) {
+        const int row = RPB * blk + lane / SPR, slot = lane % SPR;
+        const int seg = (slot >> 1) ^ tperm<TN>(row);
+        const long long off = (long long)(k0 + row) * ncols + n0 + 16 * seg + 8 * (slot & 1);
+#pragma unroll
+        for (int q = 0; q < NP; ++q)
+          __builtin_amdgcn_global_load_lds(Bh + q * plane + off, (lds_void*)&Bs[q][buf][blk * 1024], 16, 0, 0);
+      }
+    };
+    dload(0, 0);
+    for (int kc = 0; kc < nk; ++kc) {
+      const int buf = kc & 1;
+      // this chunk's loads have landed and every wave is done reading the
+      // buffer the next chunk overwrites
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      // fragments first: the compiler makes LDS reads wait for every
+      // direct-to-LDS load in flight, so the next chunk's loads are issued
+      // after them and overlap the matrix-core work
+      bf8_t a[BM][NP], bj[BN][NP];
+      read_frags(buf, a, bj);
+      if (kc + 1 < nk) dload((kc + 1) * BTK, buf ^ 1);
+      mma(a, bj);
+    }
+  } else {
+    const float* Bb = B + (long long)b * bstride;
+    bf8_t ra[NP][PA];
+    f4_t rb[PB];
+    auto gload = [&](int k0) {
+#pragma unroll
+      for (int p = 0; p < PA; ++p) {
+        const int v = tid + 256 * p;
+        if (v < NAV) {
+          const int m = v / (BTK / 8), kv = (v % (BTK / 8)) * 8;
+          // S[m][k] with S symmetric: row m, 8 consecutive k.
+          const long long off = (long long)(m0 + m) * M + k0 + kv;
+#pragma unroll
+          for (int q = 0; q < NP; ++q) ra[q][p] = *reinterpret_cast<const bf8_t*>(part(S, q) + off);
+        }
       }
 #pragma unroll
-      for (int i = 0; i < BM; ++i) acc[i][j] = mfma_split<NP>(a[i], bj, acc[i][j]);
-    }
-    if (kc + 1 < nk) lstore(buf ^ 1);
+      for (int p = 0; p < PB; ++p) {
+        const int v = tid + 256 * p;
+        if (v < NBV) {
+          const int k = v / (TN / 4), nq = (v % (TN / 4)) * 4;
+          rb[p] = *reinterpret_cast<const f4_t*>(Bb + (long long)(k0 + k) * ncols + n0 + nq);
+        }
+      }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int p = 0; p < PA; ++p) {
+        const int v = tid + 256 * p;
+        if (v < NAV) {
+          const int m = v / (BTK / 8), kv = (v % (BTK / 8)) * 8;
+#pragma unroll
+          for (int q = 0; q < NP; ++q)
+            *reinterpret_cast<bf8_t*>(&As[q][buf][kswz(m, 2 * kv)]) = ra[q][p];
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < PB; ++p) {
+        const int v = tid + 256 * p;
+        if (v < NBV) {
+          const int k = v / (TN / 4), nq = (v % (TN / 4)) * 4;
+          bf4_t w[NP];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            __bf16 x[NP];
+            split<NP>(rb[p][e], x);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) w[q][e] = x[q];
+          }
+#pragma unroll
+          for (int q = 0; q < NP; ++q)
+            *reinterpret_cast<bf4_t*>(&Bs[q][buf][tswz<TN>(k, 2 * nq)]) = w[q];
+        }
+      }
+    };
+
+    gload(0);
+    lstore(0);
     __syncthreads();
+    for (int kc = 0; kc < nk; ++kc) {
+      const int buf = kc & 1;
+      if (kc + 1 < nk) gload((kc + 1) * BTK);
+      {
+        bf8_t a[BM][NP], bj[BN][NP];
+        read_frags(buf, a, bj);
+        mma(a, bj);
+      }
+      if (kc + 1 < nk) lstore(buf ^ 1);
+      __syncthreads();
+    }
   }
 
-  float* Cb = C + (long long)b * bstride;
+  const long long cbase = (long long)b * bstride;
+  auto put = [&](long long idx, float v) {
+    if constexpr (PS)
+      put_pair((__bf16*)Cv, plane, cbase + idx, v);
+    else
+      C[cbase + idx] = v;
+  };
   if (EPI == EPI_DIVIDE) {
     // denominator scale (lam_m + lam_x + lam_y) + beta: the column part once
     // per column block, the row part once per row, one FP64 divide per entry
@@ -256,8 +338,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const f
 #pragma unroll
         for (int j = 0; j < BN; ++j) {
           const int n = n0 + wn + 16 * j + (lane & 15);
-          Cb[(long long)m * ncols + n] =
-              (float)((double)acc[i][j][q] / (scale * (lm + cn[j]) + beta));
+          put((long long)m * ncols + n, (float)((double)acc[i][j][q] / (scale * (lm + cn[j]) + beta)));
         }
       }
   } else {
@@ -268,15 +349,20 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const f
         const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
 #pragma unroll
         for (int j = 0; j < BN; ++j)
-          Cb[(long long)m * ncols + n0 + wn + 16 * j + (lane & 15)] = acc[i][j][q];
+          put((long long)m * ncols + n0 + wn + 16 * j + (lane & 15), acc[i][j][q]);
       }
   }
 }
 
 template <int NP, int TM, int TN, int EPI>
-__global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const float* __restrict__ A,
-                                                          GemmOperands S, float* __restrict__ C,
+__global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const void* __restrict__ Av,
+                                                          GemmOperands S, void* __restrict__ Cv,
                                                           int rows, int K, EpiArgs ep) {
+  // NP = 2: A and C (with EPI_STORE) are bf16 part planes; NP = 3: FP32 tensors
+  constexpr bool PS = NP == 2;
+  const float* A = (const float*)Av;
+  float* C = (float*)Cv;
+  const long long plane = (long long)rows * K;
   constexpr int WM = TM / 2, WN = TN / 2, BM = WM / 16, BN = WN / 16;
   constexpr int NAV = TM * (BTK / 8);  // (row, 8 consecutive k) groups of the tensor chunk
   constexpr int NBV = TN * (BTK / 8);  // 16-byte vectors per S part
@@ -298,84 +384,122 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const float* __restric
 #pragma unroll
     for (int j = 0; j < BN; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
 
-  f4_t ra[PA][2];
-  bf8_t rb[NP][PB];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int p = 0; p < PA; ++p) {
-      const int v = tid + 256 * p;
-      if (v < NAV) {
-        const int r = stage_row(v), kv = 8 * stage_chunk(v);
-        const float* src = A + (long long)(r0 + r) * K + k0 + kv;
-        ra[p][0] = *reinterpret_cast<const f4_t*>(src);
-        ra[p][1] = *reinterpret_cast<const f4_t*>(src + 4);
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < PB; ++p) {
-      const int v = tid + 256 * p;
-      if (v < NBV) {
-        const int n = stage_row(v), kv = 8 * stage_chunk(v);
-        // S[k][n] = S[n][k]: row n, 8 consecutive k.
-        const long long off = (long long)(n0 + n) * K + k0 + kv;
-#pragma unroll
-        for (int q = 0; q < NP; ++q) rb[q][p] = *reinterpret_cast<const bf8_t*>(part(S, q) + off);
-      }
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int p = 0; p < PA; ++p) {
-      const int v = tid + 256 * p;
-      if (v < NAV) {
-        bf8_t w[NP];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          __bf16 x[NP];
-          split<NP>(ra[p][e >> 2][e & 3], x);
-#pragma unroll
-          for (int q = 0; q < NP; ++q) w[q][e] = x[q];
-        }
-#pragma unroll
-        for (int q = 0; q < NP; ++q)
-          *reinterpret_cast<bf8_t*>(&As[q][buf][cmaj<TM>(stage_row(v), stage_chunk(v))]) = w[q];
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < PB; ++p) {
-      const int v = tid + 256 * p;
-      if (v < NBV) {
-#pragma unroll
-        for (int q = 0; q < NP; ++q)
-          *reinterpret_cast<bf8_t*>(&Bs[q][buf][cmaj<TN>(stage_row(v), stage_chunk(v))]) = rb[q][p];
-      }
-    }
-  };
-
-  const int nk = K / BTK;
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  for (int kc = 0; kc < nk; ++kc) {
-    const int buf = kc & 1;
-    if (kc + 1 < nk) gload((kc + 1) * BTK);
-    bf8_t a[BM][NP];
+  auto read_frags = [&](int buf, bf8_t (&a)[BM][NP], bf8_t (&bj)[BN][NP]) {
 #pragma unroll
     for (int i = 0; i < BM; ++i)
 #pragma unroll
       for (int q = 0; q < NP; ++q)
-        a[i][q] = *reinterpret_cast<const bf8_t*>(&As[q][buf][cmaj<TM>(wm + 16 * i + (lane & 15), lane >> 4)]);
+        a[i][q] = *reinterpret_cast<const bf8_t*>(&As[q][buf][kswz(wm + 16 * i + (lane & 15), 16 * (lane >> 4))]);
 #pragma unroll
-    for (int j = 0; j < BN; ++j) {
-      bf8_t bj[NP];
+    for (int j = 0; j < BN; ++j)
 #pragma unroll
       for (int q = 0; q < NP; ++q)
-        bj[q] = *reinterpret_cast<const bf8_t*>(&Bs[q][buf][cmaj<TN>(wn + 16 * j + (lane & 15), lane >> 4)]);
+        bj[j][q] = *reinterpret_cast<const bf8_t*>(&Bs[q][buf][kswz(wn + 16 * j + (lane & 15), 16 * (lane >> 4))]);
+  };
+  auto mma = [&](const bf8_t (&a)[BM][NP], const bf8_t (&bj)[BN][NP]) {
 #pragma unroll
-      for (int i = 0; i < BM; ++i) acc[i][j] = mfma_split<NP>(a[i], bj, acc[i][j]);
+    for (int j = 0; j < BN; ++j)
+#pragma unroll
+      for (int i = 0; i < BM; ++i) acc[i][j] = mfma_split<NP>(a[i], bj[j], acc[i][j]);
+  };
+  const int nk = K / BTK;
+  if constexpr (PS) {
+    const __bf16* Ah = (const __bf16*)Av;
+    // chunk k0 into LDS buffer buf: TM / 16 KiB blocks of data rows and TN / 16
+    // of S rows (S[k][n] = S[n][k]) per part
+    auto dload = [&](int k0, int buf) {
+#pragma unroll
+      for (int blk = wave; blk < TM / 16; blk += 4)
+#pragma unroll
+        for (int q = 0; q < NP; ++q) dload_rows(Ah + q * plane, K, r0 + 16 * blk, k0, lane, &As[q][buf][blk * 1024]);
+#pragma unroll
+      for (int blk = wave; blk < TN / 16; blk += 4)
+#pragma unroll
+        for (int q = 0; q < NP; ++q) dload_rows(part(S, q), K, n0 + 16 * blk, k0, lane, &Bs[q][buf][blk * 1024]);
+    };
+    dload(0, 0);
+    for (int kc = 0; kc < nk; ++kc) {
+      const int buf = kc & 1;
+      // this chunk's loads have landed and every wave is done reading the
+      // buffer the next chunk overwrites
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      bf8_t a[BM][NP], bj[BN][NP];
+      read_frags(buf, a, bj);
+      if (kc + 1 < nk) dload((kc + 1) * BTK, buf ^ 1);
+      mma(a, bj);
     }
-    if (kc + 1 < nk) lstore(buf ^ 1);
+  } else {
+    f4_t ra[PA][2];
+    bf8_t rb[NP][PB];
+    auto gload = [&](int k0) {
+#pragma unroll
+      for (int p = 0; p < PA; ++p) {
+        const int v = tid + 256 * p;
+        if (v < NAV) {
+          const int r = v / (BTK / 8), kv = (v % (BTK / 8)) * 8;
+          const float* src = A + (long long)(r0 + r) * K + k0 + kv;
+          ra[p][0] = *reinterpret_cast<const f4_t*>(src);
+          ra[p][1] = *reinterpret_cast<const f4_t*>(src + 4);
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < PB; ++p) {
+        const int v = tid + 256 * p;
+        if (v < NBV) {
+          const int n = v / (BTK / 8), kv = (v % (BTK / 8)) * 8;
+          // S[k][n] = S[n][k]: row n, 8 consecutive k.
+          const long long off = (long long)(n0 + n) * K + k0 + kv;
+#pragma unroll
+          for (int q = 0; q < NP; ++q) rb[q][p] = *reinterpret_cast<const bf8_t*>(part(S, q) + off);
+        }
+      }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int p = 0; p < PA; ++p) {
+        const int v = tid + 256 * p;
+        if (v < NAV) {
+          const int r = v / (BTK / 8), kv = (v % (BTK / 8)) * 8;
+          bf8_t w[NP];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            __bf16 x[NP];
+            split<NP>(ra[p][e >> 2][e & 3], x);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) w[q][e] = x[q];
+          }
+#pragma unroll
+          for (int q = 0; q < NP; ++q)
+            *reinterpret_cast<bf8_t*>(&As[q][buf][kswz(r, 2 * kv)]) = w[q];
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < PB; ++p) {
+        const int v = tid + 256 * p;
+        if (v < NBV) {
+          const int n = v / (BTK / 8), kv = (v % (BTK / 8)) * 8;
+#pragma unroll
+          for (int q = 0; q < NP; ++q)
+            *reinterpret_cast<bf8_t*>(&Bs[q][buf][kswz(n, 2 * kv)]) = rb[q][p];
+        }
+      }
+    };
+
+    gload(0);
+    lstore(0);
     __syncthreads();
+    for (int kc = 0; kc < nk; ++kc) {
+      const int buf = kc & 1;
+      if (kc + 1 < nk) gload((kc + 1) * BTK);
+      {
+        bf8_t a[BM][NP], bj[BN][NP];
+        read_frags(buf, a, bj);
+        mma(a, bj);
+      }
+      if (kc + 1 < nk) lstore(buf ^ 1);
+      __syncthreads();
+    }
   }
 
 #pragma unroll
@@ -414,7 +538,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const float* __restric
         const int n = n0 + wn + 16 * j + (lane & 15);
         const float v = acc[i][j][q];
         if (EPI == EPI_STORE) {
-          C[base[q] + n] = v;
+          if constexpr (PS)
+            put_pair((__bf16*)Cv, plane, base[q] + n, v);
+          else
+            C[base[q] + n] = v;
         } else if (row_ok[q] && n < ep.nx) {
           if (EPI == EPI_SUB_DENSE)
             ep.dense[base[q] + n] = old[q][j] - st * (double)v;
@@ -430,7 +557,7 @@ namespace {
 int parts_of(int prec) { return prec == 3 ? 3 : 2; }  // 3: bf16x6, else bf16x3
 
 template <int NP, int TM, int TN>
-hipError_t left_tile(const GemmOperands& s, const float* B, float* C, int M, int ncols, int batch,
+hipError_t left_tile(const GemmOperands& s, const void* B, void* C, int M, int ncols, int batch,
                      long long bstride, int epi, const EpiArgs& ep, hipStream_t st) {
   const unsigned g = (unsigned)((long long)batch * (M / TM) * (ncols / TN));
   if (epi == EPI_DIVIDE)
@@ -443,7 +570,7 @@ hipError_t left_tile(const GemmOperands& s, const float* B, float* C, int M, int
 }
 
 template <int NP, int TM, int TN>
-hipError_t right_tile(const GemmOperands& s, const float* A, float* C, int rows, int K, int epi,
+hipError_t right_tile(const GemmOperands& s, const void* A, void* C, int rows, int K, int epi,
                       const EpiArgs& ep, hipStream_t st) {
   const unsigned g = (unsigned)((long long)(rows / TM) * (K / TN));
   switch (epi) {
@@ -490,16 +617,12 @@ int gemm_bf_max_tile(int prec) { return parts_of(prec) == 3 ? 64 : 128; }
 hipError_t launch_gemm_left(int prec, const GemmOperands& s, const void* B, void* C, int M,
                             int ncols, int batch, long long bstride, int epi, const EpiArgs& ep,
                             int tm, int tn, hipStream_t st) {
-  const float* Bf = (const float*)B;
-  float* Cf = (float*)C;
-  QN_BF_TILES(left_tile, parts_of(prec), s, Bf, Cf, M, ncols, batch, bstride, epi, ep, st)
+  QN_BF_TILES(left_tile, parts_of(prec), s, B, C, M, ncols, batch, bstride, epi, ep, st)
 }
 
 hipError_t launch_gemm_right(int prec, const GemmOperands& s, const void* A, void* C, int rows,
                              int K, int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st) {
-  const float* Af = (const float*)A;
-  float* Cf = (float*)C;
-  QN_BF_TILES(right_tile, parts_of(prec), s, Af, Cf, rows, K, epi, ep, st)
+  QN_BF_TILES(right_tile, parts_of(prec), s, A, C, rows, K, epi, ep, st)
 }
 
 #undef QN_BF_TILES

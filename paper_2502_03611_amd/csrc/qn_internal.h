@@ -7,6 +7,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "qn.h"
+
 namespace qn {
 
 // Device-resident scalars of one context.  The residual reduction writes the
@@ -143,7 +145,9 @@ struct ResidualArgs {
   const double* U;
   const double* F;
   void* R;                 // output base
-  int out_prec;            // 0: double, 1: float
+  int out_prec;            // 0: double, 1: float, 2: bf16 part pair (hi plane at R, lo plane
+                           //    r_plane elements further; the split-bf16 transforms' storage)
+  long long r_plane = 0;   // out_prec 2: elements of one plane
   long long r_cstride;     // output stride between components
   int r_zstride, r_ystride;// output strides of z and y (x stride 1)
   int ox, oy, oz;          // output extents to cover (padded or interior)
@@ -238,6 +242,11 @@ hipError_t launch_finalize(const double* partials, int nblocks, DevScalars* sc, 
                            int iter, int max_iter, hipStream_t st, DevScalars* mirror = nullptr);
 
 // Dense (ncomp, nz, ny, nx) fp64 -> padded (ncomp, pz, py, px) fp64/fp32, zero pads.
+// Element storage of the transform workspace tensors for a qn_precision:
+// 0 FP64, 1 FP32, 2 bf16 part planes (bf16x3; out_prec of ResidualArgs).
+inline int transform_storage(int prec) {
+  return prec == QN_PREC_FP64 ? 0 : prec == QN_PREC_BF16X3 ? 2 : 1;
+}
 hipError_t launch_pad_copy(const double* src, void* dst, int out_prec, int ncomp, int nx, int ny,
                            int nz, int px, int py, int pz, hipStream_t st);
 // Write {scale, beta} into a device slot.

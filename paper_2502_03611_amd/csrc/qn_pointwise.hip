@@ -17,6 +17,7 @@
 // zero on every call, so padding never carries stale values.
 
 #include <algorithm>
+#include <type_traits>
 #include <cfloat>
 
 #include "qn_internal.h"
@@ -70,9 +71,20 @@ __device__ inline void block_reduce4(double& s0, double& mn, double& mx, double&
   }
 }
 
+// Output element types: double, float, or the split-bf16 part pair of the
+// FP32 value (hi = RNE(x) in the plane at base, lo = RNE(x - hi) in the plane
+// `plane` elements further), the storage of the bf16x3 transforms.
+struct BfPair {};
 template <typename TO>
-__device__ inline void put(void* base, long long idx, double v) {
-  reinterpret_cast<TO*>(base)[idx] = (TO)v;
+__device__ inline void put(void* base, long long idx, double v, long long plane) {
+  if constexpr (std::is_same<TO, BfPair>::value) {
+    const float x = (float)v;
+    const __bf16 h = (__bf16)x;
+    reinterpret_cast<__bf16*>(base)[idx] = h;
+    reinterpret_cast<__bf16*>(base)[plane + idx] = (__bf16)(x - (float)h);
+  } else {
+    reinterpret_cast<TO*>(base)[idx] = (TO)v;
+  }
 }
 
 // Trapezoid weight of node i of n along an axis with Neumann data.
@@ -239,14 +251,14 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
         for (int c = 0; c < NC; ++c) {
           s_r += rw * (r[c] * r[c]);
           const long long o = c * a.r_cstride + (long long)z * a.r_zstride + (long long)y * a.r_ystride + x;
-          put<TO>(a.R, o, r[c]);
+          put<TO>(a.R, o, r[c], a.r_plane);
         }
       }
     } else if (MODE != 1 && out_xy) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const long long o = c * a.r_cstride + (long long)z * a.r_zstride + (long long)y * a.r_ystride + x;
-        put<TO>(a.R, o, 0.0);
+        put<TO>(a.R, o, 0.0, a.r_plane);
       }
     }
     __syncthreads();  // the plane in LDS is overwritten next step
@@ -426,14 +438,14 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
         if constexpr (MODE != 1) {
           s_r += rw * (r[c] * r[c]);
           const long long o = c * a.r_cstride + (long long)pl * a.r_zstride + (long long)y * a.r_ystride + x;
-          put<TO>(a.R, o, r[c]);
+          put<TO>(a.R, o, r[c], a.r_plane);
         }
       }
     } else if (MODE != 1 && xout) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const long long o = c * a.r_cstride + (long long)pl * a.r_zstride + (long long)y * a.r_ystride + x;
-        put<TO>(a.R, o, 0.0);
+        put<TO>(a.R, o, 0.0, a.r_plane);
       }
     }
 #pragma unroll
@@ -480,12 +492,16 @@ static void launch_nl_bc(const ResidualArgs& a, dim3 g, bool planar, hipStream_t
   if (planar) {
     if (a.out_prec == 0 || MODE == 1)
       hipLaunchKernelGGL((k_residual2d<NL, double, BC, MODE>), g, dim3(R2X), 0, st, a);
+    else if (a.out_prec == 2 && MODE == 0)
+      hipLaunchKernelGGL((k_residual2d<NL, BfPair, BC, MODE>), g, dim3(R2X), 0, st, a);
     else
       hipLaunchKernelGGL((k_residual2d<NL, float, BC, MODE>), g, dim3(R2X), 0, st, a);
     return;
   }
   if (a.out_prec == 0 || MODE == 1)
     hipLaunchKernelGGL((k_residual<NL, double, BC, MODE>), g, dim3(RX, RY), 0, st, a);
+  else if (a.out_prec == 2 && MODE == 0)
+    hipLaunchKernelGGL((k_residual<NL, BfPair, BC, MODE>), g, dim3(RX, RY), 0, st, a);
   else
     hipLaunchKernelGGL((k_residual<NL, float, BC, MODE>), g, dim3(RX, RY), 0, st, a);
 }
@@ -764,8 +780,9 @@ hipError_t launch_breset(BState* st, int* done, int K, hipStream_t s) {
 }
 
 template <typename TO>
-__global__ __launch_bounds__(256) void k_pad_copy(const double* __restrict__ src, TO* __restrict__ dst,
-                                                  int nx, int ny, int nz, int px, int py, int pz) {
+__global__ __launch_bounds__(256) void k_pad_copy(const double* __restrict__ src, void* __restrict__ dst,
+                                                  int nx, int ny, int nz, int px, int py, int pz,
+                                                  long long plane) {
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int y = blockIdx.y * 4 + threadIdx.y;
   const int zc = blockIdx.z;  // c * pz + z
@@ -774,18 +791,22 @@ __global__ __launch_bounds__(256) void k_pad_copy(const double* __restrict__ src
   double v = 0.0;
   if (x < nx && y < ny && z < nz)
     v = src[(((long long)c * nz + z) * ny + y) * nx + x];
-  dst[((long long)zc * py + y) * px + x] = (TO)v;
+  put<TO>(dst, ((long long)zc * py + y) * px + x, v, plane);
 }
 
 hipError_t launch_pad_copy(const double* src, void* dst, int out_prec, int ncomp, int nx, int ny,
                            int nz, int px, int py, int pz, hipStream_t st) {
   dim3 g((px + 63) / 64, (py + 3) / 4, ncomp * pz);
+  const long long plane = (long long)ncomp * pz * py * px;
   if (out_prec == 0)
-    hipLaunchKernelGGL((k_pad_copy<double>), g, dim3(64, 4), 0, st, src, (double*)dst, nx, ny, nz,
-                       px, py, pz);
+    hipLaunchKernelGGL((k_pad_copy<double>), g, dim3(64, 4), 0, st, src, dst, nx, ny, nz, px, py,
+                       pz, plane);
+  else if (out_prec == 2)
+    hipLaunchKernelGGL((k_pad_copy<BfPair>), g, dim3(64, 4), 0, st, src, dst, nx, ny, nz, px, py,
+                       pz, plane);
   else
-    hipLaunchKernelGGL((k_pad_copy<float>), g, dim3(64, 4), 0, st, src, (float*)dst, nx, ny, nz,
-                       px, py, pz);
+    hipLaunchKernelGGL((k_pad_copy<float>), g, dim3(64, 4), 0, st, src, dst, nx, ny, nz, px, py,
+                       pz, plane);
   return hipGetLastError();
 }
 
