@@ -43,15 +43,19 @@ PEAK_HBM_GBS = 8000.0
 # 511^3, the read counter scaled x2.0 and the write counter x1.0 (both
 # calibrated on a plain 1 GiB device copy), keyed by kernel.  Each figure is
 # valid only while the source file it was taken on is unchanged.
-TRAFFIC_SOURCES = {"fold": ("paper_2502_03611_amd/csrc/qn_gemm_fold.hip", "c13f02002af662fc"),
-                   "pointwise": ("paper_2502_03611_amd/csrc/qn_pointwise.hip", "8bb0643855198d0a")}
-TRAFFIC = {"k_fold_right_fwd<double,64,128,0>": ("fold", 1.4505e+09, 1.0737e+09),
-           "k_fold_right_fwd<double,128,128,0>": ("fold", 1.2723e+09, 1.0737e+09),
-           "k_fold_left_fwd2<double,64,64,EPI_STORE,0>": ("fold", 1.4559e+09, 1.0737e+09),
-           "k_fold_left_fwd2<double,64,64,EPI_DIVIDE,0>": ("fold", 1.4324e+09, 1.0737e+09),
-           "k_fold_left_inv<double,64,64,0>": ("fold", 1.3846e+09, 1.0716e+09),
-           "k_fold_right_inv<double,64,64,EPI_SUB_DENSE,0>": ("fold", 2.4518e+09, 1.0725e+09),
-           "k_residual<QUASILIN,double>": ("pointwise", 2.2840e+09, 1.0739e+09)}
+TRAFFIC_SOURCES = {"fold": ("paper_2502_03611_amd/csrc/qn_gemm_fold.hip", "b58b7f07177d6690"),
+                   "pointwise": ("paper_2502_03611_amd/csrc/qn_pointwise.hip", "472e29e2e2181b53"),
+                   "bf16": ("paper_2502_03611_amd/csrc/qn_gemm_bf16.hip", "6af7334d3a289a09")}
+TRAFFIC = {"k_fold_right_fwd<double,64,128,0>": ("fold", 1.4642e+09, 1.0737e+09),
+           "k_fold_left_fwd2<double,64,64,EPI_STORE,0>": ("fold", 1.4565e+09, 1.0737e+09),
+           "k_fold_left_fwd<double,128,128,EPI_DIVIDE,0>": ("fold", 1.2583e+09, 1.0737e+09),
+           "k_fold_left_inv<double,64,64,0>": ("fold", 1.3860e+09, 1.0716e+09),
+           "k_fold_right_inv<double,64,64,EPI_SUB_DENSE,0>": ("fold", 2.5092e+09, 1.0762e+09),
+           "k_residual<QUASILIN,double>": ("pointwise", 2.2770e+09, 1.0739e+09),
+           "k_gemm_right_bf<2,128,128,EPI_STORE>": ("bf16", 6.2219e+08, 5.3691e+08),
+           "k_gemm_left_bf<2,128,128,EPI_STORE>": ("bf16", 6.2044e+08, 5.3741e+08),
+           "k_gemm_left_bf<2,128,128,EPI_DIVIDE>": ("bf16", 6.5624e+08, 5.3787e+08),
+           "k_gemm_right_bf<2,128,128,EPI_SUB_DENSE>": ("bf16", 1.7374e+09, 1.0820e+09)}
 
 
 def traffic_if_current(kernel, n):
@@ -213,6 +217,18 @@ def mixed_steps(shape, U, F, steps, precisions=("fp32", "bf16x3")):
                           "gbs_fp32_io": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)})
             rec["kernels"][k] = e
         rec["tiles"] = s.tiles()
+        if prec == "bf16x3":
+            # measured HBM bytes of the kept tiles (profiles/traffic_fp64_quasilinear_511.md)
+            keys = ["gemm_x", "gemm_yz", "gemm_divide", "gemm_yz_inv", "gemm_yz_inv", "gemm_x_update"]
+            for key, (kind, axis, tm, tn) in zip(keys, rec["tiles"]):
+                form = "k_gemm_right_bf" if kind in (0, 3) else "k_gemm_left_bf"
+                epi = ("EPI_SUB_DENSE" if kind == 3 else
+                       "EPI_DIVIDE" if (kind == 1 and axis == 2) else "EPI_STORE")
+                tr = traffic_if_current(f"{form}<2,{tm},{tn},{epi}>", n)
+                e = rec["kernels"].get(key)
+                if e is not None and tr is not None:
+                    e["traffic"] = tr
+                    e["traffic_gbs"] = round(tr / (e["avg_ms"] * 1e-3) / 1e9, 1)
         out[prec] = rec
         s.close()
     return out
