@@ -382,6 +382,8 @@ def main(argv=None):
     ap.add_argument("--save", default=WEIGHTS)
     ap.add_argument("--load", default="",
                     help="evaluate these weights (.npy) instead of training; --save is ignored")
+    ap.add_argument("--inference", choices=("fp16", "fp32"), default="fp16",
+                    help="network forward of the evaluation: the fused FP16 kernel or the FP32 layer kernels")
     args = ap.parse_args(argv)
 
     def log(m):
@@ -413,6 +415,7 @@ def main(argv=None):
             os.makedirs(os.path.dirname(os.path.abspath(args.save)), exist_ok=True)
             np.save(args.save, theta, allow_pickle=False)
         log(f"trained {args.epochs} epochs in {t_train:.1f} s; evaluating {args.eval} held-out seeds")
+    net.set_inference(args.inference)
     compare(net, range(10000, 10002), n=args.n)  # warm-up: first launches, allocations
     rows = compare(net, range(10000, 10000 + args.eval), n=args.n)
 
@@ -431,6 +434,7 @@ def main(argv=None):
            "train_s": round(t_train, 2),
            "steps": args.epochs * (args.train // args.batch),
            "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1], "held_out": args.eval,
+           "inference": args.inference,
            "fp64_zero": agg("fp64_zero"), "fp64_net": agg("fp64_net"),
            "fp32_zero": agg("fp32_zero"), "fp32_net": agg("fp32_net")}
     print(json.dumps(out))
