@@ -182,7 +182,7 @@ def test_batched_neumann_matches_single_instance_and_oracle(prec, mode, beta):
         assert np.linalg.norm(ub - ref["u"]) <= 2e-10 * np.linalg.norm(srcs[i])
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-6)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-6), ("bf16x3", 4e-5)])
 def test_batched_fdm_solve_every_instance(prec, tol):
     """qnb_fdm_solve: X_i = (scale A_h + shift I)^-1 R_i for every instance of
     a mixed pool (scalar and 2-component, uneven sizes), against the oracle's
