@@ -277,9 +277,10 @@ qn_status qn_residual(qn_ctx ctx, const double* d_U, const double* d_F, double* 
  * device current.  Finite differences only.
  * Errors: as qn_residual, plus QN_ERR_WORKSPACE when the grid needs more
  * than QN_NOALLOC_MAX_BLOCKS workgroup partials (3D grids up to about 1024^3,
- * 2D grids up to 4096^2 fit; see residual launch shape: 64 x 16 x 32-plane
+ * 2D grids up to 4096^2 fit; see residual launch shape: 64 x 8 x 64-plane
  * tiles in 3D, 256-column strips in 2D) and QN_ERR_UNSUPPORTED for spectral
- * elements. */
+ * elements.  The capacity is checked before the pointers.
+ */
 #define QN_NOALLOC_MAX_BLOCKS 65536
 qn_status qn_residual_noalloc(qn_ctx ctx, const double* d_U, const double* d_F, double* d_R,
                               double* d_red);

@@ -917,18 +917,29 @@ qn_status qn_residual_noalloc(qn_ctx c, const double* d_U, const double* d_F, do
   if (c->sem_k > 0)
     return fail(QN_ERR_UNSUPPORTED,
                 "qn_residual_noalloc: spectral elements keep their operator bands in the workspace");
-  if (!d_U || !d_F || !d_R) return fail(QN_ERR_INVALID, "null U, F or R");
-  if (!aligned8(d_U) || !aligned8(d_F) || !aligned8(d_R) || (d_red && !aligned8(d_red)))
-    return fail(QN_ERR_INVALID, "pointers must be 8-byte aligned");
-  if (d_R == d_U) return fail(QN_ERR_INVALID, "R may not alias U");
-  ResidualArgs a = residual_args(c, d_U, d_F, d_R);
-  // the launch's workgroup count, as launch_residual forms it
-  const int blocks = residual_max_blocks(a.ox, a.oy, a.oz, a.rz, a.ihz2 == 0.0);
+  // The capacity check comes before the pointer checks, so that a grid the
+  // fixed array cannot hold is refused whatever the pointers are.  The
+  // launch's workgroup count, as residual_args and launch_residual form it
+  // for a caller's R (unpadded extents).
+  const bool planar = c->dim != 3;
+  const int blocks = residual_max_blocks(
+      c->n[0], c->n[1], c->n[2], planar ? residual_planar_rows(c->n[0], c->n[1]) : RESIDUAL_RZ,
+      planar);
   if (blocks < 0 || (size_t)blocks > kNoAllocSlots)
     return fail(QN_ERR_WORKSPACE,
                 "qn_residual_noalloc: the grid needs %d workgroup partials, the static scratch "
                 "holds %zu (use qn_residual with a bound workspace)",
                 blocks, kNoAllocSlots);
+  if (!d_U || !d_F || !d_R) return fail(QN_ERR_INVALID, "null U, F or R");
+  if (!aligned8(d_U) || !aligned8(d_F) || !aligned8(d_R) || (d_red && !aligned8(d_red)))
+    return fail(QN_ERR_INVALID, "pointers must be 8-byte aligned");
+  if (d_R == d_U) return fail(QN_ERR_INVALID, "R may not alias U");
+  ResidualArgs a = residual_args(c, d_U, d_F, d_R);
+  // the launch's own grid, which the partials slots must cover
+  const int launch_blocks = residual_max_blocks(a.ox, a.oy, a.oz, a.rz, a.ihz2 == 0.0);
+  if (launch_blocks < 0 || (size_t)launch_blocks > kNoAllocSlots)
+    return fail(QN_ERR_WORKSPACE, "qn_residual_noalloc: the grid needs %d workgroup partials",
+                launch_blocks);
   char* base = nullptr;
   hipError_t e = noalloc_scratch(&base);
   if (e != hipSuccess) return hip_fail(c, e, "qn_residual_noalloc: scratch address");

@@ -206,7 +206,7 @@ hipError_t launch_scale(double* u, long long n, const double* s, hipStream_t st)
 // (1/h_z^2 = 0: 2D problems and the batched solver), which uses the planar
 // kernel with oz planes.
 int residual_max_blocks(int ox, int oy, int oz, int rz, bool planar);
-constexpr int RESIDUAL_RZ = 32;          // z-slab depth of a single 3D problem
+constexpr int RESIDUAL_RZ = 64;          // z-slab depth of a single 3D problem
 constexpr int RESIDUAL_PLANAR_ROWS = 16;  // rows per workgroup, many planes per launch
 // Rows per workgroup of the planar residual over one ox x oy plane: 16,
 // halved until the plane gives at least 1024 workgroups (or 1 row).

@@ -10,7 +10,7 @@
 //
 // The residual kernel marches along z: each thread owns one (x, y) column of
 // a z-slab and keeps U(z-1), U(z), U(z+1) in registers, so each U value is
-// fetched once for its z-neighbours; the block's current plane (64 x 16 with
+// fetched once for its z-neighbours; the block's current plane (64 x 8 with
 // a one-point halo) is staged in LDS for the x/y neighbours, so U is re-read
 // only along the halo.  2D grids are the nz = 1 case with 1/h_z^2 = 0.  Output points
 // outside the interior (padding of the transform workspace) are written as
@@ -25,7 +25,7 @@
 
 namespace qn {
 
-constexpr int RX = 64, RY = 16;  // residual block (x, y); z-slab depth is a launch argument
+constexpr int RX = 64, RY = 8;  // residual block (x, y); z-slab depth is a launch argument
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -98,8 +98,12 @@ __device__ inline double end_weight(int i, int n) { return (i == 0 || i == n - 1
 template <int NL, typename TO, int BC, int MODE = 0>
 __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
   constexpr int NC = (NL == NL_SYS2) ? 2 : 1;
-  // Current z-plane of the block's 64 x 16 tile plus a one-point x/y halo.
-  __shared__ double s_u[NC][RY + 2][RX + 2];
+  // Current z-plane of the block's 64 x 8 tile plus a one-point x/y halo,
+  // double-buffered by plane parity: plane z+1 is written into the other
+  // buffer while slower waves may still read plane z, so one barrier per
+  // plane suffices (a wave can only overwrite a buffer two planes later,
+  // after every wave has passed the barrier that follows its last read).
+  __shared__ double s_buf[2][NC][RY + 2][RX + 2];
   const int tx = threadIdx.x, ty = threadIdx.y;
   // Workgroups are dealt to the 8 XCDs round-robin in launch order; remapped,
   // each XCD walks a contiguous range of tiles (x fastest), so the halo lines
@@ -162,6 +166,7 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
   if (z0 < z1) load_plane(z0, up, f, hc, vc, pv);
   for (int z = z0; z < z1; ++z) {
     const bool zin = z < nz;
+    auto& s_u = s_buf[(z - z0) & 1];
     if (z + 1 < z1) load_plane(z + 1, n_up, n_f, n_hc, n_vc, n_pv);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -261,7 +266,6 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
         put<TO>(a.R, o, 0.0, a.r_plane);
       }
     }
-    __syncthreads();  // the plane in LDS is overwritten next step
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       um[c] = uc[c];

@@ -16,7 +16,7 @@ import synth
 from oracle import qn as oqn
 from paper_2502_03611_amd import Solver
 from paper_2502_03611_amd._binding import QNError, lib
-from paper_2502_03611_amd import QN_ERR_WORKSPACE, QN_ERR_UNSUPPORTED
+from paper_2502_03611_amd import QN_ERR_WORKSPACE, QN_ERR_UNSUPPORTED, QN_ERR_INVALID
 
 pytestmark = pytest.mark.gpu
 
@@ -71,12 +71,17 @@ def test_noalloc_residual_equals_qn_residual_twice_shrinking(first, second):
 
 def test_noalloc_residual_rejects_what_the_fixed_array_cannot_hold():
     L = lib()
-    dummy = torch.zeros(8, dtype=torch.float64, device="cuda")
-    p = ctypes.c_void_p(dummy.data_ptr())
-    # 64 x 256 x 5 = 81920 workgroups of 64 x 16 x 32 points > 65536 slots
+    # 64 x 512 x 3 = 98304 workgroups of 64 x 8 x 64 points > 65536 slots.
+    # The capacity is checked before the pointers, so null pointers are
+    # refused with QN_ERR_WORKSPACE; if the capacity check ever let this grid
+    # through, the null check answers QN_ERR_INVALID and nothing launches.
     big = Solver((160, 4096, 4096), "cubic", beta=1.0, workspace=False)
-    st = L.qn_residual_noalloc(big._ctx, p, p, ctypes.c_void_p(dummy.data_ptr() + 8), p)
+    null = ctypes.c_void_p(None)
+    st = L.qn_residual_noalloc(big._ctx, null, null, null, null)
     assert st == QN_ERR_WORKSPACE
+    # a grid that fits passes the capacity check and meets the null check
+    small = Solver((31, 45), "cubic", beta=1.0, workspace=False)
+    assert L.qn_residual_noalloc(small._ctx, null, null, null, null) == QN_ERR_INVALID
     sem = Solver((15, 15), "cubic", beta=1.0, discretization="sem", sem_order=2, workspace=False)
     with pytest.raises(QNError) as e:
         sem.residual_noalloc(torch.zeros((1, 15, 15), dtype=torch.float64, device="cuda"),
