@@ -275,11 +275,14 @@ qn_status qn_residual(qn_ctx ctx, const double* d_U, const double* d_F, double* 
  * that array, so calls that overlap on one device (other streams, other
  * threads) race; calls on one stream are ordered.  Call with the context's
  * device current.  Finite differences only.
- * Errors: as qn_residual, plus QN_ERR_WORKSPACE when the grid needs more
- * than QN_NOALLOC_MAX_BLOCKS workgroup partials (3D grids up to about 1024^3,
- * 2D grids up to 4096^2 fit; see residual launch shape: 64 x 8 x 64-plane
- * tiles in 3D, 256-column strips in 2D) and QN_ERR_UNSUPPORTED for spectral
- * elements.  The capacity is checked before the pointers.
+ * Every grid qn_setup accepts fits: the 3D residual launches at most 16384
+ * workgroups (1024-thread tiles of whole 512- to 64-column row segments,
+ * z-slabs sized to about one resident round of workgroups), the 2D one at
+ * most 4096 (256-column strips).
+ * Errors: as qn_residual, plus QN_ERR_UNSUPPORTED for spectral elements and,
+ * as a guard, QN_ERR_WORKSPACE for a launch that would need more than
+ * QN_NOALLOC_MAX_BLOCKS workgroup partials.  These two are checked before the
+ * pointers.
  */
 #define QN_NOALLOC_MAX_BLOCKS 65536
 qn_status qn_residual_noalloc(qn_ctx ctx, const double* d_U, const double* d_F, double* d_R,

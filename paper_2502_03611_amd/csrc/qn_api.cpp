@@ -298,7 +298,8 @@ ResidualArgs residual_args(qn_ctx c, const double* U, const double* F, double* R
   a.pot = c->pot;
   a.bc = c->bc;
   a.partials = c->at<double>(c->off_part);
-  a.rz = c->dim == 3 ? RESIDUAL_RZ : residual_planar_rows(a.ox, a.oy);
+  a.rz = c->dim == 3 ? residual_slab_depth(a.ox, a.oy, a.oz, residual_threads(c->nl, c->bc))
+                      : residual_planar_rows(a.ox, a.oy);
   a.sem_k = c->sem_k;
   for (int i = 0; i < c->dim && c->sem_k > 0; ++i) a.hb[i] = c->at<double>(c->off_Hb[i]);
   a.gs_da = c->gs[0];
@@ -791,8 +792,13 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   off += align256(c->tensor_elems() * c->elem());
   // partial slots for both residual launches: padded (the iteration) and
   // interior (qn_residual) extents
+  const int rt = residual_threads(c->nl, c->bc);
   if (c->dim == 3)
-    c->max_blocks = residual_max_blocks(c->p[0], c->p[1], c->p[2], RESIDUAL_RZ, false);
+    c->max_blocks = std::max(  // padded extents (transform workspace) and a caller's R
+        residual_max_blocks(c->p[0], c->p[1], c->p[2],
+                            residual_slab_depth(c->p[0], c->p[1], c->p[2], rt), false, rt),
+        residual_max_blocks(c->n[0], c->n[1], c->n[2],
+                            residual_slab_depth(c->n[0], c->n[1], c->n[2], rt), false, rt));
   else
     c->max_blocks = std::max(
         residual_max_blocks(c->p[0], c->p[1], 1, residual_planar_rows(c->p[0], c->p[1]), true),
@@ -922,9 +928,12 @@ qn_status qn_residual_noalloc(qn_ctx c, const double* d_U, const double* d_F, do
   // launch's workgroup count, as residual_args and launch_residual form it
   // for a caller's R (unpadded extents).
   const bool planar = c->dim != 3;
+  const int rt = residual_threads(c->nl, c->bc);
   const int blocks = residual_max_blocks(
-      c->n[0], c->n[1], c->n[2], planar ? residual_planar_rows(c->n[0], c->n[1]) : RESIDUAL_RZ,
-      planar);
+      c->n[0], c->n[1], c->n[2],
+      planar ? residual_planar_rows(c->n[0], c->n[1])
+             : residual_slab_depth(c->n[0], c->n[1], c->n[2], rt),
+      planar, rt);
   if (blocks < 0 || (size_t)blocks > kNoAllocSlots)
     return fail(QN_ERR_WORKSPACE,
                 "qn_residual_noalloc: the grid needs %d workgroup partials, the static scratch "
@@ -936,7 +945,7 @@ qn_status qn_residual_noalloc(qn_ctx c, const double* d_U, const double* d_F, do
   if (d_R == d_U) return fail(QN_ERR_INVALID, "R may not alias U");
   ResidualArgs a = residual_args(c, d_U, d_F, d_R);
   // the launch's own grid, which the partials slots must cover
-  const int launch_blocks = residual_max_blocks(a.ox, a.oy, a.oz, a.rz, a.ihz2 == 0.0);
+  const int launch_blocks = residual_max_blocks(a.ox, a.oy, a.oz, a.rz, a.ihz2 == 0.0, rt);
   if (launch_blocks < 0 || (size_t)launch_blocks > kNoAllocSlots)
     return fail(QN_ERR_WORKSPACE, "qn_residual_noalloc: the grid needs %d workgroup partials",
                 launch_blocks);

@@ -47,6 +47,14 @@ enum ShiftRule : int {
 // real parts of the 2 x 2 reaction-block eigenvalues.
 enum Nonlin : int { NL_CUBIC = 0, NL_QUASILIN = 1, NL_SYS2 = 2, NL_GS = 3 };
 
+// Threads per workgroup of the 3D residual: 1024 (two workgroups per CU) for
+// the variants that fit in 64 VGPRs, 512 where the kernel needs more registers
+// (two components, or Neumann data), which would otherwise leave a single
+// 1024-thread workgroup per CU.  bc: 0 Dirichlet, 1 Neumann.
+constexpr int residual_threads(int nl, int bc) {
+  return (nl == NL_QUASILIN || (nl == NL_CUBIC && bc == 0)) ? 1024 : 512;
+}
+
 // Epilogues of the mode-product GEMMs.
 enum Epi : int {
   EPI_STORE = 0,        // padded store
@@ -205,8 +213,12 @@ hipError_t launch_scale(double* u, long long n, const double* s, hipStream_t st)
 // Workgroups (= partial slots) of a residual launch; planar: no z coupling
 // (1/h_z^2 = 0: 2D problems and the batched solver), which uses the planar
 // kernel with oz planes.
-int residual_max_blocks(int ox, int oy, int oz, int rz, bool planar);
-constexpr int RESIDUAL_RZ = 64;          // z-slab depth of a single 3D problem
+int residual_max_blocks(int ox, int oy, int oz, int rz, bool planar, int threads = 1024);
+// 3D residual geometry (launch and partial-slot sizing use the same rule):
+// tile width in x of the workgroups and z-slab depth for an ox x oy x oz grid
+// and `threads` (residual_threads) per workgroup.
+int residual_tile_x(int ox);
+int residual_slab_depth(int ox, int oy, int oz, int threads);
 constexpr int RESIDUAL_PLANAR_ROWS = 16;  // rows per workgroup, many planes per launch
 // Rows per workgroup of the planar residual over one ox x oy plane: 16,
 // halved until the plane gives at least 1024 workgroups (or 1 row).

@@ -10,9 +10,9 @@
 //
 // The residual kernel marches along z: each thread owns one (x, y) column of
 // a z-slab and keeps U(z-1), U(z), U(z+1) in registers, so each U value is
-// fetched once for its z-neighbours; the block's current plane (64 x 8 with
-// a one-point halo) is staged in LDS for the x/y neighbours, so U is re-read
-// only along the halo.  2D grids are the nz = 1 case with 1/h_z^2 = 0.  Output points
+// fetched once for its z-neighbours; the block's current plane (a tile of
+// whole 512-, 256-, 128- or 64-column row segments with a one-point halo) is
+// staged in LDS for the x/y neighbours, so U is re-read only along the halo.  2D grids are the nz = 1 case with 1/h_z^2 = 0.  Output points
 // outside the interior (padding of the transform workspace) are written as
 // zero on every call, so padding never carries stale values.
 
@@ -25,7 +25,10 @@
 
 namespace qn {
 
-constexpr int RX = 64, RY = 8;  // residual block (x, y); z-slab depth is a launch argument
+// 3D residual workgroups: residual_threads(nl, bc) threads (1024 or 512) as
+// TX x (threads / TX) columns of a z-slab (TX chosen per grid by
+// residual_tile_x, the slab depth by residual_slab_depth; both are
+// launch-time choices).
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -95,10 +98,13 @@ __device__ inline double end_weight(int i, int n) { return (i == 0 || i == n - 1
 // last rows h^-2 (2, -2)); BC = 0: zero outside (Dirichlet).  MODE 1 and 2:
 // the two passes of the eigenproblem residual (cubic problem only; see
 // ResidualArgs), which read no F.
-template <int NL, typename TO, int BC, int MODE = 0>
-__global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
+template <int NL, typename TO, int BC, int MODE, int RX>
+__global__ __launch_bounds__(residual_threads(NL, BC), residual_threads(NL, BC) == 1024 ? 8 : 1)
+void k_residual(ResidualArgs a) {
   constexpr int NC = (NL == NL_SYS2) ? 2 : 1;
-  // Current z-plane of the block's 64 x 8 tile plus a one-point x/y halo,
+  constexpr int RTHREADS = residual_threads(NL, BC);
+  constexpr int RY = RTHREADS / RX;
+  // Current z-plane of the block's RX x RY tile plus a one-point x/y halo,
   // double-buffered by plane parity: plane z+1 is written into the other
   // buffer while slower waves may still read plane z, so one barrier per
   // plane suffices (a wave can only overwrite a buffer two planes later,
@@ -278,7 +284,7 @@ __global__ __launch_bounds__(RX * RY) void k_residual(ResidualArgs a) {
     pv = n_pv;
   }
 
-  block_reduce4<RX * RY / 64, MODE == 1>(s_r, mn, mx, s_f);
+  block_reduce4<RTHREADS / 64, MODE == 1>(s_r, mn, mx, s_f);
   if (threadIdx.x == 0 && threadIdx.y == 0) {
     double* pp = a.partials + 4LL * tile;  // tile = (bz * gy + by) * gx + bx
     pp[0] = s_r;
@@ -474,9 +480,56 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
   }
 }
 
-static dim3 residual_grid(int ox, int oy, int oz, int rz, bool planar) {
+// Tile width of the 3D residual: rows of 512, 256, 128 or 64 columns, the
+// widest whose lanes past the grid's x extent are at most an eighth of the
+// tiles' span, else the one that leaves the fewest idle.  Long contiguous row
+// segments per workgroup stream HBM best (511^3: 64-wide tiles 0.655 ms,
+// 512-wide 0.611 ms at the same slab depth).
+int residual_tile_x(int ox) {
+  int best = 64;
+  long long best_pad = -1;
+  for (int rx = 512; rx >= 64; rx >>= 1) {
+    const long long span = (long long)((ox + rx - 1) / rx) * rx, pad = span - ox;
+    if (pad * 8 <= span) return rx;
+    if (best_pad < 0 || pad < best_pad) {
+      best_pad = pad;
+      best = rx;
+    }
+  }
+  return best;
+}
+
+// Slab depth of the 3D residual: the fewest z-slabs per column tile that
+// fill the last round of resident workgroups (256 CUs x 2048 threads) to at
+// least 90 %, else the best fill with at most 64 slabs.  At 511^3 this is two
+// slabs of 256 planes, one resident round of 512 workgroups of 1024 threads
+// (64-plane slabs: 0.611 ms, 128: 0.601, 256: 0.580).
+int residual_slab_depth(int ox, int oy, int oz, int threads) {
+  const long long kResident = 256LL * 2048 / threads;
+  const int rx = residual_tile_x(ox), ry = threads / rx;
+  const long long cols = (long long)((ox + rx - 1) / rx) * ((oy + ry - 1) / ry);
+  const int smax = std::max(1, std::min(oz, 64));
+  int best = 1;
+  double best_fill = 0.0;
+  for (int sl = 1; sl <= smax; ++sl) {
+    const long long total = cols * sl;
+    const double fill = (double)total / (double)(kResident * ((total + kResident - 1) / kResident));
+    if (fill >= 0.9) {
+      best = sl;
+      break;
+    }
+    if (fill > best_fill) {
+      best_fill = fill;
+      best = sl;
+    }
+  }
+  return (oz + best - 1) / best;
+}
+
+static dim3 residual_grid(int ox, int oy, int oz, int rz, bool planar, int threads) {
   if (planar) return dim3((ox + R2X - 1) / R2X, (oy + rz - 1) / rz, oz);
-  return dim3((ox + RX - 1) / RX, (oy + RY - 1) / RY, (oz + rz - 1) / rz);
+  const int rx = residual_tile_x(ox), ry = threads / rx;
+  return dim3((ox + rx - 1) / rx, (oy + ry - 1) / ry, (oz + rz - 1) / rz);
 }
 
 int residual_planar_rows(int ox, int oy) {
@@ -486,9 +539,20 @@ int residual_planar_rows(int ox, int oy) {
   return r;
 }
 
-int residual_max_blocks(int ox, int oy, int oz, int rz, bool planar) {
-  const dim3 g = residual_grid(ox, oy, oz, rz, planar);
+int residual_max_blocks(int ox, int oy, int oz, int rz, bool planar, int threads) {
+  const dim3 g = residual_grid(ox, oy, oz, rz, planar, threads);
   return (int)(g.x * g.y * g.z);
+}
+
+template <int NL, int BC, int MODE, int TX>
+static void launch_3d(const ResidualArgs& a, dim3 g, hipStream_t st) {
+  const dim3 b(TX, residual_threads(NL, BC) / TX);
+  if (a.out_prec == 0 || MODE == 1)
+    hipLaunchKernelGGL((k_residual<NL, double, BC, MODE, TX>), g, b, 0, st, a);
+  else if (a.out_prec == 2 && MODE == 0)
+    hipLaunchKernelGGL((k_residual<NL, BfPair, BC, MODE, TX>), g, b, 0, st, a);
+  else
+    hipLaunchKernelGGL((k_residual<NL, float, BC, MODE, TX>), g, b, 0, st, a);
 }
 
 template <int NL, int BC, int MODE = 0>
@@ -502,12 +566,12 @@ static void launch_nl_bc(const ResidualArgs& a, dim3 g, bool planar, hipStream_t
       hipLaunchKernelGGL((k_residual2d<NL, float, BC, MODE>), g, dim3(R2X), 0, st, a);
     return;
   }
-  if (a.out_prec == 0 || MODE == 1)
-    hipLaunchKernelGGL((k_residual<NL, double, BC, MODE>), g, dim3(RX, RY), 0, st, a);
-  else if (a.out_prec == 2 && MODE == 0)
-    hipLaunchKernelGGL((k_residual<NL, BfPair, BC, MODE>), g, dim3(RX, RY), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_residual<NL, float, BC, MODE>), g, dim3(RX, RY), 0, st, a);
+  switch (residual_tile_x(a.ox)) {
+    case 512: launch_3d<NL, BC, MODE, 512>(a, g, st); break;
+    case 256: launch_3d<NL, BC, MODE, 256>(a, g, st); break;
+    case 128: launch_3d<NL, BC, MODE, 128>(a, g, st); break;
+    default: launch_3d<NL, BC, MODE, 64>(a, g, st); break;
+  }
 }
 
 template <int BC>
@@ -528,7 +592,7 @@ static void launch_nl(const ResidualArgs& a, dim3 g, bool planar, hipStream_t st
 hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t st) {
   // planes without z coupling (2D problems, batched instances): the planar kernel
   const bool planar = a.ihz2 == 0.0;
-  const dim3 g = residual_grid(a.ox, a.oy, a.oz, a.rz, planar);
+  const dim3 g = residual_grid(a.ox, a.oy, a.oz, a.rz, planar, residual_threads(a.nl, a.bc));
   *nblocks_out = (int)(g.x * g.y * g.z);
   switch (a.nl) {
     case NL_CUBIC:  // the only nonlinearity with Neumann data and eigenproblem passes

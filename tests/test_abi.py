@@ -149,6 +149,27 @@ def test_workspace_size_and_unbound_errors():
     L.qn_destroy(ctx)
 
 
+def test_noalloc_residual_host_checks():
+    """qn_residual_noalloc needs no workspace and refuses on the host, before
+    it reads a pointer: spectral elements (their operator bands live in the
+    workspace) and, as a guard, a launch beyond the fixed array.  Every grid
+    the library accepts fits that array: the 3D residual launches at most
+    16384 workgroups (here: 8 x 2048 tiles of 512 x 2 columns, one slab) and
+    the 2D one 4096 at most, so null pointers meet the null check."""
+    from paper_2502_03611_amd import Solver
+    L = qn.lib()
+    null = ctypes.c_void_p(None)
+    for shape in ((64, 4096, 3585), (4096, 4096)):
+        s = Solver(shape, "cubic", beta=1.0, workspace=False)
+        assert L.qn_residual_noalloc(s._ctx, null, null, null, null) == qn.QN_ERR_INVALID
+        assert "null" in qn.last_error()
+        s.close()
+    sem = Solver((15, 15), "cubic", beta=1.0, discretization="sem", sem_order=2, workspace=False)
+    assert L.qn_residual_noalloc(sem._ctx, null, null, null, null) == qn.QN_ERR_UNSUPPORTED
+    assert "spectral" in qn.last_error()
+    sem.close()
+
+
 def test_null_context_and_timing_table():
     L = qn.lib()
     assert L.qn_iterate(None, None, None, 0.0, 0, None) == qn.QN_ERR_INVALID

@@ -3,8 +3,8 @@ the same kernels with the reduction scratch in the library's fixed device
 array instead of the bound workspace, so the outputs must be bitwise equal.
 Two calls in a row, the second on a smaller grid (the fixed array keeps the
 first call's partials, which the second must not read), then the first
-again; a grid beyond the fixed array's capacity and spectral elements are
-refused on the host."""
+again.  (What the entry point refuses on the host, before any device work,
+is tested on the CPU in test_abi.py.)"""
 
 import ctypes
 
@@ -15,8 +15,6 @@ import torch
 import synth
 from oracle import qn as oqn
 from paper_2502_03611_amd import Solver
-from paper_2502_03611_amd._binding import QNError, lib
-from paper_2502_03611_amd import QN_ERR_WORKSPACE, QN_ERR_UNSUPPORTED, QN_ERR_INVALID
 
 pytestmark = pytest.mark.gpu
 
@@ -67,25 +65,3 @@ def test_noalloc_residual_equals_qn_residual_twice_shrinking(first, second):
             ora = oqn.residual(KIND[kind], u, f)
             scale = float(np.linalg.norm(f)) + float(np.linalg.norm(ora - (-f)))
             assert np.linalg.norm(R.cpu().numpy() - ora) <= 1e-13 * scale
-
-
-def test_noalloc_residual_rejects_what_the_fixed_array_cannot_hold():
-    L = lib()
-    # 64 x 512 x 3 = 98304 workgroups of 64 x 8 x 64 points > 65536 slots.
-    # The capacity is checked before the pointers, so null pointers are
-    # refused with QN_ERR_WORKSPACE; if the capacity check ever let this grid
-    # through, the null check answers QN_ERR_INVALID and nothing launches.
-    big = Solver((160, 4096, 4096), "cubic", beta=1.0, workspace=False)
-    null = ctypes.c_void_p(None)
-    st = L.qn_residual_noalloc(big._ctx, null, null, null, null)
-    assert st == QN_ERR_WORKSPACE
-    # a grid that fits passes the capacity check and meets the null check
-    small = Solver((31, 45), "cubic", beta=1.0, workspace=False)
-    assert L.qn_residual_noalloc(small._ctx, null, null, null, null) == QN_ERR_INVALID
-    sem = Solver((15, 15), "cubic", beta=1.0, discretization="sem", sem_order=2, workspace=False)
-    with pytest.raises(QNError) as e:
-        sem.residual_noalloc(torch.zeros((1, 15, 15), dtype=torch.float64, device="cuda"),
-                             torch.zeros((1, 15, 15), dtype=torch.float64, device="cuda"),
-                             torch.zeros((1, 15, 15), dtype=torch.float64, device="cuda"))
-    assert e.value.status == QN_ERR_UNSUPPORTED
-    torch.cuda.synchronize()
