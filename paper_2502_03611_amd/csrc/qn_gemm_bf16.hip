@@ -87,19 +87,6 @@ __device__ __forceinline__ int tswz(int k, int col_bytes) {
   return k * TN * 2 + ((((col_bytes >> 5) ^ tperm<TN>(k)) << 5) | (col_bytes & 31));
 }
 
-// x / d for the spectral divide (d > 0, the shifted eigenvalue sum), from the
-// hardware reciprocal refined by two Newton steps and one residual
-// correction: within an FP64 ulp or so of the IEEE quotient, in a third of its
-// instructions; the result is rounded to FP32 right after, so only quotients
-// within that ulp of an FP32 rounding boundary can round differently.
-__device__ __forceinline__ double quot(double x, double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
-  r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
-  const double q = x * r;
-  return __builtin_fma(__builtin_fma(-d, q, x), r, q);
-}
-
 // bf16x3 keeps every intermediate tensor of the solve as its two bf16 parts,
 // hi = RNE(x) and lo = RNE(x - hi) of the FP32 value x, in two planes (hi at
 // the tensor's base, lo one tensor size further): the parts a kernel would

@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256, 2) void k_fold_left_fwd(const T* __restrict__ 
 #pragma unroll
         for (int j = 0; j < BN; ++j) {
           const int n = n0 + wn + 16 * j + (lane & 15);
-          Cb[(long long)m * ncols + n] = (T)((double)acc[i][j][q] / (scale * (lm + cn[j]) + beta));
+          Cb[(long long)m * ncols + n] = (T)quot((double)acc[i][j][q], scale * (lm + cn[j]) + beta);
         }
       }
   } else {
@@ -360,9 +360,9 @@ __global__ __launch_bounds__(256, 2) void k_fold_left_fwd2(const T* __restrict__
       for (int j = 0; j < BN; ++j) {
         const int n = n0 + wn + 16 * j + (lane & 15);
         if (EPI == EPI_DIVIDE) {
-          Cb[(long long)m * ncols + n] = (T)((double)acce[i][j][q] / (scale * (le + cn[j]) + beta));
+          Cb[(long long)m * ncols + n] = (T)quot((double)acce[i][j][q], scale * (le + cn[j]) + beta);
           Cb[(long long)(bk + m) * ncols + n] =
-              (T)((double)acco[i][j][q] / (scale * (lo + cn[j]) + beta));
+              (T)quot((double)acco[i][j][q], scale * (lo + cn[j]) + beta);
         } else {
           Cb[(long long)m * ncols + n] = acce[i][j][q];
           Cb[(long long)(bk + m) * ncols + n] = acco[i][j][q];

@@ -31,6 +31,18 @@ struct Mfma<float> {
   __device__ static inline int row(int lane, int q) { return 4 * (lane >> 4) + q; }
 };
 
+// x / d for the spectral divide (d > 0: the shifted eigenvalue sum, padded
+// spectral entries included), from the hardware reciprocal refined by two
+// Newton steps and one residual correction of the quotient: within about an
+// FP64 ulp of the IEEE quotient in a third of its instructions.
+__device__ __forceinline__ double quot(double x, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+  r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+  const double q = x * r;
+  return __builtin_fma(__builtin_fma(-d, q, x), r, q);
+}
+
 // Tile index for workgroup w of `total`: workgroups are dealt to the 8 XCDs
 // round-robin (XCD w % 8), so XCD j is given the contiguous range of
 // total / 8 (+1 for j < total % 8) tiles starting at j * (total / 8) +
