@@ -43,19 +43,19 @@ PEAK_HBM_GBS = 8000.0
 # 511^3, the read counter scaled x2.0 and the write counter x1.0 (both
 # calibrated on a plain 1 GiB device copy), keyed by kernel.  Each figure is
 # valid only while the source file it was taken on is unchanged.
-TRAFFIC_SOURCES = {"fold": ("paper_2502_03611_amd/csrc/qn_gemm_fold.hip", "b58b7f07177d6690"),
-                   "pointwise": ("paper_2502_03611_amd/csrc/qn_pointwise.hip", "472e29e2e2181b53"),
-                   "bf16": ("paper_2502_03611_amd/csrc/qn_gemm_bf16.hip", "6af7334d3a289a09")}
-TRAFFIC = {"k_fold_right_fwd<double,64,128,0>": ("fold", 1.4642e+09, 1.0737e+09),
-           "k_fold_left_fwd2<double,64,64,EPI_STORE,0>": ("fold", 1.4565e+09, 1.0737e+09),
-           "k_fold_left_fwd<double,128,128,EPI_DIVIDE,0>": ("fold", 1.2583e+09, 1.0737e+09),
-           "k_fold_left_inv<double,64,64,0>": ("fold", 1.3860e+09, 1.0716e+09),
-           "k_fold_right_inv<double,64,64,EPI_SUB_DENSE,0>": ("fold", 2.5092e+09, 1.0762e+09),
-           "k_residual<QUASILIN,double>": ("pointwise", 2.2770e+09, 1.0739e+09),
-           "k_gemm_right_bf<2,128,128,EPI_STORE>": ("bf16", 6.2219e+08, 5.3691e+08),
-           "k_gemm_left_bf<2,128,128,EPI_STORE>": ("bf16", 6.2044e+08, 5.3741e+08),
-           "k_gemm_left_bf<2,128,128,EPI_DIVIDE>": ("bf16", 6.5624e+08, 5.3787e+08),
-           "k_gemm_right_bf<2,128,128,EPI_SUB_DENSE>": ("bf16", 1.7374e+09, 1.0820e+09)}
+TRAFFIC_SOURCES = {"fold": ("paper_2502_03611_amd/csrc/qn_gemm_fold.hip", "307100cb86d46acb"),
+                   "pointwise": ("paper_2502_03611_amd/csrc/qn_pointwise.hip", "358a3e7f44ecd7b2"),
+                   "bf16": ("paper_2502_03611_amd/csrc/qn_gemm_bf16.hip", "c6bc12d520638ac9")}
+TRAFFIC = {"k_fold_right_fwd<double,64,128,0>": ("fold", 1.4640e+09, 1.0737e+09),
+           "k_fold_left_fwd2<double,64,64,EPI_STORE,0>": ("fold", 1.4555e+09, 1.0737e+09),
+           "k_fold_left_fwd<double,128,128,EPI_DIVIDE,0>": ("fold", 1.2594e+09, 1.0737e+09),
+           "k_fold_left_inv<double,64,64,0>": ("fold", 1.3857e+09, 1.0716e+09),
+           "k_fold_right_inv<double,64,64,EPI_SUB_DENSE,0>": ("fold", 2.5080e+09, 1.0761e+09),
+           "k_residual<QUASILIN,double>": ("pointwise", 2.4003e+09, 1.0738e+09),
+           "k_gemm_right_bf<2,128,128,EPI_STORE>": ("bf16", 6.2856e+08, 5.3691e+08),
+           "k_gemm_left_bf<2,128,128,EPI_STORE>": ("bf16", 6.1749e+08, 5.3741e+08),
+           "k_gemm_left_bf<2,128,128,EPI_DIVIDE>": ("bf16", 6.5211e+08, 5.3788e+08),
+           "k_gemm_right_bf<2,128,128,EPI_SUB_DENSE>": ("bf16", 1.7389e+09, 1.0827e+09)}
 
 
 def traffic_if_current(kernel, n):
