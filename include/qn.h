@@ -276,9 +276,10 @@ qn_status qn_residual(qn_ctx ctx, const double* d_U, const double* d_F, double* 
  * threads) race; calls on one stream are ordered.  Call with the context's
  * device current.  Finite differences only.
  * Every grid qn_setup accepts fits: the 3D residual launches at most 16384
- * workgroups (1024-thread tiles of whole 512- to 64-column row segments,
- * z-slabs sized to about one resident round of workgroups), the 2D one at
- * most 4096 (256-column strips).
+ * workgroups of 1024 threads (tiles of whole 512- to 64-column row segments,
+ * z-slabs sized to about one resident round of workgroups) or 32768 of 512
+ * threads (two components or Neumann data), the 2D one at most 4096
+ * (256-column strips).
  * Errors: as qn_residual, plus QN_ERR_UNSUPPORTED for spectral elements and,
  * as a guard, QN_ERR_WORKSPACE for a launch that would need more than
  * QN_NOALLOC_MAX_BLOCKS workgroup partials.  These two are checked before the

@@ -217,7 +217,7 @@ int residual_max_blocks(int ox, int oy, int oz, int rz, bool planar, int threads
 // 3D residual geometry (launch and partial-slot sizing use the same rule):
 // tile width in x of the workgroups and z-slab depth for an ox x oy x oz grid
 // and `threads` (residual_threads) per workgroup.
-int residual_tile_x(int ox);
+int residual_tile_x(int ox, int threads);
 int residual_slab_depth(int ox, int oy, int oz, int threads);
 constexpr int RESIDUAL_PLANAR_ROWS = 16;  // rows per workgroup, many planes per launch
 // Rows per workgroup of the planar residual over one ox x oy plane: 16,

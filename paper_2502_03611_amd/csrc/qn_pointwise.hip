@@ -104,6 +104,7 @@ void k_residual(ResidualArgs a) {
   constexpr int NC = (NL == NL_SYS2) ? 2 : 1;
   constexpr int RTHREADS = residual_threads(NL, BC);
   constexpr int RY = RTHREADS / RX;
+  static_assert(RY >= 2, "the halo rows below and above need two tile rows");
   // Current z-plane of the block's RX x RY tile plus a one-point x/y halo,
   // double-buffered by plane parity: plane z+1 is written into the other
   // buffer while slower waves may still read plane z, so one barrier per
@@ -480,15 +481,16 @@ __global__ __launch_bounds__(R2X) void k_residual2d(ResidualArgs a) {
   }
 }
 
-// Tile width of the 3D residual: rows of 512, 256, 128 or 64 columns, the
-// widest whose lanes past the grid's x extent are at most an eighth of the
-// tiles' span, else the one that leaves the fewest idle.  Long contiguous row
-// segments per workgroup stream HBM best (511^3: 64-wide tiles 0.655 ms,
-// 512-wide 0.611 ms at the same slab depth).
-int residual_tile_x(int ox) {
+// Tile width of the 3D residual: rows of 512, 256, 128 or 64 columns (at
+// most half the workgroup's threads: a tile has at least two rows, one for
+// each y halo), the widest whose lanes past the grid's x extent are at most an
+// eighth of the tiles' span, else the one that leaves the fewest idle.  Long
+// contiguous row segments per workgroup stream HBM best (511^3: 64-wide tiles
+// 0.655 ms, 512-wide 0.611 ms at the same slab depth).
+int residual_tile_x(int ox, int threads) {
   int best = 64;
   long long best_pad = -1;
-  for (int rx = 512; rx >= 64; rx >>= 1) {
+  for (int rx = std::min(512, threads / 2); rx >= 64; rx >>= 1) {
     const long long span = (long long)((ox + rx - 1) / rx) * rx, pad = span - ox;
     if (pad * 8 <= span) return rx;
     if (best_pad < 0 || pad < best_pad) {
@@ -506,7 +508,7 @@ int residual_tile_x(int ox) {
 // (64-plane slabs: 0.611 ms, 128: 0.601, 256: 0.580).
 int residual_slab_depth(int ox, int oy, int oz, int threads) {
   const long long kResident = 256LL * 2048 / threads;
-  const int rx = residual_tile_x(ox), ry = threads / rx;
+  const int rx = residual_tile_x(ox, threads), ry = threads / rx;
   const long long cols = (long long)((ox + rx - 1) / rx) * ((oy + ry - 1) / ry);
   const int smax = std::max(1, std::min(oz, 64));
   int best = 1;
@@ -528,7 +530,7 @@ int residual_slab_depth(int ox, int oy, int oz, int threads) {
 
 static dim3 residual_grid(int ox, int oy, int oz, int rz, bool planar, int threads) {
   if (planar) return dim3((ox + R2X - 1) / R2X, (oy + rz - 1) / rz, oz);
-  const int rx = residual_tile_x(ox), ry = threads / rx;
+  const int rx = residual_tile_x(ox, threads), ry = threads / rx;
   return dim3((ox + rx - 1) / rx, (oy + ry - 1) / ry, (oz + rz - 1) / rz);
 }
 
@@ -566,8 +568,11 @@ static void launch_nl_bc(const ResidualArgs& a, dim3 g, bool planar, hipStream_t
       hipLaunchKernelGGL((k_residual2d<NL, float, BC, MODE>), g, dim3(R2X), 0, st, a);
     return;
   }
-  switch (residual_tile_x(a.ox)) {
-    case 512: launch_3d<NL, BC, MODE, 512>(a, g, st); break;
+  constexpr int RT = residual_threads(NL, BC);
+  switch (residual_tile_x(a.ox, RT)) {
+    case 512:  // only when RT = 1024 (residual_tile_x keeps two tile rows)
+      if constexpr (RT >= 1024) launch_3d<NL, BC, MODE, 512>(a, g, st);
+      break;
     case 256: launch_3d<NL, BC, MODE, 256>(a, g, st); break;
     case 128: launch_3d<NL, BC, MODE, 128>(a, g, st); break;
     default: launch_3d<NL, BC, MODE, 64>(a, g, st); break;

@@ -154,13 +154,16 @@ def test_noalloc_residual_host_checks():
     it reads a pointer: spectral elements (their operator bands live in the
     workspace) and, as a guard, a launch beyond the fixed array.  Every grid
     the library accepts fits that array: the 3D residual launches at most
-    16384 workgroups (here: 8 x 2048 tiles of 512 x 2 columns, one slab) and
-    the 2D one 4096 at most, so null pointers meet the null check."""
+    16384 workgroups of 1024 threads (here: 8 x 2048 tiles of 512 x 2
+    columns, one slab) or 32768 of 512 threads (two components or Neumann
+    data: 16 x 2048 tiles of 256 x 2), the 2D one 4096 at most, so null
+    pointers meet the null check."""
     from paper_2502_03611_amd import Solver
     L = qn.lib()
     null = ctypes.c_void_p(None)
-    for shape in ((64, 4096, 3585), (4096, 4096)):
-        s = Solver(shape, "cubic", beta=1.0, workspace=False)
+    for shape, kind in (((64, 4096, 3585), "cubic"), ((64, 4096, 3841), "system"),
+                        ((4096, 4096), "cubic")):
+        s = Solver(shape, kind, beta=1.0, workspace=False)
         assert L.qn_residual_noalloc(s._ctx, null, null, null, null) == qn.QN_ERR_INVALID
         assert "null" in qn.last_error()
         s.close()

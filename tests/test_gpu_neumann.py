@@ -38,7 +38,7 @@ def solver(shape, **kw):
 
 @pytest.mark.parametrize("shape,lin", [((33, 47), 0.0), ((33, 47), 1.0), ((2, 5), 1.0),
                                        ((300, 2), 0.5), ((17, 20, 23), 1.0), ((2, 3, 4), 0.0),
-                                       ((5, 70, 3), 2.0)])
+                                       ((5, 70, 3), 2.0), ((4, 6, 500), 1.0)])
 def test_residual_parity(shape, lin):
     print(f"neumann residual {shape} lin {lin}", flush=True)
     u = synth.random_field((1,) + shape, 201)

@@ -50,6 +50,11 @@ def term_scale(kind, u):
     ("cubic", (37, 45, 70)), ("cubic", (1, 1, 1)), ("cubic", (5, 1, 9)), ("cubic", (63, 63)),
     ("cubic", (100, 37)), ("cubic", (1, 1)), ("system", (17, 19, 23)), ("system", (45, 70)),
     ("quasilinear", (33, 20, 65)), ("quasilinear", (50, 61)),
+    # 3D tile widths 256 and 512 (two tiles across x at 1000), 256-wide tiles
+    # of 512-thread workgroups (two components), and a column tile over 64
+    # thin z-slabs (slab boundaries every 3 planes)
+    ("cubic", (6, 5, 250)), ("quasilinear", (4, 7, 500)), ("cubic", (3, 4, 1000)),
+    ("system", (5, 6, 500)), ("quasilinear", (130, 3, 60)),
 ])
 def test_residual_parity(kind, shape):
     print(f"residual {kind} {shape}", flush=True)

@@ -34,7 +34,8 @@ def rel(a, b):
 
 CASES = [("neumann", (33, 47)), ("neumann", (2, 5)), ("neumann", (17, 20, 23)),
          ("neumann", (5, 70, 3)), ("dirichlet", (31, 45)), ("dirichlet", (1, 70)),
-         ("dirichlet", (19, 33, 40)), ("dirichlet", (3, 1, 65))]
+         ("dirichlet", (19, 33, 40)), ("dirichlet", (3, 1, 65)),
+         ("neumann", (3, 5, 480)), ("dirichlet", (4, 3, 510))]
 
 
 @pytest.mark.parametrize("bc,shape", CASES)
