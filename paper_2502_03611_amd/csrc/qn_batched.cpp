@@ -83,6 +83,8 @@ struct qnb_ctx_s {
   double g_rtol = -1.0;
   int g_max = -1, g_iters = 0;
   hipStream_t g_stream = nullptr;
+  int* h_done = nullptr;      // pinned host copies of every class's done flags
+  BState* h_state = nullptr;  // and per-instance states (count entries each)
   hipError_t sticky = hipSuccess;
   size_t elem() const { return prec == QN_PREC_FP64 ? 8 : 4; }
 };
@@ -734,31 +736,41 @@ qn_status qnb_iterate(qnb_ctx c, double* d_U, const double* d_F, double rtol, in
     c->g_iters = graph_iters;
     c->g_stream = c->stream;
   }
-  // Replay until every instance is done (at most max_iter + 1 residual evaluations each).
-  std::vector<int> done;
+  // Replay until every instance is done (at most max_iter + 1 residual
+  // evaluations each).  After each replay the done flags of all classes are
+  // copied into one pinned host array and read after a single synchronisation.
+  if (e == hipSuccess && !c->h_done) e = hipHostMalloc((void**)&c->h_done, c->count * sizeof(int));
   const int max_replays = (max_iter + 1 + graph_iters - 1) / graph_iters + 1;
   bool all_done = false;
   for (int r = 0; r < max_replays && !all_done && e == hipSuccess; ++r) {
     e = hipGraphLaunch(c->exec, c->stream);
-    all_done = true;
+    int pos = 0;
     for (auto& k : c->cls) {
-      done.resize(k.K);
       if (e == hipSuccess)
-        e = hipMemcpyAsync(done.data(), c->ws + k.off_done, k.K * sizeof(int), hipMemcpyDeviceToHost,
-                           c->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-      for (int v : done) all_done = all_done && v;
+        e = hipMemcpyAsync(c->h_done + pos, c->ws + k.off_done, k.K * sizeof(int),
+                           hipMemcpyDeviceToHost, c->stream);
+      pos += k.K;
     }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    all_done = e == hipSuccess;
+    for (int j = 0; j < pos && all_done; ++j) all_done = c->h_done[j] != 0;
   }
   if (e != hipSuccess) return hip_bad(c, e, "graph replay");
   qn_status worst = QN_OK;
-  std::vector<BState> hs;
+  if (!c->h_state) e = hipHostMalloc((void**)&c->h_state, c->count * sizeof(BState));
+  int pos = 0;
   for (auto& k : c->cls) {
-    hs.resize(k.K);
-    e = hipMemcpyAsync(hs.data(), c->ws + k.off_state, k.K * sizeof(BState), hipMemcpyDeviceToHost,
-                       c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return hip_bad(c, e, "read results");
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->h_state + pos, c->ws + k.off_state, k.K * sizeof(BState),
+                         hipMemcpyDeviceToHost, c->stream);
+    pos += k.K;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_bad(c, e, "read results");
+  pos = 0;
+  for (auto& k : c->cls) {
+    const BState* hs = c->h_state + pos;
+    pos += k.K;
     for (int j = 0; j < k.K; ++j) {
       const BState& s = hs[j];
       const qn_status st = !s.done ? QN_ERR_NOT_CONVERGED : (qn_status)s.status;
@@ -780,6 +792,8 @@ qn_status qnb_iterate(qnb_ctx c, double* d_U, const double* d_F, double rtol, in
 void qnb_destroy(qnb_ctx c) {
   if (!c) return;
   drop_graph(c);
+  if (c->h_done) (void)hipHostFree(c->h_done);
+  if (c->h_state) (void)hipHostFree(c->h_state);
   for (auto& k : c->cls) {
     if (k.s) hipStreamDestroy(k.s);
     if (k.ev) hipEventDestroy(k.ev);
