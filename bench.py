@@ -52,10 +52,9 @@ TRAFFIC = {"k_fold_right_fwd<double,64,128,0>": ("fold", 1.4640e+09, 1.0737e+09)
            "k_fold_left_inv<double,64,64,0>": ("fold", 1.3857e+09, 1.0716e+09),
            "k_fold_right_inv<double,64,64,EPI_SUB_DENSE,0>": ("fold", 2.5080e+09, 1.0761e+09),
            "k_residual<QUASILIN,double>": ("pointwise", 2.4003e+09, 1.0738e+09),
-           "k_gemm_right_bf<2,128,128,EPI_STORE>": ("bf16", 6.2856e+08, 5.3691e+08),
-           "k_gemm_left_bf<2,128,128,EPI_STORE>": ("bf16", 6.1749e+08, 5.3741e+08),
-           "k_gemm_left_bf<2,128,128,EPI_DIVIDE>": ("bf16", 6.5211e+08, 5.3788e+08),
-           "k_gemm_right_bf<2,128,128,EPI_SUB_DENSE>": ("bf16", 1.7389e+09, 1.0827e+09)}
+           "k_gemm_right_bf<2,128,128,EPI_STORE,false>": ("bf16", 6.2856e+08, 5.3691e+08),
+           "k_gemm_left_bf<2,128,128,EPI_STORE,false>": ("bf16", 6.1749e+08, 5.3741e+08),
+           "k_gemm_left_bf<2,128,128,EPI_DIVIDE,false>": ("bf16", 6.5211e+08, 5.3788e+08)}
 
 
 def traffic_if_current(kernel, n):
@@ -224,7 +223,8 @@ def mixed_steps(shape, U, F, steps, precisions=("fp32", "bf16x3")):
                 form = "k_gemm_right_bf" if kind in (0, 3) else "k_gemm_left_bf"
                 epi = ("EPI_SUB_DENSE" if kind == 3 else
                        "EPI_DIVIDE" if (kind == 1 and axis == 2) else "EPI_STORE")
-                tr = traffic_if_current(f"{form}<2,{tm},{tn},{epi}>", n)
+                fold = "true" if kind in (2, 3) else "false"  # the inverse products are folded
+                tr = traffic_if_current(f"{form}<2,{tm},{tn},{epi},{fold}>", n)
                 e = rec["kernels"].get(key)
                 if e is not None and tr is not None:
                     e["traffic"] = tr

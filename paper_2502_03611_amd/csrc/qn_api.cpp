@@ -253,6 +253,7 @@ struct FoldStep {
   int epi;
   EpiArgs ep;
   int m, k;             // dense split-bf16 steps: contraction length (P of the axis)
+  int nmir = 0;         // bf16x3 inverse steps: folded form over an axis of nmir points
 };
 
 // Dense split-bf16 step kinds (the folded ones are FK_*).
@@ -416,6 +417,9 @@ int dense_plan(qn_ctx c, const EpiArgs& ep, int epi_last, FoldStep* st) {
   const int rows = c->ncomp * pz * py;
   const long long yslab = (long long)py * px, zslab = (long long)pz * py * px;
   int ns = 0;
+  // bf16x3: the inverse products in the reflection-folded form (half the
+  // output tiles, each from the even- and odd-mode sums); bf16x6 dense
+  const bool fold_inv = c->prec == QN_PREC_BF16X3;
   auto add = [&](int kind, int axis, int kid, const void* in, void* out, int m, int ncols, int batch,
                  long long bstride, int epi, const EpiArgs& e) {
     FoldStep f{};
@@ -426,6 +430,7 @@ int dense_plan(qn_ctx c, const EpiArgs& ep, int epi_last, FoldStep* st) {
     f.out = out;
     f.m = m;
     f.k = px;
+    if (fold_inv && (kid == K_GEMM_YZ_INV || kid == K_GEMM_X_UPDATE)) f.nmir = c->n[axis];
     f.ncols = ncols;
     f.batch = batch;
     f.bstride = bstride;
@@ -459,12 +464,14 @@ int solve_plan(qn_ctx c, const EpiArgs& ep, int epi_last, FoldStep* st) {
 }
 
 hipError_t run_step(qn_ctx c, const FoldStep& f, const FoldTile& t) {
+  // folded split-bf16 inverse: output rows / columns [0, ceil(n / 2)) rounded up to the tile
+  auto fold = [&](int side) { return f.nmir ? ((f.nmir + 1) / 2 + side - 1) / side * side : 0; };
   if (f.kind == DK_RIGHT)
     return launch_gemm_right(c->prec, operands(c, f.axis), f.in, f.out, f.rows, f.k, f.epi, f.ep,
-                             t.tm, t.tn, c->stream);
+                             t.tm, t.tn, c->stream, fold(t.tn), f.nmir);
   if (f.kind == DK_LEFT)
     return launch_gemm_left(c->prec, operands(c, f.axis), f.in, f.out, f.m, f.ncols, f.batch,
-                            f.bstride, f.epi, f.ep, t.tm, t.tn, c->stream);
+                            f.bstride, f.epi, f.ep, t.tm, t.tn, c->stream, fold(t.tm), f.nmir);
   return launch_fold(f.kind, c->prec, fold_ops(c, f.axis), f.in, f.out, c->ax[f.axis], f.ncols,
                      f.batch, f.bstride, f.rows, f.epi, f.ep, t, c->stream);
 }

@@ -24,6 +24,15 @@
 // S is P x P (P = padded axis length, a multiple of 32), symmetric and zero
 // outside the N x N block, so padded rows and columns stay exactly zero.
 //
+// bf16x3 inverse products run folded: the eigenvectors are symmetric or
+// antisymmetric about the grid centre by mode parity, S[n-1-j][k] =
+// (-1)^k S[j][k], so one tile computes output j (< ceil(n/2)) from the sums
+// over the even modes (p) and the odd modes (q), taken by masking each
+// fragment's 8 consecutive modes to its even or odd entries, and writes
+// x[j] = p + q and x[n-1-j] = p - q: half the workgroups, each with twice the
+// matrix-core work per staged chunk for the same loads.  The forward products
+// contract over the spatial index and stay dense.
+//
 // Work decomposition: a 256-thread workgroup (four wave64s in a 2 x 2 grid)
 // owns a TM x TN output tile and walks K in chunks of 32 (one matrix-core
 // step), double-buffered in LDS with one barrier per chunk (the next chunk's
@@ -47,6 +56,16 @@ namespace {
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef unsigned u4v_t __attribute__((ext_vector_type(4)));
+
+// A fragment's 8 consecutive modes k0 + 8 g + e (k0 + 8 g even) kept at the
+// even modes (e even: the low half of each 32-bit word) or at the odd ones.
+__device__ __forceinline__ bf8_t even_modes(bf8_t v) {
+  return __builtin_bit_cast(bf8_t, __builtin_bit_cast(u4v_t, v) & 0x0000FFFFu);
+}
+__device__ __forceinline__ bf8_t odd_modes(bf8_t v) {
+  return __builtin_bit_cast(bf8_t, __builtin_bit_cast(u4v_t, v) & 0xFFFF0000u);
+}
 
 constexpr int BTK = 32;  // k per chunk = one matrix-core step
 constexpr int RBK = BTK * 2;  // bytes of the 32 k values of one row of a part
@@ -145,12 +164,14 @@ __device__ inline const __bf16* part(const GemmOperands& s, int i) {
 
 }  // namespace
 
-template <int NP, int TM, int TN, int EPI>
+template <int NP, int TM, int TN, int EPI, bool FOLD = false>
 __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const void* __restrict__ Bv,
                                                          void* __restrict__ Cv, int M, int ncols,
-                                                         int batch, long long bstride, EpiArgs ep) {
+                                                         int batch, long long bstride, EpiArgs ep,
+                                                         int mh, int nmir) {
   // NP = 2: B and C are bf16 part planes; NP = 3: FP32 tensors
   constexpr bool PS = NP == 2;
+  static_assert(!FOLD || (NP == 2 && EPI == EPI_STORE), "folded: the bf16x3 inverse products");
   const float* B = (const float*)Bv;
   float* C = (float*)Cv;
   const long long plane = (long long)batch * bstride;
@@ -161,7 +182,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const v
   __shared__ __attribute__((aligned(16))) char As[NP][2][TM * RBK];
   __shared__ __attribute__((aligned(16))) char Bs[NP][2][BTK * TN * 2];
 
-  const int MT = M / TM, NT = ncols / TN;
+  // FOLD: output rows m < mh only (mh: ceil(nmir / 2) rounded up to TM), each
+  // giving rows m and nmir - 1 - m
+  const int MT = (FOLD ? mh : M) / TM, NT = ncols / TN;
   const int t = xcd_tile(blockIdx.x, batch * MT * NT);
   const int mt = t % MT, rest = t / MT, nt = rest % NT, b = rest / NT;
   const int inst = b % ep.inst_mod;
@@ -171,11 +194,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const v
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
 
-  f4_t acc[BM][BN];
+  f4_t acc[BM][BN], accq[BM][BN];  // accq: the odd modes' sums (FOLD)
 #pragma unroll
   for (int i = 0; i < BM; ++i)
 #pragma unroll
-    for (int j = 0; j < BN; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
+    for (int j = 0; j < BN; ++j) acc[i][j] = accq[i][j] = f4_t{0, 0, 0, 0};
 
   const int g = lane >> 4, li = lane & 15;
   // all matrix-core fragments of chunk buf: a[i][part], bj[j][part]
@@ -197,10 +220,29 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const v
     }
   };
   auto mma = [&](const bf8_t (&a)[BM][NP], const bf8_t (&bj)[BN][NP]) {
+    if constexpr (FOLD) {
+      // S[n-1-m][k] = (-1)^k S[m][k]: the even and odd modes' sums of row m
+      // give rows m (p + q) and n-1-m (p - q)
 #pragma unroll
-    for (int j = 0; j < BN; ++j)
+      for (int i = 0; i < BM; ++i) {
+        bf8_t ae[NP], ao[NP];
 #pragma unroll
-      for (int i = 0; i < BM; ++i) acc[i][j] = mfma_split<NP>(a[i], bj[j], acc[i][j]);
+        for (int q = 0; q < NP; ++q) {
+          ae[q] = even_modes(a[i][q]);
+          ao[q] = odd_modes(a[i][q]);
+        }
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          acc[i][j] = mfma_split<NP>(ae, bj[j], acc[i][j]);
+          accq[i][j] = mfma_split<NP>(ao, bj[j], accq[i][j]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < BN; ++j)
+#pragma unroll
+        for (int i = 0; i < BM; ++i) acc[i][j] = mfma_split<NP>(a[i], bj[j], acc[i][j]);
+    }
   };
   const int nk = M / BTK;
   if constexpr (PS) {
@@ -341,6 +383,23 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const v
           put((long long)m * ncols + n, (float)quot((double)acc[i][j][q], scale * (lm + cn[j]) + beta));
         }
       }
+  } else if constexpr (FOLD) {
+    const int half = (nmir + 1) / 2;
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
+        if (m >= half) continue;
+        const int mm = nmir - 1 - m;
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          const int n = n0 + wn + 16 * j + (lane & 15);
+          const float p = acc[i][j][q], qq = accq[i][j][q];
+          put((long long)m * ncols + n, p + qq);
+          if (mm != m) put((long long)mm * ncols + n, p - qq);
+        }
+      }
   } else {
 #pragma unroll
     for (int i = 0; i < BM; ++i)
@@ -354,12 +413,14 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const v
   }
 }
 
-template <int NP, int TM, int TN, int EPI>
+template <int NP, int TM, int TN, int EPI, bool FOLD = false>
 __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const void* __restrict__ Av,
                                                           GemmOperands S, void* __restrict__ Cv,
-                                                          int rows, int K, EpiArgs ep) {
+                                                          int rows, int K, EpiArgs ep, int nh,
+                                                          int nmir) {
   // NP = 2: A and C (with EPI_STORE) are bf16 part planes; NP = 3: FP32 tensors
   constexpr bool PS = NP == 2;
+  static_assert(!FOLD || NP == 2, "folded: the bf16x3 inverse products");
   const float* A = (const float*)Av;
   float* C = (float*)Cv;
   const long long plane = (long long)rows * K;
@@ -370,7 +431,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const void* __restrict
   __shared__ __attribute__((aligned(16))) char As[NP][2][TM * RBK];
   __shared__ __attribute__((aligned(16))) char Bs[NP][2][TN * RBK];
 
-  const int MT = rows / TM, NT = K / TN;
+  // FOLD: output columns n < nh only (nh: ceil(nmir / 2) rounded up to TN),
+  // each giving columns n and nmir - 1 - n
+  const int MT = rows / TM, NT = (FOLD ? nh : K) / TN;
   const int t = xcd_tile(blockIdx.x, MT * NT);
   const int nt = t % NT, mt = t / NT;
   const int r0 = mt * TM, n0 = nt * TN;
@@ -378,11 +441,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const void* __restrict
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
 
-  f4_t acc[BM][BN];
+  f4_t acc[BM][BN], accq[BM][BN];  // accq: the odd modes' sums (FOLD)
 #pragma unroll
   for (int i = 0; i < BM; ++i)
 #pragma unroll
-    for (int j = 0; j < BN; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
+    for (int j = 0; j < BN; ++j) acc[i][j] = accq[i][j] = f4_t{0, 0, 0, 0};
 
   auto read_frags = [&](int buf, bf8_t (&a)[BM][NP], bf8_t (&bj)[BN][NP]) {
 #pragma unroll
@@ -397,10 +460,29 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const void* __restrict
         bj[j][q] = *reinterpret_cast<const bf8_t*>(&Bs[q][buf][kswz(wn + 16 * j + (lane & 15), 16 * (lane >> 4))]);
   };
   auto mma = [&](const bf8_t (&a)[BM][NP], const bf8_t (&bj)[BN][NP]) {
+    if constexpr (FOLD) {
+      // S[n-1-j][k] = (-1)^k S[j][k]: the even and odd modes' sums of column
+      // j give columns j (p + q) and n-1-j (p - q)
 #pragma unroll
-    for (int j = 0; j < BN; ++j)
+      for (int i = 0; i < BM; ++i) {
+        bf8_t ae[NP], ao[NP];
 #pragma unroll
-      for (int i = 0; i < BM; ++i) acc[i][j] = mfma_split<NP>(a[i], bj[j], acc[i][j]);
+        for (int q = 0; q < NP; ++q) {
+          ae[q] = even_modes(a[i][q]);
+          ao[q] = odd_modes(a[i][q]);
+        }
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          acc[i][j] = mfma_split<NP>(ae, bj[j], acc[i][j]);
+          accq[i][j] = mfma_split<NP>(ao, bj[j], accq[i][j]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < BN; ++j)
+#pragma unroll
+        for (int i = 0; i < BM; ++i) acc[i][j] = mfma_split<NP>(a[i], bj[j], acc[i][j]);
+    }
   };
   const int nk = K / BTK;
   if constexpr (PS) {
@@ -520,8 +602,45 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const void* __restrict
         row_ok[q] = y < ep.ny && z < ep.nz;
       }
     }
-    double old[4][BN];
     const double st = ep.step != 0 ? ep.step : 1.0;  // U -= step dU
+    if constexpr (FOLD) {
+      const int half = (nmir + 1) / 2;
+      double old1[4][BN], old2[4][BN];
+      if (EPI == EPI_SUB_DENSE) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int j = 0; j < BN; ++j) {
+            const int n = n0 + wn + 16 * j + (lane & 15), nm = nmir - 1 - n;
+            const bool in = row_ok[q] && n < half;
+            old1[q][j] = in ? ep.dense[base[q] + n] : 0.0;
+            old2[q][j] = (in && nm != n) ? ep.dense[base[q] + nm] : 0.0;
+          }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (!row_ok[q]) continue;
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          const int n = n0 + wn + 16 * j + (lane & 15), nm = nmir - 1 - n;
+          if (n >= half) continue;
+          const float p = acc[i][j][q], qq = accq[i][j][q];
+          const float v1 = p + qq, v2 = p - qq;
+          if (EPI == EPI_STORE) {
+            put_pair((__bf16*)Cv, plane, base[q] + n, v1);
+            if (nm != n) put_pair((__bf16*)Cv, plane, base[q] + nm, v2);
+          } else if (EPI == EPI_SUB_DENSE) {
+            ep.dense[base[q] + n] = old1[q][j] - st * (double)v1;
+            if (nm != n) ep.dense[base[q] + nm] = old2[q][j] - st * (double)v2;
+          } else {
+            ep.dense[base[q] + n] = (double)v1;
+            if (nm != n) ep.dense[base[q] + nm] = (double)v2;
+          }
+        }
+      }
+      continue;
+    }
+    double old[4][BN];
     if (EPI == EPI_SUB_DENSE) {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -556,37 +675,64 @@ namespace {
 
 int parts_of(int prec) { return prec == 3 ? 3 : 2; }  // 3: bf16x6, else bf16x3
 
+// fold > 0: the reflection-folded inverse product (bf16x3 only), output rows
+// (form L) or columns (form R) [0, fold) of the axis of length nmir, fold a
+// multiple of the tile side.
 template <int NP, int TM, int TN>
 hipError_t left_tile(const GemmOperands& s, const void* B, void* C, int M, int ncols, int batch,
-                     long long bstride, int epi, const EpiArgs& ep, hipStream_t st) {
+                     long long bstride, int epi, const EpiArgs& ep, hipStream_t st, int fold,
+                     int nmir) {
+  if (fold > 0) {
+    if constexpr (NP == 2) {
+      if (epi != EPI_STORE || fold % TM != 0 || fold > M || 2 * fold < nmir) return hipErrorInvalidValue;
+      const unsigned g = (unsigned)((long long)batch * (fold / TM) * (ncols / TN));
+      hipLaunchKernelGGL((k_gemm_left_bf<NP, TM, TN, EPI_STORE, true>), dim3(g), dim3(256), 0, st, s,
+                         B, C, M, ncols, batch, bstride, ep, fold, nmir);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
   const unsigned g = (unsigned)((long long)batch * (M / TM) * (ncols / TN));
   if (epi == EPI_DIVIDE)
     hipLaunchKernelGGL((k_gemm_left_bf<NP, TM, TN, EPI_DIVIDE>), dim3(g), dim3(256), 0, st, s, B, C,
-                       M, ncols, batch, bstride, ep);
+                       M, ncols, batch, bstride, ep, 0, 0);
   else
     hipLaunchKernelGGL((k_gemm_left_bf<NP, TM, TN, EPI_STORE>), dim3(g), dim3(256), 0, st, s, B, C,
-                       M, ncols, batch, bstride, ep);
+                       M, ncols, batch, bstride, ep, 0, 0);
+  return hipGetLastError();
+}
+
+template <int NP, int TM, int TN, bool FOLD>
+hipError_t right_launch(const GemmOperands& s, const void* A, void* C, int rows, int K, int epi,
+                        const EpiArgs& ep, hipStream_t st, int nout, int nmir) {
+  const unsigned g = (unsigned)((long long)(rows / TM) * (nout / TN));
+  switch (epi) {
+    case EPI_SUB_DENSE:
+      hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_SUB_DENSE, FOLD>), dim3(g), dim3(256), 0,
+                         st, A, s, C, rows, K, ep, nout, nmir);
+      break;
+    case EPI_STORE_DENSE:
+      hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_STORE_DENSE, FOLD>), dim3(g), dim3(256), 0,
+                         st, A, s, C, rows, K, ep, nout, nmir);
+      break;
+    default:
+      hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_STORE, FOLD>), dim3(g), dim3(256), 0, st,
+                         A, s, C, rows, K, ep, nout, nmir);
+  }
   return hipGetLastError();
 }
 
 template <int NP, int TM, int TN>
 hipError_t right_tile(const GemmOperands& s, const void* A, void* C, int rows, int K, int epi,
-                      const EpiArgs& ep, hipStream_t st) {
-  const unsigned g = (unsigned)((long long)(rows / TM) * (K / TN));
-  switch (epi) {
-    case EPI_SUB_DENSE:
-      hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_SUB_DENSE>), dim3(g), dim3(256), 0, st,
-                         A, s, C, rows, K, ep);
-      break;
-    case EPI_STORE_DENSE:
-      hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_STORE_DENSE>), dim3(g), dim3(256), 0, st,
-                         A, s, C, rows, K, ep);
-      break;
-    default:
-      hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_STORE>), dim3(g), dim3(256), 0, st, A,
-                         s, C, rows, K, ep);
+                      const EpiArgs& ep, hipStream_t st, int fold, int nmir) {
+  if (fold > 0) {
+    if constexpr (NP == 2) {
+      if (fold % TN != 0 || fold > K || 2 * fold < nmir) return hipErrorInvalidValue;
+      return right_launch<NP, TM, TN, true>(s, A, C, rows, K, epi, ep, st, fold, nmir);
+    }
+    return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+  return right_launch<NP, TM, TN, false>(s, A, C, rows, K, epi, ep, st, K, 0);
 }
 
 // Instantiated tiles: bf16x3 every side in {32, 64, 128}; bf16x6 (three parts
@@ -616,13 +762,14 @@ int gemm_bf_max_tile(int prec) { return parts_of(prec) == 3 ? 64 : 128; }
 
 hipError_t launch_gemm_left(int prec, const GemmOperands& s, const void* B, void* C, int M,
                             int ncols, int batch, long long bstride, int epi, const EpiArgs& ep,
-                            int tm, int tn, hipStream_t st) {
-  QN_BF_TILES(left_tile, parts_of(prec), s, B, C, M, ncols, batch, bstride, epi, ep, st)
+                            int tm, int tn, hipStream_t st, int fold, int nmir) {
+  QN_BF_TILES(left_tile, parts_of(prec), s, B, C, M, ncols, batch, bstride, epi, ep, st, fold, nmir)
 }
 
 hipError_t launch_gemm_right(int prec, const GemmOperands& s, const void* A, void* C, int rows,
-                             int K, int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st) {
-  QN_BF_TILES(right_tile, parts_of(prec), s, A, C, rows, K, epi, ep, st)
+                             int K, int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st,
+                             int fold, int nmir) {
+  QN_BF_TILES(right_tile, parts_of(prec), s, A, C, rows, K, epi, ep, st, fold, nmir)
 }
 
 #undef QN_BF_TILES

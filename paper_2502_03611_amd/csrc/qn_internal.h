@@ -105,11 +105,18 @@ struct GemmOperands {
 // Largest tile side instantiated for the precision.
 int gemm_bf_max_tile(int prec);
 
+// fold > 0 (bf16x3 inverse products only): the reflection-folded form, which
+// computes output rows (form L) or columns (form R) m < fold and their mirrors
+// nmir - 1 - m from the even- and odd-mode sums (the eigenvectors are
+// symmetric or antisymmetric about the centre by mode parity); fold is
+// ceil(nmir / 2) rounded up to the tile side.  The rows or columns from
+// nmir up to the padded extent are left unwritten.
 hipError_t launch_gemm_left(int prec, const GemmOperands& s, const void* B, void* C, int M,
                             int ncols, int batch, long long bstride, int epi, const EpiArgs& ep,
-                            int tm, int tn, hipStream_t st);
+                            int tm, int tn, hipStream_t st, int fold = 0, int nmir = 0);
 hipError_t launch_gemm_right(int prec, const GemmOperands& s, const void* A, void* C, int rows,
-                             int K, int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st);
+                             int K, int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st,
+                             int fold = 0, int nmir = 0);
 
 // Reflection-folded mode products (qn_gemm_fold.hip).  Along a folded axis of
 // n interior points, h = n / 2, odd = n % 2, and the spectral index is stored
