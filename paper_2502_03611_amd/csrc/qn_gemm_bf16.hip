@@ -58,6 +58,15 @@ typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef unsigned u4v_t __attribute__((ext_vector_type(4)));
 
+// x / d in FP32 for d > 0: the hardware reciprocal refined by one Newton
+// step, then one residual correction of the quotient (about an FP32 ulp).
+__device__ __forceinline__ float quotf(float x, float d) {
+  float r = __builtin_amdgcn_rcpf(d);
+  r = __builtin_fmaf(__builtin_fmaf(-d, r, 1.0f), r, r);
+  const float q = x * r;
+  return __builtin_fmaf(__builtin_fmaf(-d, q, x), r, q);
+}
+
 // A fragment's 8 consecutive modes k0 + 8 g + e (k0 + 8 g even) kept at the
 // even modes (e even: the low half of each 32-bit word) or at the odd ones.
 __device__ __forceinline__ bf8_t even_modes(bf8_t v) {
@@ -361,7 +370,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const v
   };
   if (EPI == EPI_DIVIDE) {
     // denominator scale (lam_m + lam_x + lam_y) + beta: the column part once
-    // per column block, the row part once per row, one FP64 divide per entry
+    // per column block, the row part once per row, one divide per entry
     const double* cf = ep.coef + (long long)inst * ep.coef_stride;
     const double scale = cf[0], beta = cf[1];
     double cn[BN];
@@ -371,6 +380,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const v
       const int ny_ = n / ep.px;
       cn[j] = ep.lamX[n - ny_ * ep.px] + (ep.lamY ? ep.lamY[ny_] : 0.0);
     }
+    // bf16x3 rounds the quotient to FP32 and keeps it as two bf16 parts (a
+    // 2^-16 relative split): the denominator and the quotient in FP32 lose
+    // nothing at that precision and cost half the FP64 operations
+    const float sf = (float)scale, bf = (float)beta;
 #pragma unroll
     for (int i = 0; i < BM; ++i)
 #pragma unroll
@@ -380,7 +393,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const v
 #pragma unroll
         for (int j = 0; j < BN; ++j) {
           const int n = n0 + wn + 16 * j + (lane & 15);
-          put((long long)m * ncols + n, (float)quot((double)acc[i][j][q], scale * (lm + cn[j]) + beta));
+          if constexpr (NP == 2)
+            put((long long)m * ncols + n,
+                quotf(acc[i][j][q], __builtin_fmaf(sf, (float)(lm + cn[j]), bf)));
+          else
+            put((long long)m * ncols + n, (float)quot((double)acc[i][j][q], scale * (lm + cn[j]) + beta));
         }
       }
   } else if constexpr (FOLD) {
