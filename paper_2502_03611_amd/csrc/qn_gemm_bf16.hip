@@ -58,15 +58,6 @@ typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef unsigned u4v_t __attribute__((ext_vector_type(4)));
 
-// x / d in FP32 for d > 0: the hardware reciprocal refined by one Newton
-// step, then one residual correction of the quotient (about an FP32 ulp).
-__device__ __forceinline__ float quotf(float x, float d) {
-  float r = __builtin_amdgcn_rcpf(d);
-  r = __builtin_fmaf(__builtin_fmaf(-d, r, 1.0f), r, r);
-  const float q = x * r;
-  return __builtin_fmaf(__builtin_fmaf(-d, q, x), r, q);
-}
-
 // A fragment's 8 consecutive modes k0 + 8 g + e (k0 + 8 g even) kept at the
 // even modes (e even: the low half of each 32-bit word) or at the odd ones.
 __device__ __forceinline__ bf8_t even_modes(bf8_t v) {

@@ -52,6 +52,17 @@ __device__ __forceinline__ int swz(int row, int col_bytes) {
   return row * RB + ((((col_bytes >> 4) ^ t) << 4) | (col_bytes & 15));
 }
 
+// The spectral divide x / (scale * lam + beta) of a product result stored as
+// T: FP64 in FP64; FP32 results take the denominator and the quotient in FP32
+// (the stored value is rounded to FP32 anyway).
+template <typename T>
+__device__ __forceinline__ T divide_to(T x, double scale, double lam, double beta) {
+  if constexpr (sizeof(T) == 4)
+    return quotf(x, __builtin_fmaf((float)scale, (float)lam, (float)beta));
+  else
+    return quot(x, scale * lam + beta);
+}
+
 // ------------------------------------------------------------------ form L
 
 // Forward, contraction over the slab rows (the folded axis):
@@ -188,7 +199,7 @@ __global__ __launch_bounds__(256, 2) void k_fold_left_fwd(const T* __restrict__ 
 #pragma unroll
         for (int j = 0; j < BN; ++j) {
           const int n = n0 + wn + 16 * j + (lane & 15);
-          Cb[(long long)m * ncols + n] = (T)quot((double)acc[i][j][q], scale * (lm + cn[j]) + beta);
+          Cb[(long long)m * ncols + n] = divide_to<T>(acc[i][j][q], scale, lm + cn[j], beta);
         }
       }
   } else {
@@ -360,9 +371,9 @@ __global__ __launch_bounds__(256, 2) void k_fold_left_fwd2(const T* __restrict__
       for (int j = 0; j < BN; ++j) {
         const int n = n0 + wn + 16 * j + (lane & 15);
         if (EPI == EPI_DIVIDE) {
-          Cb[(long long)m * ncols + n] = (T)quot((double)acce[i][j][q], scale * (le + cn[j]) + beta);
+          Cb[(long long)m * ncols + n] = divide_to<T>(acce[i][j][q], scale, le + cn[j], beta);
           Cb[(long long)(bk + m) * ncols + n] =
-              (T)quot((double)acco[i][j][q], scale * (lo + cn[j]) + beta);
+              divide_to<T>(acco[i][j][q], scale, lo + cn[j], beta);
         } else {
           Cb[(long long)m * ncols + n] = acce[i][j][q];
           Cb[(long long)(bk + m) * ncols + n] = acco[i][j][q];

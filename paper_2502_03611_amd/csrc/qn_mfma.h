@@ -43,6 +43,16 @@ __device__ __forceinline__ double quot(double x, double d) {
   return __builtin_fma(__builtin_fma(-d, q, x), r, q);
 }
 
+// x / d in FP32 for d > 0: the hardware reciprocal refined by one Newton
+// step, then one residual correction of the quotient (about an FP32 ulp).
+// For divides whose result is stored in FP32 (or split from it).
+__device__ __forceinline__ float quotf(float x, float d) {
+  float r = __builtin_amdgcn_rcpf(d);
+  r = __builtin_fmaf(__builtin_fmaf(-d, r, 1.0f), r, r);
+  const float q = x * r;
+  return __builtin_fmaf(__builtin_fmaf(-d, q, x), r, q);
+}
+
 // Tile index for workgroup w of `total`: workgroups are dealt to the 8 XCDs
 // round-robin (XCD w % 8), so XCD j is given the contiguous range of
 // total / 8 (+1 for j < total % 8) tiles starting at j * (total / 8) +
