@@ -43,18 +43,20 @@ PEAK_HBM_GBS = 8000.0
 # 511^3, the read counter scaled x2.0 and the write counter x1.0 (both
 # calibrated on a plain 1 GiB device copy), keyed by kernel.  Each figure is
 # valid only while the source file it was taken on is unchanged.
-TRAFFIC_SOURCES = {"fold": ("paper_2502_03611_amd/csrc/qn_gemm_fold.hip", "307100cb86d46acb"),
-                   "pointwise": ("paper_2502_03611_amd/csrc/qn_pointwise.hip", "358a3e7f44ecd7b2"),
-                   "bf16": ("paper_2502_03611_amd/csrc/qn_gemm_bf16.hip", "c6bc12d520638ac9")}
-TRAFFIC = {"k_fold_right_fwd<double,64,128,0>": ("fold", 1.4640e+09, 1.0737e+09),
-           "k_fold_left_fwd2<double,64,64,EPI_STORE,0>": ("fold", 1.4555e+09, 1.0737e+09),
-           "k_fold_left_fwd<double,128,128,EPI_DIVIDE,0>": ("fold", 1.2594e+09, 1.0737e+09),
-           "k_fold_left_inv<double,64,64,0>": ("fold", 1.3857e+09, 1.0716e+09),
-           "k_fold_right_inv<double,64,64,EPI_SUB_DENSE,0>": ("fold", 2.5080e+09, 1.0761e+09),
-           "k_residual<QUASILIN,double>": ("pointwise", 2.4003e+09, 1.0738e+09),
-           "k_gemm_right_bf<2,128,128,EPI_STORE,false>": ("bf16", 6.2856e+08, 5.3691e+08),
-           "k_gemm_left_bf<2,128,128,EPI_STORE,false>": ("bf16", 6.1749e+08, 5.3741e+08),
-           "k_gemm_left_bf<2,128,128,EPI_DIVIDE,false>": ("bf16", 6.5211e+08, 5.3788e+08)}
+TRAFFIC_SOURCES = {"fold": ("paper_2502_03611_amd/csrc/qn_gemm_fold.hip", "0bf9f6298fde0112"),
+                   "pointwise": ("paper_2502_03611_amd/csrc/qn_pointwise.hip", "7db57d6c0fb14e33"),
+                   "bf16": ("paper_2502_03611_amd/csrc/qn_gemm_bf16.hip", "85a4d2113235acec")}
+TRAFFIC = {"k_fold_right_fwd<double,64,128,0>": ("fold", 1.4639e+09, 1.0737e+09),
+           "k_fold_left_fwd2<double,64,64,EPI_STORE,0>": ("fold", 1.4554e+09, 1.0737e+09),
+           "k_fold_left_fwd<double,128,128,EPI_DIVIDE,0>": ("fold", 1.2619e+09, 1.0737e+09),
+           "k_fold_left_inv<double,64,64,0>": ("fold", 1.3847e+09, 1.0716e+09),
+           "k_fold_right_inv<double,64,64,EPI_SUB_DENSE,0>": ("fold", 2.5118e+09, 1.0763e+09),
+           "k_residual<QUASILIN,double>": ("pointwise", 2.4113e+09, 1.0738e+09),
+           "k_gemm_right_bf<2,128,128,EPI_STORE,false>": ("bf16", 6.2776e+08, 5.3691e+08),
+           "k_gemm_left_bf<2,128,128,EPI_STORE,false>": ("bf16", 6.1800e+08, 5.3689e+08),
+           "k_gemm_left_bf<2,128,128,EPI_DIVIDE,false>": ("bf16", 6.2273e+08, 5.3822e+08),
+           "k_gemm_left_bf<2,128,128,EPI_STORE,true>": ("bf16", 5.7146e+08, 5.3676e+08),
+           "k_gemm_right_bf<2,128,128,EPI_SUB_DENSE,true>": ("bf16", 1.6666e+09, 1.0955e+09)}
 
 
 def traffic_if_current(kernel, n):
