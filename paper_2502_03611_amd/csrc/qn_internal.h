@@ -199,7 +199,7 @@ hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t 
 // Spectral element residual (qn_sem.hip): same outputs and partials as
 // launch_residual for the cubic problem; SEM_ROWS rows of 256 nodes per workgroup.
 constexpr int SEM_ROWS = 8;
-constexpr int SEM_RZ = 32;  // 3D: z-planes per workgroup
+constexpr int SEM_RZ = 64;  // 3D: z-planes per workgroup
 hipError_t launch_sem_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t st);
 int sem_residual_blocks(int dim, int ox, int oy, int oz);  // workgroups = partial slots
 // Eigenproblem finalizes (one workgroup each; return at once when *stop != 0).
