@@ -112,6 +112,12 @@ struct qn_ctx_s {
   FoldTile tile[6] = {};  // per mode-product launch of the folded solve (after qn_autotune)
   bool tuned = false;
   std::vector<double> hS[3], hlam[3];  // dense S or folded FeT|FoT|Fe|Fo; lam (split if folded)
+  // 3D split-bf16 solves with folded forward y and z products: half extents
+  // of the folded layouts and the forward operands (bf16 parts) of y and z
+  bool fwdfold = false;
+  int hp[3] = {0, 0, 0};
+  std::vector<double> hSf[3];
+  size_t off_Sf[3][2] = {};
   // workspace layout (byte offsets)
   size_t off_S[3] = {0, 0, 0}, off_Slo[3] = {0, 0, 0}, off_Slo2[3] = {0, 0, 0}, off_lam[3] = {0, 0, 0};
   size_t off_W1 = 0, off_W2 = 0, off_part = 0, off_scal = 0, off_coef = 0, off_cscale = 0,
@@ -254,15 +260,17 @@ struct FoldStep {
   EpiArgs ep;
   int m, k;             // dense split-bf16 steps: contraction length (P of the axis)
   int nmir = 0;         // bf16x3 inverse steps: folded form over an axis of nmir points
+  BfSplit sp{};         // 3D bf16x3 folded forward steps (mode 0: none)
+  int sop = 0;          // operands: 0 S, 1 the folded forward Sf
 };
 
 // Dense split-bf16 step kinds (the folded ones are FK_*).
 enum DenseKind { DK_RIGHT = 10, DK_LEFT = 11 };
 
-GemmOperands operands(qn_ctx c, int axis) {
+GemmOperands operands(qn_ctx c, int axis, int sop = 0) {
   GemmOperands g{};
-  g.Shi = c->ws + c->off_S[axis];
-  g.Slo = c->ws + c->off_Slo[axis];
+  g.Shi = c->ws + (sop == 1 ? c->off_Sf[axis][0] : c->off_S[axis]);
+  g.Slo = c->ws + (sop == 1 ? c->off_Sf[axis][1] : c->off_Slo[axis]);
   g.Slo2 = c->ws + c->off_Slo2[axis];
   return g;
 }
@@ -439,6 +447,29 @@ int dense_plan(qn_ctx c, const EpiArgs& ep, int epi_last, FoldStep* st) {
     f.ep = e;
     st[ns++] = f;
   };
+  if (c->fwdfold) {
+    // folded forward y and z products: the x product writes its output folded
+    // along z, the z product reads it and writes its output folded along y,
+    // the y product reads that and divides; the inverse products are the
+    // folded ones below
+    const int hy = c->hp[1], hz = c->hp[2];
+    add(DK_RIGHT, 0, K_GEMM_X, W1, W2, 0, 0, 0, 0, EPI_STORE, ep);
+    st[ns - 1].sp = BfSplit{3, 0, hz};
+    add(DK_LEFT, 2, K_GEMM_YZ, W2, W1, pz, (int)yslab, c->ncomp, zslab, EPI_STORE, ep);
+    st[ns - 1].sp = BfSplit{2, hz, hy};
+    st[ns - 1].sop = 1;
+    EpiArgs ed = ep;
+    ed.lamM = c->at<double>(c->off_lam[1]);
+    ed.lamY = nullptr;
+    ed.lamB = c->at<double>(c->off_lam[2]);
+    add(DK_LEFT, 1, K_GEMM_DIVIDE, W1, W2, py, px, c->ncomp * pz, yslab, EPI_DIVIDE, ed);
+    st[ns - 1].sp = BfSplit{1, hy, 0};
+    st[ns - 1].sop = 1;
+    add(DK_LEFT, 2, K_GEMM_YZ_INV, W2, W1, pz, (int)yslab, c->ncomp, zslab, EPI_STORE, ep);
+    add(DK_LEFT, 1, K_GEMM_YZ_INV, W1, W2, py, px, c->ncomp * pz, yslab, EPI_STORE, ep);
+    add(DK_RIGHT, 0, K_GEMM_X_UPDATE, W2, W1, 0, 0, 0, 0, epi_last, ep);
+    return ns;
+  }
   add(DK_RIGHT, 0, K_GEMM_X, W1, W2, 0, 0, 0, 0, EPI_STORE, ep);
   if (c->dim == 2) {
     EpiArgs ed = ep;
@@ -466,12 +497,13 @@ int solve_plan(qn_ctx c, const EpiArgs& ep, int epi_last, FoldStep* st) {
 hipError_t run_step(qn_ctx c, const FoldStep& f, const FoldTile& t) {
   // folded split-bf16 inverse: output rows / columns [0, ceil(n / 2)) rounded up to the tile
   auto fold = [&](int side) { return f.nmir ? ((f.nmir + 1) / 2 + side - 1) / side * side : 0; };
+  const BfSplit* sp = f.sp.mode ? &f.sp : nullptr;
   if (f.kind == DK_RIGHT)
-    return launch_gemm_right(c->prec, operands(c, f.axis), f.in, f.out, f.rows, f.k, f.epi, f.ep,
-                             t.tm, t.tn, c->stream, fold(t.tn), f.nmir);
+    return launch_gemm_right(c->prec, operands(c, f.axis, f.sop), f.in, f.out, f.rows, f.k, f.epi,
+                             f.ep, t.tm, t.tn, c->stream, fold(t.tn), f.nmir, sp);
   if (f.kind == DK_LEFT)
-    return launch_gemm_left(c->prec, operands(c, f.axis), f.in, f.out, f.m, f.ncols, f.batch,
-                            f.bstride, f.epi, f.ep, t.tm, t.tn, c->stream, fold(t.tm), f.nmir);
+    return launch_gemm_left(c->prec, operands(c, f.axis, f.sop), f.in, f.out, f.m, f.ncols, f.batch,
+                            f.bstride, f.epi, f.ep, t.tm, t.tn, c->stream, fold(t.tm), f.nmir, sp);
   return launch_fold(f.kind, c->prec, fold_ops(c, f.axis), f.in, f.out, c->ax[f.axis], f.ncols,
                      f.batch, f.bstride, f.rows, f.epi, f.ep, t, c->stream);
 }
@@ -480,6 +512,15 @@ hipError_t run_step(qn_ctx c, const FoldStep& f, const FoldTile& t) {
 void dense_extents(const FoldStep& f, long long* mext, long long* next) {
   *mext = f.kind == DK_RIGHT ? f.rows : f.m;
   *next = f.kind == DK_RIGHT ? f.k : f.ncols;
+  if (f.sp.mode == 3) *mext = 2LL * f.ep.py;  // half tiles of TM / 2 rows per plane
+  if (f.sp.mode == 2 || (f.sp.mode == 1 && !f.nmir)) *mext = f.sp.K;  // tiles in one half
+  if (f.sp.mode == 2) *next = 2LL * f.ep.px;  // half tiles of TN / 2 x values per row
+}
+
+// Smallest tile sides of a dense launch: the folded-output forms pair the
+// halves of each wave's fragment blocks.
+bool dense_tile_ok(const FoldStep& f, int tm, int tn) {
+  return !(f.sp.mode == 3 && tm < 64) && !(f.sp.mode == 2 && tn < 64);
 }
 
 // Every instantiated tile that fits launch f (at most 16).
@@ -491,7 +532,7 @@ int step_candidates(qn_ctx c, const FoldStep& f, FoldTile* out) {
     const int cap = gemm_bf_max_tile(c->prec);
     for (int tm = 32; tm <= cap; tm *= 2)
       for (int tn = 32; tn <= cap; tn *= 2)
-        if (mext % tm == 0 && next % tn == 0) out[n++] = FoldTile{tm, tn, 0, 0};
+        if (mext % tm == 0 && next % tn == 0 && dense_tile_ok(f, tm, tn)) out[n++] = FoldTile{tm, tn, 0, 0};
     return n;
   }
   const FoldTile* list;
@@ -753,6 +794,14 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
       for (double& l : c->hlam[a]) l /= length * length;
     c->lam_min_sum += c->hlam[a][0];  // lam_1 (Dirichlet) or 0 (Neumann) leads both orderings
   }
+  // 3D bf16x3: the forward y and z products run folded when both axes fit it
+  c->fwdfold = c->prec == QN_PREC_BF16X3 && c->dim == 3 && c->sem_k == 0 && c->bc == QN_BC_DIRICHLET;
+  for (int a = 1; a < 3 && c->fwdfold; ++a)
+    c->fwdfold = 2 * fold_half(c->n[a]) == c->p[a];
+  for (int a = 1; a < 3 && c->fwdfold; ++a) {
+    c->hp[a] = fold_half(c->n[a]);
+    fold_forward(c->n[a], c->p[a], c->hS[a], c->hSf[a]);
+  }
   // Gray-Scott: component c solves with D_c A_h, so the smallest eigenvalue
   // of the solve operator's linear part is min(D_A, D_S) lam_min(A_h).
   if (c->nl == QN_NL_GRAYSCOTT) c->lam_min_sum *= std::min(c->gs[0], c->gs[1]);
@@ -786,6 +835,11 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
       off += align256(c->hHb[a].size() * 8);
     }
   }
+  for (int a = 1; a < 3 && c->fwdfold; ++a)
+    for (int q = 0; q < 2; ++q) {
+      c->off_Sf[a][q] = off;
+      off += align256(c->hSf[a].size() * 2);
+    }
   if (c->dim == 2) {  // unused z axis aliases y (never read)
     c->off_S[2] = c->off_S[1];
     c->off_Slo[2] = c->off_Slo[1];
@@ -880,6 +934,21 @@ qn_status qn_bind_workspace(qn_ctx c, void* d_ws, size_t bytes) {
         e = hipMemcpyAsync(c->ws + offs[q], parts[q].data(), pp * 2, hipMemcpyHostToDevice,
                            c->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // host temporaries
+      if (c->fwdfold && a > 0 && e == hipSuccess) {  // folded forward operand: bf16 parts
+        const std::vector<double>& v = c->hSf[a];
+        std::vector<uint16_t> sp[2];
+        sp[0].resize(v.size());
+        sp[1].resize(v.size());
+        for (size_t i = 0; i < v.size(); ++i) {
+          const float r = (float)v[i];
+          sp[0][i] = bf16_rne(r);
+          sp[1][i] = bf16_rne(r - bf16_value(sp[0][i]));
+        }
+        for (int q = 0; q < 2 && e == hipSuccess; ++q)
+          e = hipMemcpyAsync(c->ws + c->off_Sf[a][q], sp[q].data(), v.size() * 2,
+                             hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // host temporaries
+      }
     }
     if (e == hipSuccess)
       e = hipMemcpyAsync(c->ws + c->off_lam[a], c->hlam[a].data(), (size_t)c->p[a] * 8,

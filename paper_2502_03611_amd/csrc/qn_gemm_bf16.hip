@@ -30,8 +30,23 @@
 // over the even modes (p) and the odd modes (q), taken by masking each
 // fragment's 8 consecutive modes to its even or odd entries, and writes
 // x[j] = p + q and x[n-1-j] = p - q: half the workgroups, each with twice the
-// matrix-core work per staged chunk for the same loads.  The forward products
-// contract over the spatial index and stay dense.
+// matrix-core work per staged chunk for the same loads.
+//
+// 3D bf16x3 solves whose y and z axes allow it (2 hp = P, hp = ceil(n / 2)
+// rounded up to 32) also fold the forward y and z products, which contract
+// over the spatial index: the producer of each one's input writes it folded
+// along that axis, and the product takes the even modes from the sums and
+// the odd modes from the differences:
+//   - the x product writes its output folded along z: plane z < hp holds
+//     X[z] + X[nz-1-z] and plane hp + z holds X[z] - X[nz-1-z] (the middle
+//     plane of odd nz once, its difference zero; planes from ceil(nz / 2) to
+//     hp zero), pairing the two planes' rows inside one tile;
+//   - a forward product over a folded input contracts hp rows for each mode,
+//     the sums for the even modes and the differences for the odd ones (S:
+//     the even modes' rows, then the odd modes', hp columns): half the loads
+//     and matrix-core work of the dense product, output in mode order; the z
+//     product writes its output folded along y in the same way (pairing the
+//     columns of rows y and ny-1-y in one tile).
 //
 // Work decomposition: a 256-thread workgroup (four wave64s in a 2 x 2 grid)
 // owns a TM x TN output tile and walks K in chunks of 32 (one matrix-core
@@ -164,14 +179,25 @@ __device__ inline const __bf16* part(const GemmOperands& s, int i) {
 
 }  // namespace
 
-template <int NP, int TM, int TN, int EPI, bool FOLD = false>
+// FWD (bf16x3, the 3D path with folded forward products; K = hp, M = 2 hp):
+//   1  forward product from a folded input: tile rows t < hp contract the
+//      mirror sums (B rows [0, hp)) into even mode 2 t, rows hp + t the
+//      differences (B rows [hp, 2 hp)) into odd mode 2 t + 1 (S: the modes'
+//      rows of S in that order, hp columns); output rows in mode order
+//   2  the same, the output written folded along y (the z product: columns
+//      y * px + x, hpo = the folded y layout's half extent)
+// K is the contraction length and the leading dimension of S (M otherwise).
+template <int NP, int TM, int TN, int EPI, bool FOLD = false, int FWD = 0>
 __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const void* __restrict__ Bv,
-                                                         void* __restrict__ Cv, int M, int ncols,
-                                                         int batch, long long bstride, EpiArgs ep,
-                                                         int mh, int nmir) {
+                                                         void* __restrict__ Cv, int M, int K,
+                                                         int ncols, int batch, long long bstride,
+                                                         EpiArgs ep, int mh, int nmir, int hpo) {
   // NP = 2: B and C are bf16 part planes; NP = 3: FP32 tensors
   constexpr bool PS = NP == 2;
+  constexpr bool FF = FWD >= 1, YF = FWD == 2;
   static_assert(!FOLD || (NP == 2 && EPI == EPI_STORE), "folded: the bf16x3 inverse products");
+  static_assert(FWD == 0 || (NP == 2 && !FOLD), "folded forward: bf16x3 forward products");
+  static_assert(!YF || (EPI == EPI_STORE && TN >= 64), "y-folded output: plain store, paired column halves");
   const float* B = (const float*)Bv;
   float* C = (float*)Cv;
   const long long plane = (long long)batch * bstride;
@@ -183,16 +209,38 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const v
   __shared__ __attribute__((aligned(16))) char Bs[NP][2][BTK * TN * 2];
 
   // FOLD: output rows m < mh only (mh: ceil(nmir / 2) rounded up to TM), each
-  // giving rows m and nmir - 1 - m
-  const int MT = (FOLD ? mh : M) / TM, NT = ncols / TN;
+  // giving rows m and nmir - 1 - m.  YF: column tiles of TN / 2 x values at
+  // rows y < hpo and ny-1-y.
+  const int MT = (FOLD ? mh : M) / TM, NT = YF ? hpo * (ep.px / (TN / 2)) : ncols / TN;
   const int t = xcd_tile(blockIdx.x, batch * MT * NT);
   const int mt = t % MT, rest = t / MT, nt = rest % NT, b = rest / NT;
   const int inst = b % ep.inst_mod;
   if (ep.skip && ep.skip[inst]) return;  // whole workgroup: finished instance
   const int m0 = mt * TM, n0 = nt * TN;
-  const float* Bb = B + (long long)b * bstride;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+  // FF: this tile's parity half of the folded input (all its rows have one
+  // parity: TM divides K); YF: its row pair and x range
+  const int krow0 = FF && m0 >= K ? K : 0;
+  auto orow = [&](int m) { return FF ? 2 * (m - krow0) + (krow0 ? 1 : 0) : m; };  // output row
+  int yf = 0, ybar = 0, x0 = 0;
+  if constexpr (YF) {
+    const int xt = ep.px / (TN / 2);
+    yf = nt / xt;
+    x0 = (nt % xt) * (TN / 2);
+    ybar = max(ep.ny - 1 - yf, 0);
+  }
+  // global column of the tile's logical column l (a multiple of 8): YF puts
+  // the x values of row y in the first half of each wave's WN columns and
+  // those of row ny-1-y in the second, so a lane holds both of a pair
+  auto bcol = [&](int l) -> long long {
+    if constexpr (YF) {
+      const int wh = l / WN, r = l % WN, mir = r >= WN / 2;
+      return (long long)(mir ? ybar : yf) * ep.px + x0 + wh * (WN / 2) + r - (mir ? WN / 2 : 0);
+    } else {
+      return n0 + l;
+    }
+  };
 
   f4_t acc[BM][BN], accq[BM][BN];  // accq: the odd modes' sums (FOLD)
 #pragma unroll
@@ -244,7 +292,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const v
         for (int i = 0; i < BM; ++i) acc[i][j] = mfma_split<NP>(a[i], bj[j], acc[i][j]);
     }
   };
-  const int nk = M / BTK;
+  const int nk = K / BTK;
   if constexpr (PS) {
     const __bf16* Bh = (const __bf16*)Bv + (long long)b * bstride;
     // chunk k0 into LDS buffer buf: the S parts' rows (TM / 16 KiB blocks per
@@ -253,13 +301,13 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const v
 #pragma unroll
       for (int blk = wave; blk < TM / 16; blk += 4)
 #pragma unroll
-        for (int q = 0; q < NP; ++q) dload_rows(part(S, q), M, m0 + 16 * blk, k0, lane, &As[q][buf][blk * 1024]);
+        for (int q = 0; q < NP; ++q) dload_rows(part(S, q), K, m0 + 16 * blk, k0, lane, &As[q][buf][blk * 1024]);
       constexpr int RPB = 512 / TN, SPR = TN / 8;  // rows per block, 16-byte slots per row
 #pragma unroll
       for (int blk = wave; blk < BTK / RPB; blk += 4) {
         const int row = RPB * blk + lane / SPR, slot = lane % SPR;
         const int seg = (slot >> 1) ^ tperm<TN>(row);
-        const long long off = (long long)(k0 + row) * ncols + n0 + 16 * seg + 8 * (slot & 1);
+        const long long off = (long long)(krow0 + k0 + row) * ncols + bcol(16 * seg + 8 * (slot & 1));
 #pragma unroll
         for (int q = 0; q < NP; ++q)
           __builtin_amdgcn_global_load_lds(Bh + q * plane + off, (lds_void*)&Bs[q][buf][blk * 1024], 16, 0, 0);
@@ -291,7 +339,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const v
         if (v < NAV) {
           const int m = v / (BTK / 8), kv = (v % (BTK / 8)) * 8;
           // S[m][k] with S symmetric: row m, 8 consecutive k.
-          const long long off = (long long)(m0 + m) * M + k0 + kv;
+          const long long off = (long long)(m0 + m) * K + k0 + kv;
 #pragma unroll
           for (int q = 0; q < NP; ++q) ra[q][p] = *reinterpret_cast<const bf8_t*>(part(S, q) + off);
         }
@@ -375,12 +423,13 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const v
     // 2^-16 relative split): the denominator and the quotient in FP32 lose
     // nothing at that precision and cost half the FP64 operations
     const float sf = (float)scale, bf = (float)beta;
+    const double lb = ep.lamB ? ep.lamB[b % ep.pz] : 0.0;  // slab's own mode (z)
 #pragma unroll
     for (int i = 0; i < BM; ++i)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
-        const double lm = ep.lamM[m];
+        const int m = orow(m0 + wm + 16 * i + 4 * (lane >> 4) + q);
+        const double lm = ep.lamM[m] + lb;
 #pragma unroll
         for (int j = 0; j < BN; ++j) {
           const int n = n0 + wn + 16 * j + (lane & 15);
@@ -408,12 +457,33 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const v
           if (mm != m) put((long long)mm * ncols + n, p - qq);
         }
       }
+  } else if constexpr (YF) {
+    // plane m of the y-folded output: row y < hpo the pair's sum, row hpo + y
+    // its difference (the middle row of odd ny once; rows from ceil(ny / 2)
+    // to hpo zero)
+    const int hy = (ep.ny + 1) / 2;
+    const int xw = x0 + (wave & 1) * (WN / 2);
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = orow(m0 + wm + 16 * i + 4 * (lane >> 4) + q);
+#pragma unroll
+        for (int j = 0; j < BN / 2; ++j) {
+          const int x = xw + 16 * j + (lane & 15);
+          const float d = acc[i][j][q], e = acc[i][j + BN / 2][q];
+          const float vp = yf >= hy ? 0.0f : ybar == yf ? d : d + e;
+          const float vm = (yf >= hy || ybar == yf) ? 0.0f : d - e;
+          put((long long)m * ncols + (long long)yf * ep.px + x, vp);
+          put((long long)m * ncols + (long long)(hpo + yf) * ep.px + x, vm);
+        }
+      }
   } else {
 #pragma unroll
     for (int i = 0; i < BM; ++i)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
+        const int m = orow(m0 + wm + 16 * i + 4 * (lane >> 4) + q);
 #pragma unroll
         for (int j = 0; j < BN; ++j)
           put((long long)m * ncols + n0 + wn + 16 * j + (lane & 15), acc[i][j][q]);
@@ -421,14 +491,20 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const v
   }
 }
 
-template <int NP, int TM, int TN, int EPI, bool FOLD = false>
+// ZF (bf16x3, the 3D split-order path): the output written folded along z,
+// hpo = the folded z layout's half extent.  A tile's rows are TM / 2 rows y of
+// plane z < hpo and the same rows of plane nz-1-z, each wave's fragment row
+// blocks split in halves so that a lane holds both values of a pair.
+template <int NP, int TM, int TN, int EPI, bool FOLD = false, bool ZF = false>
 __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const void* __restrict__ Av,
                                                           GemmOperands S, void* __restrict__ Cv,
                                                           int rows, int K, EpiArgs ep, int nh,
-                                                          int nmir) {
+                                                          int nmir, int hpo) {
   // NP = 2: A and C (with EPI_STORE) are bf16 part planes; NP = 3: FP32 tensors
   constexpr bool PS = NP == 2;
   static_assert(!FOLD || NP == 2, "folded: the bf16x3 inverse products");
+  static_assert(!ZF || (NP == 2 && !FOLD && EPI == EPI_STORE && TM >= 64),
+                "z-folded output: bf16x3 forward x product, paired row halves");
   const float* A = (const float*)Av;
   float* C = (float*)Cv;
   const long long plane = (long long)rows * K;
@@ -441,13 +517,27 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const void* __restrict
 
   // FOLD: output columns n < nh only (nh: ceil(nmir / 2) rounded up to TN),
   // each giving columns n and nmir - 1 - n
-  const int MT = rows / TM, NT = (FOLD ? nh : K) / TN;
+  constexpr int HB = BM / 2;  // ZF: fragment row blocks per wave of each plane
+  const int ytiles = ZF ? ep.py / (TM / 2) : 1;
+  const int MT = ZF ? rows / (ep.pz * ep.py) * hpo * ytiles : rows / TM, NT = (FOLD ? nh : K) / TN;
   const int t = xcd_tile(blockIdx.x, MT * NT);
   const int nt = t % NT, mt = t / NT;
   const int r0 = mt * TM, n0 = nt * TN;
-  if (ep.skip && ep.skip[(r0 / ep.py / ep.pz) % ep.inst_mod]) return;  // finished instance
+  // ZF: component, plane pair and first row of the tile
+  const int zc = ZF ? mt / ytiles : 0, zf = ZF ? zc % hpo : 0, zcomp = ZF ? zc / hpo : 0;
+  const int zbar = ZF ? max(ep.nz - 1 - zf, 0) : 0, y0 = ZF ? (mt % ytiles) * (TM / 2) : 0;
+  if (ep.skip && ep.skip[(ZF ? zcomp : r0 / ep.py / ep.pz) % ep.inst_mod]) return;  // finished instance
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+  // first data row of the tile's 16-row LDS block blk
+  auto arow = [&](int blk) -> int {
+    if constexpr (ZF) {
+      const int a = blk / BM, i = blk % BM;
+      return ((zcomp * ep.pz + (i < HB ? zf : zbar)) * ep.py) + y0 + a * (WM / 2) + 16 * (i % HB);
+    } else {
+      return r0 + 16 * blk;
+    }
+  };
 
   f4_t acc[BM][BN], accq[BM][BN];  // accq: the odd modes' sums (FOLD)
 #pragma unroll
@@ -501,7 +591,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const void* __restrict
 #pragma unroll
       for (int blk = wave; blk < TM / 16; blk += 4)
 #pragma unroll
-        for (int q = 0; q < NP; ++q) dload_rows(Ah + q * plane, K, r0 + 16 * blk, k0, lane, &As[q][buf][blk * 1024]);
+        for (int q = 0; q < NP; ++q) dload_rows(Ah + q * plane, K, arow(blk), k0, lane, &As[q][buf][blk * 1024]);
 #pragma unroll
       for (int blk = wave; blk < TN / 16; blk += 4)
 #pragma unroll
@@ -592,6 +682,30 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const void* __restrict
     }
   }
 
+  if constexpr (ZF) {
+    // plane zf of the z-folded output holds the pair's sum, plane hpo + zf its
+    // difference (the middle plane of odd nz once; planes from ceil(nz / 2)
+    // to hpo zero)
+    const int hz = (ep.nz + 1) / 2;
+    const int yw = y0 + (wave >> 1) * (WM / 2);
+    const long long pp = (long long)(zcomp * ep.pz + zf) * ep.py, pm = pp + (long long)hpo * ep.py;
+#pragma unroll
+    for (int i = 0; i < HB; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int y = yw + 16 * i + 4 * (lane >> 4) + q;
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          const int n = n0 + wn + 16 * j + (lane & 15);
+          const float d = acc[i][j][q], e = acc[i + HB][j][q];
+          const float vp = zf >= hz ? 0.0f : zbar == zf ? d : d + e;
+          const float vm = (zf >= hz || zbar == zf) ? 0.0f : d - e;
+          put_pair((__bf16*)Cv, plane, (pp + y) * K + n, vp);
+          put_pair((__bf16*)Cv, plane, (pm + y) * K + n, vm);
+        }
+      }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < BM; ++i) {
     // Row bases of this fragment row block; for U -= dU every old value of the
@@ -685,17 +799,48 @@ int parts_of(int prec) { return prec == 3 ? 3 : 2; }  // 3: bf16x6, else bf16x3
 
 // fold > 0: the reflection-folded inverse product (bf16x3 only), output rows
 // (form L) or columns (form R) [0, fold) of the axis of length nmir, fold a
-// multiple of the tile side.
+// multiple of the tile side.  sp: the folded forward products of the 3D path.
 template <int NP, int TM, int TN>
 hipError_t left_tile(const GemmOperands& s, const void* B, void* C, int M, int ncols, int batch,
                      long long bstride, int epi, const EpiArgs& ep, hipStream_t st, int fold,
-                     int nmir) {
+                     int nmir, const BfSplit* sp) {
+  const int fwd = sp ? sp->mode : 0;
+  if (fwd) {
+    if constexpr (NP == 2) {
+      const int K = sp->K;
+      if (K <= 0 || K % BTK != 0) return hipErrorInvalidValue;
+      if (fold > 0) return hipErrorInvalidValue;
+      if (M != 2 * K || K % TM != 0) return hipErrorInvalidValue;
+      if (fwd == 1) {  // forward from a folded input
+        if (ncols % TN != 0 || (epi != EPI_STORE && epi != EPI_DIVIDE)) return hipErrorInvalidValue;
+        const unsigned g = (unsigned)((long long)batch * (M / TM) * (ncols / TN));
+        if (epi == EPI_DIVIDE)
+          hipLaunchKernelGGL((k_gemm_left_bf<NP, TM, TN, EPI_DIVIDE, false, 1>), dim3(g), dim3(256), 0,
+                             st, s, B, C, M, K, ncols, batch, bstride, ep, 0, 0, 0);
+        else
+          hipLaunchKernelGGL((k_gemm_left_bf<NP, TM, TN, EPI_STORE, false, 1>), dim3(g), dim3(256), 0,
+                             st, s, B, C, M, K, ncols, batch, bstride, ep, 0, 0, 0);
+        return hipGetLastError();
+      }
+      if constexpr (TN >= 64) {
+        const int hpo = sp->hpo;  // forward, output folded along y
+        if (fwd != 2 || epi != EPI_STORE || hpo <= 0 || ep.px % (TN / 2) != 0 ||
+            (long long)ncols != (long long)ep.py * ep.px || 2 * hpo > ep.py || hpo > ep.ny)
+          return hipErrorInvalidValue;
+        const unsigned g = (unsigned)((long long)batch * (M / TM) * hpo * (ep.px / (TN / 2)));
+        hipLaunchKernelGGL((k_gemm_left_bf<NP, TM, TN, EPI_STORE, false, 2>), dim3(g), dim3(256), 0, st,
+                           s, B, C, M, K, ncols, batch, bstride, ep, 0, 0, hpo);
+        return hipGetLastError();
+      }
+    }
+    return hipErrorInvalidValue;
+  }
   if (fold > 0) {
     if constexpr (NP == 2) {
       if (epi != EPI_STORE || fold % TM != 0 || fold > M || 2 * fold < nmir) return hipErrorInvalidValue;
       const unsigned g = (unsigned)((long long)batch * (fold / TM) * (ncols / TN));
       hipLaunchKernelGGL((k_gemm_left_bf<NP, TM, TN, EPI_STORE, true>), dim3(g), dim3(256), 0, st, s,
-                         B, C, M, ncols, batch, bstride, ep, fold, nmir);
+                         B, C, M, M, ncols, batch, bstride, ep, fold, nmir, 0);
       return hipGetLastError();
     }
     return hipErrorInvalidValue;
@@ -703,10 +848,10 @@ hipError_t left_tile(const GemmOperands& s, const void* B, void* C, int M, int n
   const unsigned g = (unsigned)((long long)batch * (M / TM) * (ncols / TN));
   if (epi == EPI_DIVIDE)
     hipLaunchKernelGGL((k_gemm_left_bf<NP, TM, TN, EPI_DIVIDE>), dim3(g), dim3(256), 0, st, s, B, C,
-                       M, ncols, batch, bstride, ep, 0, 0);
+                       M, M, ncols, batch, bstride, ep, 0, 0, 0);
   else
     hipLaunchKernelGGL((k_gemm_left_bf<NP, TM, TN, EPI_STORE>), dim3(g), dim3(256), 0, st, s, B, C,
-                       M, ncols, batch, bstride, ep, 0, 0);
+                       M, M, ncols, batch, bstride, ep, 0, 0, 0);
   return hipGetLastError();
 }
 
@@ -717,22 +862,36 @@ hipError_t right_launch(const GemmOperands& s, const void* A, void* C, int rows,
   switch (epi) {
     case EPI_SUB_DENSE:
       hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_SUB_DENSE, FOLD>), dim3(g), dim3(256), 0,
-                         st, A, s, C, rows, K, ep, nout, nmir);
+                         st, A, s, C, rows, K, ep, nout, nmir, 0);
       break;
     case EPI_STORE_DENSE:
       hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_STORE_DENSE, FOLD>), dim3(g), dim3(256), 0,
-                         st, A, s, C, rows, K, ep, nout, nmir);
+                         st, A, s, C, rows, K, ep, nout, nmir, 0);
       break;
     default:
       hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_STORE, FOLD>), dim3(g), dim3(256), 0, st,
-                         A, s, C, rows, K, ep, nout, nmir);
+                         A, s, C, rows, K, ep, nout, nmir, 0);
   }
   return hipGetLastError();
 }
 
 template <int NP, int TM, int TN>
 hipError_t right_tile(const GemmOperands& s, const void* A, void* C, int rows, int K, int epi,
-                      const EpiArgs& ep, hipStream_t st, int fold, int nmir) {
+                      const EpiArgs& ep, hipStream_t st, int fold, int nmir, const BfSplit* sp) {
+  if (sp && sp->mode) {
+    if constexpr (NP == 2 && TM >= 64) {
+      const int hpo = sp->hpo;  // dense x product, output folded along z
+      if (sp->mode != 3 || fold > 0 || epi != EPI_STORE || hpo <= 0 || K % TN != 0 ||
+          ep.py % (TM / 2) != 0 || rows % (ep.pz * ep.py) != 0 || 2 * hpo > ep.pz || hpo > ep.nz)
+        return hipErrorInvalidValue;
+      const unsigned g =
+          (unsigned)((long long)(rows / (ep.pz * ep.py)) * hpo * (ep.py / (TM / 2)) * (K / TN));
+      hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_STORE, false, true>), dim3(g), dim3(256), 0,
+                         st, A, s, C, rows, K, ep, K, 0, hpo);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
   if (fold > 0) {
     if constexpr (NP == 2) {
       if (fold % TN != 0 || fold > K || 2 * fold < nmir) return hipErrorInvalidValue;
@@ -770,14 +929,14 @@ int gemm_bf_max_tile(int prec) { return parts_of(prec) == 3 ? 64 : 128; }
 
 hipError_t launch_gemm_left(int prec, const GemmOperands& s, const void* B, void* C, int M,
                             int ncols, int batch, long long bstride, int epi, const EpiArgs& ep,
-                            int tm, int tn, hipStream_t st, int fold, int nmir) {
-  QN_BF_TILES(left_tile, parts_of(prec), s, B, C, M, ncols, batch, bstride, epi, ep, st, fold, nmir)
+                            int tm, int tn, hipStream_t st, int fold, int nmir, const BfSplit* sp) {
+  QN_BF_TILES(left_tile, parts_of(prec), s, B, C, M, ncols, batch, bstride, epi, ep, st, fold, nmir, sp)
 }
 
 hipError_t launch_gemm_right(int prec, const GemmOperands& s, const void* A, void* C, int rows,
                              int K, int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st,
-                             int fold, int nmir) {
-  QN_BF_TILES(right_tile, parts_of(prec), s, A, C, rows, K, epi, ep, st, fold, nmir)
+                             int fold, int nmir, const BfSplit* sp) {
+  QN_BF_TILES(right_tile, parts_of(prec), s, A, C, rows, K, epi, ep, st, fold, nmir, sp)
 }
 
 #undef QN_BF_TILES

@@ -44,6 +44,24 @@ inline void dense_eigen(int n, int p, std::vector<double>& Sp, std::vector<doubl
   }
 }
 
+// Folded forward products of the 3D split-bf16 path: along an axis of n
+// points the input is folded about the centre (rows j < hp the mirror sums
+// U[j] + U[n-1-j], rows hp + j the differences; the middle row of odd n once),
+// hp = ceil(n / 2) rounded up to 32; usable when 2 hp equals the padded
+// extent.  Forward operand Sf (2 hp x hp): row t < hp holds even mode 2 t,
+// row hp + t odd mode 2 t + 1, each at j < ceil(n / 2) (zero rows for modes
+// from n on), from the dense padded S (p x p, S[j][k] = entry j of mode k).
+inline int fold_half(int n) { return (((n + 1) / 2 + 31) / 32) * 32; }
+inline void fold_forward(int n, int p, const std::vector<double>& Sp, std::vector<double>& Sf) {
+  const int hp = fold_half(n), h = (n + 1) / 2;
+  Sf.assign((size_t)2 * hp * hp, 0.0);
+  for (int pos = 0; pos < 2 * hp; ++pos) {
+    const int m = pos < hp ? 2 * pos : 2 * (pos - hp) + 1;
+    if (m >= n) continue;
+    for (int j = 0; j < h; ++j) Sf[(size_t)pos * hp + j] = Sp[(size_t)j * p + m];
+  }
+}
+
 // Folded form (block bk): FeT, FoT, Fe, Fo (bk x bk each, concatenated in that
 // order) and lam in split order (2 bk, padded with lam_max).
 inline void fold_eigen(int n, int bk, std::vector<double>& F4, std::vector<double>& ls) {

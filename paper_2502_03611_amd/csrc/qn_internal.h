@@ -89,6 +89,9 @@ struct EpiArgs {
   // EPI_SUB_DENSE of the folded kernels: dense = old - step * acc (the damped
   // step of the Gray-Scott system; 1 otherwise).
   double step;
+  // EPI_DIVIDE of the split-bf16 form L: eigenvalue added per slab (index
+  // b % pz: the z mode of a y product batched over z), NULL: none.
+  const double* lamB;
 };
 
 // Dense split-bf16 mode products (qn_gemm_bf16.hip), FP32 tensors.  All
@@ -111,12 +114,29 @@ int gemm_bf_max_tile(int prec);
 // symmetric or antisymmetric about the centre by mode parity); fold is
 // ceil(nmir / 2) rounded up to the tile side.  The rows or columns from
 // nmir up to the padded extent are left unwritten.
+//
+// sp (bf16x3, 3D): the folded forward products, which pass tensors folded
+// along an axis (rows [0, hp) of the axis the mirror sums, [hp, 2 hp) the
+// differences, 2 hp = P):
+//   form L, mode 1: forward from a folded input, K = hp, M = 2 hp, S the
+//                   even modes' rows of S then the odd modes', hp columns;
+//                   output rows in mode order
+//   form L, mode 2: the same with the output folded along y (the z product;
+//                   hpo: half extent of the folded y layout)
+//   form R, mode 3: dense x product, output folded along z (hpo: half extent
+//                   of the folded z layout)
+struct BfSplit {
+  int mode;
+  int K;    // form L: contraction length, the leading dimension of S
+  int hpo;  // modes 2 and 3
+};
 hipError_t launch_gemm_left(int prec, const GemmOperands& s, const void* B, void* C, int M,
                             int ncols, int batch, long long bstride, int epi, const EpiArgs& ep,
-                            int tm, int tn, hipStream_t st, int fold = 0, int nmir = 0);
+                            int tm, int tn, hipStream_t st, int fold = 0, int nmir = 0,
+                            const BfSplit* sp = nullptr);
 hipError_t launch_gemm_right(int prec, const GemmOperands& s, const void* A, void* C, int rows,
                              int K, int epi, const EpiArgs& ep, int tm, int tn, hipStream_t st,
-                             int fold = 0, int nmir = 0);
+                             int fold = 0, int nmir = 0, const BfSplit* sp = nullptr);
 
 // Reflection-folded mode products (qn_gemm_fold.hip).  Along a folded axis of
 // n interior points, h = n / 2, odd = n % 2, and the spectral index is stored

@@ -130,7 +130,7 @@ def test_fdm_solve_max_size_2d():
 # sqrt(6) 2^-16 = 3.7e-5 (the oracle's own split-bf16 solve lands at 1.1e-5);
 # bf16x6 drops only terms below 2^-24 and is bounded like FP32.
 @pytest.mark.parametrize("prec,tol", [("fp32", 3e-6), ("bf16x3", 4e-5), ("bf16x6", 3e-6)])
-@pytest.mark.parametrize("shape", [(63, 63), (31, 31, 31), (40, 50, 70)])
+@pytest.mark.parametrize("shape", [(63, 63), (31, 31, 31), (40, 50, 70), (40, 45, 33), (64, 98, 20)])
 def test_fdm_solve_reduced_precision(prec, tol, shape):
     print(f"fdm {prec} {shape}", flush=True)
     r = synth.random_field((1,) + shape, 10)
@@ -167,7 +167,8 @@ def test_split_bf16_solve_matches_the_split_oracle(prec, parts, shape, scale, sh
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
 @pytest.mark.parametrize("kind,shape,beta,mode", [
     ("cubic", (63, 63), 1.0, "fixed"), ("quasilinear", (31, 33, 35), 0.0, "fixed"),
-    ("system", (40, 45), 0.0, "midpoint"),
+    ("system", (40, 45), 0.0, "midpoint"), ("quasilinear", (40, 45, 33), 0.0, "fixed"),
+    ("system", (63, 45, 20), 0.0, "midpoint"),
 ])
 def test_reduced_precision_iterate_reaches_the_fp64_solution(prec, kind, shape, beta, mode):
     """Transforms in reduced precision with the FP64 residual and update: the
@@ -364,7 +365,8 @@ def test_deterministic_bitwise():
 
 
 @pytest.mark.parametrize("shape,prec", [((255, 255), "fp64"), ((63, 63), "fp32"),
-                                        ((40, 70, 130), "fp64")])
+                                        ((40, 70, 130), "fp64"), ((40, 45, 33), "bf16x3"),
+                                        ((64, 127, 125), "bf16x3")])
 def test_every_admissible_tile_gives_the_same_bits(shape, prec):
     """Each launch of the solve is pinned in turn to every instantiated tile
     (plain, paired, deep-staged) that qn_set_tile accepts; every solve returns
@@ -401,6 +403,7 @@ def test_every_admissible_tile_gives_the_same_bits(shape, prec):
     ("cubic", (37, 45, 70), "fp64"), ("system", (31, 64, 97), "fp64"),
     ("quasilinear", (65, 33), "fp64"), ("cubic", (40, 50, 70), "fp32"),
     ("cubic", (40, 50, 70), "bf16x3"), ("system", (33, 60), "bf16x6"),
+    ("cubic", (40, 45, 33), "bf16x3"), ("system", (36, 64, 63), "bf16x3"),
 ])
 def test_autotuned_tiles_give_bitwise_identical_solves(kind, shape, prec):
     """The tile shape changes the work split, never the arithmetic order: an
@@ -443,7 +446,8 @@ def test_mfma_probe_is_plausible():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
-@pytest.mark.parametrize("kind,shape", [("cubic", (45, 70)), ("system", (17, 19, 23))])
+@pytest.mark.parametrize("kind,shape", [("cubic", (45, 70)), ("system", (17, 19, 23)),
+                                        ("system", (63, 45, 20))])
 def test_step_size_scales_the_correction_in_every_precision(prec, kind, shape):
     """U_1 = U_0 - step dU: with step 1/2 the first update is half the undamped
     one (dU is the same bits, so the two differ by the rounding of the
