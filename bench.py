@@ -45,18 +45,18 @@ PEAK_HBM_GBS = 8000.0
 # valid only while the source file it was taken on is unchanged.
 TRAFFIC_SOURCES = {"fold": ("paper_2502_03611_amd/csrc/qn_gemm_fold.hip", "0bf9f6298fde0112"),
                    "pointwise": ("paper_2502_03611_amd/csrc/qn_pointwise.hip", "7db57d6c0fb14e33"),
-                   "bf16": ("paper_2502_03611_amd/csrc/qn_gemm_bf16.hip", "85a4d2113235acec")}
-TRAFFIC = {"k_fold_right_fwd<double,64,128,0>": ("fold", 1.4639e+09, 1.0737e+09),
-           "k_fold_left_fwd2<double,64,64,EPI_STORE,0>": ("fold", 1.4554e+09, 1.0737e+09),
-           "k_fold_left_fwd<double,128,128,EPI_DIVIDE,0>": ("fold", 1.2619e+09, 1.0737e+09),
-           "k_fold_left_inv<double,64,64,0>": ("fold", 1.3847e+09, 1.0716e+09),
-           "k_fold_right_inv<double,64,64,EPI_SUB_DENSE,0>": ("fold", 2.5118e+09, 1.0763e+09),
-           "k_residual<QUASILIN,double>": ("pointwise", 2.4113e+09, 1.0738e+09),
-           "k_gemm_right_bf<2,128,128,EPI_STORE,false>": ("bf16", 6.2776e+08, 5.3691e+08),
-           "k_gemm_left_bf<2,128,128,EPI_STORE,false>": ("bf16", 6.1800e+08, 5.3689e+08),
-           "k_gemm_left_bf<2,128,128,EPI_DIVIDE,false>": ("bf16", 6.2273e+08, 5.3822e+08),
-           "k_gemm_left_bf<2,128,128,EPI_STORE,true>": ("bf16", 5.7146e+08, 5.3676e+08),
-           "k_gemm_right_bf<2,128,128,EPI_SUB_DENSE,true>": ("bf16", 1.6666e+09, 1.0955e+09)}
+                   "bf16": ("paper_2502_03611_amd/csrc/qn_gemm_bf16.hip", "2446f2cee597a8cf")}
+TRAFFIC = {"k_fold_right_fwd<double,64,128,0>": ("fold", 1.4634e+09, 1.0737e+09),
+           "k_fold_left_fwd2<double,64,64,EPI_STORE,0>": ("fold", 1.4587e+09, 1.0737e+09),
+           "k_fold_left_fwd<double,128,128,EPI_DIVIDE,0>": ("fold", 1.2585e+09, 1.0737e+09),
+           "k_fold_left_inv<double,64,64,0>": ("fold", 1.3873e+09, 1.0716e+09),
+           "k_fold_right_inv<double,64,64,EPI_SUB_DENSE,0>": ("fold", 2.5114e+09, 1.0760e+09),
+           "k_residual<QUASILIN,double>": ("pointwise", 2.3979e+09, 1.0738e+09),
+           "k_gemm_right_bf<2,128,128,EPI_STORE,false,true>": ("bf16", 6.3455e+08, 5.3766e+08),
+           "k_gemm_left_bf<2,128,128,EPI_STORE,false,2>": ("bf16", 5.5474e+08, 5.3805e+08),
+           "k_gemm_left_bf<2,128,128,EPI_DIVIDE,false,1>": ("bf16", 5.6620e+08, 5.3688e+08),
+           "k_gemm_left_bf<2,128,128,EPI_STORE,true,0>": ("bf16", 5.7003e+08, 5.3708e+08),
+           "k_gemm_right_bf<2,64,128,EPI_SUB_DENSE,true,false>": ("bf16", 1.6765e+09, 1.1250e+09)}
 
 
 def traffic_if_current(kernel, n):
@@ -221,12 +221,14 @@ def mixed_steps(shape, U, F, steps, precisions=("fp32", "bf16x3")):
         if prec == "bf16x3":
             # measured HBM bytes of the kept tiles (profiles/traffic_fp64_quasilinear_511.md)
             keys = ["gemm_x", "gemm_yz", "gemm_divide", "gemm_yz_inv", "gemm_yz_inv", "gemm_x_update"]
+            # template tails of the 3D path: x product with its output folded along z;
+            # z product from the folded input, output folded along y; y product from
+            # the folded input with the divide; folded inverse products
+            tails = {0: "EPI_STORE,false,true", 2: "EPI_STORE,true,0", 3: "EPI_SUB_DENSE,true,false"}
             for key, (kind, axis, tm, tn) in zip(keys, rec["tiles"]):
                 form = "k_gemm_right_bf" if kind in (0, 3) else "k_gemm_left_bf"
-                epi = ("EPI_SUB_DENSE" if kind == 3 else
-                       "EPI_DIVIDE" if (kind == 1 and axis == 2) else "EPI_STORE")
-                fold = "true" if kind in (2, 3) else "false"  # the inverse products are folded
-                tr = traffic_if_current(f"{form}<2,{tm},{tn},{epi},{fold}>", n)
+                tail = tails.get(kind, "EPI_STORE,false,2" if axis == 2 else "EPI_DIVIDE,false,1")
+                tr = traffic_if_current(f"{form}<2,{tm},{tn},{tail}>", n)
                 e = rec["kernels"].get(key)
                 if e is not None and tr is not None:
                     e["traffic"] = tr
