@@ -491,7 +491,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const v
   }
 }
 
-// ZF (bf16x3, the 3D split-order path): the output written folded along z,
+// ZF (bf16x3, the 3D path with folded forward products): the output written folded along z,
 // hpo = the folded z layout's half extent.  A tile's rows are TM / 2 rows y of
 // plane z < hpo and the same rows of plane nz-1-z, each wave's fragment row
 // blocks split in halves so that a lane holds both values of a pair.
