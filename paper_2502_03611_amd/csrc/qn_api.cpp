@@ -115,6 +115,7 @@ struct qn_ctx_s {
   // 3D split-bf16 solves with folded forward y and z products: half extents
   // of the folded layouts and the forward operands (bf16 parts) of y and z
   bool fwdfold = false;
+  bool xfold = false;  // the x product too, from a residual written folded along x
   int hp[3] = {0, 0, 0};
   std::vector<double> hSf[3];
   size_t off_Sf[3][2] = {};
@@ -307,6 +308,7 @@ ResidualArgs residual_args(qn_ctx c, const double* U, const double* F, double* R
   a.pot = c->pot;
   a.bc = c->bc;
   a.partials = c->at<double>(c->off_part);
+  a.xfold = (!R_caller && c->xfold) ? c->hp[0] : 0;  // the x product reads it folded
   a.rz = c->dim == 3 ? residual_slab_depth(a.ox, a.oy, a.oz, residual_threads(c->nl, c->bc))
                       : residual_planar_rows(a.ox, a.oy);
   a.sem_k = c->sem_k;
@@ -454,7 +456,8 @@ int dense_plan(qn_ctx c, const EpiArgs& ep, int epi_last, FoldStep* st) {
     // folded ones below
     const int hy = c->hp[1], hz = c->hp[2];
     add(DK_RIGHT, 0, K_GEMM_X, W1, W2, 0, 0, 0, 0, EPI_STORE, ep);
-    st[ns - 1].sp = BfSplit{3, 0, hz};
+    st[ns - 1].sp = BfSplit{3, c->xfold ? c->hp[0] : 0, hz};  // from the x-folded residual
+    st[ns - 1].sop = c->xfold ? 1 : 0;
     add(DK_LEFT, 2, K_GEMM_YZ, W2, W1, pz, (int)yslab, c->ncomp, zslab, EPI_STORE, ep);
     st[ns - 1].sp = BfSplit{2, hz, hy};
     st[ns - 1].sop = 1;
@@ -513,6 +516,7 @@ void dense_extents(const FoldStep& f, long long* mext, long long* next) {
   *mext = f.kind == DK_RIGHT ? f.rows : f.m;
   *next = f.kind == DK_RIGHT ? f.k : f.ncols;
   if (f.sp.mode == 3) *mext = 2LL * f.ep.py;  // half tiles of TM / 2 rows per plane
+  if (f.sp.mode == 3 && f.sp.K > 0) *next = f.sp.K;  // tiles in one half of the x-folded rows
   if (f.sp.mode == 2 || (f.sp.mode == 1 && !f.nmir)) *mext = f.sp.K;  // tiles in one half
   if (f.sp.mode == 2) *next = 2LL * f.ep.px;  // half tiles of TN / 2 x values per row
 }
@@ -798,7 +802,13 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
   c->fwdfold = c->prec == QN_PREC_BF16X3 && c->dim == 3 && c->sem_k == 0 && c->bc == QN_BC_DIRICHLET;
   for (int a = 1; a < 3 && c->fwdfold; ++a)
     c->fwdfold = 2 * fold_half(c->n[a]) == c->p[a];
-  for (int a = 1; a < 3 && c->fwdfold; ++a) {
+  // x as well when the residual's tiles cover whole rows (the mirror pairs
+  // meet in one workgroup) and its folded variant keeps its registers
+  // (quasi-linear and 2-component problems; the cubic one would spill)
+  c->xfold = c->fwdfold && (c->nl == QN_NL_QUASILIN || c->nl == QN_NL_SYS2_CUBIC) &&
+             2 * fold_half(c->n[0]) == c->p[0] &&
+             residual_tile_x(c->p[0], residual_threads(c->nl, c->bc)) == c->p[0];
+  for (int a = c->xfold ? 0 : 1; a < 3 && c->fwdfold; ++a) {
     c->hp[a] = fold_half(c->n[a]);
     fold_forward(c->n[a], c->p[a], c->hS[a], c->hSf[a]);
   }
@@ -835,7 +845,7 @@ qn_status qn_setup(const qn_grid* grid, double beta, int32_t nonlinearity, const
       off += align256(c->hHb[a].size() * 8);
     }
   }
-  for (int a = 1; a < 3 && c->fwdfold; ++a)
+  for (int a = c->xfold ? 0 : 1; a < 3 && c->fwdfold; ++a)
     for (int q = 0; q < 2; ++q) {
       c->off_Sf[a][q] = off;
       off += align256(c->hSf[a].size() * 2);
@@ -934,7 +944,7 @@ qn_status qn_bind_workspace(qn_ctx c, void* d_ws, size_t bytes) {
         e = hipMemcpyAsync(c->ws + offs[q], parts[q].data(), pp * 2, hipMemcpyHostToDevice,
                            c->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // host temporaries
-      if (c->fwdfold && a > 0 && e == hipSuccess) {  // folded forward operand: bf16 parts
+      if (!c->hSf[a].empty() && e == hipSuccess) {  // folded forward operand: bf16 parts
         const std::vector<double>& v = c->hSf[a];
         std::vector<uint16_t> sp[2];
         sp[0].resize(v.size());
@@ -1055,7 +1065,8 @@ qn_status qn_fdm_solve(qn_ctx c, const double* d_R, double scale, double shift, 
   if (e == hipSuccess)
     e = timed(c, K_PAD_COPY, [&] {
       return launch_pad_copy(d_R, c->ws + c->off_W1, transform_storage(c->prec), c->ncomp,
-                             c->n[0], c->n[1], c->n[2], c->p[0], c->p[1], c->p[2], c->stream);
+                             c->n[0], c->n[1], c->n[2], c->p[0], c->p[1], c->p[2], c->stream,
+                             c->xfold ? c->hp[0] : 0);
     });
   if (e == hipSuccess) e = solve_ws(c, coef, d_X, EPI_STORE_DENSE);
   if (e != hipSuccess) return hip_fail(c, e, "fdm solve launch");

@@ -495,14 +495,20 @@ __global__ __launch_bounds__(256, 2) void k_gemm_left_bf(GemmOperands S, const v
 // hpo = the folded z layout's half extent.  A tile's rows are TM / 2 rows y of
 // plane z < hpo and the same rows of plane nz-1-z, each wave's fragment row
 // blocks split in halves so that a lane holds both values of a pair.
-template <int NP, int TM, int TN, int EPI, bool FOLD = false, bool ZF = false>
+// ZF = 2: the input is folded along x as well (row positions [0, kc) the
+// mirror sums, [kc, 2 kc) the differences, K = 2 kc): tile columns below kc
+// are the even modes 2 t, contracting the sums, the others the odd modes
+// 2 t + 1, contracting the differences (S: the even modes' rows of S then the
+// odd modes', kc columns); output columns in mode order.
+template <int NP, int TM, int TN, int EPI, bool FOLD = false, int ZF = 0>
 __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const void* __restrict__ Av,
                                                           GemmOperands S, void* __restrict__ Cv,
                                                           int rows, int K, EpiArgs ep, int nh,
-                                                          int nmir, int hpo) {
+                                                          int nmir, int hpo, int kc) {
   // NP = 2: A and C (with EPI_STORE) are bf16 part planes; NP = 3: FP32 tensors
   constexpr bool PS = NP == 2;
   static_assert(!FOLD || NP == 2, "folded: the bf16x3 inverse products");
+  static_assert(ZF >= 0 && ZF <= 2, "ZF: 0 plain, 1 z-folded output, 2 with an x-folded input");
   static_assert(!ZF || (NP == 2 && !FOLD && EPI == EPI_STORE && TM >= 64),
                 "z-folded output: bf16x3 forward x product, paired row halves");
   const float* A = (const float*)Av;
@@ -529,6 +535,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const void* __restrict
   if (ep.skip && ep.skip[(ZF ? zcomp : r0 / ep.py / ep.pz) % ep.inst_mod]) return;  // finished instance
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+  // ZF = 2: this tile's parity half of the x-folded input (TN divides kc) and
+  // the output column of a tile column
+  const int acol0 = ZF == 2 && n0 >= kc ? kc : 0;
+  auto ocol = [&](int n) { return ZF == 2 ? 2 * (n - acol0) + (acol0 ? 1 : 0) : n; };
   // first data row of the tile's 16-row LDS block blk
   auto arow = [&](int blk) -> int {
     if constexpr (ZF) {
@@ -582,7 +592,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const void* __restrict
         for (int i = 0; i < BM; ++i) acc[i][j] = mfma_split<NP>(a[i], bj[j], acc[i][j]);
     }
   };
-  const int nk = K / BTK;
+  const int nk = (ZF == 2 ? kc : K) / BTK;
   if constexpr (PS) {
     const __bf16* Ah = (const __bf16*)Av;
     // chunk k0 into LDS buffer buf: TM / 16 KiB blocks of data rows and TN / 16
@@ -591,11 +601,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const void* __restrict
 #pragma unroll
       for (int blk = wave; blk < TM / 16; blk += 4)
 #pragma unroll
-        for (int q = 0; q < NP; ++q) dload_rows(Ah + q * plane, K, arow(blk), k0, lane, &As[q][buf][blk * 1024]);
+        for (int q = 0; q < NP; ++q) dload_rows(Ah + q * plane, K, arow(blk), acol0 + k0, lane, &As[q][buf][blk * 1024]);
 #pragma unroll
       for (int blk = wave; blk < TN / 16; blk += 4)
 #pragma unroll
-        for (int q = 0; q < NP; ++q) dload_rows(part(S, q), K, n0 + 16 * blk, k0, lane, &Bs[q][buf][blk * 1024]);
+        for (int q = 0; q < NP; ++q) dload_rows(part(S, q), ZF == 2 ? kc : K, n0 + 16 * blk, k0, lane, &Bs[q][buf][blk * 1024]);
     };
     dload(0, 0);
     for (int kc = 0; kc < nk; ++kc) {
@@ -696,7 +706,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_right_bf(const void* __restrict
         const int y = yw + 16 * i + 4 * (lane >> 4) + q;
 #pragma unroll
         for (int j = 0; j < BN; ++j) {
-          const int n = n0 + wn + 16 * j + (lane & 15);
+          const int n = ocol(n0 + wn + 16 * j + (lane & 15));
           const float d = acc[i][j][q], e = acc[i + HB][j][q];
           const float vp = zf >= hz ? 0.0f : zbar == zf ? d : d + e;
           const float vm = (zf >= hz || zbar == zf) ? 0.0f : d - e;
@@ -862,15 +872,15 @@ hipError_t right_launch(const GemmOperands& s, const void* A, void* C, int rows,
   switch (epi) {
     case EPI_SUB_DENSE:
       hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_SUB_DENSE, FOLD>), dim3(g), dim3(256), 0,
-                         st, A, s, C, rows, K, ep, nout, nmir, 0);
+                         st, A, s, C, rows, K, ep, nout, nmir, 0, 0);
       break;
     case EPI_STORE_DENSE:
       hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_STORE_DENSE, FOLD>), dim3(g), dim3(256), 0,
-                         st, A, s, C, rows, K, ep, nout, nmir, 0);
+                         st, A, s, C, rows, K, ep, nout, nmir, 0, 0);
       break;
     default:
       hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_STORE, FOLD>), dim3(g), dim3(256), 0, st,
-                         A, s, C, rows, K, ep, nout, nmir, 0);
+                         A, s, C, rows, K, ep, nout, nmir, 0, 0);
   }
   return hipGetLastError();
 }
@@ -880,14 +890,21 @@ hipError_t right_tile(const GemmOperands& s, const void* A, void* C, int rows, i
                       const EpiArgs& ep, hipStream_t st, int fold, int nmir, const BfSplit* sp) {
   if (sp && sp->mode) {
     if constexpr (NP == 2 && TM >= 64) {
-      const int hpo = sp->hpo;  // dense x product, output folded along z
+      // dense x product (or, with sp->K = kc > 0, from an input folded along
+      // x), output folded along z
+      const int hpo = sp->hpo, kc = sp->K;
       if (sp->mode != 3 || fold > 0 || epi != EPI_STORE || hpo <= 0 || K % TN != 0 ||
-          ep.py % (TM / 2) != 0 || rows % (ep.pz * ep.py) != 0 || 2 * hpo > ep.pz || hpo > ep.nz)
+          ep.py % (TM / 2) != 0 || rows % (ep.pz * ep.py) != 0 || 2 * hpo > ep.pz || hpo > ep.nz ||
+          (kc > 0 && (K != 2 * kc || kc % TN != 0 || 2 * kc < ep.nx)))
         return hipErrorInvalidValue;
       const unsigned g =
           (unsigned)((long long)(rows / (ep.pz * ep.py)) * hpo * (ep.py / (TM / 2)) * (K / TN));
-      hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_STORE, false, true>), dim3(g), dim3(256), 0,
-                         st, A, s, C, rows, K, ep, K, 0, hpo);
+      if (kc > 0)
+        hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_STORE, false, 2>), dim3(g), dim3(256), 0,
+                           st, A, s, C, rows, K, ep, K, 0, hpo, kc);
+      else
+        hipLaunchKernelGGL((k_gemm_right_bf<NP, TM, TN, EPI_STORE, false, 1>), dim3(g), dim3(256), 0,
+                           st, A, s, C, rows, K, ep, K, 0, hpo, 0);
       return hipGetLastError();
     }
     return hipErrorInvalidValue;

@@ -214,6 +214,11 @@ struct ResidualArgs {
   const double* hb[3] = {nullptr, nullptr, nullptr};
   // Gray-Scott system (NL_GS): diffusion coefficients and reaction rates.
   double gs_da = 0.0, gs_ds = 0.0, gs_rho = 0.0, gs_mu = 0.0;
+  // 3D, out_prec 2, whole-row tiles (tile width = ox = 2 xfold): the output
+  // folded along x, position j < xfold of a row the mirror sum R[j] +
+  // R[nx-1-j], position xfold + j the difference (the middle point of odd nx
+  // once, its difference zero; positions from ceil(nx / 2) on zero); 0: plain.
+  int xfold = 0;
 };
 hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t st);
 // Spectral element residual (qn_sem.hip): same outputs and partials as
@@ -286,8 +291,10 @@ hipError_t launch_finalize(const double* partials, int nblocks, DevScalars* sc, 
 inline int transform_storage(int prec) {
   return prec == QN_PREC_FP64 ? 0 : prec == QN_PREC_BF16X3 ? 2 : 1;
 }
+// xfold > 0 (out_prec 2, px = 2 xfold): the copy folded along x as the
+// residual's xfold output.
 hipError_t launch_pad_copy(const double* src, void* dst, int out_prec, int ncomp, int nx, int ny,
-                           int nz, int px, int py, int pz, hipStream_t st);
+                           int nz, int px, int py, int pz, hipStream_t st, int xfold = 0);
 // Write {scale, beta} into a device slot.
 hipError_t launch_set_coef(double* slot, double scale, double beta, hipStream_t st);
 // Fill n bytes with zero (a kernel, not a memset node).

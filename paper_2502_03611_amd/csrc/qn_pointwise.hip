@@ -98,7 +98,8 @@ __device__ inline double end_weight(int i, int n) { return (i == 0 || i == n - 1
 // last rows h^-2 (2, -2)); BC = 0: zero outside (Dirichlet).  MODE 1 and 2:
 // the two passes of the eigenproblem residual (cubic problem only; see
 // ResidualArgs), which read no F.
-template <int NL, typename TO, int BC, int MODE, int RX>
+// XF: bf16 part-plane output folded along x (a.xfold, whole-row tiles).
+template <int NL, typename TO, int BC, int MODE, int RX, bool XF = false>
 __global__ __launch_bounds__(residual_threads(NL, BC), residual_threads(NL, BC) == 1024 ? 8 : 1)
 void k_residual(ResidualArgs a) {
   constexpr int NC = (NL == NL_SYS2) ? 2 : 1;
@@ -111,6 +112,12 @@ void k_residual(ResidualArgs a) {
   // plane suffices (a wave can only overwrite a buffer two planes later,
   // after every wave has passed the barrier that follows its last read).
   __shared__ double s_buf[2][NC][RY + 2][RX + 2];
+  // XF: each plane's R (rounded to FP32, as the part planes split it) is kept
+  // in LDS, double-buffered by plane parity, and stored as the row's mirror
+  // sums and differences after the next plane's barrier
+  static_assert(!XF || (std::is_same<TO, BfPair>::value && MODE == 0), "x-folded output: bf16 parts");
+  constexpr bool XFC = XF;
+  __shared__ float s_x[XFC ? 2 : 1][NC][RY][XFC ? RX : 1];
   const int tx = threadIdx.x, ty = threadIdx.y;
   // Workgroups are dealt to the 8 XCDs round-robin in launch order; remapped,
   // each XCD walks a contiguous range of tiles (x fastest), so the halo lines
@@ -170,6 +177,26 @@ void k_residual(ResidualArgs a) {
     um[c] = (zc && in_xy && z0 > 0 && z0 - 1 < nz) ? a.U[c * comp + (long long)(z0 - 1) * plane + col] : 0.0;
     uc[c] = (in_xy && z0 < nz) ? a.U[c * comp + (long long)z0 * plane + col] : 0.0;
   }
+  constexpr bool xf = XFC;
+  // store plane zp of the x-folded output (its R values sit in s_x)
+  auto put_folded = [&](int zp) {
+    if constexpr (XFC) {
+      if (y >= a.oy) return;
+      const int hpx = a.xfold;
+      const bool dif = tx >= hpx;
+      const int j = dif ? tx - hpx : tx, jm = nx - 1 - j;
+      const auto& sx = s_x[(zp - z0) & 1];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        float v = 0.0f;
+        if (j < (nx + 1) / 2)
+          v = jm == j ? (dif ? 0.0f : sx[c][ty][j])
+                      : (dif ? sx[c][ty][j] - sx[c][ty][jm] : sx[c][ty][j] + sx[c][ty][jm]);
+        const long long o = c * a.r_cstride + (long long)zp * a.r_zstride + (long long)y * a.r_ystride + tx;
+        put<TO>(a.R, o, v, a.r_plane);
+      }
+    }
+  };
   if (z0 < z1) load_plane(z0, up, f, hc, vc, pv);
   for (int z = z0; z < z1; ++z) {
     const bool zin = z < nz;
@@ -183,6 +210,7 @@ void k_residual(ResidualArgs a) {
       if (has_v) s_u[c][my_][mx_] = vc[c];
     }
     __syncthreads();
+    if (xf && z > z0) put_folded(z - 1);  // its R values were stored before this barrier
     if (in_xy && zin) {
       double r[NC];
       double rw = 1.0;  // mode 2: mass weight of the node in sum W R^2
@@ -263,6 +291,12 @@ void k_residual(ResidualArgs a) {
         for (int c = 0; c < NC; ++c) {
           s_r += rw * (r[c] * r[c]);
           const long long o = c * a.r_cstride + (long long)z * a.r_zstride + (long long)y * a.r_ystride + x;
+          if constexpr (XFC) {
+            if (xf) {
+              s_x[(z - z0) & 1][c][ty][tx] = (float)r[c];
+              continue;
+            }
+          }
           put<TO>(a.R, o, r[c], a.r_plane);
         }
       }
@@ -270,6 +304,12 @@ void k_residual(ResidualArgs a) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const long long o = c * a.r_cstride + (long long)z * a.r_zstride + (long long)y * a.r_ystride + x;
+        if constexpr (XFC) {
+          if (xf) {
+            s_x[(z - z0) & 1][c][ty][tx] = 0.0f;
+            continue;
+          }
+        }
         put<TO>(a.R, o, 0.0, a.r_plane);
       }
     }
@@ -283,6 +323,10 @@ void k_residual(ResidualArgs a) {
       vc[c] = n_vc[c];
     }
     pv = n_pv;
+  }
+  if (xf && z1 > z0) {  // the slab's last plane
+    __syncthreads();
+    put_folded(z1 - 1);
   }
 
   block_reduce4<RTHREADS / 64, MODE == 1>(s_r, mn, mx, s_f);
@@ -549,6 +593,12 @@ int residual_max_blocks(int ox, int oy, int oz, int rz, bool planar, int threads
 template <int NL, int BC, int MODE, int TX>
 static void launch_3d(const ResidualArgs& a, dim3 g, hipStream_t st) {
   const dim3 b(TX, residual_threads(NL, BC) / TX);
+  if constexpr (MODE == 0 && BC == 0) {  // the split-bf16 transforms: Dirichlet data only
+    if (a.out_prec == 2 && a.xfold > 0) {
+      hipLaunchKernelGGL((k_residual<NL, BfPair, BC, MODE, TX, true>), g, b, 0, st, a);
+      return;
+    }
+  }
   if (a.out_prec == 0 || MODE == 1)
     hipLaunchKernelGGL((k_residual<NL, double, BC, MODE, TX>), g, b, 0, st, a);
   else if (a.out_prec == 2 && MODE == 0)
@@ -599,6 +649,10 @@ hipError_t launch_residual(const ResidualArgs& a, int* nblocks_out, hipStream_t 
   const bool planar = a.ihz2 == 0.0;
   const dim3 g = residual_grid(a.ox, a.oy, a.oz, a.rz, planar, residual_threads(a.nl, a.bc));
   *nblocks_out = (int)(g.x * g.y * g.z);
+  // the x-folded output pairs points of one row inside a tile: whole-row tiles
+  if (a.xfold > 0 && (planar || a.out_prec != 2 || a.mode != 0 || a.ox != 2 * a.xfold ||
+                      2 * a.xfold < a.nx || residual_tile_x(a.ox, residual_threads(a.nl, a.bc)) != a.ox))
+    return hipErrorInvalidValue;
   switch (a.nl) {
     case NL_CUBIC:  // the only nonlinearity with Neumann data and eigenproblem passes
       if (a.bc == 1)
@@ -855,31 +909,40 @@ hipError_t launch_breset(BState* st, int* done, int K, hipStream_t s) {
 template <typename TO>
 __global__ __launch_bounds__(256) void k_pad_copy(const double* __restrict__ src, void* __restrict__ dst,
                                                   int nx, int ny, int nz, int px, int py, int pz,
-                                                  long long plane) {
+                                                  long long plane, int xfold) {
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int y = blockIdx.y * 4 + threadIdx.y;
   const int zc = blockIdx.z;  // c * pz + z
   const int z = zc % pz, c = zc / pz;
   if (x >= px || y >= py) return;
   double v = 0.0;
-  if (x < nx && y < ny && z < nz)
-    v = src[(((long long)c * nz + z) * ny + y) * nx + x];
+  const long long row = (((long long)c * nz + z) * ny + y) * nx;  // read only where y, z are interior
+  if (xfold > 0) {  // folded along x: mirror sums, then differences
+    const bool dif = x >= xfold;
+    const int j = dif ? x - xfold : x, jm = nx - 1 - j;
+    if (j < (nx + 1) / 2 && y < ny && z < nz)
+      v = jm == j ? (dif ? 0.0 : src[row + j])
+                  : (dif ? src[row + j] - src[row + jm] : src[row + j] + src[row + jm]);
+  } else if (x < nx && y < ny && z < nz) {
+    v = src[row + x];
+  }
   put<TO>(dst, ((long long)zc * py + y) * px + x, v, plane);
 }
 
 hipError_t launch_pad_copy(const double* src, void* dst, int out_prec, int ncomp, int nx, int ny,
-                           int nz, int px, int py, int pz, hipStream_t st) {
+                           int nz, int px, int py, int pz, hipStream_t st, int xfold) {
+  if (xfold > 0 && (out_prec != 2 || px != 2 * xfold || 2 * xfold < nx)) return hipErrorInvalidValue;
   dim3 g((px + 63) / 64, (py + 3) / 4, ncomp * pz);
   const long long plane = (long long)ncomp * pz * py * px;
   if (out_prec == 0)
     hipLaunchKernelGGL((k_pad_copy<double>), g, dim3(64, 4), 0, st, src, dst, nx, ny, nz, px, py,
-                       pz, plane);
+                       pz, plane, 0);
   else if (out_prec == 2)
     hipLaunchKernelGGL((k_pad_copy<BfPair>), g, dim3(64, 4), 0, st, src, dst, nx, ny, nz, px, py,
-                       pz, plane);
+                       pz, plane, xfold);
   else
     hipLaunchKernelGGL((k_pad_copy<float>), g, dim3(64, 4), 0, st, src, dst, nx, ny, nz, px, py,
-                       pz, plane);
+                       pz, plane, 0);
   return hipGetLastError();
 }
 

@@ -141,6 +141,25 @@ def test_fdm_solve_reduced_precision(prec, tol, shape):
     assert err <= tol
 
 
+@pytest.mark.parametrize("kind,shape", [("quasilinear", (40, 45, 33)), ("system", (36, 64, 63)),
+                                        ("quasilinear", (64, 127, 128))])
+def test_bf16x3_solve_from_an_input_folded_along_x(kind, shape):
+    """3D bf16x3 solvers of the quasi-linear and 2-component problems whose
+    extents allow it take every forward product folded by mode parity, the x
+    product from an input written folded along x (here by the copy of the
+    caller's right-hand side): the solve stays within the split error bound of
+    the FP64 oracle's, per component."""
+    print(f"x-folded fdm {kind} {shape}", flush=True)
+    ncomp = 2 if kind == "system" else 1
+    r = synth.random_field((ncomp,) + shape, 12)
+    s = Solver(shape, kind, beta=1.0, precision="bf16x3")
+    x = host(s.fdm_solve(dev(r), 1.3, 0.7))
+    for c in range(ncomp):
+        err = rel(x[c], otensor.fdm_solve(r[c], 0.7, 1.3))
+        print(f"  component {c}: rel err {err:.3e}", flush=True)
+        assert err <= 4e-5
+
+
 @pytest.mark.parametrize("prec,parts", [("bf16x3", 2), ("bf16x6", 3)])
 @pytest.mark.parametrize("shape,scale,shift", [((63, 63), 1.0, 0.5), ((31, 31, 31), 1.7, 0.0),
                                                ((40, 50, 70), 1.0, 2.0)])
@@ -364,18 +383,20 @@ def test_deterministic_bitwise():
     assert np.array_equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("shape,prec", [((255, 255), "fp64"), ((63, 63), "fp32"),
-                                        ((40, 70, 130), "fp64"), ((40, 45, 33), "bf16x3"),
-                                        ((64, 127, 125), "bf16x3")])
-def test_every_admissible_tile_gives_the_same_bits(shape, prec):
+@pytest.mark.parametrize("shape,prec,kind", [((255, 255), "fp64", "cubic"), ((63, 63), "fp32", "cubic"),
+                                             ((40, 70, 130), "fp64", "cubic"),
+                                             ((40, 45, 33), "bf16x3", "cubic"),
+                                             ((64, 127, 125), "bf16x3", "cubic"),
+                                             ((64, 127, 125), "bf16x3", "quasilinear")])
+def test_every_admissible_tile_gives_the_same_bits(shape, prec, kind):
     """Each launch of the solve is pinned in turn to every instantiated tile
     (plain, paired, deep-staged) that qn_set_tile accepts; every solve returns
     the bits of the default one.  Shapes that are not admissible are refused."""
-    print(f"all tiles {shape} {prec}", flush=True)
+    print(f"all tiles {shape} {prec} {kind}", flush=True)
     f = dev(synth.random_field((1,) + shape, 302, scale=20.0))
-    ref = Solver(shape, "cubic", beta=1.0, precision=prec)
+    ref = Solver(shape, kind, beta=1.0, precision=prec)
     want = ref.fdm_solve(f, scale=1.5, shift=0.25)
-    s = Solver(shape, "cubic", beta=1.0, precision=prec)
+    s = Solver(shape, kind, beta=1.0, precision=prec)
     default = s.tiles()
     tried = 0
     for i, (kind, axis, _, _) in enumerate(default):
