@@ -44,19 +44,19 @@ PEAK_HBM_GBS = 8000.0
 # calibrated on a plain 1 GiB device copy), keyed by kernel.  Each figure is
 # valid only while the source file it was taken on is unchanged.
 TRAFFIC_SOURCES = {"fold": ("paper_2502_03611_amd/csrc/qn_gemm_fold.hip", "0bf9f6298fde0112"),
-                   "pointwise": ("paper_2502_03611_amd/csrc/qn_pointwise.hip", "7db57d6c0fb14e33"),
-                   "bf16": ("paper_2502_03611_amd/csrc/qn_gemm_bf16.hip", "df63e97f041da41d")}
-TRAFFIC = {"k_fold_right_fwd<double,64,128,0>": ("fold", 1.4634e+09, 1.0737e+09),
-           "k_fold_left_fwd2<double,64,64,EPI_STORE,0>": ("fold", 1.4587e+09, 1.0737e+09),
-           "k_fold_left_fwd<double,128,128,EPI_DIVIDE,0>": ("fold", 1.2585e+09, 1.0737e+09),
-           "k_fold_left_inv<double,64,64,0>": ("fold", 1.3873e+09, 1.0716e+09),
-           "k_fold_right_inv<double,64,64,EPI_SUB_DENSE,0>": ("fold", 2.5114e+09, 1.0760e+09),
-           "k_residual<QUASILIN,double>": ("pointwise", 2.3979e+09, 1.0738e+09),
-           "k_gemm_right_bf<2,128,128,EPI_STORE,false,true>": ("bf16", 6.3455e+08, 5.3766e+08),
-           "k_gemm_left_bf<2,128,128,EPI_STORE,false,2>": ("bf16", 5.5474e+08, 5.3805e+08),
-           "k_gemm_left_bf<2,128,128,EPI_DIVIDE,false,1>": ("bf16", 5.6620e+08, 5.3688e+08),
-           "k_gemm_left_bf<2,128,128,EPI_STORE,true,0>": ("bf16", 5.7003e+08, 5.3708e+08),
-           "k_gemm_right_bf<2,64,128,EPI_SUB_DENSE,true,false>": ("bf16", 1.6765e+09, 1.1250e+09)}
+                   "pointwise": ("paper_2502_03611_amd/csrc/qn_pointwise.hip", "1f8af7022b255738"),
+                   "bf16": ("paper_2502_03611_amd/csrc/qn_gemm_bf16.hip", "c512757748bb1244")}
+TRAFFIC = {"k_fold_right_fwd<double,64,128,0>": ("fold", 1.4620e+09, 1.0737e+09),
+           "k_fold_left_fwd2<double,64,64,EPI_STORE,0>": ("fold", 1.4551e+09, 1.0737e+09),
+           "k_fold_left_fwd<double,128,128,EPI_DIVIDE,0>": ("fold", 1.2608e+09, 1.0737e+09),
+           "k_fold_left_inv<double,64,64,0>": ("fold", 1.3845e+09, 1.0716e+09),
+           "k_fold_right_inv<double,64,64,EPI_SUB_DENSE,0>": ("fold", 2.5069e+09, 1.0762e+09),
+           "k_residual<QUASILIN,double>": ("pointwise", 2.3923e+09, 1.0738e+09),
+           "k_gemm_right_bf<2,128,128,EPI_STORE,false,2>": ("bf16", 5.6274e+08, 7.5118e+08),
+           "k_gemm_left_bf<2,128,128,EPI_STORE,false,2>": ("bf16", 5.5471e+08, 5.3793e+08),
+           "k_gemm_left_bf<2,128,128,EPI_DIVIDE,false,1>": ("bf16", 5.6746e+08, 5.3688e+08),
+           "k_gemm_left_bf<2,128,128,EPI_STORE,true,0>": ("bf16", 5.7217e+08, 5.3693e+08),
+           "k_gemm_right_bf<2,64,128,EPI_SUB_DENSE,true,0>": ("bf16", 1.6730e+09, 1.1238e+09)}
 
 
 def traffic_if_current(kernel, n):
@@ -221,10 +221,10 @@ def mixed_steps(shape, U, F, steps, precisions=("fp32", "bf16x3")):
         if prec == "bf16x3":
             # measured HBM bytes of the kept tiles (profiles/traffic_fp64_quasilinear_511.md)
             keys = ["gemm_x", "gemm_yz", "gemm_divide", "gemm_yz_inv", "gemm_yz_inv", "gemm_x_update"]
-            # template tails of the 3D path: x product with its output folded along z;
-            # z product from the folded input, output folded along y; y product from
-            # the folded input with the divide; folded inverse products
-            tails = {0: "EPI_STORE,false,true", 2: "EPI_STORE,true,0", 3: "EPI_SUB_DENSE,true,false"}
+            # template tails of the 3D path: x product from the input folded along x,
+            # output folded along z; z product from the folded input, output folded
+            # along y; y product from the folded input with the divide; folded inverses
+            tails = {0: "EPI_STORE,false,2", 2: "EPI_STORE,true,0", 3: "EPI_SUB_DENSE,true,0"}
             for key, (kind, axis, tm, tn) in zip(keys, rec["tiles"]):
                 form = "k_gemm_right_bf" if kind in (0, 3) else "k_gemm_left_bf"
                 tail = tails.get(kind, "EPI_STORE,false,2" if axis == 2 else "EPI_DIVIDE,false,1")
