@@ -45,7 +45,7 @@ PEAK_HBM_GBS = 8000.0
 # valid only while the source file it was taken on is unchanged.
 TRAFFIC_SOURCES = {"fold": ("paper_2502_03611_amd/csrc/qn_gemm_fold.hip", "0bf9f6298fde0112"),
                    "pointwise": ("paper_2502_03611_amd/csrc/qn_pointwise.hip", "1f8af7022b255738"),
-                   "bf16": ("paper_2502_03611_amd/csrc/qn_gemm_bf16.hip", "c512757748bb1244")}
+                   "bf16": ("paper_2502_03611_amd/csrc/qn_gemm_bf16.hip", "37c82a36bc9257ff")}
 TRAFFIC = {"k_fold_right_fwd<double,64,128,0>": ("fold", 1.4620e+09, 1.0737e+09),
            "k_fold_left_fwd2<double,64,64,EPI_STORE,0>": ("fold", 1.4551e+09, 1.0737e+09),
            "k_fold_left_fwd<double,128,128,EPI_DIVIDE,0>": ("fold", 1.2608e+09, 1.0737e+09),

@@ -46,7 +46,11 @@
 //     the even modes' rows, then the odd modes', hp columns): half the loads
 //     and matrix-core work of the dense product, output in mode order; the z
 //     product writes its output folded along y in the same way (pairing the
-//     columns of rows y and ny-1-y in one tile).
+//     columns of rows y and ny-1-y in one tile);
+//   - quasi-linear and 2-component problems whose residual tiles cover whole
+//     rows also fold the x product: the residual (or the copy of a caller's
+//     right-hand side) writes its output folded along x, and the x product
+//     contracts half a row per mode (ZF = 2 below).
 //
 // Work decomposition: a 256-thread workgroup (four wave64s in a 2 x 2 grid)
 // owns a TM x TN output tile and walks K in chunks of 32 (one matrix-core
